@@ -1,0 +1,236 @@
+"""Pins of the oracle's electrostatics (CPU only).
+
+Each check compares the oracle with something other than itself:
+  * the folded spread against a periodic spread of explicit image charges on the
+    doubled / quadrupled domain (image construction, Sec. II.A and II.B.1);
+  * the slit Poisson solve against a triply periodic FFT solve of the odd / even
+    extension (independent route to the same discrete system);
+  * closed forms: capacitor, uniform Neumann field, mixed wall, E exact for an
+    affine potential (ghost rule, Sec. II.B.1);
+  * adjointness <S q, phi>_h = <q, J phi> (eq adjoint) with the homogeneous ghosts;
+  * electro-neutrality of an all-Neumann system (Sec. II.B.1 closing remark);
+  * physics: single charge near grounded walls and the two-ion test of Sec. III.B
+    against a sum over 1000 images (method of images, the paper's reference).
+"""
+import numpy as np
+import pytest
+
+from oracle import electrostatics as es
+from paper_2204_14167_amd.workloads import load_p3m_table, random_ions
+
+D, N = es.DIRICHLET, es.NEUMANN
+BC_PAIRS = [(D, D), (N, N), (D, N), (N, D)]
+EPS = 1.0 / (4.0 * np.pi * 4.46)
+
+
+def _image_spread_reference(grid, pos, q, bc):
+    s_lo, s_hi = es.image_sign(bc[0]), es.image_sign(bc[1])
+    Lz = grid.L[2]
+    big = es.Grid(grid.nx, grid.ny, 4 * grid.nz, grid.h)
+    zs = [pos[2], -pos[2], 2 * Lz - pos[2], 2 * Lz + pos[2]]
+    qs = [q, s_lo * q, s_hi * q, s_lo * s_hi * q]
+    P = np.concatenate([np.stack([pos[0], pos[1], np.mod(z, 4 * Lz)]) for z in zs], axis=1)
+    Q = np.concatenate(qs)
+    return es.spread_periodic(big, P, Q)[:grid.nz]
+
+
+@pytest.mark.parametrize("bc", BC_PAIRS)
+def test_spread_fold_equals_explicit_images(bc):
+    grid = es.Grid(8, 8, 8)
+    pos, q = random_ions(8, 8, 8, 60, seed=11, charge="normal")
+    pos[2, :20] = np.random.default_rng(1).uniform(0, 2.5, 20)      # near the bottom
+    pos[2, 20:40] = 8 - np.random.default_rng(2).uniform(0, 2.5, 20)  # near the top
+    pos[2, 40] = 0.0
+    pos[2, 41] = 8.0
+    rho = es.spread_charge(grid, pos, q, bc)
+    ref = _image_spread_reference(grid, pos, q, bc)
+    np.testing.assert_allclose(rho, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_spread_conserves_charge():
+    grid = es.Grid(16, 16, 16)
+    pos, q = random_ions(16, 16, 16, 200, seed=5, charge="normal")
+    rho = es.spread_charge(grid, pos, q, (N, N))
+    assert abs(rho.sum() * grid.dV - q.sum()) < 1e-12 * np.abs(q).sum()
+    pos[2] = np.clip(pos[2], 2.0, 14.0)
+    rho = es.spread_charge(grid, pos, q, (D, D))
+    assert abs(rho.sum() * grid.dV - q.sum()) < 1e-12 * np.abs(q).sum()
+
+
+@pytest.mark.parametrize("bc", BC_PAIRS)
+def test_adjointness(bc):
+    grid = es.Grid(8, 16, 8)
+    pos, q = random_ions(8, 16, 8, 40, seed=21, charge="normal")
+    pos[2, :10] = np.random.default_rng(4).uniform(0, 2.0, 10)
+    pos[2, 10:20] = 8 - np.random.default_rng(5).uniform(0, 2.0, 10)
+    phi = np.random.default_rng(6).normal(size=(8, 16, 8))
+    rho = es.spread_charge(grid, pos, q, bc)
+    lhs = grid.dV * (rho * phi).sum()
+    ext = es.ghost_extend(grid, EPS, bc, (None, None), phi)
+    rhs = (q * es.interp_scalar(grid, pos, ext)).sum()
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
+
+
+def _extension_reference(grid, eps, bc, rhs):
+    """Periodic solve of the odd/even extension over 4 nz layers."""
+    s_lo, s_hi = es.image_sign(bc[0]), es.image_sign(bc[1])
+    b = np.concatenate([rhs, s_hi * rhs[::-1]], axis=0)
+    ext = np.concatenate([b, s_lo * b[::-1]], axis=0)
+    big = es.Grid(grid.nx, grid.ny, 4 * grid.nz, grid.h)
+    return es.periodic_poisson(big, eps, ext)[:grid.nz]
+
+
+@pytest.mark.parametrize("bc", BC_PAIRS)
+@pytest.mark.parametrize("shape", [(8, 8, 8), (4, 8, 6), (16, 8, 5)])
+def test_poisson_matches_extension_solve(bc, shape):
+    nx, ny, nz = shape
+    grid = es.Grid(nx, ny, nz, 0.7)
+    rhs = np.random.default_rng(nx * 100 + nz).normal(size=(nz, ny, nx))
+    if bc == (N, N):
+        rhs -= rhs.mean()
+    phi = es.solve_poisson(grid, 0.37, bc, rhs)
+    ref = _extension_reference(grid, 0.37, bc, rhs)
+    np.testing.assert_allclose(phi, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_capacitor_closed_form():
+    grid = es.Grid(8, 8, 16, 0.5)
+    V = 1.7
+    rhs = es.bc_rhs(grid, EPS, (D, D), (V, 0.0))
+    phi = es.solve_poisson(grid, EPS, (D, D), rhs)
+    zc = (np.arange(16) + 0.5) * 0.5
+    expect = V * (1.0 - zc / grid.L[2])
+    np.testing.assert_allclose(phi, np.broadcast_to(expect[:, None, None], phi.shape),
+                               atol=1e-13)
+    # the field at arbitrary points of the channel, walls included, is exactly V / Lz
+    pos, _ = random_ions(8, 8, 16, 50, seed=2, h=0.5)
+    pos[2, 0] = 0.0
+    pos[2, 1] = grid.L[2]
+    ext = es.ghost_extend(grid, EPS, (D, D), (V, 0.0), phi)
+    E = es.interp_field(grid, pos, *es.face_fields(grid, ext))
+    np.testing.assert_allclose(E[2], V / grid.L[2], rtol=1e-13)
+    np.testing.assert_allclose(E[:2], 0.0, atol=1e-13)
+
+
+def test_neumann_uniform_field_closed_form():
+    grid = es.Grid(8, 4, 12)
+    sig = 0.3
+    rhs = es.bc_rhs(grid, EPS, (N, N), (sig, -sig))
+    phi = es.solve_poisson(grid, EPS, (N, N), rhs)
+    zc = np.arange(12) + 0.5
+    expect = -(sig / EPS) * (zc - 6.0)
+    np.testing.assert_allclose(phi[:, 0, 0], expect, rtol=1e-12)
+    pos, _ = random_ions(8, 4, 12, 50, seed=3)
+    ext = es.ghost_extend(grid, EPS, (N, N), (sig, -sig), phi)
+    E = es.interp_field(grid, pos, *es.face_fields(grid, ext))
+    # Gauss: -eps dphi/dz(0) = sigma_lo  =>  E_z = sigma_lo / eps
+    np.testing.assert_allclose(E[2], sig / EPS, rtol=1e-12)
+
+
+def test_mixed_wall_closed_form():
+    grid = es.Grid(4, 4, 10)
+    V, sig = 0.4, 0.2
+    rhs = es.bc_rhs(grid, EPS, (D, N), (V, sig))
+    phi = es.solve_poisson(grid, EPS, (D, N), rhs)
+    zc = np.arange(10) + 0.5
+    # +eps dphi/dz(Lz) = sigma_hi and phi(0) = V
+    np.testing.assert_allclose(phi[:, 1, 2], V + sig / EPS * zc, rtol=1e-12)
+
+
+def test_non_neutral_neumann_rejected():
+    grid = es.Grid(8, 8, 8)
+    pos, q = random_ions(8, 8, 8, 11, seed=3)
+    with pytest.raises(ValueError):
+        es.potential(grid, pos, q, EPS, (N, N), (None, None))
+    # made neutral by the surface charge on both walls: accepted
+    sig = -q.sum() / (2 * 64.0)
+    es.potential(grid, pos, q, EPS, (N, N), (sig, sig))
+
+
+def _image_series_field(src, charges, target, Lz, eps, bc, nimg=1000):
+    """E at target from sources and their wall images (method of images)."""
+    s_lo, s_hi = es.image_sign(bc[0]), es.image_sign(bc[1])
+    E = np.zeros(3)
+    for (x, y, z), qq in zip(src.T, charges):
+        for n in range(-nimg, nimg + 1):
+            # images of the periodic reflection group: z + 2 n Lz (sign (s_lo s_hi)^n)
+            # and -z + 2 n Lz (sign s_lo (s_lo s_hi)^n)
+            sp = (s_lo * s_hi) ** abs(n)
+            for zz, ss in ((z + 2 * n * Lz, sp), (-z + 2 * n * Lz, s_lo * sp)):
+                d = target - np.array([x, y, zz])
+                r = np.linalg.norm(d)
+                if r < 1e-12:
+                    continue
+                E += ss * qq * d / (4 * np.pi * eps * r ** 3)
+    return E
+
+
+@pytest.mark.parametrize("d", [3.0, 4.5, 6.0])
+def test_single_charge_near_grounded_wall(d):
+    grid = es.Grid(64, 64, 32)
+    pos = np.array([[20.3], [11.7], [d]])
+    q = np.array([1.0])
+    _, _, ep = es.grid_field_at_ions(grid, pos, q, EPS, (D, D), (0.0, 0.0))
+    ref = _image_series_field(pos, q, pos[:, 0], grid.L[2], EPS, (D, D))
+    assert ref[2] < 0  # attracted to the nearer wall
+    # grid-level image force: lattice anisotropy of the discrete Green's function
+    # at this placement and the laterally periodic copies give a few per cent
+    assert abs(ep[2, 0] - ref[2]) < 0.04 * abs(ref[2])
+    # the staggered field has a small position-dependent self-force parallel to
+    # the wall (translational variance), bounded by 1% of the Coulomb force at h
+    coulomb_h = 1.0 / (4 * np.pi * EPS)
+    assert abs(ep[0, 0]) < 0.01 * coulomb_h and abs(ep[1, 0]) < 0.01 * coulomb_h
+
+
+@pytest.mark.parametrize("d", [1.0, 1.5, 2.5, 4.0])
+def test_two_ions_near_grounded_wall_p3m(d):
+    """Sec. III.B: two like ions 2 h apart parallel to a grounded wall; P3M force
+    (grid + near-field correction with images) against the image sum."""
+    table, dr = load_p3m_table()
+    grid = es.Grid(64, 64, 32)
+    pos = np.array([[20.3, 22.3], [11.7, 11.7], [d, d]])
+    q = np.array([1.0, 1.0])
+    _, _, _, fp = es.grid_force(grid, pos, q, EPS, (D, D), (0.0, 0.0))
+    fn = es.near_field(grid, pos, q, EPS, 4.0, table, dr, (D, D))
+    F = fp + fn
+    ref = q[0] * _image_series_field(pos, q, pos[:, 0], grid.L[2], EPS, (D, D))
+    assert np.linalg.norm(F[:, 0] - ref) < 0.04 * np.linalg.norm(ref)
+
+
+def test_near_field_closed_forms():
+    grid = es.Grid(32, 32, 32)
+    zero = np.zeros(10)
+    # bulk pair with a zero table: the correction is the bare Coulomb force
+    pos = np.array([[10.0, 11.5], [10.0, 10.0], [16.0, 16.0]])
+    q = np.array([1.0, -2.0])
+    f = es.near_field(grid, pos, q, EPS, 4.0, zero, 1.0, (D, D))
+    expect = q[0] * q[1] / (4 * np.pi * EPS * 1.5 ** 2)
+    np.testing.assert_allclose(f[0], [-expect, expect], rtol=1e-14)
+    np.testing.assert_allclose(f[1:], 0.0, atol=1e-16)
+    # the pair wraps through the periodic boundary (minimum image)
+    pos = np.array([[0.5, 31.5], [3.0, 3.0], [16.0, 16.0]])
+    f = es.near_field(grid, pos, q, EPS, 4.0, zero, 1.0, (D, D))
+    expect = q[0] * q[1] / (4 * np.pi * EPS * 1.0)
+    np.testing.assert_allclose(f[0], [expect, -expect], rtol=1e-14)
+    # a single ion at z < psi/2 interacts with its own image at -z
+    for bc, s in (((D, D), -1.0), ((N, N), 1.0)):
+        pos = np.array([[5.0], [5.0], [1.5]])
+        f = es.near_field(grid, pos, np.array([1.0]), EPS, 4.0, zero, 1.0, bc)
+        np.testing.assert_allclose(f[2, 0], s / (4 * np.pi * EPS * 3.0 ** 2), rtol=1e-14)
+        pos[2] = 2.5  # own image beyond psi
+        f = es.near_field(grid, pos, np.array([1.0]), EPS, 4.0, zero, 1.0, bc)
+        assert f[2, 0] == 0.0
+    # a table equal to the Coulomb law cancels the correction
+    rho = np.arange(1, 400) / 64.0
+    coul = np.concatenate([[0.0], 1.0 / rho ** 2])
+    pos = np.array([[10.0, 11.5], [10.0, 10.5], [16.0, 16.0]])
+    f = es.near_field(grid, pos, np.array([1.0, -1.0]), EPS, 4.0, coul, 1 / 64.0, (D, D))
+    assert np.abs(f).max() < 1e-3
+
+
+def test_near_field_newton_third_law_in_bulk():
+    table, dr = load_p3m_table()
+    grid = es.Grid(16, 16, 32)
+    pos, q = random_ions(16, 16, 32, 300, seed=9, zmin=8.0, zmax=24.0, charge="normal")
+    f = es.near_field(grid, pos, q, EPS, 4.0, table, dr, (D, D))
+    assert np.abs(f.sum(axis=1)).max() < 1e-11 * np.abs(f).sum()
