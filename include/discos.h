@@ -1,0 +1,216 @@
+/*
+ * discos.h - C ABI of the DISCOS slit-channel particle-grid core for MI355X (gfx950).
+ *
+ * Method: Ladiges et al., "Modeling electrokinetic flows with the discrete ion
+ * stochastic continuum overdamped solvent algorithm", arXiv:2204.14167.  Ions in a
+ * channel periodic in x and y with walls at z = 0 ("lo") and z = Lz ("hi").
+ *
+ * Conventions shared by every entry point
+ *   - FP64 everywhere.  All array arguments are DEVICE pointers (hipMalloc'd or
+ *     torch tensors on the GPU) unless the comment says "host".  The caller owns
+ *     every array it passes; the context owns its own scratch.
+ *   - Ion arrays are structure-of-arrays: pos is [3][n] (all x, then all y, then
+ *     all z), q is [n].
+ *   - Grid (nx, ny, nz, h): cell-centred scalars (rho, phi, pressure) are
+ *     [nz][ny][nx] with x fastest, the cell (i, j, k) centred at
+ *     ((i+1/2)h, (j+1/2)h, (k+1/2)h).  Face fields (electric field, fluid velocity,
+ *     force density) use the staggered MAC layout: the x component at
+ *     (i h, (j+1/2) h, (k+1/2) h) as [nz][ny][nx], y likewise, and the z component
+ *     at ((i+1/2) h, (j+1/2) h, k h) as [nz+1][ny][nx] (k = 0 and nz on the walls).
+ *   - nx and ny are powers of two in [8, 1024]; nz >= 4.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on that stream; nothing synchronises except discos_check.
+ *   - Return value: DISCOS_OK (0) or a negative status.  Argument errors are
+ *     detected on the host before anything is enqueued.  Conditions that only the
+ *     device can see (an ion outside the channel, a non-finite position, a
+ *     non-neutral all-Neumann system) set a sticky flag that discos_check reports;
+ *     the kernels never read or write out of bounds because of them.
+ *   - One context per stream at a time: calls that overlap on two streams with the
+ *     same context race on its scratch.
+ */
+#ifndef DISCOS_H
+#define DISCOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define DISCOS_OK 0
+#define DISCOS_E_ARG (-1)          /* null pointer, bad enum, bad scalar */
+#define DISCOS_E_SHAPE (-2)        /* grid / size outside the supported range */
+#define DISCOS_E_HIP (-3)          /* a HIP runtime call failed */
+#define DISCOS_E_OUT_OF_DOMAIN (-4) /* sticky: an ion had z outside [0, Lz] or |x|, |y| huge */
+#define DISCOS_E_NOT_NEUTRAL (-5)  /* sticky: both walls Neumann and the system is charged */
+#define DISCOS_E_NONFINITE (-6)    /* sticky: a non-finite position or force */
+#define DISCOS_E_CAPACITY (-7)     /* n larger than the context's n_max */
+
+/* ---- wall boundary conditions for the potential (Sec. II.B.1) --------------- */
+#define DISCOS_BC_DIRICHLET 0 /* fixed potential phi_b (eq esbc1) */
+#define DISCOS_BC_NEUMANN 1   /* dielectric wall, surface charge sigma, eps >> eps_b (eq esbc3);
+                                 sign from Gauss's law: -eps dphi/dz(0+) = sigma_lo and
+                                 +eps dphi/dz(Lz-) = sigma_hi */
+
+typedef struct discos_grid {
+    int32_t nx, ny, nz; /* cells */
+    double h;           /* cell size; Lx = nx h, Ly = ny h, Lz = nz h */
+} discos_grid;
+
+/*
+ * Physical and numerical parameters, following the paper's statement of the
+ * problem.  Scalars are by value; the array members are DEVICE pointers.
+ */
+typedef struct discos_params {
+    /* electrostatics (Sec. II.B.1) */
+    double eps;                 /* solvent permittivity */
+    int32_t bc_type[2];         /* DISCOS_BC_* for the wall at z = 0 [0] and z = Lz [1] */
+    const double* bc_value[2];  /* device [ny][nx] per wall: phi_b (Dirichlet) or sigma
+                                   (Neumann) of the column above / below cell (i, j);
+                                   NULL means 0 */
+    double e_ext[3];            /* applied field; adds q E_ext to each ion (eq totalforce) */
+    /* P3M near-field correction (eqs coulomb, fullElectro, LC) */
+    double psi;                 /* cutoff radius */
+    const double* p3m_table;    /* device [p3m_len]: g(i p3m_dr), free-space grid pair force
+                                   in units of q_i q_j / (4 pi eps h^2), argument r / h */
+    int32_t p3m_len;
+    double p3m_dr;
+    /* short-range forces (Sec. II.B.2) */
+    int32_t wall_on;            /* 9-3 wall potential (eq LJ93) */
+    double wall_sigma, wall_xi, wall_cut;
+    int32_t lj_on;              /* ion-ion shifted LJ (eq potential, eq closerange) */
+    const double* lj_sigma;     /* device [nspecies][nspecies] */
+    const double* lj_xi;        /* device [nspecies][nspecies] */
+    double lj_cut_factor;       /* cutoff = factor * sigma_ij (2^(1/6): WCA, 2.5: full LJ) */
+    double lj_range;            /* largest LJ cutoff (factor * max sigma_ij); sizes the search */
+    /* dynamics (Sec. II.C, II.D) */
+    double kT, eta, dt;
+    int32_t nspecies;
+    const double* radius;       /* device [nspecies]: dry radius a, D = kT / (6 pi eta a) */
+    const double* mob_coef;     /* device [nspecies][2][7]: c1..c7 of eq fitfunction for
+                                   motion parallel [0] and perpendicular [1] to the walls */
+    uint64_t seed;              /* Philox key of every noise term */
+} discos_params;
+
+/* Ion state for discos_step.  pos, q, id and species are DEVICE arrays of length n. */
+typedef struct discos_ions {
+    int64_t n;
+    double* pos;      /* [3][n] */
+    double* q;        /* [n] */
+    int32_t* id;      /* [n] stable ids (key of the ion's noise) */
+    int32_t* species; /* [n] in [0, nspecies) */
+} discos_ions;
+
+typedef struct discos_ctx discos_ctx;
+
+/*
+ * Create a context for one grid and at most n_max ions.  Allocates every scratch
+ * buffer the other calls need (FFT twiddles, cell lists, spectra), so later calls
+ * allocate nothing.  flags: reserved, pass 0.  Uses the current HIP device.
+ * Errors: DISCOS_E_ARG, DISCOS_E_SHAPE, DISCOS_E_HIP.
+ */
+int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out);
+int discos_destroy(discos_ctx* ctx);
+
+/*
+ * Spreading S (eq kernel2) with the 4-point Peskin kernel (App. B, eq peskin1d) and
+ * image folding at the walls (Sec. II.A, Fig. folded).
+ *   DISCOS_SPREAD_CHARGE: rho = S^es q, w = q [n], out = rho [nz][ny][nx]; the image
+ *     of each charge is opposite at a Dirichlet wall and like-signed at a Neumann
+ *     wall (Sec. II.B.1).  With DISCOS_SPREAD_ADD_BC or-ed into op, the wall-condition
+ *     terms of the discrete Poisson problem are added to layers 0 and nz-1:
+ *     2 eps phi_b / h^2 (Dirichlet) or sigma / h (Neumann).
+ *   DISCOS_SPREAD_FORCE: f = S^hy F on the MAC faces, w = F [3][n], out = f_x, f_y, f_z
+ *     back to back (sizes nz*ny*nx, nz*ny*nx, (nz+1)*ny*nx); no-slip images: every
+ *     component folds with sign -1; the z-faces mirror k -> -k about the wall face.
+ * `out` is overwritten.  Ions may come in any order.
+ */
+#define DISCOS_SPREAD_CHARGE 0
+#define DISCOS_SPREAD_FORCE 1
+#define DISCOS_SPREAD_ADD_BC 0x100
+int discos_spread(discos_ctx* ctx, int op, int64_t n, const double* pos, const double* w,
+                  const discos_params* p, double* out, void* stream);
+
+/*
+ * Solve -eps lap_h phi = rhs (eq poisson) with the walls' homogeneous ghost rules
+ * (phi_{-1} = -phi_0 Dirichlet, +phi_0 Neumann); inhomogeneous wall values enter
+ * through rhs (DISCOS_SPREAD_ADD_BC).  In-plane FFTs, then one tridiagonal solve in z
+ * per Fourier mode.  When both walls are Neumann the kappa = 0 mode is solved with
+ * mean(phi) = 0 after removing the mean of its RHS; if that mean is larger than
+ * 1e-10 of the sum of the absolute plane sums the sticky DISCOS_E_NOT_NEUTRAL flag is
+ * set.  rhs is read-only; phi [nz][ny][nx] is overwritten (may alias rhs).
+ */
+int discos_solve_poisson(discos_ctx* ctx, const double* rhs, const discos_params* p,
+                         double* phi, void* stream);
+
+/*
+ * Interpolation J (eq kernel1), Delta V sum_n delta(x_i - r_n) f_n:
+ *   DISCOS_INTERP_E:   field = phi [nz][ny][nx]; out [3][n] = E^P = J^es(-grad_h phi)
+ *                      (eq efieldop), E on the faces, ghosts filled from the wall
+ *                      conditions in p (exact for potentials affine in z).
+ *   DISCOS_INTERP_FORCE: as DISCOS_INTERP_E, out [3][n] = q_i (E^P_i + E_ext), with
+ *                      q passed through `aux`.
+ *   DISCOS_INTERP_PHI: field = phi; out [n] = J phi (centres, homogeneous ghosts
+ *                      plus the wall values in p).
+ *   DISCOS_INTERP_VEL: field = v faces (layout of DISCOS_SPREAD_FORCE); out [3][n] = J^hy v
+ *                      with no-slip ghosts.
+ * out is overwritten; ions may come in any order.
+ */
+#define DISCOS_INTERP_E 0
+#define DISCOS_INTERP_FORCE 1
+#define DISCOS_INTERP_PHI 2
+#define DISCOS_INTERP_VEL 3
+int discos_interpolate(discos_ctx* ctx, int op, int64_t n, const double* pos,
+                       const double* field, const double* aux, const discos_params* p,
+                       double* out, void* stream);
+
+/*
+ * Near-field pass: the P3M correction sum_j (F^C_ij - F^P_ij) over pairs closer than
+ * psi (minimum image in x, y) and over the wall images of every ion (charge s q_j at
+ * (x_j, y_j, -z_j) and (x_j, y_j, 2 Lz - z_j), s = -1 Dirichlet, +1 Neumann,
+ * including an ion's own image) (Sec. II.B.1, eq LC), plus the 9-3 wall force and,
+ * if enabled, the ion-ion LJ force (Sec. II.B.2).  F [3][n] is ACCUMULATED (F += ...).
+ * species may be NULL when lj_on == 0.  Uses a cell list with bins of two cells.
+ */
+int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const double* q,
+                      const int32_t* species, const discos_params* p, double* F,
+                      void* stream);
+
+/*
+ * One time step (Sec. II.D).  mode DISCOS_STEP_DRY: stages 1-2 (spread, Poisson,
+ * interpolation, P3M near-field, wall and applied forces) and the dry update of
+ * eq ions3 / eq step2 with the wall-modified diffusion tensor D Gamma(z) of
+ * eq diff1 and its Ito drift D dGamma_z/dz, Euler-Maruyama in the Ito sense, noise
+ * W ~ N(0,1) from Philox4x32-10 with counter (id, step, 1, pair) and key `seed`;
+ * ions crossing a wall are reflected and x, y are wrapped into [0, L).
+ * The ion arrays are PERMUTED in place into cell order (ids follow their ions).
+ */
+#define DISCOS_STEP_DRY 0
+int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint64_t step,
+                int mode, void* stream);
+
+/*
+ * Stage timing of discos_step.  discos_profile(ctx, 1) clears the record and makes the
+ * next (up to 512) steps record a hipEvent on their stream after each stage;
+ * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
+ * the mean elapsed milliseconds per recorded step of each stage (host array of at
+ * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
+ * inverse y-FFT, inverse x-FFT, interpolation, near-field + update) and sets *count
+ * (0 when no step was recorded).
+ */
+#define DISCOS_NSTAGE 9
+int discos_profile(discos_ctx* ctx, int enable);
+int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
+
+/* Synchronise the context's last stream and return (and clear) the sticky status:
+ * DISCOS_E_NONFINITE, DISCOS_E_ARG (a species index outside [0, nspecies)),
+ * DISCOS_E_NOT_NEUTRAL or DISCOS_E_OUT_OF_DOMAIN, in that order of precedence. */
+int discos_check(discos_ctx* ctx);
+/* Text of the last host-side error on this context (static storage, never NULL). */
+const char* discos_last_error(discos_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DISCOS_H */

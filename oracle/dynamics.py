@@ -11,7 +11,8 @@ eq ions3 / eq step2 with the dry diffusion tensor of eq diff1:
 All terms are evaluated at x^n (Ito).  eq step2 prints the scalar D^dry in the
 force and noise terms while eq ions3 uses the tensor D^dry Gamma; the tensor form
 is used throughout.  Ions that cross a wall are reflected (z -> -z, or
-z -> 2 Lz - z, repeated until inside); x and y are wrapped into [0, L).
+z -> 2 Lz - z, repeated until inside; the paper uses specular reflection at the
+walls in its electro-osmosis runs); x and y are wrapped into [0, L).
 
 Parameters are a plain dict (see the keys read below).
 """
@@ -24,11 +25,17 @@ from .rng import TAG_DRY, ion_normals
 
 
 def total_force(grid, pos, q, species, p, targets=None):
-    """F = F^P + sum F^LC + F^W (+ F^R) + q E_ext, eq totalforce; returns (F, parts)."""
-    rho, phi, ep, fp = es.grid_force(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"],
-                                      p["e_ext"])
-    sel = slice(None) if targets is None else targets
-    F = fp[:, sel].copy()
+    """F = F^P + sum F^LC + F^W (+ F^R) + q E_ext, eq totalforce; returns (F, parts).
+
+    The grid part uses all ions; with `targets` the forces (interpolation,
+    near-field, short-range) are evaluated for that subset only.
+    """
+    sel = slice(None) if targets is None else np.asarray(targets)
+    rho, phi = es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
+    ext = es.ghost_extend(grid, p["eps"], p["bc_types"], p["bc_values"], phi)
+    ep = es.interp_field(grid, pos[:, sel], *es.face_fields(grid, ext))
+    fp = q[sel][None, :] * (ep + np.asarray(p["e_ext"], dtype=np.float64)[:, None])
+    F = fp.copy()
     fn = es.near_field(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
                        p["bc_types"], targets=targets)
     F += fn
@@ -49,16 +56,25 @@ def wrap_periodic(x, L):
 
 
 def reflect_walls(z, Lz):
+    """Specular reflection at z = 0 and z = Lz, repeated until inside.
+
+    Written in closed form so that arbitrarily large excursions cost O(1): a
+    single crossing maps z < 0 to -z and z > Lz to 2 Lz - z exactly; anything
+    farther is folded with period 2 Lz (the composition of the reflections).
+    """
     z = np.array(z, dtype=np.float64)
     if np.any(~np.isfinite(z)):
         raise ValueError("non-finite position")
-    while True:
-        lo = z < 0.0
-        hi = z > Lz
-        if not (lo.any() or hi.any()):
-            return z
-        z = np.where(lo, -z, z)
-        z = np.where(hi, 2.0 * Lz - z, z)
+    out = z.copy()
+    one_lo = (z < 0.0) & (z >= -Lz)
+    one_hi = (z > Lz) & (z <= 2.0 * Lz)
+    far = (z < -Lz) | (z > 2.0 * Lz)
+    out[one_lo] = -z[one_lo]
+    out[one_hi] = 2.0 * Lz - z[one_hi]
+    t = np.fmod(z[far], 2.0 * Lz)
+    t = np.where(t < 0.0, t + 2.0 * Lz, t)
+    out[far] = np.where(t <= Lz, t, 2.0 * Lz - t)
+    return out
 
 
 def dry_displacement(grid, pos, F, species, ids, p, step):
@@ -91,8 +107,10 @@ def dry_update(grid, pos, F, species, ids, p, step):
     return new
 
 
-def dry_step(grid, pos, q, species, ids, p, step):
-    """One full dry step; returns (new positions, F, intermediates)."""
-    F, parts = total_force(grid, pos, q, species, p)
-    new = dry_update(grid, pos, F, species, ids, p, step)
+def dry_step(grid, pos, q, species, ids, p, step, targets=None):
+    """One full dry step; returns (new positions, F, intermediates).  With
+    `targets` only those ions are advanced (all ions still source the fields)."""
+    F, parts = total_force(grid, pos, q, species, p, targets=targets)
+    sel = slice(None) if targets is None else np.asarray(targets)
+    new = dry_update(grid, pos[:, sel], F, species[sel], ids[sel], p, step)
     return new, F, parts

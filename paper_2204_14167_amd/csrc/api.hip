@@ -1,0 +1,361 @@
+// C ABI of the DISCOS core: argument validation, context scratch, and the order of
+// the kernels in each call.  Everything here runs on the host and only enqueues work.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using discos::Ctx;
+
+struct discos_ctx : public Ctx {};
+
+namespace discos {
+
+WallDev wall_of(const discos_params* p) {
+    WallDev w;
+    w.type[0] = p->bc_type[0];
+    w.type[1] = p->bc_type[1];
+    w.value[0] = p->bc_value[0];
+    w.value[1] = p->bc_value[1];
+    w.eps = p->eps;
+    return w;
+}
+
+int near_radius_bins(const Ctx* c, const discos_params* p);
+
+}  // namespace discos
+
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+int fail(discos_ctx* c, int code, const char* msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Checks shared by every call that reads discos_params.
+int check_es_params(discos_ctx* c, const discos_params* p) {
+    if (!p) return fail(c, DISCOS_E_ARG, "params is null");
+    if (!finite_pos(p->eps)) return fail(c, DISCOS_E_ARG, "eps must be positive");
+    for (int w = 0; w < 2; ++w)
+        if (p->bc_type[w] != DISCOS_BC_DIRICHLET && p->bc_type[w] != DISCOS_BC_NEUMANN)
+            return fail(c, DISCOS_E_ARG, "bc_type must be DISCOS_BC_DIRICHLET or DISCOS_BC_NEUMANN");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->e_ext[k])) return fail(c, DISCOS_E_ARG, "e_ext must be finite");
+    return DISCOS_OK;
+}
+
+int check_near_params(discos_ctx* c, const discos_params* p, const int32_t* species) {
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    if (!finite_pos(p->psi)) return fail(c, DISCOS_E_ARG, "psi must be positive");
+    if (!p->p3m_table || p->p3m_len < 2 || !finite_pos(p->p3m_dr))
+        return fail(c, DISCOS_E_ARG, "p3m table missing or malformed");
+    if (p->psi / c->grid.h / p->p3m_dr > (double)(p->p3m_len - 1))
+        return fail(c, DISCOS_E_ARG, "p3m table does not reach psi");
+    if (p->wall_on && (!finite_pos(p->wall_sigma) || !std::isfinite(p->wall_xi) ||
+                       !finite_pos(p->wall_cut)))
+        return fail(c, DISCOS_E_ARG, "wall potential parameters invalid");
+    if (p->lj_on) {
+        if (!p->lj_sigma || !p->lj_xi || p->nspecies < 1 || !finite_pos(p->lj_cut_factor) ||
+            !finite_pos(p->lj_range))
+            return fail(c, DISCOS_E_ARG, "LJ parameters invalid");
+        if (!species) return fail(c, DISCOS_E_ARG, "LJ needs species");
+    }
+    const int R = discos::near_radius_bins(c, p);
+    if (2 * R + 1 > c->gd.nbx || 2 * R + 1 > c->gd.nby)
+        return fail(c, DISCOS_E_SHAPE,
+                    "cutoff too large for the periodic box (need nx/2, ny/2 >= 2 ceil(psi/2h) + 1)");
+    return DISCOS_OK;
+}
+
+template <class T>
+T* carve(char*& cur, size_t count) {
+    T* p = reinterpret_cast<T*>(cur);
+    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    cur += bytes;
+    return p;
+}
+
+size_t carve_bytes(size_t count, size_t elem) { return (count * elem + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out) {
+    (void)flags;
+    if (!grid || !out) return DISCOS_E_ARG;
+    *out = nullptr;
+    if (!pow2_in(grid->nx, 8, 1024) || !pow2_in(grid->ny, 8, 1024) || grid->nz < 4 ||
+        grid->nz > 8192 || !finite_pos(grid->h))
+        return DISCOS_E_SHAPE;
+    if (n_max < 0 || n_max > (int64_t)0x7FFFFFFF) return DISCOS_E_SHAPE;
+    discos_ctx* c = new (std::nothrow) discos_ctx();
+    if (!c) return DISCOS_E_HIP;
+    c->grid = *grid;
+    c->n_max = n_max;
+    hipGetDevice(&c->device);
+    discos::GridDev& g = c->gd;
+    g.nx = grid->nx;
+    g.ny = grid->ny;
+    g.nz = grid->nz;
+    g.nxh = grid->nx / 2 + 1;
+    g.h = grid->h;
+    g.inv_h = 1.0 / grid->h;
+    g.Lx = grid->nx * grid->h;
+    g.Ly = grid->ny * grid->h;
+    g.Lz = grid->nz * grid->h;
+    g.nbx = grid->nx / DISCOS_BIN;
+    g.nby = grid->ny / DISCOS_BIN;
+    g.nbz = (grid->nz + DISCOS_BIN - 1) / DISCOS_BIN;
+    c->ncell = (int64_t)g.nx * g.ny * g.nz;
+    c->nface_z = (int64_t)g.nx * g.ny * (g.nz + 1);
+    c->nmode = (int64_t)g.nxh * g.ny;
+    c->nbins = (int64_t)g.nbx * g.nby * g.nbz;
+    const int64_t nm = std::max<int64_t>(n_max, 1);
+    const int64_t nblk = (c->nbins + 1023) / 1024 + 1;
+    const int64_t nspec = c->nmode * g.nz;
+    size_t bytes = 0;
+    bytes += 4 * carve_bytes(nm, sizeof(double));      // sx sy sz sq
+    bytes += carve_bytes(3 * nm, sizeof(double));      // fp
+    bytes += 5 * carve_bytes(nm, sizeof(int));         // sid ssp perm ion_bin ion_rank
+    bytes += carve_bytes(c->nbins, sizeof(int));
+    bytes += carve_bytes(c->nbins + 1, sizeof(int));
+    bytes += carve_bytes(nblk, sizeof(int));
+    bytes += 2 * carve_bytes(c->ncell, sizeof(double)); // rho phi
+    bytes += carve_bytes(nspec, sizeof(double2));
+    bytes += carve_bytes(nspec, sizeof(double));
+    bytes += carve_bytes(g.nx / 2, sizeof(double2));
+    bytes += carve_bytes(g.ny / 2, sizeof(double2));
+    bytes += carve_bytes(64, sizeof(int));
+    if (hipMalloc(&c->pool, bytes) != hipSuccess) {
+        delete c;
+        return DISCOS_E_HIP;
+    }
+    c->pool_bytes = bytes;
+    char* cur = static_cast<char*>(c->pool);
+    c->sx = carve<double>(cur, nm);
+    c->sy = carve<double>(cur, nm);
+    c->sz = carve<double>(cur, nm);
+    c->sq = carve<double>(cur, nm);
+    c->fp = carve<double>(cur, 3 * nm);
+    c->sid = carve<int>(cur, nm);
+    c->ssp = carve<int>(cur, nm);
+    c->perm = carve<int>(cur, nm);
+    c->ion_bin = carve<int>(cur, nm);
+    c->ion_rank = carve<int>(cur, nm);
+    c->bin_count = carve<int>(cur, c->nbins);
+    c->bin_start = carve<int>(cur, c->nbins + 1);
+    c->scan_tmp = carve<int>(cur, nblk);
+    c->rho = carve<double>(cur, c->ncell);
+    c->phi = carve<double>(cur, c->ncell);
+    c->spec = carve<double2>(cur, nspec);
+    c->cprime = carve<double>(cur, nspec);
+    c->tw_x = carve<double2>(cur, g.nx / 2);
+    c->tw_y = carve<double2>(cur, g.ny / 2);
+    c->flags = carve<int>(cur, 64);
+    // twiddles exp(-2 pi i k / N)
+    std::vector<double2> tw(std::max(g.nx, g.ny) / 2);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int N = pass == 0 ? g.nx : g.ny;
+        for (int k = 0; k < N / 2; ++k) {
+            const double a = 2.0 * M_PI * (double)k / (double)N;
+            tw[k] = make_double2(std::cos(a), -std::sin(a));
+        }
+        if (hipMemcpy(pass == 0 ? c->tw_x : c->tw_y, tw.data(), (N / 2) * sizeof(double2),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(c->pool);
+            delete c;
+            return DISCOS_E_HIP;
+        }
+    }
+    if (hipMemset(c->flags, 0, 64 * sizeof(int)) != hipSuccess) {
+        hipFree(c->pool);
+        delete c;
+        return DISCOS_E_HIP;
+    }
+    c->last_stream = nullptr;
+    c->err = "";
+    c->profile = 0;
+    c->prof_steps = 0;
+    c->ev = nullptr;
+    *out = c;
+    return DISCOS_OK;
+}
+
+int discos_destroy(discos_ctx* c) {
+    if (!c) return DISCOS_E_ARG;
+    hipDeviceSynchronize();
+    if (c->ev) {
+        for (size_t k = 0; k < (size_t)PROF_MAX * (DISCOS_NSTAGE + 1); ++k) hipEventDestroy(c->ev[k]);
+        delete[] c->ev;
+    }
+    hipFree(c->pool);
+    delete c;
+    return DISCOS_OK;
+}
+
+int discos_spread(discos_ctx* c, int op, int64_t n, const double* pos, const double* w,
+                  const discos_params* p, double* out, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const int base = op & 0xFF;
+    const int add_bc = (op & DISCOS_SPREAD_ADD_BC) ? 1 : 0;
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (!out || (n > 0 && (!pos || !w))) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    if (base == DISCOS_SPREAD_CHARGE) {
+        rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, w, nullptr, nullptr, s);
+        if (rc) return fail(c, rc, "cell list launch failed");
+        rc = discos::spread_charge_sorted(c, p, add_bc, out, s);
+        return rc ? fail(c, rc, "spread launch failed") : DISCOS_OK;
+    }
+    return fail(c, DISCOS_E_ARG, "unknown spread op");
+}
+
+int discos_solve_poisson(discos_ctx* c, const double* rhs, const discos_params* p, double* phi,
+                         void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (!rhs || !phi) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    rc = discos::solve_poisson(c, rhs, p, phi, s);
+    return rc ? fail(c, rc, "poisson launch failed") : DISCOS_OK;
+}
+
+int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, const double* field,
+                       const double* aux, const discos_params* p, double* out, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (n < 0 || n > 0x7FFFFFFF) return fail(c, DISCOS_E_SHAPE, "n out of range");
+    if (n == 0) return DISCOS_OK;
+    if (!pos || !field || !out) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    if (op == DISCOS_INTERP_E || op == DISCOS_INTERP_FORCE || op == DISCOS_INTERP_PHI) {
+        if (op == DISCOS_INTERP_FORCE && !aux) return fail(c, DISCOS_E_ARG, "charges (aux) missing");
+        rc = discos::interp_es(c, op, (int)n, pos, pos + n, pos + 2 * n, field, aux, p, out, n, s);
+        return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
+    }
+    return fail(c, DISCOS_E_ARG, "unknown interpolation op");
+}
+
+int discos_near_field(discos_ctx* c, int64_t n, const double* pos, const double* q,
+                      const int32_t* species, const discos_params* p, double* F, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (n == 0) return DISCOS_OK;
+    if (!pos || !q || !F) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_near_params(c, p, species);
+    if (rc) return rc;
+    rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, q, nullptr, species, s);
+    if (rc) return fail(c, rc, "cell list launch failed");
+    rc = discos::near_field_sorted(c, (int)n, p, F, n, 1, s);
+    return rc ? fail(c, rc, "near-field launch failed") : DISCOS_OK;
+}
+
+int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64_t step, int mode,
+                void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (!ions) return fail(c, DISCOS_E_ARG, "ions is null");
+    const int64_t n = ions->n;
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (n > 0 && (!ions->pos || !ions->q || !ions->id || !ions->species))
+        return fail(c, DISCOS_E_ARG, "null ion array");
+    if (mode != DISCOS_STEP_DRY) return fail(c, DISCOS_E_ARG, "unknown step mode");
+    int rc = check_near_params(c, p, ions->species);
+    if (rc) return rc;
+    if (!finite_pos(p->kT) || !finite_pos(p->eta) || !finite_pos(p->dt) || p->nspecies < 1 ||
+        !p->radius || !p->mob_coef)
+        return fail(c, DISCOS_E_ARG, "dynamics parameters invalid");
+    const int ni = (int)n;
+    double* pos = ions->pos;
+    discos::stage_mark(c, 0, s);
+    rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, ions->q, ions->id,
+                                 ions->species, s);
+    discos::stage_mark(c, 1, s);
+    if (!rc) rc = discos::spread_charge_sorted(c, p, 1, c->rho, s);
+    discos::stage_mark(c, 2, s);
+    if (!rc) rc = discos::solve_poisson(c, c->rho, p, c->phi, s, 3);
+    if (!rc)
+        rc = discos::interp_es(c, DISCOS_INTERP_FORCE, ni, c->sx, c->sy, c->sz, c->phi, c->sq, p,
+                               c->fp, c->n_max, s);
+    discos::stage_mark(c, 8, s);
+    if (!rc) rc = discos::force_update_dry(c, ni, p, step, pos, ions->q, ions->id, ions->species, s);
+    discos::stage_mark(c, 9, s);
+    if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
+    return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
+}
+
+int discos_profile(discos_ctx* c, int enable) {
+    if (!c) return DISCOS_E_ARG;
+    if (enable && !c->ev) {
+        const size_t ne = (size_t)PROF_MAX * (DISCOS_NSTAGE + 1);
+        c->ev = new (std::nothrow) hipEvent_t[ne];
+        if (!c->ev) return fail(c, DISCOS_E_HIP, "event table");
+        for (size_t k = 0; k < ne; ++k)
+            if (hipEventCreate(&c->ev[k]) != hipSuccess) return fail(c, DISCOS_E_HIP, "event create");
+    }
+    c->profile = enable ? 1 : 0;
+    c->prof_steps = 0;
+    return DISCOS_OK;
+}
+
+int discos_profile_read(discos_ctx* c, double* ms, int* count) {
+    if (!c || !ms || !count) return DISCOS_E_ARG;
+    *count = 0;
+    if (!c->ev) return fail(c, DISCOS_E_ARG, "profiling was never enabled");
+    const int ns = c->prof_steps;
+    for (int k = 0; k < DISCOS_NSTAGE; ++k) ms[k] = 0.0;
+    if (ns == 0) return DISCOS_OK;
+    const int row = DISCOS_NSTAGE + 1;
+    if (hipEventSynchronize(c->ev[(size_t)(ns - 1) * row + DISCOS_NSTAGE]) != hipSuccess)
+        return fail(c, DISCOS_E_HIP, "event sync");
+    for (int st = 0; st < ns; ++st)
+        for (int k = 0; k < DISCOS_NSTAGE; ++k) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, c->ev[(size_t)st * row + k], c->ev[(size_t)st * row + k + 1]) !=
+                hipSuccess)
+                return fail(c, DISCOS_E_HIP, "event elapsed");
+            ms[k] += t / ns;
+        }
+    *count = DISCOS_NSTAGE;
+    return DISCOS_OK;
+}
+
+int discos_check(discos_ctx* c) {
+    if (!c) return DISCOS_E_ARG;
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess) return fail(c, DISCOS_E_HIP, "sync failed");
+    int f = 0;
+    if (hipMemcpy(&f, c->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DISCOS_E_HIP, "flag read failed");
+    if (f) hipMemset(c->flags, 0, sizeof(int));
+    if (f & DISCOS_FLAG_NONFINITE) return fail(c, DISCOS_E_NONFINITE, "non-finite position");
+    if (f & DISCOS_FLAG_BAD_SPECIES) return fail(c, DISCOS_E_ARG, "species index out of range");
+    if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(c, DISCOS_E_NOT_NEUTRAL, "system not neutral");
+    if (f & DISCOS_FLAG_OUT_OF_DOMAIN) return fail(c, DISCOS_E_OUT_OF_DOMAIN, "ion outside channel");
+    return DISCOS_OK;
+}
+
+const char* discos_last_error(discos_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// Cell list: counting sort of ions into bins of DISCOS_BIN^3 cells (row-major bin
+// order, x fastest).  Neighbour sets of the near-field pass (Sec. II.B.1, the set
+// Omega_i^E of eq fullElectro) and the tile gathers of the spread are read from it.
+#include "kernels.h"
+
+namespace discos {
+
+__global__ void fill_i32_kernel(int* __restrict__ a, int64_t n, int v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ a, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+// Bin of each ion and its rank inside the bin (arrival order of the atomic).
+__global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z,
+                                 int* __restrict__ count, int* __restrict__ ion_bin,
+                                 int* __restrict__ ion_rank, int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = x[i], yi = y[i], zi = z[i];
+    if (!pos_ok(g, xi, yi, zi))
+        set_flag(flags, (isfinite(xi) && isfinite(yi) && isfinite(zi)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                      : DISCOS_FLAG_NONFINITE);
+    int bx, by, bz;
+    const int b = (isfinite(xi) && isfinite(yi) && isfinite(zi) && fabs(xi) < 1e12 * g.h &&
+                   fabs(yi) < 1e12 * g.h)
+                      ? bin_of(g, xi, yi, zi, bx, by, bz)
+                      : 0;
+    ion_bin[i] = b;
+    ion_rank[i] = atomicAdd(&count[b], 1);
+}
+
+// Exclusive scan of `count` (nb entries) into `start` (nb + 1 entries); three phases.
+#define SCAN_BLOCK 256
+#define SCAN_ITEMS 4
+#define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+        const int a = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[SCAN_BLOCK - 1];
+    const int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void scan_reduce_kernel(const int* __restrict__ count, int64_t nb,
+                                   int* __restrict__ block_sum) {
+    __shared__ int sh[SCAN_BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+        if (i < nb) s += count[i];
+    }
+    int total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block sums, in chunks with a running carry.
+__global__ void scan_blocks_kernel(int* __restrict__ block_sum, int nblk) {
+    __shared__ int sh[SCAN_BLOCK];
+    int carry = 0;
+    for (int c0 = 0; c0 < nblk; c0 += SCAN_BLOCK) {
+        const int i = c0 + threadIdx.x;
+        const int v = (i < nblk) ? block_sum[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, sh, total);
+        if (i < nblk) block_sum[i] = ex + carry;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void scan_final_kernel(const int* __restrict__ count, int64_t nb,
+                                  const int* __restrict__ block_off, int* __restrict__ start,
+                                  int n_total) {
+    __shared__ int sh[SCAN_BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int v[SCAN_ITEMS];
+    int s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+        v[k] = (i < nb) ? count[i] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, sh, total) + block_off[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+        if (i < nb) start[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[nb] = n_total;
+}
+
+// Sorted copies of the ion arrays; perm[sorted] = original index.
+__global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
+                                   const int* __restrict__ ion_rank, const int* __restrict__ start,
+                                   const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, const double* __restrict__ q,
+                                   const int* __restrict__ id, const int* __restrict__ sp,
+                                   double* __restrict__ sx, double* __restrict__ sy,
+                                   double* __restrict__ sz, double* __restrict__ sq,
+                                   int* __restrict__ sid, int* __restrict__ ssp,
+                                   int* __restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int d = start[ion_bin[i]] + ion_rank[i];
+    sx[d] = x[i];
+    sy[d] = y[i];
+    sz[d] = z[i];
+    if (q) sq[d] = q[i];
+    if (id) sid[d] = id[i];
+    if (sp) ssp[d] = sp[i];
+    perm[d] = i;
+}
+
+int build_cell_list(Ctx* c, int n, const double* x, const double* y, const double* z,
+                    const double* q, const int* id, const int* sp, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int64_t nb = c->nbins;
+    const int T = 256;
+    fill_i32_kernel<<<(int)std::min<int64_t>((nb + T - 1) / T, 4096), T, 0, s>>>(c->bin_count, nb, 0);
+    if (n > 0)
+        bin_count_kernel<<<(n + T - 1) / T, T, 0, s>>>(g, n, x, y, z, c->bin_count, c->ion_bin,
+                                                       c->ion_rank, c->flags);
+    const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
+    scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp);
+    scan_blocks_kernel<<<1, SCAN_BLOCK, 0, s>>>(c->scan_tmp, nblk);
+    scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp, c->bin_start, n);
+    if (n > 0)
+        bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
+                                                         x, y, z, q, id, sp, c->sx, c->sy, c->sz,
+                                                         c->sq, c->sid, c->ssp, c->perm);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+void fill_f64(double* a, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    fill_f64_kernel<<<(int)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(a, n, v);
+}
+
+}  // namespace discos

@@ -1,0 +1,143 @@
+// Device-side building blocks shared by the DISCOS kernels (gfx950, FP64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/discos.h"
+
+#define DISCOS_FLAG_OUT_OF_DOMAIN 1
+#define DISCOS_FLAG_NOT_NEUTRAL 2
+#define DISCOS_FLAG_NONFINITE 4
+#define DISCOS_FLAG_BAD_SPECIES 8
+
+// Bin edge of the cell list, in cells.  Two cells keeps the near-field search
+// volume small (5^3 bins for psi = 4 h) and gives the spread a one-bin halo.
+#define DISCOS_BIN 2
+
+namespace discos {
+
+struct GridDev {
+    int nx, ny, nz, nxh;
+    double h, inv_h, Lx, Ly, Lz;
+    int nbx, nby, nbz;  // cell-list bins per dimension
+};
+
+// Wall boundary data used by the field kernels.
+struct WallDev {
+    int type[2];              // DISCOS_BC_*
+    const double* value[2];   // [ny][nx] or null (= 0)
+    double eps;
+};
+
+__device__ __forceinline__ int wrapi(int n, int N) {
+    int r = n % N;
+    return r < 0 ? r + N : r;
+}
+
+__device__ __forceinline__ int floordiv(int a, int b) {
+    int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Positions that the kernels accept: finite, 0 <= z <= Lz, |x|, |y| moderate.
+__device__ __forceinline__ bool pos_ok(const GridDev& g, double x, double y, double z) {
+    const double big = 1.0e12 * g.h;
+    return (z >= 0.0) && (z <= g.Lz) && (fabs(x) < big) && (fabs(y) < big);
+}
+
+// 4-point Peskin weights (App. B, eq peskin1d).  For the node set {(n + off) h},
+// s = x / h - off, nodes i0 .. i0+3 with i0 = floor(s) - 1 and r = s - floor(s);
+// all four branches share q = sqrt(1 + 4 r - 4 r^2):
+//   w0 = (3 - 2r - q)/8, w1 = (3 - 2r + q)/8, w2 = (1 + 2r + q)/8, w3 = (1 + 2r - q)/8.
+__device__ __forceinline__ void peskin4(double s, int& i0, double w[4]) {
+    const double fl = floor(s);
+    const double r = s - fl;
+    const double q = sqrt(1.0 + 4.0 * r - 4.0 * r * r);
+    i0 = (int)fl - 1;
+    w[0] = (3.0 - 2.0 * r - q) * 0.125;
+    w[1] = (3.0 - 2.0 * r + q) * 0.125;
+    w[2] = (1.0 + 2.0 * r + q) * 0.125;
+    w[3] = (1.0 + 2.0 * r - q) * 0.125;
+}
+
+// x-coordinate in cells, reduced to a bounded range before the int conversion
+// (positions may be anywhere on the periodic line).
+__device__ __forceinline__ double reduce_periodic(double x, double L) {
+    double r = fmod(x, L);
+    return r < 0.0 ? r + L : r;
+}
+
+__device__ __forceinline__ void set_flag(int* flags, int f) { atomicOr(flags, f); }
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) ------------------------------------
+struct u32x4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    u32x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * 1.1102230246251565e-16;
+}
+
+// Two N(0,1) numbers for counter (index, step, tag, pair) and key seed (Box-Muller).
+__device__ __forceinline__ void normal_pair(uint64_t seed, uint64_t step, uint32_t tag,
+                                            uint32_t pair, uint32_t index, double& n0,
+                                            double& n1) {
+    u32x4 o = philox4x32_10(index, (uint32_t)(step & 0xFFFFFFFFull), tag, pair,
+                            (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
+    const double u1 = u01(o.v[0], o.v[1]);
+    const double u2 = u01(o.v[2], o.v[3]);
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 2.0 * M_PI * u2;
+    n0 = rad * cos(ang);
+    n1 = rad * sin(ang);
+}
+
+#define DISCOS_TAG_DRY 1u
+#define DISCOS_TAG_STRESS_DIAG 2u
+#define DISCOS_TAG_STRESS_EDGE 3u
+#define DISCOS_TAG_RFD 4u
+
+// Cell-list bin of a position (bins of DISCOS_BIN cells; z clamped into the channel).
+__device__ __forceinline__ int bin_of(const GridDev& g, double x, double y, double z, int& bx,
+                                      int& by, int& bz) {
+    int cx = (int)floor(reduce_periodic(x, g.Lx) * g.inv_h);
+    int cy = (int)floor(reduce_periodic(y, g.Ly) * g.inv_h);
+    int cz = (int)floor(z * g.inv_h);
+    cx = min(max(cx, 0), g.nx - 1);
+    cy = min(max(cy, 0), g.ny - 1);
+    cz = min(max(cz, 0), g.nz - 1);
+    bx = cx / DISCOS_BIN;
+    by = cy / DISCOS_BIN;
+    bz = cz / DISCOS_BIN;
+    return (bz * g.nby + by) * g.nbx + bx;
+}
+
+}  // namespace discos

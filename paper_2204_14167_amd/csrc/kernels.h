@@ -1,0 +1,80 @@
+// Host-side view of the context and the launchers shared by the kernel files.
+#pragma once
+
+#include <algorithm>
+#include <string>
+
+#include "common.h"
+
+namespace discos {
+
+struct Ctx {
+    discos_grid grid;
+    GridDev gd;
+    int64_t n_max;
+    int device;
+    int64_t ncell;   // nx ny nz
+    int64_t nface_z; // nx ny (nz + 1)
+    int64_t nmode;   // (nx/2 + 1) ny
+    int64_t nbins;
+    // sorted ion copies (cell-list order) and the permutation back
+    double *sx, *sy, *sz, *sq;
+    int *sid, *ssp, *perm;
+    int *ion_bin, *ion_rank;
+    int *bin_count, *bin_start, *scan_tmp;
+    // grid work arrays
+    double *rho, *phi;
+    double2* spec;   // half spectrum [nz][ny][nx/2+1]
+    double* cprime;  // Thomas coefficients [nz][nmode]
+    double* fp;      // [3][n_max] per-ion forces in cell-list order
+    double2 *tw_x, *tw_y;
+    int* flags;
+    void* pool;
+    size_t pool_bytes;
+    hipStream_t last_stream;
+    std::string err;
+    // stage timing (discos_profile): one row of DISCOS_NSTAGE + 1 events per step,
+    // for up to PROF_MAX steps
+    int profile;
+    int prof_steps;
+    hipEvent_t* ev;
+};
+
+#define PROF_MAX 512
+
+// Record the event that closes stage k of the current profiled step.
+inline void stage_mark(Ctx* c, int k, hipStream_t s) {
+    if (c->profile && c->prof_steps < PROF_MAX)
+        hipEventRecord(c->ev[(size_t)c->prof_steps * (DISCOS_NSTAGE + 1) + k], s);
+}
+
+WallDev wall_of(const discos_params* p);
+
+// Cell list from positions (and optional companions) in caller order.
+int build_cell_list(Ctx* c, int n, const double* x, const double* y, const double* z,
+                    const double* q, const int* id, const int* sp, hipStream_t s);
+void fill_f64(double* a, int64_t n, double v, hipStream_t s);
+
+// S^es over the cell list: rho = S q (sorted copies sx..sq) with fold signs; optional
+// wall terms of the discrete Poisson problem.
+int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out, hipStream_t s);
+
+// Poisson solve in place capable (rhs may equal phi).
+int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
+                  int mark_base = -1);
+
+// E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi (DISCOS_INTERP_PHI).
+int interp_es(Ctx* c, int op, int n, const double* x, const double* y, const double* z,
+              const double* phi, const double* q, const discos_params* p, double* out,
+              int64_t out_stride, hipStream_t s);
+
+// Near-field + wall (+ LJ) forces over the cell list; out[perm] += F if scatter, else
+// out[sorted] += F.
+int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
+                      int scatter_to_caller, hipStream_t s);
+
+// Fused force completion and dry update of the sorted ions, written to the caller arrays.
+int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, double* pos,
+                     double* q, int* id, int* sp, hipStream_t s);
+
+}  // namespace discos

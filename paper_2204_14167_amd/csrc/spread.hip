@@ -1,0 +1,183 @@
+// S^es: charge spreading with the 4-point Peskin kernel and image folding at the
+// walls (eq kernel2, Sec. II.A image construction, Sec. II.B.1 image signs).
+//
+// One workgroup owns a tile of cells and accumulates into LDS every contribution
+// that lands in it: it gathers the ions of the tile and of a two-cell halo from the
+// cell list (one bin of DISCOS_BIN cells), computes each ion's weights once, adds
+// the products that fall inside the tile with LDS atomics, and writes the tile to
+// HBM once with coalesced stores.  No global atomics and no zero-fill of the output.
+#include "kernels.h"
+
+namespace discos {
+
+#define SP_TX 16
+#define SP_TY 16
+#define SP_TZ 16
+#define SP_THREADS 256
+#define SP_MAXR 256
+
+// Row ranges of the cell list covering cells [x0-2, x0+tx+1] x [y0-2, y0+ty+1] x
+// [z0-2, z0+tz+1] (clipped to the channel in z, periodic in x and y without
+// duplicates).  Built by the whole workgroup: thread t owns candidate range t
+// (at most 11 z-bins x 11 y-bins x 2 x-segments = 242 < SP_MAXR for 16^3 tiles
+// and two-cell bins), then an exclusive scan of the range lengths gives rpre.
+// Returns the number of ranges (empty ones included).
+__device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
+                           int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan) {
+    int sa[2], sb[2], nseg;
+    {
+        const int lo = floordiv(x0 - 2, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
+        if (hi - lo + 1 >= g.nbx) {
+            nseg = 1;
+            sa[0] = 0;
+            sb[0] = g.nbx - 1;
+        } else {
+            const int a = wrapi(lo, g.nbx), b = wrapi(hi, g.nbx);
+            if (a <= b) {
+                nseg = 1;
+                sa[0] = a;
+                sb[0] = b;
+            } else {
+                nseg = 2;
+                sa[0] = a;
+                sb[0] = g.nbx - 1;
+                sa[1] = 0;
+                sb[1] = b;
+            }
+        }
+    }
+    int ylo = floordiv(y0 - 2, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
+    if (yhi - ylo + 1 >= g.nby) {
+        ylo = 0;
+        yhi = g.nby - 1;
+    }
+    const int czlo = max(z0 - 2, 0), czhi = min(z0 + tz + 1, g.nz - 1);
+    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
+    const int nyb = yhi - ylo + 1;
+    const int ncand = (bzhi - bzlo + 1) * nyb * nseg;
+    const int t = threadIdx.x;
+    int len = 0;
+    if (t < ncand && t < SP_MAXR) {
+        const int sgi = t % nseg;
+        const int yy = ylo + (t / nseg) % nyb;
+        const int bz = bzlo + t / (nseg * nyb);
+        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
+        const int st = bin_start[row + sa[sgi]];
+        const int en = bin_start[row + sb[sgi] + 1];
+        rstart[t] = st;
+        len = en - st;
+    }
+    // inclusive Hillis-Steele scan over the workgroup
+    scan[t] = len;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int a = (t >= off) ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += a;
+        __syncthreads();
+    }
+    const int nr = min(ncand, SP_MAXR);
+    if (t < nr) rpre[t] = scan[t] - len;
+    if (t == nr - 1) rpre[nr] = scan[t];
+    __syncthreads();
+    return nr;
+}
+
+__device__ __forceinline__ int find_range(const int* rpre, int nr, int f) {
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rpre[mid] <= f)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(SP_THREADS)
+spread_charge_kernel(GridDev g, const double* __restrict__ sx, const double* __restrict__ sy,
+                     const double* __restrict__ sz, const double* __restrict__ sq,
+                     const int* __restrict__ bin_start, double sign_lo, double sign_hi,
+                     int add_bc, WallDev wall, double* __restrict__ out) {
+    __shared__ double acc[SP_TX * SP_TY * SP_TZ];
+    __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
+    const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * SP_TZ;
+    const int tz = min(SP_TZ, g.nz - z0);
+    const int ncell = tx * ty * tz;
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
+    const int nr = tile_ranges(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
+    const int total = rpre[nr];
+    const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+        const int r = find_range(rpre, nr, f);
+        const int i = rstart[r] + (f - rpre[r]);
+        const double x = sx[i], y = sy[i], z = sz[i];
+        if (!pos_ok(g, x, y, z)) continue;
+        int ix0, iy0, iz0;
+        double wx[4], wy[4], wz[4];
+        peskin4(reduce_periodic(x, g.Lx) * g.inv_h - 0.5, ix0, wx);
+        peskin4(reduce_periodic(y, g.Ly) * g.inv_h - 0.5, iy0, wy);
+        peskin4(z * g.inv_h - 0.5, iz0, wz);
+        const double scale = sq[i] * inv_h3;
+        int lxs[4], lys[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lxs[a] = wrapi(ix0 + a - x0, g.nx);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lys[b] = wrapi(iy0 + b - y0, g.ny);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int kz = iz0 + c;
+            double sgn = 1.0;
+            if (kz < 0) {
+                kz = -1 - kz;
+                sgn = sign_lo;
+            } else if (kz >= g.nz) {
+                kz = 2 * g.nz - 1 - kz;
+                sgn = sign_hi;
+            }
+            const int lz = kz - z0;
+            if (lz < 0 || lz >= tz) continue;
+            const double wzc = scale * sgn * wz[c];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (lys[b] >= ty) continue;
+                const double wyz = wzc * wy[b];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    if (lxs[a] >= tx) continue;
+                    atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int lx = k % tx, ly = (k / tx) % ty, lz = k / (tx * ty);
+        const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
+        double v = acc[k];
+        if (add_bc) {
+            for (int w = 0; w < 2; ++w) {
+                if (gk != (w == 0 ? 0 : g.nz - 1)) continue;
+                const double bv = wall.value[w] ? wall.value[w][(size_t)gj * g.nx + gi] : 0.0;
+                v += (wall.type[w] == DISCOS_BC_DIRICHLET) ? 2.0 * wall.eps * bv * g.inv_h * g.inv_h
+                                                           : bv * g.inv_h;
+            }
+        }
+        out[((size_t)gk * g.ny + gj) * g.nx + gi] = v;
+    }
+}
+
+int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int tx = std::min(SP_TX, g.nx), ty = std::min(SP_TY, g.ny);
+    dim3 grid(g.nx / tx, g.ny / ty, (g.nz + SP_TZ - 1) / SP_TZ);
+    const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sx, c->sy, c->sz, c->sq, c->bin_start,
+                                                     s_lo, s_hi, add_bc, wall_of(p), out);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+}  // namespace discos

@@ -1,0 +1,267 @@
+"""ctypes binding of libdiscos.so (the C ABI in include/discos.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+arrays are torch tensors on the GPU (float64 / int32, contiguous); the stream is
+torch's current HIP stream.  Importing this module does not load the library;
+the first call does, and raises if the built library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdiscos.so")
+
+OK = 0
+E_ARG, E_SHAPE, E_HIP, E_OUT_OF_DOMAIN, E_NOT_NEUTRAL, E_NONFINITE, E_CAPACITY = (
+    -1, -2, -3, -4, -5, -6, -7)
+BC_DIRICHLET, BC_NEUMANN = 0, 1
+SPREAD_CHARGE, SPREAD_FORCE, SPREAD_ADD_BC = 0, 1, 0x100
+INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
+STEP_DRY = 0
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class DiscosGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double)]
+
+
+class DiscosParams(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("bc_type", ctypes.c_int32 * 2),
+        ("bc_value", ctypes.c_void_p * 2),
+        ("e_ext", ctypes.c_double * 3),
+        ("psi", ctypes.c_double),
+        ("p3m_table", ctypes.c_void_p),
+        ("p3m_len", ctypes.c_int32),
+        ("p3m_dr", ctypes.c_double),
+        ("wall_on", ctypes.c_int32),
+        ("wall_sigma", ctypes.c_double),
+        ("wall_xi", ctypes.c_double),
+        ("wall_cut", ctypes.c_double),
+        ("lj_on", ctypes.c_int32),
+        ("lj_sigma", ctypes.c_void_p),
+        ("lj_xi", ctypes.c_void_p),
+        ("lj_cut_factor", ctypes.c_double),
+        ("lj_range", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("nspecies", ctypes.c_int32),
+        ("radius", ctypes.c_void_p),
+        ("mob_coef", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class DiscosIons(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("pos", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("id", ctypes.c_void_p), ("species", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdiscos.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2204_14167_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64
+        L.discos_create.argtypes = [ctypes.POINTER(DiscosGrid), i64, ctypes.c_uint32,
+                                    ctypes.POINTER(vp)]
+        L.discos_destroy.argtypes = [vp]
+        L.discos_spread.argtypes = [vp, i32, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
+        L.discos_solve_poisson.argtypes = [vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
+        L.discos_interpolate.argtypes = [vp, i32, i64, vp, vp, vp, ctypes.POINTER(DiscosParams),
+                                         vp, vp]
+        L.discos_near_field.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
+        L.discos_step.argtypes = [vp, ctypes.POINTER(DiscosIons), ctypes.POINTER(DiscosParams),
+                                  u64, i32, vp]
+        L.discos_check.argtypes = [vp]
+        L.discos_profile.argtypes = [vp, i32]
+        L.discos_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int)]
+        L.discos_last_error.argtypes = [vp]
+        L.discos_last_error.restype = ctypes.c_char_p
+        for name in ("discos_create", "discos_destroy", "discos_spread", "discos_solve_poisson",
+                     "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
+                     "discos_profile", "discos_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class DiscosError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"discos error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f64(a, device):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+class Params:
+    """Device copy of a parameter dict (keys as produced by workloads.make_params)
+    plus the ctypes struct pointing into it."""
+
+    def __init__(self, p, grid, device="cuda"):
+        nx, ny = grid[0], grid[1]
+        self._keep = []
+        s = DiscosParams()
+        s.eps = p["eps"]
+        s.bc_type[0], s.bc_type[1] = int(p["bc_types"][0]), int(p["bc_types"][1])
+        for w in (0, 1):
+            v = p["bc_values"][w] if p.get("bc_values") is not None else None
+            if v is None:
+                s.bc_value[w] = None
+            else:
+                t = _f64(np.broadcast_to(np.asarray(v, dtype=np.float64), (ny, nx)), device)
+                self._keep.append(t)
+                s.bc_value[w] = t.data_ptr()
+        e = p.get("e_ext", (0.0, 0.0, 0.0))
+        for k in range(3):
+            s.e_ext[k] = float(e[k])
+        s.psi = p.get("psi", 4.0)
+        if p.get("p3m_table") is not None:
+            t = _f64(p["p3m_table"], device)
+            self._keep.append(t)
+            s.p3m_table = t.data_ptr()
+            s.p3m_len = t.numel()
+            s.p3m_dr = p["p3m_dr"]
+        s.wall_on = int(bool(p.get("wall_on", False)))
+        s.wall_sigma = p.get("wall_sigma", 1.0)
+        s.wall_xi = p.get("wall_xi", 1.0)
+        s.wall_cut = p.get("wall_cut", 3.5)
+        s.lj_on = int(bool(p.get("lj_on", False)))
+        if s.lj_on:
+            ls = _f64(p["lj_sigma"], device)
+            lx = _f64(p["lj_xi"], device)
+            self._keep += [ls, lx]
+            s.lj_sigma, s.lj_xi = ls.data_ptr(), lx.data_ptr()
+            s.lj_cut_factor = p["lj_cut_factor"]
+            s.lj_range = float(p["lj_cut_factor"] * np.max(p["lj_sigma"]))
+        s.kT = p.get("kT", 1.0)
+        s.eta = p.get("eta", 1.0)
+        s.dt = p.get("dt", 0.0)
+        if p.get("radius") is not None:
+            r = _f64(p["radius"], device)
+            self._keep.append(r)
+            s.radius = r.data_ptr()
+            s.nspecies = r.numel()
+        if p.get("mob_coef") is not None:
+            c = _f64(p["mob_coef"], device)
+            self._keep.append(c)
+            s.mob_coef = c.data_ptr()
+        s.seed = int(p.get("seed", 0))
+        self.struct = s
+
+
+class Context:
+    """One grid and up to n_max ions; owns the library context."""
+
+    def __init__(self, nx, ny, nz, h=1.0, n_max=0):
+        self.grid = (int(nx), int(ny), int(nz), float(h))
+        g = DiscosGrid(int(nx), int(ny), int(nz), float(h))
+        h_ = ctypes.c_void_p()
+        rc = lib().discos_create(ctypes.byref(g), int(n_max), 0, ctypes.byref(h_))
+        if rc != OK:
+            raise DiscosError(rc, "discos_create failed")
+        self.handle = h_
+        self.n_max = int(n_max)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().discos_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc):
+        if rc != OK:
+            raise DiscosError(rc, lib().discos_last_error(self.handle).decode())
+
+    def params(self, p, device="cuda"):
+        return Params(p, self.grid, device)
+
+    @property
+    def cell_shape(self):
+        nx, ny, nz, _ = self.grid
+        return (nz, ny, nx)
+
+    # ---- entry points (same names as the C ABI) ---------------------------------
+    def spread(self, op, pos, w, params, out=None):
+        nz, ny, nx = self.cell_shape
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.float64, device=pos.device)
+        self._rc(lib().discos_spread(self.handle, op, pos.shape[1], _ptr(pos), _ptr(w),
+                                     ctypes.byref(params.struct), _ptr(out), _stream()))
+        return out
+
+    def solve_poisson(self, rhs, params, out=None):
+        if out is None:
+            out = torch.empty_like(rhs)
+        self._rc(lib().discos_solve_poisson(self.handle, _ptr(rhs), ctypes.byref(params.struct),
+                                            _ptr(out), _stream()))
+        return out
+
+    def interpolate(self, op, pos, field, params, aux=None, out=None):
+        n = pos.shape[1]
+        if out is None:
+            shape = (n,) if op == INTERP_PHI else (3, n)
+            out = torch.empty(shape, dtype=torch.float64, device=pos.device)
+        self._rc(lib().discos_interpolate(self.handle, op, n, _ptr(pos), _ptr(field), _ptr(aux),
+                                          ctypes.byref(params.struct), _ptr(out), _stream()))
+        return out
+
+    def near_field(self, pos, q, params, species=None, F=None):
+        n = pos.shape[1]
+        if F is None:
+            F = torch.zeros((3, n), dtype=torch.float64, device=pos.device)
+        self._rc(lib().discos_near_field(self.handle, n, _ptr(pos), _ptr(q), _ptr(species),
+                                         ctypes.byref(params.struct), _ptr(F), _stream()))
+        return F
+
+    def step(self, pos, q, ids, species, params, step, mode=STEP_DRY):
+        ions = DiscosIons(pos.shape[1], pos.data_ptr(), q.data_ptr(), ids.data_ptr(),
+                          species.data_ptr())
+        self._rc(lib().discos_step(self.handle, ctypes.byref(ions), ctypes.byref(params.struct),
+                                   int(step), mode, _stream()))
+
+    STAGES = ("cell_list", "spread", "fft_x", "fft_y", "z_solve", "ifft_y", "ifft_x",
+              "interp", "near_field_update")
+
+    def profile(self, enable=True):
+        self._rc(lib().discos_profile(self.handle, int(enable)))
+
+    def profile_read(self):
+        """{stage: ms} of the most recent profiled step (synchronises)."""
+        ms = (ctypes.c_double * 16)()
+        cnt = ctypes.c_int()
+        self._rc(lib().discos_profile_read(self.handle, ms, ctypes.byref(cnt)))
+        return {self.STAGES[k]: ms[k] for k in range(cnt.value)}
+
+    def check(self):
+        """Synchronise and raise on a sticky device-side error."""
+        self._rc(lib().discos_check(self.handle))

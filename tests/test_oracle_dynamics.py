@@ -127,6 +127,27 @@ def test_free_diffusion_statistics():
     np.testing.assert_array_equal(disp2[1:], disp[1:])
 
 
+def _reflect_by_iteration(z, Lz):
+    while z < 0.0 or z > Lz:
+        z = -z if z < 0.0 else 2.0 * Lz - z
+    return z
+
+
+def test_reflection_matches_repeated_reflection():
+    rng = np.random.default_rng(4)
+    Lz = 10.0
+    z = np.concatenate([rng.uniform(-95.0, 105.0, 2000), [-10.0, 20.0, -20.0, 30.0, 0.0, 10.0]])
+    got = dynamics.reflect_walls(z, Lz)
+    ref = np.array([_reflect_by_iteration(v, Lz) for v in z])
+    # one crossing is exact; multiple crossings agree to rounding of the fold
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    one = (z >= -Lz) & (z <= 2 * Lz)
+    np.testing.assert_array_equal(got[one], ref[one])
+    assert np.all((got >= 0) & (got <= Lz))
+    huge = dynamics.reflect_walls(np.array([1e12 + 3.0, -1e12 - 3.0]), Lz)
+    assert np.all((huge >= 0) & (huge <= Lz))
+
+
 def test_reflection_and_wrap():
     z = np.array([-0.5, 10.5, 3.0, -25.0, 0.0, 10.0])
     out = dynamics.reflect_walls(z, 10.0)
