@@ -295,8 +295,9 @@ def near_field(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
     in x and y.  Each ion j (including j = i) also has an image at
     (x_j, y_j, -z_j) with charge s_lo q_j and at (x_j, y_j, 2 Lz - z_j) with
     charge s_hi q_j; every image within psi of ion i adds the same correction
-    (force on i only).  Brute force over all pairs.  `targets` restricts the
-    output to a subset of ions (all ions are still sources).
+    (force on i only).  Pairs at zero separation are skipped.  Brute force over
+    all pairs.  `targets` restricts the output to a subset of ions (all ions are
+    still sources).
     """
     L = grid.L
     h = grid.h
@@ -318,7 +319,9 @@ def near_field(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
             d[0] -= L[0] * np.round(d[0] / L[0])
             d[1] -= L[1] * np.round(d[1] / L[1])
             r = np.sqrt((d * d).sum(axis=0))
-            mask = r < psi
+            # a pair at zero separation (an ion exactly on a wall and its own
+            # image, or two coincident ions) has no direction and is skipped
+            mask = (r < psi) & (r > 0.0)
             if not is_image:
                 mask[np.arange(len(ti)), ti] = False
             rr = np.where(mask, r, 1.0)

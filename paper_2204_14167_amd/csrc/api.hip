@@ -123,7 +123,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     const int64_t nblk = (c->nbins + 1023) / 1024 + 1;
     const int64_t nspec = c->nmode * g.nz;
     size_t bytes = 0;
-    bytes += 4 * carve_bytes(nm, sizeof(double));      // sx sy sz sq
+    bytes += carve_bytes(nm, sizeof(double4));         // sxyzq
     bytes += carve_bytes(3 * nm, sizeof(double));      // fp
     bytes += 5 * carve_bytes(nm, sizeof(int));         // sid ssp perm ion_bin ion_rank
     bytes += carve_bytes(c->nbins, sizeof(int));
@@ -141,10 +141,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     }
     c->pool_bytes = bytes;
     char* cur = static_cast<char*>(c->pool);
-    c->sx = carve<double>(cur, nm);
-    c->sy = carve<double>(cur, nm);
-    c->sz = carve<double>(cur, nm);
-    c->sq = carve<double>(cur, nm);
+    c->sxyzq = carve<double4>(cur, nm);
     c->fp = carve<double>(cur, 3 * nm);
     c->sid = carve<int>(cur, nm);
     c->ssp = carve<int>(cur, nm);
@@ -239,14 +236,16 @@ int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, cons
     if (!c) return DISCOS_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
-    if (n < 0 || n > 0x7FFFFFFF) return fail(c, DISCOS_E_SHAPE, "n out of range");
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
     if (n == 0) return DISCOS_OK;
     if (!pos || !field || !out) return fail(c, DISCOS_E_ARG, "null array");
     int rc = check_es_params(c, p);
     if (rc) return rc;
     if (op == DISCOS_INTERP_E || op == DISCOS_INTERP_FORCE || op == DISCOS_INTERP_PHI) {
         if (op == DISCOS_INTERP_FORCE && !aux) return fail(c, DISCOS_E_ARG, "charges (aux) missing");
-        rc = discos::interp_es(c, op, (int)n, pos, pos + n, pos + 2 * n, field, aux, p, out, n, s);
+        if (n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+        rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, aux, nullptr, nullptr, s);
+        if (!rc) rc = discos::interp_es_sorted(c, op, (int)n, field, p, out, n, 1, s);
         return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
     }
     return fail(c, DISCOS_E_ARG, "unknown interpolation op");
@@ -293,9 +292,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc) rc = discos::spread_charge_sorted(c, p, 1, c->rho, s);
     discos::stage_mark(c, 2, s);
     if (!rc) rc = discos::solve_poisson(c, c->rho, p, c->phi, s, 3);
-    if (!rc)
-        rc = discos::interp_es(c, DISCOS_INTERP_FORCE, ni, c->sx, c->sy, c->sz, c->phi, c->sq, p,
-                               c->fp, c->n_max, s);
+    if (!rc) rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, c->phi, p, c->fp, c->n_max, 0, s);
     discos::stage_mark(c, 8, s);
     if (!rc) rc = discos::force_update_dry(c, ni, p, step, pos, ions->q, ions->id, ions->species, s);
     discos::stage_mark(c, 9, s);

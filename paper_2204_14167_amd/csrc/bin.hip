@@ -115,17 +115,18 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
                                    const double* __restrict__ x, const double* __restrict__ y,
                                    const double* __restrict__ z, const double* __restrict__ q,
                                    const int* __restrict__ id, const int* __restrict__ sp,
-                                   double* __restrict__ sx, double* __restrict__ sy,
-                                   double* __restrict__ sz, double* __restrict__ sq,
+                                   GridDev g, double4* __restrict__ sxyzq,
                                    int* __restrict__ sid, int* __restrict__ ssp,
                                    int* __restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int d = start[ion_bin[i]] + ion_rank[i];
-    sx[d] = x[i];
-    sy[d] = y[i];
-    sz[d] = z[i];
-    if (q) sq[d] = q[i];
+    double xi = x[i], yi = y[i];
+    if (isfinite(xi) && isfinite(yi)) {
+        xi = reduce_periodic(xi, g.Lx);
+        yi = reduce_periodic(yi, g.Ly);
+    }
+    sxyzq[d] = make_double4(xi, yi, z[i], q ? q[i] : 0.0);
     if (id) sid[d] = id[i];
     if (sp) ssp[d] = sp[i];
     perm[d] = i;
@@ -146,8 +147,8 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
     scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp, c->bin_start, n);
     if (n > 0)
         bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
-                                                         x, y, z, q, id, sp, c->sx, c->sy, c->sz,
-                                                         c->sq, c->sid, c->ssp, c->perm);
+                                                         x, y, z, q, id, sp, g, c->sxyzq,
+                                                         c->sid, c->ssp, c->perm);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

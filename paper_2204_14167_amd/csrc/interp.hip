@@ -2,16 +2,32 @@
 // eq kernel1) with ghost values beyond the walls filled from the wall conditions
 // (Sec. II.B.1: ghosts satisfy the boundary condition on phi).
 //
-// E lives on the faces of the cell-centred phi (the staggered location of grad_h);
-// each component is gathered from its own face nodes, computing the face
-// differences on the fly from phi, so E is never stored.
+// E lives on the faces of the cell-centred phi (the staggered location of grad_h).
+// For an ion in cell (cx, cy, cz) every node any component needs lies in the 5^3
+// window of cells cx-2 .. cx+2 (likewise y, z), so the face differences fold into
+// per-dimension "derivative weights" and the three components become
+//   E_x = -(1/h) sum_z wc_z sum_y wc_y sum_x dw_x phi,
+//   E_y = -(1/h) sum_z wc_z sum_y dw_y sum_x wc_x phi,
+//   E_z = -(1/h) sum_z dw_z sum_y wc_y sum_x wc_x phi,
+// with wc the centre-node Peskin weights and dw_k = wf_{k-1} - wf_k the differences of
+// the face-node weights: 125 loads per ion instead of 240.
+//
+// One workgroup owns a tile of cells, stages phi on the tile plus its halo in LDS
+// (ghost layers included, so the gathers have no branches), and interpolates every
+// ion of the tile from the cell list.
 #include "kernels.h"
 
 namespace discos {
 
-// phi at cell (i, j, k), i and j already periodic, k in [-3, nz + 2]: ghost layer
-// -1-m is 2 phi_b - phi_m (Dirichlet) or phi_m + (2m+1) h sigma / eps (Neumann);
-// mirror rule at the top wall.
+#define IT_TX 16
+#define IT_TY 16
+#define IT_TZ 8
+#define IT_H 5  // halo cells: 2 below, 3 above (an ion exactly on x = L or z = Lz)
+#define IT_THREADS 256
+#define IT_MAXR 64
+
+// phi at cell (i, j, k), i and j periodic, any k: ghost layer -1-m is 2 phi_b - phi_m
+// (Dirichlet) or phi_m + (2m+1) h sigma / eps (Neumann); mirror rule at the top.
 __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const GridDev& g,
                                          const WallDev& w, int i, int j, int k) {
     if (k >= 0 && k < g.nz) return phi[((size_t)k * g.ny + j) * g.nx + i];
@@ -24,134 +40,162 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
     return base + (2 * m + 1) * g.h * v / w.eps;
 }
 
-__global__ void interp_es_kernel(GridDev g, WallDev w, int n, int op,
-                                 const double* __restrict__ px, const double* __restrict__ py,
-                                 const double* __restrict__ pz, const double* __restrict__ phi,
-                                 const double* __restrict__ q, double ex0, double ex1, double ex2,
-                                 double* __restrict__ out, int64_t out_stride,
-                                 int* __restrict__ flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double x = px[i], y = py[i], z = pz[i];
-    if (!pos_ok(g, x, y, z)) {
-        set_flag(flags, (isfinite(x) && isfinite(y) && isfinite(z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
-                                                                  : DISCOS_FLAG_NONFINITE);
-        if (op == DISCOS_INTERP_PHI) {
-            out[i] = 0.0;
-        } else {
-            out[i] = 0.0;
-            out[i + out_stride] = 0.0;
-            out[i + 2 * out_stride] = 0.0;
-        }
-        return;
+// Centre weights and face-difference weights on the 5-cell window c-2 .. c+2 of the
+// coordinate u (in cells).
+__device__ __forceinline__ int window_weights(double u, double wc5[5], double dw5[5]) {
+    int ic, iff;
+    double wc[4], wf[4];
+    peskin4(u - 0.5, ic, wc);
+    peskin4(u, iff, wf);
+    const int c = iff + 1;  // floor(u)
+    const bool shift = (ic - (c - 2)) != 0;  // centre window starts at c-2 or c-1
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double lo = (k < 4) ? wc[k] : 0.0;
+        const double hi = (k > 0) ? wc[k - 1] : 0.0;
+        wc5[k] = shift ? hi : lo;
     }
-    const double xr = reduce_periodic(x, g.Lx) * g.inv_h;
-    const double yr = reduce_periodic(y, g.Ly) * g.inv_h;
-    const double zr = z * g.inv_h;
-    int icx, icy, icz;
-    double wcx[4], wcy[4], wcz[4];
-    peskin4(xr - 0.5, icx, wcx);
-    peskin4(yr - 0.5, icy, wcy);
-    peskin4(zr - 0.5, icz, wcz);
-    int jx[4], jy[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) jx[a] = wrapi(icx + a, g.nx);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) jy[b] = wrapi(icy + b, g.ny);
-
-    if (op == DISCOS_INTERP_PHI) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double row = 0.0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) row += wcx[a] * phi_at(phi, g, w, jx[a], jy[b], icz + c);
-                acc += wcz[c] * wcy[b] * row;
-            }
-        out[i] = acc;
-        return;
-    }
-
-    int ifx, ify, ifz;
-    double wfx[4], wfy[4], wfz[4];
-    peskin4(xr, ifx, wfx);
-    peskin4(yr, ify, wfy);
-    peskin4(zr, ifz, wfz);
-    const double mih = -g.inv_h;
-
-    // E_x on x-faces (i h, (j+1/2) h, (k+1/2) h): face a uses cells a-1 and a
-    double Ex = 0.0;
-    {
-        int cx[5];
-#pragma unroll
-        for (int a = 0; a < 5; ++a) cx[a] = wrapi(ifx - 1 + a, g.nx);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double v[5];
-#pragma unroll
-                for (int a = 0; a < 5; ++a) v[a] = phi_at(phi, g, w, cx[a], jy[b], icz + c);
-                double row = 0.0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) row += wfx[a] * (mih * (v[a + 1] - v[a]));
-                Ex += wcz[c] * wcy[b] * row;
-            }
-    }
-    // E_y on y-faces
-    double Ey = 0.0;
-    {
-        int cy[5];
-#pragma unroll
-        for (int b = 0; b < 5; ++b) cy[b] = wrapi(ify - 1 + b, g.ny);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double v[5];
-#pragma unroll
-                for (int b = 0; b < 5; ++b) v[b] = phi_at(phi, g, w, jx[a], cy[b], icz + c);
-                double row = 0.0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) row += wfy[b] * (mih * (v[b + 1] - v[b]));
-                Ey += wcz[c] * wcx[a] * row;
-            }
-    }
-    // E_z on z-faces ((i+1/2) h, (j+1/2) h, k h): face c uses cells c-1 and c (ghosts)
-    double Ez = 0.0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            double v[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) v[c] = phi_at(phi, g, w, jx[a], jy[b], ifz - 1 + c);
-            double col = 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) col += wfz[c] * (mih * (v[c + 1] - v[c]));
-            Ez += wcy[b] * wcx[a] * col;
-        }
-    if (op == DISCOS_INTERP_FORCE) {
-        const double qi = q[i];
-        Ex = qi * (Ex + ex0);
-        Ey = qi * (Ey + ex1);
-        Ez = qi * (Ez + ex2);
-    }
-    out[i] = Ex;
-    out[i + out_stride] = Ey;
-    out[i + 2 * out_stride] = Ez;
+    // faces c-1 .. c+2 use cells (c-2, c-1) .. (c+1, c+2)
+    dw5[0] = -wf[0];
+    dw5[1] = wf[0] - wf[1];
+    dw5[2] = wf[1] - wf[2];
+    dw5[3] = wf[2] - wf[3];
+    dw5[4] = wf[3];
+    return c;
 }
 
-int interp_es(Ctx* c, int op, int n, const double* x, const double* y, const double* z,
-              const double* phi, const double* q, const discos_params* p, double* out,
-              int64_t out_stride, hipStream_t s) {
+__global__ void __launch_bounds__(IT_THREADS)
+interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ bin_start, const int* __restrict__ perm,
+                 const double* __restrict__ phi, double ex0, double ex1, double ex2,
+                 double* __restrict__ out, int64_t stride, int scatter, int* __restrict__ flags) {
+    constexpr int LX = IT_TX + IT_H, LY = IT_TY + IT_H, LZ = IT_TZ + IT_H;
+    __shared__ double tile[LZ * LY * LX];
+    __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
+    const int tx = min(IT_TX, g.nx), ty = min(IT_TY, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * IT_TZ;
+    const int tz = min(IT_TZ, g.nz - z0);
+    const int lxn = tx + IT_H, lyn = ty + IT_H, lzn = tz + IT_H;
+    // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled
+    for (int e = threadIdx.x; e < lxn * lyn * lzn; e += blockDim.x) {
+        const int lx = e % lxn, ly = (e / lxn) % lyn, lz = e / (lxn * lyn);
+        tile[(lz * LY + ly) * LX + lx] =
+            phi_at(phi, g, w, wrapi(x0 - 2 + lx, g.nx), wrapi(y0 - 2 + ly, g.ny), z0 - 2 + lz);
+    }
+    // ions of the tile: rows (bz, by) of tx / DISCOS_BIN contiguous bins
+    const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
+    const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
+    const int nrows = (bz1 - bz0 + 1) * nbyt;
+    {
+        // thread t < nrows owns row t; a workgroup scan of the row lengths gives rpre
+        int len = 0;
+        const int t = threadIdx.x;
+        if (t < nrows) {
+            const int bz = bz0 + t / nbyt, by = y0 / DISCOS_BIN + t % nbyt;
+            const int row = (bz * g.nby + by) * g.nbx + x0 / DISCOS_BIN;
+            const int st = bin_start[row];
+            rstart[t] = st;
+            len = bin_start[row + nbxt] - st;
+        }
+        scan[t] = len;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int a = (t >= off) ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += a;
+            __syncthreads();
+        }
+        if (t < nrows) rpre[t] = scan[t] - len;
+        if (t == nrows - 1) rpre[nrows] = scan[t];
+    }
+    __syncthreads();
+    const int total = rpre[nrows];
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+        int r = 0, hi = nrows - 1;
+        while (r < hi) {  // last row with rpre[row] <= f
+            const int mid = (r + hi + 1) >> 1;
+            if (rpre[mid] <= f)
+                r = mid;
+            else
+                hi = mid - 1;
+        }
+        const int i = rstart[r] + (f - rpre[r]);
+        const int o = scatter ? perm[i] : i;
+        const double4 a4 = sxyzq[i];
+        bool ok = pos_ok(g, a4.x, a4.y, a4.z);
+        double wcx[5], dwx[5], wcy[5], dwy[5], wcz[5], dwz[5];
+        int lx0 = 0, ly0 = 0, lz0 = 0;
+        if (ok) {
+            const int cx = window_weights(a4.x * g.inv_h, wcx, dwx);
+            const int cy = window_weights(a4.y * g.inv_h, wcy, dwy);
+            const int cz = window_weights(a4.z * g.inv_h, wcz, dwz);
+            lx0 = wrapi(cx - x0, g.nx);
+            ly0 = wrapi(cy - y0, g.ny);
+            lz0 = cz - z0;
+            ok = lx0 >= 0 && lx0 <= tx && ly0 >= 0 && ly0 <= ty && lz0 >= 0 && lz0 <= tz;
+        }
+        if (!ok) {
+            set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z))
+                                ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                : DISCOS_FLAG_NONFINITE);
+            out[o] = 0.0;
+            if (op != DISCOS_INTERP_PHI) {
+                out[o + stride] = 0.0;
+                out[o + 2 * stride] = 0.0;
+            }
+            continue;
+        }
+        double Ex = 0.0, Ey = 0.0, Ez = 0.0, P = 0.0;
+#pragma unroll
+        for (int kz = 0; kz < 5; ++kz) {
+            double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+            for (int ky = 0; ky < 5; ++ky) {
+                const double* row = &tile[((lz0 + kz) * LY + ly0 + ky) * LX + lx0];
+                double d = 0.0, c = 0.0;
+#pragma unroll
+                for (int kx = 0; kx < 5; ++kx) {
+                    const double v = row[kx];
+                    d += dwx[kx] * v;
+                    c += wcx[kx] * v;
+                }
+                ax += wcy[ky] * d;
+                ay += dwy[ky] * c;
+                az += wcy[ky] * c;
+            }
+            Ex += wcz[kz] * ax;
+            Ey += wcz[kz] * ay;
+            Ez += dwz[kz] * az;
+            P += wcz[kz] * az;
+        }
+        if (op == DISCOS_INTERP_PHI) {
+            out[o] = P;
+            continue;
+        }
+        Ex *= -g.inv_h;
+        Ey *= -g.inv_h;
+        Ez *= -g.inv_h;
+        if (op == DISCOS_INTERP_FORCE) {
+            const double qi = a4.w;
+            Ex = qi * (Ex + ex0);
+            Ey = qi * (Ey + ex1);
+            Ez = qi * (Ez + ex2);
+        }
+        out[o] = Ex;
+        out[o + stride] = Ey;
+        out[o + 2 * stride] = Ez;
+    }
+}
+
+int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_params* p,
+                     double* out, int64_t out_stride, int scatter, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
-    const int T = 256;
-    interp_es_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, wall_of(p), n, op, x, y, z, phi, q,
-                                                   p->e_ext[0], p->e_ext[1], p->e_ext[2], out,
-                                                   out_stride, c->flags);
+    const GridDev& g = c->gd;
+    const int tx = std::min(IT_TX, g.nx), ty = std::min(IT_TY, g.ny);
+    dim3 grid(g.nx / tx, g.ny / ty, (g.nz + IT_TZ - 1) / IT_TZ);
+    interp_es_kernel<<<grid, IT_THREADS, 0, s>>>(g, wall_of(p), op, c->sxyzq, c->bin_start, c->perm,
+                                                 phi, p->e_ext[0], p->e_ext[1], p->e_ext[2], out,
+                                                 out_stride, scatter, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

@@ -17,8 +17,9 @@ struct Ctx {
     int64_t nface_z; // nx ny (nz + 1)
     int64_t nmode;   // (nx/2 + 1) ny
     int64_t nbins;
-    // sorted ion copies (cell-list order) and the permutation back
-    double *sx, *sy, *sz, *sq;
+    // sorted ion copies (cell-list order): (x, y, z, q) with x, y reduced into
+    // [0, L], plus ids, species and the permutation back to caller order
+    double4* sxyzq;
     int *sid, *ssp, *perm;
     int *ion_bin, *ion_rank;
     int *bin_count, *bin_start, *scan_tmp;
@@ -63,10 +64,10 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
                   int mark_base = -1);
 
-// E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi (DISCOS_INTERP_PHI).
-int interp_es(Ctx* c, int op, int n, const double* x, const double* y, const double* z,
-              const double* phi, const double* q, const discos_params* p, double* out,
-              int64_t out_stride, hipStream_t s);
+// E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi
+// (DISCOS_INTERP_PHI) for the ions of the cell list; out[perm[i]] if scatter, else out[i].
+int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_params* p,
+                     double* out, int64_t out_stride, int scatter, hipStream_t s);
 
 // Near-field + wall (+ LJ) forces over the cell list; out[perm] += F if scatter, else
 // out[sorted] += F.

@@ -9,7 +9,8 @@
 namespace discos {
 
 struct NearDev {
-    double psi, psi2g, inv4pieps, h, inv_h2, dr;
+    double psi, psi2g, inv4pieps, h, inv_h2, inv_hdr;
+    double rsearch;  // search radius: psi, or the LJ range if larger
     const double* tab;
     int tablen;
     int R;  // search radius in bins
@@ -30,11 +31,12 @@ static NearDev near_of(const Ctx* c, const discos_params* p) {
     d.inv4pieps = 1.0 / (4.0 * M_PI * p->eps);
     d.h = c->grid.h;
     d.inv_h2 = 1.0 / (c->grid.h * c->grid.h);
-    d.dr = p->p3m_dr;
+    d.inv_hdr = 1.0 / (c->grid.h * p->p3m_dr);
     d.tab = p->p3m_table;
     d.tablen = p->p3m_len;
     double range = p->psi;
     if (p->lj_on) range = std::max(range, p->lj_range);
+    d.rsearch = range;
     d.R = (int)std::ceil(range / (DISCOS_BIN * c->grid.h));
     d.s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
@@ -53,18 +55,21 @@ static NearDev near_of(const Ctx* c, const discos_params* p) {
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
 
 // F^C - F^P for one pair (or ion-image pair) at separation d, charge product qq.
+// A pair at zero separation has no direction and contributes nothing.
 __device__ __forceinline__ void es_pair(double dx, double dy, double dz, double qq,
                                         const NearDev& P, double& fx, double& fy, double& fz) {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < P.psi2g)) return;
+    if (!(r2 < P.psi2g) || !(r2 > 0.0)) return;
     const double r = sqrt(r2);
     if (!(r < P.psi)) return;
-    const double t = (r / P.h) / P.dr;
-    int k = (int)floor(t);
+    const double inv_r = 1.0 / r;
+    const double t = r * P.inv_hdr;
+    int k = (int)t;
     const double f = t - k;
     k = min(k, P.tablen - 2);
-    const double gv = P.tab[k] * (1.0 - f) + P.tab[k + 1] * f;
-    const double mag = qq * P.inv4pieps * (1.0 / (r * r) - gv * P.inv_h2) / r;
+    const double g0 = P.tab[k], g1 = P.tab[k + 1];
+    const double gv = g0 * (1.0 - f) + g1 * f;
+    const double mag = qq * P.inv4pieps * (inv_r * inv_r - gv * P.inv_h2) * inv_r;
     fx += mag * dx;
     fy += mag * dy;
     fz += mag * dz;
@@ -72,7 +77,7 @@ __device__ __forceinline__ void es_pair(double dx, double dy, double dz, double 
 
 __device__ __forceinline__ void lj_pair(double dx, double dy, double dz, int si, int sj,
                                         const NearDev& P, double& fx, double& fy, double& fz) {
-    if (si < 0 || si >= P.nsp || sj < 0 || sj >= P.nsp) return;  // flagged by the update / caller
+    if (si < 0 || si >= P.nsp || sj < 0 || sj >= P.nsp) return;  // flagged by the caller
     const double sig = P.ljs[si * P.nsp + sj];
     const double xi = P.ljx[si * P.nsp + sj];
     const double cut = P.ljf * sig;
@@ -93,39 +98,22 @@ __device__ __forceinline__ double du93(double y, const NearDev& P) {
     return c93 * P.wxi * (-9.0 * pow(P.wsig, 9.0) / pow(y, 10.0) + 3.0 * pow(P.wsig, 3.0) / pow(y, 4.0));
 }
 
-// x-segments of bins bx-R .. bx+R on the periodic row (2R+1 <= nbx, checked on host).
-__device__ __forceinline__ int row_segments(int bx, int R, int nbx, int* sa, int* sb) {
-    const int lo = bx - R, hi = bx + R;
-    if (lo < 0) {
-        sa[0] = lo + nbx;
-        sb[0] = nbx - 1;
-        sa[1] = 0;
-        sb[1] = hi;
-        return 2;
-    }
-    if (hi >= nbx) {
-        sa[0] = lo;
-        sb[0] = nbx - 1;
-        sa[1] = 0;
-        sb[1] = hi - nbx;
-        return 2;
-    }
-    sa[0] = lo;
-    sb[0] = hi;
-    return 1;
-}
-
-// Image mode: 0 = real ions (skip j == i), 1 = images at -z_j, 2 = images at 2 Lz - z_j.
-__device__ void near_force(int i, double xi, double yi, double zi, double qi, int spi,
-                           const double* __restrict__ sx, const double* __restrict__ sy,
-                           const double* __restrict__ sz, const double* __restrict__ sq,
+// Near-field force on ion i (cell-list index) from the real ions within the search
+// radius (mode 0) and from the wall images (modes 1: -z_j, 2: 2 Lz - z_j).  Rows of
+// bins are visited in unwrapped coordinates around the ion; a row is skipped when its
+// slab is farther than the search radius, and only the x-bins that can reach the
+// sphere are read.  Periodic copies get an explicit shift of +-L, so no per-pair
+// minimum-image arithmetic is needed (2R+1 <= nbx, nby is checked on the host).
+__device__ void near_force(int i, double4 me, int spi, const double4* __restrict__ sxyzq,
                            const int* __restrict__ ssp, const int* __restrict__ bin_start,
                            const GridDev& g, const NearDev& P, double& Fx, double& Fy,
                            double& Fz) {
+    const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
+    const double Bh = DISCOS_BIN * g.h;
+    const double inv_Bh = 1.0 / Bh;
+    const double rs2 = P.rsearch * P.rsearch;
     int bx, by, bz;
     bin_of(g, xi, yi, zi, bx, by, bz);
-    int sa[2], sb[2];
-    const int nseg = row_segments(bx, P.R, g.nbx, sa, sb);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int mode = 0; mode < 3; ++mode) {
         int zlo, zhi;
@@ -144,28 +132,64 @@ __device__ void near_force(int i, double xi, double yi, double zi, double qi, in
             zhi = g.nbz - 1;
             sgn = P.s_hi;
         }
-        for (int cz = zlo; cz <= zhi; ++cz)
+        const double r2m = mode == 0 ? rs2 : P.psi * P.psi;
+        for (int cz = zlo; cz <= zhi; ++cz) {
+            const double zb0 = cz * Bh, zb1 = fmin((cz + 1) * Bh, g.Lz);
+            double dzm;
+            if (mode == 0)
+                dzm = fmax(0.0, fmax(zb0 - zi, zi - zb1));
+            else if (mode == 1)
+                dzm = zi + zb0;
+            else
+                dzm = (2.0 * g.Lz - zb1) - zi;
+            const double remz = r2m - dzm * dzm;
+            if (!(remz > 0.0)) continue;
             for (int dyb = -P.R; dyb <= P.R; ++dyb) {
-                const int row = (cz * g.nby + wrapi(by + dyb, g.nby)) * g.nbx;
+                const int cyu = by + dyb;
+                const double yb0 = cyu * Bh, yb1 = yb0 + Bh;
+                const double dym = fmax(0.0, fmax(yb0 - yi, yi - yb1));
+                const double rem = remz - dym * dym;
+                if (!(rem > 0.0)) continue;
+                const double wx = sqrt(rem);
+                const int bxl = max(bx - P.R, (int)floor((xi - wx) * inv_Bh));
+                const int bxh = min(bx + P.R, (int)floor((xi + wx) * inv_Bh));
+                if (bxl > bxh) continue;
+                const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
+                const double shy = cyu < 0 ? -g.Ly : (cyu >= g.nby ? g.Ly : 0.0);
+                const int row = (cz * g.nby + cy) * g.nbx;
+                // split [bxl, bxh] into at most two wrapped segments
+                int sa[2], sb[2];
+                double shx[2];
+                int nseg = 0;
+                if (bxl < 0) {
+                    sa[nseg] = bxl + g.nbx; sb[nseg] = g.nbx - 1; shx[nseg] = -g.Lx; ++nseg;
+                    if (bxh >= 0) { sa[nseg] = 0; sb[nseg] = bxh; shx[nseg] = 0.0; ++nseg; }
+                } else if (bxh >= g.nbx) {
+                    if (bxl < g.nbx) { sa[nseg] = bxl; sb[nseg] = g.nbx - 1; shx[nseg] = 0.0; ++nseg; }
+                    sa[nseg] = max(bxl - g.nbx, 0); sb[nseg] = bxh - g.nbx; shx[nseg] = g.Lx; ++nseg;
+                } else {
+                    sa[nseg] = bxl; sb[nseg] = bxh; shx[nseg] = 0.0; ++nseg;
+                }
                 for (int s = 0; s < nseg; ++s) {
                     const int j0 = bin_start[row + sa[s]], j1 = bin_start[row + sb[s] + 1];
+                    const double xs = xi - shx[s], ys = yi - shy;
                     for (int j = j0; j < j1; ++j) {
-                        double dx = xi - sx[j];
-                        dx -= g.Lx * rint(dx / g.Lx);
-                        double dy = yi - sy[j];
-                        dy -= g.Ly * rint(dy / g.Ly);
+                        const double4 o = sxyzq[j];
+                        const double dx = xs - o.x;
+                        const double dy = ys - o.y;
                         if (mode == 0) {
                             if (j == i) continue;
-                            const double dz = zi - sz[j];
-                            es_pair(dx, dy, dz, qi * sq[j], P, fx, fy, fz);
+                            const double dz = zi - o.z;
+                            es_pair(dx, dy, dz, qi * o.w, P, fx, fy, fz);
                             if (P.lj_on) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
                         } else {
-                            const double zimg = mode == 1 ? -sz[j] : 2.0 * g.Lz - sz[j];
-                            es_pair(dx, dy, zi - zimg, qi * (sgn * sq[j]), P, fx, fy, fz);
+                            const double zimg = mode == 1 ? -o.z : 2.0 * g.Lz - o.z;
+                            es_pair(dx, dy, zi - zimg, qi * (sgn * o.w), P, fx, fy, fz);
                         }
                     }
                 }
             }
+        }
     }
     if (P.wall_on) fz += -du93(zi, P) + du93(g.Lz - zi, P);
     Fx = fx;
@@ -173,20 +197,18 @@ __device__ void near_force(int i, double xi, double yi, double zi, double qi, in
     Fz = fz;
 }
 
-__global__ void near_field_kernel(GridDev g, NearDev P, int n, const double* __restrict__ sx,
-                                  const double* __restrict__ sy, const double* __restrict__ sz,
-                                  const double* __restrict__ sq, const int* __restrict__ ssp,
-                                  const int* __restrict__ bin_start, const int* __restrict__ perm,
-                                  double* __restrict__ out, int64_t stride, int scatter,
-                                  int* __restrict__ flags) {
+__global__ void near_field_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                                  const int* __restrict__ ssp, const int* __restrict__ bin_start,
+                                  const int* __restrict__ perm, double* __restrict__ out,
+                                  int64_t stride, int scatter, int* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double xi = sx[i], yi = sy[i], zi = sz[i];
-    if (!pos_ok(g, xi, yi, zi)) return;
+    const double4 me = sxyzq[i];
+    if (!pos_ok(g, me.x, me.y, me.z)) return;
     double Fx, Fy, Fz;
     const int spi = P.lj_on ? ssp[i] : 0;
     if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
-    near_force(i, xi, yi, zi, sq[i], spi, sx, sy, sz, sq, ssp, bin_start, g, P, Fx, Fy, Fz);
+    near_force(i, me, spi, sxyzq, ssp, bin_start, g, P, Fx, Fy, Fz);
     const int o = scatter ? perm[i] : i;
     out[o] += Fx;
     out[o + stride] += Fy;
@@ -197,9 +219,9 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
                       int scatter_to_caller, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
     const int T = 128;
-    near_field_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, near_of(c, p), n, c->sx, c->sy, c->sz,
-                                                    c->sq, c->ssp, c->bin_start, c->perm, out,
-                                                    out_stride, scatter_to_caller, c->flags);
+    near_field_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, near_of(c, p), n, c->sxyzq, c->ssp,
+                                                    c->bin_start, c->perm, out, out_stride,
+                                                    scatter_to_caller, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -243,8 +265,7 @@ __device__ __forceinline__ double reflect_walls(double z, double Lz) {
 }
 
 __global__ void force_update_dry_kernel(GridDev g, NearDev P, DryDev Dd, int n,
-                                        const double* __restrict__ sx, const double* __restrict__ sy,
-                                        const double* __restrict__ sz, const double* __restrict__ sq,
+                                        const double4* __restrict__ sxyzq,
                                         const int* __restrict__ sid, const int* __restrict__ ssp,
                                         const int* __restrict__ bin_start,
                                         const double* __restrict__ fp, int64_t fstride,
@@ -253,8 +274,9 @@ __global__ void force_update_dry_kernel(GridDev g, NearDev P, DryDev Dd, int n,
                                         int* __restrict__ sp, int* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double xi = sx[i], yi = sy[i], zi = sz[i];
-    const double qi = sq[i];
+    const double4 me = sxyzq[i];
+    const double xi = me.x, yi = me.y, zi = me.z;
+    const double qi = me.w;
     const int sp_in = ssp[i];
     const int idi = sid[i];
     const bool sp_ok = sp_in >= 0 && sp_in < Dd.nsp;
@@ -263,7 +285,7 @@ __global__ void force_update_dry_kernel(GridDev g, NearDev P, DryDev Dd, int n,
     double nx = xi, ny = yi, nz = zi;
     if (pos_ok(g, xi, yi, zi)) {
         double Fx, Fy, Fz;
-        near_force(i, xi, yi, zi, qi, spi, sx, sy, sz, sq, ssp, bin_start, g, P, Fx, Fy, Fz);
+        near_force(i, me, spi, sxyzq, ssp, bin_start, g, P, Fx, Fy, Fz);
         Fx += fp[i];
         Fy += fp[i + fstride];
         Fz += fp[i + 2 * fstride];
@@ -328,7 +350,7 @@ int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, doubl
     Dd.step = step;
     const int T = 128;
     force_update_dry_kernel<<<(n + T - 1) / T, T, 0, s>>>(
-        c->gd, near_of(c, p), Dd, n, c->sx, c->sy, c->sz, c->sq, c->sid, c->ssp, c->bin_start,
+        c->gd, near_of(c, p), Dd, n, c->sxyzq, c->sid, c->ssp, c->bin_start,
         c->fp, c->n_max, pos, n, q, id, sp, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }

@@ -96,9 +96,7 @@ __device__ __forceinline__ int find_range(const int* rpre, int nr, int f) {
 }
 
 __global__ void __launch_bounds__(SP_THREADS)
-spread_charge_kernel(GridDev g, const double* __restrict__ sx, const double* __restrict__ sy,
-                     const double* __restrict__ sz, const double* __restrict__ sq,
-                     const int* __restrict__ bin_start, double sign_lo, double sign_hi,
+spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __restrict__ bin_start, double sign_lo, double sign_hi,
                      int add_bc, WallDev wall, double* __restrict__ out) {
     __shared__ double acc[SP_TX * SP_TY * SP_TZ];
     __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
@@ -113,14 +111,15 @@ spread_charge_kernel(GridDev g, const double* __restrict__ sx, const double* __r
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
         const int r = find_range(rpre, nr, f);
         const int i = rstart[r] + (f - rpre[r]);
-        const double x = sx[i], y = sy[i], z = sz[i];
+        const double4 a4 = sxyzq[i];
+        const double x = a4.x, y = a4.y, z = a4.z;
         if (!pos_ok(g, x, y, z)) continue;
         int ix0, iy0, iz0;
         double wx[4], wy[4], wz[4];
         peskin4(reduce_periodic(x, g.Lx) * g.inv_h - 0.5, ix0, wx);
         peskin4(reduce_periodic(y, g.Ly) * g.inv_h - 0.5, iy0, wy);
         peskin4(z * g.inv_h - 0.5, iz0, wz);
-        const double scale = sq[i] * inv_h3;
+        const double scale = a4.w * inv_h3;
         int lxs[4], lys[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) lxs[a] = wrapi(ix0 + a - x0, g.nx);
@@ -175,7 +174,7 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
     dim3 grid(g.nx / tx, g.ny / ty, (g.nz + SP_TZ - 1) / SP_TZ);
     const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sx, c->sy, c->sz, c->sq, c->bin_start,
+    spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sxyzq, c->bin_start,
                                                      s_lo, s_hi, add_bc, wall_of(p), out);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
