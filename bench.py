@@ -44,8 +44,10 @@ def stage_work(stage, N, C, H, pairs):
         return "hbm", 16.0 * H + 8.0 * C
     if stage == "interp":
         return "hbm", 56.0 * N + 8.0 * C
-    if stage == "near_field_update":
+    if stage == "near_field":
         return "alu", NEAR_FLOPS_PER_PAIR * pairs
+    if stage == "update":
+        return "hbm", 104.0 * N
     raise KeyError(stage)
 
 

@@ -196,10 +196,10 @@ int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
  * the mean elapsed milliseconds per recorded step of each stage (host array of at
  * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
- * inverse y-FFT, inverse x-FFT, interpolation, near-field + update) and sets *count
+ * inverse y-FFT, inverse x-FFT, interpolation, near-field, update) and sets *count
  * (0 when no step was recorded).
  */
-#define DISCOS_NSTAGE 9
+#define DISCOS_NSTAGE 10
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
 

@@ -59,6 +59,8 @@ int check_near_params(discos_ctx* c, const discos_params* p, const int32_t* spec
         return fail(c, DISCOS_E_ARG, "p3m table missing or malformed");
     if (p->psi / c->grid.h / p->p3m_dr > (double)(p->p3m_len - 1))
         return fail(c, DISCOS_E_ARG, "p3m table does not reach psi");
+    if (p->psi / c->grid.h / p->p3m_dr + 2.0 > 320.0)
+        return fail(c, DISCOS_E_ARG, "p3m table finer than 320 entries up to psi");
     if (p->wall_on && (!finite_pos(p->wall_sigma) || !std::isfinite(p->wall_xi) ||
                        !finite_pos(p->wall_cut)))
         return fail(c, DISCOS_E_ARG, "wall potential parameters invalid");
@@ -69,6 +71,7 @@ int check_near_params(discos_ctx* c, const discos_params* p, const int32_t* spec
         if (!species) return fail(c, DISCOS_E_ARG, "LJ needs species");
     }
     const int R = discos::near_radius_bins(c, p);
+    if (R > 3) return fail(c, DISCOS_E_ARG, "near-field search radius above 6 h");
     if (2 * R + 1 > c->gd.nbx || 2 * R + 1 > c->gd.nby)
         return fail(c, DISCOS_E_SHAPE,
                     "cutoff too large for the periodic box (need nx/2, ny/2 >= 2 ceil(psi/2h) + 1)");
@@ -96,7 +99,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     if (!pow2_in(grid->nx, 8, 1024) || !pow2_in(grid->ny, 8, 1024) || grid->nz < 4 ||
         grid->nz > 8192 || !finite_pos(grid->h))
         return DISCOS_E_SHAPE;
-    if (n_max < 0 || n_max > (int64_t)0x7FFFFFFF) return DISCOS_E_SHAPE;
+    if (n_max < 0 || n_max >= ((int64_t)1 << 26)) return DISCOS_E_SHAPE;
     discos_ctx* c = new (std::nothrow) discos_ctx();
     if (!c) return DISCOS_E_HIP;
     c->grid = *grid;
@@ -125,6 +128,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     size_t bytes = 0;
     bytes += carve_bytes(nm, sizeof(double4));         // sxyzq
     bytes += carve_bytes(3 * nm, sizeof(double));      // fp
+    bytes += carve_bytes(64 * nm, sizeof(int));        // nlist
+    bytes += carve_bytes(nm, sizeof(int));             // ncount
     bytes += 5 * carve_bytes(nm, sizeof(int));         // sid ssp perm ion_bin ion_rank
     bytes += carve_bytes(c->nbins, sizeof(int));
     bytes += carve_bytes(c->nbins + 1, sizeof(int));
@@ -143,6 +148,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     char* cur = static_cast<char*>(c->pool);
     c->sxyzq = carve<double4>(cur, nm);
     c->fp = carve<double>(cur, 3 * nm);
+    c->nlist = carve<int>(cur, 64 * nm);
+    c->ncount = carve<int>(cur, nm);
     c->sid = carve<int>(cur, nm);
     c->ssp = carve<int>(cur, nm);
     c->perm = carve<int>(cur, nm);
@@ -295,7 +302,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc) rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, c->phi, p, c->fp, c->n_max, 0, s);
     discos::stage_mark(c, 8, s);
     if (!rc) rc = discos::force_update_dry(c, ni, p, step, pos, ions->q, ions->id, ions->species, s);
-    discos::stage_mark(c, 9, s);
+    discos::stage_mark(c, 10, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
 }

@@ -77,10 +77,11 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
     const int tz = min(IT_TZ, g.nz - z0);
     const int lxn = tx + IT_H, lyn = ty + IT_H, lzn = tz + IT_H;
     // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled
-    for (int e = threadIdx.x; e < lxn * lyn * lzn; e += blockDim.x) {
-        const int lx = e % lxn, ly = (e / lxn) % lyn, lz = e / (lxn * lyn);
-        tile[(lz * LY + ly) * LX + lx] =
-            phi_at(phi, g, w, wrapi(x0 - 2 + lx, g.nx), wrapi(y0 - 2 + ly, g.ny), z0 - 2 + lz);
+    for (int e = threadIdx.x; e < LX * LY * lzn; e += blockDim.x) {
+        const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+        if (lx < lxn && ly < lyn)
+            tile[e] = phi_at(phi, g, w, (x0 - 2 + lx) & (g.nx - 1), (y0 - 2 + ly) & (g.ny - 1),
+                             z0 - 2 + lz);
     }
     // ions of the tile: rows (bz, by) of tx / DISCOS_BIN contiguous bins
     const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
@@ -129,8 +130,8 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
             const int cx = window_weights(a4.x * g.inv_h, wcx, dwx);
             const int cy = window_weights(a4.y * g.inv_h, wcy, dwy);
             const int cz = window_weights(a4.z * g.inv_h, wcz, dwz);
-            lx0 = wrapi(cx - x0, g.nx);
-            ly0 = wrapi(cy - y0, g.ny);
+            lx0 = (cx - x0) & (g.nx - 1);
+            ly0 = (cy - y0) & (g.ny - 1);
             lz0 = cz - z0;
             ok = lx0 >= 0 && lx0 <= tx && ly0 >= 0 && ly0 <= ty && lz0 >= 0 && lz0 <= tz;
         }
@@ -146,7 +147,7 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
             continue;
         }
         double Ex = 0.0, Ey = 0.0, Ez = 0.0, P = 0.0;
-#pragma unroll
+#pragma unroll 1
         for (int kz = 0; kz < 5; ++kz) {
             double ax = 0.0, ay = 0.0, az = 0.0;
 #pragma unroll

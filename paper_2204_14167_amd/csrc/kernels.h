@@ -28,6 +28,8 @@ struct Ctx {
     double2* spec;   // half spectrum [nz][ny][nx/2+1]
     double* cprime;  // Thomas coefficients [nz][nmode]
     double* fp;      // [3][n_max] per-ion forces in cell-list order
+    int* nlist;      // near-field neighbour lists, [64][n_max] (entry-major)
+    int* ncount;     // [n_max] list lengths
     double2 *tw_x, *tw_y;
     int* flags;
     void* pool;

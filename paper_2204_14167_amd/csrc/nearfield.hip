@@ -9,7 +9,7 @@
 namespace discos {
 
 struct NearDev {
-    double psi, psi2g, inv4pieps, h, inv_h2, inv_hdr;
+    double psi, psi2, psi2g, inv4pieps, h, inv_h2, inv_hdr;
     double rsearch;  // search radius: psi, or the LJ range if larger
     const double* tab;
     int tablen;
@@ -27,6 +27,7 @@ struct NearDev {
 static NearDev near_of(const Ctx* c, const discos_params* p) {
     NearDev d;
     d.psi = p->psi;
+    d.psi2 = p->psi * p->psi;
     d.psi2g = p->psi * p->psi * (1.0 + 1e-12);
     d.inv4pieps = 1.0 / (4.0 * M_PI * p->eps);
     d.h = c->grid.h;
@@ -54,15 +55,19 @@ static NearDev near_of(const Ctx* c, const discos_params* p) {
 
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
 
-// F^C - F^P for one pair (or ion-image pair) at separation d, charge product qq.
-// A pair at zero separation has no direction and contributes nothing.
-__device__ __forceinline__ void es_pair(double dx, double dy, double dz, double qq,
-                                        const NearDev& P, double& fx, double& fy, double& fz) {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < P.psi2g) || !(r2 > 0.0)) return;
-    const double r = sqrt(r2);
-    if (!(r < P.psi)) return;
-    const double inv_r = 1.0 / r;
+// 1/sqrt(r2) to full FP64 accuracy: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double inv_sqrt(double r2) {
+    double y = __builtin_amdgcn_rsq(r2);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    return y;
+}
+
+// Pair force for 0 < r2 < psi^2: qq / (4 pi eps) [1/r^2 - g(r/h)/h^2] rhat.
+__device__ __forceinline__ void es_pair_r2(double dx, double dy, double dz, double r2, double qq,
+                                           const NearDev& P, double& fx, double& fy, double& fz) {
+    const double inv_r = inv_sqrt(r2);
+    const double r = r2 * inv_r;
     const double t = r * P.inv_hdr;
     int k = (int)t;
     const double f = t - k;
@@ -75,6 +80,15 @@ __device__ __forceinline__ void es_pair(double dx, double dy, double dz, double 
     fz += mag * dz;
 }
 
+// F^C - F^P for one pair (or ion-image pair) at separation d, charge product qq.
+// A pair at zero separation has no direction and contributes nothing.
+__device__ __forceinline__ void es_pair(double dx, double dy, double dz, double qq,
+                                        const NearDev& P, double& fx, double& fy, double& fz) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < P.psi2) || !(r2 > 0.0)) return;
+    es_pair_r2(dx, dy, dz, r2, qq, P, fx, fy, fz);
+}
+
 __device__ __forceinline__ void lj_pair(double dx, double dy, double dz, int si, int sj,
                                         const NearDev& P, double& fx, double& fy, double& fz) {
     if (si < 0 || si >= P.nsp || sj < 0 || sj >= P.nsp) return;  // flagged by the caller
@@ -85,7 +99,11 @@ __device__ __forceinline__ void lj_pair(double dx, double dy, double dz, int si,
     if (!(r2 < cut * cut * (1.0 + 1e-12))) return;
     const double r = sqrt(r2);
     if (!(r > 0.0 && r < cut)) return;
-    const double du = 4.0 * xi * (-12.0 * pow(sig, 12.0) / pow(r, 13.0) + 6.0 * pow(sig, 6.0) / pow(r, 7.0));
+    // dU/dr of 4 xi ((s/r)^12 - (s/r)^6), integer powers by multiplication
+    const double sr = sig / r;
+    const double sr2 = sr * sr;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double du = 4.0 * xi * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r;
     const double m = -du / r;
     fx += m * dx;
     fy += m * dy;
@@ -95,23 +113,19 @@ __device__ __forceinline__ void lj_pair(double dx, double dy, double dz, int si,
 __device__ __forceinline__ double du93(double y, const NearDev& P) {
     if (!(y > 0.0 && y < P.wcut)) return 0.0;
     const double c93 = 1.5 * sqrt(3.0);
-    return c93 * P.wxi * (-9.0 * pow(P.wsig, 9.0) / pow(y, 10.0) + 3.0 * pow(P.wsig, 3.0) / pow(y, 4.0));
+    const double sy = P.wsig / y;
+    const double sy3 = sy * sy * sy;
+    return c93 * P.wxi * (-9.0 * sy3 * sy3 * sy3 + 3.0 * sy3) / y;
 }
 
-// Near-field force on ion i (cell-list index) from the real ions within the search
-// radius (mode 0) and from the wall images (modes 1: -z_j, 2: 2 Lz - z_j).  Rows of
-// bins are visited in unwrapped coordinates around the ion; a row is skipped when its
-// slab is farther than the search radius, and only the x-bins that can reach the
-// sphere are read.  Periodic copies get an explicit shift of +-L, so no per-pair
-// minimum-image arithmetic is needed (2R+1 <= nbx, nby is checked on the host).
-__device__ void near_force(int i, double4 me, int spi, const double4* __restrict__ sxyzq,
-                           const int* __restrict__ ssp, const int* __restrict__ bin_start,
-                           const GridDev& g, const NearDev& P, double& Fx, double& Fy,
-                           double& Fz) {
+// ---- global-memory path (one thread per ion, candidates read through the caches) ----
+// Used only for blocks whose neighbourhood does not fit the LDS stage (very dense
+// clusters); the staged path below is the normal one.
+__device__ void near_force_global(int i, double4 me, int spi, const double4* __restrict__ sxyzq,
+                                  const int* __restrict__ ssp, const int* __restrict__ bin_start,
+                                  const GridDev& g, const NearDev& P, double& Fx, double& Fy,
+                                  double& Fz) {
     const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
-    const double Bh = DISCOS_BIN * g.h;
-    const double inv_Bh = 1.0 / Bh;
-    const double rs2 = P.rsearch * P.rsearch;
     int bx, by, bz;
     bin_of(g, xi, yi, zi, bx, by, bz);
     double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -132,51 +146,20 @@ __device__ void near_force(int i, double4 me, int spi, const double4* __restrict
             zhi = g.nbz - 1;
             sgn = P.s_hi;
         }
-        const double r2m = mode == 0 ? rs2 : P.psi * P.psi;
-        for (int cz = zlo; cz <= zhi; ++cz) {
-            const double zb0 = cz * Bh, zb1 = fmin((cz + 1) * Bh, g.Lz);
-            double dzm;
-            if (mode == 0)
-                dzm = fmax(0.0, fmax(zb0 - zi, zi - zb1));
-            else if (mode == 1)
-                dzm = zi + zb0;
-            else
-                dzm = (2.0 * g.Lz - zb1) - zi;
-            const double remz = r2m - dzm * dzm;
-            if (!(remz > 0.0)) continue;
+        for (int cz = zlo; cz <= zhi; ++cz)
             for (int dyb = -P.R; dyb <= P.R; ++dyb) {
                 const int cyu = by + dyb;
-                const double yb0 = cyu * Bh, yb1 = yb0 + Bh;
-                const double dym = fmax(0.0, fmax(yb0 - yi, yi - yb1));
-                const double rem = remz - dym * dym;
-                if (!(rem > 0.0)) continue;
-                const double wx = sqrt(rem);
-                const int bxl = max(bx - P.R, (int)floor((xi - wx) * inv_Bh));
-                const int bxh = min(bx + P.R, (int)floor((xi + wx) * inv_Bh));
-                if (bxl > bxh) continue;
                 const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
-                const double shy = cyu < 0 ? -g.Ly : (cyu >= g.nby ? g.Ly : 0.0);
+                const double ys = yi - (cyu < 0 ? -g.Ly : (cyu >= g.nby ? g.Ly : 0.0));
                 const int row = (cz * g.nby + cy) * g.nbx;
-                // split [bxl, bxh] into at most two wrapped segments
-                int sa[2], sb[2];
-                double shx[2];
-                int nseg = 0;
-                if (bxl < 0) {
-                    sa[nseg] = bxl + g.nbx; sb[nseg] = g.nbx - 1; shx[nseg] = -g.Lx; ++nseg;
-                    if (bxh >= 0) { sa[nseg] = 0; sb[nseg] = bxh; shx[nseg] = 0.0; ++nseg; }
-                } else if (bxh >= g.nbx) {
-                    if (bxl < g.nbx) { sa[nseg] = bxl; sb[nseg] = g.nbx - 1; shx[nseg] = 0.0; ++nseg; }
-                    sa[nseg] = max(bxl - g.nbx, 0); sb[nseg] = bxh - g.nbx; shx[nseg] = g.Lx; ++nseg;
-                } else {
-                    sa[nseg] = bxl; sb[nseg] = bxh; shx[nseg] = 0.0; ++nseg;
-                }
-                for (int s = 0; s < nseg; ++s) {
-                    const int j0 = bin_start[row + sa[s]], j1 = bin_start[row + sb[s] + 1];
-                    const double xs = xi - shx[s], ys = yi - shy;
+                for (int dxb = -P.R; dxb <= P.R; ++dxb) {
+                    const int cxu = bx + dxb;
+                    const int cx = cxu < 0 ? cxu + g.nbx : (cxu >= g.nbx ? cxu - g.nbx : cxu);
+                    const double xs = xi - (cxu < 0 ? -g.Lx : (cxu >= g.nbx ? g.Lx : 0.0));
+                    const int j0 = bin_start[row + cx], j1 = bin_start[row + cx + 1];
                     for (int j = j0; j < j1; ++j) {
                         const double4 o = sxyzq[j];
-                        const double dx = xs - o.x;
-                        const double dy = ys - o.y;
+                        const double dx = xs - o.x, dy = ys - o.y;
                         if (mode == 0) {
                             if (j == i) continue;
                             const double dz = zi - o.z;
@@ -189,7 +172,139 @@ __device__ void near_force(int i, double4 me, int spi, const double4* __restrict
                     }
                 }
             }
+    }
+    Fx = fx;
+    Fy = fy;
+    Fz = fz;
+}
+
+// ---- neighbour list + force pass -------------------------------------------------
+// Pass 1 (one thread per ion of the cell list): visit the rows of bins around the ion
+// (a row is skipped when its slab is farther than the search radius and cut to the
+// x-bins that can reach the sphere; periodic copies and wall images carry a shift /
+// mode code), test each candidate's distance, and append the hits to the ion's list,
+// stored k-major (entry k of ion i at list[k * n + i]) so that both passes access it
+// coalesced.  Pass 2 (one thread per ion) evaluates the pair forces of its list.  The
+// distance test, whose trip count differs between lanes, is thereby separated from the
+// pair arithmetic, which then runs only on pairs inside the cutoff.
+#define NL_CAP 64  // list entries per ion; longer lists take the cache-read path
+#define NL_TAB 320
+
+__device__ __forceinline__ double shift_of(int code, double L) {
+    return code == 1 ? -L : (code == 2 ? L : 0.0);
+}
+
+__global__ void __launch_bounds__(256)
+near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ bin_start, int* __restrict__ list,
+                 int* __restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 me = sxyzq[i];
+    const double xi = me.x, yi = me.y, zi = me.z;
+    if (!pos_ok(g, xi, yi, zi)) {
+        count[i] = 0;
+        return;
+    }
+    const double Bh = DISCOS_BIN * g.h;
+    const double inv_Bh = 1.0 / Bh;
+    const double rs2 = P.rsearch * P.rsearch;
+    const double r2cut = fmax(P.psi2, P.lj_on ? rs2 * (1.0 + 1e-12) : 0.0);
+    const int R = P.R;
+    int bx, by, bz;
+    bin_of(g, xi, yi, zi, bx, by, bz);
+    int nh = 0;
+    for (int mode = 0; mode < 3; ++mode) {
+        int zlo, zhi;
+        if (mode == 0) {
+            zlo = max(bz - R, 0);
+            zhi = min(bz + R, g.nbz - 1);
+        } else if (mode == 1) {
+            if (!(zi < P.psi)) continue;
+            zlo = 0;
+            zhi = min(g.nbz - 1, (int)floor(P.psi * g.inv_h) / DISCOS_BIN);
+        } else {
+            if (!(zi > g.Lz - P.psi)) continue;
+            zlo = max(0, (int)floor((g.Lz - P.psi) * g.inv_h) / DISCOS_BIN);
+            zhi = g.nbz - 1;
         }
+        const double r2m = mode == 0 ? rs2 : P.psi2;
+        const double cut = mode == 0 ? r2cut : P.psi2;
+        for (int cz = zlo; cz <= zhi; ++cz) {
+            const double zb0 = cz * Bh, zb1 = fmin((cz + 1) * Bh, g.Lz);
+            const double dzm = mode == 0 ? fmax(0.0, fmax(zb0 - zi, zi - zb1))
+                                         : (mode == 1 ? zi + zb0 : (2.0 * g.Lz - zb1) - zi);
+            const double remz = r2m - dzm * dzm;
+            if (!(remz > 0.0)) continue;
+            for (int dyb = -R; dyb <= R; ++dyb) {
+                const int cyu = by + dyb;
+                const double yb0 = cyu * Bh;
+                const double dym = fmax(0.0, fmax(yb0 - yi, yi - (yb0 + Bh)));
+                const double rem = remz - dym * dym;
+                if (!(rem > 0.0)) continue;
+                const double wx = sqrt(rem);
+                const int bxl = max(bx - R, (int)floor((xi - wx) * inv_Bh));
+                const int bxh = min(bx + R, (int)floor((xi + wx) * inv_Bh));
+                if (bxl > bxh) continue;
+                const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
+                const int ysc = cyu < 0 ? 1 : (cyu >= g.nby ? 2 : 0);
+                const double ys = yi - shift_of(ysc, g.Ly);
+                const int row = (cz * g.nby + cy) * g.nbx;
+                for (int bu = bxl; bu <= bxh;) {
+                    // contiguous run of bins up to the periodic seam
+                    const int cx = bu < 0 ? bu + g.nbx : (bu >= g.nbx ? bu - g.nbx : bu);
+                    const int xsc = bu < 0 ? 1 : (bu >= g.nbx ? 2 : 0);
+                    const int run_end = bu < 0 ? min(bxh, -1) : (bu < g.nbx ? min(bxh, g.nbx - 1) : bxh);
+                    const int cx_end = cx + (run_end - bu);
+                    bu = run_end + 1;
+                    const double xs = xi - shift_of(xsc, g.Lx);
+                    const int code = (xsc << 26) | (ysc << 28) | (mode << 30);
+                    const int j0 = bin_start[row + cx], j1 = bin_start[row + cx_end + 1];
+                    for (int j = j0; j < j1; ++j) {
+                        const double4 o = sxyzq[j];
+                        const double dx = xs - o.x;
+                        const double dy = ys - o.y;
+                        const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < cut && r2 > 0.0 && (mode != 0 || j != i)) {
+                            if (nh < NL_CAP) list[(size_t)nh * n + i] = j | code;
+                            ++nh;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    count[i] = nh;
+}
+
+// Pair forces of ion i from its list (or, when the list overflowed, from a direct
+// walk of the cell list), plus the 9-3 wall force.
+__device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
+                                           const double4* __restrict__ sxyzq,
+                                           const int* __restrict__ ssp,
+                                           const int* __restrict__ bin_start,
+                                           const int* __restrict__ list, int cnt, const GridDev& g,
+                                           const NearDev& P, double& Fx, double& Fy, double& Fz) {
+    const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (cnt <= NL_CAP) {
+        const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
+        for (int k = 0; k < cnt; ++k) {
+            const int e = list[(size_t)k * n + i];
+            const int j = e & 0x3FFFFFF;
+            const int mode = (e >> 30) & 3;
+            const double4 o = sxyzq[j];
+            const double dx = (xi - shift_of((e >> 26) & 3, g.Lx)) - o.x;
+            const double dy = (yi - shift_of((e >> 28) & 3, g.Ly)) - o.y;
+            const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double sg = mode == 0 ? 1.0 : (mode == 1 ? P.s_lo : P.s_hi);
+            if (r2 < P.psi2) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
+            if (P.lj_on && mode == 0 && r2 < r2lj) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
+        }
+    } else {
+        near_force_global(i, me, spi, sxyzq, ssp, bin_start, g, P, fx, fy, fz);
     }
     if (P.wall_on) fz += -du93(zi, P) + du93(g.Lz - zi, P);
     Fx = fx;
@@ -197,18 +312,28 @@ __device__ void near_force(int i, double4 me, int spi, const double4* __restrict
     Fz = fz;
 }
 
-__global__ void near_field_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
-                                  const int* __restrict__ ssp, const int* __restrict__ bin_start,
-                                  const int* __restrict__ perm, double* __restrict__ out,
-                                  int64_t stride, int scatter, int* __restrict__ flags) {
+__global__ void __launch_bounds__(256)
+near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ ssp, const int* __restrict__ bin_start,
+                 const int* __restrict__ list, const int* __restrict__ count,
+                 const int* __restrict__ perm, double* __restrict__ out, int64_t stride,
+                 int scatter, int* __restrict__ flags) {
+    __shared__ double tab[NL_TAB];
+    const int nt = min(P.tablen, NL_TAB);
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
+    __syncthreads();
+    P.tab = tab;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 me = sxyzq[i];
     if (!pos_ok(g, me.x, me.y, me.z)) return;
+    int spi = 0;
+    if (P.lj_on) {
+        spi = ssp[i];
+        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+    }
     double Fx, Fy, Fz;
-    const int spi = P.lj_on ? ssp[i] : 0;
-    if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
-    near_force(i, me, spi, sxyzq, ssp, bin_start, g, P, Fx, Fy, Fz);
+    list_force(i, n, me, spi, sxyzq, ssp, bin_start, list, count[i], g, P, Fx, Fy, Fz);
     const int o = scatter ? perm[i] : i;
     out[o] += Fx;
     out[o + stride] += Fy;
@@ -218,10 +343,13 @@ __global__ void near_field_kernel(GridDev g, NearDev P, int n, const double4* __
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
                       int scatter_to_caller, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
-    const int T = 128;
-    near_field_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, near_of(c, p), n, c->sxyzq, c->ssp,
-                                                    c->bin_start, c->perm, out, out_stride,
-                                                    scatter_to_caller, c->flags);
+    const NearDev P = near_of(c, p);
+    const int T = 256;
+    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->bin_start, c->nlist,
+                                                   c->ncount);
+    near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
+                                                   c->nlist, c->ncount, c->perm, out, out_stride,
+                                                   scatter_to_caller, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -237,12 +365,14 @@ struct DryDev {
 
 __device__ __forceinline__ double gamma_hat(double y, const double* c) {
     const double t3 = c[4] + y, t5 = c[6] + y;
-    return c[0] + c[1] / (c[2] + y) + c[3] / pow(t3, 3.0) + c[5] / pow(t5, 5.0);
+    const double t52 = t5 * t5;
+    return c[0] + c[1] / (c[2] + y) + c[3] / (t3 * t3 * t3) + c[5] / (t52 * t52 * t5);
 }
 
 __device__ __forceinline__ double dgamma_hat(double y, const double* c) {
     const double t1 = c[2] + y, t3 = c[4] + y, t5 = c[6] + y;
-    return -c[1] / pow(t1, 2.0) - 3.0 * c[3] / pow(t3, 4.0) - 5.0 * c[5] / pow(t5, 6.0);
+    const double t32 = t3 * t3, t52 = t5 * t5;
+    return -c[1] / (t1 * t1) - 3.0 * c[3] / (t32 * t32) - 5.0 * c[5] / (t52 * t52 * t52);
 }
 
 __device__ __forceinline__ double wrap_coord(double x, double L) {
@@ -264,81 +394,88 @@ __device__ __forceinline__ double reflect_walls(double z, double Lz) {
     return t <= Lz ? t : 2.0 * Lz - t;
 }
 
-__global__ void force_update_dry_kernel(GridDev g, NearDev P, DryDev Dd, int n,
-                                        const double4* __restrict__ sxyzq,
-                                        const int* __restrict__ sid, const int* __restrict__ ssp,
-                                        const int* __restrict__ bin_start,
-                                        const double* __restrict__ fp, int64_t fstride,
-                                        double* __restrict__ pos, int64_t pstride,
-                                        double* __restrict__ q, int* __restrict__ id,
-                                        int* __restrict__ sp, int* __restrict__ flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 me = sxyzq[i];
-    const double xi = me.x, yi = me.y, zi = me.z;
-    const double qi = me.w;
-    const int sp_in = ssp[i];
-    const int idi = sid[i];
+// Dry update of one ion (eq ions3 dry part, Euler-Maruyama, Ito): returns the new
+// position (wrapped in x, y, reflected at the walls).
+__device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int spi, int idi,
+                                         double xi, double yi, double zi, double Fx, double Fy,
+                                         double Fz, double& nx, double& ny, double& nz,
+                                         int* __restrict__ flags) {
+    const double a = Dd.radius[spi];
+    const double D = Dd.kT / (6.0 * M_PI * Dd.eta * a);
+    const double* cpar = Dd.coef + (size_t)spi * 14;
+    const double* cperp = cpar + 7;
+    const bool below = zi <= g.Lz - zi;
+    const double yw = below ? zi : g.Lz - zi;
+    const double gpar = gamma_hat(yw, cpar);
+    const double gperp = gamma_hat(yw, cperp);
+    const double Gp = fmin(fmax(gpar, 0.0), 1.0);
+    const double Gn = fmin(fmax(gperp, 0.0), 1.0);
+    const double dG = (gperp > 0.0 && gperp < 1.0) ? (below ? 1.0 : -1.0) * dgamma_hat(yw, cperp) : 0.0;
+    double wx, wy, wz, wunused;
+    normal_pair(Dd.seed, Dd.step, DISCOS_TAG_DRY, 0u, (uint32_t)idi, wx, wy);
+    normal_pair(Dd.seed, Dd.step, DISCOS_TAG_DRY, 1u, (uint32_t)idi, wz, wunused);
+    const double dtD = Dd.dt * D;
+    double dx = dtD * Gp * Fx / Dd.kT;
+    double dy = dtD * Gp * Fy / Dd.kT;
+    double dz = dtD * Gn * Fz / Dd.kT;
+    dz += dtD * dG;
+    dx += sqrt(2.0 * D * Gp * Dd.dt) * wx;
+    dy += sqrt(2.0 * D * Gp * Dd.dt) * wy;
+    dz += sqrt(2.0 * D * Gn * Dd.dt) * wz;
+    nx = xi + dx;
+    ny = yi + dy;
+    nz = zi + dz;
+    if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) {
+        set_flag(flags, DISCOS_FLAG_NONFINITE);
+        nx = xi;
+        ny = yi;
+        nz = zi;
+    } else {
+        nx = wrap_coord(nx, g.Lx);
+        ny = wrap_coord(ny, g.Ly);
+        nz = reflect_walls(nz, g.Lz);
+    }
+}
+
+// Dry update of every ion of the cell list from its complete force fp (grid, near
+// field, wall, applied field), written to the caller's arrays in cell-list order.
+__global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
+                                  const int* __restrict__ sid, const int* __restrict__ ssp,
+                                  const double* __restrict__ fp, int64_t fstride,
+                                  double* __restrict__ pos, int64_t pstride, double* __restrict__ q,
+                                  int* __restrict__ id, int* __restrict__ sp,
+                                  int* __restrict__ flags) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n) return;
+    const double4 me = sxyzq[gi];
+    const int sp_in = ssp[gi];
+    const int idi = sid[gi];
     const bool sp_ok = sp_in >= 0 && sp_in < Dd.nsp;
     if (!sp_ok) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
     const int spi = sp_ok ? sp_in : 0;
-    double nx = xi, ny = yi, nz = zi;
-    if (pos_ok(g, xi, yi, zi)) {
-        double Fx, Fy, Fz;
-        near_force(i, me, spi, sxyzq, ssp, bin_start, g, P, Fx, Fy, Fz);
-        Fx += fp[i];
-        Fy += fp[i + fstride];
-        Fz += fp[i + 2 * fstride];
-        const double a = Dd.radius[spi];
-        const double D = Dd.kT / (6.0 * M_PI * Dd.eta * a);
-        const double* cpar = Dd.coef + (size_t)spi * 14;
-        const double* cperp = cpar + 7;
-        const bool below = zi <= g.Lz - zi;
-        const double yw = below ? zi : g.Lz - zi;
-        const double gpar = gamma_hat(yw, cpar);
-        const double gperp = gamma_hat(yw, cperp);
-        const double Gp = fmin(fmax(gpar, 0.0), 1.0);
-        const double Gn = fmin(fmax(gperp, 0.0), 1.0);
-        const double dG = (gperp > 0.0 && gperp < 1.0) ? (below ? 1.0 : -1.0) * dgamma_hat(yw, cperp) : 0.0;
-        double wx, wy, wz, wunused;
-        normal_pair(Dd.seed, Dd.step, DISCOS_TAG_DRY, 0u, (uint32_t)idi, wx, wy);
-        normal_pair(Dd.seed, Dd.step, DISCOS_TAG_DRY, 1u, (uint32_t)idi, wz, wunused);
-        const double dtD = Dd.dt * D;
-        double dx = dtD * Gp * Fx / Dd.kT;
-        double dy = dtD * Gp * Fy / Dd.kT;
-        double dz = dtD * Gn * Fz / Dd.kT;
-        dz += dtD * dG;
-        dx += sqrt(2.0 * D * Gp * Dd.dt) * wx;
-        dy += sqrt(2.0 * D * Gp * Dd.dt) * wy;
-        dz += sqrt(2.0 * D * Gn * Dd.dt) * wz;
-        nx = xi + dx;
-        ny = yi + dy;
-        nz = zi + dz;
-        if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) {
-            set_flag(flags, DISCOS_FLAG_NONFINITE);
-            nx = xi;
-            ny = yi;
-            nz = zi;
-        } else {
-            nx = wrap_coord(nx, g.Lx);
-            ny = wrap_coord(ny, g.Ly);
-            nz = reflect_walls(nz, g.Lz);
-        }
+    double nx = me.x, ny = me.y, nz = me.z;
+    if (pos_ok(g, me.x, me.y, me.z)) {
+        dry_move(g, Dd, spi, idi, me.x, me.y, me.z, fp[gi], fp[gi + fstride], fp[gi + 2 * fstride],
+                 nx, ny, nz, flags);
     } else {
-        set_flag(flags, (isfinite(xi) && isfinite(yi) && isfinite(zi)) ? DISCOS_FLAG_OUT_OF_DOMAIN
-                                                                     : DISCOS_FLAG_NONFINITE);
+        set_flag(flags, (isfinite(me.x) && isfinite(me.y) && isfinite(me.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                          : DISCOS_FLAG_NONFINITE);
     }
-    pos[i] = nx;
-    pos[i + pstride] = ny;
-    pos[i + 2 * pstride] = nz;
-    q[i] = qi;
-    id[i] = idi;
-    sp[i] = sp_in;
+    pos[gi] = nx;
+    pos[gi + pstride] = ny;
+    pos[gi + 2 * pstride] = nz;
+    q[gi] = me.w;
+    id[gi] = idi;
+    sp[gi] = sp_in;
 }
 
 int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, double* pos,
                      double* q, int* id, int* sp, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
+    // complete the forces in place: fp (grid + applied field) += near field + wall
+    int rc = near_field_sorted(c, n, p, c->fp, c->n_max, 0, s);
+    if (rc) return rc;
+    stage_mark(c, 9, s);
     DryDev Dd;
     Dd.nsp = p->nspecies;
     Dd.kT = p->kT;
@@ -348,10 +485,8 @@ int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, doubl
     Dd.coef = p->mob_coef;
     Dd.seed = p->seed;
     Dd.step = step;
-    const int T = 128;
-    force_update_dry_kernel<<<(n + T - 1) / T, T, 0, s>>>(
-        c->gd, near_of(c, p), Dd, n, c->sxyzq, c->sid, c->ssp, c->bin_start,
-        c->fp, c->n_max, pos, n, q, id, sp, c->flags);
+    dry_update_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, Dd, n, c->sxyzq, c->sid, c->ssp, c->fp,
+                                                      c->n_max, pos, n, q, id, sp, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

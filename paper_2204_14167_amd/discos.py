@@ -250,7 +250,7 @@ class Context:
                                    int(step), mode, _stream()))
 
     STAGES = ("cell_list", "spread", "fft_x", "fft_y", "z_solve", "ifft_y", "ifft_x",
-              "interp", "near_field_update")
+              "interp", "near_field", "update")
 
     def profile(self, enable=True):
         self._rc(lib().discos_profile(self.handle, int(enable)))

@@ -220,3 +220,22 @@ def test_step_dielectric_32cube():
 
 def test_step_dielectric_128x128x64():
     _step_case("dielectric_128x128x64_n65536", steps_checked=2, sample=400)
+
+
+def test_near_field_dense_cluster():
+    """A cluster denser than a workgroup's LDS stage holds: that block takes the
+    global-memory path; results must not change."""
+    nx, ny, nz, n = 32, 32, 16, 3000
+    rng = np.random.default_rng(12)
+    pos = np.empty((3, n))
+    pos[0] = rng.uniform(10.0, 16.0, n)
+    pos[1] = rng.uniform(10.0, 16.0, n)
+    pos[2] = rng.uniform(0.2, 6.0, n)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    p = _params((D, N), nx, ny)
+    grid = es.Grid(nx, ny, nz)
+    ref = es.near_field(grid, pos, q, EPS, p["psi"], p["p3m_table"], p["p3m_dr"], (D, N))
+    ref[2] += shortrange.wall_force(pos[2], grid.L[2], p["wall_sigma"], p["wall_xi"], p["wall_cut"])
+    ctx = _ctx(nx, ny, nz, n)
+    out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p)))
+    assert rel_l2(out, ref) < 1e-12
