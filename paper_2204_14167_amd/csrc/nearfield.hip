@@ -182,11 +182,12 @@ __device__ void near_force_global(int i, double4 me, int spi, const double4* __r
 // Pass 1 (one thread per ion of the cell list): visit the rows of bins around the ion
 // (a row is skipped when its slab is farther than the search radius and cut to the
 // x-bins that can reach the sphere; periodic copies and wall images carry a shift /
-// mode code), test each candidate's distance, and append the hits to the ion's list,
-// stored k-major (entry k of ion i at list[k * n + i]) so that both passes access it
-// coalesced.  Pass 2 (one thread per ion) evaluates the pair forces of its list.  The
+// mode code), test each candidate's distance, and append the hits to the ion's list.
+// Pass 2 (one thread per ion) evaluates the pair forces of its list.  The
 // distance test, whose trip count differs between lanes, is thereby separated from the
-// pair arithmetic, which then runs only on pairs inside the cutoff.
+// pair arithmetic, which then runs only on pairs inside the cutoff.  Lists are written
+// and read in chunks of four entries; chunk c of ion i sits at [c * n + i], so the
+// chunk reads of a wavefront are contiguous.
 #define NL_CAP 64  // list entries per ion; longer lists take the cache-read path
 #define NL_TAB 320
 
@@ -213,7 +214,8 @@ near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
     const int R = P.R;
     int bx, by, bz;
     bin_of(g, xi, yi, zi, bx, by, bz);
-    int nh = 0;
+    int4* chunks = reinterpret_cast<int4*>(list);  // chunk c of ion i at [c * n + i]
+    int nh = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
     for (int mode = 0; mode < 3; ++mode) {
         int zlo, zhi;
         if (mode == 0) {
@@ -267,7 +269,14 @@ near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
                         const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
                         const double r2 = dx * dx + dy * dy + dz * dz;
                         if (r2 < cut && r2 > 0.0 && (mode != 0 || j != i)) {
-                            if (nh < NL_CAP) list[(size_t)nh * n + i] = j | code;
+                            const int e = j | code;
+                            const int slot = nh & 3;
+                            h0 = slot == 0 ? e : h0;
+                            h1 = slot == 1 ? e : h1;
+                            h2 = slot == 2 ? e : h2;
+                            h3 = slot == 3 ? e : h3;
+                            if (slot == 3 && nh < NL_CAP)
+                                chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
                             ++nh;
                         }
                     }
@@ -275,6 +284,8 @@ near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
             }
         }
     }
+    // the incomplete last chunk
+    if ((nh & 3) && nh <= NL_CAP) chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
     count[i] = nh;
 }
 
@@ -290,18 +301,25 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (cnt <= NL_CAP) {
         const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
-        for (int k = 0; k < cnt; ++k) {
-            const int e = list[(size_t)k * n + i];
-            const int j = e & 0x3FFFFFF;
-            const int mode = (e >> 30) & 3;
-            const double4 o = sxyzq[j];
-            const double dx = (xi - shift_of((e >> 26) & 3, g.Lx)) - o.x;
-            const double dy = (yi - shift_of((e >> 28) & 3, g.Ly)) - o.y;
-            const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double sg = mode == 0 ? 1.0 : (mode == 1 ? P.s_lo : P.s_hi);
-            if (r2 < P.psi2) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
-            if (P.lj_on && mode == 0 && r2 < r2lj) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
+        const int4* chunks = reinterpret_cast<const int4*>(list);
+        for (int k4 = 0; k4 < cnt; k4 += 4) {
+            const int4 ch = chunks[(size_t)(k4 >> 2) * n + i];
+            const int m4 = min(4, cnt - k4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u >= m4) break;
+                const int e = u == 0 ? ch.x : (u == 1 ? ch.y : (u == 2 ? ch.z : ch.w));
+                const int j = e & 0x3FFFFFF;
+                const int mode = (e >> 30) & 3;
+                const double4 o = sxyzq[j];
+                const double dx = (xi - shift_of((e >> 26) & 3, g.Lx)) - o.x;
+                const double dy = (yi - shift_of((e >> 28) & 3, g.Ly)) - o.y;
+                const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double sg = mode == 0 ? 1.0 : (mode == 1 ? P.s_lo : P.s_hi);
+                if (r2 < P.psi2) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
+                if (P.lj_on && mode == 0 && r2 < r2lj) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
+            }
         }
     } else {
         near_force_global(i, me, spi, sxyzq, ssp, bin_start, g, P, fx, fy, fz);
