@@ -105,11 +105,14 @@ typedef struct discos_ions {
 typedef struct discos_ctx discos_ctx;
 
 /*
- * Create a context for one grid and at most n_max ions.  Allocates every scratch
- * buffer the other calls need (FFT twiddles, cell lists, spectra), so later calls
- * allocate nothing.  flags: reserved, pass 0.  Uses the current HIP device.
+ * Create a context for one grid and at most n_max ions (n_max < 2^26).  Allocates
+ * every scratch buffer the other calls need (FFT twiddles, cell lists, neighbour
+ * lists, spectra), so later calls allocate nothing.  flags: DISCOS_CREATE_HYDRO adds
+ * the buffers of discos_solve_stokes, DISCOS_SPREAD_FORCE, DISCOS_INTERP_VEL and the
+ * wet step (about 200 bytes per cell).  Uses the current HIP device.
  * Errors: DISCOS_E_ARG, DISCOS_E_SHAPE, DISCOS_E_HIP.
  */
+#define DISCOS_CREATE_HYDRO 1u /* also allocate the Stokes / wet-step scratch */
 int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out);
 int discos_destroy(discos_ctx* ctx);
 
@@ -143,6 +146,22 @@ int discos_spread(discos_ctx* ctx, int op, int64_t n, const double* pos, const d
  */
 int discos_solve_poisson(discos_ctx* ctx, const double* rhs, const discos_params* p,
                          double* phi, void* stream);
+
+/*
+ * Fluctuating Stokes solve with no-slip walls (eq disc_stokes / disc_stokes_temp):
+ * G p - eta lap_h v = f + sqrt(2 kT eta / (dV dt)) div_h Z,  D v = 0,  with w = 0 on the
+ * wall faces and ghosts u_{-1} = -u_0 for the tangential components.  f and v are
+ * three face arrays back to back (layout of DISCOS_SPREAD_FORCE); pres ([nz][ny][nx],
+ * mean zero) may be NULL.  With DISCOS_STOKES_NOISE the stochastic stress Z is drawn
+ * from Philox with key p->seed and counter step `step`: diagonal entries at cell
+ * centres (variance 2), off-diagonal entries on cell edges (variance 1, and 2 for the
+ * xz / yz edges on the walls, which makes the discrete fluctuation-dissipation balance
+ * exact).  Uses p->eta, p->kT, p->dt.  Needs a context created with
+ * DISCOS_CREATE_HYDRO.  f is read-only; v and f must not overlap.
+ */
+#define DISCOS_STOKES_NOISE 1
+int discos_solve_stokes(discos_ctx* ctx, const double* f, const discos_params* p, uint64_t step,
+                        int flags, double* v, double* pres, void* stream);
 
 /*
  * Interpolation J (eq kernel1), Delta V sum_n delta(x_i - r_n) f_n:
@@ -187,6 +206,12 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
  * The ion arrays are PERMUTED in place into cell order (ids follow their ions).
  */
 #define DISCOS_STEP_DRY 0
+/* DISCOS_STEP_WET: the forces as in the dry step, then stage 3 (S^hy F, fluctuating
+ * no-slip Stokes solve with noise counter `step`) and stage 4 (eq step1 / step2): the
+ * midpoint x* = x + dt/2 J(x) v (wrapped and reflected like the final positions),
+ * x+ = x + dt J(x*) v plus the dry terms evaluated at x (the dry radius in p->radius;
+ * a very large radius switches the dry part off).  Needs DISCOS_CREATE_HYDRO. */
+#define DISCOS_STEP_WET 1
 int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint64_t step,
                 int mode, void* stream);
 

@@ -332,6 +332,64 @@ def near_field(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
     return out
 
 
+def near_field_pairs(grid, pos, q, eps, psi, table, dr, bc_types):
+    """The same correction as near_field for all ions, with the candidate pairs found
+    by a k-d tree (scipy cKDTree, periodic in x and y) instead of brute force; the
+    wall images are taken by brute force among the ions closer than psi to a wall."""
+    from scipy.spatial import cKDTree
+    L = grid.L
+    h = grid.h
+    n = pos.shape[1]
+    out = np.zeros((3, n))
+    pts = pos.T.copy()
+    pts[:, 0] = np.mod(pts[:, 0], L[0])
+    pts[:, 1] = np.mod(pts[:, 1], L[1])
+    tree = cKDTree(pts, boxsize=[L[0], L[1], 4.0 * L[2] + 4.0 * psi])
+    pairs = tree.query_pairs(psi, output_type="ndarray")
+    if len(pairs):
+        i, j = pairs[:, 0], pairs[:, 1]
+        d = pos[:, i] - pos[:, j]
+        d[0] -= L[0] * np.round(d[0] / L[0])
+        d[1] -= L[1] * np.round(d[1] / L[1])
+        r = np.sqrt((d * d).sum(axis=0))
+        ok = (r < psi) & (r > 0.0)
+        i, j, d, r = i[ok], j[ok], d[:, ok], r[ok]
+        g = table_lookup(table, dr, r / h)
+        mag = (q[i] * q[j]) / (4.0 * np.pi * eps) * (1.0 / r ** 2 - g / h ** 2) / r
+        for k in range(3):
+            np.add.at(out[k], i, mag * d[k])
+            np.add.at(out[k], j, -mag * d[k])
+    s = (image_sign(bc_types[0]), image_sign(bc_types[1]))
+    for wall, near in ((0, pos[2] < psi), (1, pos[2] > L[2] - psi)):
+        idx = np.nonzero(near)[0]
+        if len(idx) == 0:
+            continue
+        sub = pts[idx].copy()
+        img = sub.copy()
+        img[:, 2] = -sub[:, 2] if wall == 0 else 2.0 * L[2] - sub[:, 2]
+        off = 2.0 * psi  # keep both point sets inside the tree box in z
+        sub[:, 2] += off
+        img[:, 2] += off
+        box = [L[0], L[1], 4.0 * L[2] + 8.0 * psi]
+        sm = cKDTree(sub, boxsize=box).sparse_distance_matrix(
+            cKDTree(img, boxsize=box), psi, output_type="ndarray")
+        if len(sm) == 0:
+            continue
+        a, b = idx[sm["i"]], idx[sm["j"]]
+        zimg = -pos[2, b] if wall == 0 else 2.0 * L[2] - pos[2, b]
+        d = np.stack([pos[0, a] - pos[0, b], pos[1, a] - pos[1, b], pos[2, a] - zimg])
+        d[0] -= L[0] * np.round(d[0] / L[0])
+        d[1] -= L[1] * np.round(d[1] / L[1])
+        r = np.sqrt((d * d).sum(axis=0))
+        ok = (r < psi) & (r > 0.0)
+        a, b, d, r = a[ok], b[ok], d[:, ok], r[ok]
+        g = table_lookup(table, dr, r / h)
+        mag = (q[a] * (s[wall] * q[b])) / (4.0 * np.pi * eps) * (1.0 / r ** 2 - g / h ** 2) / r
+        for k in range(3):
+            np.add.at(out[k], a, mag * d[k])
+    return out
+
+
 def periodic_poisson(grid, eps, rho):
     """-eps lap_h phi = rho on a triply periodic grid (mean-zero gauge); used only
     to tabulate the free-space grid pair force."""

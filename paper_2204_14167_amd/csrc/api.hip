@@ -185,6 +185,36 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         delete c;
         return DISCOS_E_HIP;
     }
+    c->hydro = 0;
+    if (flags & DISCOS_CREATE_HYDRO) {
+        const size_t ncell = (size_t)c->ncell, nlev = (size_t)c->nface_z;
+        const size_t nsp = (size_t)g.nxh * g.ny;
+        size_t hb = 0;
+        hb += carve_bytes(nsp * (4 * (size_t)g.nz + 1), sizeof(double2));  // u v w p spectra
+        hb += carve_bytes(16 * (size_t)g.nz * nsp, sizeof(double));         // mode scratch
+        hb += carve_bytes(4 * ncell, sizeof(double));                       // stress diag + xy
+        hb += carve_bytes(2 * nlev, sizeof(double));                        // stress xz yz
+        hb += 2 * carve_bytes(2 * ncell + nlev, sizeof(double));            // hvel, hfor
+        hb += carve_bytes(3 * nm, sizeof(double));                          // hvi
+        hb += carve_bytes(nm, sizeof(double4));                             // hmid
+        void* hp = nullptr;
+        if (hipMalloc(&hp, hb) != hipSuccess) {
+            hipFree(c->pool);
+            delete c;
+            return DISCOS_E_HIP;
+        }
+        c->hpool = hp;
+        char* hc = static_cast<char*>(hp);
+        c->hspec = carve<double2>(hc, nsp * (4 * (size_t)g.nz + 1));
+        c->hscr = carve<double>(hc, 16 * (size_t)g.nz * nsp);
+        c->hz_diag = carve<double>(hc, 4 * ncell);
+        c->hz_edge = carve<double>(hc, 2 * nlev);
+        c->hvel = carve<double>(hc, 2 * ncell + nlev);
+        c->hfor = carve<double>(hc, 2 * ncell + nlev);
+        c->hvi = carve<double>(hc, 3 * nm);
+        c->hmid = carve<double4>(hc, nm);
+        c->hydro = 1;
+    }
     c->last_stream = nullptr;
     c->err = "";
     c->profile = 0;
@@ -202,6 +232,7 @@ int discos_destroy(discos_ctx* c) {
         delete[] c->ev;
     }
     hipFree(c->pool);
+    if (c->hydro) hipFree(c->hpool);
     delete c;
     return DISCOS_OK;
 }
@@ -223,6 +254,14 @@ int discos_spread(discos_ctx* c, int op, int64_t n, const double* pos, const dou
         rc = discos::spread_charge_sorted(c, p, add_bc, out, s);
         return rc ? fail(c, rc, "spread launch failed") : DISCOS_OK;
     }
+    if (base == DISCOS_SPREAD_FORCE) {
+        if (add_bc) return fail(c, DISCOS_E_ARG, "DISCOS_SPREAD_ADD_BC applies to charges only");
+        rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, nullptr,
+                                     s, w, n);
+        if (rc) return fail(c, rc, "cell list launch failed");
+        rc = discos::spread_force_sorted(c, out, s);
+        return rc ? fail(c, rc, "spread launch failed") : DISCOS_OK;
+    }
     return fail(c, DISCOS_E_ARG, "unknown spread op");
 }
 
@@ -236,6 +275,23 @@ int discos_solve_poisson(discos_ctx* c, const double* rhs, const discos_params* 
     if (rc) return rc;
     rc = discos::solve_poisson(c, rhs, p, phi, s);
     return rc ? fail(c, rc, "poisson launch failed") : DISCOS_OK;
+}
+
+int discos_solve_stokes(discos_ctx* c, const double* f, const discos_params* p, uint64_t step,
+                        int flags, double* v, double* pres, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (!c->hydro) return fail(c, DISCOS_E_ARG, "context created without DISCOS_CREATE_HYDRO");
+    if (!f || !v || !p) return fail(c, DISCOS_E_ARG, "null array");
+    if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive");
+    const int noise = (flags & DISCOS_STOKES_NOISE) ? 1 : 0;
+    if (noise && (!finite_pos(p->kT) || !finite_pos(p->dt)))
+        return fail(c, DISCOS_E_ARG, "noise needs kT > 0 and dt > 0");
+    const size_t total = 2 * (size_t)c->ncell + (size_t)c->nface_z;
+    if (v < f + total && f < v + total) return fail(c, DISCOS_E_ARG, "f and v overlap");
+    int rc = discos::solve_stokes(c, f, p, step, noise, v, pres, s);
+    return rc ? fail(c, rc, "stokes launch failed") : DISCOS_OK;
 }
 
 int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, const double* field,
@@ -253,6 +309,12 @@ int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, cons
         if (n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
         rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, aux, nullptr, nullptr, s);
         if (!rc) rc = discos::interp_es_sorted(c, op, (int)n, field, p, out, n, 1, s);
+        return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
+    }
+    if (op == DISCOS_INTERP_VEL) {
+        if (n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+        rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, nullptr, s);
+        if (!rc) rc = discos::interp_hy_sorted(c, (int)n, field, out, n, 1, s);
         return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
     }
     return fail(c, DISCOS_E_ARG, "unknown interpolation op");

@@ -117,7 +117,9 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
                                    const int* __restrict__ id, const int* __restrict__ sp,
                                    GridDev g, double4* __restrict__ sxyzq,
                                    int* __restrict__ sid, int* __restrict__ ssp,
-                                   int* __restrict__ perm) {
+                                   int* __restrict__ perm, const double* __restrict__ w3,
+                                   int64_t w3_stride, double* __restrict__ sw3,
+                                   int64_t sw3_stride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int d = start[ion_bin[i]] + ion_rank[i];
@@ -129,11 +131,17 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
     sxyzq[d] = make_double4(xi, yi, z[i], q ? q[i] : 0.0);
     if (id) sid[d] = id[i];
     if (sp) ssp[d] = sp[i];
+    if (w3) {
+        sw3[d] = w3[i];
+        sw3[d + sw3_stride] = w3[i + w3_stride];
+        sw3[d + 2 * sw3_stride] = w3[i + 2 * w3_stride];
+    }
     perm[d] = i;
 }
 
 int build_cell_list(Ctx* c, int n, const double* x, const double* y, const double* z,
-                    const double* q, const int* id, const int* sp, hipStream_t s) {
+                    const double* q, const int* id, const int* sp, hipStream_t s,
+                    const double* w3, int64_t w3_stride) {
     const GridDev& g = c->gd;
     const int64_t nb = c->nbins;
     const int T = 256;
@@ -148,7 +156,8 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
     if (n > 0)
         bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
                                                          x, y, z, q, id, sp, g, c->sxyzq,
-                                                         c->sid, c->ssp, c->perm);
+                                                         c->sid, c->ssp, c->perm, w3, w3_stride,
+                                                         c->fp, c->n_max);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

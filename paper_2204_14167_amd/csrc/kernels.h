@@ -31,8 +31,19 @@ struct Ctx {
     int* nlist;      // near-field neighbour lists, [64][n_max] (entry-major)
     int* ncount;     // [n_max] list lengths
     double2 *tw_x, *tw_y;
+    // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
+    int hydro;
+    double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
+    double* hscr;     // per-mode block-Thomas scratch, 16 doubles per level
+    double* hz_diag;  // stress normals: xx, yy, zz, xy per cell
+    double* hz_edge;  // stress normals: xz, yz per z-level edge
+    double* hvel;     // face velocity scratch for the wet step (3 face arrays)
+    double* hfor;     // face force scratch (3 face arrays)
+    double* hvi;      // [3][n_max] interpolated ion velocities
+    double4* hmid;    // [n_max] midpoint positions (x, y, z, q) in cell-list order
     int* flags;
     void* pool;
+    void* hpool;
     size_t pool_bytes;
     hipStream_t last_stream;
     std::string err;
@@ -55,7 +66,8 @@ WallDev wall_of(const discos_params* p);
 
 // Cell list from positions (and optional companions) in caller order.
 int build_cell_list(Ctx* c, int n, const double* x, const double* y, const double* z,
-                    const double* q, const int* id, const int* sp, hipStream_t s);
+                    const double* q, const int* id, const int* sp, hipStream_t s,
+                    const double* w3 = nullptr, int64_t w3_stride = 0);
 void fill_f64(double* a, int64_t n, double v, hipStream_t s);
 
 // S^es over the cell list: rho = S q (sorted copies sx..sq) with fold signs; optional
@@ -75,6 +87,15 @@ int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_para
 // out[sorted] += F.
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
                       int scatter_to_caller, hipStream_t s);
+
+// S^hy of the sorted forces c->fp onto the three face arrays of out.
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s);
+// Stokes solve with no-slip walls (f: three face arrays; vel likewise; pres nullable).
+int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
+                 double* vel, double* pres, hipStream_t s);
+// J^hy of the face velocity for the ions of the cell list.
+int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
+                     hipStream_t s);
 
 // Fused force completion and dry update of the sorted ions, written to the caller arrays.
 int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, double* pos,

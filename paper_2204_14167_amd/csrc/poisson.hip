@@ -242,6 +242,35 @@ static int ilog2(int n) {
     return l;
 }
 
+// Real FFT along x of nrows rows (nrows even) into half spectra, and its inverse;
+// complex FFT along y of nlev levels of half spectra.
+int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t s) {
+    const int nx = c->gd.nx;
+    const int npairs = nrows / 2;
+    const int ppb = std::max(1, 2048 / nx);
+    fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
+        in, spec, nx, ilog2(nx), npairs, ppb, c->tw_x);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_t s) {
+    const int nx = c->gd.nx;
+    const int npairs = nrows / 2;
+    const int ppb = std::max(1, 2048 / nx);
+    fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
+        spec, out, nx, ilog2(nx), npairs, ppb, c->tw_x);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
+    const int ny = c->gd.ny, nxh = c->gd.nxh;
+    const int mc = std::max(1, std::min(16, 2048 / ny));
+    dim3 gy((nxh + mc - 1) / mc, nlev);
+    fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * ny * sizeof(double2), s>>>(spec, nxh, ny, ilog2(ny), mc,
+                                                                           c->tw_y, inv);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
                   int mark_base) {
     const GridDev& g = c->gd;

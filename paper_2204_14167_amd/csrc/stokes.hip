@@ -1,0 +1,531 @@
+// Overdamped Stokes with no-slip walls on the MAC grid (eq disc_stokes, eq fluidbc,
+// eq disc_stokes_temp), hydrodynamic spreading S^hy and interpolation J^hy
+// (eq kernel2, eq kernel1, Fig. folded, ghost rule for interpolation).
+//
+// Mode solve: after the in-plane FFTs, each mode (m, n) with kappa != 0 is rotated
+// onto e = (G_x, G_y) / kappa, G the symbols of the face gradient:
+//   b = e_perp^H u   obeys eta T b = f_perp            (T = -D_zz + kappa^2, walls),
+//   a = e^H u, w, p  obey  eta T a + kappa p = f_par,  eta T_w w + G_z p = f_z,
+//                          -kappa a + D_z w = 0,
+// a real 3x3 block-tridiagonal saddle system in z solved by block Thomas (one thread
+// per mode).  kappa = 0: tridiagonal solves for the mean flow, w = 0, the pressure
+// from its z-gradient with mean zero.
+#include "kernels.h"
+
+namespace discos {
+
+// ---- S^hy: force spreading on one face grid (tile gather, as the charge spread) ----
+#define SH_TX 16
+#define SH_TY 16
+#define SH_TZ 16
+#define SH_THREADS 256
+#define SH_MAXR 256
+
+__device__ int tile_ranges_h(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
+                             int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan) {
+    int sa[2], sb[2], nseg;
+    {
+        const int lo = floordiv(x0 - 2, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
+        if (hi - lo + 1 >= g.nbx) {
+            nseg = 1; sa[0] = 0; sb[0] = g.nbx - 1;
+        } else {
+            const int a = wrapi(lo, g.nbx), b = wrapi(hi, g.nbx);
+            if (a <= b) { nseg = 1; sa[0] = a; sb[0] = b; }
+            else { nseg = 2; sa[0] = a; sb[0] = g.nbx - 1; sa[1] = 0; sb[1] = b; }
+        }
+    }
+    int ylo = floordiv(y0 - 2, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
+    if (yhi - ylo + 1 >= g.nby) { ylo = 0; yhi = g.nby - 1; }
+    const int czlo = max(z0 - 2, 0), czhi = min(z0 + tz + 1, g.nz - 1);
+    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
+    const int nyb = yhi - ylo + 1;
+    const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
+    const int t = threadIdx.x;
+    int len = 0;
+    if (t < ncand && t < SH_MAXR) {
+        const int sgi = t % nseg;
+        const int yy = ylo + (t / nseg) % nyb;
+        const int bz = bzlo + t / (nseg * nyb);
+        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
+        const int st = bin_start[row + sa[sgi]];
+        rstart[t] = st;
+        len = bin_start[row + sb[sgi] + 1] - st;
+    }
+    scan[t] = len;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int a = (t >= off) ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += a;
+        __syncthreads();
+    }
+    const int nr = max(min(ncand, SH_MAXR), 1);
+    if (t < nr) rpre[t] = scan[t] - len;
+    if (t == nr - 1) rpre[nr] = (ncand > 0) ? scan[t] : 0;
+    if (ncand == 0 && t == 0) { rstart[0] = 0; rpre[0] = 0; rpre[1] = 0; }
+    __syncthreads();
+    return nr;
+}
+
+// COMP 0 / 1: x / y component at cell-centre heights, images fold k -> -1-k (sign -1).
+// COMP 2: z component on z-faces, images fold k -> -k (sign -1); wall faces hold 0.
+template <int COMP>
+__global__ void __launch_bounds__(SH_THREADS)
+spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
+                   const int* __restrict__ bin_start, double* __restrict__ out) {
+    __shared__ double acc[SH_TX * SH_TY * SH_TZ];
+    __shared__ int rstart[SH_MAXR], rpre[SH_MAXR + 1], scan[SH_THREADS];
+    const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
+    const int tx = min(SH_TX, g.nx), ty = min(SH_TY, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * SH_TZ;
+    const int tz = min(SH_TZ, nzn - z0);
+    const int ncell = tx * ty * tz;
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
+    // ions that can reach node levels [z0, z0+tz): cells [z0-2, z0+tz+1]
+    const int nr = tile_ranges_h(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
+                                 rpre, scan);
+    const int total = rpre[nr];
+    const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
+    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+        int r = 0, hi = nr - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (rpre[mid] <= f) r = mid; else hi = mid - 1;
+        }
+        const int i = rstart[r] + (f - rpre[r]);
+        const double4 a4 = sxyzq[i];
+        if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
+        int ix0, iy0, iz0;
+        double wx[4], wy[4], wz[4];
+        peskin4(a4.x * g.inv_h - ox, ix0, wx);
+        peskin4(a4.y * g.inv_h - oy, iy0, wy);
+        peskin4(a4.z * g.inv_h - oz, iz0, wz);
+        const double scale = fw[i] * inv_h3;
+        int lxs[4], lys[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int kz = iz0 + c;
+            double sgn = 1.0;
+            if (COMP == 2) {
+                if (kz < 0) { kz = -kz; sgn = -1.0; }
+                else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
+                if (kz == 0 || kz == g.nz) continue;
+            } else {
+                if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
+                else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
+            }
+            const int lz = kz - z0;
+            if (lz < 0 || lz >= tz) continue;
+            const double wzc = scale * sgn * wz[c];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (lys[b] >= ty) continue;
+                const double wyz = wzc * wy[b];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    if (lxs[a] >= tx) continue;
+                    atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int lx = k % tx, ly = (k / tx) % ty, lz = k / (tx * ty);
+        const int gk = z0 + lz;
+        double v = acc[k];
+        if (COMP == 2 && (gk == 0 || gk == g.nz)) v = 0.0;
+        out[((size_t)gk * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = v;
+    }
+}
+
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int tx = std::min(SH_TX, g.nx), ty = std::min(SH_TY, g.ny);
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + SH_TZ - 1) / SH_TZ);
+    dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + SH_TZ - 1) / SH_TZ);
+    spread_face_kernel<0><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, out);
+    spread_face_kernel<1><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max, c->bin_start,
+                                                       out + ncell);
+    spread_face_kernel<2><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
+                                                       c->bin_start, out + 2 * ncell);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+// ---- stochastic stress --------------------------------------------------------
+// Unit normals (Philox, counters as in the oracle): diagonal tag, cell index
+// (pair 0 -> xx, yy; pair 1 -> zz); edge tag, z-level index (k ny + j) nx + i with
+// k = 0..nz (pair 0 -> xz, yz; pair 1 -> xy for k < nz).  Z_aa = sqrt(2) W, Z_ab = W,
+// and the xz / yz edges on the walls (k = 0, nz) carry sqrt(2) W.
+__global__ void stress_kernel(GridDev g, uint64_t seed, uint64_t step, double* __restrict__ zd,
+                              double* __restrict__ ze) {
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t nlev = (int64_t)g.nx * g.ny * (g.nz + 1);
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nlev) return;
+    const double s2 = 1.4142135623730951;
+    const int k = (int)(t / ((int64_t)g.nx * g.ny));
+    double a, b;
+    if (t < ncell) {
+        normal_pair(seed, step, DISCOS_TAG_STRESS_DIAG, 0u, (uint32_t)t, a, b);
+        zd[t] = s2 * a;
+        zd[t + ncell] = s2 * b;
+        normal_pair(seed, step, DISCOS_TAG_STRESS_DIAG, 1u, (uint32_t)t, a, b);
+        zd[t + 2 * ncell] = s2 * a;
+    }
+    normal_pair(seed, step, DISCOS_TAG_STRESS_EDGE, 0u, (uint32_t)t, a, b);
+    const double ws = (k == 0 || k == g.nz) ? s2 : 1.0;
+    ze[t] = ws * a;          // xz
+    ze[t + nlev] = ws * b;   // yz
+    if (k < g.nz) {
+        normal_pair(seed, step, DISCOS_TAG_STRESS_EDGE, 1u, (uint32_t)t, a, b);
+        zd[t + 3 * ncell] = a;  // xy
+    }
+}
+
+// f += amp div_h Z on the faces (wall faces of w untouched).
+__global__ void stress_div_kernel(GridDev g, double amp, const double* __restrict__ zd,
+                                  const double* __restrict__ ze, double* __restrict__ f) {
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t nlev = (int64_t)g.nx * g.ny * (g.nz + 1);
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nlev) return;
+    const int nx = g.nx, ny = g.ny;
+    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / ((int64_t)nx * ny));
+    const double ih = g.inv_h;
+    const int im = (i - 1) & (nx - 1), ip = (i + 1) & (nx - 1);
+    const int jm = (j - 1) & (ny - 1), jp = (j + 1) & (ny - 1);
+    auto C = [&](int kk, int jj, int ii) { return ((int64_t)kk * ny + jj) * nx + ii; };
+    const double* Zxx = zd;
+    const double* Zyy = zd + ncell;
+    const double* Zzz = zd + 2 * ncell;
+    const double* Zxy = zd + 3 * ncell;
+    const double* Zxz = ze;
+    const double* Zyz = ze + nlev;
+    if (k < g.nz) {
+        // x-face (i, j+1/2, k+1/2)
+        const double fx = (Zxx[C(k, j, i)] - Zxx[C(k, j, im)]) + (Zxy[C(k, jp, i)] - Zxy[C(k, j, i)]) +
+                          (Zxz[C(k + 1, j, i)] - Zxz[C(k, j, i)]);
+        f[C(k, j, i)] += amp * ih * fx;
+        // y-face (i+1/2, j, k+1/2)
+        const double fy = (Zxy[C(k, j, ip)] - Zxy[C(k, j, i)]) + (Zyy[C(k, j, i)] - Zyy[C(k, jm, i)]) +
+                          (Zyz[C(k + 1, j, i)] - Zyz[C(k, j, i)]);
+        f[ncell + C(k, j, i)] += amp * ih * fy;
+    }
+    if (k >= 1 && k < g.nz) {
+        // z-face (i+1/2, j+1/2, k)
+        const double fz = (Zxz[C(k, j, ip)] - Zxz[C(k, j, i)]) + (Zyz[C(k, jp, i)] - Zyz[C(k, j, i)]) +
+                          (Zzz[C(k, j, i)] - Zzz[C(k - 1, j, i)]);
+        f[2 * ncell + C(k, j, i)] += amp * ih * fz;
+    }
+}
+
+// ---- per-mode solve -------------------------------------------------------------
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// 3x3 real inverse by cofactors.
+__device__ __forceinline__ void inv3(const double M[9], double R[9]) {
+    const double c00 = M[4] * M[8] - M[5] * M[7];
+    const double c01 = M[5] * M[6] - M[3] * M[8];
+    const double c02 = M[3] * M[7] - M[4] * M[6];
+    const double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    const double id = 1.0 / det;
+    R[0] = c00 * id;
+    R[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+    R[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+    R[3] = c01 * id;
+    R[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+    R[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+    R[6] = c02 * id;
+    R[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+    R[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+}
+
+// One thread per in-plane mode t = n * nxh + m.  su, sv, sp: spectra [nz][ny][nxh];
+// sw: [nz+1][ny][nxh].  On entry su, sv, sw hold the force, on exit the velocity and
+// sp the pressure.  scr: per-mode scratch, 16 doubles per level, stride nmode.
+__global__ void stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv,
+                                   double2* __restrict__ sw, double2* __restrict__ sp,
+                                   double* __restrict__ scr, int nx, int ny, int nz, double h,
+                                   double eta, double norm) {
+    const int nxh = nx / 2 + 1;
+    const int nmode = nxh * ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nmode) return;
+    const int m = t % nxh, n = t / nxh;
+    const size_t st = (size_t)nmode;
+    const double ih = 1.0 / h, ih2 = ih * ih;
+    const double tx = 2.0 * M_PI * m / nx, ty = 2.0 * M_PI * n / ny;
+    // G = (1 - e^{-i theta}) / h
+    const double2 gx = make_double2((1.0 - cos(tx)) * ih, sin(tx) * ih);
+    const double2 gy = make_double2((1.0 - cos(ty)) * ih, sin(ty) * ih);
+    const double k2 = gx.x * gx.x + gx.y * gx.y + gy.x * gy.x + gy.y * gy.y;
+    double* cpb = scr + t;                 // [nz] tridiagonal coefficients of b
+    double* Cp = scr + (size_t)nz * st + t;  // [nz][9] block C'
+    double* Yp = scr + (size_t)10 * nz * st + t;  // [nz][6] block y (3 complex)
+    const double off = -eta * ih2;
+    if (m == 0 && n == 0) {
+        // mean flow: eta T u = f with the wall rows; w = 0; p from G_z p = f_z, mean 0
+        for (int comp = 0; comp < 2; ++comp) {
+            double2* col = comp == 0 ? su + t : sv + t;
+            double c_prev = 0.0;
+            double2 d_prev = make_double2(0.0, 0.0);
+            for (int k = 0; k < nz; ++k) {
+                double diag = eta * 2.0 * ih2;
+                if (k == 0) diag += eta * ih2;
+                if (k == nz - 1) diag += eta * ih2;
+                const double den = diag - off * c_prev;
+                const double c = off / den;
+                const double2 r = cscale(norm, col[k * st]);
+                const double2 d = cscale(1.0 / den, csub(r, cscale(off, d_prev)));
+                cpb[k * st] = c;
+                col[k * st] = d;
+                c_prev = c;
+                d_prev = d;
+            }
+            double2 x = d_prev;
+            for (int k = nz - 2; k >= 0; --k) {
+                x = csub(col[k * st], cscale(cpb[k * st], x));
+                col[k * st] = x;
+            }
+        }
+        double2 pk = make_double2(0.0, 0.0), psum = make_double2(0.0, 0.0);
+        for (int k = 0; k < nz; ++k) {
+            if (k > 0) pk = cadd(pk, cscale(h * norm, sw[k * st + t]));
+            sp[k * st + t] = pk;
+            psum = cadd(psum, pk);
+        }
+        const double2 mean = cscale(1.0 / nz, psum);
+        for (int k = 0; k < nz; ++k) sp[k * st + t] = csub(sp[k * st + t], mean);
+        for (int k = 0; k <= nz; ++k) sw[k * st + t] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double kap = sqrt(k2);
+    const double ik = 1.0 / kap;
+    // e = G / kappa; a = e^H u, b = e_perp^H u with e_perp = (-conj gy, conj gx) / kappa
+    // forward sweeps (b: scalar tridiagonal; (a, w, p): 3x3 blocks)
+    double cb_prev = 0.0;
+    double2 db_prev = make_double2(0.0, 0.0);
+    double Cprev[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double2 Yprev[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    const double dgn = eta * (2.0 * ih2 + k2);
+    for (int k = 0; k < nz; ++k) {
+        const double2 fxk = cscale(norm, su[k * st + t]);
+        const double2 fyk = cscale(norm, sv[k * st + t]);
+        const double2 fzk = (k == 0) ? make_double2(0.0, 0.0) : cscale(norm, sw[k * st + t]);
+        const double2 fa = cscale(ik, cadd(cm(cconj(gx), fxk), cm(cconj(gy), fyk)));
+        const double2 fb = cscale(ik, csub(cm(gx, fyk), cm(gy, fxk)));
+        const double wall = (k == 0 ? 1.0 : 0.0) + (k == nz - 1 ? 1.0 : 0.0);
+        const double da = dgn + eta * wall * ih2;
+        // b: tridiagonal
+        {
+            const double den = da - off * cb_prev;
+            const double c = off / den;
+            const double2 d = cscale(1.0 / den, csub(fb, cscale(off, db_prev)));
+            cpb[k * st] = c;
+            cb_prev = c;
+            db_prev = d;
+            // d kept in Y slot 0 of this level temporarily (complex b) -> store in sv
+            sv[k * st + t] = d;
+        }
+        // blocks for level k (rows E1 a-momentum, E2 w-momentum, E3 continuity; cols a, w, p)
+        double B[9] = {da, 0.0, kap, 0.0, dgn, ih, -kap, -ih, 0.0};
+        if (k == 0) { B[3] = 0.0; B[4] = 1.0; B[5] = 0.0; }
+        double2 r0 = fa, r1 = fzk, r2 = make_double2(0.0, 0.0);
+        if (k > 0) {
+            // S = B - A C'_{k-1};  A = [[off,0,0],[0,off,-ih],[0,0,0]]
+            B[0] -= off * Cprev[0];
+            B[1] -= off * Cprev[1];
+            B[2] -= off * Cprev[2];
+            B[3] -= off * Cprev[3] - ih * Cprev[6];
+            B[4] -= off * Cprev[4] - ih * Cprev[7];
+            B[5] -= off * Cprev[5] - ih * Cprev[8];
+            // r - A y_{k-1}
+            r0 = csub(r0, cscale(off, Yprev[0]));
+            r1 = csub(r1, csub(cscale(off, Yprev[1]), cscale(ih, Yprev[2])));
+        }
+        double Si[9];
+        inv3(B, Si);
+        // C'_k = S^-1 C_k;  C = [[off,0,0],[0,off,0],[0,ih,0]] (row 2 of C is 0 at k = 0)
+        const double c11 = (k == 0) ? 0.0 : off;
+        double Cn[9];
+        for (int r = 0; r < 3; ++r) {
+            Cn[3 * r + 0] = Si[3 * r + 0] * off;
+            Cn[3 * r + 1] = Si[3 * r + 1] * c11 + Si[3 * r + 2] * ih;
+            Cn[3 * r + 2] = 0.0;
+        }
+        if (k == nz - 1)
+            for (int q = 0; q < 9; ++q) Cn[q] = 0.0;
+        double2 Yn[3];
+        for (int r = 0; r < 3; ++r)
+            Yn[r] = cadd(cadd(cscale(Si[3 * r], r0), cscale(Si[3 * r + 1], r1)), cscale(Si[3 * r + 2], r2));
+        for (int q = 0; q < 9; ++q) {
+            Cp[((size_t)k * 9 + q) * st] = Cn[q];
+            Cprev[q] = Cn[q];
+        }
+        for (int r = 0; r < 3; ++r) {
+            Yp[((size_t)k * 6 + 2 * r) * st] = Yn[r].x;
+            Yp[((size_t)k * 6 + 2 * r + 1) * st] = Yn[r].y;
+            Yprev[r] = Yn[r];
+        }
+    }
+    // back substitution; rotate (a, b) back to (u, v)
+    double2 xa = Yprev[0], xw = Yprev[1], xp = Yprev[2];
+    double2 xb = db_prev;
+    for (int k = nz - 1; k >= 0; --k) {
+        if (k < nz - 1) {
+            double C[9];
+            for (int q = 0; q < 9; ++q) C[q] = Cp[((size_t)k * 9 + q) * st];
+            double2 y[3];
+            for (int r = 0; r < 3; ++r)
+                y[r] = make_double2(Yp[((size_t)k * 6 + 2 * r) * st], Yp[((size_t)k * 6 + 2 * r + 1) * st]);
+            // x_k = y_k - C'_k x_{k+1}; C'_k column 2 is zero
+            const double2 na = csub(y[0], cadd(cscale(C[0], xa), cscale(C[1], xw)));
+            const double2 nw = csub(y[1], cadd(cscale(C[3], xa), cscale(C[4], xw)));
+            const double2 np = csub(y[2], cadd(cscale(C[6], xa), cscale(C[7], xw)));
+            xa = na;
+            xw = nw;
+            xp = np;
+            xb = csub(sv[k * st + t], cscale(cpb[k * st], xb));
+        }
+        // u = a e + b e_perp = (a gx - b conj gy) / kappa, v = (a gy + b conj gx) / kappa
+        su[k * st + t] = cscale(ik, csub(cm(xa, gx), cm(xb, cconj(gy))));
+        sv[k * st + t] = cscale(ik, cadd(cm(xa, gy), cm(xb, cconj(gx))));
+        sw[k * st + t] = (k == 0) ? make_double2(0.0, 0.0) : xw;
+        sp[k * st + t] = xp;
+    }
+    sw[(size_t)nz * st + t] = make_double2(0.0, 0.0);
+}
+
+// ---- J^hy -------------------------------------------------------------------------
+// V = J^hy v with the no-slip ghosts: tangential components u_{-1-m} = -u_m (cell
+// heights), normal component w_{-k} = -w_k (faces), mirrored at the top.
+__device__ __forceinline__ double face_val(const double* __restrict__ a, const GridDev& g, int comp,
+                                           int i, int j, int k) {
+    double s = 1.0;
+    if (comp < 2) {
+        if (k < 0) { k = -1 - k; s = -1.0; }
+        else if (k >= g.nz) { k = 2 * g.nz - 1 - k; s = -1.0; }
+        k = min(max(k, 0), g.nz - 1);
+    } else {
+        if (k < 0) { k = -k; s = -1.0; }
+        else if (k > g.nz) { k = 2 * g.nz - k; s = -1.0; }
+        k = min(max(k, 0), g.nz);
+    }
+    return s * a[((size_t)k * g.ny + j) * g.nx + i];
+}
+
+__global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ sxyzq,
+                                 const int* __restrict__ perm, const double* __restrict__ vel,
+                                 double* __restrict__ out, int64_t stride, int scatter,
+                                 int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = scatter ? perm[i] : i;
+    const double4 a4 = sxyzq[i];
+    if (!pos_ok(g, a4.x, a4.y, a4.z)) {
+        set_flag(flags, DISCOS_FLAG_OUT_OF_DOMAIN);
+        out[o] = out[o + stride] = out[o + 2 * stride] = 0.0;
+        return;
+    }
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    double res[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const double* a = vel + comp * ncell;
+        int ix0, iy0, iz0;
+        double wx[4], wy[4], wz[4];
+        peskin4(a4.x * g.inv_h - (comp == 0 ? 0.0 : 0.5), ix0, wx);
+        peskin4(a4.y * g.inv_h - (comp == 1 ? 0.0 : 0.5), iy0, wy);
+        peskin4(a4.z * g.inv_h - (comp == 2 ? 0.0 : 0.5), iz0, wz);
+        double acc = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            double accy = 0.0;
+            for (int b = 0; b < 4; ++b) {
+                const int jj = (iy0 + b) & (g.ny - 1);
+                double accx = 0.0;
+#pragma unroll
+                for (int aa = 0; aa < 4; ++aa)
+                    accx += wx[aa] * face_val(a, g, comp, (ix0 + aa) & (g.nx - 1), jj, iz0 + c);
+                accy += wy[b] * accx;
+            }
+            acc += wz[c] * accy;
+        }
+        res[comp] = acc;
+    }
+    out[o] = res[0];
+    out[o + stride] = res[1];
+    out[o + 2 * stride] = res[2];
+}
+
+int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
+                     hipStream_t s) {
+    if (n <= 0) return DISCOS_OK;
+    interp_hy_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, out, stride,
+                                                    scatter, c->flags);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+// ---- solve ----------------------------------------------------------------------
+int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t s);
+int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_t s);
+int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s);
+
+int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
+                 double* vel, double* pres, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t ncell = (size_t)nx * ny * nz;
+    const size_t nlev = (size_t)nx * ny * (nz + 1);
+    const double* frhs = f;
+    if (noise) {
+        // f + amp div Z, built in the velocity buffer (the solve reads it once)
+        hipMemcpyAsync(vel, f, (2 * ncell + nlev) * sizeof(double), hipMemcpyDeviceToDevice, s);
+        const double amp = sqrt(2.0 * p->kT * p->eta / (c->grid.h * c->grid.h * c->grid.h * p->dt));
+        const int T = 256;
+        stress_kernel<<<(int)((nlev + T - 1) / T), T, 0, s>>>(g, p->seed, step, c->hz_diag, c->hz_edge);
+        stress_div_kernel<<<(int)((nlev + T - 1) / T), T, 0, s>>>(g, amp, c->hz_diag, c->hz_edge, vel);
+        frhs = vel;
+    }
+    const size_t nsp = (size_t)g.nxh * ny;
+    double2* su = c->hspec;
+    double2* sv = su + nsp * nz;
+    double2* sw = sv + nsp * nz;
+    double2* sp = sw + nsp * (nz + 1);
+    int rc = fft_rows_r2c(c, frhs, su, ny * nz, s);
+    if (!rc) rc = fft_rows_r2c(c, frhs + ncell, sv, ny * nz, s);
+    if (!rc) rc = fft_rows_r2c(c, frhs + 2 * ncell, sw, ny * (nz + 1), s);
+    if (!rc) rc = fft_cols(c, su, nz, 0, s);
+    if (!rc) rc = fft_cols(c, sv, nz, 0, s);
+    if (!rc) rc = fft_cols(c, sw, nz + 1, 0, s);
+    if (rc) return rc;
+    const int nmode = g.nxh * ny;
+    const double norm = 1.0 / ((double)nx * ny);
+    stokes_mode_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hscr, nx, ny, nz,
+                                                       c->grid.h, p->eta, norm);
+    rc = fft_cols(c, su, nz, 1, s);
+    if (!rc) rc = fft_cols(c, sv, nz, 1, s);
+    if (!rc) rc = fft_cols(c, sw, nz + 1, 1, s);
+    if (!rc && pres) rc = fft_cols(c, sp, nz, 1, s);
+    if (!rc) rc = fft_rows_c2r(c, su, vel, ny * nz, s);
+    if (!rc) rc = fft_rows_c2r(c, sv, vel + ncell, ny * nz, s);
+    if (!rc) rc = fft_rows_c2r(c, sw, vel + 2 * ncell, ny * (nz + 1), s);
+    if (!rc && pres) rc = fft_rows_c2r(c, sp, pres, ny * nz, s);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+}  // namespace discos

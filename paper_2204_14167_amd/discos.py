@@ -20,7 +20,9 @@ E_ARG, E_SHAPE, E_HIP, E_OUT_OF_DOMAIN, E_NOT_NEUTRAL, E_NONFINITE, E_CAPACITY =
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 SPREAD_CHARGE, SPREAD_FORCE, SPREAD_ADD_BC = 0, 1, 0x100
 INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
-STEP_DRY = 0
+STEP_DRY, STEP_WET = 0, 1
+CREATE_HYDRO = 1
+STOKES_NOISE = 1
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -81,6 +83,8 @@ def lib():
         L.discos_destroy.argtypes = [vp]
         L.discos_spread.argtypes = [vp, i32, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
         L.discos_solve_poisson.argtypes = [vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
+        L.discos_solve_stokes.argtypes = [vp, vp, ctypes.POINTER(DiscosParams), u64, i32, vp, vp,
+                                          vp]
         L.discos_interpolate.argtypes = [vp, i32, i64, vp, vp, vp, ctypes.POINTER(DiscosParams),
                                          vp, vp]
         L.discos_near_field.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
@@ -93,6 +97,7 @@ def lib():
         L.discos_last_error.argtypes = [vp]
         L.discos_last_error.restype = ctypes.c_char_p
         for name in ("discos_create", "discos_destroy", "discos_spread", "discos_solve_poisson",
+                     "discos_solve_stokes",
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
                      "discos_profile", "discos_profile_read"):
             getattr(L, name).restype = ctypes.c_int
@@ -177,11 +182,12 @@ class Params:
 class Context:
     """One grid and up to n_max ions; owns the library context."""
 
-    def __init__(self, nx, ny, nz, h=1.0, n_max=0):
+    def __init__(self, nx, ny, nz, h=1.0, n_max=0, hydro=False):
         self.grid = (int(nx), int(ny), int(nz), float(h))
         g = DiscosGrid(int(nx), int(ny), int(nz), float(h))
         h_ = ctypes.c_void_p()
-        rc = lib().discos_create(ctypes.byref(g), int(n_max), 0, ctypes.byref(h_))
+        flags = CREATE_HYDRO if hydro else 0
+        rc = lib().discos_create(ctypes.byref(g), int(n_max), flags, ctypes.byref(h_))
         if rc != OK:
             raise DiscosError(rc, "discos_create failed")
         self.handle = h_
@@ -211,10 +217,23 @@ class Context:
         return (nz, ny, nx)
 
     # ---- entry points (same names as the C ABI) ---------------------------------
+    @property
+    def face_size(self):
+        nx, ny, nz, _ = self.grid
+        return 2 * nx * ny * nz + nx * ny * (nz + 1)
+
+    def split_faces(self, a):
+        """(u, v, w) views of a flat face array."""
+        nx, ny, nz, _ = self.grid
+        c = nx * ny * nz
+        return (a[:c].view(nz, ny, nx), a[c:2 * c].view(nz, ny, nx),
+                a[2 * c:].view(nz + 1, ny, nx))
+
     def spread(self, op, pos, w, params, out=None):
         nz, ny, nx = self.cell_shape
         if out is None:
-            out = torch.empty((nz, ny, nx), dtype=torch.float64, device=pos.device)
+            shape = (self.face_size,) if (op & 0xFF) == SPREAD_FORCE else (nz, ny, nx)
+            out = torch.empty(shape, dtype=torch.float64, device=pos.device)
         self._rc(lib().discos_spread(self.handle, op, pos.shape[1], _ptr(pos), _ptr(w),
                                      ctypes.byref(params.struct), _ptr(out), _stream()))
         return out
@@ -224,6 +243,14 @@ class Context:
             out = torch.empty_like(rhs)
         self._rc(lib().discos_solve_poisson(self.handle, _ptr(rhs), ctypes.byref(params.struct),
                                             _ptr(out), _stream()))
+        return out
+
+    def solve_stokes(self, f, params, step=0, noise=False, out=None, pres=None):
+        if out is None:
+            out = torch.empty_like(f)
+        self._rc(lib().discos_solve_stokes(self.handle, _ptr(f), ctypes.byref(params.struct),
+                                           int(step), STOKES_NOISE if noise else 0, _ptr(out),
+                                           _ptr(pres), _stream()))
         return out
 
     def interpolate(self, op, pos, field, params, aux=None, out=None):

@@ -234,3 +234,16 @@ def test_near_field_newton_third_law_in_bulk():
     pos, q = random_ions(16, 16, 32, 300, seed=9, zmin=8.0, zmax=24.0, charge="normal")
     f = es.near_field(grid, pos, q, EPS, 4.0, table, dr, (D, D))
     assert np.abs(f.sum(axis=1)).max() < 1e-11 * np.abs(f).sum()
+
+
+@pytest.mark.parametrize("bc", [(D, D), (N, N), (D, N)])
+def test_kdtree_near_field_matches_brute_force(bc):
+    table, dr = load_p3m_table()
+    grid = es.Grid(32, 32, 24)
+    pos, q = random_ions(32, 32, 24, 2000, seed=3, charge="normal")
+    rng = np.random.default_rng(1)
+    pos[2, :200] = rng.uniform(0, 3, 200)
+    pos[2, 200:300] = 24 - rng.uniform(0, 3, 100)
+    a = es.near_field(grid, pos, q, EPS, 4.0, table, dr, bc)
+    b = es.near_field_pairs(grid, pos, q, EPS, 4.0, table, dr, bc)
+    assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
