@@ -1,4 +1,4 @@
-"""The dry DISCOS time step, written from Sec. II.C-II.D (test oracle only).
+"""The DISCOS time step, dry and wet, written from Sec. II.C-II.D (test oracle only).
 
 Stages (Sec. II.D): (1) spread charges, solve Poisson; (2) interpolate the field,
 F^P = q E^P, add the P3M near-field correction, the short-range wall force and
@@ -14,6 +14,19 @@ is used throughout.  Ions that cross a wall are reflected (z -> -z, or
 z -> 2 Lz - z, repeated until inside; the paper uses specular reflection at the
 walls in its electro-osmosis runs); x and y are wrapped into [0, L).
 
+Wet step (Sec. II.D stages 3-4, eq disc_stokes_temp, eq step1, eq step2): the
+same forces F^n are spread with S^hy, the fluctuating no-slip Stokes problem is
+solved once for v^n, and the ions move by the midpoint rule
+
+  x*      = x^n + (dt/2) J(x^n) v^n                     (wrapped / reflected)
+  x^{n+1} = x^n + dt J(x*) v^n + [dry terms of eq step2 at x^n]
+
+with the optional thermal forcing f^th = kT div_x S^hy (eq thermforce) by the random
+finite difference (kT/delta) [S(x + delta/2 W) W - S(x - delta/2 W) W], one
+Gaussian W per ion from its own stream.  The dry terms use the caller's dry radius
+(a_d of eq einstein; an infinite radius means no dry diffusion) and the same
+Gamma coefficients as the dry step.
+
 Parameters are a plain dict (see the keys read below).
 """
 import numpy as np
@@ -21,14 +34,17 @@ import numpy as np
 from . import electrostatics as es
 from . import mobility
 from . import shortrange
-from .rng import TAG_DRY, ion_normals
+from . import stokes
+from .rng import TAG_DRY, TAG_RFD, ion_normals
 
 
-def total_force(grid, pos, q, species, p, targets=None):
+def total_force(grid, pos, q, species, p, targets=None, near="brute"):
     """F = F^P + sum F^LC + F^W (+ F^R) + q E_ext, eq totalforce; returns (F, parts).
 
     The grid part uses all ions; with `targets` the forces (interpolation,
-    near-field, short-range) are evaluated for that subset only.
+    near-field, short-range) are evaluated for that subset only.  near="pairs"
+    takes the near-field sum from the k-d tree pair search (all ions, no
+    `targets`), for large systems.
     """
     sel = slice(None) if targets is None else np.asarray(targets)
     rho, phi = es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
@@ -36,8 +52,14 @@ def total_force(grid, pos, q, species, p, targets=None):
     ep = es.interp_field(grid, pos[:, sel], *es.face_fields(grid, ext))
     fp = q[sel][None, :] * (ep + np.asarray(p["e_ext"], dtype=np.float64)[:, None])
     F = fp.copy()
-    fn = es.near_field(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
-                       p["bc_types"], targets=targets)
+    if near == "pairs":
+        if targets is not None:
+            raise ValueError("near='pairs' evaluates every ion")
+        fn = es.near_field_pairs(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
+                                 p["bc_types"])
+    else:
+        fn = es.near_field(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
+                           p["bc_types"], targets=targets)
     F += fn
     if p.get("wall_on", True):
         F[2] += shortrange.wall_force(pos[2, sel], grid.L[2], p["wall_sigma"], p["wall_xi"],
@@ -114,3 +136,50 @@ def dry_step(grid, pos, q, species, ids, p, step, targets=None):
     sel = slice(None) if targets is None else np.asarray(targets)
     new = dry_update(grid, pos[:, sel], F, species[sel], ids[sel], p, step)
     return new, F, parts
+
+
+def confine(grid, pos):
+    """x, y wrapped into [0, L), z reflected into [0, Lz]."""
+    out = np.empty_like(pos)
+    out[0] = wrap_periodic(pos[0], grid.L[0])
+    out[1] = wrap_periodic(pos[1], grid.L[1])
+    out[2] = reflect_walls(pos[2], grid.L[2])
+    return out
+
+
+def thermal_forcing(grid, pos, ids, kT, delta, seed, step):
+    """f^th = kT div_x S^hy (eq thermforce) by the random finite difference
+    (kT / delta) [S(x + delta/2 W) W - S(x - delta/2 W) W], W ~ N(0, I) per ion."""
+    if not delta > 0.0:
+        raise ValueError("delta must be positive")
+    W = ion_normals(seed, step, TAG_RFD, ids)
+    half = 0.5 * delta * W
+    if np.abs(half).max(initial=0.0) >= grid.h:
+        raise ValueError("random finite difference shift of a cell or more")
+    plus = stokes.spread_force(grid, pos + half, W, slack=grid.h)
+    minus = stokes.spread_force(grid, pos - half, W, slack=grid.h)
+    return tuple(kT / delta * (a - b) for a, b in zip(plus, minus))
+
+
+def wet_step(grid, pos, q, species, ids, p, step, noise=True, rfd_delta=0.0, near="brute",
+             targets=None):
+    """One wet step (eq disc_stokes_temp, eq step1, eq step2); returns
+    (new positions of `targets` (all ions by default), F, intermediates)."""
+    F, parts = total_force(grid, pos, q, species, p, near=near)
+    fx, fy, fz = stokes.spread_force(grid, pos, F)
+    if rfd_delta > 0.0:
+        tx, ty, tz = thermal_forcing(grid, pos, ids, p["kT"], rfd_delta, p["seed"], step)
+        fx, fy, fz = fx + tx, fy + ty, fz + tz
+    if noise:
+        nfx, nfy, nfz = stokes.noise_force(grid, p["kT"], p["eta"], p["dt"], p["seed"], step)
+        fx, fy, fz = fx + nfx, fy + nfy, fz + nfz
+    u, v, w, _ = stokes.solve_stokes(grid, p["eta"], fx, fy, fz)
+    sel = slice(None) if targets is None else np.asarray(targets)
+    x0 = pos[:, sel]
+    dt = p["dt"]
+    V0 = stokes.interp_velocity(grid, x0, u, v, w)
+    mid = confine(grid, x0 + 0.5 * dt * V0)
+    V1 = stokes.interp_velocity(grid, mid, u, v, w)
+    disp = dt * V1 + dry_displacement(grid, x0, F[:, sel], species[sel], ids[sel], p, step)
+    new = confine(grid, x0 + disp)
+    return new, F, dict(parts, V0=V0, V1=V1, mid=mid, vel=(u, v, w))

@@ -30,14 +30,15 @@ from .peskin import node_weights
 from .rng import TAG_STRESS_DIAG, TAG_STRESS_EDGE, normal_pair
 
 
-def _check(grid, pos):
+def _check(grid, pos, slack=0.0):
     if grid.nz < 4:
         raise ValueError("nz must be >= 4")
-    if np.any(~np.isfinite(pos)) or np.any(pos[2] < 0) or np.any(pos[2] > grid.L[2]):
+    if (np.any(~np.isfinite(pos)) or np.any(pos[2] < -slack)
+            or np.any(pos[2] > grid.L[2] + slack)):
         raise ValueError("ion outside the channel")
 
 
-def spread_force(grid, pos, F):
+def spread_force(grid, pos, F, slack=0.0):
     """S^hy F on the faces with no-slip images (eq kernel2, Fig. folded).
 
     Every component's image is opposite (zero tangential and normal mobility at a
@@ -45,8 +46,11 @@ def spread_force(grid, pos, F):
     the wall (k < 0) lands on -1-k with sign -1.  The z component lives on z-faces:
     a node at k < 0 lands on -k with sign -1, so the wall face itself collects
     f - f = 0; likewise at the top.
+
+    `slack` admits kernel centres up to that far outside the walls (the shifted
+    positions of the random finite difference); the same folds apply.
     """
-    _check(grid, pos)
+    _check(grid, pos, slack)
     nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
     out = []
     for comp, offs in ((0, (0.0, 0.5, 0.5)), (1, (0.5, 0.0, 0.5)), (2, (0.5, 0.5, 0.0))):
