@@ -87,10 +87,14 @@ typedef struct discos_params {
     /* dynamics (Sec. II.C, II.D) */
     double kT, eta, dt;
     int32_t nspecies;
-    const double* radius;       /* device [nspecies]: dry radius a, D = kT / (6 pi eta a) */
+    const double* radius;       /* device [nspecies]: dry radius a, D = kT / (6 pi eta a)
+                                   (eq einstein); +INFINITY means no dry diffusion */
     const double* mob_coef;     /* device [nspecies][2][7]: c1..c7 of eq fitfunction for
                                    motion parallel [0] and perpendicular [1] to the walls */
     uint64_t seed;              /* Philox key of every noise term */
+    double rfd_delta;           /* step delta of the random finite difference that gives
+                                   the thermal forcing f^th = kT div_x S^hy (eq thermforce)
+                                   in a DISCOS_STEP_RFD step; (0, 0.1 h] */
 } discos_params;
 
 /* Ion state for discos_step.  pos, q, id and species are DEVICE arrays of length n. */
@@ -207,11 +211,17 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
  */
 #define DISCOS_STEP_DRY 0
 /* DISCOS_STEP_WET: the forces as in the dry step, then stage 3 (S^hy F, fluctuating
- * no-slip Stokes solve with noise counter `step`) and stage 4 (eq step1 / step2): the
- * midpoint x* = x + dt/2 J(x) v (wrapped and reflected like the final positions),
- * x+ = x + dt J(x*) v plus the dry terms evaluated at x (the dry radius in p->radius;
- * a very large radius switches the dry part off).  Needs DISCOS_CREATE_HYDRO. */
+ * no-slip Stokes solve with noise counter `step`, eq disc_stokes_temp) and stage 4
+ * (eq step1 / step2): the midpoint x* = x + dt/2 J(x) v (wrapped and reflected like
+ * the final positions), x+ = x + dt J(x*) v plus the dry terms evaluated at x (the
+ * dry radius in p->radius; +INFINITY switches the dry part off).  Needs
+ * DISCOS_CREATE_HYDRO and kT, dt > 0.
+ * DISCOS_STEP_RFD (or-ed with DISCOS_STEP_WET) adds the thermal forcing of
+ * eq thermforce by the random finite difference
+ *   f^th = (kT / delta) [S^hy(x + delta/2 W) W - S^hy(x - delta/2 W) W],
+ * W ~ N(0, I) per ion from Philox counter (id, step, 4, pair), delta = p->rfd_delta. */
 #define DISCOS_STEP_WET 1
+#define DISCOS_STEP_RFD 0x10
 int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint64_t step,
                 int mode, void* stream);
 
@@ -221,10 +231,11 @@ int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
  * the mean elapsed milliseconds per recorded step of each stage (host array of at
  * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
- * inverse y-FFT, inverse x-FFT, interpolation, near-field, update) and sets *count
- * (0 when no step was recorded).
+ * inverse y-FFT, inverse x-FFT, interpolation, near-field, S^hy, Stokes solve, the two
+ * J^hy passes with the predictor, update; the hydrodynamic stages read 0 in dry
+ * steps) and sets *count (0 when no step was recorded).
  */
-#define DISCOS_NSTAGE 10
+#define DISCOS_NSTAGE 13
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
 

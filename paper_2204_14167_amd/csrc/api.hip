@@ -346,12 +346,22 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
     if (n > 0 && (!ions->pos || !ions->q || !ions->id || !ions->species))
         return fail(c, DISCOS_E_ARG, "null ion array");
-    if (mode != DISCOS_STEP_DRY) return fail(c, DISCOS_E_ARG, "unknown step mode");
+    const int base = mode & 0xF;
+    const int rfd = (mode & DISCOS_STEP_RFD) ? 1 : 0;
+    if ((mode & ~(0xF | DISCOS_STEP_RFD)) || (base != DISCOS_STEP_DRY && base != DISCOS_STEP_WET))
+        return fail(c, DISCOS_E_ARG, "unknown step mode");
+    const int wet = base == DISCOS_STEP_WET;
+    if (rfd && !wet) return fail(c, DISCOS_E_ARG, "DISCOS_STEP_RFD needs DISCOS_STEP_WET");
+    if (wet && !c->hydro) return fail(c, DISCOS_E_ARG, "context created without DISCOS_CREATE_HYDRO");
     int rc = check_near_params(c, p, ions->species);
     if (rc) return rc;
     if (!finite_pos(p->kT) || !finite_pos(p->eta) || !finite_pos(p->dt) || p->nspecies < 1 ||
         !p->radius || !p->mob_coef)
         return fail(c, DISCOS_E_ARG, "dynamics parameters invalid");
+    // |delta W / 2| <= 0.05 h * 8.6 (the largest Box-Muller normal of 53-bit uniforms)
+    // stays below half a cell, the reach the S^hy tiles assume
+    if (rfd && !(finite_pos(p->rfd_delta) && p->rfd_delta <= 0.1 * c->grid.h))
+        return fail(c, DISCOS_E_ARG, "rfd_delta must lie in (0, 0.1 h]");
     const int ni = (int)n;
     double* pos = ions->pos;
     discos::stage_mark(c, 0, s);
@@ -363,8 +373,33 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc) rc = discos::solve_poisson(c, c->rho, p, c->phi, s, 3);
     if (!rc) rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, c->phi, p, c->fp, c->n_max, 0, s);
     discos::stage_mark(c, 8, s);
-    if (!rc) rc = discos::force_update_dry(c, ni, p, step, pos, ions->q, ions->id, ions->species, s);
-    discos::stage_mark(c, 10, s);
+    // complete the forces in place: fp (grid + applied field) += near field + wall (+ LJ)
+    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s);
+    discos::stage_mark(c, 9, s);
+    const double* vwet = nullptr;
+    if (wet && !rc && ni > 0) {
+        discos::RfdDev rd{};
+        if (rfd) {
+            rd.sid = c->sid;
+            rd.scale = p->kT / p->rfd_delta;
+            rd.half = 0.5 * p->rfd_delta;
+            rd.seed = p->seed;
+            rd.step = step;
+        }
+        rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr);
+        discos::stage_mark(c, 10, s);
+        if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
+        discos::stage_mark(c, 11, s);
+        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s);
+        discos::stage_mark(c, 12, s);
+        vwet = c->hvi;
+    } else {
+        discos::stage_mark(c, 10, s);
+        discos::stage_mark(c, 11, s);
+        discos::stage_mark(c, 12, s);
+    }
+    if (!rc) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
+    discos::stage_mark(c, 13, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
 }

@@ -140,4 +140,24 @@ __device__ __forceinline__ int bin_of(const GridDev& g, double x, double y, doub
     return (bz * g.nby + by) * g.nbx + bx;
 }
 
+// Periodic wrap into [0, L) (-0 and L map to 0).
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+    double r = fmod(x, L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    if (r == 0.0) r = 0.0;
+    return r;
+}
+
+// Specular reflection at both walls until inside: exact for one crossing, the
+// period-2Lz fold of the reflections for anything farther.
+__device__ __forceinline__ double reflect_walls(double z, double Lz) {
+    if (z >= 0.0 && z <= Lz) return z;
+    if (z < 0.0 && z >= -Lz) return -z;
+    if (z > Lz && z <= 2.0 * Lz) return 2.0 * Lz - z;
+    double t = fmod(z, 2.0 * Lz);
+    if (t < 0.0) t += 2.0 * Lz;
+    return t <= Lz ? t : 2.0 * Lz - t;
+}
+
 }  // namespace discos

@@ -88,8 +88,17 @@ int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_para
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
                       int scatter_to_caller, hipStream_t s);
 
-// S^hy of the sorted forces c->fp onto the three face arrays of out.
-int spread_force_sorted(Ctx* c, double* out, hipStream_t s);
+// Random finite difference of the thermal forcing (scale = kT / delta, half = delta / 2;
+// scale 0: off); sid holds the ions' stable ids in cell-list order.
+struct RfdDev {
+    const int* sid;
+    double scale, half;
+    uint64_t seed, step;
+};
+
+// S^hy of the sorted forces c->fp onto the three face arrays of out (+ the thermal
+// forcing when rfd is given).
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd = nullptr);
 // Stokes solve with no-slip walls (f: three face arrays; vel likewise; pres nullable).
 int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
                  double* vel, double* pres, hipStream_t s);
@@ -97,8 +106,13 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
 int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
                      hipStream_t s);
 
-// Fused force completion and dry update of the sorted ions, written to the caller arrays.
-int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, double* pos,
-                     double* q, int* id, int* sp, hipStream_t s);
+// Predictor and corrector velocities of the wet step: c->hmid = x*, c->hvi = J(x*) v.
+int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s);
+
+// Update of the sorted ions from their complete forces c->fp (dry terms of eq step2)
+// plus dt * vwet (nullable, [3][n_max] sorted), written to the caller's arrays in
+// cell-list order.
+int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
+                  double* pos, double* q, int* id, int* sp, hipStream_t s);
 
 }  // namespace discos

@@ -393,30 +393,13 @@ __device__ __forceinline__ double dgamma_hat(double y, const double* c) {
     return -c[1] / (t1 * t1) - 3.0 * c[3] / (t32 * t32) - 5.0 * c[5] / (t52 * t52 * t52);
 }
 
-__device__ __forceinline__ double wrap_coord(double x, double L) {
-    double r = fmod(x, L);
-    if (r < 0.0) r += L;
-    if (r >= L) r -= L;
-    if (r == 0.0) r = 0.0;
-    return r;
-}
-
-// Specular reflection at both walls until inside: exact for one crossing, the
-// period-2Lz fold of the reflections for anything farther.
-__device__ __forceinline__ double reflect_walls(double z, double Lz) {
-    if (z >= 0.0 && z <= Lz) return z;
-    if (z < 0.0 && z >= -Lz) return -z;
-    if (z > Lz && z <= 2.0 * Lz) return 2.0 * Lz - z;
-    double t = fmod(z, 2.0 * Lz);
-    if (t < 0.0) t += 2.0 * Lz;
-    return t <= Lz ? t : 2.0 * Lz - t;
-}
-
-// Dry update of one ion (eq ions3 dry part, Euler-Maruyama, Ito): returns the new
-// position (wrapped in x, y, reflected at the walls).
+// Update of one ion: the dry terms of eq ions3 / eq step2 (Euler-Maruyama, Ito) plus
+// the wet displacement (wx0, wy0, wz0) = dt J(x*) v (zero in a dry step); returns the
+// new position (wrapped in x, y, reflected at the walls).
 __device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int spi, int idi,
                                          double xi, double yi, double zi, double Fx, double Fy,
-                                         double Fz, double& nx, double& ny, double& nz,
+                                         double Fz, double wx0, double wy0, double wz0,
+                                         double& nx, double& ny, double& nz,
                                          int* __restrict__ flags) {
     const double a = Dd.radius[spi];
     const double D = Dd.kT / (6.0 * M_PI * Dd.eta * a);
@@ -440,9 +423,9 @@ __device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int
     dx += sqrt(2.0 * D * Gp * Dd.dt) * wx;
     dy += sqrt(2.0 * D * Gp * Dd.dt) * wy;
     dz += sqrt(2.0 * D * Gn * Dd.dt) * wz;
-    nx = xi + dx;
-    ny = yi + dy;
-    nz = zi + dz;
+    nx = xi + (wx0 + dx);
+    ny = yi + (wy0 + dy);
+    nz = zi + (wz0 + dz);
     if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) {
         set_flag(flags, DISCOS_FLAG_NONFINITE);
         nx = xi;
@@ -455,11 +438,13 @@ __device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int
     }
 }
 
-// Dry update of every ion of the cell list from its complete force fp (grid, near
-// field, wall, applied field), written to the caller's arrays in cell-list order.
+// Update of every ion of the cell list from its complete force fp (grid, near field,
+// wall, applied field) and, in a wet step, its velocity vw = J(x*) v, written to the
+// caller's arrays in cell-list order.
 __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
                                   const int* __restrict__ sid, const int* __restrict__ ssp,
                                   const double* __restrict__ fp, int64_t fstride,
+                                  const double* __restrict__ vw,
                                   double* __restrict__ pos, int64_t pstride, double* __restrict__ q,
                                   int* __restrict__ id, int* __restrict__ sp,
                                   int* __restrict__ flags) {
@@ -473,8 +458,14 @@ __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __
     const int spi = sp_ok ? sp_in : 0;
     double nx = me.x, ny = me.y, nz = me.z;
     if (pos_ok(g, me.x, me.y, me.z)) {
+        double wx0 = 0.0, wy0 = 0.0, wz0 = 0.0;
+        if (vw) {
+            wx0 = Dd.dt * vw[gi];
+            wy0 = Dd.dt * vw[gi + fstride];
+            wz0 = Dd.dt * vw[gi + 2 * fstride];
+        }
         dry_move(g, Dd, spi, idi, me.x, me.y, me.z, fp[gi], fp[gi + fstride], fp[gi + 2 * fstride],
-                 nx, ny, nz, flags);
+                 wx0, wy0, wz0, nx, ny, nz, flags);
     } else {
         set_flag(flags, (isfinite(me.x) && isfinite(me.y) && isfinite(me.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
                                                                           : DISCOS_FLAG_NONFINITE);
@@ -487,13 +478,9 @@ __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __
     sp[gi] = sp_in;
 }
 
-int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, double* pos,
-                     double* q, int* id, int* sp, hipStream_t s) {
+int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
+                  double* pos, double* q, int* id, int* sp, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
-    // complete the forces in place: fp (grid + applied field) += near field + wall
-    int rc = near_field_sorted(c, n, p, c->fp, c->n_max, 0, s);
-    if (rc) return rc;
-    stage_mark(c, 9, s);
     DryDev Dd;
     Dd.nsp = p->nspecies;
     Dd.kT = p->kT;
@@ -504,7 +491,7 @@ int force_update_dry(Ctx* c, int n, const discos_params* p, uint64_t step, doubl
     Dd.seed = p->seed;
     Dd.step = step;
     dry_update_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, Dd, n, c->sxyzq, c->sid, c->ssp, c->fp,
-                                                      c->n_max, pos, n, q, id, sp, c->flags);
+                                                      c->n_max, vwet, pos, n, q, id, sp, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

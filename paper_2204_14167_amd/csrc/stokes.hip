@@ -67,12 +67,61 @@ __device__ int tile_ranges_h(const GridDev& g, const int* __restrict__ bin_start
     return nr;
 }
 
+// Deposit val * phi(x - node) / h^3 of one kernel centre (px, py, pz) into the tile.
 // COMP 0 / 1: x / y component at cell-centre heights, images fold k -> -1-k (sign -1).
 // COMP 2: z component on z-faces, images fold k -> -k (sign -1); wall faces hold 0.
 template <int COMP>
+__device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int x0, int y0, int z0,
+                                             int tx, int ty, int tz, double px, double py,
+                                             double pz, double val) {
+    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
+    int ix0, iy0, iz0;
+    double wx[4], wy[4], wz[4];
+    peskin4(px * g.inv_h - ox, ix0, wx);
+    peskin4(py * g.inv_h - oy, iy0, wy);
+    peskin4(pz * g.inv_h - oz, iz0, wz);
+    int lxs[4], lys[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int kz = iz0 + c;
+        double sgn = 1.0;
+        if (COMP == 2) {
+            if (kz < 0) { kz = -kz; sgn = -1.0; }
+            else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
+            if (kz == 0 || kz == g.nz) continue;
+        } else {
+            if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
+            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
+        }
+        const int lz = kz - z0;
+        if (lz < 0 || lz >= tz) continue;
+        const double wzc = val * sgn * wz[c];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (lys[b] >= ty) continue;
+            const double wyz = wzc * wy[b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (lxs[a] >= tx) continue;
+                atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
+            }
+        }
+    }
+}
+
+// S^hy F on one face grid; with rfd.scale != 0 every ion also deposits the random
+// finite difference (kT / delta) [phi(x + delta/2 W) - phi(x - delta/2 W)] W_COMP of
+// the thermal forcing.  The shifts are below half a cell, so the shifted kernels
+// reach only nodes within two cells of the ion's own cell, the range the tile's
+// candidate rows cover.
+template <int COMP>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
-                   const int* __restrict__ bin_start, double* __restrict__ out) {
+                   const int* __restrict__ bin_start, RfdDev rfd, double* __restrict__ out) {
     __shared__ double acc[SH_TX * SH_TY * SH_TZ];
     __shared__ int rstart[SH_MAXR], rpre[SH_MAXR + 1], scan[SH_THREADS];
     const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
@@ -86,7 +135,6 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
                                  rpre, scan);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
-    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
         int r = 0, hi = nr - 1;
         while (r < hi) {
@@ -96,42 +144,17 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
         const int i = rstart[r] + (f - rpre[r]);
         const double4 a4 = sxyzq[i];
         if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
-        int ix0, iy0, iz0;
-        double wx[4], wy[4], wz[4];
-        peskin4(a4.x * g.inv_h - ox, ix0, wx);
-        peskin4(a4.y * g.inv_h - oy, iy0, wy);
-        peskin4(a4.z * g.inv_h - oz, iz0, wz);
-        const double scale = fw[i] * inv_h3;
-        int lxs[4], lys[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            int kz = iz0 + c;
-            double sgn = 1.0;
-            if (COMP == 2) {
-                if (kz < 0) { kz = -kz; sgn = -1.0; }
-                else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
-                if (kz == 0 || kz == g.nz) continue;
-            } else {
-                if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
-                else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
-            }
-            const int lz = kz - z0;
-            if (lz < 0 || lz >= tz) continue;
-            const double wzc = scale * sgn * wz[c];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (lys[b] >= ty) continue;
-                const double wyz = wzc * wy[b];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    if (lxs[a] >= tx) continue;
-                    atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
-                }
-            }
+        deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, fw[i] * inv_h3);
+        if (rfd.scale != 0.0) {
+            double w0, w1, w2, unused;
+            const uint32_t idi = (uint32_t)rfd.sid[i];
+            normal_pair(rfd.seed, rfd.step, DISCOS_TAG_RFD, 0u, idi, w0, w1);
+            normal_pair(rfd.seed, rfd.step, DISCOS_TAG_RFD, 1u, idi, w2, unused);
+            const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
+            const double v = rfd.scale * wc * inv_h3;
+            const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
+            deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x + hx, a4.y + hy, a4.z + hz, v);
+            deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x - hx, a4.y - hy, a4.z - hz, -v);
         }
     }
     __syncthreads();
@@ -144,17 +167,19 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     }
 }
 
-int spread_force_sorted(Ctx* c, double* out, hipStream_t s) {
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in) {
     const GridDev& g = c->gd;
+    RfdDev rfd{};
+    if (rfd_in) rfd = *rfd_in;
     const int tx = std::min(SH_TX, g.nx), ty = std::min(SH_TY, g.ny);
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + SH_TZ - 1) / SH_TZ);
     dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + SH_TZ - 1) / SH_TZ);
-    spread_face_kernel<0><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, out);
+    spread_face_kernel<0><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd, out);
     spread_face_kernel<1><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max, c->bin_start,
-                                                       out + ncell);
+                                                       rfd, out + ncell);
     spread_face_kernel<2><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
-                                                       c->bin_start, out + 2 * ncell);
+                                                       c->bin_start, rfd, out + 2 * ncell);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -428,17 +453,26 @@ __device__ __forceinline__ double face_val(const double* __restrict__ a, const G
     return s * a[((size_t)k * g.ny + j) * g.nx + i];
 }
 
-__global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ sxyzq,
+// V = J^hy v at the positions xs.  With mid != nullptr the kernel is the predictor of
+// eq step1: mid[i] = (x + half_dt V wrapped in x, y and reflected in z, q); otherwise
+// V goes to out[o] (o = perm[i] if scatter) with the given component stride.
+__global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ xs,
                                  const int* __restrict__ perm, const double* __restrict__ vel,
                                  double* __restrict__ out, int64_t stride, int scatter,
+                                 double4* __restrict__ mid, double half_dt,
                                  int* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int o = scatter ? perm[i] : i;
-    const double4 a4 = sxyzq[i];
+    const double4 a4 = xs[i];
     if (!pos_ok(g, a4.x, a4.y, a4.z)) {
-        set_flag(flags, DISCOS_FLAG_OUT_OF_DOMAIN);
-        out[o] = out[o + stride] = out[o + 2 * stride] = 0.0;
+        set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                          : DISCOS_FLAG_NONFINITE);
+        if (mid) {
+            mid[i] = a4;
+        } else {
+            const int o = scatter ? perm[i] : i;
+            out[o] = out[o + stride] = out[o + 2 * stride] = 0.0;
+        }
         return;
     }
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
@@ -466,6 +500,17 @@ __global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ s
         }
         res[comp] = acc;
     }
+    if (mid) {
+        double mx = a4.x + half_dt * res[0], my = a4.y + half_dt * res[1], mz = a4.z + half_dt * res[2];
+        if (!(isfinite(mx) && isfinite(my) && isfinite(mz))) {
+            set_flag(flags, DISCOS_FLAG_NONFINITE);
+            mid[i] = a4;
+            return;
+        }
+        mid[i] = make_double4(wrap_coord(mx, g.Lx), wrap_coord(my, g.Ly), reflect_walls(mz, g.Lz), a4.w);
+        return;
+    }
+    const int o = scatter ? perm[i] : i;
     out[o] = res[0];
     out[o + stride] = res[1];
     out[o + 2 * stride] = res[2];
@@ -475,7 +520,19 @@ int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stri
                      hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
     interp_hy_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, out, stride,
-                                                    scatter, c->flags);
+                                                    scatter, nullptr, 0.0, c->flags);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+// Stage 4 velocities of the wet step for the ions of the cell list: the predictor
+// x* = x + dt/2 J(x) v into c->hmid, then J(x*) v into c->hvi ([3][n_max], sorted).
+int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s) {
+    if (n <= 0) return DISCOS_OK;
+    const int blocks = (n + 255) / 256;
+    interp_hy_kernel<<<blocks, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, nullptr, 0, 0,
+                                           c->hmid, 0.5 * dt, c->flags);
+    interp_hy_kernel<<<blocks, 256, 0, s>>>(c->gd, n, c->hmid, c->perm, vel, c->hvi, c->n_max, 0,
+                                           nullptr, 0.0, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

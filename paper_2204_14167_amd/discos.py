@@ -20,7 +20,7 @@ E_ARG, E_SHAPE, E_HIP, E_OUT_OF_DOMAIN, E_NOT_NEUTRAL, E_NONFINITE, E_CAPACITY =
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 SPREAD_CHARGE, SPREAD_FORCE, SPREAD_ADD_BC = 0, 1, 0x100
 INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
-STEP_DRY, STEP_WET = 0, 1
+STEP_DRY, STEP_WET, STEP_RFD = 0, 1, 0x10
 CREATE_HYDRO = 1
 STOKES_NOISE = 1
 
@@ -58,6 +58,7 @@ class DiscosParams(ctypes.Structure):
         ("radius", ctypes.c_void_p),
         ("mob_coef", ctypes.c_void_p),
         ("seed", ctypes.c_uint64),
+        ("rfd_delta", ctypes.c_double),
     ]
 
 
@@ -176,6 +177,7 @@ class Params:
             self._keep.append(c)
             s.mob_coef = c.data_ptr()
         s.seed = int(p.get("seed", 0))
+        s.rfd_delta = float(p.get("rfd_delta", 0.0))
         self.struct = s
 
 
@@ -277,7 +279,7 @@ class Context:
                                    int(step), mode, _stream()))
 
     STAGES = ("cell_list", "spread", "fft_x", "fft_y", "z_solve", "ifft_y", "ifft_x",
-              "interp", "near_field", "update")
+              "interp", "near_field", "spread_hy", "stokes", "interp_hy", "update")
 
     def profile(self, enable=True):
         self._rc(lib().discos_profile(self.handle, int(enable)))

@@ -4,12 +4,16 @@ import ctypes
 import glob
 import os
 import re
+import shutil
+import subprocess
+import tempfile
 
 import pytest
 
 from paper_2204_14167_amd import discos
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
@@ -38,12 +42,30 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_ctypes_layout_matches_header():
-    # offsets of the struct members as the C compiler lays them out on x86-64
-    expect = dict(eps=0, bc_type=8, bc_value=16, e_ext=32, psi=56, p3m_table=64, p3m_len=72,
-                  p3m_dr=80, wall_on=88, wall_sigma=96, lj_on=120, lj_range=152, kT=160,
-                  nspecies=184, radius=192, mob_coef=200, seed=208)
-    for k, v in expect.items():
-        assert getattr(discos.DiscosParams, k).offset == v, k
-    assert ctypes.sizeof(discos.DiscosParams) == 216
-    assert ctypes.sizeof(discos.DiscosIons) == 40
+def _c_layout(struct, members):
+    """offsetof of each member and sizeof, as gcc lays out the header's struct."""
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"discos.h\"\nint main(void) {\n"
+    for m in members:
+        src += f'    printf("%zu\\n", offsetof({struct}, {m}));\n'
+    src += f'    printf("%zu\\n", sizeof({struct}));\n    return 0;\n}}\n'
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", INCLUDE, c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    return dict(zip(members, vals[:-1])), vals[-1]
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+@pytest.mark.parametrize("cls,name", [("DiscosParams", "discos_params"), ("DiscosIons", "discos_ions"),
+                                      ("DiscosGrid", "discos_grid")])
+def test_ctypes_layout_matches_header(cls, name):
+    st = getattr(discos, cls)
+    members = [f[0] for f in st._fields_]
+    offs, size = _c_layout(name, members)
+    for m in members:
+        assert getattr(st, m).offset == offs[m], m
+    assert ctypes.sizeof(st) == size
