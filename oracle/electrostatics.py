@@ -134,7 +134,7 @@ def _thomas(lower, diag, upper, rhs):
 NEUTRALITY_TOL = 1e-10
 
 
-def solve_poisson(grid, eps, bc_types, rhs):
+def solve_poisson(grid, eps, bc_types, rhs, project=False):
     """Solve -eps lap_h phi = rhs (eq poisson) with homogeneous wall ghosts.
 
     lap_h is the 7-point Laplacian; the ghost rules are phi_{-1} = -phi_0 at a
@@ -148,7 +148,9 @@ def solve_poisson(grid, eps, bc_types, rhs):
     only if the system is neutral (Sec. II.B.1).  That mode is solved in the
     least-squares minimum-norm sense, which fixes mean(phi) = 0; a violation of
     neutrality beyond NEUTRALITY_TOL (relative to the sum over layers of the
-    absolute plane sums) raises ValueError.
+    absolute plane sums) raises ValueError.  project=True skips that check and
+    applies the pseudo-inverse to any rhs (the component along the null space is
+    dropped): the adjoint of the minimum-norm solve, used by the gradient sweeps.
     """
     nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
     R = np.fft.fft2(rhs, axes=(1, 2)) * (h * h / eps)
@@ -166,7 +168,7 @@ def solve_poisson(grid, eps, bc_types, rhs):
         r0 = R[:, 0, 0].copy()
         total = abs(r0.sum())
         scale = np.abs(r0).sum()
-        if total > NEUTRALITY_TOL * max(scale, 1e-300):
+        if not project and total > NEUTRALITY_TOL * max(scale, 1e-300):
             raise ValueError("all-Neumann system is not electro-neutral")
         diag[:, 0, 0] = 1.0 + 2.0  # placeholder, that mode is replaced below
     X = _thomas(-1.0, diag, -1.0, R)

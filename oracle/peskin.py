@@ -44,3 +44,34 @@ def node_weights(x, h, offset, period=None):
     if period is not None:
         n = np.mod(n, period)
     return n, w
+
+
+def dphi_pe(zeta):
+    """d phi_pe / d zeta, the derivative of each branch of eq peskin1d (odd in zeta).
+
+    Continuous everywhere (the kernel is C^1); zero for |zeta| >= 2 and at 0.
+    """
+    z = np.asarray(zeta, dtype=np.float64)
+    r = np.abs(z)
+    out = np.zeros_like(r)
+    inner = r <= 1.0
+    outer = (r > 1.0) & (r < 2.0)
+    ri = r[inner]
+    out[inner] = (-2.0 + (2.0 - 4.0 * ri) / np.sqrt(1.0 + 4.0 * ri - 4.0 * ri * ri)) / 8.0
+    ro = r[outer]
+    rad = np.maximum(-7.0 + 12.0 * ro - 4.0 * ro * ro, 1e-300)
+    out[outer] = (-2.0 - (6.0 - 4.0 * ro) / np.sqrt(rad)) / 8.0
+    return np.sign(z) * out
+
+
+def node_weights_grad(x, h, offset, period=None):
+    """As node_weights, plus d w / d x (= dphi_pe(zeta) / h) for each node."""
+    x = np.asarray(x, dtype=np.float64)
+    s = x / h - offset
+    n0 = np.floor(s).astype(np.int64)
+    n = n0[:, None] + np.arange(-2, 3)[None, :]
+    w = phi_pe(s[:, None] - n)
+    dw = dphi_pe(s[:, None] - n) / h
+    if period is not None:
+        n = np.mod(n, period)
+    return n, w, dw
