@@ -226,6 +226,35 @@ int discos_step(discos_ctx* ctx, discos_ions* ions, const discos_params* p, uint
                 int mode, void* stream);
 
 /*
+ * Energy and electro-osmotic flux of the electrostatic pass (a project addition on
+ * Sec. II.B.1 and stages 1-2 of Sec. II.D):
+ *   rho = S^es q + b (b: the wall terms), phi = A^+ rho (A = -eps lap_h with homogeneous
+ *   ghosts; the mean-zero solution when both walls are Neumann),
+ *   U = (1/2) dV <rho, phi>,   Q = sum_i w(z_i) q_i (E^P_x,i + E_ext,x),
+ * with E^P from J^es of the staggered field (eq efieldop) and w(z) the channel-mean x
+ * velocity per unit x force at height z of the no-slip Stokes flow: the kappa = 0 mode
+ * of eq disc_stokes, -eta D_zz g = 1 / nz, spread with S^hy (needs p->eta > 0).
+ * phi: DEVICE [nz][ny][nx], receives the potential (the checkpoint of the backward
+ * pass); out: DEVICE [2], receives U and Q.  pos [3][n] and q [n] are DEVICE arrays.
+ */
+int discos_energy_flux(discos_ctx* ctx, int64_t n, const double* pos, const double* q,
+                       const discos_params* p, double* phi, double* out, void* stream);
+
+/*
+ * Vector-Jacobian product of discos_energy_flux (hand-written adjoint): with the
+ * cotangents g = (gU, gQ) (DEVICE [2]) writes gU dU/d(.) + gQ dQ/d(.) with respect to
+ * the positions (dpos, [3][n]), the charges (dq, [n]), the wall fields (dbc_lo,
+ * dbc_hi, [ny][nx]: phi_b or sigma of each column) and the applied field (de, [3]).
+ * Every output is a DEVICE array, may be NULL (not computed), and is overwritten.
+ * phi must be the checkpoint written by discos_energy_flux for the same pos, q and p.
+ * Cost: one transposed interpolation, one Poisson solve, one gradient gather.
+ */
+int discos_energy_flux_backward(discos_ctx* ctx, int64_t n, const double* pos, const double* q,
+                                const discos_params* p, const double* phi, const double* g,
+                                double* dpos, double* dq, double* dbc_lo, double* dbc_hi,
+                                double* de, void* stream);
+
+/*
  * Stage timing of discos_step.  discos_profile(ctx, 1) clears the record and makes the
  * next (up to 512) steps record a hipEvent on their stream after each stage;
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes

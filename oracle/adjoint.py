@@ -116,9 +116,10 @@ def _scatter_ex(grid, pos, lam, depth=3):
     return out
 
 
-def gradients(grid, pos, q, p, gU=1.0, gQ=1.0, depth=3):
+def gradients(grid, pos, q, p, gU=1.0, gQ=1.0, depth=3, targets=None):
     """gU dU + gQ dQ with respect to positions [3, n], charges [n], the two wall
-    fields ([ny, nx] each) and the applied field [3]."""
+    fields ([ny, nx] each) and the applied field [3].  With `targets` the position
+    and charge gradients are those of that subset of ions only."""
     eps, bct = p["eps"], p["bc_types"]
     nz, h = grid.nz, grid.h
     U, Q, st = forward(grid, pos, q, p)
@@ -149,6 +150,9 @@ def gradients(grid, pos, q, p, gU=1.0, gQ=1.0, depth=3):
     for wall, layer in ((0, 0), (1, nz - 1)):
         coef = 2.0 * eps / h ** 2 if bct[wall] == es.DIRICHLET else 1.0 / h
         dbc[wall] += coef * rbar[layer]
+    de = np.array([gQ * float((q * w).sum()), 0.0, 0.0])
+    sel = slice(None) if targets is None else np.asarray(targets)
+    pos, q, w, dw, Fx, Ex = pos[:, sel], q[sel], w[sel], dw[sel], Fx[sel], Ex[sel]
     # S^T rbar at the ions (value and gradient): J with the homogeneous ghosts / dV
     val, grad = _gather_value_grad(grid, pos, _homogeneous(grid, p, rbar), (0.5, 0.5, 0.5), depth)
     dq = val / grid.dV
@@ -158,5 +162,4 @@ def gradients(grid, pos, q, p, gU=1.0, gQ=1.0, depth=3):
     _, gEx = _gather_value_grad(grid, pos, ex, (0.0, 0.5, 0.5), depth)
     dpos += (gQ * w * q)[None, :] * gEx
     dpos[2] += gQ * dw * Fx
-    de = np.array([gQ * float((q * w).sum()), 0.0, 0.0])
     return dict(U=U, Q=Q, pos=dpos, q=dq, bc=dbc, e_ext=de)

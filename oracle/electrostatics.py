@@ -229,7 +229,7 @@ def _gather(grid, pos, field_ext, offsets, depth):
     iy, wy = node_weights(pos[1], h, offsets[1], ny)
     iz, wz = node_weights(pos[2], h, offsets[2])
     iz = iz + depth
-    if iz.min() < 0 or iz.max() >= field_ext.shape[0]:
+    if iz.size and (iz.min() < 0 or iz.max() >= field_ext.shape[0]):
         raise ValueError("interpolation stencil leaves the ghost-extended grid")
     out = np.zeros(pos.shape[1])
     for c in range(5):

@@ -1,0 +1,461 @@
+// Energy U and electro-osmotic flux Q of the electrostatic pass (Sec. II.B.1, Sec. II.D
+// stages 1-2) and their vector-Jacobian product, a hand-written adjoint:
+//
+//   rho = S q + b,  phi = A^+ rho,  E_i = J^es(-grad_h phi_ext)(x_i),
+//   U = (1/2) dV <rho, phi>,   Q = sum_i w(z_i) q_i (E_x,i + E_ext,x),
+//
+// A = -eps lap_h with homogeneous ghosts (symmetric), b the wall terms, phi_ext the
+// ghost-extended potential.  w(z) is the channel-mean x velocity per unit x force at
+// height z from the kappa = 0 no-slip Stokes mode: with -eta D_zz g = 1 / nz and the
+// no-slip ghosts, g_k = (z_k (Lz - z_k) + h^2 / 4) / (2 eta nz) exactly (z_k the cell
+// heights), and w(z) = sum_k s_k g_k wz_k(z) / (nx ny h^3) with the no-slip image
+// signs s.
+//
+// Reverse sweep for cotangents (gU, gQ):
+//   lambda_i = gQ w_i q_i on E_x,i  ->  transposed E_x gather (face differences, ghost
+//   folds; the ghost layers' dependence on the wall fields gives part of their
+//   gradient)  ->  mu = A^+ lambda_phi (one Poisson solve)  ->  rbar = gU dV phi + mu,
+//   the cotangent of rho  ->  per ion: dq = (J rbar)/dV + gQ w (E_x + E_ext,x),
+//   dx = q grad(J rbar)/dV + gQ w q grad E_x + gQ F_x w'(z) e_z  (J with the
+//   homogeneous folds of S);  wall fields: B^T rbar + ghost part;  dE_ext,x = gQ sum q w.
+#include "kernels.h"
+
+namespace discos {
+
+// 4-point Peskin weights (as peskin4) and their derivatives d w / d s.
+__device__ __forceinline__ void peskin4_d(double s, int& i0, double w[4], double dw[4]) {
+    const double fl = floor(s);
+    const double r = s - fl;
+    const double q = sqrt(1.0 + 4.0 * r - 4.0 * r * r);
+    const double dq = (2.0 - 4.0 * r) / q;
+    i0 = (int)fl - 1;
+    w[0] = (3.0 - 2.0 * r - q) * 0.125;
+    w[1] = (3.0 - 2.0 * r + q) * 0.125;
+    w[2] = (1.0 + 2.0 * r + q) * 0.125;
+    w[3] = (1.0 + 2.0 * r - q) * 0.125;
+    dw[0] = (-2.0 - dq) * 0.125;
+    dw[1] = (-2.0 + dq) * 0.125;
+    dw[2] = (2.0 + dq) * 0.125;
+    dw[3] = (2.0 - dq) * 0.125;
+}
+
+// On the 5-cell window c-2 .. c+2 (c = floor(u)): centre weights wc and d/du, and the
+// face-difference weights fd (E component along this axis: -(1/h) sum fd phi) and d/du.
+__device__ __forceinline__ int window_weights_d(double u, double wc5[5], double dc5[5],
+                                                double fd5[5], double df5[5]) {
+    int ic, iff;
+    double wc[4], dc[4], wf[4], df[4];
+    peskin4_d(u - 0.5, ic, wc, dc);
+    peskin4_d(u, iff, wf, df);
+    const int c = iff + 1;
+    const bool shift = (ic - (c - 2)) != 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double lo = (k < 4) ? wc[k] : 0.0, hi = (k > 0) ? wc[k - 1] : 0.0;
+        const double dlo = (k < 4) ? dc[k] : 0.0, dhi = (k > 0) ? dc[k - 1] : 0.0;
+        wc5[k] = shift ? hi : lo;
+        dc5[k] = shift ? dhi : dlo;
+    }
+    fd5[0] = -wf[0];
+    df5[0] = -df[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        fd5[k] = wf[k - 1] - wf[k];
+        df5[k] = df[k - 1] - df[k];
+    }
+    fd5[4] = wf[3];
+    df5[4] = df[3];
+    return c;
+}
+
+struct FluxDev {
+    double norm;       // 1 / (nx ny h^3)
+    double inv2etanz;  // 1 / (2 eta nz)
+};
+
+// w(z) and dw/dz.
+__device__ __forceinline__ void flux_weight(const GridDev& g, const FluxDev& f, double z, double& w,
+                                            double& dw) {
+    int i0;
+    double wz[4], dz[4];
+    peskin4_d(z * g.inv_h - 0.5, i0, wz, dz);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int k = i0 + c;
+        double s = 1.0;
+        if (k < 0) { k = -1 - k; s = -1.0; }
+        else if (k >= g.nz) { k = 2 * g.nz - 1 - k; s = -1.0; }
+        const double zk = (k + 0.5) * g.h;
+        const double gk = s * (zk * (g.Lz - zk) + 0.25 * g.h * g.h) * f.inv2etanz;
+        a += gk * wz[c];
+        b += gk * dz[c];
+    }
+    w = f.norm * a;
+    dw = f.norm * b * g.inv_h;
+}
+
+// ---- deterministic reductions (fixed grid, fixed order) ---------------------------
+#define RD_THREADS 256
+
+__device__ __forceinline__ void block_sum_store(double v, double* out) {
+    __shared__ double red[RD_THREADS];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = RD_THREADS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void __launch_bounds__(RD_THREADS)
+dot_partials_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                    double* __restrict__ part) {
+    double acc = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)RD_THREADS + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * RD_THREADS)
+        acc += a[k] * b[k];
+    block_sum_store(acc, part + blockIdx.x);
+}
+
+// sum_i w(z_i) v_i with v the sorted x forces (fx) or, with fx null, the charges.
+__global__ void __launch_bounds__(RD_THREADS)
+flux_partials_kernel(GridDev g, FluxDev f, const double4* __restrict__ sxyzq,
+                     const double* __restrict__ fx, int n, double* __restrict__ part) {
+    double acc = 0.0;
+    for (int i = blockIdx.x * RD_THREADS + threadIdx.x; i < n; i += gridDim.x * RD_THREADS) {
+        const double4 a4 = sxyzq[i];
+        if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
+        double w, dw;
+        flux_weight(g, f, a4.z, w, dw);
+        acc += w * (fx ? fx[i] : a4.w);
+    }
+    block_sum_store(acc, part + blockIdx.x);
+}
+
+// out[0] = scale (* mul[0] if given) * sum(part); with zero_tail also out[1] = out[2] = 0.
+__global__ void __launch_bounds__(RD_THREADS)
+finish_kernel(const double* __restrict__ part, int nparts, double scale, const double* __restrict__ mul,
+              int zero_tail, double* __restrict__ out) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += RD_THREADS) acc += part[k];
+    __shared__ double tot;
+    block_sum_store(acc, &tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = scale * (mul ? mul[0] : 1.0) * tot;
+        if (zero_tail) {
+            out[1] = 0.0;
+            out[2] = 0.0;
+        }
+    }
+}
+
+static int nparts_for(int64_t n) {
+    const int64_t b = (n + RD_THREADS - 1) / RD_THREADS;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, PART_MAX));
+}
+
+// ---- transposed E_x gather: lambda_i = gQ w_i q_i onto the cell grid --------------
+#define AS_T 16
+#define AS_THREADS 256
+#define AS_MAXR 256
+
+__global__ void __launch_bounds__(AS_THREADS)
+flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
+                   const int* __restrict__ bin_start, const double* __restrict__ gvec,
+                   double* __restrict__ lam, double* __restrict__ bcg) {
+    __shared__ double acc[AS_T * AS_T * AS_T];
+    __shared__ double glo[AS_T * AS_T], ghi[AS_T * AS_T];
+    __shared__ int rstart[AS_MAXR], rpre[AS_MAXR + 1], scan[AS_THREADS];
+    const int tx = min(AS_T, g.nx), ty = min(AS_T, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * AS_T;
+    const int tz = min(AS_T, g.nz - z0);
+    const bool has_lo = z0 == 0, has_hi = z0 + tz == g.nz;
+    for (int k = threadIdx.x; k < tx * ty * tz; k += blockDim.x) acc[k] = 0.0;
+    for (int k = threadIdx.x; k < tx * ty; k += blockDim.x) glo[k] = ghi[k] = 0.0;
+    const int nr = tile_ranges<AS_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
+    const int total = rpre[nr];
+    const double gQ = gvec[1];
+    const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = 0, hi = nr - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (rpre[mid] <= e) r = mid; else hi = mid - 1;
+        }
+        const int i = rstart[r] + (e - rpre[r]);
+        const double4 a4 = sxyzq[i];
+        if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
+        double w, dw;
+        flux_weight(g, f, a4.z, w, dw);
+        const double val = -gQ * w * a4.w * g.inv_h;
+        if (val == 0.0) continue;
+        double wcx[5], dcx[5], fdx[5], dfx[5], wcy[5], dcy[5], fdy[5], dfy[5], wcz[5], dcz[5], fdz[5], dfz[5];
+        const int cx = window_weights_d(a4.x * g.inv_h, wcx, dcx, fdx, dfx);
+        const int cy = window_weights_d(a4.y * g.inv_h, wcy, dcy, fdy, dfy);
+        const int cz = window_weights_d(a4.z * g.inv_h, wcz, dcz, fdz, dfz);
+#pragma unroll 1
+        for (int kz = 0; kz < 5; ++kz) {
+            if (wcz[kz] == 0.0) continue;
+            const int k = cz - 2 + kz;
+            int layer = k, m = -1, wall = -1;
+            double sg = 1.0;
+            if (k < 0) { m = -1 - k; layer = m; sg = s_lo; wall = 0; }
+            else if (k >= g.nz) { m = k - g.nz; layer = g.nz - 1 - m; sg = s_hi; wall = 1; }
+            const int lz = layer - z0;
+            const bool in_z = lz >= 0 && lz < tz;
+            // the ghost layer's dependence on the wall field: 2 (Dirichlet) or
+            // (2m+1) h / eps (Neumann) per unit of the column's value
+            const bool ghost = (wall == 0 && has_lo) || (wall == 1 && has_hi);
+            double gcoef = 0.0;
+            if (ghost)
+                gcoef = wl.type[wall] == DISCOS_BC_DIRICHLET ? 2.0 : (2 * m + 1) * g.h / wl.eps;
+            if (!in_z && !ghost) continue;
+            double* gl = wall == 0 ? glo : ghi;
+            const double vz = val * wcz[kz];
+#pragma unroll
+            for (int ky = 0; ky < 5; ++ky) {
+                const int ly = (cy - 2 + ky - y0) & (g.ny - 1);
+                if (ly >= ty || wcy[ky] == 0.0) continue;
+                const double vyz = vz * wcy[ky];
+#pragma unroll
+                for (int kx = 0; kx < 5; ++kx) {
+                    const int lx = (cx - 2 + kx - x0) & (g.nx - 1);
+                    if (lx >= tx) continue;
+                    const double v = vyz * fdx[kx];
+                    if (in_z) atomicAdd(&acc[(lz * ty + ly) * tx + lx], sg * v);
+                    if (ghost) atomicAdd(&gl[ly * tx + lx], gcoef * v);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < tx * ty * tz; k += blockDim.x) {
+        const int lx = k % tx, ly = (k / tx) % ty, lz = k / (tx * ty);
+        lam[((size_t)(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = acc[k];
+    }
+    for (int k = threadIdx.x; k < tx * ty; k += blockDim.x) {
+        const size_t col = (size_t)(y0 + k / tx) * g.nx + (x0 + k % tx);
+        if (has_lo) bcg[col] = glo[k];
+        if (has_hi) bcg[(size_t)g.nx * g.ny + col] = ghi[k];
+    }
+}
+
+// ---- per-ion gradients: gather of rbar (homogeneous folds) and phi (wall ghosts) ----
+#define GT_TX 16
+#define GT_TY 16
+#define GT_TZ 4
+#define GT_H 5
+#define GT_THREADS 256
+#define GT_MAXR 64
+
+__global__ void __launch_bounds__(GT_THREADS)
+flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
+                        const int* __restrict__ bin_start, const int* __restrict__ perm,
+                        const double* __restrict__ phi, const double* __restrict__ mu,
+                        const double* __restrict__ gvec, double ex0, double* __restrict__ dpos,
+                        double* __restrict__ dq, int64_t stride, int* __restrict__ flags) {
+    constexpr int LX = GT_TX + GT_H, LY = GT_TY + GT_H, LZ = GT_TZ + GT_H;
+    __shared__ double trb[LZ * LY * LX];
+    __shared__ double tph[LZ * LY * LX];
+    __shared__ int rstart[GT_MAXR], rpre[GT_MAXR + 1], scan[GT_THREADS];
+    const int tx = min(GT_TX, g.nx), ty = min(GT_TY, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * GT_TZ;
+    const int tz = min(GT_TZ, g.nz - z0);
+    const int lxn = tx + GT_H, lyn = ty + GT_H, lzn = tz + GT_H;
+    const double dV = g.h * g.h * g.h;
+    const double gU = gvec[0], gQ = gvec[1];
+    const double udv = gU * dV;
+    const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    for (int e = threadIdx.x; e < LX * LY * lzn; e += blockDim.x) {
+        const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+        if (lx >= lxn || ly >= lyn) continue;
+        const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+        const int k = z0 - 2 + lz;
+        int src = k;
+        double sg = 1.0;
+        if (k < 0) { src = -1 - k; sg = s_lo; }
+        else if (k >= g.nz) { src = 2 * g.nz - 1 - k; sg = s_hi; }
+        src = min(max(src, 0), g.nz - 1);
+        const size_t o = ((size_t)src * g.ny + j) * g.nx + i;
+        trb[e] = sg * (udv * phi[o] + mu[o]);
+        tph[e] = phi_at(phi, g, wl, i, j, k);
+    }
+    const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
+    const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
+    const int nrows = (bz1 - bz0 + 1) * nbyt;
+    {
+        int len = 0;
+        const int t = threadIdx.x;
+        if (t < nrows) {
+            const int bz = bz0 + t / nbyt, by = y0 / DISCOS_BIN + t % nbyt;
+            const int row = (bz * g.nby + by) * g.nbx + x0 / DISCOS_BIN;
+            const int st = bin_start[row];
+            rstart[t] = st;
+            len = bin_start[row + nbxt] - st;
+        }
+        scan[t] = len;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int a = (t >= off) ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += a;
+            __syncthreads();
+        }
+        if (t < nrows) rpre[t] = scan[t] - len;
+        if (t == nrows - 1) rpre[nrows] = scan[t];
+    }
+    __syncthreads();
+    const int total = rpre[nrows];
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int r = 0, hi = nrows - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (rpre[mid] <= e) r = mid; else hi = mid - 1;
+        }
+        const int i = rstart[r] + (e - rpre[r]);
+        const int o = perm[i];
+        const double4 a4 = sxyzq[i];
+        bool ok = pos_ok(g, a4.x, a4.y, a4.z);
+        double wcx[5], dcx[5], fdx[5], dfx[5], wcy[5], dcy[5], fdy[5], dfy[5], wcz[5], dcz[5], fdz[5], dfz[5];
+        int lx0 = 0, ly0 = 0, lz0 = 0;
+        if (ok) {
+            const int cx = window_weights_d(a4.x * g.inv_h, wcx, dcx, fdx, dfx);
+            const int cy = window_weights_d(a4.y * g.inv_h, wcy, dcy, fdy, dfy);
+            const int cz = window_weights_d(a4.z * g.inv_h, wcz, dcz, fdz, dfz);
+            lx0 = (cx - x0) & (g.nx - 1);
+            ly0 = (cy - y0) & (g.ny - 1);
+            lz0 = cz - z0;
+            ok = lx0 <= tx && ly0 <= ty && lz0 >= 0 && lz0 <= tz;
+        }
+        if (!ok) {
+            set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                              : DISCOS_FLAG_NONFINITE);
+            if (dq) dq[o] = 0.0;
+            if (dpos) dpos[o] = dpos[o + stride] = dpos[o + 2 * stride] = 0.0;
+            continue;
+        }
+        // R = J rbar and its gradient (x, y, z); P = sum fd_x wc_y wc_z phi and gradient
+        double R = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, P = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+#pragma unroll 1
+        for (int kz = 0; kz < 5; ++kz) {
+            double c00 = 0.0, c10 = 0.0, c01 = 0.0, e00 = 0.0, e10 = 0.0, e01 = 0.0;
+#pragma unroll
+            for (int ky = 0; ky < 5; ++ky) {
+                const int base = ((lz0 + kz) * LY + ly0 + ky) * LX + lx0;
+                double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+                for (int kx = 0; kx < 5; ++kx) {
+                    const double rv = trb[base + kx], pv = tph[base + kx];
+                    a0 += wcx[kx] * rv;
+                    a1 += dcx[kx] * rv;
+                    b0 += fdx[kx] * pv;
+                    b1 += dfx[kx] * pv;
+                }
+                c00 += wcy[ky] * a0;
+                c10 += wcy[ky] * a1;
+                c01 += dcy[ky] * a0;
+                e00 += wcy[ky] * b0;
+                e10 += wcy[ky] * b1;
+                e01 += dcy[ky] * b0;
+            }
+            R += wcz[kz] * c00;
+            Rx += wcz[kz] * c10;
+            Ry += wcz[kz] * c01;
+            Rz += dcz[kz] * c00;
+            P += wcz[kz] * e00;
+            Px += wcz[kz] * e10;
+            Py += wcz[kz] * e01;
+            Pz += dcz[kz] * e00;
+        }
+        const double ih = g.inv_h;
+        const double Ex = -ih * P;
+        double w, dw;
+        flux_weight(g, f, a4.z, w, dw);
+        const double qi = a4.w;
+        const double Fx = qi * (Ex + ex0);
+        const double gwq = gQ * w * qi;
+        if (dq) dq[o] = R / dV + gQ * w * (Ex + ex0);
+        if (dpos) {
+            const double s = qi * ih / dV;
+            const double e2 = -ih * ih;
+            dpos[o] = s * Rx + gwq * e2 * Px;
+            dpos[o + stride] = s * Ry + gwq * e2 * Py;
+            dpos[o + 2 * stride] = s * Rz + gwq * e2 * Pz + gQ * dw * Fx;
+        }
+    }
+}
+
+// Wall-field gradients: B^T rbar on the end layers plus the ghost-layer part.
+__global__ void flux_bc_kernel(GridDev g, WallDev wl, const double* __restrict__ phi,
+                               const double* __restrict__ mu, const double* __restrict__ gvec,
+                               const double* __restrict__ bcg, double* __restrict__ dlo,
+                               double* __restrict__ dhi) {
+    const int64_t ncol = (int64_t)g.nx * g.ny;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ncol) return;
+    const double udv = gvec[0] * g.h * g.h * g.h;
+    for (int wall = 0; wall < 2; ++wall) {
+        double* d = wall == 0 ? dlo : dhi;
+        if (!d) continue;
+        const size_t o = (size_t)(wall == 0 ? 0 : g.nz - 1) * ncol + t;
+        const double coef = wl.type[wall] == DISCOS_BC_DIRICHLET ? 2.0 * wl.eps * g.inv_h * g.inv_h : g.inv_h;
+        d[t] = coef * (udv * phi[o] + mu[o]) + bcg[wall * ncol + t];
+    }
+}
+
+static FluxDev flux_of(const Ctx* c, const discos_params* p) {
+    FluxDev f;
+    const double h = c->grid.h;
+    f.norm = 1.0 / ((double)c->grid.nx * c->grid.ny * h * h * h);
+    f.inv2etanz = 1.0 / (2.0 * p->eta * c->grid.nz);
+    return f;
+}
+
+int energy_flux(Ctx* c, int n, const discos_params* p, const double* phi, double* out, hipStream_t s) {
+    // U = (1/2) dV <rho, phi> (c->rho holds S q + b), Q = sum w(z) F_x (c->fp sorted)
+    const double dV = c->grid.h * c->grid.h * c->grid.h;
+    const int pu = nparts_for(c->ncell);
+    dot_partials_kernel<<<pu, RD_THREADS, 0, s>>>(c->rho, phi, c->ncell, c->part);
+    finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part, pu, 0.5 * dV, nullptr, 0, out);
+    const int pq = nparts_for(n);
+    flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(c->gd, flux_of(c, p), c->sxyzq, c->fp, n,
+                                                   c->part + PART_MAX);
+    finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part + PART_MAX, pq, 1.0, nullptr, 0, out + 1);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* phi, const double* gvec,
+                         double* dpos, double* dq, double* dlo, double* dhi, double* de,
+                         hipStream_t s) {
+    const GridDev& g = c->gd;
+    const FluxDev f = flux_of(c, p);
+    const WallDev wl = wall_of(p);
+    // lambda_phi -> c->rho, wall ghost part -> c->bcg
+    dim3 ga(g.nx / std::min(AS_T, g.nx), g.ny / std::min(AS_T, g.ny), (g.nz + AS_T - 1) / AS_T);
+    flux_lambda_kernel<<<ga, AS_THREADS, 0, s>>>(g, wl, f, c->sxyzq, c->bin_start, gvec, c->rho, c->bcg);
+    // mu = A^+ lambda_phi -> c->phi
+    int rc = solve_poisson(c, c->rho, p, c->phi, s, -1, 1);
+    if (rc) return rc;
+    if (n > 0 && (dpos || dq)) {
+        dim3 gg(g.nx / std::min(GT_TX, g.nx), g.ny / std::min(GT_TY, g.ny), (g.nz + GT_TZ - 1) / GT_TZ);
+        flux_energy_grad_kernel<<<gg, GT_THREADS, 0, s>>>(g, wl, f, c->sxyzq, c->bin_start, c->perm, phi,
+                                                         c->phi, gvec, p->e_ext[0], dpos, dq, n, c->flags);
+    }
+    if (dlo || dhi) {
+        const int64_t ncol = (int64_t)g.nx * g.ny;
+        flux_bc_kernel<<<(int)((ncol + 255) / 256), 256, 0, s>>>(g, wl, phi, c->phi, gvec, c->bcg, dlo, dhi);
+    }
+    if (de) {
+        const int pq = nparts_for(n);
+        flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(g, f, c->sxyzq, nullptr, n, c->part + PART_MAX);
+        finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part + PART_MAX, pq, 1.0, gvec + 1, 1, de);
+    }
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+}  // namespace discos

@@ -140,6 +140,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     bytes += carve_bytes(g.nx / 2, sizeof(double2));
     bytes += carve_bytes(g.ny / 2, sizeof(double2));
     bytes += carve_bytes(64, sizeof(int));
+    bytes += carve_bytes(2 * PART_MAX, sizeof(double));                 // reduction partials
+    bytes += carve_bytes(2 * (size_t)g.nx * g.ny, sizeof(double));     // wall adjoints
     if (hipMalloc(&c->pool, bytes) != hipSuccess) {
         delete c;
         return DISCOS_E_HIP;
@@ -165,6 +167,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->tw_x = carve<double2>(cur, g.nx / 2);
     c->tw_y = carve<double2>(cur, g.ny / 2);
     c->flags = carve<int>(cur, 64);
+    c->part = carve<double>(cur, 2 * PART_MAX);
+    c->bcg = carve<double>(cur, 2 * (size_t)g.nx * g.ny);
     // twiddles exp(-2 pi i k / N)
     std::vector<double2> tw(std::max(g.nx, g.ny) / 2);
     for (int pass = 0; pass < 2; ++pass) {
@@ -402,6 +406,44 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     discos::stage_mark(c, 13, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
+}
+
+int discos_energy_flux(discos_ctx* c, int64_t n, const double* pos, const double* q,
+                       const discos_params* p, double* phi, double* out, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (!phi || !out || (n > 0 && (!pos || !q))) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
+    const int ni = (int)n;
+    rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
+    if (!rc) rc = discos::spread_charge_sorted(c, p, 1, c->rho, s);
+    if (!rc) rc = discos::solve_poisson(c, c->rho, p, phi, s);
+    if (!rc && ni > 0)
+        rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, phi, p, c->fp, c->n_max, 0, s);
+    if (!rc) rc = discos::energy_flux(c, ni, p, phi, out, s);
+    return rc ? fail(c, rc, "energy/flux launch failed") : DISCOS_OK;
+}
+
+int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, const double* q,
+                                const discos_params* p, const double* phi, const double* g,
+                                double* dpos, double* dq, double* dbc_lo, double* dbc_hi,
+                                double* de, void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (!phi || !g || (n > 0 && (!pos || !q))) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
+    const int ni = (int)n;
+    rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
+    if (!rc) rc = discos::energy_flux_backward(c, ni, p, phi, g, dpos, dq, dbc_lo, dbc_hi, de, s);
+    return rc ? fail(c, rc, "energy/flux backward launch failed") : DISCOS_OK;
 }
 
 int discos_profile(discos_ctx* c, int enable) {

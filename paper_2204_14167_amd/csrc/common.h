@@ -160,4 +160,69 @@ __device__ __forceinline__ double reflect_walls(double z, double Lz) {
     return t <= Lz ? t : 2.0 * Lz - t;
 }
 
+// phi at cell (i, j, k), i and j periodic, any k: ghost layer -1-m is 2 phi_b - phi_m
+// (Dirichlet) or phi_m + (2m+1) h sigma / eps (Neumann); mirror rule at the top.
+__device__ __forceinline__ double phi_at(const double* __restrict__ phi, const GridDev& g,
+                                         const WallDev& w, int i, int j, int k) {
+    if (k >= 0 && k < g.nz) return phi[((size_t)k * g.ny + j) * g.nx + i];
+    const int wall = k < 0 ? 0 : 1;
+    const int m = k < 0 ? -1 - k : k - g.nz;
+    const int src = min(max(k < 0 ? m : g.nz - 1 - m, 0), g.nz - 1);
+    const double base = phi[((size_t)src * g.ny + j) * g.nx + i];
+    const double v = w.value[wall] ? w.value[wall][(size_t)j * g.nx + i] : 0.0;
+    if (w.type[wall] == DISCOS_BC_DIRICHLET) return 2.0 * v - base;
+    return base + (2 * m + 1) * g.h * v / w.eps;
+}
+
+// Cell-list rows of the ions that can reach the nodes of the tile [x0, x0+tx) x
+// [y0, y0+ty) x [z0, z0+tz) with a window of two cells on each side (cells x0-2 ..
+// x0+tx+1, periodic in x and y, clipped at the walls in z).  Thread t < MAXR owns one
+// candidate row (rstart[t], length from the prefix sums rpre); returns the row count.
+template <int MAXR>
+__device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
+                             int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan) {
+    int sa[2], sb[2], nseg;
+    {
+        const int lo = floordiv(x0 - 2, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
+        if (hi - lo + 1 >= g.nbx) {
+            nseg = 1; sa[0] = 0; sb[0] = g.nbx - 1;
+        } else {
+            const int a = wrapi(lo, g.nbx), b = wrapi(hi, g.nbx);
+            if (a <= b) { nseg = 1; sa[0] = a; sb[0] = b; }
+            else { nseg = 2; sa[0] = a; sb[0] = g.nbx - 1; sa[1] = 0; sb[1] = b; }
+        }
+    }
+    int ylo = floordiv(y0 - 2, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
+    if (yhi - ylo + 1 >= g.nby) { ylo = 0; yhi = g.nby - 1; }
+    const int czlo = max(z0 - 2, 0), czhi = min(z0 + tz + 1, g.nz - 1);
+    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
+    const int nyb = yhi - ylo + 1;
+    const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
+    const int t = threadIdx.x;
+    int len = 0;
+    if (t < ncand && t < MAXR) {
+        const int sgi = t % nseg;
+        const int yy = ylo + (t / nseg) % nyb;
+        const int bz = bzlo + t / (nseg * nyb);
+        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
+        const int st = bin_start[row + sa[sgi]];
+        rstart[t] = st;
+        len = bin_start[row + sb[sgi] + 1] - st;
+    }
+    scan[t] = len;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int a = (t >= off) ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += a;
+        __syncthreads();
+    }
+    const int nr = max(min(ncand, MAXR), 1);
+    if (t < nr) rpre[t] = scan[t] - len;
+    if (t == nr - 1) rpre[nr] = (ncand > 0) ? scan[t] : 0;
+    if (ncand == 0 && t == 0) { rstart[0] = 0; rpre[0] = 0; rpre[1] = 0; }
+    __syncthreads();
+    return nr;
+}
+
 }  // namespace discos

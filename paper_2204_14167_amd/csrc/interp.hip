@@ -26,20 +26,6 @@ namespace discos {
 #define IT_THREADS 256
 #define IT_MAXR 64
 
-// phi at cell (i, j, k), i and j periodic, any k: ghost layer -1-m is 2 phi_b - phi_m
-// (Dirichlet) or phi_m + (2m+1) h sigma / eps (Neumann); mirror rule at the top.
-__device__ __forceinline__ double phi_at(const double* __restrict__ phi, const GridDev& g,
-                                         const WallDev& w, int i, int j, int k) {
-    if (k >= 0 && k < g.nz) return phi[((size_t)k * g.ny + j) * g.nx + i];
-    const int wall = k < 0 ? 0 : 1;
-    const int m = k < 0 ? -1 - k : k - g.nz;
-    const int src = min(max(k < 0 ? m : g.nz - 1 - m, 0), g.nz - 1);
-    const double base = phi[((size_t)src * g.ny + j) * g.nx + i];
-    const double v = w.value[wall] ? w.value[wall][(size_t)j * g.nx + i] : 0.0;
-    if (w.type[wall] == DISCOS_BC_DIRICHLET) return 2.0 * v - base;
-    return base + (2 * m + 1) * g.h * v / w.eps;
-}
-
 // Centre weights and face-difference weights on the 5-cell window c-2 .. c+2 of the
 // coordinate u (in cells).
 __device__ __forceinline__ int window_weights(double u, double wc5[5], double dw5[5]) {

@@ -41,6 +41,8 @@ struct Ctx {
     double* hfor;     // face force scratch (3 face arrays)
     double* hvi;      // [3][n_max] interpolated ion velocities
     double4* hmid;    // [n_max] midpoint positions (x, y, z, q) in cell-list order
+    double* part;     // [2][PART_MAX] partial sums of the deterministic reductions
+    double* bcg;      // [2][ny][nx] wall-field adjoints gathered from the ghost layers
     int* flags;
     void* pool;
     void* hpool;
@@ -55,6 +57,7 @@ struct Ctx {
 };
 
 #define PROF_MAX 512
+#define PART_MAX 1024
 
 // Record the event that closes stage k of the current profiled step.
 inline void stage_mark(Ctx* c, int k, hipStream_t s) {
@@ -74,9 +77,10 @@ void fill_f64(double* a, int64_t n, double v, hipStream_t s);
 // wall terms of the discrete Poisson problem.
 int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out, hipStream_t s);
 
-// Poisson solve in place capable (rhs may equal phi).
+// Poisson solve in place capable (rhs may equal phi).  project != 0: the pseudo-inverse
+// for any rhs in the all-Neumann case (the adjoint solve), without the neutrality flag.
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
-                  int mark_base = -1);
+                  int mark_base = -1, int project = 0);
 
 // E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi
 // (DISCOS_INTERP_PHI) for the ions of the cell list; out[perm[i]] if scatter, else out[i].
@@ -114,5 +118,13 @@ int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s
 // cell-list order.
 int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
                   double* pos, double* q, int* id, int* sp, hipStream_t s);
+
+// U = (1/2) dV <c->rho, phi> and Q = sum w(z) F_x over the sorted forces c->fp into
+// out[0], out[1] (device).
+int energy_flux(Ctx* c, int n, const discos_params* p, const double* phi, double* out, hipStream_t s);
+// Reverse sweep of energy_flux over the current cell list (outputs nullable).
+int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* phi, const double* gvec,
+                         double* dpos, double* dq, double* dlo, double* dhi, double* de,
+                         hipStream_t s);
 
 }  // namespace discos

@@ -161,8 +161,9 @@ __global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ c
     double2* col = spec + t;
     double* cpc = cp + t;
     if (singular && m == 0 && j == 0) {
-        // kappa = 0 with both walls Neumann: compatibility (neutrality), mean removal,
-        // phi_0 pinned to 0, rows 1 .. nz-1 solved, then shifted to mean(phi) = 0.
+        // kappa = 0 with both walls Neumann: compatibility (neutrality), mean removal
+        // (the projection onto the range), phi_0 pinned to 0, rows 1 .. nz-1 solved,
+        // then shifted to mean(phi) = 0: the pseudo-inverse.
         double2 sum = make_double2(0.0, 0.0);
         double asum = 0.0;
         for (int k = 0; k < nz; ++k) {
@@ -171,7 +172,7 @@ __global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ c
             sum.y += r.y;
             asum += sqrt(r.x * r.x + r.y * r.y);
         }
-        if (sqrt(sum.x * sum.x + sum.y * sum.y) > 1e-10 * fmax(asum, 1e-300))
+        if (singular == 1 && sqrt(sum.x * sum.x + sum.y * sum.y) > 1e-10 * fmax(asum, 1e-300))
             set_flag(flags, DISCOS_FLAG_NOT_NEUTRAL);
         const double2 mean = make_double2(sum.x / nz, sum.y / nz);
         // forward sweep over unknowns 1 .. nz-1 (diag 2, last row 1)
@@ -272,7 +273,7 @@ int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
 }
 
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
-                  int mark_base) {
+                  int mark_base, int project) {
     const GridDev& g = c->gd;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;
@@ -290,7 +291,10 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     const double scale = (c->grid.h * c->grid.h / p->eps) / ((double)nx * ny);
     const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    const int singular = (p->bc_type[0] == DISCOS_BC_NEUMANN && p->bc_type[1] == DISCOS_BC_NEUMANN);
+    // 1: all-Neumann, check neutrality; 2: all-Neumann, pseudo-inverse of any rhs
+    const int singular = (p->bc_type[0] == DISCOS_BC_NEUMANN && p->bc_type[1] == DISCOS_BC_NEUMANN)
+                             ? (project ? 2 : 1)
+                             : 0;
     const int nmode = nxh * ny;
     zsolve_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->spec, c->cprime, nx, ny, nz, scale, s_lo, s_hi,
                                                   singular, c->flags);

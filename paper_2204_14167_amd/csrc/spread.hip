@@ -16,72 +16,6 @@ namespace discos {
 #define SP_THREADS 256
 #define SP_MAXR 256
 
-// Row ranges of the cell list covering cells [x0-2, x0+tx+1] x [y0-2, y0+ty+1] x
-// [z0-2, z0+tz+1] (clipped to the channel in z, periodic in x and y without
-// duplicates).  Built by the whole workgroup: thread t owns candidate range t
-// (at most 11 z-bins x 11 y-bins x 2 x-segments = 242 < SP_MAXR for 16^3 tiles
-// and two-cell bins), then an exclusive scan of the range lengths gives rpre.
-// Returns the number of ranges (empty ones included).
-__device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
-                           int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan) {
-    int sa[2], sb[2], nseg;
-    {
-        const int lo = floordiv(x0 - 2, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
-        if (hi - lo + 1 >= g.nbx) {
-            nseg = 1;
-            sa[0] = 0;
-            sb[0] = g.nbx - 1;
-        } else {
-            const int a = wrapi(lo, g.nbx), b = wrapi(hi, g.nbx);
-            if (a <= b) {
-                nseg = 1;
-                sa[0] = a;
-                sb[0] = b;
-            } else {
-                nseg = 2;
-                sa[0] = a;
-                sb[0] = g.nbx - 1;
-                sa[1] = 0;
-                sb[1] = b;
-            }
-        }
-    }
-    int ylo = floordiv(y0 - 2, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
-    if (yhi - ylo + 1 >= g.nby) {
-        ylo = 0;
-        yhi = g.nby - 1;
-    }
-    const int czlo = max(z0 - 2, 0), czhi = min(z0 + tz + 1, g.nz - 1);
-    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
-    const int nyb = yhi - ylo + 1;
-    const int ncand = (bzhi - bzlo + 1) * nyb * nseg;
-    const int t = threadIdx.x;
-    int len = 0;
-    if (t < ncand && t < SP_MAXR) {
-        const int sgi = t % nseg;
-        const int yy = ylo + (t / nseg) % nyb;
-        const int bz = bzlo + t / (nseg * nyb);
-        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
-        const int st = bin_start[row + sa[sgi]];
-        const int en = bin_start[row + sb[sgi] + 1];
-        rstart[t] = st;
-        len = en - st;
-    }
-    // inclusive Hillis-Steele scan over the workgroup
-    scan[t] = len;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const int a = (t >= off) ? scan[t - off] : 0;
-        __syncthreads();
-        scan[t] += a;
-        __syncthreads();
-    }
-    const int nr = min(ncand, SP_MAXR);
-    if (t < nr) rpre[t] = scan[t] - len;
-    if (t == nr - 1) rpre[nr] = scan[t];
-    __syncthreads();
-    return nr;
-}
 
 __device__ __forceinline__ int find_range(const int* rpre, int nr, int f) {
     int lo = 0, hi = nr - 1;
@@ -105,7 +39,7 @@ spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __
     const int tz = min(SP_TZ, g.nz - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
-    const int nr = tile_ranges(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
+    const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {

@@ -21,52 +21,6 @@ namespace discos {
 #define SH_THREADS 256
 #define SH_MAXR 256
 
-__device__ int tile_ranges_h(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
-                             int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan) {
-    int sa[2], sb[2], nseg;
-    {
-        const int lo = floordiv(x0 - 2, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
-        if (hi - lo + 1 >= g.nbx) {
-            nseg = 1; sa[0] = 0; sb[0] = g.nbx - 1;
-        } else {
-            const int a = wrapi(lo, g.nbx), b = wrapi(hi, g.nbx);
-            if (a <= b) { nseg = 1; sa[0] = a; sb[0] = b; }
-            else { nseg = 2; sa[0] = a; sb[0] = g.nbx - 1; sa[1] = 0; sb[1] = b; }
-        }
-    }
-    int ylo = floordiv(y0 - 2, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
-    if (yhi - ylo + 1 >= g.nby) { ylo = 0; yhi = g.nby - 1; }
-    const int czlo = max(z0 - 2, 0), czhi = min(z0 + tz + 1, g.nz - 1);
-    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
-    const int nyb = yhi - ylo + 1;
-    const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
-    const int t = threadIdx.x;
-    int len = 0;
-    if (t < ncand && t < SH_MAXR) {
-        const int sgi = t % nseg;
-        const int yy = ylo + (t / nseg) % nyb;
-        const int bz = bzlo + t / (nseg * nyb);
-        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
-        const int st = bin_start[row + sa[sgi]];
-        rstart[t] = st;
-        len = bin_start[row + sb[sgi] + 1] - st;
-    }
-    scan[t] = len;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const int a = (t >= off) ? scan[t - off] : 0;
-        __syncthreads();
-        scan[t] += a;
-        __syncthreads();
-    }
-    const int nr = max(min(ncand, SH_MAXR), 1);
-    if (t < nr) rpre[t] = scan[t] - len;
-    if (t == nr - 1) rpre[nr] = (ncand > 0) ? scan[t] : 0;
-    if (ncand == 0 && t == 0) { rstart[0] = 0; rpre[0] = 0; rpre[1] = 0; }
-    __syncthreads();
-    return nr;
-}
-
 // Deposit val * phi(x - node) / h^3 of one kernel centre (px, py, pz) into the tile.
 // COMP 0 / 1: x / y component at cell-centre heights, images fold k -> -1-k (sign -1).
 // COMP 2: z component on z-faces, images fold k -> -k (sign -1); wall faces hold 0.
@@ -131,7 +85,7 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
     // ions that can reach node levels [z0, z0+tz): cells [z0-2, z0+tz+1]
-    const int nr = tile_ranges_h(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
+    const int nr = tile_ranges<SH_MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
                                  rpre, scan);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;

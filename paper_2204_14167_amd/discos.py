@@ -95,12 +95,16 @@ def lib():
         L.discos_profile.argtypes = [vp, i32]
         L.discos_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int)]
+        L.discos_energy_flux.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp, vp]
+        L.discos_energy_flux_backward.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp,
+                                                  vp, vp, vp, vp, vp, vp]
         L.discos_last_error.argtypes = [vp]
         L.discos_last_error.restype = ctypes.c_char_p
         for name in ("discos_create", "discos_destroy", "discos_spread", "discos_solve_poisson",
                      "discos_solve_stokes",
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
-                     "discos_profile", "discos_profile_read"):
+                     "discos_profile", "discos_profile_read", "discos_energy_flux",
+                     "discos_energy_flux_backward"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,6 +142,12 @@ class Params:
             v = p["bc_values"][w] if p.get("bc_values") is not None else None
             if v is None:
                 s.bc_value[w] = None
+            elif isinstance(v, torch.Tensor) and v.device.type == "cuda":
+                # used in place (the autograd path): must be float64 [ny][nx], contiguous
+                if v.dtype != torch.float64 or tuple(v.shape) != (ny, nx) or not v.is_contiguous():
+                    raise ValueError("wall field tensors must be contiguous float64 [ny, nx]")
+                self._keep.append(v)
+                s.bc_value[w] = v.data_ptr()
             else:
                 t = _f64(np.broadcast_to(np.asarray(v, dtype=np.float64), (ny, nx)), device)
                 self._keep.append(t)
@@ -290,6 +300,35 @@ class Context:
         cnt = ctypes.c_int()
         self._rc(lib().discos_profile_read(self.handle, ms, ctypes.byref(cnt)))
         return {self.STAGES[k]: ms[k] for k in range(cnt.value)}
+
+    def energy_flux(self, pos, q, params, phi=None, out=None):
+        """(out, phi): out = [U, Q] (device), phi the checkpoint of the backward pass."""
+        n = pos.shape[1] if pos is not None else 0
+        nx, ny, nz, _ = self.grid
+        if phi is None:
+            phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device="cuda")
+        self._rc(lib().discos_energy_flux(self.handle, n, _ptr(pos), _ptr(q), ctypes.byref(params.struct),
+                                          _ptr(phi), _ptr(out), _stream()))
+        return out, phi
+
+    def energy_flux_backward(self, pos, q, params, phi, g, want=("pos", "q", "bc_lo", "bc_hi", "e_ext")):
+        """gU dU + gQ dQ (g = [gU, gQ] on the device) w.r.t. the requested inputs."""
+        n = pos.shape[1] if pos is not None else 0
+        nx, ny, nz, _ = self.grid
+        dev = dict(dtype=torch.float64, device="cuda")
+        res = {}
+        res["pos"] = torch.empty((3, n), **dev) if "pos" in want else None
+        res["q"] = torch.empty(n, **dev) if "q" in want else None
+        res["bc_lo"] = torch.empty((ny, nx), **dev) if "bc_lo" in want else None
+        res["bc_hi"] = torch.empty((ny, nx), **dev) if "bc_hi" in want else None
+        res["e_ext"] = torch.empty(3, **dev) if "e_ext" in want else None
+        self._rc(lib().discos_energy_flux_backward(
+            self.handle, n, _ptr(pos), _ptr(q), ctypes.byref(params.struct), _ptr(phi), _ptr(g),
+            _ptr(res["pos"]), _ptr(res["q"]), _ptr(res["bc_lo"]), _ptr(res["bc_hi"]), _ptr(res["e_ext"]),
+            _stream()))
+        return res
 
     def check(self):
         """Synchronise and raise on a sticky device-side error."""
