@@ -4,12 +4,16 @@ Workload: 1,048,576 ions (+1 / -1 halves, z uniform in [a, Lz - a]) on a
 256 x 256 x 128 channel, dielectric walls (Neumann limit, sigma = 0), applied field
 E_x = 0.1, P3M cutoff 4 h, 9-3 walls, wall-modified dry diffusion, Philox noise.
 A step is discos_step: cell list, S^es spread, Poisson (FFT x/y + z tridiagonal),
-J^es interpolation, P3M near-field + wall force + dry update.
+J^es interpolation, P3M near-field + wall force + dry update.  The same workload also
+times the energy / electro-osmotic-flux pass and its hand-written adjoint
+(discos_energy_flux, discos_energy_flux_backward) for the adjoint/forward ratio.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                [--adjoint-steps A] [--copy-calibration]
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,11 +31,48 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per launch of each stage (bytes that the stage must move, or
 # FP64 flops for the compute-bound near-field), for N ions, C cells and H = (nx/2+1) ny nz
-# half-spectrum cells.  See the design doc for the derivation.
-NEAR_FLOPS_PER_PAIR = 40.0
+# half-spectrum cells.
+NEAR_FLOPS_PER_PAIR = 40.0   # pair force of the P3M correction, wall images included
+LIST_FLOPS_PER_TEST = 9.0    # one candidate distance test: 3 sub, 3 mul, 2 add, 1 cmp
+
+# Stages that are one kernel launch each, with the kernel's name in rocprofv3 output.
+STAGE_KERNEL = {"spread": "spread_charge_kernel", "fft_x": "fft_x_r2c_kernel",
+                "z_solve": "zsolve_kernel", "ifft_x": "fft_x_c2r_kernel",
+                "interp": "interp_es_kernel", "near_list": "near_list_kernel",
+                "near_eval": "near_eval_kernel", "update": "dry_update_kernel"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_dry_step_256x256x128_n1048576.md")
 
 
-def stage_work(stage, N, C, H, pairs):
+def kernel_source_hash():
+    """sha256 over the HIP sources and headers: the traffic figures of a committed
+    counter profile apply only while this is unchanged."""
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2204_14167_amd", "csrc")
+    for name in sorted(os.listdir(base)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(base, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or None if absent or taken on other sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    block = text.split("```json", 1)
+    if len(block) < 2:
+        return None
+    data = json.loads(block[1].split("```", 1)[0])
+    if data.get("source_sha256") != kernel_source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def stage_work(stage, N, C, H, pairs, tests):
     if stage == "cell_list":
         return "hbm", 84.0 * N
     if stage == "spread":
@@ -44,45 +85,130 @@ def stage_work(stage, N, C, H, pairs):
         return "hbm", 16.0 * H + 8.0 * C
     if stage == "interp":
         return "hbm", 56.0 * N + 8.0 * C
-    if stage == "near_field":
+    if stage == "near_list":
+        return "alu", LIST_FLOPS_PER_TEST * tests
+    if stage == "near_eval":
         return "alu", NEAR_FLOPS_PER_PAIR * pairs
     if stage == "update":
         return "hbm", 104.0 * N
-    raise KeyError(stage)
+    return None, None  # multi-kernel or hydrodynamic stages (zero in a dry step)
 
 
-def cpu_baseline(w, p, pos, q, ids, species, n_sample=16):
+def cpu_baseline(w, p, pos, q, ids, species, n_sample=262144):
     """The oracle on the host: its grid part (spread + Poisson) on the whole workload,
-    its per-ion part (interpolation, brute-force near-field, update) on n_sample ions,
-    extrapolated to one full step."""
+    its per-ion part (interpolation, k-d tree near-field, wall force, update) on
+    n_sample ions (every ion still sources the fields), extrapolated linearly in the
+    ion count to one full step."""
     from oracle import dynamics, electrostatics as es
     grid = es.Grid(w.nx, w.ny, w.nz, w.h)
     t0 = time.perf_counter()
-    es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
+    pot = es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
     t_grid = time.perf_counter() - t0
     targets = np.sort(np.random.default_rng(0).choice(w.n, n_sample, replace=False))
     t0 = time.perf_counter()
-    dynamics.dry_step(grid, pos, q, species, ids, p, 0, targets=targets)
-    t_sample = time.perf_counter() - t0
-    t_ion = max(t_sample - t_grid, 0.0) / n_sample
-    t_step = t_grid + t_ion * w.n
+    dynamics.dry_step(grid, pos, q, species, ids, p, 0, targets=targets, near="pairs", pot=pot)
+    t_ions = time.perf_counter() - t0
+    t_step = t_grid + t_ions * w.n / n_sample
     return {"value": w.n / t_step, "unit": "ion-timesteps/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle grid part (spread + Poisson) on all {w.n} ions and "
-                       f"{w.nx}x{w.ny}x{w.nz} cells ({t_grid:.1f} s) plus its per-ion part "
-                       f"(interpolation, brute-force near-field, update) on {n_sample} ions "
-                       f"({t_sample - t_grid:.1f} s), extrapolated to one step of {w.n} ions; "
-                       "numpy, single thread")}
+                       f"{w.nx}x{w.ny}x{w.nz} cells ({t_grid:.1f} s), then the per-ion part "
+                       f"of the dry step for {n_sample} sampled ions (interpolation, k-d tree "
+                       f"near-field, wall force, update: {t_ions:.1f} s), extrapolated "
+                       f"linearly to one step of {w.n} ions; numpy / scipy, one thread")}
 
 
 def count_pairs(pos, L, psi, sample=4096):
-    """Mean number of neighbours within psi (sampled), for the near-field flop count."""
+    """Mean number of neighbours within psi (sampled), for the near-field flop count;
+    wall images within psi count as pairs too."""
     rng = np.random.default_rng(1)
     idx = rng.choice(pos.shape[1], sample, replace=False)
     from scipy.spatial import cKDTree
     pts = pos.T.copy()
     tree = cKDTree(pts, boxsize=[L[0], L[1], 1e9])
     cnt = tree.query_ball_point(pts[idx], psi, return_length=True) - 1
+    # images below z = 0 (z -> -z) and above z = Lz (z -> 2 Lz - z)
+    for zmap in (lambda z: -z, lambda z: 2.0 * L[2] - z):
+        img = pts[idx].copy()
+        img[:, 2] = zmap(img[:, 2])
+        cnt = cnt + tree.query_ball_point(img, psi, return_length=True)
     return float(np.mean(cnt))
+
+
+def count_tests(pos, grid, psi, sample=4096, binw=2):
+    """Mean number of candidate distance tests per ion of the neighbour-list build: the
+    ions of every bin row segment the search visits (bins of binw cells, rows trimmed to
+    the search sphere, wall-image passes for ions within psi of a wall)."""
+    nx, ny, nz, h = grid
+    Bh = binw * h
+    nbx, nby, nbz = nx // binw, ny // binw, (nz + binw - 1) // binw
+    b = np.minimum((pos / Bh).astype(np.int64), np.array([[nbx - 1], [nby - 1], [nbz - 1]]))
+    counts = np.zeros((nbz, nby, nbx), dtype=np.int64)
+    np.add.at(counts, (b[2], b[1], b[0]), 1)
+    R = int(np.ceil(psi / Bh))
+    rng = np.random.default_rng(2)
+    idx = rng.choice(pos.shape[1], sample, replace=False)
+    Lz = nz * h
+    total = 0
+    for i in idx:
+        xi, yi, zi = pos[:, i]
+        bx, by, bz = b[:, i]
+        for mode in range(3):
+            if mode == 0:
+                zl, zh = max(bz - R, 0), min(bz + R, nbz - 1)
+            elif mode == 1:
+                if not zi < psi:
+                    continue
+                zl, zh = 0, min(nbz - 1, int(np.floor(psi / h)) // binw)
+            else:
+                if not zi > Lz - psi:
+                    continue
+                zl, zh = max(0, int(np.floor((Lz - psi) / h)) // binw), nbz - 1
+            for cz in range(zl, zh + 1):
+                zb0, zb1 = cz * Bh, min((cz + 1) * Bh, Lz)
+                dzm = (max(0.0, zb0 - zi, zi - zb1) if mode == 0 else
+                       (zi + zb0 if mode == 1 else (2 * Lz - zb1) - zi))
+                remz = psi * psi - dzm * dzm
+                if remz <= 0:
+                    continue
+                for dyb in range(-R, R + 1):
+                    yb0 = (by + dyb) * Bh
+                    dym = max(0.0, yb0 - yi, yi - (yb0 + Bh))
+                    rem = remz - dym * dym
+                    if rem <= 0:
+                        continue
+                    wx = np.sqrt(rem)
+                    lo = max(bx - R, int(np.floor((xi - wx) / Bh)))
+                    hi = min(bx + R, int(np.floor((xi + wx) / Bh)))
+                    if lo > hi:
+                        continue
+                    cols = np.arange(lo, hi + 1) % nbx
+                    total += int(counts[cz, (by + dyb) % nby, cols].sum())
+    return total / sample
+
+
+def adjoint_timing(ctx, dp, dpos, dq, steps):
+    """Mean times of the energy / flux forward pass and of its backward pass (all
+    gradients: positions, charges, both wall fields, applied field) on the same
+    ions; ratio = (forward + backward) / forward."""
+    import torch
+    g = torch.ones(2, dtype=torch.float64, device="cuda")
+    out, phi = ctx.energy_flux(dpos, dq, dp)
+    ctx.energy_flux_backward(dpos, dq, dp, phi, g)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(steps):
+        ctx.energy_flux(dpos, dq, dp, phi=phi, out=out)
+    ev[1].record()
+    for _ in range(steps):
+        ctx.energy_flux_backward(dpos, dq, dp, phi, g)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ctx.check()
+    f = ev[0].elapsed_time(ev[1]) / steps
+    b = ev[1].elapsed_time(ev[2]) / steps
+    return {"forward_ms": f, "backward_ms": b, "ratio": (f + b) / f,
+            "gradients": "dU, dQ w.r.t. positions, charges, wall fields, E_ext"}
 
 
 def main():
@@ -91,6 +217,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,29 +263,47 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = w.n * args.steps / elapsed
 
+    adj = adjoint_timing(ctx, dp, dpos, dq, args.adjoint_steps) if args.adjoint_steps > 0 else None
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     N = w.n
     C = w.nx * w.ny * w.nz
     H = (w.nx // 2 + 1) * w.ny * w.nz
     final = dpos.cpu().numpy()
-    pairs = count_pairs(final, np.array([w.nx, w.ny, w.nz]) * w.h, p["psi"]) * N
-    dom = max(stages, key=stages.get)
-    bound, work = stage_work(dom, N, C, H, pairs)
-    t_dom = stages[dom] * 1e-3
+    L = np.array([w.nx, w.ny, w.nz]) * w.h
+    pairs = count_pairs(final, L, p["psi"]) * N
+    tests = count_tests(final, (w.nx, w.ny, w.nz, w.h), p["psi"]) * N
+    timed = {k: v for k, v in stages.items() if k in STAGE_KERNEL}
+    dom = max(timed, key=timed.get)
+    bound, work = stage_work(dom, N, C, H, pairs, tests)
+    t_dom = timed[dom] * 1e-3
+    traffic = committed_traffic(STAGE_KERNEL[dom])
     if bound == "hbm":
         achieved = work / t_dom / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes": work}
+        roof = {"bound": "hbm", "kernel": STAGE_KERNEL[dom], "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "algorithmic_bytes": work, "ms_per_launch": timed[dom]}
     else:
         achieved = work / t_dom / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                "algorithmic_flops": work, "pairs_per_ion": pairs / N}
+        roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom], "achieved": achieved,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": traffic, "algorithmic_flops": work, "ms_per_launch": timed[dom],
+                "pairs_per_ion": pairs / N, "tests_per_ion": tests / N}
     per_stage = {}
     for k, v in stages.items():
-        b, wk = stage_work(k, N, C, H, pairs)
-        per_stage[k] = {"ms": round(v, 5), "bound": b,
-                        ("GB/s" if b == "hbm" else "TFLOP/s"): round(wk / (v * 1e-3) / (1e9 if b == "hbm" else 1e12), 2)}
+        b, wk = stage_work(k, N, C, H, pairs, tests)
+        if v == 0.0 and b is None:
+            continue
+        e = {"ms": round(v, 5)}
+        if b is not None:
+            e["bound"] = b
+            e["GB/s" if b == "hbm" else "TFLOP/s"] = round(wk / (v * 1e-3) / (1e9 if b == "hbm" else 1e12), 2)
+        per_stage[k] = e
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -180,7 +327,8 @@ def main():
                    "psi": p["psi"], "mode": "dry step"},
         "roofline": roof,
         "stages": per_stage,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": None if adj is None else adj["ratio"],
+        "adjoint": adj,
         "cpu_baseline": cpu,
         "device_status": "; ".join(status) if status else "ok",
     }

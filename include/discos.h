@@ -260,11 +260,12 @@ int discos_energy_flux_backward(discos_ctx* ctx, int64_t n, const double* pos, c
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
  * the mean elapsed milliseconds per recorded step of each stage (host array of at
  * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
- * inverse y-FFT, inverse x-FFT, interpolation, near-field, S^hy, Stokes solve, the two
- * J^hy passes with the predictor, update; the hydrodynamic stages read 0 in dry
- * steps) and sets *count (0 when no step was recorded).
+ * inverse y-FFT, inverse x-FFT, interpolation, near-field neighbour lists, near-field
+ * forces, S^hy, Stokes solve, the two J^hy passes with the predictor, update; the
+ * hydrodynamic stages read 0 in dry steps) and sets *count (0 when no step was
+ * recorded).
  */
-#define DISCOS_NSTAGE 13
+#define DISCOS_NSTAGE 14
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
 

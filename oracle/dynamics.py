@@ -38,25 +38,25 @@ from . import stokes
 from .rng import TAG_DRY, TAG_RFD, ion_normals
 
 
-def total_force(grid, pos, q, species, p, targets=None, near="brute"):
+def total_force(grid, pos, q, species, p, targets=None, near="brute", pot=None):
     """F = F^P + sum F^LC + F^W (+ F^R) + q E_ext, eq totalforce; returns (F, parts).
 
     The grid part uses all ions; with `targets` the forces (interpolation,
     near-field, short-range) are evaluated for that subset only.  near="pairs"
-    takes the near-field sum from the k-d tree pair search (all ions, no
-    `targets`), for large systems.
+    takes the near-field sum from the k-d tree pair search, for large systems.
+    `pot` = (rho, phi) of es.potential for these ions, if already computed.
     """
     sel = slice(None) if targets is None else np.asarray(targets)
-    rho, phi = es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
+    if pot is None:
+        pot = es.potential(grid, pos, q, p["eps"], p["bc_types"], p["bc_values"])
+    rho, phi = pot
     ext = es.ghost_extend(grid, p["eps"], p["bc_types"], p["bc_values"], phi)
     ep = es.interp_field(grid, pos[:, sel], *es.face_fields(grid, ext))
     fp = q[sel][None, :] * (ep + np.asarray(p["e_ext"], dtype=np.float64)[:, None])
     F = fp.copy()
     if near == "pairs":
-        if targets is not None:
-            raise ValueError("near='pairs' evaluates every ion")
         fn = es.near_field_pairs(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
-                                 p["bc_types"])
+                                 p["bc_types"], targets=targets)
     else:
         fn = es.near_field(grid, pos, q, p["eps"], p["psi"], p["p3m_table"], p["p3m_dr"],
                            p["bc_types"], targets=targets)
@@ -129,10 +129,12 @@ def dry_update(grid, pos, F, species, ids, p, step):
     return new
 
 
-def dry_step(grid, pos, q, species, ids, p, step, targets=None):
+def dry_step(grid, pos, q, species, ids, p, step, targets=None, near="brute", pot=None):
     """One full dry step; returns (new positions, F, intermediates).  With
-    `targets` only those ions are advanced (all ions still source the fields)."""
-    F, parts = total_force(grid, pos, q, species, p, targets=targets)
+    `targets` only those ions are advanced (all ions still source the fields);
+    near="pairs" takes the near-field sum from the pair search; `pot` as in
+    total_force."""
+    F, parts = total_force(grid, pos, q, species, p, targets=targets, near=near, pot=pot)
     sel = slice(None) if targets is None else np.asarray(targets)
     new = dry_update(grid, pos[:, sel], F, species[sel], ids[sel], p, step)
     return new, F, parts

@@ -334,11 +334,66 @@ def near_field(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
     return out
 
 
-def near_field_pairs(grid, pos, q, eps, psi, table, dr, bc_types):
-    """The same correction as near_field for all ions, with the candidate pairs found
-    by a k-d tree (scipy cKDTree, periodic in x and y) instead of brute force; the
-    wall images are taken by brute force among the ions closer than psi to a wall."""
+def _pair_force(grid, eps, psi, table, dr, q_a, q_b, d):
+    """P3M pair correction on separations d [3, m] (minimum image applied here);
+    returns (mask of pairs with 0 < r < psi, force on a for those pairs)."""
+    L, h = grid.L, grid.h
+    d = d.copy()
+    d[0] -= L[0] * np.round(d[0] / L[0])
+    d[1] -= L[1] * np.round(d[1] / L[1])
+    r = np.sqrt((d * d).sum(axis=0))
+    ok = (r < psi) & (r > 0.0)
+    r, d = r[ok], d[:, ok]
+    g = table_lookup(table, dr, r / h)
+    mag = (q_a[ok] * q_b[ok]) / (4.0 * np.pi * eps) * (1.0 / r ** 2 - g / h ** 2) / r
+    return ok, mag * d
+
+
+def _near_field_targets(grid, pos, q, eps, psi, table, dr, bc_types, targets):
+    """near_field_pairs for the ions `targets` only (tree of all ions, ball queries)."""
     from scipy.spatial import cKDTree
+    L = grid.L
+    t = np.asarray(targets)
+    out = np.zeros((3, len(t)))
+    pts = pos.T.copy()
+    pts[:, 0] = np.mod(pts[:, 0], L[0])
+    pts[:, 1] = np.mod(pts[:, 1], L[1])
+    box = [L[0], L[1], 4.0 * L[2] + 8.0 * psi]
+    off = 2.0 * psi  # keep every point set inside the tree box in z
+    s = (image_sign(bc_types[0]), image_sign(bc_types[1]))
+    sets = [(pts, np.arange(pos.shape[1]), 1.0)]
+    for wall in (0, 1):
+        idx = np.nonzero(pos[2] < psi if wall == 0 else pos[2] > L[2] - psi)[0]
+        img = pts[idx].copy()
+        img[:, 2] = -img[:, 2] if wall == 0 else 2.0 * L[2] - img[:, 2]
+        sets.append((img, idx, s[wall]))
+    for src, ids, sign in sets:
+        if len(ids) == 0:
+            continue
+        shifted = src.copy()
+        shifted[:, 2] += off
+        tq = pts[t].copy()
+        tq[:, 2] += off
+        lists = cKDTree(shifted, boxsize=box).query_ball_point(tq, psi)
+        a = np.repeat(np.arange(len(t)), [len(x) for x in lists])
+        if len(a) == 0:
+            continue
+        b = np.concatenate([np.asarray(x, dtype=np.int64) for x in lists])
+        d = pos[:, t[a]] - np.stack([pos[0, ids[b]], pos[1, ids[b]], src[b, 2]])
+        ok, f = _pair_force(grid, eps, psi, table, dr, q[t[a]], sign * q[ids[b]], d)
+        for k in range(3):
+            np.add.at(out[k], a[ok], f[k])
+    return out
+
+
+def near_field_pairs(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
+    """The same correction as near_field, with the candidate pairs found by a k-d tree
+    (scipy cKDTree, periodic in x and y) instead of brute force; the wall images are
+    taken among the ions closer than psi to a wall.  With `targets` the forces of
+    that subset only (each found by a ball query against all ions and images)."""
+    from scipy.spatial import cKDTree
+    if targets is not None:
+        return _near_field_targets(grid, pos, q, eps, psi, table, dr, bc_types, targets)
     L = grid.L
     h = grid.h
     n = pos.shape[1]

@@ -378,8 +378,9 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc) rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, c->phi, p, c->fp, c->n_max, 0, s);
     discos::stage_mark(c, 8, s);
     // complete the forces in place: fp (grid + applied field) += near field + wall (+ LJ)
-    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s);
-    discos::stage_mark(c, 9, s);
+    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9);
+    else discos::stage_mark(c, 9, s);
+    discos::stage_mark(c, 10, s);
     const double* vwet = nullptr;
     if (wet && !rc && ni > 0) {
         discos::RfdDev rd{};
@@ -391,19 +392,19 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
             rd.step = step;
         }
         rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr);
-        discos::stage_mark(c, 10, s);
-        if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 11, s);
-        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s);
+        if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 12, s);
+        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s);
+        discos::stage_mark(c, 13, s);
         vwet = c->hvi;
     } else {
-        discos::stage_mark(c, 10, s);
         discos::stage_mark(c, 11, s);
         discos::stage_mark(c, 12, s);
+        discos::stage_mark(c, 13, s);
     }
     if (!rc) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
-    discos::stage_mark(c, 13, s);
+    discos::stage_mark(c, 14, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
 }

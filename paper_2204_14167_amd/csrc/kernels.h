@@ -88,9 +88,10 @@ int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_para
                      double* out, int64_t out_stride, int scatter, hipStream_t s);
 
 // Near-field + wall (+ LJ) forces over the cell list; out[perm] += F if scatter, else
-// out[sorted] += F.
+// out[sorted] += F.  mark >= 0: profiling stage mark between the list build and the
+// force pass.
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
-                      int scatter_to_caller, hipStream_t s);
+                      int scatter_to_caller, hipStream_t s, int mark = -1);
 
 // Random finite difference of the thermal forcing (scale = kT / delta, half = delta / 2;
 // scale 0: off); sid holds the ions' stable ids in cell-list order.

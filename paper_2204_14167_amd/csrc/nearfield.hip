@@ -359,12 +359,13 @@ near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
 }
 
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
-                      int scatter_to_caller, hipStream_t s) {
+                      int scatter_to_caller, hipStream_t s, int mark) {
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
     const int T = 256;
     near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->bin_start, c->nlist,
                                                    c->ncount);
+    if (mark >= 0) stage_mark(c, mark, s);
     near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
                                                    c->nlist, c->ncount, c->perm, out, out_stride,
                                                    scatter_to_caller, c->flags);

@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 result databases for the profiles/ folder.
+
+  python -m paper_2204_14167_amd.rocprof_summary kernels KT.db --command "..." > out.md
+      per-kernel dispatch count and mean / min / max duration (kernel-trace run)
+  python -m paper_2204_14167_amd.rocprof_summary traffic FETCH.db WRITE.db --command "..." > out.md
+      HBM bytes per dispatch of every kernel from a FETCH_SIZE run and a WRITE_SIZE run,
+      each scaled by what the same counter reads for the 1 GiB device copy those runs
+      include (bench.py --copy-calibration), with a fenced JSON block that bench.py reads
+
+Both read only the rocpd SQLite tables `kernels` and `counters_collection`.
+"""
+import argparse
+import json
+import re
+import sqlite3
+import sys
+
+COPY_BYTES = 1 << 30  # the calibration copy of bench.py --copy-calibration
+
+
+def _short(name):
+    return re.sub(r"\(.*", "", name).replace("discos::", "")
+
+
+def kernel_rows(db):
+    cur = sqlite3.connect(db).cursor()
+    q = ("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
+         "from kernels group by name order by sum(duration) desc")
+    return [(_short(r[0]),) + tuple(r[1:]) for r in cur.execute(q).fetchall()]
+
+
+def counter_means(db, counter):
+    """{kernel: (dispatches, mean KiB, max KiB)} for one counter."""
+    cur = sqlite3.connect(db).cursor()
+    q = ("select kernel_name, count(*), avg(value), max(value) from counters_collection "
+         "where counter_name = ? group by kernel_name")
+    return {_short(r[0]): (r[1], r[2], r[3]) for r in cur.execute(q, (counter,)).fetchall()}
+
+
+def copy_factor(means):
+    """Known bytes / counted bytes of the largest device-copy dispatch (the 1 GiB copy)."""
+    best = 0.0
+    for k, (_, _, mx) in means.items():
+        if "copyBuffer" in k:
+            best = max(best, mx)
+    if best <= 0.0:
+        raise SystemExit("no calibration copy in the counter run (bench.py --copy-calibration)")
+    return COPY_BYTES / (best * 1024.0)
+
+
+def cmd_kernels(args):
+    rows = kernel_rows(args.db)
+    tot = sum(r[5] for r in rows)
+    print(f"# Kernel trace: {args.title}\n")
+    print(f"Command:\n\n    {args.command}\n")
+    print("| kernel | dispatches | mean us | min us | max us | total ms | % |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for name, n, avg, mn, mx, s in rows:
+        print(f"| {name[:60]} | {n} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} | "
+              f"{s / 1e6:.3f} | {100 * s / tot:.1f} |")
+
+
+def cmd_traffic(args):
+    fetch = counter_means(args.fetch_db, "FETCH_SIZE")
+    write = counter_means(args.write_db, "WRITE_SIZE")
+    ff, fw = copy_factor(fetch), copy_factor(write)
+    kern = {}
+    for k in sorted(set(fetch) & set(write)):
+        if "rocclr" in k or "at::native" in k:
+            continue
+        fb = fetch[k][1] * 1024.0 * ff
+        wb = write[k][1] * 1024.0 * fw
+        kern[k] = {"dispatches": fetch[k][0], "fetch_kib_raw": round(fetch[k][1], 1),
+                   "write_kib_raw": round(write[k][1], 1), "hbm_bytes_per_launch": round(fb + wb)}
+    print(f"# HBM traffic per dispatch: {args.title}\n")
+    print("Commands (one counter per run, each with the 1 GiB calibration copy):\n")
+    for c in args.command:
+        print(f"    {c}")
+    print(f"\nCalibration: the 1 GiB device copy reads {COPY_BYTES / ff / 1024:.1f} KiB of "
+          f"FETCH_SIZE (factor {ff:.4f}) and {COPY_BYTES / fw / 1024:.1f} KiB of WRITE_SIZE "
+          f"(factor {fw:.4f}).  Traffic = FETCH_SIZE x {ff:.4f} + WRITE_SIZE x {fw:.4f}.\n")
+    print("| kernel | dispatches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | HBM MB / launch |")
+    print("|---|---:|---:|---:|---:|")
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"]):
+        print(f"| {k} | {v['dispatches']} | {v['fetch_kib_raw']} | {v['write_kib_raw']} | "
+              f"{v['hbm_bytes_per_launch'] / 1e6:.1f} |")
+    data = {"source_sha256": args.source_sha256, "fetch_factor": ff, "write_factor": fw,
+            "kernels": {k: {"hbm_bytes_per_launch": v["hbm_bytes_per_launch"]} for k, v in kern.items()}}
+    print("\n```json\n" + json.dumps(data, indent=1) + "\n```")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("kernels")
+    a.add_argument("db")
+    a.add_argument("--command", required=True)
+    a.add_argument("--title", default="")
+    a.set_defaults(fn=cmd_kernels)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_db")
+    b.add_argument("write_db")
+    b.add_argument("--command", action="append", required=True)
+    b.add_argument("--title", default="")
+    b.add_argument("--source-sha256", required=True)
+    b.set_defaults(fn=cmd_traffic)
+    args = ap.parse_args(argv)
+    args.fn(args)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -247,3 +247,6 @@ def test_kdtree_near_field_matches_brute_force(bc):
     a = es.near_field(grid, pos, q, EPS, 4.0, table, dr, bc)
     b = es.near_field_pairs(grid, pos, q, EPS, 4.0, table, dr, bc)
     assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+    t = np.array([0, 5, 150, 210, 299, 1000, 1999])
+    c = es.near_field_pairs(grid, pos, q, EPS, 4.0, table, dr, bc, targets=t)
+    assert np.abs(a[:, t] - c).max() < 1e-13 * np.abs(a).max()
