@@ -255,6 +255,54 @@ int discos_energy_flux_backward(discos_ctx* ctx, int64_t n, const double* pos, c
                                 double* de, void* stream);
 
 /*
+ * Batches of independent channels (a project addition; each channel is exactly the
+ * problem of discos_step in dry mode, with its own grid, ion count, noise key and wall
+ * values; Sec. II.D stages 1-2 and the dry update).  All channels share h and the
+ * physics of one discos_params (its bc_value and seed are ignored: each channel
+ * brings its own).  Every stage is one launch over all channels: tile stages walk a
+ * (channel, tile) task table in a persistent grid, per-ion stages look up each ion's
+ * channel, and the FFTs run per (nx, ny) size class.
+ */
+typedef struct discos_replica {
+    int32_t nx, ny, nz;         /* nx, ny powers of two in [8, 1024]; nz >= 4 */
+    int64_t n;                  /* ions of this channel */
+    double bc_value[2];         /* uniform wall values (phi_b or sigma) of the two walls */
+    uint64_t seed;              /* Philox key of this channel's noise */
+    const double* mob_coef;     /* device [nspecies][2][7] for this channel height, or NULL
+                                   for p->mob_coef */
+} discos_replica;
+
+typedef struct discos_batch discos_batch;
+
+/* Lays the channels out and allocates every buffer (nothing is allocated later).
+ * reps: host array of `count` channels.  The ions of channel r occupy entries
+ * [off_r, off_r + n_r) of the batch ion arrays, off_r = n_0 + ... + n_{r-1}. */
+int discos_batch_create(const discos_replica* reps, int32_t count, double h,
+                        const discos_params* p, discos_batch** out);
+int discos_batch_destroy(discos_batch* b);
+
+/* One dry step of every channel.  pos [3][N], q [N], id [N], species [N] (DEVICE,
+ * N = total ions) are permuted in place into cell order within each channel's range.
+ * flags & DISCOS_BATCH_GRAPH: run the step as a captured hipGraph (captured on the first
+ * call, and again whenever the arrays change); the step counter then lives on the
+ * device and advances with each replay. */
+#define DISCOS_BATCH_GRAPH 1u
+int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int32_t* species,
+                      uint64_t step, uint32_t flags, void* stream);
+
+/* Autotuner: times the spread tile (8^3 or 16^3) with its persistent block count, the
+ * interpolation tile (8x8x8 or 16x16x8) with its block count, and the workgroup size of
+ * the per-ion stages on the current ions, without advancing them, and keeps the fastest
+ * of each.  cfg (host [5], nullable) receives spread tile, spread blocks (0 = one per
+ * task), interpolation tile, interpolation blocks, per-ion workgroup size. */
+int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const int32_t* id,
+                      const int32_t* species, int32_t* cfg, void* stream);
+
+/* Sticky device flags of the batch (as discos_check) and the last host error. */
+int discos_batch_check(discos_batch* b);
+const char* discos_batch_last_error(discos_batch* b);
+
+/*
  * Stage timing of discos_step.  discos_profile(ctx, 1) clears the record and makes the
  * next (up to 512) steps record a hipEvent on their stream after each stage;
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes

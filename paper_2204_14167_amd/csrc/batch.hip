@@ -1,0 +1,486 @@
+// Batches of independent channels: layout, launch order, the captured hipGraph of one
+// batched step and the launch-parameter autotuner.  Each channel is exactly the dry
+// step of a single context (Sec. II.D stages 1-2, eq ions3); nothing couples channels.
+//
+// Layout: ions and bins follow the channels' order (channel r owns ion slots
+// [off_r, off_r + n_r) and a contiguous range of bins, so one batch-wide counting sort
+// keeps every channel's ions inside its own slots); cells, spectra and Thomas scratch
+// are grouped by (nx, ny) class so that each class's FFT rows and levels are single
+// ranges for one launch.
+#include <cmath>
+#include <map>
+#include <new>
+
+#include "kernels.h"
+
+using discos::Batch;
+
+struct discos_batch : public Batch {};
+
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int fail(discos_batch* b, int code, const char* msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+size_t carve_bytes(size_t n, size_t elem) { return (n * elem + 255) & ~(size_t)255; }
+
+template <class T>
+T* carve(char*& cur, size_t n) {
+    T* p = reinterpret_cast<T*>(cur);
+    cur += carve_bytes(n, sizeof(T));
+    return p;
+}
+
+// Tile counts of one channel for a tile of (tx, ty, tz) (tx, ty clipped to the grid).
+int tiles_of(const discos_replica& r, int tx, int ty, int tz) {
+    return (r.nx / std::min(tx, r.nx)) * (r.ny / std::min(ty, r.ny)) * ((r.nz + tz - 1) / tz);
+}
+
+void destroy(discos_batch* b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->own) hipStreamDestroy(b->own);
+    if (b->pool) hipFree(b->pool);
+    delete b;
+}
+
+int run_step(discos_batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s) {
+    int rc = discos::batch_cell_list(b, pos, q, id, sp, s);
+    if (!rc) rc = discos::batch_spread(b, s);
+    if (!rc) rc = discos::batch_poisson(b, s);
+    if (!rc) rc = discos::batch_interp(b, s);
+    if (!rc) rc = discos::batch_near(b, s);
+    if (!rc) rc = discos::batch_update(b, pos, q, id, sp, s);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int discos_batch_create(const discos_replica* reps, int32_t count, double h, const discos_params* p,
+                        discos_batch** out) {
+    if (!out) return DISCOS_E_ARG;
+    *out = nullptr;
+    if (!reps || count < 1 || !p) return DISCOS_E_ARG;
+    if (!finite_pos(h) || !finite_pos(p->eps) || !finite_pos(p->psi) || !finite_pos(p->kT) ||
+        !finite_pos(p->eta) || !finite_pos(p->dt) || p->nspecies < 1 || !p->radius ||
+        !p->p3m_table || p->p3m_len < 2 || !finite_pos(p->p3m_dr))
+        return DISCOS_E_ARG;
+    for (int w = 0; w < 2; ++w)
+        if (p->bc_type[w] != DISCOS_BC_DIRICHLET && p->bc_type[w] != DISCOS_BC_NEUMANN)
+            return DISCOS_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->e_ext[k])) return DISCOS_E_ARG;
+    if (p->psi / h / p->p3m_dr > (double)(p->p3m_len - 1)) return DISCOS_E_ARG;
+    // the entries the cutoff can reach are copied to LDS by the force pass (320 at most)
+    if (p->psi / h / p->p3m_dr + 2.0 > 320.0) return DISCOS_E_ARG;
+    if (p->lj_on && (!p->lj_sigma || !p->lj_xi || !finite_pos(p->lj_range))) return DISCOS_E_ARG;
+    const int Rb = discos::near_radius_bins_h(h, p);
+    if (Rb > 3) return DISCOS_E_ARG;
+    int64_t n_tot = 0;
+    for (int r = 0; r < count; ++r) {
+        const discos_replica& c = reps[r];
+        if (!pow2_in(c.nx, 8, 1024) || !pow2_in(c.ny, 8, 1024) || c.nz < 4 || c.nz > 4096 || c.n < 0)
+            return DISCOS_E_SHAPE;
+        if (2 * Rb + 1 > c.nx / DISCOS_BIN || 2 * Rb + 1 > c.ny / DISCOS_BIN) return DISCOS_E_SHAPE;
+        if (!c.mob_coef && !p->mob_coef) return DISCOS_E_ARG;
+        if (!std::isfinite(c.bc_value[0]) || !std::isfinite(c.bc_value[1])) return DISCOS_E_ARG;
+        n_tot += c.n;
+    }
+    if (n_tot >= (int64_t(1) << 26)) return DISCOS_E_CAPACITY;
+
+    discos_batch* b = new (std::nothrow) discos_batch();
+    if (!b) return DISCOS_E_HIP;
+    b->R = count;
+    b->h = h;
+    b->p = *p;
+    b->reps.assign(reps, reps + count);
+    b->n_tot = n_tot;
+    b->cfg = {16, 0, 16, 0, 256};
+    b->next_step = ~uint64_t(0);
+    int dev = 0;
+    hipGetDevice(&dev);
+    b->ncu = 256;
+    hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+
+    // ions and bins in channel order
+    b->ion_off.assign(count + 1, 0);
+    std::vector<int> bin_off(count + 1, 0);
+    for (int r = 0; r < count; ++r) {
+        const discos_replica& c = reps[r];
+        b->ion_off[r + 1] = b->ion_off[r] + c.n;
+        const int nb = (c.nx / DISCOS_BIN) * (c.ny / DISCOS_BIN) * ((c.nz + DISCOS_BIN - 1) / DISCOS_BIN);
+        bin_off[r + 1] = bin_off[r] + nb;
+    }
+    b->nbins_tot = bin_off[count];
+    // cells and spectra by (nx, ny) class
+    std::map<std::pair<int, int>, std::vector<int>> cls;
+    for (int r = 0; r < count; ++r) cls[{reps[r].nx, reps[r].ny}].push_back(r);
+    b->reps_h.resize(count);
+    std::vector<int> mode_off(count + 1, 0), mode_rep(count, 0);
+    int64_t cell = 0, spec = 0, wall = 0;
+    int slot = 0;
+    for (auto& kv : cls) {
+        discos::BatchClass k{};
+        k.nx = kv.first.first;
+        k.ny = kv.first.second;
+        k.rep_first = slot;
+        k.rep_count = (int)kv.second.size();
+        k.cell_off = cell;
+        k.spec_off = spec;
+        for (int r : kv.second) {
+            const discos_replica& c = reps[r];
+            discos::RepDev& d = b->reps_h[r];
+            discos::GridDev& g = d.g;
+            g.nx = c.nx;
+            g.ny = c.ny;
+            g.nz = c.nz;
+            g.nxh = c.nx / 2 + 1;
+            g.h = h;
+            g.inv_h = 1.0 / h;
+            g.Lx = c.nx * h;
+            g.Ly = c.ny * h;
+            g.Lz = c.nz * h;
+            g.nbx = c.nx / DISCOS_BIN;
+            g.nby = c.ny / DISCOS_BIN;
+            g.nbz = (c.nz + DISCOS_BIN - 1) / DISCOS_BIN;
+            d.cell_off = cell;
+            d.spec_off = spec;
+            d.bin_off = bin_off[r];
+            d.ion_off = (int)b->ion_off[r];
+            d.n = (int)c.n;
+            d.s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+            d.s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+            d.scale = (h * h / p->eps) / ((double)c.nx * c.ny);
+            d.singular = p->bc_type[0] == DISCOS_BC_NEUMANN && p->bc_type[1] == DISCOS_BC_NEUMANN;
+            d.nmode = g.nxh * c.ny;
+            d.seed = c.seed;
+            d.coef = c.mob_coef ? c.mob_coef : p->mob_coef;
+            d.w.type[0] = p->bc_type[0];
+            d.w.type[1] = p->bc_type[1];
+            d.w.eps = p->eps;
+            d.w.value[0] = reinterpret_cast<const double*>(wall);  // offsets; rebased below
+            d.w.value[1] = reinterpret_cast<const double*>(wall + (int64_t)c.nx * c.ny);
+            wall += 2 * (int64_t)c.nx * c.ny;
+            cell += (int64_t)c.nx * c.ny * c.nz;
+            spec += (int64_t)g.nxh * c.ny * c.nz;
+            k.rows += c.ny * c.nz;
+            k.levels += c.nz;
+            mode_rep[slot] = r;
+            mode_off[slot + 1] = mode_off[slot] + d.nmode;
+            ++slot;
+        }
+        b->classes.push_back(k);
+    }
+    b->ncell_tot = cell;
+    b->nspec_tot = spec;
+    b->nmode_tot = mode_off[count];
+    // tile tasks, largest channels first
+    std::vector<int> order(count);
+    for (int r = 0; r < count; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (int64_t)reps[a].nx * reps[a].ny * reps[a].nz > (int64_t)reps[c].nx * reps[c].ny * reps[c].nz;
+    });
+    std::vector<int2> tk[2][2];
+    const int tsz[2][2][3] = {{{8, 8, 8}, {16, 16, 16}}, {{8, 8, 8}, {16, 16, 8}}};
+    for (int kind = 0; kind < 2; ++kind)
+        for (int v = 0; v < 2; ++v)
+            for (int r : order) {
+                const int nt = tiles_of(reps[r], tsz[kind][v][0], tsz[kind][v][1], tsz[kind][v][2]);
+                for (int t = 0; t < nt; ++t) tk[kind][v].push_back(make_int2(r, t));
+            }
+    // twiddles per distinct axis length
+    std::map<int, int> tw_index;
+    std::vector<double2> tw_all;
+    auto tw_of = [&](int N) {
+        auto it = tw_index.find(N);
+        if (it != tw_index.end()) return it->second;
+        const int at = (int)tw_all.size();
+        for (int q = 0; q < N / 2; ++q) {
+            const double a = 2.0 * M_PI * (double)q / (double)N;
+            tw_all.push_back(make_double2(std::cos(a), -std::sin(a)));
+        }
+        tw_index[N] = at;
+        return at;
+    };
+    std::vector<std::pair<int, int>> tw_at;
+    for (auto& k : b->classes) tw_at.push_back({tw_of(k.nx), tw_of(k.ny)});
+
+    // one allocation
+    const size_t n = (size_t)std::max<int64_t>(n_tot, 1);
+    const size_t nblk = (size_t)(b->nbins_tot + 1023) / 1024 + 1;
+    size_t bytes = 0;
+    bytes += carve_bytes(n, sizeof(double4));
+    bytes += 6 * carve_bytes(n, sizeof(int));  // sid ssp perm ion_bin ion_rank ion_rep
+    bytes += carve_bytes(b->nbins_tot, sizeof(int)) + carve_bytes(b->nbins_tot + 1, sizeof(int));
+    bytes += carve_bytes(nblk, sizeof(int));
+    bytes += 2 * carve_bytes(b->ncell_tot, sizeof(double));
+    bytes += carve_bytes(b->nspec_tot, sizeof(double2)) + carve_bytes(b->nspec_tot, sizeof(double));
+    bytes += carve_bytes(3 * n, sizeof(double));
+    bytes += carve_bytes(64 * n, sizeof(int)) + carve_bytes(n, sizeof(int));
+    bytes += carve_bytes(64, sizeof(int)) + carve_bytes(1, sizeof(uint64_t));
+    bytes += carve_bytes(count + 1, sizeof(int)) + carve_bytes(count, sizeof(int));
+    bytes += carve_bytes(count, sizeof(discos::RepDev));
+    for (int kind = 0; kind < 2; ++kind)
+        for (int v = 0; v < 2; ++v) bytes += carve_bytes(std::max<size_t>(tk[kind][v].size(), 1), sizeof(int2));
+    bytes += carve_bytes(std::max<int64_t>(wall, 1), sizeof(double));
+    bytes += carve_bytes(tw_all.size(), sizeof(double2));
+    if (hipMalloc(&b->pool, bytes) != hipSuccess) {
+        destroy(b);
+        return DISCOS_E_HIP;
+    }
+    char* cur = static_cast<char*>(b->pool);
+    b->sxyzq = carve<double4>(cur, n);
+    b->sid = carve<int>(cur, n);
+    b->ssp = carve<int>(cur, n);
+    b->perm = carve<int>(cur, n);
+    b->ion_bin = carve<int>(cur, n);
+    b->ion_rank = carve<int>(cur, n);
+    b->ion_rep = carve<int>(cur, n);
+    b->bin_count = carve<int>(cur, b->nbins_tot);
+    b->bin_start = carve<int>(cur, b->nbins_tot + 1);
+    b->scan_tmp = carve<int>(cur, nblk);
+    b->rho = carve<double>(cur, b->ncell_tot);
+    b->phi = carve<double>(cur, b->ncell_tot);
+    b->spec = carve<double2>(cur, b->nspec_tot);
+    b->cprime = carve<double>(cur, b->nspec_tot);
+    b->fp = carve<double>(cur, 3 * n);
+    b->nlist = carve<int>(cur, 64 * n);
+    b->ncount = carve<int>(cur, n);
+    b->flags = carve<int>(cur, 64);
+    b->step_d = carve<uint64_t>(cur, 1);
+    b->mode_off = carve<int>(cur, count + 1);
+    b->mode_rep = carve<int>(cur, count);
+    b->reps_d = carve<discos::RepDev>(cur, count);
+    for (int kind = 0; kind < 2; ++kind)
+        for (int v = 0; v < 2; ++v) {
+            b->tasks[kind][v] = carve<int2>(cur, std::max<size_t>(tk[kind][v].size(), 1));
+            b->ntasks[kind][v] = (int)tk[kind][v].size();
+        }
+    b->walls = carve<double>(cur, std::max<int64_t>(wall, 1));
+    double2* tw_d = carve<double2>(cur, tw_all.size());
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+        b->classes[c].tw_x = tw_d + tw_at[c].first;
+        b->classes[c].tw_y = tw_d + tw_at[c].second;
+    }
+    // host tables -> device
+    std::vector<int> ion_rep(n, 0);
+    std::vector<double> walls(std::max<int64_t>(wall, 1), 0.0);
+    for (int r = 0; r < count; ++r) {
+        for (int64_t i = b->ion_off[r]; i < b->ion_off[r + 1]; ++i) ion_rep[i] = r;
+        discos::RepDev& d = b->reps_h[r];
+        const int64_t w0 = reinterpret_cast<int64_t>(d.w.value[0]);
+        const int64_t ncol = (int64_t)reps[r].nx * reps[r].ny;
+        for (int64_t k = 0; k < ncol; ++k) {
+            walls[w0 + k] = reps[r].bc_value[0];
+            walls[w0 + ncol + k] = reps[r].bc_value[1];
+        }
+        d.w.value[0] = b->walls + w0;
+        d.w.value[1] = b->walls + w0 + ncol;
+    }
+    bool ok = hipMemcpy(b->ion_rep, ion_rep.data(), n * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->walls, walls.data(), walls.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->reps_d, b->reps_h.data(), count * sizeof(discos::RepDev), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->mode_off, mode_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->mode_rep, mode_rep.data(), count * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(tw_d, tw_all.data(), tw_all.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;
+    for (int kind = 0; kind < 2; ++kind)
+        for (int v = 0; v < 2; ++v)
+            if (!tk[kind][v].empty())
+                ok = ok && hipMemcpy(b->tasks[kind][v], tk[kind][v].data(), tk[kind][v].size() * sizeof(int2),
+                                     hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(b->flags, 0, 64 * sizeof(int)) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        destroy(b);
+        return DISCOS_E_HIP;
+    }
+    *out = b;
+    return DISCOS_OK;
+}
+
+int discos_batch_destroy(discos_batch* b) {
+    if (!b) return DISCOS_E_ARG;
+    hipDeviceSynchronize();
+    destroy(b);
+    return DISCOS_OK;
+}
+
+int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int32_t* species,
+                      uint64_t step, uint32_t flags, void* stream) {
+    if (!b) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    b->last_stream = s;
+    if (flags & ~DISCOS_BATCH_GRAPH) return fail(b, DISCOS_E_ARG, "unknown batch step flags");
+    if (b->n_tot > 0 && (!pos || !q || !id || !species)) return fail(b, DISCOS_E_ARG, "null ion array");
+    if (!(flags & DISCOS_BATCH_GRAPH)) {
+        int rc = discos::batch_set_step(b, step, s);
+        if (!rc) rc = run_step(b, pos, q, id, species, s);
+        b->next_step = ~uint64_t(0);  // the device counter no longer matches a graph's view
+        return rc ? fail(b, rc, "batch step launch failed") : DISCOS_OK;
+    }
+    const void* args[4] = {pos, q, id, species};
+    const bool same = b->exec && args[0] == b->graph_args[0] && args[1] == b->graph_args[1] &&
+                      args[2] == b->graph_args[2] && args[3] == b->graph_args[3];
+    if (!same) {
+        if (b->exec) {
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        if (hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(b, DISCOS_E_HIP, "graph capture could not start");
+        const int rc = run_step(b, pos, q, id, species, b->own);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->own, &g);
+        if (rc || e != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return fail(b, DISCOS_E_HIP, "graph capture failed");
+        }
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            b->exec = nullptr;
+            return fail(b, DISCOS_E_HIP, "graph instantiation failed");
+        }
+        for (int k = 0; k < 4; ++k) b->graph_args[k] = args[k];
+        b->next_step = ~uint64_t(0);
+    }
+    // order the replay after the caller's stream, and the caller's stream after it
+    if (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(b->own, b->ev_in, 0) != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "stream ordering failed");
+    if (step != b->next_step && discos::batch_set_step(b, step, b->own))
+        return fail(b, DISCOS_E_HIP, "step counter update failed");
+    if (hipGraphLaunch(b->exec, b->own) != hipSuccess) return fail(b, DISCOS_E_HIP, "graph launch failed");
+    b->next_step = step + 1;
+    if (hipEventRecord(b->ev_out, b->own) != hipSuccess || hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "stream ordering failed");
+    return DISCOS_OK;
+}
+
+int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const int32_t* id,
+                      const int32_t* species, int32_t* cfg_out, void* stream) {
+    if (!b) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    b->last_stream = s;
+    if (b->n_tot > 0 && (!pos || !q || !id || !species)) return fail(b, DISCOS_E_ARG, "null ion array");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(b, DISCOS_E_HIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(b, DISCOS_E_HIP, "event create");
+    }
+    const int reps = 3;
+    auto timed = [&](auto&& fn) -> float {
+        fn();  // warm
+        hipEventRecord(e0, s);
+        for (int k = 0; k < reps; ++k) fn();
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    int rc = discos::batch_cell_list(b, pos, q, const_cast<int*>(id), const_cast<int*>(species), s);
+    const int blocks[3] = {0, 4 * b->ncu, 8 * b->ncu};
+    // spread: tile edge x persistent blocks
+    float best = 1e30f;
+    discos::BatchCfg c = b->cfg;
+    for (int t : {8, 16})
+        for (int nb : blocks) {
+            b->cfg.spread_t = t;
+            b->cfg.spread_blocks = nb;
+            const float ms = timed([&] { discos::batch_spread(b, s); });
+            if (ms < best) {
+                best = ms;
+                c.spread_t = t;
+                c.spread_blocks = nb;
+            }
+        }
+    b->cfg.spread_t = c.spread_t;
+    b->cfg.spread_blocks = c.spread_blocks;
+    if (!rc) rc = discos::batch_spread(b, s);
+    if (!rc) rc = discos::batch_poisson(b, s);
+    // interpolation: tile shape x persistent blocks
+    best = 1e30f;
+    for (int t : {8, 16})
+        for (int nb : blocks) {
+            b->cfg.interp_t = t;
+            b->cfg.interp_blocks = nb;
+            const float ms = timed([&] { discos::batch_interp(b, s); });
+            if (ms < best) {
+                best = ms;
+                c.interp_t = t;
+                c.interp_blocks = nb;
+            }
+        }
+    b->cfg.interp_t = c.interp_t;
+    b->cfg.interp_blocks = c.interp_blocks;
+    // per-ion stages: workgroup size (the near-field pair of kernels)
+    best = 1e30f;
+    for (int wg : {64, 128, 256}) {
+        b->cfg.ion_block = wg;
+        const float ms = timed([&] { discos::batch_near(b, s); });
+        if (ms < best) {
+            best = ms;
+            c.ion_block = wg;
+        }
+    }
+    b->cfg = c;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // a captured graph holds the previous launch shapes
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (cfg_out) {
+        cfg_out[0] = c.spread_t;
+        cfg_out[1] = c.spread_blocks;
+        cfg_out[2] = c.interp_t;
+        cfg_out[3] = c.interp_blocks;
+        cfg_out[4] = c.ion_block;
+    }
+    if (rc || hipGetLastError() != hipSuccess) return fail(b, DISCOS_E_HIP, "tuning launch failed");
+    return DISCOS_OK;
+}
+
+int discos_batch_check(discos_batch* b) {
+    if (!b) return DISCOS_E_ARG;
+    if (hipStreamSynchronize(b->last_stream) != hipSuccess || hipStreamSynchronize(b->own) != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "sync failed");
+    int f = 0;
+    if (hipMemcpy(&f, b->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "flag read failed");
+    if (f) hipMemset(b->flags, 0, sizeof(int));
+    if (f & DISCOS_FLAG_NONFINITE) return fail(b, DISCOS_E_NONFINITE, "non-finite position");
+    if (f & DISCOS_FLAG_BAD_SPECIES) return fail(b, DISCOS_E_ARG, "species index out of range");
+    if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(b, DISCOS_E_NOT_NEUTRAL, "channel not neutral");
+    if (f & DISCOS_FLAG_OUT_OF_DOMAIN) return fail(b, DISCOS_E_OUT_OF_DOMAIN, "ion outside its channel");
+    return DISCOS_OK;
+}
+
+const char* discos_batch_last_error(discos_batch* b) {
+    if (!b) return "null batch";
+    return b->err.c_str();
+}
+
+}  // extern "C"

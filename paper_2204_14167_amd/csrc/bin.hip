@@ -17,13 +17,14 @@ __global__ void fill_f64_kernel(double* __restrict__ a, int64_t n, double v) {
         a[i] = v;
 }
 
-// Bin of each ion and its rank inside the bin (arrival order of the atomic).
-__global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
-                                 const double* __restrict__ y, const double* __restrict__ z,
-                                 int* __restrict__ count, int* __restrict__ ion_bin,
-                                 int* __restrict__ ion_rank, int* __restrict__ flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Bin of ion i (bins of its channel start at bin_off) and its rank inside the bin
+// (arrival order of the atomic).
+__device__ __forceinline__ void bin_count_one(const GridDev& g, int bin_off, int i,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ z,
+                                              int* __restrict__ count, int* __restrict__ ion_bin,
+                                              int* __restrict__ ion_rank, int* __restrict__ flags) {
     const double xi = x[i], yi = y[i], zi = z[i];
     if (!pos_ok(g, xi, yi, zi))
         set_flag(flags, (isfinite(xi) && isfinite(yi) && isfinite(zi)) ? DISCOS_FLAG_OUT_OF_DOMAIN
@@ -33,8 +34,28 @@ __global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
                    fabs(yi) < 1e12 * g.h)
                       ? bin_of(g, xi, yi, zi, bx, by, bz)
                       : 0;
-    ion_bin[i] = b;
-    ion_rank[i] = atomicAdd(&count[b], 1);
+    ion_bin[i] = bin_off + b;
+    ion_rank[i] = atomicAdd(&count[bin_off + b], 1);
+}
+
+__global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z,
+                                 int* __restrict__ count, int* __restrict__ ion_bin,
+                                 int* __restrict__ ion_rank, int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bin_count_one(g, 0, i, x, y, z, count, ion_bin, ion_rank, flags);
+}
+
+__global__ void bin_count_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                                       int n, const double* __restrict__ x,
+                                       const double* __restrict__ y, const double* __restrict__ z,
+                                       int* __restrict__ count, int* __restrict__ ion_bin,
+                                       int* __restrict__ ion_rank, int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RepDev& R = reps[ion_rep[i]];
+    bin_count_one(R.g, R.bin_off, i, x, y, z, count, ion_bin, ion_rank, flags);
 }
 
 // Exclusive scan of `count` (nb entries) into `start` (nb + 1 entries); three phases.
@@ -110,6 +131,31 @@ __global__ void scan_final_kernel(const int* __restrict__ count, int64_t nb,
 }
 
 // Sorted copies of the ion arrays; perm[sorted] = original index.
+__global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
+                                         const int* __restrict__ ion_rep, int n,
+                                         const int* __restrict__ ion_bin,
+                                         const int* __restrict__ ion_rank,
+                                         const int* __restrict__ start, const double* __restrict__ x,
+                                         const double* __restrict__ y, const double* __restrict__ z,
+                                         const double* __restrict__ q, const int* __restrict__ id,
+                                         const int* __restrict__ sp, double4* __restrict__ sxyzq,
+                                         int* __restrict__ sid, int* __restrict__ ssp,
+                                         int* __restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const GridDev& g = reps[ion_rep[i]].g;
+    const int d = start[ion_bin[i]] + ion_rank[i];
+    double xi = x[i], yi = y[i];
+    if (isfinite(xi) && isfinite(yi)) {
+        xi = reduce_periodic(xi, g.Lx);
+        yi = reduce_periodic(yi, g.Ly);
+    }
+    sxyzq[d] = make_double4(xi, yi, z[i], q[i]);
+    sid[d] = id[i];
+    ssp[d] = sp[i];
+    perm[d] = i;
+}
+
 __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
                                    const int* __restrict__ ion_rank, const int* __restrict__ start,
                                    const double* __restrict__ x, const double* __restrict__ y,
@@ -158,6 +204,26 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
                                                          x, y, z, q, id, sp, g, c->sxyzq,
                                                          c->sid, c->ssp, c->perm, w3, w3_stride,
                                                          c->fp, c->n_max);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id, const int* sp,
+                    hipStream_t s) {
+    const int64_t nb = b->nbins_tot;
+    const int n = (int)b->n_tot;
+    const int T = b->cfg.ion_block;
+    fill_i32_kernel<<<(int)std::min<int64_t>((nb + 255) / 256, 4096), 256, 0, s>>>(b->bin_count, nb, 0);
+    bin_count_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, pos, pos + n,
+                                                         pos + 2 * (int64_t)n, b->bin_count,
+                                                         b->ion_bin, b->ion_rank, b->flags);
+    const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
+    scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp);
+    scan_blocks_kernel<<<1, SCAN_BLOCK, 0, s>>>(b->scan_tmp, nblk);
+    scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp, b->bin_start, n);
+    bin_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, b->ion_bin,
+                                                           b->ion_rank, b->bin_start, pos, pos + n,
+                                                           pos + 2 * (int64_t)n, q, id, sp, b->sxyzq,
+                                                           b->sid, b->ssp, b->perm);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

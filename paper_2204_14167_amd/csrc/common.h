@@ -30,6 +30,24 @@ struct WallDev {
     double eps;
 };
 
+// One channel of a batch as the kernels see it: its grid and walls, and where its data
+// sit in the batch arrays (cells and spectra grouped by size class, ions and bins in
+// channel order).
+struct RepDev {
+    GridDev g;
+    WallDev w;           // wall value pointers already offset to this channel
+    int64_t cell_off;    // rho, phi
+    int64_t spec_off;    // half spectra and Thomas scratch
+    int bin_off;         // first bin
+    int ion_off, n;      // ions [ion_off, ion_off + n)
+    double s_lo, s_hi;   // image signs of the two walls
+    double scale;        // h^2 / eps / (nx ny), the Poisson right-hand side scale
+    int singular;        // both walls Neumann
+    int nmode;           // (nx/2 + 1) ny
+    uint64_t seed;       // Philox key of this channel's noise
+    const double* coef;  // mobility fit [nspecies][2][7]
+};
+
 __device__ __forceinline__ int wrapi(int n, int N) {
     int r = n % N;
     return r < 0 ? r + N : r;

@@ -50,17 +50,21 @@ __device__ __forceinline__ int window_weights(double u, double wc5[5], double dw
     return c;
 }
 
-__global__ void __launch_bounds__(IT_THREADS)
-interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq,
-                 const int* __restrict__ bin_start, const int* __restrict__ perm,
-                 const double* __restrict__ phi, double ex0, double ex1, double ex2,
-                 double* __restrict__ out, int64_t stride, int scatter, int* __restrict__ flags) {
-    constexpr int LX = IT_TX + IT_H, LY = IT_TY + IT_H, LZ = IT_TZ + IT_H;
-    __shared__ double tile[LZ * LY * LX];
-    __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
-    const int tx = min(IT_TX, g.nx), ty = min(IT_TY, g.ny);
-    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * IT_TZ;
-    const int tz = min(IT_TZ, g.nz - z0);
+// One tile of TX x TY x TZ cells (clipped to the grid) starting at (x0, y0, z0):
+// stage phi with its halo and ghost layers in LDS (tile holds (TX+5)(TY+5)(TZ+5)
+// doubles) and interpolate every ion of the tile's cells.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, int op,
+                                            const double4* __restrict__ sxyzq,
+                                            const int* __restrict__ bin_start,
+                                            const int* __restrict__ perm,
+                                            const double* __restrict__ phi, double ex0, double ex1,
+                                            double ex2, double* __restrict__ out, int64_t stride,
+                                            int scatter, int* __restrict__ flags, int x0, int y0,
+                                            int z0, double* tile, int* rstart, int* rpre, int* scan) {
+    constexpr int LX = TX + IT_H, LY = TY + IT_H;
+    const int tx = min(TX, g.nx), ty = min(TY, g.ny);
+    const int tz = min(TZ, g.nz - z0);
     const int lxn = tx + IT_H, lyn = ty + IT_H, lzn = tz + IT_H;
     // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled
     for (int e = threadIdx.x; e < LX * LY * lzn; e += blockDim.x) {
@@ -174,6 +178,45 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
     }
 }
 
+__global__ void __launch_bounds__(IT_THREADS)
+interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ bin_start, const int* __restrict__ perm,
+                 const double* __restrict__ phi, double ex0, double ex1, double ex2,
+                 double* __restrict__ out, int64_t stride, int scatter, int* __restrict__ flags) {
+    __shared__ double tile[(IT_TZ + IT_H) * (IT_TY + IT_H) * (IT_TX + IT_H)];
+    __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
+    const int tx = min(IT_TX, g.nx), ty = min(IT_TY, g.ny);
+    interp_tile<IT_TX, IT_TY, IT_TZ>(g, w, op, sxyzq, bin_start, perm, phi, ex0, ex1, ex2, out, stride,
+                                     scatter, flags, blockIdx.x * tx, blockIdx.y * ty,
+                                     blockIdx.z * IT_TZ, tile, rstart, rpre, scan);
+}
+
+// Batched: forces q (E^P + E_ext) of every channel's ions, in cell-list order; the
+// persistent grid walks the (channel, tile) tasks.
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(IT_THREADS)
+interp_es_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__ tasks,
+                       int ntasks, const double4* __restrict__ sxyzq,
+                       const int* __restrict__ bin_start, const int* __restrict__ perm,
+                       const double* __restrict__ phi, double ex0, double ex1, double ex2,
+                       double* __restrict__ out, int64_t stride, int* __restrict__ flags) {
+    __shared__ double tile[(TZ + IT_H) * (TY + IT_H) * (TX + IT_H)];
+    __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const int2 task = tasks[t];
+        const RepDev& R = reps[task.x];
+        const GridDev g = R.g;
+        const int tx = min(TX, g.nx), ty = min(TY, g.ny);
+        const int ntx = g.nx / tx, nty = g.ny / ty;
+        const int k = task.y;
+        interp_tile<TX, TY, TZ>(g, R.w, DISCOS_INTERP_FORCE, sxyzq, bin_start + R.bin_off, perm,
+                                phi + R.cell_off, ex0, ex1, ex2, out, stride, 0, flags,
+                                (k % ntx) * tx, ((k / ntx) % nty) * ty, (k / (ntx * nty)) * TZ,
+                                tile, rstart, rpre, scan);
+        __syncthreads();
+    }
+}
+
 int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_params* p,
                      double* out, int64_t out_stride, int scatter, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
@@ -183,6 +226,23 @@ int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_para
     interp_es_kernel<<<grid, IT_THREADS, 0, s>>>(g, wall_of(p), op, c->sxyzq, c->bin_start, c->perm,
                                                  phi, p->e_ext[0], p->e_ext[1], p->e_ext[2], out,
                                                  out_stride, scatter, c->flags);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int batch_interp(Batch* b, hipStream_t s) {
+    const int v = b->cfg.interp_t == 8 ? 0 : 1;
+    const int nt = b->ntasks[1][v];
+    if (nt == 0) return DISCOS_OK;
+    const int nb = b->cfg.interp_blocks > 0 ? std::min(nt, b->cfg.interp_blocks) : nt;
+    const double* e = b->p.e_ext;
+    if (v == 0)
+        interp_es_batch_kernel<8, 8, 8><<<nb, IT_THREADS, 0, s>>>(
+            b->reps_d, b->tasks[1][0], nt, b->sxyzq, b->bin_start, b->perm, b->phi, e[0], e[1], e[2],
+            b->fp, b->n_tot, b->flags);
+    else
+        interp_es_batch_kernel<IT_TX, IT_TY, IT_TZ><<<nb, IT_THREADS, 0, s>>>(
+            b->reps_d, b->tasks[1][1], nt, b->sxyzq, b->bin_start, b->perm, b->phi, e[0], e[1], e[2],
+            b->fp, b->n_tot, b->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -57,6 +58,58 @@ struct Ctx {
 };
 
 #define PROF_MAX 512
+
+// A batch of independent channels (one dry step each per discos_batch_step).
+struct BatchClass {   // channels of one (nx, ny): their grids and spectra are contiguous
+    int nx, ny, rep_first, rep_count;
+    int64_t cell_off, spec_off;  // of the first channel of the class
+    int rows, levels;            // sum of ny nz and of nz over the class
+    double2 *tw_x, *tw_y;
+};
+
+struct BatchCfg {   // launch choices (the autotuner's output)
+    int spread_t;       // spread tile edge: 8 or 16
+    int spread_blocks;  // persistent blocks of the spread (0: one per task)
+    int interp_t;       // interpolation tile: 16 -> 16x16x8, 8 -> 8x8x8
+    int interp_blocks;  // persistent blocks of the interpolation (0: one per task)
+    int ion_block;      // workgroup size of the per-ion kernels
+};
+
+struct Batch {
+    int R;
+    double h;
+    discos_params p;              // shared physics (copied)
+    std::vector<discos_replica> reps;
+    std::vector<RepDev> reps_h;
+    RepDev* reps_d;
+    int64_t n_tot, ncell_tot, nspec_tot, nbins_tot;
+    std::vector<int64_t> ion_off;  // [R + 1]
+    int* ion_rep;                  // [n_tot] channel of each ion slot
+    int* mode_off;                 // [R + 1] prefix of the channels' mode counts (class order)
+    int* mode_rep;                 // [R] channel of each position in mode_off
+    int64_t nmode_tot;
+    int2* tasks[2][2];             // [kernel: spread, interp][variant]: (channel, tile)
+    int ntasks[2][2];
+    std::vector<BatchClass> classes;
+    double* walls;                 // per-channel wall fields [2][ny][nx], back to back
+    double4* sxyzq;
+    int *sid, *ssp, *perm, *ion_bin, *ion_rank, *bin_count, *bin_start, *scan_tmp;
+    double *rho, *phi, *cprime, *fp;
+    double2* spec;
+    int *nlist, *ncount, *flags;
+    uint64_t* step_d;
+    void* pool;
+    BatchCfg cfg;
+    int ncu;
+    hipStream_t own;               // stream of the captured graph
+    hipEvent_t ev_in, ev_out;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    const void* graph_args[4];
+    uint64_t next_step;
+    hipStream_t last_stream;
+    std::string err;
+};
 #define PART_MAX 1024
 
 // Record the event that closes stage k of the current profiled step.
@@ -127,5 +180,16 @@ int energy_flux(Ctx* c, int n, const discos_params* p, const double* phi, double
 int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* phi, const double* gvec,
                          double* dpos, double* dq, double* dlo, double* dhi, double* de,
                          hipStream_t s);
+
+// Batched stages (one launch each over all channels of the batch).
+int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id, const int* sp,
+                    hipStream_t s);
+int batch_spread(Batch* b, hipStream_t s);
+int batch_poisson(Batch* b, hipStream_t s);
+int batch_interp(Batch* b, hipStream_t s);
+int batch_near(Batch* b, hipStream_t s);
+int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s);
+int batch_set_step(Batch* b, uint64_t v, hipStream_t s);
+int near_radius_bins_h(double h, const discos_params* p);
 
 }  // namespace discos

@@ -24,21 +24,21 @@ struct NearDev {
     int nsp;
 };
 
-static NearDev near_of(const Ctx* c, const discos_params* p) {
+static NearDev near_of_h(double h, const discos_params* p) {
     NearDev d;
     d.psi = p->psi;
     d.psi2 = p->psi * p->psi;
     d.psi2g = p->psi * p->psi * (1.0 + 1e-12);
     d.inv4pieps = 1.0 / (4.0 * M_PI * p->eps);
-    d.h = c->grid.h;
-    d.inv_h2 = 1.0 / (c->grid.h * c->grid.h);
-    d.inv_hdr = 1.0 / (c->grid.h * p->p3m_dr);
+    d.h = h;
+    d.inv_h2 = 1.0 / (h * h);
+    d.inv_hdr = 1.0 / (h * p->p3m_dr);
     d.tab = p->p3m_table;
     d.tablen = p->p3m_len;
     double range = p->psi;
     if (p->lj_on) range = std::max(range, p->lj_range);
     d.rsearch = range;
-    d.R = (int)std::ceil(range / (DISCOS_BIN * c->grid.h));
+    d.R = (int)std::ceil(range / (DISCOS_BIN * h));
     d.s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.wall_on = p->wall_on;
@@ -53,7 +53,10 @@ static NearDev near_of(const Ctx* c, const discos_params* p) {
     return d;
 }
 
+static NearDev near_of(const Ctx* c, const discos_params* p) { return near_of_h(c->grid.h, p); }
+
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
+int near_radius_bins_h(double h, const discos_params* p) { return near_of_h(h, p).R; }
 
 // 1/sqrt(r2) to full FP64 accuracy: hardware estimate plus two Newton steps.
 __device__ __forceinline__ double inv_sqrt(double r2) {
@@ -195,12 +198,10 @@ __device__ __forceinline__ double shift_of(int code, double L) {
     return code == 1 ? -L : (code == 2 ? L : 0.0);
 }
 
-__global__ void __launch_bounds__(256)
-near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
-                 const int* __restrict__ bin_start, int* __restrict__ list,
-                 int* __restrict__ count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P, int i, int n,
+                                              const double4* __restrict__ sxyzq,
+                                              const int* __restrict__ bin_start,
+                                              int* __restrict__ list, int* __restrict__ count) {
     const double4 me = sxyzq[i];
     const double xi = me.x, yi = me.y, zi = me.z;
     if (!pos_ok(g, xi, yi, zi)) {
@@ -289,6 +290,27 @@ near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
     count[i] = nh;
 }
 
+__global__ void __launch_bounds__(256)
+near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ bin_start, int* __restrict__ list,
+                 int* __restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    near_list_one(g, P, i, n, sxyzq, bin_start, list, count);
+}
+
+// Batched: ion i (cell-list order) belongs to channel ion_rep[i]; its bins start at the
+// channel's bin offset, and its list entries are batch-wide sorted indices.
+__global__ void near_list_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                                       NearDev P, int n, const double4* __restrict__ sxyzq,
+                                       const int* __restrict__ bin_start, int* __restrict__ list,
+                                       int* __restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RepDev& R = reps[ion_rep[i]];
+    near_list_one(R.g, P, i, n, sxyzq, bin_start + R.bin_off, list, count);
+}
+
 // Pair forces of ion i from its list (or, when the list overflowed, from a direct
 // walk of the cell list), plus the 9-3 wall force.
 __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
@@ -356,6 +378,37 @@ near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
     out[o] += Fx;
     out[o + stride] += Fy;
     out[o + 2 * stride] += Fz;
+}
+
+__global__ void __launch_bounds__(256)
+near_eval_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep, NearDev P,
+                       int n, const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
+                       const int* __restrict__ bin_start, const int* __restrict__ list,
+                       const int* __restrict__ count, double* __restrict__ out,
+                       int* __restrict__ flags) {
+    __shared__ double tab[NL_TAB];
+    const int nt = min(P.tablen, NL_TAB);
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
+    __syncthreads();
+    P.tab = tab;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RepDev& R = reps[ion_rep[i]];
+    const GridDev g = R.g;
+    P.s_lo = R.s_lo;
+    P.s_hi = R.s_hi;
+    const double4 me = sxyzq[i];
+    if (!pos_ok(g, me.x, me.y, me.z)) return;
+    int spi = 0;
+    if (P.lj_on) {
+        spi = ssp[i];
+        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+    }
+    double Fx, Fy, Fz;
+    list_force(i, n, me, spi, sxyzq, ssp, bin_start + R.bin_off, list, count[i], g, P, Fx, Fy, Fz);
+    out[i] += Fx;
+    out[i + n] += Fy;
+    out[i + 2 * (int64_t)n] += Fz;
 }
 
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
@@ -442,15 +495,14 @@ __device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int
 // Update of every ion of the cell list from its complete force fp (grid, near field,
 // wall, applied field) and, in a wet step, its velocity vw = J(x*) v, written to the
 // caller's arrays in cell-list order.
-__global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
-                                  const int* __restrict__ sid, const int* __restrict__ ssp,
-                                  const double* __restrict__ fp, int64_t fstride,
-                                  const double* __restrict__ vw,
-                                  double* __restrict__ pos, int64_t pstride, double* __restrict__ q,
-                                  int* __restrict__ id, int* __restrict__ sp,
-                                  int* __restrict__ flags) {
-    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= n) return;
+__device__ __forceinline__ void update_one(const GridDev& g, const DryDev& Dd, int gi,
+                                           const double4* __restrict__ sxyzq,
+                                           const int* __restrict__ sid, const int* __restrict__ ssp,
+                                           const double* __restrict__ fp, int64_t fstride,
+                                           const double* __restrict__ vw, double* __restrict__ pos,
+                                           int64_t pstride, double* __restrict__ q,
+                                           int* __restrict__ id, int* __restrict__ sp,
+                                           int* __restrict__ flags) {
     const double4 me = sxyzq[gi];
     const int sp_in = ssp[gi];
     const int idi = sid[gi];
@@ -477,6 +529,78 @@ __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __
     q[gi] = me.w;
     id[gi] = idi;
     sp[gi] = sp_in;
+}
+
+__global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
+                                  const int* __restrict__ sid, const int* __restrict__ ssp,
+                                  const double* __restrict__ fp, int64_t fstride,
+                                  const double* __restrict__ vw,
+                                  double* __restrict__ pos, int64_t pstride, double* __restrict__ q,
+                                  int* __restrict__ id, int* __restrict__ sp,
+                                  int* __restrict__ flags) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n) return;
+    update_one(g, Dd, gi, sxyzq, sid, ssp, fp, fstride, vw, pos, pstride, q, id, sp, flags);
+}
+
+// Batched: each ion's channel supplies its grid, noise key and mobility fit; the step
+// index is read from device memory (it advances with captured-graph replays).
+__global__ void dry_update_batch_kernel(const RepDev* __restrict__ reps,
+                                        const int* __restrict__ ion_rep, DryDev Dd,
+                                        const uint64_t* __restrict__ step, int n,
+                                        const double4* __restrict__ sxyzq,
+                                        const int* __restrict__ sid, const int* __restrict__ ssp,
+                                        const double* __restrict__ fp, double* __restrict__ pos,
+                                        double* __restrict__ q, int* __restrict__ id,
+                                        int* __restrict__ sp, int* __restrict__ flags) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n) return;
+    const RepDev& R = reps[ion_rep[gi]];
+    Dd.seed = R.seed;
+    Dd.coef = R.coef;
+    Dd.step = *step;
+    update_one(R.g, Dd, gi, sxyzq, sid, ssp, fp, n, nullptr, pos, n, q, id, sp, flags);
+}
+
+__global__ void step_advance_kernel(uint64_t* step) { *step += 1; }
+__global__ void step_set_kernel(uint64_t* step, uint64_t v) { *step = v; }
+
+int batch_near(Batch* b, hipStream_t s) {
+    const int n = (int)b->n_tot;
+    if (n == 0) return DISCOS_OK;
+    const NearDev P = near_of_h(b->h, &b->p);
+    const int T = b->cfg.ion_block;
+    near_list_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
+                                                         b->bin_start, b->nlist, b->ncount);
+    near_eval_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
+                                                         b->ssp, b->bin_start, b->nlist, b->ncount,
+                                                         b->fp, b->flags);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s) {
+    const int n = (int)b->n_tot;
+    if (n == 0) return DISCOS_OK;
+    DryDev Dd;
+    Dd.nsp = b->p.nspecies;
+    Dd.kT = b->p.kT;
+    Dd.eta = b->p.eta;
+    Dd.dt = b->p.dt;
+    Dd.radius = b->p.radius;
+    Dd.coef = nullptr;
+    Dd.seed = 0;
+    Dd.step = 0;
+    const int T = b->cfg.ion_block;
+    dry_update_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, Dd, b->step_d, n,
+                                                          b->sxyzq, b->sid, b->ssp, b->fp, pos, q, id,
+                                                          sp, b->flags);
+    step_advance_kernel<<<1, 1, 0, s>>>(b->step_d);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int batch_set_step(Batch* b, uint64_t v, hipStream_t s) {
+    step_set_kernel<<<1, 1, 0, s>>>(b->step_d, v);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,

@@ -149,17 +149,12 @@ fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int mc,
 // Tridiagonal solve along z for every in-plane mode (one thread per mode).
 // Rows (scaled by h^2 / eps): -x_{k-1} + (2 + kappa^2 h^2) x_k - x_{k+1} = r_k, with
 // the ghost rule folded into the end rows (diag - s_lo, diag - s_hi).
-__global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ cp, int nx, int ny,
-                              int nz, double scale, double s_lo, double s_hi, int singular,
-                              int* __restrict__ flags) {
-    const int nxh = nx / 2 + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nmode = nxh * ny;
-    if (t >= nmode) return;
-    const int m = t % nxh, j = t / nxh;
-    const size_t st = (size_t)nmode;
-    double2* col = spec + t;
-    double* cpc = cp + t;
+// Mode (m, j) of a grid with nx, ny, nz: col and cpc point at its level-0 entries,
+// levels st apart.
+__device__ __forceinline__ void zsolve_mode(double2* __restrict__ col, double* __restrict__ cpc,
+                                            size_t st, int m, int j, int nx, int ny, int nz,
+                                            double scale, double s_lo, double s_hi, int singular,
+                                            int* __restrict__ flags) {
     if (singular && m == 0 && j == 0) {
         // kappa = 0 with both walls Neumann: compatibility (neutrality), mean removal
         // (the projection onto the range), phi_0 pinned to 0, rows 1 .. nz-1 solved,
@@ -237,6 +232,37 @@ __global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ c
     }
 }
 
+__global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ cp, int nx, int ny,
+                              int nz, double scale, double s_lo, double s_hi, int singular,
+                              int* __restrict__ flags) {
+    const int nxh = nx / 2 + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nmode = nxh * ny;
+    if (t >= nmode) return;
+    zsolve_mode(spec + t, cp + t, (size_t)nmode, t % nxh, t / nxh, nx, ny, nz, scale, s_lo, s_hi,
+                singular, flags);
+}
+
+// Batched: one thread per mode of every channel; mode_off is the prefix of the
+// channels' mode counts (in mode_rep order).
+__global__ void zsolve_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ mode_off,
+                                    const int* __restrict__ mode_rep, int nrep, int64_t nmode_tot,
+                                    double2* __restrict__ spec, double* __restrict__ cp,
+                                    int* __restrict__ flags) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nmode_tot) return;
+    int lo = 0, hi = nrep - 1;  // last slot with mode_off[slot] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mode_off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const RepDev& R = reps[mode_rep[lo]];
+    const int tl = (int)(t - mode_off[lo]);
+    const int nxh = R.g.nxh;
+    zsolve_mode(spec + R.spec_off + tl, cp + R.spec_off + tl, (size_t)R.nmode, tl % nxh, tl / nxh,
+                R.g.nx, R.g.ny, R.g.nz, R.scale, R.s_lo, R.s_hi, R.singular, flags);
+}
+
 static int ilog2(int n) {
     int l = 0;
     while ((1 << l) < n) ++l;
@@ -304,6 +330,36 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(c->spec, phi, nx, ilog2(nx),
                                                                         npairs, ppb, c->tw_x);
     if (mark_base >= 0) stage_mark(c, mark_base + 4, s);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+// Poisson for every channel: x- and y-FFTs per size class (a class's grids and spectra
+// are contiguous, so its rows and levels form single ranges), one z-solve launch.
+int batch_poisson(Batch* b, hipStream_t s) {
+    for (const BatchClass& k : b->classes) {
+        const int nxh = k.nx / 2 + 1;
+        const int ppb = std::max(1, 2048 / k.nx);
+        const int npairs = k.rows / 2;
+        fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * k.nx * sizeof(double2), s>>>(
+            b->rho + k.cell_off, b->spec + k.spec_off, k.nx, ilog2(k.nx), npairs, ppb, k.tw_x);
+        const int mc = std::max(1, std::min(16, 2048 / k.ny));
+        dim3 gy((nxh + mc - 1) / mc, k.levels);
+        fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * k.ny * sizeof(double2), s>>>(
+            b->spec + k.spec_off, nxh, k.ny, ilog2(k.ny), mc, k.tw_y, 0);
+    }
+    zsolve_batch_kernel<<<(int)((b->nmode_tot + 63) / 64), 64, 0, s>>>(
+        b->reps_d, b->mode_off, b->mode_rep, b->R, b->nmode_tot, b->spec, b->cprime, b->flags);
+    for (const BatchClass& k : b->classes) {
+        const int nxh = k.nx / 2 + 1;
+        const int mc = std::max(1, std::min(16, 2048 / k.ny));
+        dim3 gy((nxh + mc - 1) / mc, k.levels);
+        fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * k.ny * sizeof(double2), s>>>(
+            b->spec + k.spec_off, nxh, k.ny, ilog2(k.ny), mc, k.tw_y, 1);
+        const int ppb = std::max(1, 2048 / k.nx);
+        const int npairs = k.rows / 2;
+        fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * k.nx * sizeof(double2), s>>>(
+            b->spec + k.spec_off, b->phi + k.cell_off, k.nx, ilog2(k.nx), npairs, ppb, k.tw_x);
+    }
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

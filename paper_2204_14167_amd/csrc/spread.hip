@@ -29,14 +29,16 @@ __device__ __forceinline__ int find_range(const int* rpre, int nr, int f) {
     return lo;
 }
 
-__global__ void __launch_bounds__(SP_THREADS)
-spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __restrict__ bin_start, double sign_lo, double sign_hi,
-                     int add_bc, WallDev wall, double* __restrict__ out) {
-    __shared__ double acc[SP_TX * SP_TY * SP_TZ];
-    __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
-    const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
-    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * SP_TZ;
-    const int tz = min(SP_TZ, g.nz - z0);
+// One tile [x0, x0 + T) x [y0, y0 + T) x [z0, z0 + T) (clipped to the grid): gather the
+// ions of the tile and its halo, accumulate in LDS, store once.  acc holds T^3 doubles.
+template <int T>
+__device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __restrict__ sxyzq,
+                                            const int* __restrict__ bin_start, double sign_lo,
+                                            double sign_hi, int add_bc, const WallDev& wall,
+                                            double* __restrict__ out, int x0, int y0, int z0,
+                                            double* acc, int* rstart, int* rpre, int* scan) {
+    const int tx = min(T, g.nx), ty = min(T, g.ny);
+    const int tz = min(T, g.nz - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
     const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
@@ -102,6 +104,41 @@ spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __
     }
 }
 
+__global__ void __launch_bounds__(SP_THREADS)
+spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __restrict__ bin_start,
+                     double sign_lo, double sign_hi, int add_bc, WallDev wall,
+                     double* __restrict__ out) {
+    __shared__ double acc[SP_TX * SP_TY * SP_TZ];
+    __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
+    const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
+    spread_tile<SP_TX>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, blockIdx.x * tx,
+                       blockIdx.y * ty, blockIdx.z * SP_TZ, acc, rstart, rpre, scan);
+}
+
+// Batched: a persistent grid walks the (channel, tile) tasks; each channel's bins,
+// cells and walls come from its descriptor.  The tile index runs x fastest over the
+// channel's (nx / tx) x (ny / ty) x ceil(nz / T) tiles.
+template <int T>
+__global__ void __launch_bounds__(SP_THREADS)
+spread_charge_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__ tasks,
+                           int ntasks, const double4* __restrict__ sxyzq,
+                           const int* __restrict__ bin_start, double* __restrict__ out) {
+    __shared__ double acc[T * T * T];
+    __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const int2 task = tasks[t];
+        const RepDev& R = reps[task.x];
+        const GridDev g = R.g;
+        const int tx = min(T, g.nx), ty = min(T, g.ny);
+        const int ntx = g.nx / tx, nty = g.ny / ty;
+        const int k = task.y;
+        spread_tile<T>(g, sxyzq, bin_start + R.bin_off, R.s_lo, R.s_hi, 1, R.w, out + R.cell_off,
+                       (k % ntx) * tx, ((k / ntx) % nty) * ty, (k / (ntx * nty)) * T, acc, rstart,
+                       rpre, scan);
+        __syncthreads();
+    }
+}
+
 int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out, hipStream_t s) {
     const GridDev& g = c->gd;
     const int tx = std::min(SP_TX, g.nx), ty = std::min(SP_TY, g.ny);
@@ -110,6 +147,20 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
     const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sxyzq, c->bin_start,
                                                      s_lo, s_hi, add_bc, wall_of(p), out);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+int batch_spread(Batch* b, hipStream_t s) {
+    const int v = b->cfg.spread_t == 8 ? 0 : 1;
+    const int nt = b->ntasks[0][v];
+    if (nt == 0) return DISCOS_OK;
+    const int nb = b->cfg.spread_blocks > 0 ? std::min(nt, b->cfg.spread_blocks) : nt;
+    if (v == 0)
+        spread_charge_batch_kernel<8><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][0], nt,
+                                                               b->sxyzq, b->bin_start, b->rho);
+    else
+        spread_charge_batch_kernel<16><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][1], nt,
+                                                                b->sxyzq, b->bin_start, b->rho);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

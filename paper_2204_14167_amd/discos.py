@@ -98,16 +98,31 @@ def lib():
         L.discos_energy_flux.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp, vp]
         L.discos_energy_flux_backward.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp,
                                                   vp, vp, vp, vp, vp, vp]
+        L.discos_batch_create.argtypes = [ctypes.POINTER(DiscosReplica), i32, ctypes.c_double,
+                                          ctypes.POINTER(DiscosParams), ctypes.POINTER(vp)]
+        L.discos_batch_destroy.argtypes = [vp]
+        L.discos_batch_step.argtypes = [vp, vp, vp, vp, vp, u64, ctypes.c_uint32, vp]
+        L.discos_batch_tune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+        L.discos_batch_check.argtypes = [vp]
+        L.discos_batch_last_error.argtypes = [vp]
+        L.discos_batch_last_error.restype = ctypes.c_char_p
         L.discos_last_error.argtypes = [vp]
         L.discos_last_error.restype = ctypes.c_char_p
         for name in ("discos_create", "discos_destroy", "discos_spread", "discos_solve_poisson",
                      "discos_solve_stokes",
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
                      "discos_profile", "discos_profile_read", "discos_energy_flux",
-                     "discos_energy_flux_backward"):
+                     "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
+                     "discos_batch_step", "discos_batch_tune", "discos_batch_check"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+class DiscosReplica(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("bc_value", ctypes.c_double * 2),
+                ("seed", ctypes.c_uint64), ("mob_coef", ctypes.c_void_p)]
 
 
 class DiscosError(RuntimeError):
@@ -333,3 +348,70 @@ class Context:
     def check(self):
         """Synchronise and raise on a sticky device-side error."""
         self._rc(lib().discos_check(self.handle))
+
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """A batch of independent channels (library discos_batch).  `reps` is a list of
+    dicts with nx, ny, nz, n, bc_values (two scalars), seed and optionally mob_coef
+    (a [nspecies, 2, 7] array); `params` the shared physics (keys of make_params)."""
+
+    def __init__(self, reps, h, params, device="cuda"):
+        self._keep = []
+        p = dict(params)
+        p["bc_values"] = (None, None)
+        self.params = Params(p, (reps[0]["nx"], reps[0]["ny"]), device)
+        arr = (DiscosReplica * len(reps))()
+        coefs = {}
+        for k, r in enumerate(reps):
+            arr[k].nx, arr[k].ny, arr[k].nz = int(r["nx"]), int(r["ny"]), int(r["nz"])
+            arr[k].n = int(r["n"])
+            arr[k].bc_value[0] = float(r["bc_values"][0])
+            arr[k].bc_value[1] = float(r["bc_values"][1])
+            arr[k].seed = int(r["seed"])
+            c = r.get("mob_coef")
+            if c is not None:
+                key = np.asarray(c, dtype=np.float64).tobytes()
+                if key not in coefs:
+                    coefs[key] = _f64(c, device)
+                arr[k].mob_coef = coefs[key].data_ptr()
+        self._keep += list(coefs.values())
+        self.offsets = np.concatenate([[0], np.cumsum([int(r["n"]) for r in reps])])
+        h_ = ctypes.c_void_p()
+        rc = lib().discos_batch_create(arr, len(reps), float(h), ctypes.byref(self.params.struct),
+                                       ctypes.byref(h_))
+        if rc != OK:
+            raise DiscosError(rc, "discos_batch_create failed")
+        self.handle = h_
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().discos_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc):
+        if rc != OK:
+            raise DiscosError(rc, lib().discos_batch_last_error(self.handle).decode())
+
+    def step(self, pos, q, ids, species, step, graph=False):
+        self._rc(lib().discos_batch_step(self.handle, _ptr(pos), _ptr(q), _ptr(ids), _ptr(species),
+                                         int(step), BATCH_GRAPH if graph else 0, _stream()))
+
+    def tune(self, pos, q, ids, species):
+        cfg = (ctypes.c_int32 * 5)()
+        self._rc(lib().discos_batch_tune(self.handle, _ptr(pos), _ptr(q), _ptr(ids), _ptr(species),
+                                         cfg, _stream()))
+        return dict(spread_tile=cfg[0], spread_blocks=cfg[1], interp_tile=cfg[2],
+                    interp_blocks=cfg[3], ion_block=cfg[4])
+
+    def check(self):
+        self._rc(lib().discos_batch_check(self.handle))
+

@@ -146,3 +146,40 @@ def random_ions(nx, ny, nz, n, seed, h=1.0, zmin=0.0, zmax=None, charge="pm"):
     else:
         q = rng.normal(size=n)
     return pos, q
+
+
+def make_batch(count=512, seed=None):
+    """Independent channels for the batched step: nx, ny drawn from {16, 32, 64}, nz
+    from {32, 64}, ion counts log-uniform on [64, 4096] (even: half +1, half -1), a
+    grounded top wall and a bottom wall potential uniform in [-2, 2] kT/e, one noise
+    key per channel.  Returns (channels, pos [3, N], q, ids, species) with the ions of
+    channel r at entries off_r .. off_r + n_r - 1 and ids 0 .. n_r - 1 per channel."""
+    rng = np.random.default_rng(MASTER_SEED + 4 if seed is None else seed)
+    reps, parts = [], []
+    for r in range(count):
+        nx = int(rng.choice([16, 32, 64]))
+        ny = int(rng.choice([16, 32, 64]))
+        nz = int(rng.choice([32, 64]))
+        n = int(round(np.exp(rng.uniform(np.log(64.0), np.log(4096.0)))))
+        n -= n % 2
+        phi_lo = float(rng.uniform(-2.0, 2.0))
+        w = Workload(f"channel_{r}", nx, ny, nz, n, (DIRICHLET, DIRICHLET), (phi_lo, 0.0),
+                     seed=int(rng.integers(1, 2**62)))
+        pos, q, ids, species = make_ions(w)
+        reps.append(dict(nx=nx, ny=ny, nz=nz, n=n, bc_values=(phi_lo, 0.0), seed=w.seed + 1000,
+                         workload=w))
+        parts.append((pos, q, ids, species))
+    pos = np.concatenate([a[0] for a in parts], axis=1) if parts else np.zeros((3, 0))
+    q = np.concatenate([a[1] for a in parts])
+    ids = np.concatenate([a[2] for a in parts]).astype(np.int32)
+    species = np.concatenate([a[3] for a in parts]).astype(np.int32)
+    return reps, pos, q, ids, species
+
+
+def batch_channel_params(rep):
+    """Parameter dict of one channel of a batch (the same keys as make_params)."""
+    w = rep["workload"]
+    p = make_params(w)
+    p["seed"] = rep["seed"]
+    return p
+

@@ -61,7 +61,8 @@ def _c_layout(struct, members):
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
 @pytest.mark.parametrize("cls,name", [("DiscosParams", "discos_params"), ("DiscosIons", "discos_ions"),
-                                      ("DiscosGrid", "discos_grid")])
+                                      ("DiscosGrid", "discos_grid"),
+                                      ("DiscosReplica", "discos_replica")])
 def test_ctypes_layout_matches_header(cls, name):
     st = getattr(discos, cls)
     members = [f[0] for f in st._fields_]
