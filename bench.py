@@ -211,6 +211,58 @@ def adjoint_timing(ctx, dp, dpos, dq, steps):
             "gradients": "dU, dQ w.r.t. positions, charges, wall fields, E_ext"}
 
 
+def batch_timing(steps, seq_steps=3):
+    """The 512-channel batch (dry steps, uneven grids 16x16x32 .. 64x64x64 and 64 .. 4096
+    ions): ion-timesteps/s as one captured graph, as eager batched launches, and with
+    the same channels stepped one by one through single-channel contexts."""
+    import torch
+    from paper_2204_14167_amd import discos, workloads
+    reps, pos, q, ids, sp = workloads.make_batch(512)
+    for r in reps:
+        r["mob_coef"] = workloads.batch_channel_params(r)["mob_coef"]
+    b = discos.Batch(reps, 1.0, workloads.batch_channel_params(reps[0]))
+    arr = [torch.from_numpy(a.copy()).cuda() for a in (pos, q, ids, sp)]
+    cfg = b.tune(*arr)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    b.step(*arr, step=0, graph=True)
+    b.step(*arr, step=1)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for k in range(steps):
+        b.step(*arr, step=2 + k, graph=True)
+    ev[1].record()
+    for k in range(steps):
+        b.step(*arr, step=2 + steps + k)
+    ev[2].record()
+    torch.cuda.synchronize()
+    b.check()
+    t_graph = ev[0].elapsed_time(ev[1]) / steps
+    t_eager = ev[1].elapsed_time(ev[2]) / steps
+    # the same channels one by one (one context per channel, discos_step each)
+    ctxs = []
+    for r, rep in enumerate(reps):
+        w = rep["workload"]
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        c = discos.Context(w.nx, w.ny, w.nz, w.h, w.n)
+        ctxs.append((c, c.params(workloads.batch_channel_params(rep)),
+                     [t[..., lo:hi].contiguous() if t.dim() == 2 else t[lo:hi].clone() for t in arr]))
+    for c, prm, a in ctxs:
+        c.step(*a, prm, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(seq_steps):
+        for c, prm, a in ctxs:
+            c.step(*a, prm, 1 + k)
+    torch.cuda.synchronize()
+    t_seq = 1e3 * (time.perf_counter() - t0) / seq_steps
+    n = pos.shape[1]
+    return {"channels": len(reps), "ions": int(n), "cells": int(sum(r["nx"] * r["ny"] * r["nz"] for r in reps)),
+            "graph_ms_per_step": t_graph, "eager_ms_per_step": t_eager,
+            "one_by_one_ms_per_step": t_seq,
+            "ion_timesteps_per_s_graph": n / (t_graph * 1e-3),
+            "speedup_vs_one_by_one": t_seq / t_graph, "tuned": cfg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +270,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="steps of the 512-channel batch (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -264,6 +318,7 @@ def main():
     value = w.n * args.steps / elapsed
 
     adj = adjoint_timing(ctx, dp, dpos, dq, args.adjoint_steps) if args.adjoint_steps > 0 else None
+    batched = batch_timing(args.batch_steps) if args.batch_steps > 0 else None
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -329,6 +384,7 @@ def main():
         "stages": per_stage,
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "adjoint": adj,
+        "batched": batched,
         "cpu_baseline": cpu,
         "device_status": "; ".join(status) if status else "ok",
     }

@@ -140,7 +140,7 @@ def _stream():
 
 
 def _f64(a, device):
-    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+    return torch.as_tensor(np.array(a, dtype=np.float64, copy=True, order="C"), device=device)
 
 
 class Params:
