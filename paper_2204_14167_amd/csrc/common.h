@@ -48,6 +48,28 @@ struct RepDev {
     const double* coef;  // mobility fit [nspecies][2][7]
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each XCD has its
+// own L2.  xcd_block renumbers them (a bijection on [0, nb)) so that XCD x runs one
+// contiguous range of logical blocks: gathers whose neighbours sit in nearby blocks
+// (cell-list neighbours, tile halos) then find them in the L2 of the XCD that fetched
+// them.
+#define DISCOS_NXCD 8
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb / DISCOS_NXCD, r = nb % DISCOS_NXCD;
+    const int x = b % DISCOS_NXCD, k = b / DISCOS_NXCD;
+    return x * q + min(x, r) + k;
+}
+
+// (bx, by, bz) of the renumbered block of a 3-D grid.
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int L = xcd_block(lin, nb);
+    bx = L % gridDim.x;
+    by = (L / gridDim.x) % gridDim.y;
+    bz = L / (gridDim.x * gridDim.y);
+}
+
 __device__ __forceinline__ int wrapi(int n, int N) {
     int r = n % N;
     return r < 0 ? r + N : r;

@@ -186,9 +186,11 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
     __shared__ double tile[(IT_TZ + IT_H) * (IT_TY + IT_H) * (IT_TX + IT_H)];
     __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
     const int tx = min(IT_TX, g.nx), ty = min(IT_TY, g.ny);
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);
     interp_tile<IT_TX, IT_TY, IT_TZ>(g, w, op, sxyzq, bin_start, perm, phi, ex0, ex1, ex2, out, stride,
-                                     scatter, flags, blockIdx.x * tx, blockIdx.y * ty,
-                                     blockIdx.z * IT_TZ, tile, rstart, rpre, scan);
+                                     scatter, flags, bx * tx, by * ty, bz * IT_TZ, tile, rstart, rpre,
+                                     scan);
 }
 
 // Batched: forces q (E^P + E_ext) of every channel's ions, in cell-list order; the

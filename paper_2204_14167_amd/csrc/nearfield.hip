@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256)
 near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
                  const int* __restrict__ bin_start, int* __restrict__ list,
                  int* __restrict__ count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     near_list_one(g, P, i, n, sxyzq, bin_start, list, count);
 }
@@ -363,7 +363,7 @@ near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
     for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
     __syncthreads();
     P.tab = tab;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 me = sxyzq[i];
     if (!pos_ok(g, me.x, me.y, me.z)) return;

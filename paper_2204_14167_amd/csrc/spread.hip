@@ -111,8 +111,10 @@ spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __
     __shared__ double acc[SP_TX * SP_TY * SP_TZ];
     __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
     const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
-    spread_tile<SP_TX>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, blockIdx.x * tx,
-                       blockIdx.y * ty, blockIdx.z * SP_TZ, acc, rstart, rpre, scan);
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);
+    spread_tile<SP_TX>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, bx * tx, by * ty,
+                       bz * SP_TZ, acc, rstart, rpre, scan);
 }
 
 // Batched: a persistent grid walks the (channel, tile) tasks; each channel's bins,
