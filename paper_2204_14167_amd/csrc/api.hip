@@ -219,6 +219,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hmid = carve<double4>(hc, nm);
         c->hydro = 1;
     }
+    c->zg_key = -1;
     c->last_stream = nullptr;
     c->err = "";
     c->profile = 0;

@@ -27,7 +27,8 @@ struct Ctx {
     // grid work arrays
     double *rho, *phi;
     double2* spec;   // half spectrum [nz][ny][nx/2+1]
-    double* cprime;  // Thomas coefficients [nz][nmode]
+    double* cprime;  // z-solve pivots [nz][nmode] (or Thomas scratch when nz > 128)
+    int zg_key;      // wall types the pivots in cprime were computed for (-1: none)
     double* fp;      // [3][n_max] per-ion forces in cell-list order
     int* nlist;      // near-field neighbour lists, [64][n_max] (entry-major)
     int* ncount;     // [n_max] list lengths

@@ -15,6 +15,14 @@ __device__ __forceinline__ int bitrev(int n, int logN) {
     return (int)(__brev((unsigned)n) >> (32 - logN));
 }
 
+// 1/a to full FP64 accuracy: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    y = fma(fma(-a, y, 1.0), y, y);
+    y = fma(fma(-a, y, 1.0), y, y);
+    return y;
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -206,33 +214,61 @@ __device__ __forceinline__ void zsolve_mode(double2* __restrict__ col, double* _
     }
     const double sx = sin(M_PI * m / nx), sy = sin(M_PI * j / ny);
     const double b = 2.0 + 4.0 * (sx * sx + sy * sy);
+    // Forward sweep.  Whole windows of ZW levels are fetched before use (no bounds test
+    // inside a window, so all ZW loads are in flight together: a thread per mode leaves
+    // few wavefronts, and only outstanding loads hide the memory latency); the last
+    // nz % ZW levels go one by one.  One reciprocal per level (hardware estimate + two
+    // Newton steps).
+    constexpr int ZW = 16;
     double c_prev = 0.0;
     double2 d_prev = make_double2(0.0, 0.0);
-    for (int k = 0; k < nz; ++k) {
-        const double2 r0 = col[k * st];
-        const double2 r = make_double2(r0.x * scale, r0.y * scale);
+    auto fwd = [&](int k, double2 rk) {
         double diag = b;
         if (k == 0) diag -= s_lo;
         if (k == nz - 1) diag -= s_hi;
         const double den = (k == 0) ? diag : diag + c_prev;
-        const double c = -1.0 / den;
-        const double2 d = (k == 0) ? make_double2(r.x / den, r.y / den)
-                                   : make_double2((r.x + d_prev.x) / den, (r.y + d_prev.y) / den);
-        cpc[k * st] = c;
-        col[k * st] = d;
-        c_prev = c;
+        const double inv = recip(den);
+        const double2 d = make_double2((rk.x * scale + d_prev.x) * inv, (rk.y * scale + d_prev.y) * inv);
+        cpc[(size_t)k * st] = -inv;
+        col[(size_t)k * st] = d;
+        c_prev = -inv;
         d_prev = d;
+    };
+    int k0 = 0;
+    for (; k0 + ZW <= nz; k0 += ZW) {
+        double2 rb[ZW];
+#pragma unroll
+        for (int u = 0; u < ZW; ++u) rb[u] = col[(size_t)(k0 + u) * st];
+#pragma unroll
+        for (int u = 0; u < ZW; ++u) fwd(k0 + u, rb[u]);
     }
+    for (; k0 < nz; ++k0) fwd(k0, col[(size_t)k0 * st]);
+    // back substitution over levels nz-2 .. 0, likewise by whole windows
     double2 x = d_prev;
-    for (int k = nz - 2; k >= 0; --k) {
-        const double2 d = col[k * st];
-        const double c = cpc[k * st];
+    int k1 = nz - 2;
+    for (; k1 - ZW + 1 >= 0; k1 -= ZW) {
+        double2 db[ZW];
+        double cb[ZW];
+#pragma unroll
+        for (int u = 0; u < ZW; ++u) {
+            db[u] = col[(size_t)(k1 - u) * st];
+            cb[u] = cpc[(size_t)(k1 - u) * st];
+        }
+#pragma unroll
+        for (int u = 0; u < ZW; ++u) {
+            x = make_double2(db[u].x - cb[u] * x.x, db[u].y - cb[u] * x.y);
+            col[(size_t)(k1 - u) * st] = x;
+        }
+    }
+    for (; k1 >= 0; --k1) {
+        const double2 d = col[(size_t)k1 * st];
+        const double c = cpc[(size_t)k1 * st];
         x = make_double2(d.x - c * x.x, d.y - c * x.y);
-        col[k * st] = x;
+        col[(size_t)k1 * st] = x;
     }
 }
 
-__global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ cp, int nx, int ny,
+__global__ void __launch_bounds__(64) zsolve_kernel(double2* __restrict__ spec, double* __restrict__ cp, int nx, int ny,
                               int nz, double scale, double s_lo, double s_hi, int singular,
                               int* __restrict__ flags) {
     const int nxh = nx / 2 + 1;
@@ -245,7 +281,7 @@ __global__ void zsolve_kernel(double2* __restrict__ spec, double* __restrict__ c
 
 // Batched: one thread per mode of every channel; mode_off is the prefix of the
 // channels' mode counts (in mode_rep order).
-__global__ void zsolve_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ mode_off,
+__global__ void __launch_bounds__(64) zsolve_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ mode_off,
                                     const int* __restrict__ mode_rep, int nrep, int64_t nmode_tot,
                                     double2* __restrict__ spec, double* __restrict__ cp,
                                     int* __restrict__ flags) {
@@ -261,6 +297,193 @@ __global__ void zsolve_batch_kernel(const RepDev* __restrict__ reps, const int* 
     const int nxh = R.g.nxh;
     zsolve_mode(spec + R.spec_off + tl, cp + R.spec_off + tl, (size_t)R.nmode, tl % nxh, tl / nxh,
                 R.g.nx, R.g.ny, R.g.nz, R.scale, R.s_lo, R.s_hi, R.singular, flags);
+}
+
+// Pivots of the per-mode Thomas factorisation, g_k = 1 / (diag_k - g_{k-1}) (the
+// reciprocal pivots; RHS independent), for every mode: [nz][nmode].  The singular
+// kappa = 0 mode of an all-Neumann problem is solved separately and gets none.
+__global__ void __launch_bounds__(64) zpivot_kernel(double* __restrict__ zg, int nx, int ny, int nz,
+                                                   double s_lo, double s_hi, int singular) {
+    const int nxh = nx / 2 + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nmode = nxh * ny;
+    if (t >= nmode) return;
+    const int m = t % nxh, j = t / nxh;
+    const double sx = sin(M_PI * m / nx), sy = sin(M_PI * j / ny);
+    const double b = 2.0 + 4.0 * (sx * sx + sy * sy);
+    double gprev = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        double diag = b;
+        if (k == 0) diag -= s_lo;
+        if (k == nz - 1) diag -= s_hi;
+        const double gk = (singular && t == 0) ? 0.0 : recip(diag - gprev);
+        zg[(size_t)k * nmode + t] = gk;
+        gprev = gk;
+    }
+}
+
+// Solve along z with the pivots g: forward d_k = g_k (r_k + d_{k-1}), back
+// x_k = d_k + g_k x_{k+1} (x_nz = 0) -- two first-order linear recurrences.  Four lanes
+// share a mode, each holding one segment of L levels in registers: a segment's local
+// recurrence gives an affine map (product of its g, local end value), a scan of those
+// maps over the four lanes gives each segment's carry, and a second pass applies it.
+// Lane l of a wavefront: mode 16 w + (l & 15), segment l >> 4, so one load instruction
+// reads 16 consecutive modes at four levels.
+template <int L>
+__global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ spec,
+                                                        const double* __restrict__ zg, int nmode,
+                                                        int nz, double scale, int skip0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ml = lane & 15, seg = lane >> 4;
+    const int t = (blockIdx.x * 4 + wave) * 16 + ml;
+    const bool valid = t < nmode && !(skip0 && t == 0);
+    const int tt = min(t, nmode - 1);
+    const int k0 = seg * L;
+    const int len = max(0, min(L, nz - k0));
+    double2 d[L];
+    double g[L];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        const size_t k = (size_t)min(k0 + u, nz - 1);
+        d[u] = spec[k * nmode + tt];
+        g[u] = zg[k * nmode + tt];
+    }
+    // forward, local (carry in = 0)
+    double2 dl = make_double2(0.0, 0.0);
+    double A = 1.0;
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        if (u < len) {
+            dl = make_double2(g[u] * (d[u].x * scale + dl.x), g[u] * (d[u].y * scale + dl.y));
+            A *= g[u];
+            d[u] = dl;
+        }
+    }
+    // carry into this segment: maps of the segments below, in order
+    double2 din = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int sp = 0; sp < 3; ++sp) {
+        const int src = ml + 16 * sp;
+        const double As = __shfl(A, src, 64);
+        const double bx = __shfl(dl.x, src, 64), by = __shfl(dl.y, src, 64);
+        if (seg > sp) din = make_double2(As * din.x + bx, As * din.y + by);
+    }
+    double p = 1.0;
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+        if (u < len) {
+            p *= g[u];
+            d[u] = make_double2(d[u].x + p * din.x, d[u].y + p * din.y);
+        }
+    }
+    // backward, local (x at the segment's top boundary = 0)
+    double2 xl = make_double2(0.0, 0.0);
+    double B = 1.0;
+#pragma unroll
+    for (int u = L - 1; u >= 0; --u) {
+        if (u < len) {
+            xl = make_double2(d[u].x + g[u] * xl.x, d[u].y + g[u] * xl.y);
+            B *= g[u];
+            d[u] = xl;
+        }
+    }
+    double2 xin = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int sp = 3; sp >= 1; --sp) {
+        const int src = ml + 16 * sp;
+        const double Bs = __shfl(B, src, 64);
+        const double bx = __shfl(xl.x, src, 64), by = __shfl(xl.y, src, 64);
+        if (seg < sp) xin = make_double2(Bs * xin.x + bx, Bs * xin.y + by);
+    }
+    double q = 1.0;
+#pragma unroll
+    for (int u = L - 1; u >= 0; --u) {
+        if (u < len) {
+            q *= g[u];
+            d[u] = make_double2(d[u].x + q * xin.x, d[u].y + q * xin.y);
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int u = 0; u < L; ++u)
+        if (u < len) spec[(size_t)(k0 + u) * nmode + t] = d[u];
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_incl_scan(double v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// The singular kappa = 0 mode of an all-Neumann problem, by one wavefront.  Its rows
+// (x_0 - x_1 = r_0, -x_{k-1} + 2 x_k - x_{k+1} = r_k, -x_{nz-2} + x_{nz-1} = r_{nz-1})
+// are solvable iff sum r = 0 (neutrality; flagged unless the caller asked for the
+// pseudo-inverse); with r' = r - mean(r) the differences are
+// x_{k+1} - x_k = -(r'_0 + ... + r'_k), so x is a double prefix sum, shifted to mean 0:
+// the minimum-norm solution.  Levels are taken 64 at a time with running carries.
+__global__ void __launch_bounds__(64) zsolve_mode0_kernel(double2* __restrict__ spec, int nmode, int nz,
+                                                         double scale, int singular,
+                                                         int* __restrict__ flags) {
+    const int lane = threadIdx.x;
+    double sx = 0.0, sy = 0.0, ax = 0.0;
+    for (int k0 = 0; k0 < nz; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < nz) {
+            const double2 r = spec[(size_t)k * nmode];
+            sx += r.x;
+            sy += r.y;
+            ax += sqrt(r.x * r.x + r.y * r.y);
+        }
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    ax = wave_sum(ax);
+    if (lane == 0 && singular == 1 && sqrt(sx * sx + sy * sy) > 1e-10 * fmax(ax, 1e-300))
+        set_flag(flags, DISCOS_FLAG_NOT_NEUTRAL);
+    const double mx = sx / nz, my = sy / nz;
+    // pass 1: x_k (with x_0 = 0) = sum_{m<k} D_m, D_m = -S_m, S_m = r'_0 + .. + r'_m
+    double cSx = 0.0, cSy = 0.0, cXx = 0.0, cXy = 0.0, tx = 0.0, ty = 0.0;
+    for (int k0 = 0; k0 < nz; k0 += 64) {
+        const int k = k0 + lane;
+        double2 r = make_double2(0.0, 0.0);
+        if (k < nz) r = spec[(size_t)k * nmode];
+        const double rx = (k < nz) ? (r.x - mx) * scale : 0.0;
+        const double ry = (k < nz) ? (r.y - my) * scale : 0.0;
+        const double Sx = wave_incl_scan(rx) + cSx, Sy = wave_incl_scan(ry) + cSy;
+        // x_k = -(S_0 + .. + S_{k-1}): exclusive scan of S
+        const double Ix = wave_incl_scan(Sx), Iy = wave_incl_scan(Sy);
+        const double xx = -(Ix - Sx + cXx), xy = -(Iy - Sy + cXy);
+        if (k < nz) {
+            spec[(size_t)k * nmode] = make_double2(xx, xy);
+            tx += xx;
+            ty += xy;
+        }
+        cSx = __shfl(Sx, 63, 64);
+        cSy = __shfl(Sy, 63, 64);
+        cXx += __shfl(Ix, 63, 64);
+        cXy += __shfl(Iy, 63, 64);
+    }
+    // pass 2: mean zero
+    tx = wave_sum(tx) / nz;
+    ty = wave_sum(ty) / nz;
+    for (int k0 = 0; k0 < nz; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < nz) {
+            const double2 v = spec[(size_t)k * nmode];
+            spec[(size_t)k * nmode] = make_double2(v.x - tx, v.y - ty);
+        }
+    }
 }
 
 static int ilog2(int n) {
@@ -322,8 +545,27 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
                              ? (project ? 2 : 1)
                              : 0;
     const int nmode = nxh * ny;
-    zsolve_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->spec, c->cprime, nx, ny, nz, scale, s_lo, s_hi,
-                                                  singular, c->flags);
+    if (nz <= 128) {
+        // pivots once per wall-type pair (the buffer then holds them, not Thomas scratch)
+        const int key = p->bc_type[0] * 2 + p->bc_type[1];
+        if (c->zg_key != key) {
+            zpivot_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->cprime, nx, ny, nz, s_lo, s_hi, singular != 0);
+            c->zg_key = key;
+        }
+        const int L = (nz + 3) / 4;
+        const int nb = (nmode + 63) / 64;
+        if (L <= 8)
+            zsolve_seg_kernel<8><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
+        else if (L <= 16)
+            zsolve_seg_kernel<16><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
+        else
+            zsolve_seg_kernel<32><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
+        if (singular) zsolve_mode0_kernel<<<1, 64, 0, s>>>(c->spec, nmode, nz, scale, singular, c->flags);
+    } else {
+        c->zg_key = -1;
+        zsolve_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->spec, c->cprime, nx, ny, nz, scale, s_lo, s_hi,
+                                                      singular, c->flags);
+    }
     if (mark_base >= 0) stage_mark(c, mark_base + 2, s);
     fft_y_kernel<<<gy, FFT_THREADS, ldsy, s>>>(c->spec, nxh, ny, ilog2(ny), mc, c->tw_y, 1);
     if (mark_base >= 0) stage_mark(c, mark_base + 3, s);
