@@ -27,24 +27,66 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 DIT FFTs of `lines` lines of length N stored back to back in LDS,
-// input in bit-reversed order.  tw[k] = exp(-2 pi i k / N), k < N/2; `inv` conjugates.
+// In-place radix-2 DIT FFTs of `lines` lines of length N = 2^logN stored back to back in
+// LDS, input in bit-reversed order.  tw[k] = exp(-2 pi i k / N), k < N/2; `inv`
+// conjugates.  Stages are taken two at a time (radix 2^2): a thread loads the four
+// elements i, i+h, i+2h, i+3h of a group of 4h, applies stage s (pairs at distance h)
+// and stage s+1 (pairs at distance 2h) in registers and stores once -- the same
+// operations as two radix-2 stages, with half the LDS round trips and barriers.  An odd
+// logN ends with one radix-2 stage.  Index arithmetic is shifts and masks.
 __device__ void lds_fft(double2* a, int N, int logN, int lines, const double2* __restrict__ tw,
                         int inv) {
-    const int halfN = N >> 1;
-    const int nb = lines * halfN;
-    for (int s = 1; s <= logN; ++s) {
-        const int half = 1 << (s - 1);
-        const int tstride = N >> s;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int line = b / halfN;
-            const int bb = b - line * halfN;
-            const int grp = bb / half;
-            const int p = bb - grp * half;
-            const int i = line * N + grp * 2 * half + p;
+    const double sg = inv ? -1.0 : 1.0;
+    int s = 1;
+    if (logN >= 2) {
+        const int lq = logN - 2;  // log2(N / 4)
+        const int nq = lines << lq;
+        for (; s + 1 <= logN; s += 2) {
+            const int ls = s - 1;
+            const int h = 1 << ls;
+            for (int qd = threadIdx.x; qd < nq; qd += blockDim.x) {
+                const int line = qd >> lq;
+                const int qq = qd & ((1 << lq) - 1);
+                const int grp = qq >> ls;
+                const int p = qq & (h - 1);
+                const int i0 = (line << logN) + (grp << (s + 1)) + p;
+                double2 w1 = tw[p << (logN - s)];
+                double2 wa = tw[p << (logN - s - 1)];
+                double2 wb = tw[(p + h) << (logN - s - 1)];
+                w1.y *= sg;
+                wa.y *= sg;
+                wb.y *= sg;
+                const double2 x0 = a[i0], x1 = a[i0 + h], x2 = a[i0 + 2 * h], x3 = a[i0 + 3 * h];
+                // stage s
+                const double2 v1 = cmul(x1, w1), v3 = cmul(x3, w1);
+                const double2 b0 = make_double2(x0.x + v1.x, x0.y + v1.y);
+                const double2 b1 = make_double2(x0.x - v1.x, x0.y - v1.y);
+                const double2 b2 = make_double2(x2.x + v3.x, x2.y + v3.y);
+                const double2 b3 = make_double2(x2.x - v3.x, x2.y - v3.y);
+                // stage s + 1
+                const double2 c2 = cmul(b2, wa), c3 = cmul(b3, wb);
+                a[i0] = make_double2(b0.x + c2.x, b0.y + c2.y);
+                a[i0 + 2 * h] = make_double2(b0.x - c2.x, b0.y - c2.y);
+                a[i0 + h] = make_double2(b1.x + c3.x, b1.y + c3.y);
+                a[i0 + 3 * h] = make_double2(b1.x - c3.x, b1.y - c3.y);
+            }
+            __syncthreads();
+        }
+    }
+    if (s == logN) {  // one radix-2 stage left
+        const int lh = logN - 1;
+        const int nb = lines << lh;
+        const int ls = s - 1;
+        const int half = 1 << ls;
+        for (int bq = threadIdx.x; bq < nb; bq += blockDim.x) {
+            const int line = bq >> lh;
+            const int bb = bq & ((1 << lh) - 1);
+            const int grp = bb >> ls;
+            const int p = bb & (half - 1);
+            const int i = (line << logN) + (grp << s) + p;
             const int j = i + half;
-            double2 w = tw[p * tstride];
-            if (inv) w.y = -w.y;
+            double2 w = tw[p];
+            w.y *= sg;
             const double2 u = a[i];
             const double2 v = cmul(a[j], w);
             a[i] = make_double2(u.x + v.x, u.y + v.y);
@@ -65,7 +107,7 @@ fft_x_r2c_kernel(const double* __restrict__ in, double2* __restrict__ spec, int 
     const int nxh = nx / 2 + 1;
     const int p0 = blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, n = e - p * nx;
+        const int p = e >> logN, n = e & (nx - 1);
         const int pr = p0 + p;
         double2 v = make_double2(0.0, 0.0);
         if (pr < npairs) {
@@ -76,12 +118,23 @@ fft_x_r2c_kernel(const double* __restrict__ in, double2* __restrict__ spec, int 
     }
     __syncthreads();
     lds_fft(lds, nx, logN, ppb, tw, 0);
+    // e -> (p, m) with p = e / nxh through a float reciprocal (exact after one
+    // correction for e < 2^20) instead of an integer division
+    const float inv_nxh = 1.0f / (float)nxh;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
-        const int p = e / nxh, m = e - p * nxh;
+        int p = (int)((float)e * inv_nxh);
+        int m = e - p * nxh;
+        if (m < 0) {
+            --p;
+            m += nxh;
+        } else if (m >= nxh) {
+            ++p;
+            m -= nxh;
+        }
         const int pr = p0 + p;
         if (pr >= npairs) continue;
-        const double2 Z = lds[p * nx + (m % nx)];
-        const double2 Zr = lds[p * nx + ((nx - m) % nx)];
+        const double2 Z = lds[p * nx + (m & (nx - 1))];
+        const double2 Zr = lds[p * nx + ((nx - m) & (nx - 1))];
         // A = (Z + conj Zr) / 2, B = (Z - conj Zr) / (2i)
         const double2 A = make_double2(0.5 * (Z.x + Zr.x), 0.5 * (Z.y - Zr.y));
         const double2 B = make_double2(0.5 * (Z.y + Zr.y), -0.5 * (Z.x - Zr.x));
@@ -99,7 +152,7 @@ fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int
     const int nxh = nx / 2 + 1;
     const int p0 = blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, n = e - p * nx;
+        const int p = e >> logN, n = e & (nx - 1);
         const int pr = p0 + p;
         double2 z = make_double2(0.0, 0.0);
         if (pr < npairs) {
@@ -122,7 +175,7 @@ fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int
     __syncthreads();
     lds_fft(lds, nx, logN, ppb, tw, 1);
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, n = e - p * nx;
+        const int p = e >> logN, n = e & (nx - 1);
         const int pr = p0 + p;
         if (pr >= npairs) continue;
         const size_t r0 = 2 * (size_t)pr;
@@ -139,8 +192,9 @@ fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int mc,
     extern __shared__ double2 lds[];
     const int m0 = blockIdx.x * mc;
     const size_t kbase = (size_t)blockIdx.y * ny * nxh;
+    const int lmc = __builtin_ctz(mc);
     for (int e = threadIdx.x; e < mc * ny; e += blockDim.x) {
-        const int c = e % mc, j = e / mc;
+        const int c = e & (mc - 1), j = e >> lmc;
         const int m = m0 + c;
         lds[c * ny + bitrev(j, logN)] =
             (m < nxh) ? spec[kbase + (size_t)j * nxh + m] : make_double2(0.0, 0.0);
@@ -148,7 +202,7 @@ fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int mc,
     __syncthreads();
     lds_fft(lds, ny, logN, mc, tw, inv);
     for (int e = threadIdx.x; e < mc * ny; e += blockDim.x) {
-        const int c = e % mc, j = e / mc;
+        const int c = e & (mc - 1), j = e >> lmc;
         const int m = m0 + c;
         if (m < nxh) spec[kbase + (size_t)j * nxh + m] = lds[c * ny + j];
     }

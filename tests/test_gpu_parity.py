@@ -85,7 +85,8 @@ def test_spread_empty_and_capacity():
 
 
 @pytest.mark.parametrize("bc", BC_PAIRS)
-@pytest.mark.parametrize("shape", [(32, 32, 32), (8, 16, 5), (64, 8, 12), (256, 16, 4), (16, 128, 9)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (8, 16, 5), (64, 8, 12), (256, 16, 4), (16, 128, 9),
+                                   (16, 16, 61), (32, 16, 100), (8, 8, 127), (16, 8, 130)])
 def test_poisson(bc, shape):
     nx, ny, nz = shape
     log(f"poisson bc={bc} shape={shape}")
@@ -97,6 +98,22 @@ def test_poisson(bc, shape):
     ctx = _ctx(nx, ny, nz, 1, h=0.5)
     out = host(ctx.solve_poisson(dev(rhs), ctx.params(_params(bc, nx, ny))))
     assert rel_l2(out, ref) < 1e-12
+    ctx.check()
+
+
+def test_poisson_wall_types_change_on_one_context():
+    """The z-solve caches its pivots per wall-type pair: switching types on one context
+    must give each problem's own solution."""
+    nx, ny, nz = 16, 32, 40
+    ctx = _ctx(nx, ny, nz, 1, h=0.5)
+    grid = es.Grid(nx, ny, nz, 0.5)
+    for k, bc in enumerate([(D, D), (N, N), (D, N), (N, N), (D, D)]):
+        rhs = np.random.default_rng(k).normal(size=(nz, ny, nx))
+        if bc == (N, N):
+            rhs -= rhs.mean()
+        ref = es.solve_poisson(grid, EPS, bc, rhs)
+        out = host(ctx.solve_poisson(dev(rhs), ctx.params(_params(bc, nx, ny))))
+        assert rel_l2(out, ref) < 1e-12, bc
     ctx.check()
 
 
