@@ -104,6 +104,14 @@ __device__ __forceinline__ void peskin4(double s, int& i0, double w[4]) {
 // x-coordinate in cells, reduced to a bounded range before the int conversion
 // (positions may be anywhere on the periodic line).
 __device__ __forceinline__ double reduce_periodic(double x, double L) {
+    // fmod(x, L) is x on [0, L) and x - L on [L, 2L) exactly (Sterbenz), so the library
+    // call is needed only for far excursions
+    if (x >= 0.0) {
+        if (x < L) return x;
+        if (x < 2.0 * L) return x - L;
+    } else if (x >= -L) {
+        return x + L;
+    }
     double r = fmod(x, L);
     return r < 0.0 ? r + L : r;
 }
@@ -182,7 +190,13 @@ __device__ __forceinline__ int bin_of(const GridDev& g, double x, double y, doub
 
 // Periodic wrap into [0, L) (-0 and L map to 0).
 __device__ __forceinline__ double wrap_coord(double x, double L) {
-    double r = fmod(x, L);
+    double r;
+    if (x >= 0.0 && x < 2.0 * L)
+        r = x < L ? x : x - L;  // fmod(x, L) exactly
+    else if (x < 0.0 && x >= -L)
+        r = x;
+    else
+        r = fmod(x, L);
     if (r < 0.0) r += L;
     if (r >= L) r -= L;
     if (r == 0.0) r = 0.0;

@@ -52,15 +52,16 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
         if (!pos_ok(g, x, y, z)) continue;
         int ix0, iy0, iz0;
         double wx[4], wy[4], wz[4];
-        peskin4(reduce_periodic(x, g.Lx) * g.inv_h - 0.5, ix0, wx);
-        peskin4(reduce_periodic(y, g.Ly) * g.inv_h - 0.5, iy0, wy);
+        // x, y of the cell list are already reduced into [0, L]
+        peskin4(x * g.inv_h - 0.5, ix0, wx);
+        peskin4(y * g.inv_h - 0.5, iy0, wy);
         peskin4(z * g.inv_h - 0.5, iz0, wz);
         const double scale = a4.w * inv_h3;
         int lxs[4], lys[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) lxs[a] = wrapi(ix0 + a - x0, g.nx);
+        for (int a = 0; a < 4; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) lys[b] = wrapi(iy0 + b - y0, g.ny);
+        for (int b = 0; b < 4; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             int kz = iz0 + c;
