@@ -127,6 +127,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     const int64_t nspec = c->nmode * g.nz;
     size_t bytes = 0;
     bytes += carve_bytes(nm, sizeof(double4));         // sxyzq
+    bytes += carve_bytes(nm, sizeof(float4));          // sxyzf
     bytes += carve_bytes(3 * nm, sizeof(double));      // fp
     bytes += carve_bytes(64 * nm, sizeof(int));        // nlist
     bytes += carve_bytes(nm, sizeof(int));             // ncount
@@ -149,6 +150,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->pool_bytes = bytes;
     char* cur = static_cast<char*>(c->pool);
     c->sxyzq = carve<double4>(cur, nm);
+    c->sxyzf = carve<float4>(cur, nm);
     c->fp = carve<double>(cur, 3 * nm);
     c->nlist = carve<int>(cur, 64 * nm);
     c->ncount = carve<int>(cur, nm);

@@ -220,7 +220,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     const size_t n = (size_t)std::max<int64_t>(n_tot, 1);
     const size_t nblk = (size_t)(b->nbins_tot + 1023) / 1024 + 1;
     size_t bytes = 0;
-    bytes += carve_bytes(n, sizeof(double4));
+    bytes += carve_bytes(n, sizeof(double4)) + carve_bytes(n, sizeof(float4));
     bytes += 6 * carve_bytes(n, sizeof(int));  // sid ssp perm ion_bin ion_rank ion_rep
     bytes += carve_bytes(b->nbins_tot, sizeof(int)) + carve_bytes(b->nbins_tot + 1, sizeof(int));
     bytes += carve_bytes(nblk, sizeof(int));
@@ -241,6 +241,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     }
     char* cur = static_cast<char*>(b->pool);
     b->sxyzq = carve<double4>(cur, n);
+    b->sxyzf = carve<float4>(cur, n);
     b->sid = carve<int>(cur, n);
     b->ssp = carve<int>(cur, n);
     b->perm = carve<int>(cur, n);

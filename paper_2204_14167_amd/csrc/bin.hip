@@ -139,8 +139,8 @@ __global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
                                          const double* __restrict__ y, const double* __restrict__ z,
                                          const double* __restrict__ q, const int* __restrict__ id,
                                          const int* __restrict__ sp, double4* __restrict__ sxyzq,
-                                         int* __restrict__ sid, int* __restrict__ ssp,
-                                         int* __restrict__ perm) {
+                                         float4* __restrict__ sxyzf, int* __restrict__ sid,
+                                         int* __restrict__ ssp, int* __restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const GridDev& g = reps[ion_rep[i]].g;
@@ -151,6 +151,7 @@ __global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
         yi = reduce_periodic(yi, g.Ly);
     }
     sxyzq[d] = make_double4(xi, yi, z[i], q[i]);
+    sxyzf[d] = make_float4((float)xi, (float)yi, (float)z[i], 0.0f);
     sid[d] = id[i];
     ssp[d] = sp[i];
     perm[d] = i;
@@ -161,7 +162,7 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
                                    const double* __restrict__ x, const double* __restrict__ y,
                                    const double* __restrict__ z, const double* __restrict__ q,
                                    const int* __restrict__ id, const int* __restrict__ sp,
-                                   GridDev g, double4* __restrict__ sxyzq,
+                                   GridDev g, double4* __restrict__ sxyzq, float4* __restrict__ sxyzf,
                                    int* __restrict__ sid, int* __restrict__ ssp,
                                    int* __restrict__ perm, const double* __restrict__ w3,
                                    int64_t w3_stride, double* __restrict__ sw3,
@@ -175,6 +176,7 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
         yi = reduce_periodic(yi, g.Ly);
     }
     sxyzq[d] = make_double4(xi, yi, z[i], q ? q[i] : 0.0);
+    sxyzf[d] = make_float4((float)xi, (float)yi, (float)z[i], 0.0f);
     if (id) sid[d] = id[i];
     if (sp) ssp[d] = sp[i];
     if (w3) {
@@ -201,7 +203,7 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
     scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp, c->bin_start, n);
     if (n > 0)
         bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
-                                                         x, y, z, q, id, sp, g, c->sxyzq,
+                                                         x, y, z, q, id, sp, g, c->sxyzq, c->sxyzf,
                                                          c->sid, c->ssp, c->perm, w3, w3_stride,
                                                          c->fp, c->n_max);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
@@ -223,7 +225,7 @@ int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id,
     bin_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, b->ion_bin,
                                                            b->ion_rank, b->bin_start, pos, pos + n,
                                                            pos + 2 * (int64_t)n, q, id, sp, b->sxyzq,
-                                                           b->sid, b->ssp, b->perm);
+                                                           b->sxyzf, b->sid, b->ssp, b->perm);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

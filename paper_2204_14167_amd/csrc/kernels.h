@@ -21,6 +21,7 @@ struct Ctx {
     // sorted ion copies (cell-list order): (x, y, z, q) with x, y reduced into
     // [0, L], plus ids, species and the permutation back to caller order
     double4* sxyzq;
+    float4* sxyzf;   // the same positions in FP32: candidate filter of the neighbour lists
     int *sid, *ssp, *perm;
     int *ion_bin, *ion_rank;
     int *bin_count, *bin_start, *scan_tmp;
@@ -94,6 +95,7 @@ struct Batch {
     std::vector<BatchClass> classes;
     double* walls;                 // per-channel wall fields [2][ny][nx], back to back
     double4* sxyzq;
+    float4* sxyzf;
     int *sid, *ssp, *perm, *ion_bin, *ion_rank, *bin_count, *bin_start, *scan_tmp;
     double *rho, *phi, *cprime, *fp;
     double2* spec;

@@ -200,6 +200,7 @@ __device__ __forceinline__ double shift_of(int code, double L) {
 
 __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P, int i, int n,
                                               const double4* __restrict__ sxyzq,
+                                              const float4* __restrict__ sxyzf,
                                               const int* __restrict__ bin_start,
                                               int* __restrict__ list, int* __restrict__ count) {
     const double4 me = sxyzq[i];
@@ -216,6 +217,12 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
     int bx, by, bz;
     bin_of(g, xi, yi, zi, bx, by, bz);
     int4* chunks = reinterpret_cast<int4*>(list);  // chunk c of ion i at [c * n + i]
+    // Candidates are filtered in FP32 against the cutoff widened by a margin that bounds
+    // the FP32 error of the squared distance (coordinates up to Lmax, distances up to
+    // the search radius): the lists are a superset of the pairs inside the cutoff, and
+    // the force pass applies the exact FP64 test.
+    const double Lmax = fmax(fmax(g.Lx, g.Ly), 2.0 * g.Lz);
+    const double margin = 32.0 * sqrt(r2cut) * Lmax * 0x1.0p-24;
     int nh = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
     for (int mode = 0; mode < 3; ++mode) {
         int zlo, zhi;
@@ -263,13 +270,19 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
                     const double xs = xi - shift_of(xsc, g.Lx);
                     const int code = (xsc << 26) | (ysc << 28) | (mode << 30);
                     const int j0 = bin_start[row + cx], j1 = bin_start[row + cx_end + 1];
+                    const float xsf = (float)xs, ysf = (float)ys;
+                    const float zsf = mode == 0 ? 1.0f : -1.0f;
+                    const float zef = (float)(mode == 2 ? zi - 2.0 * g.Lz : zi);
+                    const float cutf = (float)(cut * (1.0 + 1e-5) + margin);
                     for (int j = j0; j < j1; ++j) {
-                        const double4 o = sxyzq[j];
-                        const double dx = xs - o.x;
-                        const double dy = ys - o.y;
-                        const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 < cut && r2 > 0.0 && (mode != 0 || j != i)) {
+                        const float4 o = sxyzf[j];
+                        const float dx = xsf - o.x;
+                        const float dy = ysf - o.y;
+                        const float dz = zef - zsf * o.z;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        // the ion itself is excluded by index: a zero FP32 distance may be
+                        // a distinct (coincident in FP32) pair
+                        if (r2 < cutf && (mode != 0 || j != i)) {
                             const int e = j | code;
                             const int slot = nh & 3;
                             h0 = slot == 0 ? e : h0;
@@ -292,23 +305,25 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
 
 __global__ void __launch_bounds__(256)
 near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                 const float4* __restrict__ sxyzf,
                  const int* __restrict__ bin_start, int* __restrict__ list,
                  int* __restrict__ count) {
     const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    near_list_one(g, P, i, n, sxyzq, bin_start, list, count);
+    near_list_one(g, P, i, n, sxyzq, sxyzf, bin_start, list, count);
 }
 
 // Batched: ion i (cell-list order) belongs to channel ion_rep[i]; its bins start at the
 // channel's bin offset, and its list entries are batch-wide sorted indices.
 __global__ void near_list_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
                                        NearDev P, int n, const double4* __restrict__ sxyzq,
+                                       const float4* __restrict__ sxyzf,
                                        const int* __restrict__ bin_start, int* __restrict__ list,
                                        int* __restrict__ count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const RepDev& R = reps[ion_rep[i]];
-    near_list_one(R.g, P, i, n, sxyzq, bin_start + R.bin_off, list, count);
+    near_list_one(R.g, P, i, n, sxyzq, sxyzf, bin_start + R.bin_off, list, count);
 }
 
 // Pair forces of ion i from its list (or, when the list overflowed, from a direct
@@ -339,8 +354,10 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
                 const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 const double sg = mode == 0 ? 1.0 : (mode == 1 ? P.s_lo : P.s_hi);
-                if (r2 < P.psi2) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
-                if (P.lj_on && mode == 0 && r2 < r2lj) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
+                // the list is a superset (FP32 filter): the exact FP64 tests decide, and a
+                // pair at zero separation has no direction and contributes nothing
+                if (r2 < P.psi2 && r2 > 0.0) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
+                if (P.lj_on && mode == 0 && r2 < r2lj && r2 > 0.0) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
             }
         }
     } else {
@@ -416,8 +433,8 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
     const int T = 256;
-    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->bin_start, c->nlist,
-                                                   c->ncount);
+    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->sxyzf, c->bin_start,
+                                                   c->nlist, c->ncount);
     if (mark >= 0) stage_mark(c, mark, s);
     near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
                                                    c->nlist, c->ncount, c->perm, out, out_stride,
@@ -571,7 +588,7 @@ int batch_near(Batch* b, hipStream_t s) {
     const NearDev P = near_of_h(b->h, &b->p);
     const int T = b->cfg.ion_block;
     near_list_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
-                                                         b->bin_start, b->nlist, b->ncount);
+                                                         b->sxyzf, b->bin_start, b->nlist, b->ncount);
     near_eval_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
                                                          b->ssp, b->bin_start, b->nlist, b->ncount,
                                                          b->fp, b->flags);

@@ -256,3 +256,40 @@ def test_near_field_dense_cluster():
     ctx = _ctx(nx, ny, nz, n)
     out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p)))
     assert rel_l2(out, ref) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [(D, D), (N, N)])
+def test_near_field_cutoff_and_coincidence_edges(bc):
+    """Pairs just inside / just outside the cutoff far from the origin of a wide box
+    (where FP32 positions are coarsest), a pair closer than the FP32 resolution, a
+    coincident pair and an ion on a wall: the FP32 candidate filter keeps every pair
+    inside the cutoff, the exact FP64 test decides, zero separations contribute nothing."""
+    nx, ny, nz = 1024, 16, 24
+    psi = 4.0
+    pts, qs = [], []
+    rng = np.random.default_rng(31)
+    for k in range(40):  # pairs at psi -/+ 1e-9 along random directions, x near 1000
+        c = np.array([1000.0 + rng.uniform(-10, 10), rng.uniform(0, 16), rng.uniform(6, 18)])
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        r = psi - 1e-9 if k % 2 == 0 else psi + 1e-9
+        pts += [c, c + r * d]
+        qs += [1.0, -1.0]
+    c = np.array([1017.3, 5.5, 12.0])
+    pts += [c, c + np.array([1e-7, 0.0, 0.0])]  # distinct in FP64, equal in FP32
+    qs += [1.0, 1.0]
+    pts += [np.array([3.0, 7.0, 9.0])] * 2       # coincident
+    qs += [1.0, -1.0]
+    pts += [np.array([500.0, 3.0, 0.0]), np.array([501.5, 3.0, 24.0])]  # on the walls
+    qs += [1.0, -1.0]
+    pos = np.array(pts).T.copy()
+    pos[0] %= nx
+    q = np.array(qs)
+    p = _params(bc, nx, ny)
+    grid = es.Grid(nx, ny, nz)
+    ref = es.near_field(grid, pos, q, EPS, psi, p["p3m_table"], p["p3m_dr"], bc)
+    ref[2] += shortrange.wall_force(pos[2], grid.L[2], p["wall_sigma"], p["wall_xi"], p["wall_cut"])
+    ctx = _ctx(nx, ny, nz, pos.shape[1])
+    out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p)))
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, ref) < 1e-12
