@@ -158,7 +158,8 @@ static int nparts_for(int64_t n) {
 }
 
 // ---- transposed E_x gather: lambda_i = gQ w_i q_i onto the cell grid --------------
-#define AS_T 16
+#define AS_T 16   // tile edge in x and y
+#define AS_TZ 8   // tile edge in z
 #define AS_THREADS 256
 #define AS_MAXR 256
 
@@ -166,12 +167,14 @@ __global__ void __launch_bounds__(AS_THREADS)
 flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
                    const int* __restrict__ bin_start, const double* __restrict__ gvec,
                    double* __restrict__ lam, double* __restrict__ bcg) {
-    __shared__ double acc[AS_T * AS_T * AS_T];
+    __shared__ double acc[AS_T * AS_T * AS_TZ];
     __shared__ double glo[AS_T * AS_T], ghi[AS_T * AS_T];
     __shared__ int rstart[AS_MAXR], rpre[AS_MAXR + 1], scan[AS_THREADS];
     const int tx = min(AS_T, g.nx), ty = min(AS_T, g.ny);
-    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * AS_T;
-    const int tz = min(AS_T, g.nz - z0);
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);
+    const int x0 = bx * tx, y0 = by * ty, z0 = bz * AS_TZ;
+    const int tz = min(AS_TZ, g.nz - z0);
     const bool has_lo = z0 == 0, has_hi = z0 + tz == g.nz;
     for (int k = threadIdx.x; k < tx * ty * tz; k += blockDim.x) acc[k] = 0.0;
     for (int k = threadIdx.x; k < tx * ty; k += blockDim.x) glo[k] = ghi[k] = 0.0;
@@ -180,14 +183,20 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
     const double gQ = gvec[1];
     const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    auto ion_at = [&](int e) {
         int r = 0, hi = nr - 1;
         while (r < hi) {
             const int mid = (r + hi + 1) >> 1;
             if (rpre[mid] <= e) r = mid; else hi = mid - 1;
         }
-        const int i = rstart[r] + (e - rpre[r]);
-        const double4 a4 = sxyzq[i];
+        return sxyzq[rstart[r] + (e - rpre[r])];
+    };
+    // the next ion's record is loaded before the current one's LDS atomics
+    double4 nxt = make_double4(0.0, 0.0, 0.0, 0.0);
+    if ((int)threadIdx.x < total) nxt = ion_at(threadIdx.x);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const double4 a4 = nxt;
+        if (e + (int)blockDim.x < total) nxt = ion_at(e + blockDim.x);
         if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
         double w, dw;
         flux_weight(g, f, a4.z, w, dw);
@@ -233,15 +242,23 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < tx * ty * tz; k += blockDim.x) {
-        const int lx = k % tx, ly = (k / tx) % ty, lz = k / (tx * ty);
-        lam[((size_t)(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = acc[k];
-    }
-    for (int k = threadIdx.x; k < tx * ty; k += blockDim.x) {
-        const size_t col = (size_t)(y0 + k / tx) * g.nx + (x0 + k % tx);
-        if (has_lo) bcg[col] = glo[k];
-        if (has_hi) bcg[(size_t)g.nx * g.ny + col] = ghi[k];
-    }
+    // store the tile (tile sizes known at compile time for full tiles: no divisions)
+    auto store = [&](const int sx, const int sy) {
+        for (int k = threadIdx.x; k < sx * sy * tz; k += blockDim.x) {
+            const int lx = k % sx, ly = (k / sx) % sy, lz = k / (sx * sy);
+            lam[((size_t)(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = acc[k];
+        }
+        if (has_lo || has_hi)
+            for (int k = threadIdx.x; k < sx * sy; k += blockDim.x) {
+                const size_t col = (size_t)(y0 + k / sx) * g.nx + (x0 + k % sx);
+                if (has_lo) bcg[col] = glo[k];
+                if (has_hi) bcg[(size_t)g.nx * g.ny + col] = ghi[k];
+            }
+    };
+    if (tx == AS_T && ty == AS_T)
+        store(AS_T, AS_T);
+    else
+        store(tx, ty);
 }
 
 // ---- per-ion gradients: gather of rbar (homogeneous folds) and phi (wall ghosts) ----
@@ -251,6 +268,7 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
 #define GT_H 5
 #define GT_THREADS 256
 #define GT_MAXR 64
+#define GT_UNROLL 4  // staging elements in flight per thread
 
 __global__ void __launch_bounds__(GT_THREADS)
 flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
@@ -271,20 +289,6 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     const double udv = gU * dV;
     const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    for (int e = threadIdx.x; e < LX * LY * lzn; e += blockDim.x) {
-        const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
-        if (lx >= lxn || ly >= lyn) continue;
-        const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
-        const int k = z0 - 2 + lz;
-        int src = k;
-        double sg = 1.0;
-        if (k < 0) { src = -1 - k; sg = s_lo; }
-        else if (k >= g.nz) { src = 2 * g.nz - 1 - k; sg = s_hi; }
-        src = min(max(src, 0), g.nz - 1);
-        const size_t o = ((size_t)src * g.ny + j) * g.nx + i;
-        trb[e] = sg * (udv * phi[o] + mu[o]);
-        tph[e] = phi_at(phi, g, wl, i, j, k);
-    }
     const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
     const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
     const int nrows = (bz1 - bz0 + 1) * nbyt;
@@ -308,6 +312,49 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
         }
         if (t < nrows) rpre[t] = scan[t] - len;
         if (t == nrows - 1) rpre[nrows] = scan[t];
+    }
+    __syncthreads();
+    if (rpre[nrows] == 0) return;  // the same for the whole workgroup
+    // rbar (homogeneous folds) and phi (wall ghosts) on the tile and its halo; GT_UNROLL
+    // elements per thread are loaded before the first LDS store
+    const int ne = LX * LY * lzn;
+    const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
+    for (int e0 = threadIdx.x; e0 < ne; e0 += GT_UNROLL * GT_THREADS) {
+        double vr[GT_UNROLL], vp[GT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < GT_UNROLL; ++u) {
+            const int e = e0 + u * GT_THREADS;
+            const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+            const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+            const int k = z0 - 2 + lz;
+            vr[u] = 0.0;
+            vp[u] = 0.0;
+            if (e < ne && lx < lxn && ly < lyn) {
+                if (inner) {
+                    const size_t o = ((size_t)k * g.ny + j) * g.nx + i;
+                    const double pv = phi[o];
+                    vr[u] = udv * pv + mu[o];
+                    vp[u] = pv;
+                } else {
+                    int src = k;
+                    double sg = 1.0;
+                    if (k < 0) { src = -1 - k; sg = s_lo; }
+                    else if (k >= g.nz) { src = 2 * g.nz - 1 - k; sg = s_hi; }
+                    src = min(max(src, 0), g.nz - 1);
+                    const size_t o = ((size_t)src * g.ny + j) * g.nx + i;
+                    vr[u] = sg * (udv * phi[o] + mu[o]);
+                    vp[u] = phi_at(phi, g, wl, i, j, k);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GT_UNROLL; ++u) {
+            const int e = e0 + u * GT_THREADS;
+            if (e < ne) {
+                trb[e] = vr[u];
+                tph[e] = vp[u];
+            }
+        }
     }
     __syncthreads();
     const int total = rpre[nrows];
@@ -436,7 +483,7 @@ int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* ph
     const FluxDev f = flux_of(c, p);
     const WallDev wl = wall_of(p);
     // lambda_phi -> c->rho, wall ghost part -> c->bcg
-    dim3 ga(g.nx / std::min(AS_T, g.nx), g.ny / std::min(AS_T, g.ny), (g.nz + AS_T - 1) / AS_T);
+    dim3 ga(g.nx / std::min(AS_T, g.nx), g.ny / std::min(AS_T, g.ny), (g.nz + AS_TZ - 1) / AS_TZ);
     flux_lambda_kernel<<<ga, AS_THREADS, 0, s>>>(g, wl, f, c->sxyzq, c->bin_start, gvec, c->rho, c->bcg);
     // mu = A^+ lambda_phi -> c->phi
     int rc = solve_poisson(c, c->rho, p, c->phi, s, -1, 1);

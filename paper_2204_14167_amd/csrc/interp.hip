@@ -50,9 +50,48 @@ __device__ __forceinline__ int window_weights(double u, double wc5[5], double dw
     return c;
 }
 
+// Weighted sums over the 5^3 window whose first node is (lx0, ly0, lz0) of the array
+// that fetch(x, y, z) reads: returns E_x, E_y, E_z times -h and the potential P.  UY
+// unrolls the y loop (the loads of UY rows in flight at once).
+template <int UY, class F>
+__device__ __forceinline__ void window_sums(const F& fetch, const double wcx[5], const double dwx[5],
+                                            const double wcy[5], const double dwy[5],
+                                            const double wcz[5], const double dwz[5], double& Ex,
+                                            double& Ey, double& Ez, double& P) {
+    Ex = Ey = Ez = P = 0.0;
+#pragma unroll 1
+    for (int kz = 0; kz < 5; ++kz) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll UY
+        for (int ky = 0; ky < 5; ++ky) {
+            double d = 0.0, c = 0.0;
+#pragma unroll
+            for (int kx = 0; kx < 5; ++kx) {
+                const double v = fetch(kx, ky, kz);
+                d += dwx[kx] * v;
+                c += wcx[kx] * v;
+            }
+            ax += wcy[ky] * d;
+            ay += dwy[ky] * c;
+            az += wcy[ky] * c;
+        }
+        Ex += wcz[kz] * ax;
+        Ey += wcz[kz] * ay;
+        Ez += dwz[kz] * az;
+        P += wcz[kz] * az;
+    }
+}
+
+// Tiles with at most this many ions gather phi straight from memory (125 loads per ion)
+// instead of staging the (TX+5)(TY+5)(TZ+5) window: sparse channels of a batch.
+#define IT_DIRECT 16
+// Staging loads in flight per thread.
+#define IT_UNROLL 8
+
 // One tile of TX x TY x TZ cells (clipped to the grid) starting at (x0, y0, z0):
-// stage phi with its halo and ghost layers in LDS (tile holds (TX+5)(TY+5)(TZ+5)
-// doubles) and interpolate every ion of the tile's cells.
+// find the tile's ions in the cell list; if there are any, stage phi with its halo and
+// ghost layers in LDS (tile holds (TX+5)(TY+5)(TZ+5) doubles) or, for a few ions, read
+// it directly, and interpolate every ion of the tile's cells.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, int op,
                                             const double4* __restrict__ sxyzq,
@@ -66,13 +105,6 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
     const int tx = min(TX, g.nx), ty = min(TY, g.ny);
     const int tz = min(TZ, g.nz - z0);
     const int lxn = tx + IT_H, lyn = ty + IT_H, lzn = tz + IT_H;
-    // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled
-    for (int e = threadIdx.x; e < LX * LY * lzn; e += blockDim.x) {
-        const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
-        if (lx < lxn && ly < lyn)
-            tile[e] = phi_at(phi, g, w, (x0 - 2 + lx) & (g.nx - 1), (y0 - 2 + ly) & (g.ny - 1),
-                             z0 - 2 + lz);
-    }
     // ions of the tile: rows (bz, by) of tx / DISCOS_BIN contiguous bins
     const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
     const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
@@ -101,6 +133,36 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
     }
     __syncthreads();
     const int total = rpre[nrows];
+    if (total == 0) return;  // the same for the whole workgroup
+    const bool direct = total <= IT_DIRECT;
+    if (!direct) {
+        // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled;
+        // IT_UNROLL loads per thread are issued before the first LDS store
+        const int ne = LX * LY * lzn;
+        const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
+        for (int e0 = threadIdx.x; e0 < ne; e0 += IT_UNROLL * IT_THREADS) {
+            double v[IT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < IT_UNROLL; ++u) {
+                const int e = e0 + u * IT_THREADS;
+                const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+                const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+                v[u] = 0.0;
+                if (e < ne && lx < lxn && ly < lyn) {
+                    if (inner)
+                        v[u] = phi[((size_t)(z0 - 2 + lz) * g.ny + j) * g.nx + i];
+                    else
+                        v[u] = phi_at(phi, g, w, i, j, z0 - 2 + lz);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < IT_UNROLL; ++u) {
+                const int e = e0 + u * IT_THREADS;
+                if (e < ne) tile[e] = v[u];
+            }
+        }
+        __syncthreads();
+    }
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
         int r = 0, hi = nrows - 1;
         while (r < hi) {  // last row with rpre[row] <= f
@@ -115,11 +177,11 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
         const double4 a4 = sxyzq[i];
         bool ok = pos_ok(g, a4.x, a4.y, a4.z);
         double wcx[5], dwx[5], wcy[5], dwy[5], wcz[5], dwz[5];
-        int lx0 = 0, ly0 = 0, lz0 = 0;
+        int cx = 0, cy = 0, cz = 0, lx0 = 0, ly0 = 0, lz0 = 0;
         if (ok) {
-            const int cx = window_weights(a4.x * g.inv_h, wcx, dwx);
-            const int cy = window_weights(a4.y * g.inv_h, wcy, dwy);
-            const int cz = window_weights(a4.z * g.inv_h, wcz, dwz);
+            cx = window_weights(a4.x * g.inv_h, wcx, dwx);
+            cy = window_weights(a4.y * g.inv_h, wcy, dwy);
+            cz = window_weights(a4.z * g.inv_h, wcz, dwz);
             lx0 = (cx - x0) & (g.nx - 1);
             ly0 = (cy - y0) & (g.ny - 1);
             lz0 = cz - z0;
@@ -136,28 +198,27 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
             }
             continue;
         }
-        double Ex = 0.0, Ey = 0.0, Ez = 0.0, P = 0.0;
-#pragma unroll 1
-        for (int kz = 0; kz < 5; ++kz) {
-            double ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-            for (int ky = 0; ky < 5; ++ky) {
-                const double* row = &tile[((lz0 + kz) * LY + ly0 + ky) * LX + lx0];
-                double d = 0.0, c = 0.0;
-#pragma unroll
-                for (int kx = 0; kx < 5; ++kx) {
-                    const double v = row[kx];
-                    d += dwx[kx] * v;
-                    c += wcx[kx] * v;
-                }
-                ax += wcy[ky] * d;
-                ay += dwy[ky] * c;
-                az += wcy[ky] * c;
-            }
-            Ex += wcz[kz] * ax;
-            Ey += wcz[kz] * ay;
-            Ez += dwz[kz] * az;
-            P += wcz[kz] * az;
+        double Ex, Ey, Ez, P;
+        if (!direct) {
+            const double* base = &tile[(lz0 * LY + ly0) * LX + lx0];
+            window_sums<5>([&](int kx, int ky, int kz) { return base[(kz * LY + ky) * LX + kx]; },
+                        wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+        } else if (cz >= 2 && cz + 2 < g.nz) {
+            // window cells cx-2 .. cx+2 (likewise y, z), all inside the channel
+            const int nx1 = g.nx - 1, ny1 = g.ny - 1;
+            window_sums<1>(
+                [&](int kx, int ky, int kz) {
+                    return phi[((size_t)(cz - 2 + kz) * g.ny + ((cy - 2 + ky) & ny1)) * g.nx +
+                               ((cx - 2 + kx) & nx1)];
+                },
+                wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+        } else {
+            const int nx1 = g.nx - 1, ny1 = g.ny - 1;
+            window_sums<1>(
+                [&](int kx, int ky, int kz) {
+                    return phi_at(phi, g, w, (cx - 2 + kx) & nx1, (cy - 2 + ky) & ny1, cz - 2 + kz);
+                },
+                wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
         }
         if (op == DISCOS_INTERP_PHI) {
             out[o] = P;

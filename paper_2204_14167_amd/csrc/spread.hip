@@ -44,10 +44,19 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
     const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
+    // the next ion's record is loaded before the current one's LDS atomics
+    double4 nxt = make_double4(0.0, 0.0, 0.0, 0.0);
+    if ((int)threadIdx.x < total) {
+        const int r = find_range(rpre, nr, threadIdx.x);
+        nxt = sxyzq[rstart[r] + ((int)threadIdx.x - rpre[r])];
+    }
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
-        const int r = find_range(rpre, nr, f);
-        const int i = rstart[r] + (f - rpre[r]);
-        const double4 a4 = sxyzq[i];
+        const double4 a4 = nxt;
+        const int fn = f + blockDim.x;
+        if (fn < total) {
+            const int r = find_range(rpre, nr, fn);
+            nxt = sxyzq[rstart[r] + (fn - rpre[r])];
+        }
         const double x = a4.x, y = a4.y, z = a4.z;
         if (!pos_ok(g, x, y, z)) continue;
         int ix0, iy0, iz0;
@@ -89,20 +98,27 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
-        const int lx = k % tx, ly = (k / tx) % ty, lz = k / (tx * ty);
-        const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
-        double v = acc[k];
-        if (add_bc) {
-            for (int w = 0; w < 2; ++w) {
-                if (gk != (w == 0 ? 0 : g.nz - 1)) continue;
-                const double bv = wall.value[w] ? wall.value[w][(size_t)gj * g.nx + gi] : 0.0;
-                v += (wall.type[w] == DISCOS_BC_DIRICHLET) ? 2.0 * wall.eps * bv * g.inv_h * g.inv_h
-                                                           : bv * g.inv_h;
+    // store the tile (tile sizes known at compile time for full tiles: no divisions)
+    auto store = [&](const int sx, const int sy) {
+        for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+            const int lx = k % sx, ly = (k / sx) % sy, lz = k / (sx * sy);
+            const int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
+            double v = acc[k];
+            if (add_bc && (gk == 0 || gk == g.nz - 1)) {
+                for (int w = 0; w < 2; ++w) {
+                    if (gk != (w == 0 ? 0 : g.nz - 1)) continue;
+                    const double bv = wall.value[w] ? wall.value[w][(size_t)gj * g.nx + gi] : 0.0;
+                    v += (wall.type[w] == DISCOS_BC_DIRICHLET) ? 2.0 * wall.eps * bv * g.inv_h * g.inv_h
+                                                               : bv * g.inv_h;
+                }
             }
+            out[((size_t)gk * g.ny + gj) * g.nx + gi] = v;
         }
-        out[((size_t)gk * g.ny + gj) * g.nx + gi] = v;
-    }
+    };
+    if (tx == T && ty == T)
+        store(T, T);
+    else
+        store(tx, ty);
 }
 
 __global__ void __launch_bounds__(SP_THREADS)
