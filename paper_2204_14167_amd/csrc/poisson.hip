@@ -186,12 +186,17 @@ fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int
 }
 
 // Complex FFT along y of spec[k][j][m] for a block of MC consecutive m at one k.
+// Spectrum rows (nx/2 + 1 entries) do not start on cache-line boundaries, so the
+// blocks of neighbouring m share lines; the XCD renumbering runs all blocks of a level
+// on one XCD, where the second read of a shared line hits its L2.
 __global__ void __launch_bounds__(FFT_THREADS)
 fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int mc,
              const double2* __restrict__ tw, int inv) {
     extern __shared__ double2 lds[];
-    const int m0 = blockIdx.x * mc;
-    const size_t kbase = (size_t)blockIdx.y * ny * nxh;
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);
+    const int m0 = bx * mc;
+    const size_t kbase = (size_t)by * ny * nxh;
     const int lmc = __builtin_ctz(mc);
     for (int e = threadIdx.x; e < mc * ny; e += blockDim.x) {
         const int c = e & (mc - 1), j = e >> lmc;
