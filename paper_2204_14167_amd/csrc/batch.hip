@@ -7,6 +7,7 @@
 // keeps every channel's ions inside its own slots); cells, spectra and Thomas scratch
 // are grouped by (nx, ny) class so that each class's FFT rows and levels are single
 // ranges for one launch.
+#include <array>
 #include <cmath>
 #include <map>
 #include <new>
@@ -185,6 +186,33 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->ncell_tot = cell;
     b->nspec_tot = spec;
     b->nmode_tot = mode_off[count];
+    // z-solve: pivots once per grid shape (channels with nz <= 128), tasks of 16 modes per
+    // wavefront grouped by segment length; channels with nz > 128 keep the per-mode
+    // Thomas sweep with spectrum-sized scratch
+    std::map<std::array<int, 3>, int64_t> zshape;
+    int64_t zg_len = 0;
+    std::vector<int2> zt[3];
+    for (int r = 0; r < count; ++r) {
+        const discos_replica& c = reps[r];
+        discos::RepDev& d = b->reps_h[r];
+        d.zg_off = 0;
+        if (d.singular) b->z_singular = true;
+        if (c.nz > 128) {
+            b->z_legacy = true;
+            continue;
+        }
+        const std::array<int, 3> key{c.nx, c.ny, c.nz};
+        auto it = zshape.find(key);
+        if (it == zshape.end()) {
+            it = zshape.emplace(key, zg_len).first;
+            b->zshapes.push_back({(int64_t)c.nx, (int64_t)c.ny, (int64_t)c.nz, zg_len});
+            zg_len += (int64_t)c.nz * d.nmode;
+        }
+        d.zg_off = it->second;
+        const int L = (c.nz + 3) / 4;
+        const int v = L <= 8 ? 0 : (L <= 16 ? 1 : 2);
+        for (int t0 = 0; t0 < d.nmode; t0 += 16) zt[v].push_back(make_int2(r, t0));
+    }
     // tile tasks, largest channels first
     std::vector<int> order(count);
     for (int r = 0; r < count; ++r) order[r] = r;
@@ -225,7 +253,10 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     bytes += carve_bytes(b->nbins_tot, sizeof(int)) + carve_bytes(b->nbins_tot + 1, sizeof(int));
     bytes += carve_bytes(nblk, sizeof(int));
     bytes += 2 * carve_bytes(b->ncell_tot, sizeof(double));
-    bytes += carve_bytes(b->nspec_tot, sizeof(double2)) + carve_bytes(b->nspec_tot, sizeof(double));
+    const int64_t ncp = b->z_legacy ? b->nspec_tot : 1;
+    bytes += carve_bytes(b->nspec_tot, sizeof(double2)) + carve_bytes(ncp, sizeof(double));
+    bytes += carve_bytes(std::max<int64_t>(zg_len, 1), sizeof(double));
+    for (int v = 0; v < 3; ++v) bytes += carve_bytes(std::max<size_t>(zt[v].size(), 1), sizeof(int2));
     bytes += carve_bytes(3 * n, sizeof(double));
     bytes += carve_bytes(64 * n, sizeof(int)) + carve_bytes(n, sizeof(int));
     bytes += carve_bytes(64, sizeof(int)) + carve_bytes(1, sizeof(uint64_t));
@@ -254,7 +285,12 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->rho = carve<double>(cur, b->ncell_tot);
     b->phi = carve<double>(cur, b->ncell_tot);
     b->spec = carve<double2>(cur, b->nspec_tot);
-    b->cprime = carve<double>(cur, b->nspec_tot);
+    b->cprime = carve<double>(cur, ncp);
+    b->zg = carve<double>(cur, std::max<int64_t>(zg_len, 1));
+    for (int v = 0; v < 3; ++v) {
+        b->ztasks[v] = carve<int2>(cur, std::max<size_t>(zt[v].size(), 1));
+        b->ztasks_n[v] = (int)zt[v].size();
+    }
     b->fp = carve<double>(cur, 3 * n);
     b->nlist = carve<int>(cur, 64 * n);
     b->ncount = carve<int>(cur, n);
@@ -300,6 +336,11 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
             if (!tk[kind][v].empty())
                 ok = ok && hipMemcpy(b->tasks[kind][v], tk[kind][v].data(), tk[kind][v].size() * sizeof(int2),
                                      hipMemcpyHostToDevice) == hipSuccess;
+    for (int v = 0; v < 3; ++v)
+        if (!zt[v].empty())
+            ok = ok && hipMemcpy(b->ztasks[v], zt[v].data(), zt[v].size() * sizeof(int2),
+                                 hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && discos::batch_pivots(b, 0) == DISCOS_OK && hipStreamSynchronize(0) == hipSuccess;
     ok = ok && hipMemset(b->flags, 0, 64 * sizeof(int)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess;

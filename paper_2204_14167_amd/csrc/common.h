@@ -38,6 +38,7 @@ struct RepDev {
     WallDev w;           // wall value pointers already offset to this channel
     int64_t cell_off;    // rho, phi
     int64_t spec_off;    // half spectra and Thomas scratch
+    int64_t zg_off;      // z-solve pivots of this channel's grid shape (nz <= 128)
     int bin_off;         // first bin
     int ion_off, n;      // ions [ion_off, ion_off + n)
     double s_lo, s_hi;   // image signs of the two walls

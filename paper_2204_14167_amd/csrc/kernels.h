@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "common.h"
@@ -92,6 +93,12 @@ struct Batch {
     int64_t nmode_tot;
     int2* tasks[2][2];             // [kernel: spread, interp][variant]: (channel, tile)
     int ntasks[2][2];
+    int2* ztasks[3];               // z-solve with pivots, L = 8, 16, 32: (channel, first mode)
+    int ztasks_n[3];
+    std::vector<std::array<int64_t, 4>> zshapes;  // (nx, ny, nz, pivot offset) per grid shape
+    double* zg;                    // pivots of every shape, [nz][nmode] each
+    bool z_legacy = false;         // some channel has nz > 128 (per-mode Thomas, scratch cprime)
+    bool z_singular = false;       // both walls Neumann
     std::vector<BatchClass> classes;
     double* walls;                 // per-channel wall fields [2][ny][nx], back to back
     double4* sxyzq;
@@ -188,6 +195,7 @@ int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* ph
 int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id, const int* sp,
                     hipStream_t s);
 int batch_spread(Batch* b, hipStream_t s);
+int batch_pivots(Batch* b, hipStream_t s);
 int batch_poisson(Batch* b, hipStream_t s);
 int batch_interp(Batch* b, hipStream_t s);
 int batch_near(Batch* b, hipStream_t s);

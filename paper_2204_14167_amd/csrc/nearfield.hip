@@ -342,13 +342,20 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
         for (int k4 = 0; k4 < cnt; k4 += 4) {
             const int4 ch = chunks[(size_t)(k4 >> 2) * n + i];
             const int m4 = min(4, cnt - k4);
+            // the four gathers are issued together (unused slots read the ion itself)
+            double4 ob[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = u == 0 ? ch.x : (u == 1 ? ch.y : (u == 2 ? ch.z : ch.w));
+                ob[u] = sxyzq[u < m4 ? (e & 0x3FFFFFF) : i];
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (u >= m4) break;
                 const int e = u == 0 ? ch.x : (u == 1 ? ch.y : (u == 2 ? ch.z : ch.w));
                 const int j = e & 0x3FFFFFF;
                 const int mode = (e >> 30) & 3;
-                const double4 o = sxyzq[j];
+                const double4 o = ob[u];
                 const double dx = (xi - shift_of((e >> 26) & 3, g.Lx)) - o.x;
                 const double dy = (yi - shift_of((e >> 28) & 3, g.Ly)) - o.y;
                 const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));

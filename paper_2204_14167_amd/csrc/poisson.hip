@@ -338,8 +338,8 @@ __global__ void __launch_bounds__(64) zsolve_kernel(double2* __restrict__ spec, 
                 singular, flags);
 }
 
-// Batched: one thread per mode of every channel; mode_off is the prefix of the
-// channels' mode counts (in mode_rep order).
+// Batched, for channels with nz > 128: one thread per mode of every channel; mode_off
+// is the prefix of the channels' mode counts (in mode_rep order).
 __global__ void __launch_bounds__(64) zsolve_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ mode_off,
                                     const int* __restrict__ mode_rep, int nrep, int64_t nmode_tot,
                                     double2* __restrict__ spec, double* __restrict__ cp,
@@ -352,6 +352,7 @@ __global__ void __launch_bounds__(64) zsolve_batch_kernel(const RepDev* __restri
         if (mode_off[mid] <= t) lo = mid; else hi = mid - 1;
     }
     const RepDev& R = reps[mode_rep[lo]];
+    if (R.g.nz <= 128) return;  // solved with pivots
     const int tl = (int)(t - mode_off[lo]);
     const int nxh = R.g.nxh;
     zsolve_mode(spec + R.spec_off + tl, cp + R.spec_off + tl, (size_t)R.nmode, tl % nxh, tl / nxh,
@@ -389,12 +390,11 @@ __global__ void __launch_bounds__(64) zpivot_kernel(double* __restrict__ zg, int
 // Lane l of a wavefront: mode 16 w + (l & 15), segment l >> 4, so one load instruction
 // reads 16 consecutive modes at four levels.
 template <int L>
-__global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ spec,
-                                                        const double* __restrict__ zg, int nmode,
-                                                        int nz, double scale, int skip0) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, const double* __restrict__ zg,
+                                                int nmode, int nz, double scale, int skip0, int t0) {
+    const int lane = threadIdx.x & 63;
     const int ml = lane & 15, seg = lane >> 4;
-    const int t = (blockIdx.x * 4 + wave) * 16 + ml;
+    const int t = t0 + ml;
     const bool valid = t < nmode && !(skip0 && t == 0);
     const int tt = min(t, nmode - 1);
     const int k0 = seg * L;
@@ -468,6 +468,29 @@ __global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ s
         if (u < len) spec[(size_t)(k0 + u) * nmode + t] = d[u];
 }
 
+// Wavefront w of block b solves modes 16 (4 b + w) .. + 15.
+template <int L>
+__global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ spec,
+                                                        const double* __restrict__ zg, int nmode,
+                                                        int nz, double scale, int skip0) {
+    zsolve_seg_wave<L>(spec, zg, nmode, nz, scale, skip0, (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16);
+}
+
+// Batched: task (channel, first mode) per wavefront, for channels whose nz fits L
+// levels per segment; the pivots of each channel's grid shape start at zg_off.
+template <int L>
+__global__ void __launch_bounds__(256) zsolve_seg_batch_kernel(const RepDev* __restrict__ reps,
+                                                              const int2* __restrict__ tasks,
+                                                              int ntasks, double2* __restrict__ spec,
+                                                              const double* __restrict__ zg) {
+    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= ntasks) return;  // the whole wavefront
+    const int2 tk = tasks[task];
+    const RepDev& R = reps[tk.x];
+    zsolve_seg_wave<L>(spec + R.spec_off, zg + R.zg_off, R.nmode, R.g.nz, R.scale, R.singular != 0,
+                       tk.y);
+}
+
 // Inclusive prefix sum over the 64 lanes of a wavefront.
 __device__ __forceinline__ double wave_incl_scan(double v) {
     const int lane = threadIdx.x & 63;
@@ -491,10 +514,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // pseudo-inverse); with r' = r - mean(r) the differences are
 // x_{k+1} - x_k = -(r'_0 + ... + r'_k), so x is a double prefix sum, shifted to mean 0:
 // the minimum-norm solution.  Levels are taken 64 at a time with running carries.
-__global__ void __launch_bounds__(64) zsolve_mode0_kernel(double2* __restrict__ spec, int nmode, int nz,
-                                                         double scale, int singular,
-                                                         int* __restrict__ flags) {
-    const int lane = threadIdx.x;
+__device__ __forceinline__ void zsolve_mode0_wave(double2* __restrict__ spec, int nmode, int nz,
+                                                  double scale, int singular, int* __restrict__ flags) {
+    const int lane = threadIdx.x & 63;
     double sx = 0.0, sy = 0.0, ax = 0.0;
     for (int k0 = 0; k0 < nz; k0 += 64) {
         const int k = k0 + lane;
@@ -543,6 +565,22 @@ __global__ void __launch_bounds__(64) zsolve_mode0_kernel(double2* __restrict__ 
             spec[(size_t)k * nmode] = make_double2(v.x - tx, v.y - ty);
         }
     }
+}
+
+__global__ void __launch_bounds__(64) zsolve_mode0_kernel(double2* __restrict__ spec, int nmode, int nz,
+                                                         double scale, int singular,
+                                                         int* __restrict__ flags) {
+    zsolve_mode0_wave(spec, nmode, nz, scale, singular, flags);
+}
+
+// Batched: block r solves the kappa = 0 mode of channel r when its walls are both
+// Neumann and its z-solve uses pivots (nz <= 128).
+__global__ void __launch_bounds__(64) zsolve_mode0_batch_kernel(const RepDev* __restrict__ reps,
+                                                               double2* __restrict__ spec,
+                                                               int* __restrict__ flags) {
+    const RepDev& R = reps[blockIdx.x];
+    if (!R.singular || R.g.nz > 128) return;
+    zsolve_mode0_wave(spec + R.spec_off, R.nmode, R.g.nz, R.scale, R.singular, flags);
 }
 
 static int ilog2(int n) {
@@ -634,8 +672,22 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
+// Pivots of every grid shape of a batch with nz <= 128 (all channels share the wall types).
+int batch_pivots(Batch* b, hipStream_t s) {
+    const double s_lo = b->p.bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    const double s_hi = b->p.bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    for (const auto& sh : b->zshapes) {
+        const int nx = (int)sh[0], ny = (int)sh[1], nz = (int)sh[2];
+        const int nmode = (nx / 2 + 1) * ny;
+        zpivot_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(b->zg + sh[3], nx, ny, nz, s_lo, s_hi,
+                                                        b->z_singular ? 1 : 0);
+    }
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
 // Poisson for every channel: x- and y-FFTs per size class (a class's grids and spectra
-// are contiguous, so its rows and levels form single ranges), one z-solve launch.
+// are contiguous, so its rows and levels form single ranges); z-solves with pivots per
+// segment length (one launch each), the Thomas sweep for channels with nz > 128.
 int batch_poisson(Batch* b, hipStream_t s) {
     for (const BatchClass& k : b->classes) {
         const int nxh = k.nx / 2 + 1;
@@ -648,8 +700,19 @@ int batch_poisson(Batch* b, hipStream_t s) {
         fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * k.ny * sizeof(double2), s>>>(
             b->spec + k.spec_off, nxh, k.ny, ilog2(k.ny), mc, k.tw_y, 0);
     }
-    zsolve_batch_kernel<<<(int)((b->nmode_tot + 63) / 64), 64, 0, s>>>(
-        b->reps_d, b->mode_off, b->mode_rep, b->R, b->nmode_tot, b->spec, b->cprime, b->flags);
+    if (b->ztasks_n[0] > 0)
+        zsolve_seg_batch_kernel<8><<<(b->ztasks_n[0] + 3) / 4, 256, 0, s>>>(b->reps_d, b->ztasks[0],
+                                                                          b->ztasks_n[0], b->spec, b->zg);
+    if (b->ztasks_n[1] > 0)
+        zsolve_seg_batch_kernel<16><<<(b->ztasks_n[1] + 3) / 4, 256, 0, s>>>(b->reps_d, b->ztasks[1],
+                                                                           b->ztasks_n[1], b->spec, b->zg);
+    if (b->ztasks_n[2] > 0)
+        zsolve_seg_batch_kernel<32><<<(b->ztasks_n[2] + 3) / 4, 256, 0, s>>>(b->reps_d, b->ztasks[2],
+                                                                           b->ztasks_n[2], b->spec, b->zg);
+    if (b->z_singular) zsolve_mode0_batch_kernel<<<b->R, 64, 0, s>>>(b->reps_d, b->spec, b->flags);
+    if (b->z_legacy)
+        zsolve_batch_kernel<<<(int)((b->nmode_tot + 63) / 64), 64, 0, s>>>(
+            b->reps_d, b->mode_off, b->mode_rep, b->R, b->nmode_tot, b->spec, b->cprime, b->flags);
     for (const BatchClass& k : b->classes) {
         const int nxh = k.nx / 2 + 1;
         const int mc = std::max(1, std::min(16, 2048 / k.ny));

@@ -28,10 +28,11 @@ def _channel(b, reps, arrays, r):
     return pos[:, lo:hi], q[lo:hi], ids[lo:hi], sp[lo:hi]
 
 
-def _oracle_check(reps, b, before, after, r, step, sample=None):
+def _oracle_check(reps, b, before, after, r, step, sample=None, p=None):
     rep = reps[r]
     w = rep["workload"]
-    p = workloads.batch_channel_params(rep)
+    if p is None:
+        p = workloads.batch_channel_params(rep)
     grid = es.Grid(w.nx, w.ny, w.nz, w.h)
     pos0, q0, ids0, sp0 = _channel(b, reps, before, r)
     order = np.argsort(ids0)
@@ -170,3 +171,73 @@ def test_full_512_channel_batch_sampled():
         err = _oracle_check(reps, b, before, after, int(r), 0, sample=150)
         log(f"channel {r} ({reps[r]['nx']}x{reps[r]['ny']}x{reps[r]['nz']}, {reps[r]['n']} ions) rel {err:.3e}")
         assert err < TOL
+
+
+def _custom_params(rep):
+    """Parameters of a custom channel: the shared physics and tables, the channel's noise
+    key, and its mobility coefficients (the stored fit of the nearest tabulated height;
+    any coefficients are valid inputs for parity)."""
+    p = workloads.make_params(rep["workload"], with_tables=False)
+    p["p3m_table"], p["p3m_dr"] = workloads.load_p3m_table()
+    p["mob_coef"] = rep["mob_coef"]
+    p["seed"] = rep["seed"]
+    return p
+
+
+def _custom_batch(shapes, bc_types, bc_values, seed):
+    """Batch of channels with the given (nx, ny, nz, n) and walls (all channels share the
+    wall types, as a batch requires)."""
+    from paper_2204_14167_amd import discos
+    rng = np.random.default_rng(seed)
+    reps, parts = [], []
+    for r, (nx, ny, nz, n) in enumerate(shapes):
+        w = workloads.Workload(f"custom_{r}", nx, ny, nz, n, bc_types, bc_values,
+                               seed=int(rng.integers(1, 2**62)))
+        rep = dict(nx=nx, ny=ny, nz=nz, n=n, bc_values=bc_values, seed=w.seed + 1000, workload=w)
+        height = min((16, 32, 64, 128), key=lambda H: abs(H - nz))
+        coef = workloads.load_mobility_coef(float(height))
+        rep["mob_coef"] = np.stack([coef, coef])
+        reps.append(rep)
+        parts.append(workloads.make_ions(w))
+    pos = np.concatenate([a[0] for a in parts], axis=1)
+    q = np.concatenate([a[1] for a in parts])
+    ids = np.concatenate([a[2] for a in parts]).astype(np.int32)
+    sp = np.concatenate([a[3] for a in parts]).astype(np.int32)
+    b = discos.Batch(reps, 1.0, _custom_params(reps[0]))
+    return b, reps, pos, q, ids, sp
+
+
+@pytest.mark.parametrize("walls", [((workloads.NEUMANN, workloads.NEUMANN), (0.0, 0.0)),
+                                   ((workloads.DIRICHLET, workloads.NEUMANN), (0.5, 0.0))])
+def test_batch_z_solve_paths(walls):
+    """Every z-solve path of a batch: segment lengths 8 (nz = 8, 32) and 16 (nz = 37, 64),
+    the per-mode Thomas sweep (nz = 160 > 128), and, with both walls Neumann, the singular
+    kappa = 0 mode of each channel; against the oracle and against single contexts."""
+    from paper_2204_14167_amd import discos
+    shapes = [(16, 16, 32, 200), (32, 16, 64, 512), (16, 16, 37, 120), (16, 32, 160, 600),
+              (16, 16, 8, 40)]
+    b, reps, pos, q, ids, sp = _custom_batch(shapes, walls[0], walls[1], seed=303)
+    arrays = (dev(pos), dev(q), dev(ids), dev(sp))
+    before = _host_all(arrays)
+    b.step(*arrays, step=2)
+    b.check()
+    after = _host_all(arrays)
+    for r in range(len(reps)):
+        p = _custom_params(reps[r])
+        err = _oracle_check(reps, b, before, after, r, 2, p=p)
+        log(f"{walls[0]} channel {shapes[r]} vs oracle rel {err:.3e}")
+        assert err < TOL
+        w = reps[r]["workload"]
+        ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n)
+        lo, hi = b.offsets[r], b.offsets[r + 1]
+        one = (dev(pos[:, lo:hi]), dev(q[lo:hi]), dev(ids[lo:hi]), dev(sp[lo:hi]))
+        ctx.step(*one, ctx.params(p), 2)
+        ctx.check()
+        ref_pos, _, ref_ids, _ = _host_all(one)
+        gpos, _, gids, _ = _channel(b, reps, after, r)
+        L = np.array([w.nx, w.ny, w.nz], float)
+        a = by_id(gpos, gids, np.arange(w.n))
+        c = by_id(ref_pos, ref_ids, np.arange(w.n))
+        e = np.linalg.norm(min_image(a - c, L)) / np.linalg.norm(min_image(c - pos[:, lo:hi], L))
+        log(f"  vs single context rel {e:.3e}")
+        assert e < 1e-12
