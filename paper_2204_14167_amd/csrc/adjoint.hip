@@ -167,17 +167,21 @@ __global__ void __launch_bounds__(AS_THREADS)
 flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
                    const int* __restrict__ bin_start, const double* __restrict__ gvec,
                    double* __restrict__ lam, double* __restrict__ bcg) {
-    __shared__ double acc[AS_T * AS_T * AS_TZ];
-    __shared__ double glo[AS_T * AS_T], ghi[AS_T * AS_T];
+    // mu on the x-faces x0 .. x0 + tx of the tile (face F between cells F - 1 and F), then
+    // lambda_phi(cell c) = mu(c) - mu(c + 1): the transpose of the face differences
+    constexpr int FX = AS_T + 1;
+    __shared__ double acc[FX * AS_T * AS_TZ];
+    __shared__ double glo[FX * AS_T], ghi[FX * AS_T];
     __shared__ int rstart[AS_MAXR], rpre[AS_MAXR + 1], scan[AS_THREADS];
     const int tx = min(AS_T, g.nx), ty = min(AS_T, g.ny);
+    const int fx = tx + 1;  // face columns held (face x0 + tx is face x0 when tx = nx)
     int bx, by, bz;
     xcd_block3(bx, by, bz);
     const int x0 = bx * tx, y0 = by * ty, z0 = bz * AS_TZ;
     const int tz = min(AS_TZ, g.nz - z0);
     const bool has_lo = z0 == 0, has_hi = z0 + tz == g.nz;
-    for (int k = threadIdx.x; k < tx * ty * tz; k += blockDim.x) acc[k] = 0.0;
-    for (int k = threadIdx.x; k < tx * ty; k += blockDim.x) glo[k] = ghi[k] = 0.0;
+    for (int k = threadIdx.x; k < fx * ty * tz; k += blockDim.x) acc[k] = 0.0;
+    for (int k = threadIdx.x; k < fx * ty; k += blockDim.x) glo[k] = ghi[k] = 0.0;
     const int nr = tile_ranges<AS_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
     const int total = rpre[nr];
     const double gQ = gvec[1];
@@ -202,14 +206,20 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
         flux_weight(g, f, a4.z, w, dw);
         const double val = -gQ * w * a4.w * g.inv_h;
         if (val == 0.0) continue;
-        double wcx[5], dcx[5], fdx[5], dfx[5], wcy[5], dcy[5], fdy[5], dfy[5], wcz[5], dcz[5], fdz[5], dfz[5];
-        const int cx = window_weights_d(a4.x * g.inv_h, wcx, dcx, fdx, dfx);
-        const int cy = window_weights_d(a4.y * g.inv_h, wcy, dcy, fdy, dfy);
-        const int cz = window_weights_d(a4.z * g.inv_h, wcz, dcz, fdz, dfz);
+        int ifx, icy, icz;
+        double wfx[4], wcy[4], wcz[4];
+        peskin4(a4.x * g.inv_h, ifx, wfx);
+        peskin4(a4.y * g.inv_h - 0.5, icy, wcy);
+        peskin4(a4.z * g.inv_h - 0.5, icz, wcz);
+        int lfs[4], lys[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lfs[q] = (ifx + q - x0) & (g.nx - 1);
+            lys[q] = (icy + q - y0) & (g.ny - 1);
+        }
 #pragma unroll 1
-        for (int kz = 0; kz < 5; ++kz) {
-            if (wcz[kz] == 0.0) continue;
-            const int k = cz - 2 + kz;
+        for (int c = 0; c < 4; ++c) {
+            const int k = icz + c;
             int layer = k, m = -1, wall = -1;
             double sg = 1.0;
             if (k < 0) { m = -1 - k; layer = m; sg = s_lo; wall = 0; }
@@ -224,35 +234,41 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
                 gcoef = wl.type[wall] == DISCOS_BC_DIRICHLET ? 2.0 : (2 * m + 1) * g.h / wl.eps;
             if (!in_z && !ghost) continue;
             double* gl = wall == 0 ? glo : ghi;
-            const double vz = val * wcz[kz];
+            const double vz = val * wcz[c];
 #pragma unroll
-            for (int ky = 0; ky < 5; ++ky) {
-                const int ly = (cy - 2 + ky - y0) & (g.ny - 1);
-                if (ly >= ty || wcy[ky] == 0.0) continue;
-                const double vyz = vz * wcy[ky];
+            for (int bq = 0; bq < 4; ++bq) {
+                const int ly = lys[bq];
+                if (ly >= ty) continue;
+                const double vyz = vz * wcy[bq];
 #pragma unroll
-                for (int kx = 0; kx < 5; ++kx) {
-                    const int lx = (cx - 2 + kx - x0) & (g.nx - 1);
-                    if (lx >= tx) continue;
-                    const double v = vyz * fdx[kx];
-                    if (in_z) atomicAdd(&acc[(lz * ty + ly) * tx + lx], sg * v);
-                    if (ghost) atomicAdd(&gl[ly * tx + lx], gcoef * v);
+                for (int aq = 0; aq < 4; ++aq) {
+                    const int lf = lfs[aq];
+                    if (lf >= fx) continue;
+                    const double v = vyz * wfx[aq];
+                    if (in_z) atomicAdd(&acc[(lz * ty + ly) * fx + lf], sg * v);
+                    if (ghost) atomicAdd(&gl[ly * fx + lf], gcoef * v);
                 }
             }
         }
     }
     __syncthreads();
-    // store the tile (tile sizes known at compile time for full tiles: no divisions)
+    // store lambda_phi = mu(c) - mu(c + 1) per cell (and the same difference of the ghost
+    // parts per wall column); tile sizes known at compile time for full tiles
+    const bool wrap = tx == g.nx;  // the face after the last cell is face 0
     auto store = [&](const int sx, const int sy) {
         for (int k = threadIdx.x; k < sx * sy * tz; k += blockDim.x) {
             const int lx = k % sx, ly = (k / sx) % sy, lz = k / (sx * sy);
-            lam[((size_t)(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = acc[k];
+            const int nx1 = (wrap && lx == sx - 1) ? 0 : lx + 1;
+            const int row = (lz * sy + ly) * fx;
+            lam[((size_t)(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = acc[row + lx] - acc[row + nx1];
         }
         if (has_lo || has_hi)
             for (int k = threadIdx.x; k < sx * sy; k += blockDim.x) {
-                const size_t col = (size_t)(y0 + k / sx) * g.nx + (x0 + k % sx);
-                if (has_lo) bcg[col] = glo[k];
-                if (has_hi) bcg[(size_t)g.nx * g.ny + col] = ghi[k];
+                const int lx = k % sx, ly = k / sx;
+                const int nx1 = (wrap && lx == sx - 1) ? 0 : lx + 1;
+                const size_t col = (size_t)(y0 + ly) * g.nx + (x0 + lx);
+                if (has_lo) bcg[col] = glo[ly * fx + lx] - glo[ly * fx + nx1];
+                if (has_hi) bcg[(size_t)g.nx * g.ny + col] = ghi[ly * fx + lx] - ghi[ly * fx + nx1];
             }
     };
     if (tx == AS_T && ty == AS_T)
@@ -327,14 +343,15 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
             const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
             const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
             const int k = z0 - 2 + lz;
+            const int il = (i - 1) & (g.nx - 1);  // left neighbour: face i lies between il and i
             vr[u] = 0.0;
             vp[u] = 0.0;
             if (e < ne && lx < lxn && ly < lyn) {
                 if (inner) {
-                    const size_t o = ((size_t)k * g.ny + j) * g.nx + i;
-                    const double pv = phi[o];
-                    vr[u] = udv * pv + mu[o];
-                    vp[u] = pv;
+                    const size_t row = ((size_t)k * g.ny + j) * g.nx;
+                    const double pv = phi[row + i];
+                    vr[u] = udv * pv + mu[row + i];
+                    vp[u] = pv - phi[row + il];
                 } else {
                     int src = k;
                     double sg = 1.0;
@@ -343,7 +360,7 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
                     src = min(max(src, 0), g.nz - 1);
                     const size_t o = ((size_t)src * g.ny + j) * g.nx + i;
                     vr[u] = sg * (udv * phi[o] + mu[o]);
-                    vp[u] = phi_at(phi, g, wl, i, j, k);
+                    vp[u] = phi_at(phi, g, wl, i, j, k) - phi_at(phi, g, wl, il, j, k);
                 }
             }
         }
@@ -368,16 +385,27 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
         const int o = perm[i];
         const double4 a4 = sxyzq[i];
         bool ok = pos_ok(g, a4.x, a4.y, a4.z);
-        double wcx[5], dcx[5], fdx[5], dfx[5], wcy[5], dcy[5], fdy[5], dfy[5], wcz[5], dcz[5], fdz[5], dfz[5];
-        int lx0 = 0, ly0 = 0, lz0 = 0;
+        // centre weights (and d/du) in x, y, z; face weights (and d/du) in x
+        double wcx[4], dcx[4], wfx[4], dfx[4], wcy[4], dcy[4], wcz[4], dcz[4];
+        int ax = 0, dx0 = 0, ay = 0, az = 0;  // tile indices of the window starts
         if (ok) {
-            const int cx = window_weights_d(a4.x * g.inv_h, wcx, dcx, fdx, dfx);
-            const int cy = window_weights_d(a4.y * g.inv_h, wcy, dcy, fdy, dfy);
-            const int cz = window_weights_d(a4.z * g.inv_h, wcz, dcz, fdz, dfz);
-            lx0 = (cx - x0) & (g.nx - 1);
-            ly0 = (cy - y0) & (g.ny - 1);
-            lz0 = cz - z0;
+            const double ux = a4.x * g.inv_h, uy = a4.y * g.inv_h, uz = a4.z * g.inv_h;
+            int icx, ifx, icy, icz;
+            peskin4_d(ux - 0.5, icx, wcx, dcx);
+            peskin4_d(ux, ifx, wfx, dfx);
+            peskin4_d(uy - 0.5, icy, wcy, dcy);
+            peskin4_d(uz - 0.5, icz, wcz, dcz);
+            const int cx = ifx + 1, cy = (int)floor(uy), cz = (int)floor(uz);
+            const int lx0 = (cx - x0) & (g.nx - 1);
+            const int ly0 = (cy - y0) & (g.ny - 1);
+            const int lz0 = cz - z0;
             ok = lx0 <= tx && ly0 <= ty && lz0 >= 0 && lz0 <= tz;
+            // the tile starts at cell x0 - 2; faces F (between cells F - 1 and F) are
+            // stored at the index of cell F
+            ax = lx0 + (icx - (cx - 2));
+            dx0 = lx0 + 1;
+            ay = ly0 + (icy - (cy - 2));
+            az = lz0 + (icz - (cz - 2));
         }
         if (!ok) {
             set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
@@ -386,38 +414,41 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
             if (dpos) dpos[o] = dpos[o + stride] = dpos[o + 2 * stride] = 0.0;
             continue;
         }
-        // R = J rbar and its gradient (x, y, z); P = sum fd_x wc_y wc_z phi and gradient
+        // R = J rbar and its gradient (4^3 centre window); P = sum wf_x wc_y wc_z D (the
+        // x-face differences of phi_ext, 4^3 window) and its gradient
         double R = 0.0, Rx = 0.0, Ry = 0.0, Rz = 0.0, P = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
 #pragma unroll 1
-        for (int kz = 0; kz < 5; ++kz) {
+        for (int c = 0; c < 4; ++c) {
             double c00 = 0.0, c10 = 0.0, c01 = 0.0, e00 = 0.0, e10 = 0.0, e01 = 0.0;
 #pragma unroll
-            for (int ky = 0; ky < 5; ++ky) {
-                const int base = ((lz0 + kz) * LY + ly0 + ky) * LX + lx0;
+            for (int b = 0; b < 4; ++b) {
+                const int rowc = ((az + c) * LY + ay + b) * LX;
+                const double* ra = &trb[rowc + ax];
+                const double* rd = &tph[rowc + dx0];
                 double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-                for (int kx = 0; kx < 5; ++kx) {
-                    const double rv = trb[base + kx], pv = tph[base + kx];
-                    a0 += wcx[kx] * rv;
-                    a1 += dcx[kx] * rv;
-                    b0 += fdx[kx] * pv;
-                    b1 += dfx[kx] * pv;
+                for (int a = 0; a < 4; ++a) {
+                    const double rv = ra[a], dv = rd[a];
+                    a0 += wcx[a] * rv;
+                    a1 += dcx[a] * rv;
+                    b0 += wfx[a] * dv;
+                    b1 += dfx[a] * dv;
                 }
-                c00 += wcy[ky] * a0;
-                c10 += wcy[ky] * a1;
-                c01 += dcy[ky] * a0;
-                e00 += wcy[ky] * b0;
-                e10 += wcy[ky] * b1;
-                e01 += dcy[ky] * b0;
+                c00 += wcy[b] * a0;
+                c10 += wcy[b] * a1;
+                c01 += dcy[b] * a0;
+                e00 += wcy[b] * b0;
+                e10 += wcy[b] * b1;
+                e01 += dcy[b] * b0;
             }
-            R += wcz[kz] * c00;
-            Rx += wcz[kz] * c10;
-            Ry += wcz[kz] * c01;
-            Rz += dcz[kz] * c00;
-            P += wcz[kz] * e00;
-            Px += wcz[kz] * e10;
-            Py += wcz[kz] * e01;
-            Pz += dcz[kz] * e00;
+            R += wcz[c] * c00;
+            Rx += wcz[c] * c10;
+            Ry += wcz[c] * c01;
+            Rz += dcz[c] * c00;
+            P += wcz[c] * e00;
+            Px += wcz[c] * e10;
+            Py += wcz[c] * e01;
+            Pz += dcz[c] * e00;
         }
         const double ih = g.inv_h;
         const double Ex = -ih * P;

@@ -60,6 +60,25 @@ def test_forward_and_backward_parity(bc):
     assert rel_l2(got["e_ext"], ref["e_ext"]) < TOL
 
 
+@pytest.mark.parametrize("shape", [(8, 16, 9, 120), (64, 8, 20, 700), (32, 32, 37, 900)])
+def test_parity_tile_shapes(shape):
+    """Grids narrower than a tile (one tile spans the periodic x or y axis), several
+    tiles with a ragged last z tile, wall-hugging ions: the face accumulation of the
+    transposed E_x gather and the 4^3 gradient windows at tile seams."""
+    nx, ny, nz, n = shape
+    grid, pos, q, p = _case((N, D), nx=nx, ny=ny, nz=nz, n=n, seed=11)
+    ref = adjoint.gradients(grid, pos, q, p, gU=0.4, gQ=-0.9)
+    out, got = _gpu_grads(_ctx(grid, pos.shape[1]), pos, q, p, 0.4, -0.9)
+    log(f"adjoint shape {shape}: pos {rel_l2(got['pos'], ref['pos']):.2e} "
+        f"bc_lo {rel_l2(got['bc_lo'], ref['bc'][0]):.2e}")
+    assert abs(out[1] - ref["Q"]) <= TOL * abs(ref["Q"])
+    for k in ("pos", "q"):
+        assert rel_l2(got[k], ref[k]) < TOL
+    assert rel_l2(got["bc_lo"], ref["bc"][0]) < TOL
+    assert rel_l2(got["bc_hi"], ref["bc"][1]) < TOL
+    assert rel_l2(got["e_ext"], ref["e_ext"]) < TOL
+
+
 @pytest.mark.parametrize("gU,gQ", [(1.0, 0.0), (0.0, 1.0)])
 def test_each_functional_alone(gU, gQ):
     grid, pos, q, p = _case((D, N), seed=5)
