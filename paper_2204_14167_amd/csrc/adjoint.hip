@@ -280,7 +280,7 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
 // ---- per-ion gradients: gather of rbar (homogeneous folds) and phi (wall ghosts) ----
 #define GT_TX 16
 #define GT_TY 16
-#define GT_TZ 4
+#define GT_TZ 6
 #define GT_H 5
 #define GT_THREADS 256
 #define GT_MAXR 64
