@@ -1,0 +1,123 @@
+"""Wall mobility of the hydrodynamic kernel, measured on the GPU Stokes solver, and the
+fit of eq fitfunction (Sec. III.A, the measurement of the gamma functions).
+
+A single ion is placed at height z in the channel, kT = 0, a unit force is applied along
+x (parallel) or z (perpendicular), and the ion's velocity J L^-1 S F is read back:
+discos_spread (S^hy), discos_solve_stokes without noise (no-slip walls), and
+discos_interpolate (J^hy) on the library, one pull per height and direction.  The
+mobility divided by the free-space mobility 1 / (6 pi eta a_w) of the kernel gives
+gamma(y) with y the distance to the nearest wall; a_w = 1.2555 h for the 4-point Peskin
+kernel.
+
+The fit follows the paper's procedure (least squares including the point (0, 0)), with
+the pole offsets c3, c5, c7 of eq fitfunction bounded below: with offsets near zero the
+fitted function has poles just outside the channel and swings far outside [0, 1]
+between the wall and the first measured height.
+
+  python -m paper_2204_14167_amd.mobility_measure --nx 128 --ny 128 --nz 24 --out fit.json
+"""
+import argparse
+import json
+
+import numpy as np
+
+PESKIN4_RADIUS = 1.2555  # free-space hydrodynamic radius of the 4-point Peskin kernel, in h
+
+
+def _params(eta):
+    # only eta enters the deterministic pull; the electrostatic fields are unused
+    return dict(eps=1.0, bc_types=(0, 0), bc_values=None, eta=eta, kT=0.0, dt=1.0)
+
+
+def pull_mobility(ctx, heights, eta, x0, y0):
+    """Mobility (velocity per unit force) of a single ion at (x0, y0, z) for each z in
+    heights: parallel (force and velocity along x) and perpendicular (along z)."""
+    import torch
+    from . import discos
+    prm = ctx.params(_params(eta))
+    par = np.empty(len(heights))
+    perp = np.empty(len(heights))
+    for k, z in enumerate(heights):
+        pos = torch.tensor([[x0], [y0], [float(z)]], dtype=torch.float64, device="cuda")
+        for d, out in ((0, par), (2, perp)):
+            F = torch.zeros((3, 1), dtype=torch.float64, device="cuda")
+            F[d, 0] = 1.0
+            f = ctx.spread(discos.SPREAD_FORCE, pos, F, prm)
+            v = ctx.solve_stokes(f, prm, noise=False)
+            u = ctx.interpolate(discos.INTERP_VEL, pos, v, prm)
+            out[k] = float(u[d, 0])
+    ctx.check()
+    return par, perp
+
+
+def measure(nx, ny, nz, h=1.0, eta=1.0 / (6.0 * np.pi), heights=None, x0=None, y0=None):
+    """gamma_parallel(y), gamma_perpendicular(y) at the wall distances y = heights (from
+    the lower wall, default 0 .. Lz/2 in steps of h/8), relative to the free-space
+    mobility of the kernel."""
+    from . import discos
+    Lz = nz * h
+    if heights is None:
+        heights = np.arange(0.0, Lz / 2.0 + 1e-12, h / 8.0)
+    heights = np.asarray(heights, dtype=np.float64)
+    x0 = 0.5 * nx * h if x0 is None else x0
+    y0 = 0.5 * ny * h if y0 is None else y0
+    ctx = discos.Context(nx, ny, nz, h, 1, hydro=True)
+    try:
+        par, perp = pull_mobility(ctx, heights, eta, x0, y0)
+    finally:
+        ctx.close()
+    mu0 = 1.0 / (6.0 * np.pi * eta * PESKIN4_RADIUS * h)
+    return heights, par / mu0, perp / mu0
+
+
+def fit_function(y, c):
+    """eq fitfunction."""
+    return c[0] + c[1] / (c[2] + y) + c[3] / (c[4] + y) ** 3 + c[5] / (c[6] + y) ** 5
+
+
+def fit(y, gamma, pole_min=0.25):
+    """Least-squares c1..c7 of eq fitfunction to gamma(y), the point (0, 0) included,
+    with c3, c5, c7 in [pole_min, 20]; returns (c, max |residual|)."""
+    from scipy.optimize import least_squares
+    ys = np.concatenate([[0.0], np.asarray(y, dtype=np.float64)])
+    ts = np.concatenate([[0.0], np.asarray(gamma, dtype=np.float64)])
+
+    def resid(c):
+        return fit_function(ys, c) - ts
+
+    lo = [-np.inf, -np.inf, pole_min, -np.inf, pole_min, -np.inf, pole_min]
+    hi = [np.inf, np.inf, 20.0, np.inf, 20.0, np.inf, 20.0]
+    best = None
+    for c0 in ([1.0, -0.6, 1.0, 0.1, 1.0, 0.0, 1.0], [1.0, -1.0, 0.5, 0.5, 2.0, -0.1, 3.0]):
+        sol = least_squares(resid, np.array(c0), bounds=(lo, hi), xtol=1e-14, ftol=1e-14,
+                            gtol=1e-14, max_nfev=20000)
+        if best is None or sol.cost < best.cost:
+            best = sol
+    return best.x, float(np.abs(resid(best.x)).max())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nx", type=int, default=128)
+    ap.add_argument("--ny", type=int, default=128)
+    ap.add_argument("--nz", type=int, default=24)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    y, gpar, gperp = measure(args.nx, args.ny, args.nz)
+    res = {"grid": [args.nx, args.ny, args.nz], "y": y.tolist(),
+           "gamma_parallel": gpar.tolist(), "gamma_perpendicular": gperp.tolist()}
+    for name, g in (("parallel", gpar), ("perpendicular", gperp)):
+        # the fit takes the measured points beyond the wall itself ((0, 0) is added)
+        c, r = fit(y[1:], g[1:])
+        res[name] = c.tolist()
+        res[name + "_max_residual"] = r
+    text = json.dumps(res, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    else:
+        print(text)
+
+
+if __name__ == "__main__":
+    main()
