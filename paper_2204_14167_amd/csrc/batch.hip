@@ -244,6 +244,11 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     std::vector<std::pair<int, int>> tw_at;
     for (auto& k : b->classes) tw_at.push_back({tw_of(k.nx), tw_of(k.ny)});
 
+    // neighbour lists sized for the densest channel
+    double rho_max = 0.0;
+    for (int r = 0; r < count; ++r)
+        rho_max = std::max(rho_max, (double)reps[r].n / ((double)reps[r].nx * reps[r].ny * reps[r].nz * h * h * h));
+    b->nl_cap = discos::near_list_capacity(h, p, rho_max);
     // one allocation
     const size_t n = (size_t)std::max<int64_t>(n_tot, 1);
     const size_t nblk = (size_t)(b->nbins_tot + 1023) / 1024 + 1;
@@ -258,7 +263,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     bytes += carve_bytes(std::max<int64_t>(zg_len, 1), sizeof(double));
     for (int v = 0; v < 3; ++v) bytes += carve_bytes(std::max<size_t>(zt[v].size(), 1), sizeof(int2));
     bytes += carve_bytes(3 * n, sizeof(double));
-    bytes += carve_bytes(64 * n, sizeof(int)) + carve_bytes(n, sizeof(int));
+    bytes += carve_bytes((size_t)b->nl_cap * n, sizeof(int)) + carve_bytes(n, sizeof(int));
     bytes += carve_bytes(64, sizeof(int)) + carve_bytes(1, sizeof(uint64_t));
     bytes += carve_bytes(count + 1, sizeof(int)) + carve_bytes(count, sizeof(int));
     bytes += carve_bytes(count, sizeof(discos::RepDev));
@@ -292,7 +297,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         b->ztasks_n[v] = (int)zt[v].size();
     }
     b->fp = carve<double>(cur, 3 * n);
-    b->nlist = carve<int>(cur, 64 * n);
+    b->nlist = carve<int>(cur, (size_t)b->nl_cap * n);
     b->ncount = carve<int>(cur, n);
     b->flags = carve<int>(cur, 64);
     b->step_d = carve<uint64_t>(cur, 1);

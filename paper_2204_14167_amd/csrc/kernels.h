@@ -99,6 +99,7 @@ struct Batch {
     double* zg;                    // pivots of every shape, [nz][nmode] each
     bool z_legacy = false;         // some channel has nz > 128 (per-mode Thomas, scratch cprime)
     bool z_singular = false;       // both walls Neumann
+    int nl_cap = 64;               // neighbour-list entries per ion (densest channel)
     std::vector<BatchClass> classes;
     double* walls;                 // per-channel wall fields [2][ny][nx], back to back
     double4* sxyzq;
@@ -202,5 +203,6 @@ int batch_near(Batch* b, hipStream_t s);
 int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s);
 int batch_set_step(Batch* b, uint64_t v, hipStream_t s);
 int near_radius_bins_h(double h, const discos_params* p);
+int near_list_capacity(double h, const discos_params* p, double rho_max);
 
 }  // namespace discos

@@ -8,6 +8,8 @@
 
 namespace discos {
 
+#define NL_CAP_DEFAULT 64  // list entries per ion of a single context
+
 struct NearDev {
     double psi, psi2, psi2g, inv4pieps, h, inv_h2, inv_hdr;
     double rsearch;  // search radius: psi, or the LJ range if larger
@@ -22,6 +24,7 @@ struct NearDev {
     const double* ljx;
     double ljf;
     int nsp;
+    int cap;  // list entries per ion (a multiple of 4); longer lists take the cache-read path
 };
 
 static NearDev near_of_h(double h, const discos_params* p) {
@@ -50,12 +53,24 @@ static NearDev near_of_h(double h, const discos_params* p) {
     d.ljx = p->lj_xi;
     d.ljf = p->lj_cut_factor;
     d.nsp = p->nspecies;
+    d.cap = NL_CAP_DEFAULT;
     return d;
 }
 
 static NearDev near_of(const Ctx* c, const discos_params* p) { return near_of_h(c->grid.h, p); }
 
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
+
+// List capacity for ion densities up to rho_max (ions per unit volume): the mean number
+// of candidates inside the search sphere (wall images replace the part of the sphere
+// beyond a wall, so the sphere bounds them), 25 % more for the FP32 margin and bin
+// shapes, plus six standard deviations; at least the single-context capacity.
+int near_list_capacity(double h, const discos_params* p, double rho_max) {
+    const double r = near_of_h(h, p).rsearch;
+    const double mean = 1.25 * (4.0 / 3.0) * M_PI * r * r * r * rho_max;
+    const int cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+    return std::max(NL_CAP_DEFAULT, (cap + 3) & ~3);
+}
 int near_radius_bins_h(double h, const discos_params* p) { return near_of_h(h, p).R; }
 
 // 1/sqrt(r2) to full FP64 accuracy: hardware estimate plus two Newton steps.
@@ -191,7 +206,6 @@ __device__ void near_force_global(int i, double4 me, int spi, const double4* __r
 // pair arithmetic, which then runs only on pairs inside the cutoff.  Lists are written
 // and read in chunks of four entries; chunk c of ion i sits at [c * n + i], so the
 // chunk reads of a wavefront are contiguous.
-#define NL_CAP 64  // list entries per ion; longer lists take the cache-read path
 #define NL_TAB 320
 
 __device__ __forceinline__ double shift_of(int code, double L) {
@@ -289,7 +303,7 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
                             h1 = slot == 1 ? e : h1;
                             h2 = slot == 2 ? e : h2;
                             h3 = slot == 3 ? e : h3;
-                            if (slot == 3 && nh < NL_CAP)
+                            if (slot == 3 && nh < P.cap)
                                 chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
                             ++nh;
                         }
@@ -299,7 +313,7 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
         }
     }
     // the incomplete last chunk
-    if ((nh & 3) && nh <= NL_CAP) chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
+    if ((nh & 3) && nh <= P.cap) chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
     count[i] = nh;
 }
 
@@ -336,7 +350,7 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
                                            const NearDev& P, double& Fx, double& Fy, double& Fz) {
     const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (cnt <= NL_CAP) {
+    if (cnt <= P.cap) {
         const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
         const int4* chunks = reinterpret_cast<const int4*>(list);
         for (int k4 = 0; k4 < cnt; k4 += 4) {
@@ -592,7 +606,8 @@ __global__ void step_set_kernel(uint64_t* step, uint64_t v) { *step = v; }
 int batch_near(Batch* b, hipStream_t s) {
     const int n = (int)b->n_tot;
     if (n == 0) return DISCOS_OK;
-    const NearDev P = near_of_h(b->h, &b->p);
+    NearDev P = near_of_h(b->h, &b->p);
+    P.cap = b->nl_cap;
     const int T = b->cfg.ion_block;
     near_list_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
                                                          b->sxyzf, b->bin_start, b->nlist, b->ncount);
