@@ -96,6 +96,32 @@ def fit(y, gamma, pole_min=0.25):
     return best.x, float(np.abs(resid(best.x)).max())
 
 
+def mixed_dry_gamma(nx, ny, nz, h=1.0, factor=2, eta=1.0 / (6.0 * np.pi)):
+    """Dry mobility function of a mixed wet / dry run (eq diff2),
+        Gamma = (gamma_tot D_tot - gamma_wet D_wet) / D_dry,
+    with gamma_tot measured on the fully wet grid (nz cells of size h, kernel radius
+    a_t = 1.2555 h) and gamma_wet on the same channel with cells `factor` times larger
+    (the grid of the wet fraction 1 / factor, kernel radius a_w = factor a_t).  With
+    D = kT / (6 pi eta a) and D_dry = D_tot - D_wet (1 / a_d = 1 / a_t - 1 / a_w) this is
+        Gamma = (gamma_tot - gamma_wet / factor) / (1 - 1 / factor).
+    Returns the wall distances y (those of the coarse grid's pulls, 0 .. Lz/2 in steps of
+    factor h / 8), Gamma parallel and perpendicular, and the dry radius a_d."""
+    if factor < 2 or nx % factor or ny % factor or nz % factor:
+        raise ValueError("factor must be an integer >= 2 dividing nx, ny and nz")
+    Lz = nz * h
+    hw = factor * h
+    y = np.arange(0.0, Lz / 2.0 + 1e-12, hw / 8.0)
+    _, tpar, tperp = measure(nx, ny, nz, h, eta, heights=y)
+    _, wpar, wperp = measure(nx // factor, ny // factor, nz // factor, hw, eta, heights=y)
+    # measure() normalises by the free-space mobility of its own grid's kernel
+    scale = 1.0 / (1.0 - 1.0 / factor)
+    gpar = (tpar - wpar / factor) * scale
+    gperp = (tperp - wperp / factor) * scale
+    a_t = PESKIN4_RADIUS * h
+    a_d = 1.0 / (1.0 / a_t - 1.0 / (factor * a_t))
+    return y, gpar, gperp, a_d
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--nx", type=int, default=128)

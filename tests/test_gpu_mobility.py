@@ -52,3 +52,28 @@ def test_measured_channel_mobility_and_fit():
         assert res < 0.03
         assert f.min() > -0.05 and f.max() < 1.0
         assert min(c[2], c[4], c[6]) >= 0.25 - 1e-12
+
+
+def test_mixed_wet_dry_gamma():
+    """eq diff2 on the 50 % wet grid: the dry part Gamma vanishes on the wall, matches the
+    same combination of the analytic channel mobilities away from it, and its fit stays
+    bounded."""
+    from paper_2204_14167_amd import mobility_measure as mm
+    nz = 24
+    y, gpar, gperp, a_d = mm.mixed_dry_gamma(128, 128, nz, factor=2)
+    a_t = mm.PESKIN4_RADIUS
+    assert abs(a_d - 2.0 * a_t) < 1e-12  # 50 % wet: a_d = a_w = 2 a_t
+    assert gpar[0] == 0.0 and abs(gperp[0]) < 1e-14
+    far = y >= 4.0
+    for name, g, direction in (("parallel", gpar, mobility.PAR), ("perpendicular", gperp, mobility.PERP)):
+        ref = 2.0 * (mobility.gamma_channel(y[far], a_t, float(nz), direction)
+                     - 0.5 * mobility.gamma_channel(y[far], 2.0 * a_t, float(nz), direction))
+        dev = np.abs(g[far] - ref).max()
+        c, res = mm.fit(y[1:], g[1:])
+        f = mm.fit_function(np.linspace(0.0, nz / 2.0, 4001), c)
+        log(f"mixed {name}: max |Gamma - analytic| {dev:.4f} (y >= 4), fit residual {res:.4f}, "
+            f"fit range [{f.min():.4f}, {f.max():.4f}]")
+        # two measured mobilities, each within a few % of the superposition formula
+        assert dev < 0.08
+        assert res < 0.05
+        assert f.min() > -0.1 and f.max() < 1.1
