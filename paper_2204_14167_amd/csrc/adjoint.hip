@@ -12,9 +12,9 @@
 // signs s.
 //
 // Reverse sweep for cotangents (gU, gQ):
-//   lambda_i = gQ w_i q_i on E_x,i  ->  transposed E_x gather (face differences, ghost
-//   folds; the ghost layers' dependence on the wall fields gives part of their
-//   gradient)  ->  mu = A^+ lambda_phi (one Poisson solve)  ->  rbar = gU dV phi + mu,
+//   lambda_i = gQ w_i q_i on E_x,i  ->  transposed E_x gather (onto x-faces with the
+//   face weights, then the transposed face difference; ghost folds, and the ghost
+//   layers' dependence on the wall fields gives part of their gradient)  ->  mu = A^+ lambda_phi (one Poisson solve)  ->  rbar = gU dV phi + mu,
 //   the cotangent of rho  ->  per ion: dq = (J rbar)/dV + gQ w (E_x + E_ext,x),
 //   dx = q grad(J rbar)/dV + gQ w q grad E_x + gQ F_x w'(z) e_z  (J with the
 //   homogeneous folds of S);  wall fields: B^T rbar + ghost part;  dE_ext,x = gQ sum q w.
@@ -37,35 +37,6 @@ __device__ __forceinline__ void peskin4_d(double s, int& i0, double w[4], double
     dw[1] = (-2.0 + dq) * 0.125;
     dw[2] = (2.0 + dq) * 0.125;
     dw[3] = (2.0 - dq) * 0.125;
-}
-
-// On the 5-cell window c-2 .. c+2 (c = floor(u)): centre weights wc and d/du, and the
-// face-difference weights fd (E component along this axis: -(1/h) sum fd phi) and d/du.
-__device__ __forceinline__ int window_weights_d(double u, double wc5[5], double dc5[5],
-                                                double fd5[5], double df5[5]) {
-    int ic, iff;
-    double wc[4], dc[4], wf[4], df[4];
-    peskin4_d(u - 0.5, ic, wc, dc);
-    peskin4_d(u, iff, wf, df);
-    const int c = iff + 1;
-    const bool shift = (ic - (c - 2)) != 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const double lo = (k < 4) ? wc[k] : 0.0, hi = (k > 0) ? wc[k - 1] : 0.0;
-        const double dlo = (k < 4) ? dc[k] : 0.0, dhi = (k > 0) ? dc[k - 1] : 0.0;
-        wc5[k] = shift ? hi : lo;
-        dc5[k] = shift ? dhi : dlo;
-    }
-    fd5[0] = -wf[0];
-    df5[0] = -df[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-        fd5[k] = wf[k - 1] - wf[k];
-        df5[k] = df[k - 1] - df[k];
-    }
-    fd5[4] = wf[3];
-    df5[4] = df[3];
-    return c;
 }
 
 struct FluxDev {
@@ -277,7 +248,8 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
         store(tx, ty);
 }
 
-// ---- per-ion gradients: gather of rbar (homogeneous folds) and phi (wall ghosts) ----
+// ---- per-ion gradients: gather of rbar (homogeneous folds) on the centre window and of
+// the x-face differences of phi_ext (wall ghosts) on the face window ------------------
 #define GT_TX 16
 #define GT_TY 16
 #define GT_TZ 6

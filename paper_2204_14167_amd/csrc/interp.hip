@@ -14,7 +14,8 @@
 //
 // One workgroup owns a tile of cells, stages phi on the tile plus its halo in LDS
 // (ghost layers included, so the gathers have no branches), and interpolates every
-// ion of the tile from the cell list.
+// ion of the tile from the cell list.  Tiles without ions stage nothing; tiles with a
+// few ions (sparse channels of a batch) read their windows straight from memory.
 #include "kernels.h"
 
 namespace discos {
