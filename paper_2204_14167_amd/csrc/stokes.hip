@@ -69,9 +69,9 @@ __device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int 
 
 // S^hy F on one face grid; with rfd.scale != 0 every ion also deposits the random
 // finite difference (kT / delta) [phi(x + delta/2 W) - phi(x - delta/2 W)] W_COMP of
-// the thermal forcing.  The shifts are below half a cell, so the shifted kernels
-// reach only nodes within two cells of the ion's own cell, the range the tile's
-// candidate rows cover.
+// the thermal forcing.  The shifts are below half a cell: along an axis whose nodes
+// sit on faces, a kernel shifted up from the cell below the tile's two-cell window
+// reaches the tile's first node, so the candidate rows then reach three cells down.
 template <int COMP>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
@@ -86,7 +86,7 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
     // ions that can reach node levels [z0, z0+tz): cells [z0-2, z0+tz+1]
     const int nr = tile_ranges<SH_MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
-                                 rpre, scan);
+                                 rpre, scan, rfd.scale != 0.0 ? 3 : 2);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {

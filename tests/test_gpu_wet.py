@@ -96,3 +96,36 @@ def test_wet_step_rejections():
         ctx.step(*args, ctx.params(p), 0, mode=2)
     # nothing was launched: the ions are untouched
     assert np.array_equal(host(args[0]), pos)
+
+
+def test_wet_step_rfd_shifted_kernels_at_tile_edges():
+    """Random finite difference with the largest step (delta = 0.1 h): ions just below
+    the lower edge of a tile's gathered cells (x, y, z = 14 - eps or 30 - eps on a 32^3
+    grid with 16^3 force tiles) reach the tile's first nodes only through their shifted
+    kernels; the step must still equal the oracle's."""
+    from paper_2204_14167_amd import discos
+    w = workloads.WORKLOADS["dirichlet_32x32x32_n256"]
+    p = workloads.make_params(w)
+    delta = 0.1 * w.h
+    p["rfd_delta"] = delta
+    pos, q, ids, species = workloads.make_ions(w)
+    rng = np.random.default_rng(41)
+    n = w.n
+    k = np.arange(n)
+    edge = np.where(rng.uniform(size=n) < 0.5, 14.0, 30.0) - rng.uniform(1e-4, 0.02, n)
+    axis = k % 3
+    for d in range(3):
+        sel = axis == d
+        pos[d, sel] = edge[sel]
+    pos[2] = np.clip(pos[2], 1.0, w.nz - 1.0)
+    grid = es.Grid(w.nx, w.ny, w.nz, w.h)
+    ctx = _ctx(w)
+    dp = ctx.params(p)
+    args = (dev(pos), dev(q), dev(ids), dev(species))
+    ref, _, _ = dynamics.wet_step(grid, pos, q, species, ids, p, 3, rfd_delta=delta, near="brute")
+    ctx.step(*args, dp, 3, mode=discos.STEP_WET | discos.STEP_RFD)
+    ctx.check()
+    got = by_id(host(args[0]), host(args[2]), ids)
+    r = np.linalg.norm(min_image(got - ref, grid.L)) / np.linalg.norm(min_image(ref - pos, grid.L))
+    log(f"rfd at tile edges rel={r:.3e}")
+    assert r < TOL
