@@ -149,7 +149,31 @@ def confine(grid, pos):
     return out
 
 
-def thermal_forcing(grid, pos, ids, kT, delta, seed, step):
+def hydro_kernels(p, species):
+    """Per-ion hydrodynamic kernels (w, beta) from p["hydro_kernel"] ([nspecies][2], w = 0
+    for the 4-point Peskin kernel), or None when every species uses the Peskin kernel."""
+    hk = p.get("hydro_kernel")
+    if hk is None:
+        return None
+    hk = np.asarray(hk, dtype=np.float64).reshape(-1, 2)
+    if np.all(hk[:, 0] == 0):
+        return None
+    return hk[np.asarray(species, dtype=np.int64)]
+
+
+def _spread(grid, pos, F, kernels, slack=0.0):
+    if kernels is None:
+        return stokes.spread_force(grid, pos, F, slack=slack)
+    return stokes.spread_force_kernels(grid, pos, F, kernels, slack=slack)
+
+
+def _interp(grid, pos, u, v, w, kernels):
+    if kernels is None:
+        return stokes.interp_velocity(grid, pos, u, v, w)
+    return stokes.interp_velocity_kernels(grid, pos, u, v, w, kernels)
+
+
+def thermal_forcing(grid, pos, ids, kT, delta, seed, step, kernels=None):
     """f^th = kT div_x S^hy (eq thermforce) by the random finite difference
     (kT / delta) [S(x + delta/2 W) W - S(x - delta/2 W) W], W ~ N(0, I) per ion."""
     if not delta > 0.0:
@@ -158,8 +182,8 @@ def thermal_forcing(grid, pos, ids, kT, delta, seed, step):
     half = 0.5 * delta * W
     if np.abs(half).max(initial=0.0) >= grid.h:
         raise ValueError("random finite difference shift of a cell or more")
-    plus = stokes.spread_force(grid, pos + half, W, slack=grid.h)
-    minus = stokes.spread_force(grid, pos - half, W, slack=grid.h)
+    plus = _spread(grid, pos + half, W, kernels, slack=grid.h)
+    minus = _spread(grid, pos - half, W, kernels, slack=grid.h)
     return tuple(kT / delta * (a - b) for a, b in zip(plus, minus))
 
 
@@ -168,9 +192,10 @@ def wet_step(grid, pos, q, species, ids, p, step, noise=True, rfd_delta=0.0, nea
     """One wet step (eq disc_stokes_temp, eq step1, eq step2); returns
     (new positions of `targets` (all ions by default), F, intermediates)."""
     F, parts = total_force(grid, pos, q, species, p, near=near)
-    fx, fy, fz = stokes.spread_force(grid, pos, F)
+    kern = hydro_kernels(p, species)
+    fx, fy, fz = _spread(grid, pos, F, kern)
     if rfd_delta > 0.0:
-        tx, ty, tz = thermal_forcing(grid, pos, ids, p["kT"], rfd_delta, p["seed"], step)
+        tx, ty, tz = thermal_forcing(grid, pos, ids, p["kT"], rfd_delta, p["seed"], step, kern)
         fx, fy, fz = fx + tx, fy + ty, fz + tz
     if noise:
         nfx, nfy, nfz = stokes.noise_force(grid, p["kT"], p["eta"], p["dt"], p["seed"], step)
@@ -179,9 +204,10 @@ def wet_step(grid, pos, q, species, ids, p, step, noise=True, rfd_delta=0.0, nea
     sel = slice(None) if targets is None else np.asarray(targets)
     x0 = pos[:, sel]
     dt = p["dt"]
-    V0 = stokes.interp_velocity(grid, x0, u, v, w)
+    ksel = None if kern is None else kern[sel]
+    V0 = _interp(grid, x0, u, v, w, ksel)
     mid = confine(grid, x0 + 0.5 * dt * V0)
-    V1 = stokes.interp_velocity(grid, mid, u, v, w)
+    V1 = _interp(grid, mid, u, v, w, ksel)
     disp = dt * V1 + dry_displacement(grid, x0, F[:, sel], species[sel], ids[sel], p, step)
     new = confine(grid, x0 + disp)
     return new, F, dict(parts, V0=V0, V1=V1, mid=mid, vel=(u, v, w))

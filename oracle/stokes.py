@@ -26,6 +26,7 @@ tests).  The paper puts Delta t under the square root and also calls the Gaussia
 import numpy as np
 from scipy.linalg import solve_banded
 
+from . import esc
 from .peskin import node_weights
 from .rng import TAG_STRESS_DIAG, TAG_STRESS_EDGE, normal_pair
 
@@ -78,6 +79,72 @@ def spread_force(grid, pos, F, slack=0.0):
             arr[nz] = 0.0
         out.append(arr)
     return tuple(out)
+
+
+def _kernel_groups(kernels, n):
+    """(kernel, ion indices) for each distinct hydrodynamic kernel; kernels is an [n, 2]
+    array of (w, beta) per ion (w = 0: 4-point Peskin)."""
+    kk = np.asarray(kernels, dtype=np.float64).reshape(n, 2)
+    groups = {}
+    for i in range(n):
+        groups.setdefault((int(kk[i, 0]), float(kk[i, 1])), []).append(i)
+    return [(k, np.array(v, dtype=np.int64)) for k, v in groups.items()]
+
+
+def spread_force_kernels(grid, pos, F, kernels, slack=0.0):
+    """S^hy F as spread_force, each ion with its own kernel (oracle.esc): the kernel's
+    nodes on the nine-node window, the same no-slip folds."""
+    _check(grid, pos, slack)
+    nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
+    out = [np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx)), np.zeros((nz + 1, ny, nx))]
+    for kern, idx in _kernel_groups(kernels, pos.shape[1]):
+        p = pos[:, idx]
+        for comp, offs in ((0, (0.0, 0.5, 0.5)), (1, (0.5, 0.0, 0.5)), (2, (0.5, 0.5, 0.0))):
+            ix, wx = esc.node_weights_kernel(p[0], h, offs[0], kern, nx)
+            iy, wy = esc.node_weights_kernel(p[1], h, offs[1], kern, ny)
+            iz, wz = esc.node_weights_kernel(p[2], h, offs[2], kern)
+            s = np.ones_like(wz)
+            if comp < 2:
+                lo, hi = iz < 0, iz >= nz
+                iz = np.where(lo, -1 - iz, np.where(hi, 2 * nz - 1 - iz, iz))
+            else:
+                lo, hi = iz < 0, iz > nz
+                iz = np.where(lo, -iz, np.where(hi, 2 * nz - iz, iz))
+            s[lo] = -1.0
+            s[hi] = -1.0
+            f = F[comp, idx]
+            for c in range(9):
+                for b in range(9):
+                    for a in range(9):
+                        np.add.at(out[comp], (iz[:, c], iy[:, b], ix[:, a]),
+                                  f * s[:, c] * wx[:, a] * wy[:, b] * wz[:, c] / h ** 3)
+    out[2][0] = 0.0
+    out[2][nz] = 0.0
+    return tuple(out)
+
+
+def interp_velocity_kernels(grid, pos, u, v, w, kernels):
+    """J^hy v as interp_velocity, each ion with its own kernel, ghosts five layers deep."""
+    _check(grid, pos)
+    nx, ny, h = grid.nx, grid.ny, grid.h
+    depth = 5
+    fields = (_ghost_tangential(u, depth), _ghost_tangential(v, depth), _ghost_normal(w, depth))
+    out = np.zeros((3, pos.shape[1]))
+    for kern, idx in _kernel_groups(kernels, pos.shape[1]):
+        p = pos[:, idx]
+        for comp, offs in ((0, (0.0, 0.5, 0.5)), (1, (0.5, 0.0, 0.5)), (2, (0.5, 0.5, 0.0))):
+            ix, wx = esc.node_weights_kernel(p[0], h, offs[0], kern, nx)
+            iy, wy = esc.node_weights_kernel(p[1], h, offs[1], kern, ny)
+            iz, wz = esc.node_weights_kernel(p[2], h, offs[2], kern)
+            iz = iz + depth
+            f = fields[comp]
+            acc = np.zeros(idx.size)
+            for c in range(9):
+                for b in range(9):
+                    for a in range(9):
+                        acc += wx[:, a] * wy[:, b] * wz[:, c] * f[iz[:, c], iy[:, b], ix[:, a]]
+            out[comp, idx] = acc
+    return out
 
 
 def _ghost_tangential(a, depth=3):
@@ -307,11 +374,17 @@ def noise_force(grid, kT, eta, dt, seed, step):
     return amp * fx, amp * fy, amp * fz
 
 
-def velocity_at_ions(grid, pos, F, eta, kT=0.0, dt=1.0, seed=0, step=0):
-    """V = J^hy L^-1 (S^hy F + noise) (eq ions2 without the thermal drift)."""
-    fx, fy, fz = spread_force(grid, pos, F)
+def velocity_at_ions(grid, pos, F, eta, kT=0.0, dt=1.0, seed=0, step=0, kernels=None):
+    """V = J^hy L^-1 (S^hy F + noise) (eq ions2 without the thermal drift); kernels:
+    per-ion hydrodynamic kernels (w, beta), or None for the 4-point Peskin kernel."""
+    if kernels is None:
+        fx, fy, fz = spread_force(grid, pos, F)
+    else:
+        fx, fy, fz = spread_force_kernels(grid, pos, F, kernels)
     if kT > 0.0:
         nx_, ny_, nz_ = noise_force(grid, kT, eta, dt, seed, step)
         fx, fy, fz = fx + nx_, fy + ny_, fz + nz_
     u, v, w, p = solve_stokes(grid, eta, fx, fy, fz)
-    return interp_velocity(grid, pos, u, v, w), (u, v, w, p)
+    if kernels is None:
+        return interp_velocity(grid, pos, u, v, w), (u, v, w, p)
+    return interp_velocity_kernels(grid, pos, u, v, w, kernels), (u, v, w, p)
