@@ -189,6 +189,32 @@ int discos_interpolate(discos_ctx* ctx, int op, int64_t n, const double* pos,
                        double* out, void* stream);
 
 /*
+ * Hydrodynamic kernel per species (App. B, eq eskernel; a project addition on Sec. III.B,
+ * where cations and anions use different kernels).  kernel: HOST array [nspecies][2] of
+ * (w, beta): w = 0 keeps the 4-point Peskin kernel; w = 2 .. 8 selects the ESC kernel
+ *   phi(zeta) = exp(beta (sqrt(1 - (zeta / alpha)^2) - 1)) / I,  alpha = w h / 2,
+ * normalised by its integral I, with beta in [0, 100].  Species beyond nspecies use the
+ * Peskin kernel; nspecies = 0 (or kernel = NULL) restores it for all.  The kernels apply
+ * to discos_spread_force_species, discos_interpolate_vel_species and the hydrodynamic
+ * stages of discos_step (S^hy, the random finite difference, J^hy); the plain
+ * DISCOS_SPREAD_FORCE and DISCOS_INTERP_VEL keep the Peskin kernel.  Needs
+ * DISCOS_CREATE_HYDRO and nz > w for every w > 0.  Errors: DISCOS_E_ARG, DISCOS_E_SHAPE.
+ */
+#define DISCOS_HY_MAXSP 8
+int discos_set_hydro_kernel(discos_ctx* ctx, int32_t nspecies, const double* kernel);
+
+/* S^hy F (as DISCOS_SPREAD_FORCE) with each ion's kernel chosen by its species (DEVICE
+ * [n], values in [0, nspecies of p]); out: the three face arrays back to back. */
+int discos_spread_force_species(discos_ctx* ctx, int64_t n, const double* pos, const double* F,
+                                const int32_t* species, const discos_params* p, double* out,
+                                void* stream);
+
+/* J^hy v (as DISCOS_INTERP_VEL) with each ion's kernel chosen by its species; out [3][n]. */
+int discos_interpolate_vel_species(discos_ctx* ctx, int64_t n, const double* pos, const double* v,
+                                   const int32_t* species, const discos_params* p, double* out,
+                                   void* stream);
+
+/*
  * Near-field pass: the P3M correction sum_j (F^C_ij - F^P_ij) over pairs closer than
  * psi (minimum image in x, y) and over the wall images of every ion (charge s q_j at
  * (x_j, y_j, -z_j) and (x_j, y_j, 2 Lz - z_j), s = -1 Dirichlet, +1 Neumann,

@@ -78,6 +78,65 @@ int check_near_params(discos_ctx* c, const discos_params* p, const int32_t* spec
     return DISCOS_OK;
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n from the
+// three-term recurrence, started at the Chebyshev-like guess cos(pi (k - 1/4) / (n + 1/2))).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt) {
+    x.assign(n, 0.0);
+    wt.assign(n, 0.0);
+    for (int k = 0; k < (n + 1) / 2; ++k) {
+        double z = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[k] = -z;
+        x[n - 1 - k] = z;
+        wt[k] = wt[n - 1 - k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Integral of exp(beta (sqrt(1 - (z / alpha)^2) - 1)) over (-alpha, alpha), in cells
+// (App. B, eq eskernel): with z = alpha sin(theta) the integrand becomes
+// alpha exp(beta (cos(theta) - 1)) cos(theta) on (-pi/2, pi/2), analytic, so composite
+// Gauss-Legendre (32 panels of 24 nodes) reaches rounding level for beta <= 100.
+double esc_integral(double w, double beta) {
+    std::vector<double> gx, gw;
+    gauss_legendre(24, gx, gw);
+    const double alpha = 0.5 * w;
+    const int panels = 32;
+    const double hw = M_PI / panels;
+    double sum = 0.0;
+    for (int pnl = 0; pnl < panels; ++pnl) {
+        const double c0 = -0.5 * M_PI + (pnl + 0.5) * hw;
+        double ps = 0.0;
+        for (size_t k = 0; k < gx.size(); ++k) {
+            const double th = c0 + 0.5 * hw * gx[k];
+            const double ct = std::cos(th);
+            ps += gw[k] * std::exp(beta * (ct - 1.0)) * ct;
+        }
+        sum += 0.5 * hw * ps;
+    }
+    return alpha * sum;
+}
+
 template <class T>
 T* carve(char*& cur, size_t count) {
     T* p = reinterpret_cast<T*>(cur);
@@ -203,6 +262,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         hb += 2 * carve_bytes(2 * ncell + nlev, sizeof(double));            // hvel, hfor
         hb += carve_bytes(3 * nm, sizeof(double));                          // hvi
         hb += carve_bytes(nm, sizeof(double4));                             // hmid
+        hb += carve_bytes(4 * DISCOS_HY_MAXSP, sizeof(double));              // kernel table
         void* hp = nullptr;
         if (hipMalloc(&hp, hb) != hipSuccess) {
             hipFree(c->pool);
@@ -219,9 +279,19 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hfor = carve<double>(hc, 2 * ncell + nlev);
         c->hvi = carve<double>(hc, 3 * nm);
         c->hmid = carve<double4>(hc, nm);
+        c->hy_tab = carve<double>(hc, 4 * DISCOS_HY_MAXSP);
+        // every species on the 4-point Peskin kernel (rows of zeros: w = 0)
+        if (hipMemset(c->hy_tab, 0, 4 * DISCOS_HY_MAXSP * sizeof(double)) != hipSuccess) {
+            hipFree(hp);
+            hipFree(c->pool);
+            delete c;
+            return DISCOS_E_HIP;
+        }
         c->hydro = 1;
     }
     c->zg_key = -1;
+    c->hy_km = 0;
+    if (!c->hydro) c->hy_tab = nullptr;
     c->last_stream = nullptr;
     c->err = "";
     c->profile = 0;
@@ -327,6 +397,77 @@ int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, cons
     return fail(c, DISCOS_E_ARG, "unknown interpolation op");
 }
 
+int discos_set_hydro_kernel(discos_ctx* c, int32_t nspecies, const double* kernel) {
+    if (!c) return DISCOS_E_ARG;
+    if (!c->hydro) return fail(c, DISCOS_E_ARG, "context created without DISCOS_CREATE_HYDRO");
+    if (nspecies < 0 || nspecies > DISCOS_HY_MAXSP)
+        return fail(c, DISCOS_E_ARG, "nspecies must lie in [0, DISCOS_HY_MAXSP]");
+    if (!kernel) nspecies = 0;
+    double tab[4 * DISCOS_HY_MAXSP] = {};
+    int km = 0;
+    bool any_esc = false;
+    for (int sp = 0; sp < nspecies; ++sp) {
+        const double w = kernel[2 * sp], beta = kernel[2 * sp + 1];
+        if (w == 0.0) {
+            km = std::max(km, 2);
+            continue;
+        }
+        if (!(w >= 2.0 && w <= 8.0 && w == std::floor(w)))
+            return fail(c, DISCOS_E_ARG, "kernel width w must be 0 or an integer in [2, 8]");
+        if (!(std::isfinite(beta) && beta >= 0.0 && beta <= 100.0))
+            return fail(c, DISCOS_E_ARG, "kernel beta must lie in [0, 100]");
+        if (c->grid.nz <= (int)w) return fail(c, DISCOS_E_SHAPE, "nz must exceed the kernel width");
+        const double norm = esc_integral(w, beta);
+        tab[4 * sp + 0] = w;
+        tab[4 * sp + 1] = beta;
+        tab[4 * sp + 2] = 2.0 / w;
+        tab[4 * sp + 3] = 1.0 / norm;
+        km = std::max(km, (int)std::ceil(0.5 * w));
+        any_esc = true;
+    }
+    // calls in flight may read the table: let them finish before it changes
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(c->hy_tab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, DISCOS_E_HIP, "kernel table upload failed");
+    c->hy_km = any_esc ? km : 0;
+    return DISCOS_OK;
+}
+
+int discos_spread_force_species(discos_ctx* c, int64_t n, const double* pos, const double* F,
+                                const int32_t* species, const discos_params* p, double* out,
+                                void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (!c->hydro) return fail(c, DISCOS_E_ARG, "context created without DISCOS_CREATE_HYDRO");
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (!out || (n > 0 && (!pos || !F || !species))) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, species, s,
+                                 F, n);
+    if (rc) return fail(c, rc, "cell list launch failed");
+    rc = discos::spread_force_sorted(c, out, s, nullptr, 1);
+    return rc ? fail(c, rc, "spread launch failed") : DISCOS_OK;
+}
+
+int discos_interpolate_vel_species(discos_ctx* c, int64_t n, const double* pos, const double* v,
+                                   const int32_t* species, const discos_params* p, double* out,
+                                   void* stream) {
+    if (!c) return DISCOS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (!c->hydro) return fail(c, DISCOS_E_ARG, "context created without DISCOS_CREATE_HYDRO");
+    if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+    if (n == 0) return DISCOS_OK;
+    if (!pos || !v || !out || !species) return fail(c, DISCOS_E_ARG, "null array");
+    int rc = check_es_params(c, p);
+    if (rc) return rc;
+    rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, species, s);
+    if (!rc) rc = discos::interp_hy_sorted(c, (int)n, v, out, n, 1, s, 1);
+    return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
+}
+
 int discos_near_field(discos_ctx* c, int64_t n, const double* pos, const double* q,
                       const int32_t* species, const discos_params* p, double* F, void* stream) {
     if (!c) return DISCOS_E_ARG;
@@ -394,11 +535,11 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
             rd.seed = p->seed;
             rd.step = step;
         }
-        rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr);
+        rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr, 1);
         discos::stage_mark(c, 11, s);
         if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 12, s);
-        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s);
+        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s, 1);
         discos::stage_mark(c, 13, s);
         vwet = c->hvi;
     } else {

@@ -231,17 +231,18 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
 
 // Cell-list rows of the ions that can reach the nodes of the tile [x0, x0+tx) x
 // [y0, y0+ty) x [z0, z0+tz) with a window of hlo cells below and two above (cells
-// x0-hlo .. x0+tx+1, periodic in x and y, clipped at the walls in z).  hlo = 2 covers
-// the 4-point kernel; kernels shifted by up to half a cell (the random finite
-// difference) reach one cell further down.  Thread t < MAXR owns one candidate row
-// (rstart[t], length from the prefix sums rpre); returns the row count.
+// x0-hlo .. x0+tx-1+hhi, periodic in x and y, clipped at the walls in z).  hlo = hhi = 2
+// covers the 4-point kernel (a kernel with a window of 2K nodes needs K); kernels shifted
+// by up to half a cell (the random finite difference) reach one cell further down.
+// Thread t < MAXR owns one candidate row (rstart[t], length from the prefix sums rpre);
+// returns the row count.  The caller sizes the tile so that the rows fit in MAXR.
 template <int MAXR>
 __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
                              int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan,
-                             int hlo = 2) {
+                             int hlo = 2, int hhi = 2) {
     int sa[2], sb[2], nseg;
     {
-        const int lo = floordiv(x0 - hlo, DISCOS_BIN), hi = floordiv(x0 + tx + 1, DISCOS_BIN);
+        const int lo = floordiv(x0 - hlo, DISCOS_BIN), hi = floordiv(x0 + tx - 1 + hhi, DISCOS_BIN);
         if (hi - lo + 1 >= g.nbx) {
             nseg = 1; sa[0] = 0; sb[0] = g.nbx - 1;
         } else {
@@ -250,9 +251,9 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
             else { nseg = 2; sa[0] = a; sb[0] = g.nbx - 1; sa[1] = 0; sb[1] = b; }
         }
     }
-    int ylo = floordiv(y0 - hlo, DISCOS_BIN), yhi = floordiv(y0 + ty + 1, DISCOS_BIN);
+    int ylo = floordiv(y0 - hlo, DISCOS_BIN), yhi = floordiv(y0 + ty - 1 + hhi, DISCOS_BIN);
     if (yhi - ylo + 1 >= g.nby) { ylo = 0; yhi = g.nby - 1; }
-    const int czlo = max(z0 - hlo, 0), czhi = min(z0 + tz + 1, g.nz - 1);
+    const int czlo = max(z0 - hlo, 0), czhi = min(z0 + tz - 1 + hhi, g.nz - 1);
     const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
     const int nyb = yhi - ylo + 1;
     const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;

@@ -47,6 +47,11 @@ struct Ctx {
     double4* hmid;    // [n_max] midpoint positions (x, y, z, q) in cell-list order
     double* part;     // [2][PART_MAX] partial sums of the deterministic reductions
     double* bcg;      // [2][ny][nx] wall-field adjoints gathered from the ghost layers
+    // hydrodynamic kernel per species: [DISCOS_HY_MAXSP][4] rows (w, beta, 1 / alpha,
+    // 1 / integral), w = 0 for the 4-point Peskin kernel (every row past the set ones);
+    // hy_km: half-width of the node window of the widest set kernel (0: all Peskin)
+    double* hy_tab;
+    int hy_km;
     int* flags;
     void* pool;
     void* hpool;
@@ -167,16 +172,18 @@ struct RfdDev {
 
 // S^hy of the sorted forces c->fp onto the three face arrays of out (+ the thermal
 // forcing when rfd is given).
-int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd = nullptr);
+// species != 0: each ion's kernel from c->hy_tab by its species c->ssp.
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd = nullptr,
+                        int species = 0);
 // Stokes solve with no-slip walls (f: three face arrays; vel likewise; pres nullable).
 int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
                  double* vel, double* pres, hipStream_t s);
 // J^hy of the face velocity for the ions of the cell list.
 int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
-                     hipStream_t s);
+                     hipStream_t s, int species = 0);
 
 // Predictor and corrector velocities of the wet step: c->hmid = x*, c->hvi = J(x*) v.
-int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s);
+int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s, int species = 0);
 
 // Update of the sorted ions from their complete forces c->fp (dry terms of eq step2)
 // plus dt * vwet (nullable, [3][n_max] sorted), written to the caller's arrays in

@@ -16,8 +16,6 @@ namespace discos {
 
 // ---- S^hy: force spreading on one face grid (tile gather, as the charge spread) ----
 #define SH_TX 16
-#define SH_TY 16
-#define SH_TZ 16
 #define SH_THREADS 256
 #define SH_MAXR 256
 
@@ -67,26 +65,115 @@ __device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int 
     }
 }
 
+// ---- hydrodynamic kernels per species (App. B, eq eskernel) ----------------------
+// Row of the kernel table for species sp: (w, beta, 1 / alpha, 1 / integral); species
+// outside the table use the last row, which is the 4-point Peskin kernel (w = 0).
+__device__ __forceinline__ const double* hy_row(const double* __restrict__ tab, int sp) {
+    return tab + 4 * ((sp >= 0 && sp < DISCOS_HY_MAXSP) ? sp : DISCOS_HY_MAXSP - 1);
+}
+
+// phi(zeta), zeta in cells: the 4-point Peskin kernel of eq peskin1d for w = 0, else
+// the ESC kernel exp(beta (sqrt(1 - (zeta / alpha)^2) - 1)) / integral, zero from
+// |zeta| = alpha = w / 2 on.
+__device__ __forceinline__ double hy_weight(double zeta, double w, double beta, double inv_alpha,
+                                           double inv_norm) {
+    const double r = fabs(zeta);
+    if (w == 0.0) {
+        if (r < 1.0) return (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r)) * 0.125;
+        if (r < 2.0) return (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r)) * 0.125;
+        return 0.0;
+    }
+    if (r < 0.5 * w) {
+        const double t = zeta * inv_alpha;
+        return exp(beta * (sqrt(fmax(1.0 - t * t, 0.0)) - 1.0)) * inv_norm;
+    }
+    return 0.0;
+}
+
+// Weights of the 2 KM nodes floor(s) + 1 - KM + a, a = 0 .. 2 KM - 1, of one axis (zero
+// outside the kernel's support); returns the first node.
+template <int KM>
+__device__ __forceinline__ int hy_axis(double s, const double* kr, double* wt) {
+    const double fl = floor(s);
+    const int i0 = (int)fl + 1 - KM;
+#pragma unroll
+    for (int a = 0; a < 2 * KM; ++a)
+        wt[a] = hy_weight(s - (double)(i0 + a), kr[0], kr[1], kr[2], kr[3]);
+    return i0;
+}
+
+// deposit_face for a kernel from the table (kr: its row) over a window of 2 KM nodes per
+// axis; folds as deposit_face (one fold suffices: nz >= KM).
+template <int COMP, int KM>
+__device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, int x0, int y0, int z0,
+                                               int tx, int ty, int tz, double px, double py,
+                                               double pz, double val, const double* kr) {
+    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
+    double wx[2 * KM], wy[2 * KM];
+    const int ix0 = hy_axis<KM>(px * g.inv_h - ox, kr, wx);
+    const int iy0 = hy_axis<KM>(py * g.inv_h - oy, kr, wy);
+    const double sz = pz * g.inv_h - oz;
+    const int iz0 = (int)floor(sz) + 1 - KM;
+    int lxs[2 * KM], lys[2 * KM];
+#pragma unroll
+    for (int a = 0; a < 2 * KM; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+#pragma unroll
+    for (int b = 0; b < 2 * KM; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+    for (int c = 0; c < 2 * KM; ++c) {
+        const double wzc0 = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
+        if (wzc0 == 0.0) continue;
+        int kz = iz0 + c;
+        double sgn = 1.0;
+        if (COMP == 2) {
+            if (kz < 0) { kz = -kz; sgn = -1.0; }
+            else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
+            if (kz == 0 || kz == g.nz) continue;
+        } else {
+            if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
+            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
+        }
+        const int lz = kz - z0;
+        if (lz < 0 || lz >= tz) continue;
+        const double wzc = val * sgn * wzc0;
+#pragma unroll
+        for (int b = 0; b < 2 * KM; ++b) {
+            if (lys[b] >= ty || wy[b] == 0.0) continue;
+            const double wyz = wzc * wy[b];
+#pragma unroll
+            for (int a = 0; a < 2 * KM; ++a) {
+                if (lxs[a] >= tx || wx[a] == 0.0) continue;
+                atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
+            }
+        }
+    }
+}
+
 // S^hy F on one face grid; with rfd.scale != 0 every ion also deposits the random
 // finite difference (kT / delta) [phi(x + delta/2 W) - phi(x - delta/2 W)] W_COMP of
 // the thermal forcing.  The shifts are below half a cell: along an axis whose nodes
 // sit on faces, a kernel shifted up from the cell below the tile's two-cell window
 // reaches the tile's first node, so the candidate rows then reach three cells down.
-template <int COMP>
+// KM = 0: the 4-point Peskin kernel for every ion; KM = 2 or 4: each ion's kernel from
+// the table by its species, over a window of 2 KM nodes (tile edge T = 16 or 8, so that
+// the candidate rows of the wider halo stay within SH_MAXR).
+template <int COMP, int T, int KM>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
-                   const int* __restrict__ bin_start, RfdDev rfd, double* __restrict__ out) {
-    __shared__ double acc[SH_TX * SH_TY * SH_TZ];
+                   const int* __restrict__ bin_start, RfdDev rfd, const int* __restrict__ ssp,
+                   const double* __restrict__ hy_tab, double* __restrict__ out) {
+    __shared__ double acc[T * T * T];
     __shared__ int rstart[SH_MAXR], rpre[SH_MAXR + 1], scan[SH_THREADS];
     const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
-    const int tx = min(SH_TX, g.nx), ty = min(SH_TY, g.ny);
-    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * SH_TZ;
-    const int tz = min(SH_TZ, nzn - z0);
+    const int tx = min(T, g.nx), ty = min(T, g.ny);
+    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * T;
+    const int tz = min(T, nzn - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
-    // ions that can reach node levels [z0, z0+tz): cells [z0-2, z0+tz+1]
+    // ions that can reach node levels [z0, z0+tz): cells [z0-K, z0+tz-1+K] for a window
+    // of 2K nodes (K = 2 for the Peskin kernel)
+    const int K = KM == 0 ? 2 : KM;
     const int nr = tile_ranges<SH_MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
-                                 rpre, scan, rfd.scale != 0.0 ? 3 : 2);
+                                 rpre, scan, rfd.scale != 0.0 ? K + 1 : K, K);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
@@ -98,7 +185,16 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
         const int i = rstart[r] + (f - rpre[r]);
         const double4 a4 = sxyzq[i];
         if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
-        deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, fw[i] * inv_h3);
+        double kr[4];
+        if (KM != 0) {
+            const double* row = hy_row(hy_tab, ssp[i]);
+            kr[0] = row[0]; kr[1] = row[1]; kr[2] = row[2]; kr[3] = row[3];
+        }
+        auto dep = [&](double px, double py, double pz, double v) {
+            if constexpr (KM == 0) deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v);
+            else deposit_face_k<COMP, KM>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v, kr);
+        };
+        dep(a4.x, a4.y, a4.z, fw[i] * inv_h3);
         if (rfd.scale != 0.0) {
             double w0, w1, w2, unused;
             const uint32_t idi = (uint32_t)rfd.sid[i];
@@ -107,8 +203,8 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
             const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
             const double v = rfd.scale * wc * inv_h3;
             const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
-            deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x + hx, a4.y + hy, a4.z + hz, v);
-            deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x - hx, a4.y - hy, a4.z - hz, -v);
+            dep(a4.x + hx, a4.y + hy, a4.z + hz, v);
+            dep(a4.x - hx, a4.y - hy, a4.z - hz, -v);
         }
     }
     __syncthreads();
@@ -121,19 +217,30 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     }
 }
 
-int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in) {
+template <int T, int KM>
+static void spread_faces(Ctx* c, const RfdDev& rfd, const int* ssp, double* out, hipStream_t s) {
     const GridDev& g = c->gd;
+    const int tx = std::min(T, g.nx), ty = std::min(T, g.ny);
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + T - 1) / T);
+    dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + T - 1) / T);
+    spread_face_kernel<0, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd,
+                                                              ssp, c->hy_tab, out);
+    spread_face_kernel<1, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max,
+                                                              c->bin_start, rfd, ssp, c->hy_tab,
+                                                              out + ncell);
+    spread_face_kernel<2, T, KM><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
+                                                              c->bin_start, rfd, ssp, c->hy_tab,
+                                                              out + 2 * ncell);
+}
+
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in, int species) {
     RfdDev rfd{};
     if (rfd_in) rfd = *rfd_in;
-    const int tx = std::min(SH_TX, g.nx), ty = std::min(SH_TY, g.ny);
-    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
-    dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + SH_TZ - 1) / SH_TZ);
-    dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + SH_TZ - 1) / SH_TZ);
-    spread_face_kernel<0><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd, out);
-    spread_face_kernel<1><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max, c->bin_start,
-                                                       rfd, out + ncell);
-    spread_face_kernel<2><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
-                                                       c->bin_start, rfd, out + 2 * ncell);
+    const int km = species ? c->hy_km : 0;
+    if (km == 0) spread_faces<SH_TX, 0>(c, rfd, nullptr, out, s);
+    else if (km <= 2) spread_faces<16, 2>(c, rfd, c->ssp, out, s);
+    else spread_faces<8, 4>(c, rfd, c->ssp, out, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -409,12 +516,16 @@ __device__ __forceinline__ double face_val(const double* __restrict__ a, const G
 
 // V = J^hy v at the positions xs.  With mid != nullptr the kernel is the predictor of
 // eq step1: mid[i] = (x + half_dt V wrapped in x, y and reflected in z, q); otherwise
-// V goes to out[o] (o = perm[i] if scatter) with the given component stride.
-__global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ xs,
+// V goes to out[o] (o = perm[i] if scatter) with the given component stride.  KM = 0:
+// the 4-point Peskin kernel; KM = 2 or 4: ion i's kernel from the table by its species
+// ssp[i], over a window of 2 KM nodes per axis.
+template <int KM>
+__global__ void __launch_bounds__(256) interp_hy_kernel(GridDev g, int n, const double4* __restrict__ xs,
                                  const int* __restrict__ perm, const double* __restrict__ vel,
                                  double* __restrict__ out, int64_t stride, int scatter,
                                  double4* __restrict__ mid, double half_dt,
-                                 int* __restrict__ flags) {
+                                 int* __restrict__ flags, const int* __restrict__ ssp,
+                                 const double* __restrict__ hy_tab) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double4 a4 = xs[i];
@@ -431,6 +542,51 @@ __global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ x
     }
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     double res[3];
+    if constexpr (KM != 0) {
+        const double* row = hy_row(hy_tab, ssp[i]);
+        const double kr[4] = {row[0], row[1], row[2], row[3]};
+        for (int comp = 0; comp < 3; ++comp) {
+            const double* a = vel + comp * ncell;
+            double wx[2 * KM], wy[2 * KM];
+            const int ix0 = hy_axis<KM>(a4.x * g.inv_h - (comp == 0 ? 0.0 : 0.5), kr, wx);
+            const int iy0 = hy_axis<KM>(a4.y * g.inv_h - (comp == 1 ? 0.0 : 0.5), kr, wy);
+            const double sz = a4.z * g.inv_h - (comp == 2 ? 0.0 : 0.5);
+            const int iz0 = (int)floor(sz) + 1 - KM;
+            int ii[2 * KM];
+#pragma unroll
+            for (int aa = 0; aa < 2 * KM; ++aa) ii[aa] = (ix0 + aa) & (g.nx - 1);
+            double acc = 0.0;
+            for (int c = 0; c < 2 * KM; ++c) {
+                const double wz = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
+                if (wz == 0.0) continue;
+                // no-slip ghost of the level (one fold: nz >= KM)
+                int k = iz0 + c;
+                double sg = 1.0;
+                if (comp < 2) {
+                    if (k < 0) { k = -1 - k; sg = -1.0; }
+                    else if (k >= g.nz) { k = 2 * g.nz - 1 - k; sg = -1.0; }
+                    k = min(max(k, 0), g.nz - 1);
+                } else {
+                    if (k < 0) { k = -k; sg = -1.0; }
+                    else if (k > g.nz) { k = 2 * g.nz - k; sg = -1.0; }
+                    k = min(max(k, 0), g.nz);
+                }
+                const double* plane = a + (size_t)k * g.ny * g.nx;
+                double accy = 0.0;
+#pragma unroll
+                for (int b = 0; b < 2 * KM; ++b) {
+                    if (wy[b] == 0.0) continue;
+                    const double* rowp = plane + (size_t)((iy0 + b) & (g.ny - 1)) * g.nx;
+                    double accx = 0.0;
+#pragma unroll
+                    for (int aa = 0; aa < 2 * KM; ++aa) accx += wx[aa] * rowp[ii[aa]];
+                    accy += wy[b] * accx;
+                }
+                acc += sg * wz * accy;
+            }
+            res[comp] = acc;
+        }
+    } else {
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
         const double* a = vel + comp * ncell;
@@ -454,6 +610,7 @@ __global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ x
         }
         res[comp] = acc;
     }
+    }
     if (mid) {
         double mx = a4.x + half_dt * res[0], my = a4.y + half_dt * res[1], mz = a4.z + half_dt * res[2];
         if (!(isfinite(mx) && isfinite(my) && isfinite(mz))) {
@@ -470,23 +627,36 @@ __global__ void interp_hy_kernel(GridDev g, int n, const double4* __restrict__ x
     out[o + 2 * stride] = res[2];
 }
 
+template <int KM>
+static void interp_hy_launch(Ctx* c, int n, const double4* xs, const double* vel, double* out,
+                             int64_t stride, int scatter, double4* mid, double half_dt, hipStream_t s) {
+    interp_hy_kernel<KM><<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, xs, c->perm, vel, out, stride,
+                                                        scatter, mid, half_dt, c->flags, c->ssp,
+                                                        c->hy_tab);
+}
+
+static void interp_hy_any(Ctx* c, int species, int n, const double4* xs, const double* vel,
+                          double* out, int64_t stride, int scatter, double4* mid, double half_dt,
+                          hipStream_t s) {
+    const int km = species ? c->hy_km : 0;
+    if (km == 0) interp_hy_launch<0>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
+    else if (km <= 2) interp_hy_launch<2>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
+    else interp_hy_launch<4>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
+}
+
 int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
-                     hipStream_t s) {
+                     hipStream_t s, int species) {
     if (n <= 0) return DISCOS_OK;
-    interp_hy_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, out, stride,
-                                                    scatter, nullptr, 0.0, c->flags);
+    interp_hy_any(c, species, n, c->sxyzq, vel, out, stride, scatter, nullptr, 0.0, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 // Stage 4 velocities of the wet step for the ions of the cell list: the predictor
 // x* = x + dt/2 J(x) v into c->hmid, then J(x*) v into c->hvi ([3][n_max], sorted).
-int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s) {
+int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s, int species) {
     if (n <= 0) return DISCOS_OK;
-    const int blocks = (n + 255) / 256;
-    interp_hy_kernel<<<blocks, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, nullptr, 0, 0,
-                                           c->hmid, 0.5 * dt, c->flags);
-    interp_hy_kernel<<<blocks, 256, 0, s>>>(c->gd, n, c->hmid, c->perm, vel, c->hvi, c->n_max, 0,
-                                           nullptr, 0.0, c->flags);
+    interp_hy_any(c, species, n, c->sxyzq, vel, nullptr, 0, 0, c->hmid, 0.5 * dt, s);
+    interp_hy_any(c, species, n, c->hmid, vel, c->hvi, c->n_max, 0, nullptr, 0.0, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

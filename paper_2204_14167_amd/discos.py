@@ -91,6 +91,11 @@ def lib():
         L.discos_near_field.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(DiscosParams), vp, vp]
         L.discos_step.argtypes = [vp, ctypes.POINTER(DiscosIons), ctypes.POINTER(DiscosParams),
                                   u64, i32, vp]
+        L.discos_set_hydro_kernel.argtypes = [vp, i32, vp]
+        L.discos_spread_force_species.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(DiscosParams),
+                                                  vp, vp]
+        L.discos_interpolate_vel_species.argtypes = [vp, i64, vp, vp, vp,
+                                                     ctypes.POINTER(DiscosParams), vp, vp]
         L.discos_check.argtypes = [vp]
         L.discos_profile.argtypes = [vp, i32]
         L.discos_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -113,7 +118,9 @@ def lib():
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
                      "discos_profile", "discos_profile_read", "discos_energy_flux",
                      "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
-                     "discos_batch_step", "discos_batch_tune", "discos_batch_check"):
+                     "discos_batch_step", "discos_batch_tune", "discos_batch_check",
+                     "discos_set_hydro_kernel", "discos_spread_force_species",
+                     "discos_interpolate_vel_species"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -287,6 +294,33 @@ class Context:
             out = torch.empty(shape, dtype=torch.float64, device=pos.device)
         self._rc(lib().discos_interpolate(self.handle, op, n, _ptr(pos), _ptr(field), _ptr(aux),
                                           ctypes.byref(params.struct), _ptr(out), _stream()))
+        return out
+
+    def set_hydro_kernel(self, kernels):
+        """Hydrodynamic kernel per species: a sequence of (w, beta), w = 0 for the 4-point
+        Peskin kernel, w = 2 .. 8 for the ESC kernel of App. B; None or [] restores Peskin."""
+        rows = [] if kernels is None else [(float(w), float(b)) for w, b in kernels]
+        buf = (ctypes.c_double * max(2 * len(rows), 1))(*[v for r in rows for v in r])
+        self._rc(lib().discos_set_hydro_kernel(self.handle, len(rows),
+                                               ctypes.cast(buf, ctypes.c_void_p)))
+
+    def spread_species(self, pos, F, species, params, out=None):
+        """S^hy F with each ion's kernel chosen by its species (int32, device)."""
+        if out is None:
+            out = torch.empty((self.face_size,), dtype=torch.float64, device=pos.device)
+        self._rc(lib().discos_spread_force_species(self.handle, pos.shape[1], _ptr(pos), _ptr(F),
+                                                   _ptr(species), ctypes.byref(params.struct),
+                                                   _ptr(out), _stream()))
+        return out
+
+    def interpolate_vel_species(self, pos, v, species, params, out=None):
+        """J^hy v with each ion's kernel chosen by its species (int32, device)."""
+        n = pos.shape[1]
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        self._rc(lib().discos_interpolate_vel_species(self.handle, n, _ptr(pos), _ptr(v),
+                                                      _ptr(species), ctypes.byref(params.struct),
+                                                      _ptr(out), _stream()))
         return out
 
     def near_field(self, pos, q, params, species=None, F=None):

@@ -29,6 +29,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("discos_create", "discos_destroy", "discos_spread", "discos_solve_poisson",
+                     "discos_set_hydro_kernel", "discos_spread_force_species",
+                     "discos_interpolate_vel_species",
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
                      "discos_last_error"):
         assert required in names
