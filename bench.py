@@ -8,8 +8,12 @@ J^es interpolation, P3M near-field + wall force + dry update.  The same workload
 times the energy / electro-osmotic-flux pass and its hand-written adjoint
 (discos_energy_flux, discos_energy_flux_backward) for the adjoint/forward ratio.
 
+The same run times the 512-channel batch and, on the resolved-hydrodynamics channel
+(262,144 ions, 128^3, charged walls), the wet midpoint step with the Peskin kernel and
+with the ESC pair per species.
+
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--adjoint-steps A] [--copy-calibration]
+                [--adjoint-steps A] [--batch-steps B] [--wet-steps S] [--copy-calibration]
 Prints one JSON line.
 """
 import argparse
@@ -44,6 +48,12 @@ STAGE_KERNEL = {"spread": "spread_charge_kernel", "fft_x": "fft_x_r2c_kernel",
                 "interp": "interp_es_kernel", "near_list": "near_list_kernel",
                 "near_eval": "near_eval_kernel", "update": "dry_update_kernel"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_dry_step_256x256x128_n1048576.md")
+
+# The resolved-hydrodynamics channel: wet midpoint step with the random finite
+# difference and the stochastic stress, with the 4-point Peskin kernel and with the ESC
+# pair of the electro-osmosis runs (App. B: cations w = 7, beta = 7; anions w = 4, beta = 8).
+WET_WORKLOAD = "eo_stokes_128x128x128_n262144"
+ESC_PAIR = [(7, 7.0), (4, 8.0)]
 
 
 def kernel_source_hash():
@@ -214,6 +224,83 @@ def adjoint_timing(ctx, dp, dpos, dq, steps):
             "gradients": "dU, dQ w.r.t. positions, charges, wall fields, E_ext"}
 
 
+def wet_stage_bytes(stage, N, C3):
+    """Algorithmic bytes of the hydrodynamic stages of one wet step (N ions, C3 face
+    values of the three velocity components): S^hy reads positions (32 B), forces
+    (24 B) and ids (4 B, the random finite difference) and writes every face once; the
+    midpoint J^hy reads positions, writes x* (32 B), reads x* and writes V (24 B), and
+    reads the faces once per pass."""
+    if stage == "spread_hy":
+        return 60.0 * N + 8.0 * C3
+    if stage == "interp_hy":
+        return 120.0 * N + 16.0 * C3
+    return None
+
+
+def wet_timing(steps, warmup=2):
+    """Wet midpoint steps (+ random finite difference, stochastic stress) on the
+    resolved-hydrodynamics channel, with the 4-point Peskin kernel and with the ESC
+    pair per species: ion-timesteps/s and per-stage times (hipEvents).
+
+    Every timed step starts from the workload's initial ions (restored by on-device
+    copies outside the timed brackets; each step draws new noise).  The workload has no
+    ion-ion repulsion, so a few free steps at dt = 0.01 drive close +/- pairs' kicks into
+    the 9-3 walls' core, and the wet step carries that unbalanced wall force to every ion
+    through the fluid; the model then leaves the stated configuration."""
+    import torch
+    from paper_2204_14167_amd import discos, workloads
+    w = workloads.WORKLOADS[WET_WORKLOAD]
+    p = workloads.make_params(w)
+    p["rfd_delta"] = 1e-4 * w.h
+    pos, q, ids, species = workloads.make_ions(w)
+    C3 = 3 * w.nx * w.ny * w.nz + w.nx * w.ny
+    out = {"workload": WET_WORKLOAD, "n_ions": w.n, "grid": [w.nx, w.ny, w.nz],
+           "mode": "wet midpoint step + RFD, stochastic stress, no-slip walls", "steps": steps,
+           "timing": "each step from the initial ions, hipEvents around discos_step"}
+    for name, kern in (("peskin4", None), ("esc_w7b7_w4b8", ESC_PAIR)):
+        ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, hydro=True)
+        if kern is not None:
+            ctx.set_hydro_kernel(kern)
+        dp = ctx.params(p)
+        base = [torch.from_numpy(a.copy()).cuda() for a in (pos, q, ids, species)]
+        arr = [t.clone() for t in base]
+        mode = discos.STEP_WET | discos.STEP_RFD
+        for s in range(warmup):
+            for a, b in zip(arr, base):
+                a.copy_(b)
+            ctx.step(*arr, dp, s, mode=mode)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+        for s in range(steps):
+            for a, b in zip(arr, base):
+                a.copy_(b)
+            ev[2 * s].record()
+            ctx.step(*arr, dp, warmup + s, mode=mode)
+            ev[2 * s + 1].record()
+        torch.cuda.synchronize()
+        el = 1e-3 * sum(ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(steps))
+        st = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+        ctx.close()
+        stages = {}
+        for k, v in st.items():
+            if v <= 0.0:
+                continue
+            e = {"ms": round(v, 5)}
+            b = wet_stage_bytes(k, w.n, C3)
+            if b is not None:
+                e["GB/s"] = round(b / (v * 1e-3) / 1e9, 1)
+                e["hbm_frac"] = round(b / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            stages[k] = e
+        out[name] = {"kernels": "4-point Peskin" if kern is None else
+                     "ESC (w, beta) = (7, 7) cations, (4, 8) anions",
+                     "ms_per_step": 1e3 * el / steps, "ion_timesteps_per_s": w.n * steps / el,
+                     "stages": stages}
+    return out
+
+
 def batch_timing(steps, seq_steps=3, one_by_one=True):
     """The 512-channel batch (dry steps, uneven grids 16x16x32 .. 64x64x64 and 64 .. 4096
     ions): ion-timesteps/s as one captured graph, as eager batched launches, and with
@@ -282,6 +369,8 @@ def main():
     ap.add_argument("--no-one-by-one", action="store_true",
                     help="skip stepping the batch's channels one by one (keeps kernel traces "
                          "of the batch free of the many small single-channel launches)")
+    ap.add_argument("--wet-steps", type=int, default=10,
+                    help="wet steps of the 262,144-ion hydrodynamic channel per kernel (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -329,6 +418,7 @@ def main():
 
     adj = adjoint_timing(ctx, dp, dpos, dq, args.adjoint_steps) if args.adjoint_steps > 0 else None
     batched = batch_timing(args.batch_steps, one_by_one=not args.no_one_by_one) if args.batch_steps > 0 else None
+    wet = wet_timing(args.wet_steps) if args.wet_steps > 0 else None
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -397,6 +487,7 @@ def main():
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "adjoint": adj,
         "batched": batched,
+        "wet": wet,
         "cpu_baseline": cpu,
         "device_status": "; ".join(status) if status else "ok",
     }

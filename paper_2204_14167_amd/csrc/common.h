@@ -230,12 +230,14 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
 }
 
 // Cell-list rows of the ions that can reach the nodes of the tile [x0, x0+tx) x
-// [y0, y0+ty) x [z0, z0+tz) with a window of hlo cells below and two above (cells
+// [y0, y0+ty) x [z0, z0+tz) with a window of hlo cells below and hhi above (cells
 // x0-hlo .. x0+tx-1+hhi, periodic in x and y, clipped at the walls in z).  hlo = hhi = 2
 // covers the 4-point kernel (a kernel with a window of 2K nodes needs K); kernels shifted
 // by up to half a cell (the random finite difference) reach one cell further down.
-// Thread t < MAXR owns one candidate row (rstart[t], length from the prefix sums rpre);
-// returns the row count.  The caller sizes the tile so that the rows fit in MAXR.
+// Row r gets rstart[r] and the prefix sum rpre[r] of the row lengths (rpre[nr] = total);
+// the rows are taken in chunks of blockDim.x, so MAXR may exceed the block (rstart and
+// rpre hold MAXR and MAXR + 1 entries, scan blockDim.x).  Returns the row count; the
+// caller sizes the tile so that the rows fit in MAXR.
 template <int MAXR>
 __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
                              int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan,
@@ -257,29 +259,37 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
     const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
     const int nyb = yhi - ylo + 1;
     const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
-    const int t = threadIdx.x;
-    int len = 0;
-    if (t < ncand && t < MAXR) {
-        const int sgi = t % nseg;
-        const int yy = ylo + (t / nseg) % nyb;
-        const int bz = bzlo + t / (nseg * nyb);
-        const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
-        const int st = bin_start[row + sa[sgi]];
-        rstart[t] = st;
-        len = bin_start[row + sb[sgi] + 1] - st;
-    }
-    scan[t] = len;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const int a = (t >= off) ? scan[t - off] : 0;
-        __syncthreads();
-        scan[t] += a;
-        __syncthreads();
-    }
+    const int t = threadIdx.x, bd = blockDim.x;
     const int nr = max(min(ncand, MAXR), 1);
-    if (t < nr) rpre[t] = scan[t] - len;
-    if (t == nr - 1) rpre[nr] = (ncand > 0) ? scan[t] : 0;
-    if (ncand == 0 && t == 0) { rstart[0] = 0; rpre[0] = 0; rpre[1] = 0; }
+    int carry = 0;
+    for (int base = 0; base < nr; base += bd) {
+        const int r = base + t;
+        int len = 0;
+        if (r < ncand && r < MAXR) {
+            const int sgi = r % nseg;
+            const int yy = ylo + (r / nseg) % nyb;
+            const int bz = bzlo + r / (nseg * nyb);
+            const int row = (bz * g.nby + wrapi(yy, g.nby)) * g.nbx;
+            const int st = bin_start[row + sa[sgi]];
+            rstart[r] = st;
+            len = bin_start[row + sb[sgi] + 1] - st;
+        }
+        scan[t] = len;
+        __syncthreads();
+        for (int off = 1; off < bd; off <<= 1) {
+            const int a = (t >= off) ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += a;
+            __syncthreads();
+        }
+        if (r < nr) rpre[r] = carry + scan[t] - len;
+        carry += scan[bd - 1];
+        __syncthreads();  // scan is rewritten by the next chunk
+    }
+    if (t == 0) {
+        rpre[nr] = (ncand > 0) ? carry : 0;
+        if (ncand == 0) { rstart[0] = 0; rpre[0] = 0; }
+    }
     __syncthreads();
     return nr;
 }

@@ -103,25 +103,29 @@ __device__ __forceinline__ int hy_axis(double s, const double* kr, double* wt) {
 }
 
 // deposit_face for a kernel from the table (kr: its row) over a window of 2 KM nodes per
-// axis; folds as deposit_face (one fold suffices: nz >= KM).
+// axis; folds as deposit_face (one fold suffices: nz >= KM).  Weights are evaluated only
+// for the nodes inside the tile.
 template <int COMP, int KM>
 __device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, int x0, int y0, int z0,
                                                int tx, int ty, int tz, double px, double py,
                                                double pz, double val, const double* kr) {
     const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
-    double wx[2 * KM], wy[2 * KM];
-    const int ix0 = hy_axis<KM>(px * g.inv_h - ox, kr, wx);
-    const int iy0 = hy_axis<KM>(py * g.inv_h - oy, kr, wy);
-    const double sz = pz * g.inv_h - oz;
+    const double sx = px * g.inv_h - ox, sy = py * g.inv_h - oy, sz = pz * g.inv_h - oz;
+    const int ix0 = (int)floor(sx) + 1 - KM, iy0 = (int)floor(sy) + 1 - KM;
     const int iz0 = (int)floor(sz) + 1 - KM;
+    double wx[2 * KM], wy[2 * KM];
     int lxs[2 * KM], lys[2 * KM];
 #pragma unroll
-    for (int a = 0; a < 2 * KM; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+    for (int a = 0; a < 2 * KM; ++a) {
+        lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+        wx[a] = lxs[a] < tx ? hy_weight(sx - (double)(ix0 + a), kr[0], kr[1], kr[2], kr[3]) : 0.0;
+    }
 #pragma unroll
-    for (int b = 0; b < 2 * KM; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+    for (int b = 0; b < 2 * KM; ++b) {
+        lys[b] = (iy0 + b - y0) & (g.ny - 1);
+        wy[b] = lys[b] < ty ? hy_weight(sy - (double)(iy0 + b), kr[0], kr[1], kr[2], kr[3]) : 0.0;
+    }
     for (int c = 0; c < 2 * KM; ++c) {
-        const double wzc0 = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
-        if (wzc0 == 0.0) continue;
         int kz = iz0 + c;
         double sgn = 1.0;
         if (COMP == 2) {
@@ -134,14 +138,16 @@ __device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, in
         }
         const int lz = kz - z0;
         if (lz < 0 || lz >= tz) continue;
+        const double wzc0 = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
+        if (wzc0 == 0.0) continue;
         const double wzc = val * sgn * wzc0;
 #pragma unroll
         for (int b = 0; b < 2 * KM; ++b) {
-            if (lys[b] >= ty || wy[b] == 0.0) continue;
+            if (wy[b] == 0.0) continue;
             const double wyz = wzc * wy[b];
 #pragma unroll
             for (int a = 0; a < 2 * KM; ++a) {
-                if (lxs[a] >= tx || wx[a] == 0.0) continue;
+                if (wx[a] == 0.0) continue;
                 atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
             }
         }
@@ -154,15 +160,17 @@ __device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, in
 // sit on faces, a kernel shifted up from the cell below the tile's two-cell window
 // reaches the tile's first node, so the candidate rows then reach three cells down.
 // KM = 0: the 4-point Peskin kernel for every ion; KM = 2 or 4: each ion's kernel from
-// the table by its species, over a window of 2 KM nodes (tile edge T = 16 or 8, so that
-// the candidate rows of the wider halo stay within SH_MAXR).
+// the table by its species, over a window of 2 KM nodes.  16^3 tiles: the halo of the
+// 8-node window (K + 1 = 5 cells below, 4 above) needs up to 13 x 13 bin rows of two
+// x segments, 338 candidate rows, within MAXR = 512.
 template <int COMP, int T, int KM>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
                    const int* __restrict__ bin_start, RfdDev rfd, const int* __restrict__ ssp,
                    const double* __restrict__ hy_tab, double* __restrict__ out) {
+    constexpr int MAXR = KM == 4 ? 2 * SH_MAXR : SH_MAXR;
     __shared__ double acc[T * T * T];
-    __shared__ int rstart[SH_MAXR], rpre[SH_MAXR + 1], scan[SH_THREADS];
+    __shared__ int rstart[MAXR], rpre[MAXR + 1], scan[SH_THREADS];
     const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
     const int tx = min(T, g.nx), ty = min(T, g.ny);
     const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * T;
@@ -172,7 +180,7 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     // ions that can reach node levels [z0, z0+tz): cells [z0-K, z0+tz-1+K] for a window
     // of 2K nodes (K = 2 for the Peskin kernel)
     const int K = KM == 0 ? 2 : KM;
-    const int nr = tile_ranges<SH_MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
+    const int nr = tile_ranges<MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
                                  rpre, scan, rfd.scale != 0.0 ? K + 1 : K, K);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
@@ -240,7 +248,7 @@ int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in
     const int km = species ? c->hy_km : 0;
     if (km == 0) spread_faces<SH_TX, 0>(c, rfd, nullptr, out, s);
     else if (km <= 2) spread_faces<16, 2>(c, rfd, c->ssp, out, s);
-    else spread_faces<8, 4>(c, rfd, c->ssp, out, s);
+    else spread_faces<16, 4>(c, rfd, c->ssp, out, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

@@ -344,7 +344,8 @@ class Context:
         self._rc(lib().discos_profile(self.handle, int(enable)))
 
     def profile_read(self):
-        """{stage: ms} of the most recent profiled step (synchronises)."""
+        """{stage: ms}, the mean over the steps profiled since profiling was enabled
+        (synchronises)."""
         ms = (ctypes.c_double * 16)()
         cnt = ctypes.c_int()
         self._rc(lib().discos_profile_read(self.handle, ms, ctypes.byref(cnt)))

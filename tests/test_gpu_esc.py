@@ -155,11 +155,12 @@ def _wet(table, rfd, name="dirichlet_32x32x32_n256", edge=False, step=0):
     p["rfd_delta"] = delta
     pos, q, ids, species = workloads.make_ions(w)
     if edge:
-        # just below the cells an 8^3 face tile gathers without the random finite
-        # difference (x0 - 4 for x0 = 16, 24): only the shifted w = 8 kernels reach it
+        # just below the cells a 16^3 face tile gathers without the random finite
+        # difference (x0 - 4 for x0 = 16 and 32 = 0): only the shifted w = 8 kernels
+        # reach the tile
         rng = np.random.default_rng(43)
         k = np.arange(w.n)
-        e = np.where(rng.uniform(size=w.n) < 0.5, 12.0, 20.0) - rng.uniform(1e-4, 0.02, w.n)
+        e = np.where(rng.uniform(size=w.n) < 0.5, 12.0, 28.0) - rng.uniform(1e-4, 0.02, w.n)
         for d in range(3):
             pos[d, k % 3 == d] = e[k % 3 == d]
     grid = es.Grid(w.nx, w.ny, w.nz, w.h)
