@@ -256,7 +256,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         const size_t nsp = (size_t)g.nxh * g.ny;
         size_t hb = 0;
         hb += carve_bytes(nsp * (4 * (size_t)g.nz + 1), sizeof(double2));  // u v w p spectra
-        hb += carve_bytes(16 * (size_t)g.nz * nsp, sizeof(double));         // mode scratch
+        hb += carve_bytes(14 * (size_t)g.nz * nsp, sizeof(double));         // mode factors
         hb += carve_bytes(4 * ncell, sizeof(double));                       // stress diag + xy
         hb += carve_bytes(2 * nlev, sizeof(double));                        // stress xz yz
         hb += 2 * carve_bytes(2 * ncell + nlev, sizeof(double));            // hvel, hfor
@@ -272,7 +272,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hpool = hp;
         char* hc = static_cast<char*>(hp);
         c->hspec = carve<double2>(hc, nsp * (4 * (size_t)g.nz + 1));
-        c->hscr = carve<double>(hc, 16 * (size_t)g.nz * nsp);
+        c->hfac = carve<double>(hc, 14 * (size_t)g.nz * nsp);
         c->hz_diag = carve<double>(hc, 4 * ncell);
         c->hz_edge = carve<double>(hc, 2 * nlev);
         c->hvel = carve<double>(hc, 2 * ncell + nlev);
@@ -280,8 +280,10 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hvi = carve<double>(hc, 3 * nm);
         c->hmid = carve<double4>(hc, nm);
         c->hy_tab = carve<double>(hc, 4 * DISCOS_HY_MAXSP);
-        // every species on the 4-point Peskin kernel (rows of zeros: w = 0)
-        if (hipMemset(c->hy_tab, 0, 4 * DISCOS_HY_MAXSP * sizeof(double)) != hipSuccess) {
+        // every species on the 4-point Peskin kernel (rows of zeros: w = 0); the Stokes
+        // mode factorisation of this grid
+        if (hipMemset(c->hy_tab, 0, 4 * DISCOS_HY_MAXSP * sizeof(double)) != hipSuccess ||
+            discos::stokes_factor(c, nullptr) != DISCOS_OK || hipDeviceSynchronize() != hipSuccess) {
             hipFree(hp);
             hipFree(c->pool);
             delete c;

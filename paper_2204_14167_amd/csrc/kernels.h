@@ -38,7 +38,7 @@ struct Ctx {
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
     int hydro;
     double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
-    double* hscr;     // per-mode block-Thomas scratch, 16 doubles per level
+    double* hfac;     // block-Thomas factors of the Stokes mode systems, 14 doubles per level and mode
     double* hz_diag;  // stress normals: xx, yy, zz, xy per cell
     double* hz_edge;  // stress normals: xz, yz per z-level edge
     double* hvel;     // face velocity scratch for the wet step (3 face arrays)
@@ -175,6 +175,8 @@ struct RfdDev {
 // species != 0: each ion's kernel from c->hy_tab by its species c->ssp.
 int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd = nullptr,
                         int species = 0);
+// Factorisation of the Stokes mode systems of the context's grid (once, at creation).
+int stokes_factor(Ctx* c, hipStream_t s);
 // Stokes solve with no-slip walls (f: three face arrays; vel likewise; pres nullable).
 int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
                  double* vel, double* pres, hipStream_t s);

@@ -348,97 +348,55 @@ __device__ __forceinline__ void inv3(const double M[9], double R[9]) {
     R[8] = (M[0] * M[4] - M[1] * M[3]) * id;
 }
 
-// One thread per in-plane mode t = n * nxh + m.  su, sv, sp: spectra [nz][ny][nxh];
-// sw: [nz+1][ny][nxh].  On entry su, sv, sw hold the force, on exit the velocity and
-// sp the pressure.  scr: per-mode scratch, 16 doubles per level, stride nmode.
-__global__ void stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv,
-                                   double2* __restrict__ sw, double2* __restrict__ sp,
-                                   double* __restrict__ scr, int nx, int ny, int nz, double h,
-                                   double eta, double norm) {
+// The mode systems scaled by 1 / eta (pressure p' = p / eta): eta-free, so their
+// factorisation depends only on the grid and is computed once per context.  Per level k
+// and mode t, fac[(k * SF_N + q) * nmode + t] holds
+//   q = 0, 1        1 / den_k and c'_k of the scalar tridiagonal (b, or u and v of the
+//                   mean flow: -D_zz + kappa^2 with the wall rows);
+//   q = 2 .. 7      columns 0, 1 of S_k^-1, S_k the pivot block of (a, w, p) (the
+//                   continuity row's right-hand side is zero, so column 2 is unused);
+//   q = 8 .. 13     columns 0, 1 of C'_k = S_k^-1 C_k (column 2 of C_k is zero).
+#define SF_N 14
+
+__device__ __forceinline__ void mode_symbols(int t, int nx, int ny, double ih, double2& gx,
+                                             double2& gy, double& k2) {
     const int nxh = nx / 2 + 1;
-    const int nmode = nxh * ny;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nmode) return;
     const int m = t % nxh, n = t / nxh;
-    const size_t st = (size_t)nmode;
-    const double ih = 1.0 / h, ih2 = ih * ih;
     const double tx = 2.0 * M_PI * m / nx, ty = 2.0 * M_PI * n / ny;
     // G = (1 - e^{-i theta}) / h
-    const double2 gx = make_double2((1.0 - cos(tx)) * ih, sin(tx) * ih);
-    const double2 gy = make_double2((1.0 - cos(ty)) * ih, sin(ty) * ih);
-    const double k2 = gx.x * gx.x + gx.y * gx.y + gy.x * gy.x + gy.y * gy.y;
-    double* cpb = scr + t;                 // [nz] tridiagonal coefficients of b
-    double* Cp = scr + (size_t)nz * st + t;  // [nz][9] block C'
-    double* Yp = scr + (size_t)10 * nz * st + t;  // [nz][6] block y (3 complex)
-    const double off = -eta * ih2;
-    if (m == 0 && n == 0) {
-        // mean flow: eta T u = f with the wall rows; w = 0; p from G_z p = f_z, mean 0
-        for (int comp = 0; comp < 2; ++comp) {
-            double2* col = comp == 0 ? su + t : sv + t;
-            double c_prev = 0.0;
-            double2 d_prev = make_double2(0.0, 0.0);
-            for (int k = 0; k < nz; ++k) {
-                double diag = eta * 2.0 * ih2;
-                if (k == 0) diag += eta * ih2;
-                if (k == nz - 1) diag += eta * ih2;
-                const double den = diag - off * c_prev;
-                const double c = off / den;
-                const double2 r = cscale(norm, col[k * st]);
-                const double2 d = cscale(1.0 / den, csub(r, cscale(off, d_prev)));
-                cpb[k * st] = c;
-                col[k * st] = d;
-                c_prev = c;
-                d_prev = d;
-            }
-            double2 x = d_prev;
-            for (int k = nz - 2; k >= 0; --k) {
-                x = csub(col[k * st], cscale(cpb[k * st], x));
-                col[k * st] = x;
-            }
-        }
-        double2 pk = make_double2(0.0, 0.0), psum = make_double2(0.0, 0.0);
-        for (int k = 0; k < nz; ++k) {
-            if (k > 0) pk = cadd(pk, cscale(h * norm, sw[k * st + t]));
-            sp[k * st + t] = pk;
-            psum = cadd(psum, pk);
-        }
-        const double2 mean = cscale(1.0 / nz, psum);
-        for (int k = 0; k < nz; ++k) sp[k * st + t] = csub(sp[k * st + t], mean);
-        for (int k = 0; k <= nz; ++k) sw[k * st + t] = make_double2(0.0, 0.0);
-        return;
-    }
+    gx = make_double2((1.0 - cos(tx)) * ih, sin(tx) * ih);
+    gy = make_double2((1.0 - cos(ty)) * ih, sin(ty) * ih);
+    k2 = gx.x * gx.x + gx.y * gx.y + gy.x * gy.x + gy.y * gy.y;
+}
+
+// Block-Thomas factorisation of every mode (rows E1 a-momentum, E2 w-momentum, E3
+// continuity; columns a, w, p; A, B, C the sub-, main and super-diagonal blocks).
+__global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, int nz, double h) {
+    const int nmode = (nx / 2 + 1) * ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nmode) return;
+    const size_t st = (size_t)nmode;
+    const double ih = 1.0 / h, ih2 = ih * ih;
+    double2 gx, gy;
+    double k2;
+    mode_symbols(t, nx, ny, ih, gx, gy, k2);
     const double kap = sqrt(k2);
-    const double ik = 1.0 / kap;
-    // e = G / kappa; a = e^H u, b = e_perp^H u with e_perp = (-conj gy, conj gx) / kappa
-    // forward sweeps (b: scalar tridiagonal; (a, w, p): 3x3 blocks)
+    const double off = -ih2;
+    const double dgn = 2.0 * ih2 + k2;
     double cb_prev = 0.0;
-    double2 db_prev = make_double2(0.0, 0.0);
     double Cprev[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double2 Yprev[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-    const double dgn = eta * (2.0 * ih2 + k2);
     for (int k = 0; k < nz; ++k) {
-        const double2 fxk = cscale(norm, su[k * st + t]);
-        const double2 fyk = cscale(norm, sv[k * st + t]);
-        const double2 fzk = (k == 0) ? make_double2(0.0, 0.0) : cscale(norm, sw[k * st + t]);
-        const double2 fa = cscale(ik, cadd(cm(cconj(gx), fxk), cm(cconj(gy), fyk)));
-        const double2 fb = cscale(ik, csub(cm(gx, fyk), cm(gy, fxk)));
+        double* f = fac + (size_t)k * SF_N * st + t;
         const double wall = (k == 0 ? 1.0 : 0.0) + (k == nz - 1 ? 1.0 : 0.0);
-        const double da = dgn + eta * wall * ih2;
-        // b: tridiagonal
-        {
-            const double den = da - off * cb_prev;
-            const double c = off / den;
-            const double2 d = cscale(1.0 / den, csub(fb, cscale(off, db_prev)));
-            cpb[k * st] = c;
-            cb_prev = c;
-            db_prev = d;
-            // d kept in Y slot 0 of this level temporarily (complex b) -> store in sv
-            sv[k * st + t] = d;
-        }
-        // blocks for level k (rows E1 a-momentum, E2 w-momentum, E3 continuity; cols a, w, p)
+        const double da = dgn + wall * ih2;
+        const double den = da - off * cb_prev;
+        const double cb = off / den;
+        f[0] = 1.0 / den;
+        f[st] = cb;
+        cb_prev = cb;
+        if (t == 0) continue;  // the mean flow uses the scalar factors only
         double B[9] = {da, 0.0, kap, 0.0, dgn, ih, -kap, -ih, 0.0};
-        if (k == 0) { B[3] = 0.0; B[4] = 1.0; B[5] = 0.0; }
-        double2 r0 = fa, r1 = fzk, r2 = make_double2(0.0, 0.0);
+        if (k == 0) { B[3] = 0.0; B[4] = 1.0; B[5] = 0.0; }  // w_0 = 0
         if (k > 0) {
             // S = B - A C'_{k-1};  A = [[off,0,0],[0,off,-ih],[0,0,0]]
             B[0] -= off * Cprev[0];
@@ -447,59 +405,243 @@ __global__ void stokes_mode_kernel(double2* __restrict__ su, double2* __restrict
             B[3] -= off * Cprev[3] - ih * Cprev[6];
             B[4] -= off * Cprev[4] - ih * Cprev[7];
             B[5] -= off * Cprev[5] - ih * Cprev[8];
-            // r - A y_{k-1}
-            r0 = csub(r0, cscale(off, Yprev[0]));
-            r1 = csub(r1, csub(cscale(off, Yprev[1]), cscale(ih, Yprev[2])));
         }
         double Si[9];
         inv3(B, Si);
-        // C'_k = S^-1 C_k;  C = [[off,0,0],[0,off,0],[0,ih,0]] (row 2 of C is 0 at k = 0)
+        // C = [[off,0,0],[0,off,0],[0,ih,0]] (row 1 of C is 0 at k = 0)
         const double c11 = (k == 0) ? 0.0 : off;
-        double Cn[9];
         for (int r = 0; r < 3; ++r) {
-            Cn[3 * r + 0] = Si[3 * r + 0] * off;
-            Cn[3 * r + 1] = Si[3 * r + 1] * c11 + Si[3 * r + 2] * ih;
-            Cn[3 * r + 2] = 0.0;
-        }
-        if (k == nz - 1)
-            for (int q = 0; q < 9; ++q) Cn[q] = 0.0;
-        double2 Yn[3];
-        for (int r = 0; r < 3; ++r)
-            Yn[r] = cadd(cadd(cscale(Si[3 * r], r0), cscale(Si[3 * r + 1], r1)), cscale(Si[3 * r + 2], r2));
-        for (int q = 0; q < 9; ++q) {
-            Cp[((size_t)k * 9 + q) * st] = Cn[q];
-            Cprev[q] = Cn[q];
-        }
-        for (int r = 0; r < 3; ++r) {
-            Yp[((size_t)k * 6 + 2 * r) * st] = Yn[r].x;
-            Yp[((size_t)k * 6 + 2 * r + 1) * st] = Yn[r].y;
-            Yprev[r] = Yn[r];
+            Cprev[3 * r + 0] = Si[3 * r + 0] * off;
+            Cprev[3 * r + 1] = Si[3 * r + 1] * c11 + Si[3 * r + 2] * ih;
+            Cprev[3 * r + 2] = 0.0;
+            f[(2 + 2 * r) * st] = Si[3 * r + 0];
+            f[(3 + 2 * r) * st] = Si[3 * r + 1];
+            f[(8 + 2 * r) * st] = Cprev[3 * r + 0];
+            f[(9 + 2 * r) * st] = Cprev[3 * r + 1];
         }
     }
-    // back substitution; rotate (a, b) back to (u, v)
-    double2 xa = Yprev[0], xw = Yprev[1], xp = Yprev[2];
-    double2 xb = db_prev;
-    for (int k = nz - 1; k >= 0; --k) {
-        if (k < nz - 1) {
-            double C[9];
-            for (int q = 0; q < 9; ++q) C[q] = Cp[((size_t)k * 9 + q) * st];
-            double2 y[3];
-            for (int r = 0; r < 3; ++r)
-                y[r] = make_double2(Yp[((size_t)k * 6 + 2 * r) * st], Yp[((size_t)k * 6 + 2 * r + 1) * st]);
-            // x_k = y_k - C'_k x_{k+1}; C'_k column 2 is zero
-            const double2 na = csub(y[0], cadd(cscale(C[0], xa), cscale(C[1], xw)));
-            const double2 nw = csub(y[1], cadd(cscale(C[3], xa), cscale(C[4], xw)));
-            const double2 np = csub(y[2], cadd(cscale(C[6], xa), cscale(C[7], xw)));
-            xa = na;
-            xw = nw;
-            xp = np;
-            xb = csub(sv[k * st + t], cscale(cpb[k * st], xb));
+}
+
+// Levels a thread's loads run ahead of its sweep: the mode solve has one wave per SIMD
+// at most, so the latency of each level's loads is hidden only by loads in flight.
+#define SM_AHEAD 8
+
+// Mean flow (kappa = 0): -D_zz u = f / eta with the wall rows for one tangential
+// component (col: its [nz] levels at stride st), by the scalar factors of mode 0.
+__device__ void mean_flow_component(double2* __restrict__ col, const double* __restrict__ F,
+                                    size_t st, int nz, double sc, double off) {
+    double2 br[SM_AHEAD];
+    double bf[SM_AHEAD];
+#pragma unroll
+    for (int j = 0; j < SM_AHEAD; ++j)
+        if (j < nz) { br[j] = col[j * st]; bf[j] = F[(size_t)j * SF_N * st]; }
+    double2 d = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            const int k = k0 + j;
+            if (k < nz) {
+                const double2 r = cscale(sc, br[j]);
+                const double idn = bf[j];
+                if (k + SM_AHEAD < nz) {
+                    br[j] = col[(k + SM_AHEAD) * st];
+                    bf[j] = F[(size_t)(k + SM_AHEAD) * SF_N * st];
+                }
+                d = cscale(idn, csub(r, cscale(off, d)));
+                col[k * st] = d;
+            }
         }
-        // u = a e + b e_perp = (a gx - b conj gy) / kappa, v = (a gy + b conj gx) / kappa
-        su[k * st + t] = cscale(ik, csub(cm(xa, gx), cm(xb, cconj(gy))));
-        sv[k * st + t] = cscale(ik, cadd(cm(xa, gy), cm(xb, cconj(gx))));
-        sw[k * st + t] = (k == 0) ? make_double2(0.0, 0.0) : xw;
-        sp[k * st + t] = xp;
+    }
+    // x_k = d_k - c'_k x_{k+1}, k = nz-2 .. 0 (slot i holds level nz-2-i)
+    double2 x = d;
+    const int nb = nz - 1;
+#pragma unroll
+    for (int j = 0; j < SM_AHEAD; ++j)
+        if (j < nb) { br[j] = col[(nz - 2 - j) * st]; bf[j] = F[((size_t)(nz - 2 - j) * SF_N + 1) * st]; }
+    for (int i0 = 0; i0 < nb; i0 += SM_AHEAD) {
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            const int i = i0 + j;
+            if (i < nb) {
+                const int k = nz - 2 - i;
+                const double2 dk = br[j];
+                const double cb = bf[j];
+                if (i + SM_AHEAD < nb) {
+                    br[j] = col[(k - SM_AHEAD) * st];
+                    bf[j] = F[((size_t)(k - SM_AHEAD) * SF_N + 1) * st];
+                }
+                x = csub(dk, cscale(cb, x));
+                col[k * st] = x;
+            }
+        }
+    }
+}
+
+// Mean pressure from G_z p = f_z (p_0 = 0, then mean zero) and w = 0.
+__device__ void mean_pressure(double2* __restrict__ sw, double2* __restrict__ sp, size_t st, int nz,
+                              double hn) {
+    double2 bw[SM_AHEAD];
+    double2 pk = make_double2(0.0, 0.0), psum = pk;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double2 mean = cscale(1.0 / nz, psum);
+        pk = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j)
+            if (j < nz) bw[j] = sw[j * st];
+        for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
+#pragma unroll
+            for (int j = 0; j < SM_AHEAD; ++j) {
+                const int k = k0 + j;
+                if (k < nz) {
+                    const double2 wk = bw[j];
+                    if (k + SM_AHEAD < nz) bw[j] = sw[(k + SM_AHEAD) * st];
+                    if (k > 0) pk = cadd(pk, cscale(hn, wk));
+                    if (pass == 0) psum = cadd(psum, pk);
+                    else sp[k * st] = csub(pk, mean);
+                }
+            }
+        }
+    }
+    for (int k = 0; k <= nz; ++k) sw[k * st] = make_double2(0.0, 0.0);
+}
+
+// Threads t < nmode: in-plane mode t = n * nxh + m (t = 0: the mean flow's u); t = nmode:
+// the mean flow's v; t = nmode + 1: the mean pressure and w.  su, sv, sp: spectra
+// [nz][ny][nxh]; sw: [nz+1][ny][nxh].  On entry su, sv, sw hold the force, on exit the
+// velocity and sp the pressure.  fac: the factorisation of stokes_factor_kernel.  The
+// forward sweep writes y (a, w, p', b) over the inputs, the backward sweep the solution.
+__global__ void __launch_bounds__(64)
+stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* __restrict__ sw,
+                   double2* __restrict__ sp, const double* __restrict__ fac, int nx, int ny,
+                   int nz, double h, double eta, double norm) {
+    const int nmode = (nx / 2 + 1) * ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nmode + 2) return;
+    const size_t st = (size_t)nmode;
+    const double ih = 1.0 / h, ih2 = ih * ih;
+    const double off = -ih2;
+    const double sc = norm / eta;  // scaled right-hand side
+    if (t == 0 || t == nmode) {
+        mean_flow_component(t == 0 ? su : sv, fac, st, nz, sc, off);
+        return;
+    }
+    if (t == nmode + 1) {
+        mean_pressure(sw, sp, st, nz, h * norm);
+        return;
+    }
+    const double* F = fac + t;
+    double2 gx, gy;
+    double k2;
+    mode_symbols(t, nx, ny, ih, gx, gy, k2);
+    const double ik = 1.0 / sqrt(k2);
+    // e = G / kappa; a = e^H u, b = e_perp^H u with e_perp = (-conj gy, conj gx) / kappa
+    double2 ya = make_double2(0.0, 0.0), yw = ya, yp = ya, yb = ya;
+    {
+        double2 bx[SM_AHEAD], by[SM_AHEAD], bz[SM_AHEAD];
+        double bf[SM_AHEAD][8];
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            if (j < nz) {
+                const size_t o = (size_t)j * st + t;
+                bx[j] = su[o];
+                by[j] = sv[o];
+                bz[j] = j == 0 ? make_double2(0.0, 0.0) : sw[o];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bf[j][q] = F[((size_t)j * SF_N + q) * st];
+            }
+        }
+        for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
+#pragma unroll
+            for (int j = 0; j < SM_AHEAD; ++j) {
+                const int k = k0 + j;
+                if (k < nz) {
+                    const double2 fxk = cscale(sc, bx[j]), fyk = cscale(sc, by[j]), fzk = cscale(sc, bz[j]);
+                    double f[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) f[q] = bf[j][q];
+                    if (k + SM_AHEAD < nz) {
+                        const size_t o = (size_t)(k + SM_AHEAD) * st + t;
+                        bx[j] = su[o];
+                        by[j] = sv[o];
+                        bz[j] = sw[o];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) bf[j][q] = F[((size_t)(k + SM_AHEAD) * SF_N + q) * st];
+                    }
+                    const double2 fa = cscale(ik, cadd(cm(cconj(gx), fxk), cm(cconj(gy), fyk)));
+                    const double2 fb = cscale(ik, csub(cm(gx, fyk), cm(gy, fxk)));
+                    // b: y_b = (f_b - off y_b,prev) / den
+                    yb = cscale(f[0], csub(fb, cscale(off, yb)));
+                    // (a, w, p'): y = S^-1 (r - A y_prev), r = (f_a, f_z, 0)
+                    const double2 r0 = csub(fa, cscale(off, ya));
+                    const double2 r1 = csub(fzk, csub(cscale(off, yw), cscale(ih, yp)));
+                    ya = cadd(cscale(f[2], r0), cscale(f[3], r1));
+                    yw = cadd(cscale(f[4], r0), cscale(f[5], r1));
+                    yp = cadd(cscale(f[6], r0), cscale(f[7], r1));
+                    const size_t o = (size_t)k * st + t;
+                    su[o] = ya;
+                    sw[o] = yw;
+                    sp[o] = yp;
+                    sv[o] = yb;
+                }
+            }
+        }
+    }
+    // back substitution x_k = y_k - C'_k x_{k+1}; rotate (a, b) back to (u, v)
+    double2 xa = ya, xw = yw, xp = yp, xb = yb;
+    {
+        const size_t o = (size_t)(nz - 1) * st + t;
+        su[o] = cscale(ik, csub(cm(xa, gx), cm(xb, cconj(gy))));
+        sv[o] = cscale(ik, cadd(cm(xa, gy), cm(xb, cconj(gx))));
+        sw[o] = xw;
+        sp[o] = cscale(eta, xp);
+    }
+    const int nb = nz - 1;  // levels nz-2 .. 0; slot j holds level nz-2-i for i = j mod SM_AHEAD
+    double2 ba[SM_AHEAD], bw[SM_AHEAD], bp[SM_AHEAD], bb[SM_AHEAD];
+    double bc[SM_AHEAD][7];
+#pragma unroll
+    for (int j = 0; j < SM_AHEAD; ++j) {
+        if (j < nb) {
+            const int k = nz - 2 - j;
+            const size_t o = (size_t)k * st + t;
+            ba[j] = su[o]; bw[j] = sw[o]; bp[j] = sp[o]; bb[j] = sv[o];
+            bc[j][0] = F[((size_t)k * SF_N + 1) * st];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) bc[j][1 + q] = F[((size_t)k * SF_N + 8 + q) * st];
+        }
+    }
+    for (int i0 = 0; i0 < nb; i0 += SM_AHEAD) {
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            const int i = i0 + j;
+            if (i < nb) {
+                const int k = nz - 2 - i;
+                const double2 y0 = ba[j], y1 = bw[j], y2 = bp[j], y3 = bb[j];
+                double c[7];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) c[q] = bc[j][q];
+                if (i + SM_AHEAD < nb) {
+                    const int kn = k - SM_AHEAD;
+                    const size_t o = (size_t)kn * st + t;
+                    ba[j] = su[o]; bw[j] = sw[o]; bp[j] = sp[o]; bb[j] = sv[o];
+                    bc[j][0] = F[((size_t)kn * SF_N + 1) * st];
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) bc[j][1 + q] = F[((size_t)kn * SF_N + 8 + q) * st];
+                }
+                const double2 ta = csub(y0, cadd(cscale(c[1], xa), cscale(c[2], xw)));
+                const double2 tw = csub(y1, cadd(cscale(c[3], xa), cscale(c[4], xw)));
+                const double2 tp = csub(y2, cadd(cscale(c[5], xa), cscale(c[6], xw)));
+                xb = csub(y3, cscale(c[0], xb));
+                xa = ta;
+                xw = tw;
+                xp = tp;
+                // u = a e + b e_perp = (a gx - b conj gy) / kappa, v = (a gy + b conj gx) / kappa
+                const size_t o = (size_t)k * st + t;
+                su[o] = cscale(ik, csub(cm(xa, gx), cm(xb, cconj(gy))));
+                sv[o] = cscale(ik, cadd(cm(xa, gy), cm(xb, cconj(gx))));
+                sw[o] = (k == 0) ? make_double2(0.0, 0.0) : xw;
+                sp[o] = cscale(eta, xp);
+            }
+        }
     }
     sw[(size_t)nz * st + t] = make_double2(0.0, 0.0);
 }
@@ -673,6 +815,14 @@ int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t
 int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_t s);
 int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s);
 
+// Factorisation of the mode systems of this context's grid (once, at creation).
+int stokes_factor(Ctx* c, hipStream_t s) {
+    const int nmode = c->gd.nxh * c->gd.ny;
+    stokes_factor_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->hfac, c->gd.nx, c->gd.ny, c->gd.nz,
+                                                         c->grid.h);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
 int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step, int noise,
                  double* vel, double* pres, hipStream_t s) {
     const GridDev& g = c->gd;
@@ -703,7 +853,7 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
     if (rc) return rc;
     const int nmode = g.nxh * ny;
     const double norm = 1.0 / ((double)nx * ny);
-    stokes_mode_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hscr, nx, ny, nz,
+    stokes_mode_kernel<<<(nmode + 2 + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hfac, nx, ny, nz,
                                                        c->grid.h, p->eta, norm);
     rc = fft_cols(c, su, nz, 1, s);
     if (!rc) rc = fft_cols(c, sv, nz, 1, s);
