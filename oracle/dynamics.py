@@ -161,19 +161,25 @@ def hydro_kernels(p, species):
     return hk[np.asarray(species, dtype=np.int64)]
 
 
-def _spread(grid, pos, F, kernels, slack=0.0):
+def hydro_walls(p):
+    """(lower, upper) slip flags of the hydrodynamic walls, p["slip"] (default no-slip)."""
+    sl = p.get("slip", (False, False))
+    return bool(sl[0]), bool(sl[1])
+
+
+def _spread(grid, pos, F, kernels, slack=0.0, slip=(False, False)):
     if kernels is None:
-        return stokes.spread_force(grid, pos, F, slack=slack)
-    return stokes.spread_force_kernels(grid, pos, F, kernels, slack=slack)
+        return stokes.spread_force(grid, pos, F, slack=slack, slip=slip)
+    return stokes.spread_force_kernels(grid, pos, F, kernels, slack=slack, slip=slip)
 
 
-def _interp(grid, pos, u, v, w, kernels):
+def _interp(grid, pos, u, v, w, kernels, slip=(False, False)):
     if kernels is None:
-        return stokes.interp_velocity(grid, pos, u, v, w)
-    return stokes.interp_velocity_kernels(grid, pos, u, v, w, kernels)
+        return stokes.interp_velocity(grid, pos, u, v, w, slip=slip)
+    return stokes.interp_velocity_kernels(grid, pos, u, v, w, kernels, slip=slip)
 
 
-def thermal_forcing(grid, pos, ids, kT, delta, seed, step, kernels=None):
+def thermal_forcing(grid, pos, ids, kT, delta, seed, step, kernels=None, slip=(False, False)):
     """f^th = kT div_x S^hy (eq thermforce) by the random finite difference
     (kT / delta) [S(x + delta/2 W) W - S(x - delta/2 W) W], W ~ N(0, I) per ion."""
     if not delta > 0.0:
@@ -182,8 +188,8 @@ def thermal_forcing(grid, pos, ids, kT, delta, seed, step, kernels=None):
     half = 0.5 * delta * W
     if np.abs(half).max(initial=0.0) >= grid.h:
         raise ValueError("random finite difference shift of a cell or more")
-    plus = _spread(grid, pos + half, W, kernels, slack=grid.h)
-    minus = _spread(grid, pos - half, W, kernels, slack=grid.h)
+    plus = _spread(grid, pos + half, W, kernels, slack=grid.h, slip=slip)
+    minus = _spread(grid, pos - half, W, kernels, slack=grid.h, slip=slip)
     return tuple(kT / delta * (a - b) for a, b in zip(plus, minus))
 
 
@@ -193,21 +199,24 @@ def wet_step(grid, pos, q, species, ids, p, step, noise=True, rfd_delta=0.0, nea
     (new positions of `targets` (all ions by default), F, intermediates)."""
     F, parts = total_force(grid, pos, q, species, p, near=near)
     kern = hydro_kernels(p, species)
-    fx, fy, fz = _spread(grid, pos, F, kern)
+    slip = hydro_walls(p)
+    fx, fy, fz = _spread(grid, pos, F, kern, slip=slip)
     if rfd_delta > 0.0:
-        tx, ty, tz = thermal_forcing(grid, pos, ids, p["kT"], rfd_delta, p["seed"], step, kern)
+        tx, ty, tz = thermal_forcing(grid, pos, ids, p["kT"], rfd_delta, p["seed"], step, kern,
+                                     slip=slip)
         fx, fy, fz = fx + tx, fy + ty, fz + tz
     if noise:
-        nfx, nfy, nfz = stokes.noise_force(grid, p["kT"], p["eta"], p["dt"], p["seed"], step)
+        nfx, nfy, nfz = stokes.noise_force(grid, p["kT"], p["eta"], p["dt"], p["seed"], step,
+                                           slip=slip)
         fx, fy, fz = fx + nfx, fy + nfy, fz + nfz
-    u, v, w, _ = stokes.solve_stokes(grid, p["eta"], fx, fy, fz)
+    u, v, w, _ = stokes.solve_stokes(grid, p["eta"], fx, fy, fz, slip=slip)
     sel = slice(None) if targets is None else np.asarray(targets)
     x0 = pos[:, sel]
     dt = p["dt"]
     ksel = None if kern is None else kern[sel]
-    V0 = _interp(grid, x0, u, v, w, ksel)
+    V0 = _interp(grid, x0, u, v, w, ksel, slip)
     mid = confine(grid, x0 + 0.5 * dt * V0)
-    V1 = _interp(grid, mid, u, v, w, ksel)
+    V1 = _interp(grid, mid, u, v, w, ksel, slip)
     disp = dt * V1 + dry_displacement(grid, x0, F[:, sel], species[sel], ids[sel], p, step)
     new = confine(grid, x0 + disp)
     return new, F, dict(parts, V0=V0, V1=V1, mid=mid, vel=(u, v, w))

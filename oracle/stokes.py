@@ -1,14 +1,16 @@
-"""Overdamped Stokes with no-slip walls on the MAC grid, written from Sec. II.A
-(eq stokes, eq disc_stokes, eq fluidbc no-slip case, eq kernel1 / kernel2, the image
-construction of Fig. folded and the ghost rule for interpolation).
+"""Overdamped Stokes with no-slip or slip walls on the MAC grid, written from Sec. II.A
+(eq stokes, eq disc_stokes, eq fluidbc, eq kernel1 / kernel2, the image construction of
+Fig. folded and the ghost rule for interpolation).
 
 Part of the test oracle (test infrastructure only).
 
 Layout (staggered / MAC): u on x-faces (i h, (j+1/2) h, (k+1/2) h) as [nz][ny][nx],
 v on y-faces, w on z-faces ((i+1/2) h, (j+1/2) h, k h) as [nz+1][ny][nx] with
-k = 0 and nz on the walls, pressure at cell centres [nz][ny][nx].  No-slip:
-w = 0 on the wall faces; the tangential components have ghosts u_{-1} = -u_0
-(zero at the wall, second order), mirrored at the top.
+k = 0 and nz on the walls, pressure at cell centres [nz][ny][nx].  Every wall has
+w = 0 on its face.  At a no-slip wall the tangential components have ghosts
+u_{-1} = -u_0 (zero at the wall, second order); at a slip wall (zero tangential stress,
+eq fluidbc) u_{-1} = +u_0; mirrored at the top.  `slip` = (lower, upper) selects the
+type of each wall (default no-slip).
 
 Discrete operator (eq disc_stokes):   G p - eta lap_h v = f,   D v = 0
   (G_x p)_i = (p_i - p_{i-1}) / h on x-faces, likewise y; (G_z p)_k = (p_k - p_{k-1}) / h
@@ -17,10 +19,15 @@ Discrete operator (eq disc_stokes):   G p - eta lap_h v = f,   D v = 0
 
 Stochastic stress (eq disc_stokes_temp): f_noise = sqrt(2 kT eta / (dV dt)) div_h Z,
 with Z symmetric, diagonal entries at cell centres of variance 2, off-diagonal
-entries on cell edges of variance 1; the xz and yz edges that lie on a wall have
-variance 2, the reading under which the discrete fluctuation-dissipation balance
-holds exactly with these ghost rules (pinned by the covariance identity in the
-tests).  The paper puts Delta t under the square root and also calls the Gaussian
+entries on cell edges of variance 1; the xz and yz edges that lie on a no-slip wall
+have variance 2 and those on a slip wall variance 0 (a slip wall carries no
+tangential stress), the readings under which the discrete fluctuation-dissipation
+balance holds exactly with these ghost rules (pinned by the covariance identity in
+the tests).
+
+Two slip walls leave the kappa = 0 tangential problem singular (constant flow is free
+and a net force has no steady solution).  Like the kappa = 0 mode of a periodic box,
+that mode is solved with its z-mean force removed and its z-mean velocity zero.  The paper puts Delta t under the square root and also calls the Gaussian
 "scaled by 1/sqrt(dt)"; it is counted once.
 """
 import numpy as np
@@ -39,14 +46,20 @@ def _check(grid, pos, slack=0.0):
         raise ValueError("ion outside the channel")
 
 
-def spread_force(grid, pos, F, slack=0.0):
-    """S^hy F on the faces with no-slip images (eq kernel2, Fig. folded).
+def _tsign(slip):
+    """Image sign of the tangential components at the (lower, upper) wall."""
+    return (1.0 if slip[0] else -1.0), (1.0 if slip[1] else -1.0)
 
-    Every component's image is opposite (zero tangential and normal mobility at a
-    no-slip wall).  x and y components live at cell-centre heights: a node below
-    the wall (k < 0) lands on -1-k with sign -1.  The z component lives on z-faces:
-    a node at k < 0 lands on -k with sign -1, so the wall face itself collects
-    f - f = 0; likewise at the top.
+
+def spread_force(grid, pos, F, slack=0.0, slip=(False, False)):
+    """S^hy F on the faces with wall images (eq kernel2, Fig. folded).
+
+    The normal component's image is opposite (zero normal mobility at any wall); the
+    tangential components' image is opposite at a no-slip wall and equal at a slip
+    wall.  x and y components live at cell-centre heights: a node below the wall
+    (k < 0) lands on -1-k with the tangential sign.  The z component lives on
+    z-faces: a node at k < 0 lands on -k with sign -1, so the wall face itself
+    collects f - f = 0; likewise at the top.
 
     `slack` admits kernel centres up to that far outside the walls (the shifted
     positions of the random finite difference); the same folds apply.
@@ -63,12 +76,14 @@ def spread_force(grid, pos, F, slack=0.0):
             lo, hi = iz < 0, iz >= nz
             iz = np.where(lo, -1 - iz, np.where(hi, 2 * nz - 1 - iz, iz))
             arr = np.zeros((nz, ny, nx))
+            s_lo, s_hi = _tsign(slip)
         else:
             lo, hi = iz < 0, iz > nz
             iz = np.where(lo, -iz, np.where(hi, 2 * nz - iz, iz))
             arr = np.zeros((nz + 1, ny, nx))
-        s[lo] = -1.0
-        s[hi] = -1.0
+            s_lo, s_hi = -1.0, -1.0
+        s[lo] = s_lo
+        s[hi] = s_hi
         for c in range(5):
             for b in range(5):
                 for a in range(5):
@@ -91,9 +106,9 @@ def _kernel_groups(kernels, n):
     return [(k, np.array(v, dtype=np.int64)) for k, v in groups.items()]
 
 
-def spread_force_kernels(grid, pos, F, kernels, slack=0.0):
+def spread_force_kernels(grid, pos, F, kernels, slack=0.0, slip=(False, False)):
     """S^hy F as spread_force, each ion with its own kernel (oracle.esc): the kernel's
-    nodes on the nine-node window, the same no-slip folds."""
+    nodes on the nine-node window, the same wall folds."""
     _check(grid, pos, slack)
     nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
     out = [np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx)), np.zeros((nz + 1, ny, nx))]
@@ -107,11 +122,13 @@ def spread_force_kernels(grid, pos, F, kernels, slack=0.0):
             if comp < 2:
                 lo, hi = iz < 0, iz >= nz
                 iz = np.where(lo, -1 - iz, np.where(hi, 2 * nz - 1 - iz, iz))
+                s_lo, s_hi = _tsign(slip)
             else:
                 lo, hi = iz < 0, iz > nz
                 iz = np.where(lo, -iz, np.where(hi, 2 * nz - iz, iz))
-            s[lo] = -1.0
-            s[hi] = -1.0
+                s_lo, s_hi = -1.0, -1.0
+            s[lo] = s_lo
+            s[hi] = s_hi
             f = F[comp, idx]
             for c in range(9):
                 for b in range(9):
@@ -123,12 +140,13 @@ def spread_force_kernels(grid, pos, F, kernels, slack=0.0):
     return tuple(out)
 
 
-def interp_velocity_kernels(grid, pos, u, v, w, kernels):
+def interp_velocity_kernels(grid, pos, u, v, w, kernels, slip=(False, False)):
     """J^hy v as interp_velocity, each ion with its own kernel, ghosts five layers deep."""
     _check(grid, pos)
     nx, ny, h = grid.nx, grid.ny, grid.h
     depth = 5
-    fields = (_ghost_tangential(u, depth), _ghost_tangential(v, depth), _ghost_normal(w, depth))
+    fields = (_ghost_tangential(u, depth, slip), _ghost_tangential(v, depth, slip),
+              _ghost_normal(w, depth))
     out = np.zeros((3, pos.shape[1]))
     for kern, idx in _kernel_groups(kernels, pos.shape[1]):
         p = pos[:, idx]
@@ -147,14 +165,16 @@ def interp_velocity_kernels(grid, pos, u, v, w, kernels):
     return out
 
 
-def _ghost_tangential(a, depth=3):
-    """[nz + 2 depth] cell-height layers with u_{-1-m} = -u_m, u_{nz+m} = -u_{nz-1-m}."""
+def _ghost_tangential(a, depth=3, slip=(False, False)):
+    """[nz + 2 depth] cell-height layers with u_{-1-m} = s_lo u_m and
+    u_{nz+m} = s_hi u_{nz-1-m}: s = -1 at a no-slip wall, +1 at a slip wall."""
     nz = a.shape[0]
+    s_lo, s_hi = _tsign(slip)
     out = np.empty((nz + 2 * depth,) + a.shape[1:])
     out[depth:depth + nz] = a
     for m in range(depth):
-        out[depth - 1 - m] = -a[m]
-        out[depth + nz + m] = -a[nz - 1 - m]
+        out[depth - 1 - m] = s_lo * a[m]
+        out[depth + nz + m] = s_hi * a[nz - 1 - m]
     return out
 
 
@@ -169,13 +189,14 @@ def _ghost_normal(wf, depth=3):
     return out
 
 
-def interp_velocity(grid, pos, u, v, w):
+def interp_velocity(grid, pos, u, v, w, slip=(False, False)):
     """J^hy v = dV sum delta(x_i - r) v(r) per component (eq kernel1), ghosts filled
-    with the no-slip rules so the adjoint identity holds with spread_force."""
+    with the wall rules so the adjoint identity holds with spread_force."""
     _check(grid, pos)
     nx, ny, h = grid.nx, grid.ny, grid.h
     depth = 3
-    fields = (_ghost_tangential(u, depth), _ghost_tangential(v, depth), _ghost_normal(w, depth))
+    fields = (_ghost_tangential(u, depth, slip), _ghost_tangential(v, depth, slip),
+              _ghost_normal(w, depth))
     out = np.zeros((3, pos.shape[1]))
     for comp, offs in ((0, (0.0, 0.5, 0.5)), (1, (0.5, 0.0, 0.5)), (2, (0.5, 0.5, 0.0))):
         ix, wx = node_weights(pos[0], h, offs[0], nx)
@@ -192,8 +213,8 @@ def interp_velocity(grid, pos, u, v, w):
 
 # ---- operator -------------------------------------------------------------------
 
-def _lap_tangential(a, h):
-    g = _ghost_tangential(a, 1)
+def _lap_tangential(a, h, slip=(False, False)):
+    g = _ghost_tangential(a, 1, slip)
     lz = (g[2:] - 2 * a + g[:-2]) / h ** 2
     lx = (np.roll(a, -1, 2) - 2 * a + np.roll(a, 1, 2)) / h ** 2
     ly = (np.roll(a, -1, 1) - 2 * a + np.roll(a, 1, 1)) / h ** 2
@@ -209,15 +230,15 @@ def _lap_normal(wf, h):
     return lx + ly + lz
 
 
-def apply_stokes(grid, eta, u, v, w, p):
+def apply_stokes(grid, eta, u, v, w, p, slip=(False, False)):
     """(G p - eta lap_h v, D v): force on the faces (w rows on interior faces only)
     and the divergence in the cells.  The plain definition of eq disc_stokes."""
     h = grid.h
     wf = w.copy()
     wf[0] = 0.0
     wf[-1] = 0.0
-    fx = (p - np.roll(p, 1, 2)) / h - eta * _lap_tangential(u, h)
-    fy = (p - np.roll(p, 1, 1)) / h - eta * _lap_tangential(v, h)
+    fx = (p - np.roll(p, 1, 2)) / h - eta * _lap_tangential(u, h, slip)
+    fy = (p - np.roll(p, 1, 1)) / h - eta * _lap_tangential(v, h, slip)
     fz = np.zeros_like(w)
     fz[1:-1] = (p[1:] - p[:-1]) / h - eta * _lap_normal(wf, h)
     div = ((np.roll(u, -1, 2) - u) + (np.roll(v, -1, 1) - v) + (wf[1:] - wf[:-1])) / h
@@ -226,8 +247,10 @@ def apply_stokes(grid, eta, u, v, w, p):
 
 # ---- solve ----------------------------------------------------------------------
 
-def solve_stokes(grid, eta, fx, fy, fz):
-    """Solve eq disc_stokes for (u, v, w, p) with no-slip walls; pressure gauge mean 0.
+def solve_stokes(grid, eta, fx, fy, fz, slip=(False, False)):
+    """Solve eq disc_stokes for (u, v, w, p) with the walls of `slip`; pressure gauge
+    mean 0 (and, with two slip walls, the kappa = 0 tangential flow of zero mean for
+    the force with its mean removed).
 
     In-plane DFT; for each mode a banded system in z with unknowns ordered
     (u_k, v_k, w_k, p_k), solved by LU with partial pivoting (LAPACK gbsv).  The
@@ -248,9 +271,11 @@ def solve_stokes(grid, eta, fx, fy, fz):
     ih2 = 1.0 / h ** 2
     k = np.arange(nz)
     iu, iv, iw, ip = 4 * k, 4 * k + 1, 4 * k + 2, 4 * k + 3
-    wall_extra = np.where((k == 0) | (k == nz - 1), ih2, 0.0)
-    if nz == 1:
-        wall_extra = np.array([2 * ih2])
+    # ghost term of the wall rows: u_{-1} = -u_0 adds +1/h^2, u_{-1} = +u_0 adds -1/h^2
+    s_lo, s_hi = _tsign(slip)
+    wall_extra = np.zeros(nz)
+    wall_extra[0] += -s_lo * ih2
+    wall_extra[nz - 1] += -s_hi * ih2
     for n_ in range(ny):
         for m in range(nx):
             tx = 2 * np.pi * m / nx
@@ -267,7 +292,7 @@ def solve_stokes(grid, eta, fx, fy, fz):
                                     np.broadcast_to(vals, np.shape(np.atleast_1d(rows)))):
                     A[(int(r), int(c))] = v_
 
-            # tangential momentum rows (ghost -u_0 at both walls)
+            # tangential momentum rows (wall ghosts of `slip`)
             for rows, g in ((iu, gx), (iv, gy)):
                 put(rows, rows, eta * (2 * ih2 + k2 + wall_extra))
                 put(rows[1:], rows[:-1], -eta * ih2)
@@ -298,6 +323,14 @@ def solve_stokes(grid, eta, fx, fy, fz):
                 D[nu - 1, :] = 0.0
                 D[nu - 1, ip] = 1.0
                 rhs[nu - 1] = 0.0
+                if slip[0] and slip[1]:
+                    # the tangential rows sum to zero: remove the mean force and let
+                    # the last row of each component fix the mean flow to zero
+                    for rows in (iu, iv):
+                        rhs[rows] -= rhs[rows].mean()
+                        D[rows[-1], :] = 0.0
+                        D[rows[-1], rows] = 1.0
+                        rhs[rows[-1]] = 0.0
                 x = np.linalg.solve(D, rhs)
             else:
                 ab = np.zeros((2 * bw + 1, nu), dtype=complex)
@@ -340,19 +373,20 @@ def stress_normals(grid, seed, step):
             e1.reshape(shl), e2.reshape(shl))
 
 
-def stress_divergence(grid, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz):
+def stress_divergence(grid, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, slip=(False, False)):
     """div_h Z on the faces for the symmetric stress built from unit normals.
 
     Z_aa = sqrt(2) W_aa at cell centres; Z_xy = W_xy on edges (i h, j h, (k+1/2) h);
     Z_xz = W_xz on edges (i h, (j+1/2) h, k h), Z_yz = W_yz on ((i+1/2) h, j h, k h),
-    k = 0..nz, times sqrt(2) on the wall levels k = 0 and nz.
+    k = 0..nz, times sqrt(2) on a no-slip wall level (k = 0 or nz) and 0 on a slip one.
     """
     h = grid.h
     nz = grid.nz
     s2 = np.sqrt(2.0)
     Zxx, Zyy, Zzz = s2 * Wxx, s2 * Wyy, s2 * Wzz
     wall = np.ones((nz + 1, 1, 1))
-    wall[0] = wall[-1] = s2
+    wall[0] = 0.0 if slip[0] else s2
+    wall[-1] = 0.0 if slip[1] else s2
     Zxz = Wxz * wall
     Zyz = Wyz * wall
     Zxy = Wxy
@@ -367,24 +401,25 @@ def stress_divergence(grid, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz):
     return fx, fy, fz
 
 
-def noise_force(grid, kT, eta, dt, seed, step):
+def noise_force(grid, kT, eta, dt, seed, step, slip=(False, False)):
     """sqrt(2 kT eta / (dV dt)) div_h Z (eq disc_stokes_temp)."""
     amp = np.sqrt(2.0 * kT * eta / (grid.dV * dt))
-    fx, fy, fz = stress_divergence(grid, *stress_normals(grid, seed, step))
+    fx, fy, fz = stress_divergence(grid, *stress_normals(grid, seed, step), slip=slip)
     return amp * fx, amp * fy, amp * fz
 
 
-def velocity_at_ions(grid, pos, F, eta, kT=0.0, dt=1.0, seed=0, step=0, kernels=None):
+def velocity_at_ions(grid, pos, F, eta, kT=0.0, dt=1.0, seed=0, step=0, kernels=None,
+                     slip=(False, False)):
     """V = J^hy L^-1 (S^hy F + noise) (eq ions2 without the thermal drift); kernels:
     per-ion hydrodynamic kernels (w, beta), or None for the 4-point Peskin kernel."""
     if kernels is None:
-        fx, fy, fz = spread_force(grid, pos, F)
+        fx, fy, fz = spread_force(grid, pos, F, slip=slip)
     else:
-        fx, fy, fz = spread_force_kernels(grid, pos, F, kernels)
+        fx, fy, fz = spread_force_kernels(grid, pos, F, kernels, slip=slip)
     if kT > 0.0:
-        nx_, ny_, nz_ = noise_force(grid, kT, eta, dt, seed, step)
+        nx_, ny_, nz_ = noise_force(grid, kT, eta, dt, seed, step, slip=slip)
         fx, fy, fz = fx + nx_, fy + ny_, fz + nz_
-    u, v, w, p = solve_stokes(grid, eta, fx, fy, fz)
+    u, v, w, p = solve_stokes(grid, eta, fx, fy, fz, slip=slip)
     if kernels is None:
-        return interp_velocity(grid, pos, u, v, w), (u, v, w, p)
-    return interp_velocity_kernels(grid, pos, u, v, w, kernels), (u, v, w, p)
+        return interp_velocity(grid, pos, u, v, w, slip=slip), (u, v, w, p)
+    return interp_velocity_kernels(grid, pos, u, v, w, kernels, slip=slip), (u, v, w, p)
