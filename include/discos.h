@@ -95,7 +95,17 @@ typedef struct discos_params {
     double rfd_delta;           /* step delta of the random finite difference that gives
                                    the thermal forcing f^th = kT div_x S^hy (eq thermforce)
                                    in a DISCOS_STEP_RFD step; (0, 0.1 h] */
+    /* hydrodynamic walls (eq fluidbc, Fig. folded) */
+    int32_t hydro_bc[2];        /* DISCOS_HYDRO_* for the wall at z = 0 [0] and z = Lz [1]:
+                                   no-slip (zero velocity, opposite images) or slip (zero
+                                   normal velocity and tangential stress, same-sign
+                                   tangential images); with two slip walls the in-plane
+                                   mean of the tangential force is solved with its z-mean
+                                   removed and zero z-mean flow */
 } discos_params;
+
+#define DISCOS_HYDRO_NOSLIP 0
+#define DISCOS_HYDRO_SLIP 1
 
 /* Ion state for discos_step.  pos, q, id and species are DEVICE arrays of length n. */
 typedef struct discos_ions {

@@ -137,6 +137,18 @@ double esc_integral(double w, double beta) {
     return alpha * sum;
 }
 
+// Wall types of the hydrodynamic calls (eq fluidbc): checked, then kept as the image
+// signs of the tangential velocity in the context's grid descriptor, which every
+// hydrodynamic kernel launched by this call receives.
+int set_hydro_walls(discos_ctx* c, const discos_params* p) {
+    for (int w = 0; w < 2; ++w)
+        if (p->hydro_bc[w] != DISCOS_HYDRO_NOSLIP && p->hydro_bc[w] != DISCOS_HYDRO_SLIP)
+            return fail(c, DISCOS_E_ARG, "hydro_bc must be DISCOS_HYDRO_NOSLIP or DISCOS_HYDRO_SLIP");
+    c->gd.tsg[0] = p->hydro_bc[0] == DISCOS_HYDRO_SLIP ? 1.0 : -1.0;
+    c->gd.tsg[1] = p->hydro_bc[1] == DISCOS_HYDRO_SLIP ? 1.0 : -1.0;
+    return DISCOS_OK;
+}
+
 template <class T>
 T* carve(char*& cur, size_t count) {
     T* p = reinterpret_cast<T*>(cur);
@@ -280,6 +292,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hvi = carve<double>(hc, 3 * nm);
         c->hmid = carve<double4>(hc, nm);
         c->hy_tab = carve<double>(hc, 4 * DISCOS_HY_MAXSP);
+        c->gd.tsg[0] = c->gd.tsg[1] = -1.0;  // no-slip until a call says otherwise
         // every species on the 4-point Peskin kernel (rows of zeros: w = 0); the Stokes
         // mode factorisation of this grid
         if (hipMemset(c->hy_tab, 0, 4 * DISCOS_HY_MAXSP * sizeof(double)) != hipSuccess ||
@@ -335,6 +348,8 @@ int discos_spread(discos_ctx* c, int op, int64_t n, const double* pos, const dou
     }
     if (base == DISCOS_SPREAD_FORCE) {
         if (add_bc) return fail(c, DISCOS_E_ARG, "DISCOS_SPREAD_ADD_BC applies to charges only");
+        rc = set_hydro_walls(c, p);
+        if (rc) return rc;
         rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, nullptr,
                                      s, w, n);
         if (rc) return fail(c, rc, "cell list launch failed");
@@ -369,7 +384,9 @@ int discos_solve_stokes(discos_ctx* c, const double* f, const discos_params* p, 
         return fail(c, DISCOS_E_ARG, "noise needs kT > 0 and dt > 0");
     const size_t total = 2 * (size_t)c->ncell + (size_t)c->nface_z;
     if (v < f + total && f < v + total) return fail(c, DISCOS_E_ARG, "f and v overlap");
-    int rc = discos::solve_stokes(c, f, p, step, noise, v, pres, s);
+    int rc = set_hydro_walls(c, p);
+    if (rc) return rc;
+    rc = discos::solve_stokes(c, f, p, step, noise, v, pres, s);
     return rc ? fail(c, rc, "stokes launch failed") : DISCOS_OK;
 }
 
@@ -392,6 +409,8 @@ int discos_interpolate(discos_ctx* c, int op, int64_t n, const double* pos, cons
     }
     if (op == DISCOS_INTERP_VEL) {
         if (n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
+        rc = set_hydro_walls(c, p);
+        if (rc) return rc;
         rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, nullptr, s);
         if (!rc) rc = discos::interp_hy_sorted(c, (int)n, field, out, n, 1, s);
         return rc ? fail(c, rc, "interpolation launch failed") : DISCOS_OK;
@@ -445,6 +464,7 @@ int discos_spread_force_species(discos_ctx* c, int64_t n, const double* pos, con
     if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
     if (!out || (n > 0 && (!pos || !F || !species))) return fail(c, DISCOS_E_ARG, "null array");
     int rc = check_es_params(c, p);
+    if (!rc) rc = set_hydro_walls(c, p);
     if (rc) return rc;
     rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, species, s,
                                  F, n);
@@ -464,6 +484,7 @@ int discos_interpolate_vel_species(discos_ctx* c, int64_t n, const double* pos, 
     if (n == 0) return DISCOS_OK;
     if (!pos || !v || !out || !species) return fail(c, DISCOS_E_ARG, "null array");
     int rc = check_es_params(c, p);
+    if (!rc) rc = set_hydro_walls(c, p);
     if (rc) return rc;
     rc = discos::build_cell_list(c, (int)n, pos, pos + n, pos + 2 * n, nullptr, nullptr, species, s);
     if (!rc) rc = discos::interp_hy_sorted(c, (int)n, v, out, n, 1, s, 1);
@@ -512,6 +533,10 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     // stays below half a cell, the reach the S^hy tiles assume
     if (rfd && !(finite_pos(p->rfd_delta) && p->rfd_delta <= 0.1 * c->grid.h))
         return fail(c, DISCOS_E_ARG, "rfd_delta must lie in (0, 0.1 h]");
+    if (wet) {
+        rc = set_hydro_walls(c, p);
+        if (rc) return rc;
+    }
     const int ni = (int)n;
     double* pos = ions->pos;
     discos::stage_mark(c, 0, s);

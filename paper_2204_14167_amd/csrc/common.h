@@ -21,6 +21,9 @@ struct GridDev {
     int nx, ny, nz, nxh;
     double h, inv_h, Lx, Ly, Lz;
     int nbx, nby, nbz;  // cell-list bins per dimension
+    // image sign of the tangential velocity components at the lower / upper wall:
+    // -1 no-slip, +1 slip (set per hydrodynamic call)
+    double tsg[2] = {-1.0, -1.0};
 };
 
 // Wall boundary data used by the field kernels.

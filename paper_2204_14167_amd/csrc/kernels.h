@@ -39,6 +39,7 @@ struct Ctx {
     int hydro;
     double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
     double* hfac;     // block-Thomas factors of the Stokes mode systems, 14 doubles per level and mode
+    int hfac_key;     // wall types hfac was computed for: bit 0 lower slip, bit 1 upper slip
     double* hz_diag;  // stress normals: xx, yy, zz, xy per cell
     double* hz_edge;  // stress normals: xz, yz per z-level edge
     double* hvel;     // face velocity scratch for the wet step (3 face arrays)

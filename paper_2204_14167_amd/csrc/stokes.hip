@@ -20,8 +20,9 @@ namespace discos {
 #define SH_MAXR 256
 
 // Deposit val * phi(x - node) / h^3 of one kernel centre (px, py, pz) into the tile.
-// COMP 0 / 1: x / y component at cell-centre heights, images fold k -> -1-k (sign -1).
-// COMP 2: z component on z-faces, images fold k -> -k (sign -1); wall faces hold 0.
+// COMP 0 / 1: x / y component at cell-centre heights, images fold k -> -1-k with the
+// wall's tangential sign g.tsg (-1 no-slip, +1 slip).  COMP 2: z component on z-faces,
+// images fold k -> -k (sign -1); wall faces hold 0.
 template <int COMP>
 __device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int x0, int y0, int z0,
                                              int tx, int ty, int tz, double px, double py,
@@ -46,8 +47,8 @@ __device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int 
             else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
             if (kz == 0 || kz == g.nz) continue;
         } else {
-            if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
-            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
+            if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
+            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
         }
         const int lz = kz - z0;
         if (lz < 0 || lz >= tz) continue;
@@ -133,8 +134,8 @@ __device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, in
             else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
             if (kz == 0 || kz == g.nz) continue;
         } else {
-            if (kz < 0) { kz = -1 - kz; sgn = -1.0; }
-            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = -1.0; }
+            if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
+            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
         }
         const int lz = kz - z0;
         if (lz < 0 || lz >= tz) continue;
@@ -274,7 +275,9 @@ __global__ void stress_kernel(GridDev g, uint64_t seed, uint64_t step, double* _
         zd[t + 2 * ncell] = s2 * a;
     }
     normal_pair(seed, step, DISCOS_TAG_STRESS_EDGE, 0u, (uint32_t)t, a, b);
-    const double ws = (k == 0 || k == g.nz) ? s2 : 1.0;
+    // wall edges: variance 2 on a no-slip wall, 0 on a slip wall (no tangential stress)
+    const double ws = k == 0 ? (g.tsg[0] > 0.0 ? 0.0 : s2)
+                             : (k == g.nz ? (g.tsg[1] > 0.0 ? 0.0 : s2) : 1.0);
     ze[t] = ws * a;          // xz
     ze[t + nlev] = ws * b;   // yz
     if (k < g.nz) {
@@ -352,7 +355,7 @@ __device__ __forceinline__ void inv3(const double M[9], double R[9]) {
 // factorisation depends only on the grid and is computed once per context.  Per level k
 // and mode t, fac[(k * SF_N + q) * nmode + t] holds
 //   q = 0, 1        1 / den_k and c'_k of the scalar tridiagonal (b, or u and v of the
-//                   mean flow: -D_zz + kappa^2 with the wall rows);
+//                   mean flow: -D_zz + kappa^2 with the wall rows of the wall types);
 //   q = 2 .. 7      columns 0, 1 of S_k^-1, S_k the pivot block of (a, w, p) (the
 //                   continuity row's right-hand side is zero, so column 2 is unused);
 //   q = 8 .. 13     columns 0, 1 of C'_k = S_k^-1 C_k (column 2 of C_k is zero).
@@ -371,7 +374,8 @@ __device__ __forceinline__ void mode_symbols(int t, int nx, int ny, double ih, d
 
 // Block-Thomas factorisation of every mode (rows E1 a-momentum, E2 w-momentum, E3
 // continuity; columns a, w, p; A, B, C the sub-, main and super-diagonal blocks).
-__global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, int nz, double h) {
+__global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, int nz, double h,
+                                     double tsg_lo, double tsg_hi) {
     const int nmode = (nx / 2 + 1) * ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nmode) return;
@@ -387,14 +391,15 @@ __global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, i
     double Cprev[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < nz; ++k) {
         double* f = fac + (size_t)k * SF_N * st + t;
-        const double wall = (k == 0 ? 1.0 : 0.0) + (k == nz - 1 ? 1.0 : 0.0);
+        // ghost u_{-1} = s u_0 of a tangential wall row adds -s / h^2
+        const double wall = (k == 0 ? -tsg_lo : 0.0) + (k == nz - 1 ? -tsg_hi : 0.0);
         const double da = dgn + wall * ih2;
         const double den = da - off * cb_prev;
         const double cb = off / den;
         f[0] = 1.0 / den;
         f[st] = cb;
         cb_prev = cb;
-        if (t == 0) continue;  // the mean flow uses the scalar factors only
+        if (t == 0) continue;  // the mean flow uses the scalar factors only (none with two slip walls)
         double B[9] = {da, 0.0, kap, 0.0, dgn, ih, -kap, -ih, 0.0};
         if (k == 0) { B[3] = 0.0; B[4] = 1.0; B[5] = 0.0; }  // w_0 = 0
         if (k > 0) {
@@ -477,6 +482,49 @@ __device__ void mean_flow_component(double2* __restrict__ col, const double* __r
     }
 }
 
+// Mean flow between two slip walls: -D_zz u = f / eta has the constant flow in its
+// null space and needs a zero-mean force.  The force's z-mean is removed and the flow
+// of zero z-mean taken: with d_{k+1/2} = u_{k+1} - u_k, d_{-1/2} = 0, each row gives
+// d_{k+1/2} = -h^2 sum_{j<=k} (g_j - mean g).
+__device__ void mean_flow_two_slip(double2* __restrict__ col, size_t st, int nz, double sc, double h2) {
+    double2 br[SM_AHEAD];
+    double2 fsum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < SM_AHEAD; ++j)
+        if (j < nz) br[j] = col[j * st];
+    for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            const int k = k0 + j;
+            if (k < nz) {
+                fsum = cadd(fsum, br[j]);
+                if (k + SM_AHEAD < nz) br[j] = col[(k + SM_AHEAD) * st];
+            }
+        }
+    }
+    const double2 gmean = cscale(sc / nz, fsum);
+    double2 G = make_double2(0.0, 0.0), u = G, usum = G;
+#pragma unroll
+    for (int j = 0; j < SM_AHEAD; ++j)
+        if (j < nz) br[j] = col[j * st];
+    for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
+#pragma unroll
+        for (int j = 0; j < SM_AHEAD; ++j) {
+            const int k = k0 + j;
+            if (k < nz) {
+                const double2 g = csub(cscale(sc, br[j]), gmean);
+                if (k + SM_AHEAD < nz) br[j] = col[(k + SM_AHEAD) * st];
+                col[k * st] = u;
+                usum = cadd(usum, u);
+                G = cadd(G, g);
+                u = csub(u, cscale(h2, G));
+            }
+        }
+    }
+    const double2 umean = cscale(1.0 / nz, usum);
+    for (int k = 0; k < nz; ++k) col[k * st] = csub(col[k * st], umean);
+}
+
 // Mean pressure from G_z p = f_z (p_0 = 0, then mean zero) and w = 0.
 __device__ void mean_pressure(double2* __restrict__ sw, double2* __restrict__ sp, size_t st, int nz,
                               double hn) {
@@ -513,7 +561,7 @@ __device__ void mean_pressure(double2* __restrict__ sw, double2* __restrict__ sp
 __global__ void __launch_bounds__(64)
 stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* __restrict__ sw,
                    double2* __restrict__ sp, const double* __restrict__ fac, int nx, int ny,
-                   int nz, double h, double eta, double norm) {
+                   int nz, double h, double eta, double norm, int two_slip) {
     const int nmode = (nx / 2 + 1) * ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nmode + 2) return;
@@ -522,7 +570,8 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
     const double off = -ih2;
     const double sc = norm / eta;  // scaled right-hand side
     if (t == 0 || t == nmode) {
-        mean_flow_component(t == 0 ? su : sv, fac, st, nz, sc, off);
+        if (two_slip) mean_flow_two_slip(t == 0 ? su : sv, st, nz, sc, h * h);
+        else mean_flow_component(t == 0 ? su : sv, fac, st, nz, sc, off);
         return;
     }
     if (t == nmode + 1) {
@@ -647,14 +696,15 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
 }
 
 // ---- J^hy -------------------------------------------------------------------------
-// V = J^hy v with the no-slip ghosts: tangential components u_{-1-m} = -u_m (cell
-// heights), normal component w_{-k} = -w_k (faces), mirrored at the top.
+// V = J^hy v with the wall ghosts: tangential components u_{-1-m} = s u_m (cell
+// heights; s = -1 no-slip, +1 slip), normal component w_{-k} = -w_k (faces), mirrored
+// at the top.
 __device__ __forceinline__ double face_val(const double* __restrict__ a, const GridDev& g, int comp,
                                            int i, int j, int k) {
     double s = 1.0;
     if (comp < 2) {
-        if (k < 0) { k = -1 - k; s = -1.0; }
-        else if (k >= g.nz) { k = 2 * g.nz - 1 - k; s = -1.0; }
+        if (k < 0) { k = -1 - k; s = g.tsg[0]; }
+        else if (k >= g.nz) { k = 2 * g.nz - 1 - k; s = g.tsg[1]; }
         k = min(max(k, 0), g.nz - 1);
     } else {
         if (k < 0) { k = -k; s = -1.0; }
@@ -713,8 +763,8 @@ __global__ void __launch_bounds__(256) interp_hy_kernel(GridDev g, int n, const 
                 int k = iz0 + c;
                 double sg = 1.0;
                 if (comp < 2) {
-                    if (k < 0) { k = -1 - k; sg = -1.0; }
-                    else if (k >= g.nz) { k = 2 * g.nz - 1 - k; sg = -1.0; }
+                    if (k < 0) { k = -1 - k; sg = g.tsg[0]; }
+                    else if (k >= g.nz) { k = 2 * g.nz - 1 - k; sg = g.tsg[1]; }
                     k = min(max(k, 0), g.nz - 1);
                 } else {
                     if (k < 0) { k = -k; sg = -1.0; }
@@ -819,7 +869,8 @@ int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s);
 int stokes_factor(Ctx* c, hipStream_t s) {
     const int nmode = c->gd.nxh * c->gd.ny;
     stokes_factor_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->hfac, c->gd.nx, c->gd.ny, c->gd.nz,
-                                                         c->grid.h);
+                                                         c->grid.h, c->gd.tsg[0], c->gd.tsg[1]);
+    c->hfac_key = (c->gd.tsg[0] > 0.0 ? 1 : 0) | (c->gd.tsg[1] > 0.0 ? 2 : 0);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -829,6 +880,12 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t ncell = (size_t)nx * ny * nz;
     const size_t nlev = (size_t)nx * ny * (nz + 1);
+    // factors of the current wall types (they are cached per context)
+    const int key = (g.tsg[0] > 0.0 ? 1 : 0) | (g.tsg[1] > 0.0 ? 2 : 0);
+    if (key != c->hfac_key) {
+        const int rcf = stokes_factor(c, s);
+        if (rcf) return rcf;
+    }
     const double* frhs = f;
     if (noise) {
         // f + amp div Z, built in the velocity buffer (the solve reads it once)
@@ -854,7 +911,7 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
     const int nmode = g.nxh * ny;
     const double norm = 1.0 / ((double)nx * ny);
     stokes_mode_kernel<<<(nmode + 2 + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hfac, nx, ny, nz,
-                                                       c->grid.h, p->eta, norm);
+                                                       c->grid.h, p->eta, norm, key == 3 ? 1 : 0);
     rc = fft_cols(c, su, nz, 1, s);
     if (!rc) rc = fft_cols(c, sv, nz, 1, s);
     if (!rc) rc = fft_cols(c, sw, nz + 1, 1, s);

@@ -23,6 +23,7 @@ INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
 STEP_DRY, STEP_WET, STEP_RFD = 0, 1, 0x10
 CREATE_HYDRO = 1
 STOKES_NOISE = 1
+HYDRO_NOSLIP, HYDRO_SLIP = 0, 1
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -59,6 +60,7 @@ class DiscosParams(ctypes.Structure):
         ("mob_coef", ctypes.c_void_p),
         ("seed", ctypes.c_uint64),
         ("rfd_delta", ctypes.c_double),
+        ("hydro_bc", ctypes.c_int32 * 2),
     ]
 
 
@@ -210,6 +212,10 @@ class Params:
             s.mob_coef = c.data_ptr()
         s.seed = int(p.get("seed", 0))
         s.rfd_delta = float(p.get("rfd_delta", 0.0))
+        # hydrodynamic walls: p["slip"] = (lower, upper), default no-slip
+        sl = p.get("slip", (False, False))
+        s.hydro_bc[0] = HYDRO_SLIP if sl[0] else HYDRO_NOSLIP
+        s.hydro_bc[1] = HYDRO_SLIP if sl[1] else HYDRO_NOSLIP
         self.struct = s
 
 
