@@ -239,8 +239,9 @@ def wet_stage_bytes(stage, N, C3):
 
 def wet_timing(steps, warmup=2):
     """Wet midpoint steps (+ random finite difference, stochastic stress) on the
-    resolved-hydrodynamics channel, with the 4-point Peskin kernel and with the ESC
-    pair per species: ion-timesteps/s and per-stage times (hipEvents).
+    resolved-hydrodynamics channel, with the 4-point Peskin kernel, with the ESC pair
+    per species, and with the Peskin kernel between two slip walls: ion-timesteps/s and
+    per-stage times (hipEvents).
 
     Every timed step starts from the workload's initial ions (restored by on-device
     copies outside the timed brackets; each step draws new noise).  The workload has no
@@ -257,11 +258,13 @@ def wet_timing(steps, warmup=2):
     out = {"workload": WET_WORKLOAD, "n_ions": w.n, "grid": [w.nx, w.ny, w.nz],
            "mode": "wet midpoint step + RFD, stochastic stress, no-slip walls", "steps": steps,
            "timing": "each step from the initial ions, hipEvents around discos_step"}
-    for name, kern in (("peskin4", None), ("esc_w7b7_w4b8", ESC_PAIR)):
+    for name, kern, slip in (("peskin4", None, (False, False)),
+                             ("esc_w7b7_w4b8", ESC_PAIR, (False, False)),
+                             ("peskin4_two_slip_walls", None, (True, True))):
         ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, hydro=True)
         if kern is not None:
             ctx.set_hydro_kernel(kern)
-        dp = ctx.params(p)
+        dp = ctx.params(dict(p, slip=slip))
         base = [torch.from_numpy(a.copy()).cuda() for a in (pos, q, ids, species)]
         arr = [t.clone() for t in base]
         mode = discos.STEP_WET | discos.STEP_RFD
@@ -296,6 +299,7 @@ def wet_timing(steps, warmup=2):
             stages[k] = e
         out[name] = {"kernels": "4-point Peskin" if kern is None else
                      "ESC (w, beta) = (7, 7) cations, (4, 8) anions",
+                     "walls": "slip, slip" if slip[0] else "no-slip, no-slip",
                      "ms_per_step": 1e3 * el / steps, "ion_timesteps_per_s": w.n * steps / el,
                      "stages": stages}
     return out

@@ -24,17 +24,19 @@ import numpy as np
 PESKIN4_RADIUS = 1.2555  # free-space hydrodynamic radius of the 4-point Peskin kernel, in h
 
 
-def _params(eta):
-    # only eta enters the deterministic pull; the electrostatic fields are unused
-    return dict(eps=1.0, bc_types=(0, 0), bc_values=None, eta=eta, kT=0.0, dt=1.0)
+def _params(eta, slip=(False, False)):
+    # only eta and the wall types enter the deterministic pull; the electrostatic
+    # fields are unused
+    return dict(eps=1.0, bc_types=(0, 0), bc_values=None, eta=eta, kT=0.0, dt=1.0, slip=slip)
 
 
-def pull_mobility(ctx, heights, eta, x0, y0):
+def pull_mobility(ctx, heights, eta, x0, y0, slip=(False, False)):
     """Mobility (velocity per unit force) of a single ion at (x0, y0, z) for each z in
-    heights: parallel (force and velocity along x) and perpendicular (along z)."""
+    heights: parallel (force and velocity along x) and perpendicular (along z), with
+    the hydrodynamic walls of `slip` = (lower, upper) (eq fluidbc)."""
     import torch
     from . import discos
-    prm = ctx.params(_params(eta))
+    prm = ctx.params(_params(eta, slip))
     par = np.empty(len(heights))
     perp = np.empty(len(heights))
     for k, z in enumerate(heights):
@@ -50,10 +52,11 @@ def pull_mobility(ctx, heights, eta, x0, y0):
     return par, perp
 
 
-def measure(nx, ny, nz, h=1.0, eta=1.0 / (6.0 * np.pi), heights=None, x0=None, y0=None):
+def measure(nx, ny, nz, h=1.0, eta=1.0 / (6.0 * np.pi), heights=None, x0=None, y0=None,
+            slip=(False, False)):
     """gamma_parallel(y), gamma_perpendicular(y) at the wall distances y = heights (from
     the lower wall, default 0 .. Lz/2 in steps of h/8), relative to the free-space
-    mobility of the kernel."""
+    mobility of the kernel; `slip` = (lower, upper) wall types."""
     from . import discos
     Lz = nz * h
     if heights is None:
@@ -63,7 +66,7 @@ def measure(nx, ny, nz, h=1.0, eta=1.0 / (6.0 * np.pi), heights=None, x0=None, y
     y0 = 0.5 * ny * h if y0 is None else y0
     ctx = discos.Context(nx, ny, nz, h, 1, hydro=True)
     try:
-        par, perp = pull_mobility(ctx, heights, eta, x0, y0)
+        par, perp = pull_mobility(ctx, heights, eta, x0, y0, slip)
     finally:
         ctx.close()
     mu0 = 1.0 / (6.0 * np.pi * eta * PESKIN4_RADIUS * h)

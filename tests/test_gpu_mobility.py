@@ -1,6 +1,6 @@
 """Wall mobility measured on the GPU Stokes solver (Sec. III.A): single-ion pulls at
-kT = 0 (S^hy, no-slip Stokes solve, J^hy through the library) equal the oracle's pull
-velocities to 1e-10; on the paper's channel (24 cells high) the measured gamma vanishes
+kT = 0 (S^hy, Stokes solve, J^hy through the library) equal the oracle's pull
+velocities to 1e-10, between no-slip walls and with a slip wall; on the paper's channel (24 cells high) the measured gamma vanishes
 on the wall, agrees with the analytic channel mobility of eq mob_analytic away from it,
 and its fit of eq fitfunction stays inside [0, 1] down to the wall."""
 import numpy as np
@@ -30,6 +30,28 @@ def test_pulls_match_oracle():
             want = stokes.velocity_at_ions(grid, pos, F, ETA)[0][d, 0]
             log(f"pull z={z} dir={d}: GPU {got:.15e} oracle {want:.15e}")
             assert abs(got - want) <= 1e-10 * abs(want) + 1e-300
+
+
+def test_slip_wall_pulls_match_oracle():
+    """Pulls between a slip wall (below) and a no-slip wall (above) equal the
+    oracle's; at the slip wall the parallel mobility rises (same-sign image) and the
+    perpendicular one vanishes."""
+    from paper_2204_14167_amd import discos, mobility_measure as mm
+    nx, ny, nz = 16, 16, 12
+    grid = es.Grid(nx, ny, nz)
+    heights = [0.0, 0.4, 1.5, 6.0, 11.5]
+    x0, y0 = 8.2, 7.1
+    slip = (True, False)
+    ctx = discos.Context(nx, ny, nz, 1.0, 1, hydro=True)
+    par, perp = mm.pull_mobility(ctx, heights, ETA, x0, y0, slip=slip)
+    for k, z in enumerate(heights):
+        pos = np.array([[x0], [y0], [z]])
+        for d, got in ((0, par[k]), (2, perp[k])):
+            F = np.zeros((3, 1))
+            F[d, 0] = 1.0
+            want = stokes.velocity_at_ions(grid, pos, F, ETA, slip=slip)[0][d, 0]
+            assert abs(got - want) <= 1e-10 * abs(want) + 1e-15
+    assert par[0] > 1.5 * par[3] and abs(perp[0]) < 1e-14 and par[4] < 0.3 * par[3]
 
 
 def test_measured_channel_mobility_and_fit():
