@@ -353,13 +353,15 @@ __device__ __forceinline__ void inv3(const double M[9], double R[9]) {
 
 // The mode systems scaled by 1 / eta (pressure p' = p / eta): eta-free, so their
 // factorisation depends only on the grid and is computed once per context.  Per level k
-// and mode t, fac[(k * SF_N + q) * nmode + t] holds
-//   q = 0, 1        1 / den_k and c'_k of the scalar tridiagonal (b, or u and v of the
+// and mode t, the double2 pairs fac2[(k * SF_P + q) * nmode + t] hold
+//   q = 0           (1 / den_k, c'_k) of the scalar tridiagonal (b, or u and v of the
 //                   mean flow: -D_zz + kappa^2 with the wall rows of the wall types);
-//   q = 2 .. 7      columns 0, 1 of S_k^-1, S_k the pivot block of (a, w, p) (the
-//                   continuity row's right-hand side is zero, so column 2 is unused);
-//   q = 8 .. 13     columns 0, 1 of C'_k = S_k^-1 C_k (column 2 of C_k is zero).
-#define SF_N 14
+//   q = 1 .. 3      row q-1 of S_k^-1, columns 0 and 1 (S_k the pivot block of (a, w, p);
+//                   the continuity row's right-hand side is zero, so column 2 is unused);
+//   q = 4 .. 6      row q-4 of C'_k = S_k^-1 C_k, columns 0 and 1 (column 2 of C_k is 0).
+// Pairs halve the load instructions per level: the sweeps are bound by the loads a
+// wave can keep in flight.
+#define SF_P 7
 
 __device__ __forceinline__ void mode_symbols(int t, int nx, int ny, double ih, double2& gx,
                                              double2& gy, double& k2) {
@@ -390,14 +392,13 @@ __global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, i
     double cb_prev = 0.0;
     double Cprev[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < nz; ++k) {
-        double* f = fac + (size_t)k * SF_N * st + t;
+        double2* f = reinterpret_cast<double2*>(fac) + (size_t)k * SF_P * st + t;
         // ghost u_{-1} = s u_0 of a tangential wall row adds -s / h^2
         const double wall = (k == 0 ? -tsg_lo : 0.0) + (k == nz - 1 ? -tsg_hi : 0.0);
         const double da = dgn + wall * ih2;
         const double den = da - off * cb_prev;
         const double cb = off / den;
-        f[0] = 1.0 / den;
-        f[st] = cb;
+        f[0] = make_double2(1.0 / den, cb);
         cb_prev = cb;
         if (t == 0) continue;  // the mean flow uses the scalar factors only (none with two slip walls)
         double B[9] = {da, 0.0, kap, 0.0, dgn, ih, -kap, -ih, 0.0};
@@ -419,10 +420,8 @@ __global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, i
             Cprev[3 * r + 0] = Si[3 * r + 0] * off;
             Cprev[3 * r + 1] = Si[3 * r + 1] * c11 + Si[3 * r + 2] * ih;
             Cprev[3 * r + 2] = 0.0;
-            f[(2 + 2 * r) * st] = Si[3 * r + 0];
-            f[(3 + 2 * r) * st] = Si[3 * r + 1];
-            f[(8 + 2 * r) * st] = Cprev[3 * r + 0];
-            f[(9 + 2 * r) * st] = Cprev[3 * r + 1];
+            f[(1 + r) * st] = make_double2(Si[3 * r + 0], Si[3 * r + 1]);
+            f[(4 + r) * st] = make_double2(Cprev[3 * r + 0], Cprev[3 * r + 1]);
         }
     }
 }
@@ -433,13 +432,13 @@ __global__ void stokes_factor_kernel(double* __restrict__ fac, int nx, int ny, i
 
 // Mean flow (kappa = 0): -D_zz u = f / eta with the wall rows for one tangential
 // component (col: its [nz] levels at stride st), by the scalar factors of mode 0.
-__device__ void mean_flow_component(double2* __restrict__ col, const double* __restrict__ F,
+__device__ void mean_flow_component(double2* __restrict__ col, const double2* __restrict__ F,
                                     size_t st, int nz, double sc, double off) {
     double2 br[SM_AHEAD];
     double bf[SM_AHEAD];
 #pragma unroll
     for (int j = 0; j < SM_AHEAD; ++j)
-        if (j < nz) { br[j] = col[j * st]; bf[j] = F[(size_t)j * SF_N * st]; }
+        if (j < nz) { br[j] = col[j * st]; bf[j] = F[(size_t)j * SF_P * st].x; }
     double2 d = make_double2(0.0, 0.0);
     for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
 #pragma unroll
@@ -450,7 +449,7 @@ __device__ void mean_flow_component(double2* __restrict__ col, const double* __r
                 const double idn = bf[j];
                 if (k + SM_AHEAD < nz) {
                     br[j] = col[(k + SM_AHEAD) * st];
-                    bf[j] = F[(size_t)(k + SM_AHEAD) * SF_N * st];
+                    bf[j] = F[(size_t)(k + SM_AHEAD) * SF_P * st].x;
                 }
                 d = cscale(idn, csub(r, cscale(off, d)));
                 col[k * st] = d;
@@ -462,7 +461,7 @@ __device__ void mean_flow_component(double2* __restrict__ col, const double* __r
     const int nb = nz - 1;
 #pragma unroll
     for (int j = 0; j < SM_AHEAD; ++j)
-        if (j < nb) { br[j] = col[(nz - 2 - j) * st]; bf[j] = F[((size_t)(nz - 2 - j) * SF_N + 1) * st]; }
+        if (j < nb) { br[j] = col[(nz - 2 - j) * st]; bf[j] = F[(size_t)(nz - 2 - j) * SF_P * st].y; }
     for (int i0 = 0; i0 < nb; i0 += SM_AHEAD) {
 #pragma unroll
         for (int j = 0; j < SM_AHEAD; ++j) {
@@ -473,7 +472,7 @@ __device__ void mean_flow_component(double2* __restrict__ col, const double* __r
                 const double cb = bf[j];
                 if (i + SM_AHEAD < nb) {
                     br[j] = col[(k - SM_AHEAD) * st];
-                    bf[j] = F[((size_t)(k - SM_AHEAD) * SF_N + 1) * st];
+                    bf[j] = F[(size_t)(k - SM_AHEAD) * SF_P * st].y;
                 }
                 x = csub(dk, cscale(cb, x));
                 col[k * st] = x;
@@ -571,14 +570,14 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
     const double sc = norm / eta;  // scaled right-hand side
     if (t == 0 || t == nmode) {
         if (two_slip) mean_flow_two_slip(t == 0 ? su : sv, st, nz, sc, h * h);
-        else mean_flow_component(t == 0 ? su : sv, fac, st, nz, sc, off);
+        else mean_flow_component(t == 0 ? su : sv, reinterpret_cast<const double2*>(fac), st, nz, sc, off);
         return;
     }
     if (t == nmode + 1) {
         mean_pressure(sw, sp, st, nz, h * norm);
         return;
     }
-    const double* F = fac + t;
+    const double2* F = reinterpret_cast<const double2*>(fac) + t;
     double2 gx, gy;
     double k2;
     mode_symbols(t, nx, ny, ih, gx, gy, k2);
@@ -596,7 +595,11 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
                 by[j] = sv[o];
                 bz[j] = j == 0 ? make_double2(0.0, 0.0) : sw[o];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bf[j][q] = F[((size_t)j * SF_N + q) * st];
+                for (int q = 0; q < 4; ++q) {
+                    const double2 v = F[((size_t)j * SF_P + q) * st];
+                    bf[j][2 * q] = v.x;
+                    bf[j][2 * q + 1] = v.y;
+                }
             }
         }
         for (int k0 = 0; k0 < nz; k0 += SM_AHEAD) {
@@ -614,7 +617,11 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
                         by[j] = sv[o];
                         bz[j] = sw[o];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) bf[j][q] = F[((size_t)(k + SM_AHEAD) * SF_N + q) * st];
+                        for (int q = 0; q < 4; ++q) {
+                            const double2 v = F[((size_t)(k + SM_AHEAD) * SF_P + q) * st];
+                            bf[j][2 * q] = v.x;
+                            bf[j][2 * q + 1] = v.y;
+                        }
                     }
                     const double2 fa = cscale(ik, cadd(cm(cconj(gx), fxk), cm(cconj(gy), fyk)));
                     const double2 fb = cscale(ik, csub(cm(gx, fyk), cm(gy, fxk)));
@@ -653,9 +660,13 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
             const int k = nz - 2 - j;
             const size_t o = (size_t)k * st + t;
             ba[j] = su[o]; bw[j] = sw[o]; bp[j] = sp[o]; bb[j] = sv[o];
-            bc[j][0] = F[((size_t)k * SF_N + 1) * st];
+            bc[j][0] = F[(size_t)k * SF_P * st].y;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) bc[j][1 + q] = F[((size_t)k * SF_N + 8 + q) * st];
+            for (int q = 0; q < 3; ++q) {
+                const double2 v = F[((size_t)k * SF_P + 4 + q) * st];
+                bc[j][1 + 2 * q] = v.x;
+                bc[j][2 + 2 * q] = v.y;
+            }
         }
     }
     for (int i0 = 0; i0 < nb; i0 += SM_AHEAD) {
@@ -672,9 +683,13 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
                     const int kn = k - SM_AHEAD;
                     const size_t o = (size_t)kn * st + t;
                     ba[j] = su[o]; bw[j] = sw[o]; bp[j] = sp[o]; bb[j] = sv[o];
-                    bc[j][0] = F[((size_t)kn * SF_N + 1) * st];
+                    bc[j][0] = F[(size_t)kn * SF_P * st].y;
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) bc[j][1 + q] = F[((size_t)kn * SF_N + 8 + q) * st];
+                    for (int q = 0; q < 3; ++q) {
+                        const double2 v = F[((size_t)kn * SF_P + 4 + q) * st];
+                        bc[j][1 + 2 * q] = v.x;
+                        bc[j][2 + 2 * q] = v.y;
+                    }
                 }
                 const double2 ta = csub(y0, cadd(cscale(c[1], xa), cscale(c[2], xw)));
                 const double2 tw = csub(y1, cadd(cscale(c[3], xa), cscale(c[4], xw)));
