@@ -710,6 +710,401 @@ stokes_mode_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* 
     sw[(size_t)nz * st + t] = make_double2(0.0, 0.0);
 }
 
+// ---- per-mode solve in segments ----------------------------------------------------
+// The same sweeps with SEG_S levels per lane and L = 2^lgL lanes per mode (L SEG_S >= nz,
+// L <= 64), so that a mode's levels are worked on in parallel (SEG_S = 4: nz <= 256).  Every sweep is a
+// first-order affine recurrence y_k = M_k y_{k-1} + g_k: each lane composes the maps of
+// its levels, a Hillis-Steele scan over the lanes (shuffles) composes the prefixes, and
+// each lane reruns its levels from the state its predecessors hand it.
+
+__device__ __forceinline__ double2 shfl_up2(double2 v, int d, int w) {
+    return make_double2(__shfl_up(v.x, d, w), __shfl_up(v.y, d, w));
+}
+__device__ __forceinline__ double2 shfl_down2(double2 v, int d, int w) {
+    return make_double2(__shfl_down(v.x, d, w), __shfl_down(v.y, d, w));
+}
+__device__ __forceinline__ double2 shfl_xor2(double2 v, int m, int w) {
+    return make_double2(__shfl_xor(v.x, m, w), __shfl_xor(v.y, m, w));
+}
+
+// Scalar affine maps y -> a y + b composed over the lanes of a group: on return (a, b)
+// is the composition of the maps of lanes 0..lane (forward) or lane..L-1 (backward,
+// applied from the top lane down).
+template <bool FWD>
+__device__ __forceinline__ void scan_affine1(double& a, double2& b, int lane, int L) {
+    for (int d = 1; d < L; d <<= 1) {
+        const double ap = FWD ? __shfl_up(a, d, L) : __shfl_down(a, d, L);
+        const double2 bp = FWD ? shfl_up2(b, d, L) : shfl_down2(b, d, L);
+        if (FWD ? lane >= d : lane + d < L) {
+            b = cadd(cscale(a, bp), b);
+            a = a * ap;
+        }
+    }
+}
+
+// The state handed to this lane: the composed map of the lanes before it applied to 0.
+template <bool FWD>
+__device__ __forceinline__ double2 handed1(double2 b, int lane, int L) {
+    const double2 r = FWD ? shfl_up2(b, 1, L) : shfl_down2(b, 1, L);
+    return (FWD ? lane >= 1 : lane + 1 < L) ? r : make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ double2 group_sum(double2 v, int L) {
+    for (int m = 1; m < L; m <<= 1) v = cadd(v, shfl_xor2(v, m, L));
+    return v;
+}
+
+// 3-vector affine maps Y -> T Y + V (T real 3x3, V complex 3), composed as above.
+template <bool FWD>
+__device__ __forceinline__ void scan_affine3(double T[9], double2 V[3], int lane, int L) {
+    for (int d = 1; d < L; d <<= 1) {
+        double Tp[9];
+        double2 Vp[3];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Tp[q] = FWD ? __shfl_up(T[q], d, L) : __shfl_down(T[q], d, L);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Vp[r] = FWD ? shfl_up2(V[r], d, L) : shfl_down2(V[r], d, L);
+        if (FWD ? lane >= d : lane + d < L) {
+            double2 Vn[3];
+            double Tn[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                Vn[r] = cadd(V[r], cadd(cadd(cscale(T[3 * r], Vp[0]), cscale(T[3 * r + 1], Vp[1])),
+                                        cscale(T[3 * r + 2], Vp[2])));
+#pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2)
+                    Tn[3 * r + c2] = T[3 * r] * Tp[c2] + T[3 * r + 1] * Tp[3 + c2] + T[3 * r + 2] * Tp[6 + c2];
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) T[q] = Tn[q];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) V[r] = Vn[r];
+        }
+    }
+}
+
+// Mean flow of one tangential component (t = 0) in segments: the tridiagonal sweeps of
+// mean_flow_component, or between two slip walls the zero-mean double prefix sum of
+// mean_flow_two_slip.
+template <int SEG_S>
+__device__ void mean_flow_seg(double2* __restrict__ col, const double2* __restrict__ F, size_t st,
+                              int nz, double sc, double off, double h2, int two_slip, int lane,
+                              int L) {
+    double2 g[SEG_S];
+    const int k0 = lane * SEG_S;
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j)
+        g[j] = (k0 + j < nz) ? cscale(sc, col[(k0 + j) * st]) : make_double2(0.0, 0.0);
+    if (two_slip) {
+        double2 loc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < SEG_S; ++j) loc = cadd(loc, g[j]);
+        const double2 gmean = cscale(1.0 / nz, group_sum(loc, L));
+        // G_k = sum_{j<=k} (g_j - mean); u_k = -h^2 sum_{j<k} G_j; then zero mean
+        double2 G[SEG_S];
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < SEG_S; ++j) {
+            if (k0 + j < nz) acc = cadd(acc, csub(g[j], gmean));
+            G[j] = acc;
+        }
+        double one = 1.0;
+        double2 tot = acc;
+        scan_affine1<true>(one, tot, lane, L);
+        const double2 Gin = handed1<true>(tot, lane, L);
+        double2 u[SEG_S];
+        double2 uacc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < SEG_S; ++j) {
+            u[j] = uacc;  // exclusive within the lane
+            if (k0 + j < nz) uacc = cadd(uacc, cadd(G[j], Gin));
+        }
+        double one2 = 1.0;
+        double2 utot = uacc;
+        scan_affine1<true>(one2, utot, lane, L);
+        const double2 uin = handed1<true>(utot, lane, L);
+        double2 usum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < SEG_S; ++j) {
+            u[j] = cscale(-h2, cadd(u[j], uin));
+            if (k0 + j < nz) usum = cadd(usum, u[j]);
+        }
+        const double2 umean = cscale(1.0 / nz, group_sum(usum, L));
+#pragma unroll
+        for (int j = 0; j < SEG_S; ++j)
+            if (k0 + j < nz) col[(k0 + j) * st] = csub(u[j], umean);
+        return;
+    }
+    // forward: y_k = f0 (g_k - off y_{k-1});  backward: x_k = y_k - c'_k x_{k+1}
+    double al[SEG_S], cb[SEG_S];
+    double a = 1.0;
+    double2 b = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            const double2 f = F[(size_t)k * SF_P * st];
+            al[j] = -off * f.x;
+            g[j] = cscale(f.x, g[j]);
+            cb[j] = f.y;
+            a = al[j] * a;
+            b = cadd(cscale(al[j], b), g[j]);
+        } else {
+            al[j] = 1.0;
+            cb[j] = 0.0;
+        }
+    }
+    scan_affine1<true>(a, b, lane, L);
+    double2 y = handed1<true>(b, lane, L);
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        if (k0 + j < nz) {
+            y = cadd(cscale(al[j], y), g[j]);
+            g[j] = y;
+        }
+    }
+    // backward over the lane's levels from the top; x_{nz-1} = y_{nz-1}
+    a = 1.0;
+    b = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = SEG_S - 1; j >= 0; --j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            const double m = (k == nz - 1) ? 0.0 : -cb[j];
+            cb[j] = m;
+            a = m * a;
+            b = cadd(cscale(m, b), g[j]);
+        }
+    }
+    scan_affine1<false>(a, b, lane, L);
+    double2 x = handed1<false>(b, lane, L);
+#pragma unroll
+    for (int j = SEG_S - 1; j >= 0; --j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            x = cadd(cscale(cb[j], x), g[j]);
+            col[k * st] = x;
+        }
+    }
+}
+
+// Mean pressure in segments (mean_pressure): inclusive prefix sum of h n sw_k (k >= 1),
+// zero mean; w = 0.
+template <int SEG_S>
+__device__ void mean_pressure_seg(double2* __restrict__ sw, double2* __restrict__ sp, size_t st,
+                                  int nz, double hn, int lane, int L) {
+    const int k0 = lane * SEG_S;
+    double2 pk[SEG_S];
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        const int k = k0 + j;
+        if (k >= 1 && k < nz) acc = cadd(acc, cscale(hn, sw[k * st]));
+        pk[j] = acc;
+    }
+    double one = 1.0;
+    double2 tot = acc;
+    scan_affine1<true>(one, tot, lane, L);
+    const double2 pin = handed1<true>(tot, lane, L);
+    double2 psum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        pk[j] = cadd(pk[j], pin);
+        if (k0 + j < nz) psum = cadd(psum, pk[j]);
+    }
+    const double2 mean = cscale(1.0 / nz, group_sum(psum, L));
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j)
+        if (k0 + j < nz) sp[(k0 + j) * st] = csub(pk[j], mean);
+    for (int k = lane; k <= nz; k += L) sw[k * st] = make_double2(0.0, 0.0);
+}
+
+// Groups of L lanes: group t < nmode solves mode t (t = 0: the mean flow's u, v and
+// pressure one after the other).  Same inputs and outputs as stokes_mode_kernel.
+template <int SEG_S>
+__global__ void __launch_bounds__(256)
+stokes_mode_seg_kernel(double2* __restrict__ su, double2* __restrict__ sv, double2* __restrict__ sw,
+                       double2* __restrict__ sp, const double* __restrict__ fac, int nx, int ny,
+                       int nz, double h, double eta, double norm, int two_slip, int lgL) {
+    const int nmode = (nx / 2 + 1) * ny;
+    const int L = 1 << lgL;
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gt >> lgL, lane = gt & (L - 1);
+    if (t >= nmode) return;  // whole groups: L divides the block
+    const size_t st = (size_t)nmode;
+    const double ih = 1.0 / h, ih2 = ih * ih;
+    const double off = -ih2;
+    const double sc = norm / eta;
+    const double2* F0 = reinterpret_cast<const double2*>(fac) + t;
+    if (t == 0) {
+        mean_flow_seg<SEG_S>(su, F0, st, nz, sc, off, h * h, two_slip, lane, L);
+        mean_flow_seg<SEG_S>(sv, F0, st, nz, sc, off, h * h, two_slip, lane, L);
+        mean_pressure_seg<SEG_S>(sw, sp, st, nz, h * norm, lane, L);
+        return;
+    }
+    double2 gx, gy;
+    double k2;
+    mode_symbols(t, nx, ny, ih, gx, gy, k2);
+    const double ik = 1.0 / sqrt(k2);
+    const int k0 = lane * SEG_S;
+    // forward maps: Y_k = M_k Y_{k-1} + G_k with M_k = S^-1 [[-off,0,0],[0,-off,ih],[0,0,0]]
+    // applied through columns 0, 1 of S^-1; b: yb_k = al_k yb_{k-1} + gb_k
+    double si[SEG_S][6];
+    double2 G[SEG_S][3], gb[SEG_S];
+    double al[SEG_S];
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            const size_t o = (size_t)k * st + t;
+            const double2 fxk = cscale(sc, su[o]), fyk = cscale(sc, sv[o]);
+            const double2 fzk = k == 0 ? make_double2(0.0, 0.0) : cscale(sc, sw[o]);
+            const double2 f0 = F0[(size_t)k * SF_P * st];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double2 v = F0[((size_t)k * SF_P + 1 + r) * st];
+                si[j][2 * r] = v.x;
+                si[j][2 * r + 1] = v.y;
+            }
+            const double2 fa = cscale(ik, cadd(cm(cconj(gx), fxk), cm(cconj(gy), fyk)));
+            const double2 fb = cscale(ik, csub(cm(gx, fyk), cm(gy, fxk)));
+            al[j] = -off * f0.x;
+            gb[j] = cscale(f0.x, fb);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) G[j][r] = cadd(cscale(si[j][2 * r], fa), cscale(si[j][2 * r + 1], fzk));
+        } else {
+            al[j] = 1.0;
+            gb[j] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                G[j][r] = make_double2(0.0, 0.0);
+                si[j][2 * r] = si[j][2 * r + 1] = 0.0;
+            }
+        }
+    }
+    auto Mrow = [&](int j, int r, int c2) -> double {  // M_k entries (identity beyond nz)
+        if (k0 + j >= nz) return r == c2 ? 1.0 : 0.0;
+        return c2 == 0 ? -off * si[j][2 * r] : (c2 == 1 ? -off * si[j][2 * r + 1] : ih * si[j][2 * r + 1]);
+    };
+    double T[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double2 V[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    double ab = 1.0;
+    double2 bb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        double Tn[9];
+        double2 Vn[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double m0 = Mrow(j, r, 0), m1 = Mrow(j, r, 1), m2 = Mrow(j, r, 2);
+            Vn[r] = cadd(G[j][r], cadd(cadd(cscale(m0, V[0]), cscale(m1, V[1])), cscale(m2, V[2])));
+#pragma unroll
+            for (int c2 = 0; c2 < 3; ++c2) Tn[3 * r + c2] = m0 * T[c2] + m1 * T[3 + c2] + m2 * T[6 + c2];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) T[q] = Tn[q];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) V[r] = Vn[r];
+        bb = cadd(cscale(al[j], bb), gb[j]);
+        ab = al[j] * ab;
+    }
+    scan_affine3<true>(T, V, lane, L);
+    scan_affine1<true>(ab, bb, lane, L);
+    double2 y[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) y[r] = handed1<true>(V[r], lane, L);
+    double2 yb = handed1<true>(bb, lane, L);
+    // rerun: Y_k into G, yb_k into gb
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        if (k0 + j < nz) {
+            double2 yn[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                yn[r] = cadd(G[j][r], cadd(cadd(cscale(Mrow(j, r, 0), y[0]), cscale(Mrow(j, r, 1), y[1])),
+                                           cscale(Mrow(j, r, 2), y[2])));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                y[r] = yn[r];
+                G[j][r] = yn[r];
+            }
+            yb = cadd(cscale(al[j], yb), gb[j]);
+            gb[j] = yb;
+        }
+    }
+    // backward maps: X_k = N_k X_{k+1} + Y_k, N_k = -C'_k (columns 0, 1), N_{nz-1} = 0;
+    // xb_k = -c'_k xb_{k+1} + yb_k
+    double cn[SEG_S][6];
+    double cbm[SEG_S];
+#pragma unroll
+    for (int j = 0; j < SEG_S; ++j) {
+        const int k = k0 + j;
+        if (k < nz - 1) {
+            cbm[j] = -F0[(size_t)k * SF_P * st].y;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double2 v = F0[((size_t)k * SF_P + 4 + r) * st];
+                cn[j][2 * r] = -v.x;
+                cn[j][2 * r + 1] = -v.y;
+            }
+        } else {
+            cbm[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) cn[j][q] = 0.0;
+        }
+    }
+    double U[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double2 W[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    ab = 1.0;
+    bb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = SEG_S - 1; j >= 0; --j) {
+        if (k0 + j < nz) {
+            double Un[9];
+            double2 Wn[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double n0 = cn[j][2 * r], n1 = cn[j][2 * r + 1];
+                Wn[r] = cadd(G[j][r], cadd(cscale(n0, W[0]), cscale(n1, W[1])));
+#pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2) Un[3 * r + c2] = n0 * U[c2] + n1 * U[3 + c2];
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) U[q] = Un[q];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) W[r] = Wn[r];
+            bb = cadd(cscale(cbm[j], bb), gb[j]);
+            ab = cbm[j] * ab;
+        }
+    }
+    scan_affine3<false>(U, W, lane, L);
+    scan_affine1<false>(ab, bb, lane, L);
+    double2 x[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x[r] = handed1<false>(W[r], lane, L);
+    double2 xb = handed1<false>(bb, lane, L);
+#pragma unroll
+    for (int j = SEG_S - 1; j >= 0; --j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            double2 xn[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                xn[r] = cadd(G[j][r], cadd(cscale(cn[j][2 * r], x[0]), cscale(cn[j][2 * r + 1], x[1])));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) x[r] = xn[r];
+            xb = cadd(cscale(cbm[j], xb), gb[j]);
+            // u = a e + b e_perp = (a gx - b conj gy) / kappa, v = (a gy + b conj gx) / kappa
+            const size_t o = (size_t)k * st + t;
+            su[o] = cscale(ik, csub(cm(x[0], gx), cm(xb, cconj(gy))));
+            sv[o] = cscale(ik, cadd(cm(x[0], gy), cm(xb, cconj(gx))));
+            sw[o] = (k == 0) ? make_double2(0.0, 0.0) : x[1];
+            sp[o] = cscale(eta, x[2]);
+        }
+    }
+    if (lane == 0) sw[(size_t)nz * st + t] = make_double2(0.0, 0.0);
+}
+
 // ---- J^hy -------------------------------------------------------------------------
 // V = J^hy v with the wall ghosts: tangential components u_{-1-m} = s u_m (cell
 // heights; s = -1 no-slip, +1 slip), normal component w_{-k} = -w_k (faces), mirrored
@@ -925,8 +1320,18 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
     if (rc) return rc;
     const int nmode = g.nxh * ny;
     const double norm = 1.0 / ((double)nx * ny);
-    stokes_mode_kernel<<<(nmode + 2 + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hfac, nx, ny, nz,
-                                                       c->grid.h, p->eta, norm, key == 3 ? 1 : 0);
+    if (nz <= 256) {
+        // 4 levels per lane (2 per lane runs slower: the longer scans of 3x3 maps cost
+        // more than the occupancy gains); lanes per mode: the power of two covering nz
+        int lgL = 0;
+        while ((4 << lgL) < nz) ++lgL;
+        const int64_t threads = (int64_t)nmode << lgL;
+        stokes_mode_seg_kernel<4><<<(int)((threads + 255) / 256), 256, 0, s>>>(
+            su, sv, sw, sp, c->hfac, nx, ny, nz, c->grid.h, p->eta, norm, key == 3 ? 1 : 0, lgL);
+    } else {
+        stokes_mode_kernel<<<(nmode + 2 + 63) / 64, 64, 0, s>>>(su, sv, sw, sp, c->hfac, nx, ny, nz,
+                                                           c->grid.h, p->eta, norm, key == 3 ? 1 : 0);
+    }
     rc = fft_cols(c, su, nz, 1, s);
     if (!rc) rc = fft_cols(c, sv, nz, 1, s);
     if (!rc) rc = fft_cols(c, sw, nz + 1, 1, s);

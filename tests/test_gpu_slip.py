@@ -75,8 +75,10 @@ def test_spread_and_interp_with_slip(slip):
 
 
 @pytest.mark.parametrize("slip", WALLS)
-@pytest.mark.parametrize("shape", [(16, 16, 12), (32, 8, 7), (8, 16, 40)])
+@pytest.mark.parametrize("shape", [(16, 16, 12), (32, 8, 7), (8, 16, 40), (8, 8, 160), (8, 8, 300)])
 def test_stokes_deterministic_with_slip(slip, shape):
+    """Both mode-solve paths: segments of 4 levels per lane, 2 to 64 lanes per mode
+    (nz <= 256), and one thread per mode beyond."""
     nx, ny, nz = shape
     log(f"slip stokes {slip} {shape}")
     grid = es.Grid(nx, ny, nz, 0.8)
