@@ -347,11 +347,17 @@ const char* discos_batch_last_error(discos_batch* b);
  * inverse y-FFT, inverse x-FFT, interpolation, near-field neighbour lists, near-field
  * forces, S^hy, Stokes solve, the two J^hy passes with the predictor, update; the
  * hydrodynamic stages read 0 in dry steps) and sets *count (0 when no step was
- * recorded).
+ * recorded).  Each recorded event costs the stream a few microseconds.
  */
 #define DISCOS_NSTAGE 14
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
+
+/* As discos_profile(ctx, 1), but only the stages whose bit (1 << k, k in the order
+ * above) is set in `stages` are timed: their two bounding events are the only ones
+ * recorded (each recorded event costs the stream a few microseconds).  The other
+ * stages read 0.  stages = 0 stops recording. */
+int discos_profile_stages(discos_ctx* ctx, uint32_t stages);
 
 /* Synchronise the context's last stream and return (and clear) the sticky status:
  * DISCOS_E_NONFINITE, DISCOS_E_ARG (a species index outside [0, nspecies)),

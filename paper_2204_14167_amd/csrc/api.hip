@@ -310,6 +310,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->last_stream = nullptr;
     c->err = "";
     c->profile = 0;
+    c->prof_stages = 0;
+    c->prof_marks = 0;
     c->prof_steps = 0;
     c->ev = nullptr;
     *out = c;
@@ -619,7 +621,13 @@ int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, con
 }
 
 int discos_profile(discos_ctx* c, int enable) {
+    return discos_profile_stages(c, enable ? (1u << DISCOS_NSTAGE) - 1u : 0u);
+}
+
+int discos_profile_stages(discos_ctx* c, uint32_t stages) {
     if (!c) return DISCOS_E_ARG;
+    stages &= (1u << DISCOS_NSTAGE) - 1u;
+    const int enable = stages != 0;
     if (enable && !c->ev) {
         const size_t ne = (size_t)PROF_MAX * (DISCOS_NSTAGE + 1);
         c->ev = new (std::nothrow) hipEvent_t[ne];
@@ -628,6 +636,8 @@ int discos_profile(discos_ctx* c, int enable) {
             if (hipEventCreate(&c->ev[k]) != hipSuccess) return fail(c, DISCOS_E_HIP, "event create");
     }
     c->profile = enable ? 1 : 0;
+    c->prof_stages = stages;
+    c->prof_marks = stages | (stages << 1);
     c->prof_steps = 0;
     return DISCOS_OK;
 }
@@ -640,10 +650,13 @@ int discos_profile_read(discos_ctx* c, double* ms, int* count) {
     for (int k = 0; k < DISCOS_NSTAGE; ++k) ms[k] = 0.0;
     if (ns == 0) return DISCOS_OK;
     const int row = DISCOS_NSTAGE + 1;
-    if (hipEventSynchronize(c->ev[(size_t)(ns - 1) * row + DISCOS_NSTAGE]) != hipSuccess)
+    // the last step's highest recorded event
+    const int kmax = 31 - __builtin_clz(c->prof_marks);
+    if (hipEventSynchronize(c->ev[(size_t)(ns - 1) * row + kmax]) != hipSuccess)
         return fail(c, DISCOS_E_HIP, "event sync");
     for (int st = 0; st < ns; ++st)
         for (int k = 0; k < DISCOS_NSTAGE; ++k) {
+            if (!((c->prof_stages >> k) & 1u)) continue;
             float t = 0.0f;
             if (hipEventElapsedTime(&t, c->ev[(size_t)st * row + k], c->ev[(size_t)st * row + k + 1]) !=
                 hipSuccess)

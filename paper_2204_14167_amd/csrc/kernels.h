@@ -62,6 +62,8 @@ struct Ctx {
     // stage timing (discos_profile): one row of DISCOS_NSTAGE + 1 events per step,
     // for up to PROF_MAX steps
     int profile;
+    uint32_t prof_stages;  // stages timed (bit k: stage k)
+    uint32_t prof_marks;   // events recorded: both bounds of every timed stage
     int prof_steps;
     hipEvent_t* ev;
 };
@@ -131,7 +133,7 @@ struct Batch {
 
 // Record the event that closes stage k of the current profiled step.
 inline void stage_mark(Ctx* c, int k, hipStream_t s) {
-    if (c->profile && c->prof_steps < PROF_MAX)
+    if (c->profile && c->prof_steps < PROF_MAX && ((c->prof_marks >> k) & 1u))
         hipEventRecord(c->ev[(size_t)c->prof_steps * (DISCOS_NSTAGE + 1) + k], s);
 }
 

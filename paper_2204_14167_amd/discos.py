@@ -100,6 +100,7 @@ def lib():
                                                      ctypes.POINTER(DiscosParams), vp, vp]
         L.discos_check.argtypes = [vp]
         L.discos_profile.argtypes = [vp, i32]
+        L.discos_profile_stages.argtypes = [vp, ctypes.c_uint32]
         L.discos_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int)]
         L.discos_energy_flux.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp, vp]
@@ -122,7 +123,7 @@ def lib():
                      "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
                      "discos_batch_step", "discos_batch_tune", "discos_batch_check",
                      "discos_set_hydro_kernel", "discos_spread_force_species",
-                     "discos_interpolate_vel_species"):
+                     "discos_interpolate_vel_species", "discos_profile_stages"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -348,6 +349,13 @@ class Context:
 
     def profile(self, enable=True):
         self._rc(lib().discos_profile(self.handle, int(enable)))
+
+    def profile_stages(self, names):
+        """Time only the named stages (their two bounding events per step); [] stops."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << self.STAGES.index(nm)
+        self._rc(lib().discos_profile_stages(self.handle, mask))
 
     def profile_read(self):
         """{stage: ms}, the mean over the steps profiled since profiling was enabled
