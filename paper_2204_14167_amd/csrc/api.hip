@@ -257,7 +257,9 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
             return DISCOS_E_HIP;
         }
     }
-    if (hipMemset(c->flags, 0, 64 * sizeof(int)) != hipSuccess) {
+    // flags, and the bin counts (the scan that reads them clears them again)
+    if (hipMemset(c->flags, 0, 64 * sizeof(int)) != hipSuccess ||
+        hipMemset(c->bin_count, 0, c->nbins * sizeof(int)) != hipSuccess) {
         hipFree(c->pool);
         delete c;
         return DISCOS_E_HIP;

@@ -347,6 +347,8 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
                                  hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && discos::batch_pivots(b, 0) == DISCOS_OK && hipStreamSynchronize(0) == hipSuccess;
     ok = ok && hipMemset(b->flags, 0, 64 * sizeof(int)) == hipSuccess;
+    // bin counts start at zero; the scan that reads them clears them again
+    ok = ok && hipMemset(b->bin_count, 0, b->nbins_tot * sizeof(int)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;

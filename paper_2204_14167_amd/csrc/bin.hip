@@ -108,7 +108,9 @@ __global__ void scan_blocks_kernel(int* __restrict__ block_sum, int nblk) {
     }
 }
 
-__global__ void scan_final_kernel(const int* __restrict__ count, int64_t nb,
+// Also clears the counts it has read, so that the next binning starts from zero
+// without a fill (contexts and batches clear them once at creation).
+__global__ void scan_final_kernel(int* __restrict__ count, int64_t nb,
                                   const int* __restrict__ block_off, int* __restrict__ start,
                                   int n_total) {
     __shared__ int sh[SCAN_BLOCK];
@@ -118,6 +120,7 @@ __global__ void scan_final_kernel(const int* __restrict__ count, int64_t nb,
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
         v[k] = (i < nb) ? count[i] : 0;
+        if (i < nb) count[i] = 0;
         s += v[k];
     }
     int total;
@@ -193,7 +196,6 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
     const GridDev& g = c->gd;
     const int64_t nb = c->nbins;
     const int T = 256;
-    fill_i32_kernel<<<(int)std::min<int64_t>((nb + T - 1) / T, 4096), T, 0, s>>>(c->bin_count, nb, 0);
     if (n > 0)
         bin_count_kernel<<<(n + T - 1) / T, T, 0, s>>>(g, n, x, y, z, c->bin_count, c->ion_bin,
                                                        c->ion_rank, c->flags);
@@ -214,7 +216,6 @@ int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id,
     const int64_t nb = b->nbins_tot;
     const int n = (int)b->n_tot;
     const int T = b->cfg.ion_block;
-    fill_i32_kernel<<<(int)std::min<int64_t>((nb + 255) / 256, 4096), 256, 0, s>>>(b->bin_count, nb, 0);
     bin_count_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, pos, pos + n,
                                                          pos + 2 * (int64_t)n, b->bin_count,
                                                          b->ion_bin, b->ion_rank, b->flags);

@@ -468,12 +468,22 @@ __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, cons
         if (u < len) spec[(size_t)(k0 + u) * nmode + t] = d[u];
 }
 
-// Wavefront w of block b solves modes 16 (4 b + w) .. + 15.
+__device__ __forceinline__ void zsolve_mode0_wave(double2* __restrict__ spec, int nmode, int nz,
+                                                  double scale, int singular, int* __restrict__ flags);
+
+// Wavefront w of block b solves modes 16 (4 b + w) .. + 15.  With singular != 0 mode 0
+// is skipped there and solved by the first wavefront of one extra last block.
 template <int L>
 __global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ spec,
                                                         const double* __restrict__ zg, int nmode,
-                                                        int nz, double scale, int skip0) {
-    zsolve_seg_wave<L>(spec, zg, nmode, nz, scale, skip0, (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16);
+                                                        int nz, double scale, int singular,
+                                                        int* __restrict__ flags) {
+    if (singular && blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x < 64) zsolve_mode0_wave(spec, nmode, nz, scale, singular, flags);
+        return;
+    }
+    zsolve_seg_wave<L>(spec, zg, nmode, nz, scale, singular != 0,
+                       (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16);
 }
 
 // Batched: task (channel, first mode) per wavefront, for channels whose nz fits L
@@ -567,12 +577,6 @@ __device__ __forceinline__ void zsolve_mode0_wave(double2* __restrict__ spec, in
     }
 }
 
-__global__ void __launch_bounds__(64) zsolve_mode0_kernel(double2* __restrict__ spec, int nmode, int nz,
-                                                         double scale, int singular,
-                                                         int* __restrict__ flags) {
-    zsolve_mode0_wave(spec, nmode, nz, scale, singular, flags);
-}
-
 // Batched: block r solves the kappa = 0 mode of channel r when its walls are both
 // Neumann and its z-solve uses pivots (nz <= 128).
 __global__ void __launch_bounds__(64) zsolve_mode0_batch_kernel(const RepDev* __restrict__ reps,
@@ -650,14 +654,14 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
             c->zg_key = key;
         }
         const int L = (nz + 3) / 4;
-        const int nb = (nmode + 63) / 64;
+        // one extra block carries the singular kappa = 0 mode
+        const int nb = (nmode + 63) / 64 + (singular ? 1 : 0);
         if (L <= 8)
-            zsolve_seg_kernel<8><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
+            zsolve_seg_kernel<8><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
         else if (L <= 16)
-            zsolve_seg_kernel<16><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
+            zsolve_seg_kernel<16><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
         else
-            zsolve_seg_kernel<32><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular != 0);
-        if (singular) zsolve_mode0_kernel<<<1, 64, 0, s>>>(c->spec, nmode, nz, scale, singular, c->flags);
+            zsolve_seg_kernel<32><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
     } else {
         c->zg_key = -1;
         zsolve_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->spec, c->cprime, nx, ny, nz, scale, s_lo, s_hi,
