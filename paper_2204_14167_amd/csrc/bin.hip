@@ -58,7 +58,8 @@ __global__ void bin_count_batch_kernel(const RepDev* __restrict__ reps, const in
     bin_count_one(R.g, R.bin_off, i, x, y, z, count, ion_bin, ion_rank, flags);
 }
 
-// Exclusive scan of `count` (nb entries) into `start` (nb + 1 entries); three phases.
+// Exclusive scan of `count` (nb entries) into `start` (nb + 1 entries) in two launches:
+// per-block sums, then each block adds the sums of the blocks before it and scans.
 #define SCAN_BLOCK 256
 #define SCAN_ITEMS 4
 #define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
@@ -93,28 +94,18 @@ __global__ void scan_reduce_kernel(const int* __restrict__ count, int64_t nb,
     if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block sums, in chunks with a running carry.
-__global__ void scan_blocks_kernel(int* __restrict__ block_sum, int nblk) {
-    __shared__ int sh[SCAN_BLOCK];
-    int carry = 0;
-    for (int c0 = 0; c0 < nblk; c0 += SCAN_BLOCK) {
-        const int i = c0 + threadIdx.x;
-        const int v = (i < nblk) ? block_sum[i] : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, sh, total);
-        if (i < nblk) block_sum[i] = ex + carry;
-        carry += total;
-        __syncthreads();
-    }
-}
-
 // Also clears the counts it has read, so that the next binning starts from zero
 // without a fill (contexts and batches clear them once at creation).
 __global__ void scan_final_kernel(int* __restrict__ count, int64_t nb,
-                                  const int* __restrict__ block_off, int* __restrict__ start,
+                                  const int* __restrict__ block_sum, int* __restrict__ start,
                                   int n_total) {
     __shared__ int sh[SCAN_BLOCK];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    // this block's offset: the sums of the blocks before it
+    int part = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += SCAN_BLOCK) part += block_sum[j];
+    int block_off;
+    block_exclusive_scan(part, sh, block_off);
     int v[SCAN_ITEMS];
     int s = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -124,7 +115,7 @@ __global__ void scan_final_kernel(int* __restrict__ count, int64_t nb,
         s += v[k];
     }
     int total;
-    int ex = block_exclusive_scan(s, sh, total) + block_off[blockIdx.x];
+    int ex = block_exclusive_scan(s, sh, total) + block_off;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + k;
         if (i < nb) start[i] = ex;
@@ -201,7 +192,6 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
                                                        c->ion_rank, c->flags);
     const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
     scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp);
-    scan_blocks_kernel<<<1, SCAN_BLOCK, 0, s>>>(c->scan_tmp, nblk);
     scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp, c->bin_start, n);
     if (n > 0)
         bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
@@ -221,7 +211,6 @@ int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id,
                                                          b->ion_bin, b->ion_rank, b->flags);
     const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
     scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp);
-    scan_blocks_kernel<<<1, SCAN_BLOCK, 0, s>>>(b->scan_tmp, nblk);
     scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp, b->bin_start, n);
     bin_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, b->ion_bin,
                                                            b->ion_rank, b->bin_start, pos, pos + n,
