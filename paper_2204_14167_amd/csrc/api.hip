@@ -552,8 +552,11 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc) rc = discos::solve_poisson(c, c->rho, p, c->phi, s, 3);
     if (!rc) rc = discos::interp_es_sorted(c, DISCOS_INTERP_FORCE, ni, c->phi, p, c->fp, c->n_max, 0, s);
     discos::stage_mark(c, 8, s);
-    // complete the forces in place: fp (grid + applied field) += near field + wall (+ LJ)
-    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9);
+    // complete the forces in place: fp (grid + applied field) += near field + wall (+ LJ);
+    // in a dry step the same pass applies the update from the complete forces
+    discos::DryStepOut dry_out{step, pos, ions->q, ions->id, ions->species};
+    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9,
+                                                      wet ? nullptr : &dry_out);
     else discos::stage_mark(c, 9, s);
     discos::stage_mark(c, 10, s);
     const double* vwet = nullptr;
@@ -578,7 +581,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
         discos::stage_mark(c, 12, s);
         discos::stage_mark(c, 13, s);
     }
-    if (!rc) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
+    if (!rc && wet) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
     discos::stage_mark(c, 14, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;

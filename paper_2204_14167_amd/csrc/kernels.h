@@ -159,11 +159,22 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
 int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_params* p,
                      double* out, int64_t out_stride, int scatter, hipStream_t s);
 
+// Caller arrays of a dry step whose update the force pass performs itself.
+struct DryStepOut {
+    uint64_t step;
+    double* pos;
+    double* q;
+    int* id;
+    int* sp;
+};
+
 // Near-field + wall (+ LJ) forces over the cell list; out[perm] += F if scatter, else
 // out[sorted] += F.  mark >= 0: profiling stage mark between the list build and the
-// force pass.
+// force pass.  upd: a dry step's update from the complete forces out[sorted] + F is
+// done in the same pass (out is not written).
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
-                      int scatter_to_caller, hipStream_t s, int mark = -1);
+                      int scatter_to_caller, hipStream_t s, int mark = -1,
+                      const DryStepOut* upd = nullptr);
 
 // Random finite difference of the thermal forcing (scale = kT / delta, half = delta / 2;
 // scale 0: off); sid holds the ions' stable ids in cell-list order.

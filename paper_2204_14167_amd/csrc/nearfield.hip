@@ -390,79 +390,6 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
     Fz = fz;
 }
 
-__global__ void __launch_bounds__(256)
-near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
-                 const int* __restrict__ ssp, const int* __restrict__ bin_start,
-                 const int* __restrict__ list, const int* __restrict__ count,
-                 const int* __restrict__ perm, double* __restrict__ out, int64_t stride,
-                 int scatter, int* __restrict__ flags) {
-    __shared__ double tab[NL_TAB];
-    const int nt = min(P.tablen, NL_TAB);
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
-    __syncthreads();
-    P.tab = tab;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 me = sxyzq[i];
-    if (!pos_ok(g, me.x, me.y, me.z)) return;
-    int spi = 0;
-    if (P.lj_on) {
-        spi = ssp[i];
-        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
-    }
-    double Fx, Fy, Fz;
-    list_force(i, n, me, spi, sxyzq, ssp, bin_start, list, count[i], g, P, Fx, Fy, Fz);
-    const int o = scatter ? perm[i] : i;
-    out[o] += Fx;
-    out[o + stride] += Fy;
-    out[o + 2 * stride] += Fz;
-}
-
-__global__ void __launch_bounds__(256)
-near_eval_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep, NearDev P,
-                       int n, const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
-                       const int* __restrict__ bin_start, const int* __restrict__ list,
-                       const int* __restrict__ count, double* __restrict__ out,
-                       int* __restrict__ flags) {
-    __shared__ double tab[NL_TAB];
-    const int nt = min(P.tablen, NL_TAB);
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
-    __syncthreads();
-    P.tab = tab;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const RepDev& R = reps[ion_rep[i]];
-    const GridDev g = R.g;
-    P.s_lo = R.s_lo;
-    P.s_hi = R.s_hi;
-    const double4 me = sxyzq[i];
-    if (!pos_ok(g, me.x, me.y, me.z)) return;
-    int spi = 0;
-    if (P.lj_on) {
-        spi = ssp[i];
-        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
-    }
-    double Fx, Fy, Fz;
-    list_force(i, n, me, spi, sxyzq, ssp, bin_start + R.bin_off, list, count[i], g, P, Fx, Fy, Fz);
-    out[i] += Fx;
-    out[i + n] += Fy;
-    out[i + 2 * (int64_t)n] += Fz;
-}
-
-int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
-                      int scatter_to_caller, hipStream_t s, int mark) {
-    if (n <= 0) return DISCOS_OK;
-    const NearDev P = near_of(c, p);
-    const int T = 256;
-    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->sxyzf, c->bin_start,
-                                                   c->nlist, c->ncount);
-    if (mark >= 0) stage_mark(c, mark, s);
-    near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
-                                                   c->nlist, c->ncount, c->perm, out, out_stride,
-                                                   scatter_to_caller, c->flags);
-    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
-}
-
 // ---- dry update --------------------------------------------------------------
 
 struct DryDev {
@@ -533,6 +460,32 @@ __device__ __forceinline__ void dry_move(const GridDev& g, const DryDev& Dd, int
 // Update of every ion of the cell list from its complete force fp (grid, near field,
 // wall, applied field) and, in a wet step, its velocity vw = J(x*) v, written to the
 // caller's arrays in cell-list order.
+// The update of ion gi of the cell list with complete force (Fx, Fy, Fz).
+__device__ __forceinline__ void update_with_force(const GridDev& g, const DryDev& Dd, int gi,
+                                                  double4 me, int sp_in, int idi, double Fx,
+                                                  double Fy, double Fz, double wx0, double wy0,
+                                                  double wz0, double* __restrict__ pos,
+                                                  int64_t pstride, double* __restrict__ q,
+                                                  int* __restrict__ id, int* __restrict__ sp,
+                                                  int* __restrict__ flags) {
+    const bool sp_ok = sp_in >= 0 && sp_in < Dd.nsp;
+    if (!sp_ok) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+    const int spi = sp_ok ? sp_in : 0;
+    double nx = me.x, ny = me.y, nz = me.z;
+    if (pos_ok(g, me.x, me.y, me.z)) {
+        dry_move(g, Dd, spi, idi, me.x, me.y, me.z, Fx, Fy, Fz, wx0, wy0, wz0, nx, ny, nz, flags);
+    } else {
+        set_flag(flags, (isfinite(me.x) && isfinite(me.y) && isfinite(me.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                          : DISCOS_FLAG_NONFINITE);
+    }
+    pos[gi] = nx;
+    pos[gi + pstride] = ny;
+    pos[gi + 2 * pstride] = nz;
+    q[gi] = me.w;
+    id[gi] = idi;
+    sp[gi] = sp_in;
+}
+
 __device__ __forceinline__ void update_one(const GridDev& g, const DryDev& Dd, int gi,
                                            const double4* __restrict__ sxyzq,
                                            const int* __restrict__ sid, const int* __restrict__ ssp,
@@ -544,29 +497,137 @@ __device__ __forceinline__ void update_one(const GridDev& g, const DryDev& Dd, i
     const double4 me = sxyzq[gi];
     const int sp_in = ssp[gi];
     const int idi = sid[gi];
-    const bool sp_ok = sp_in >= 0 && sp_in < Dd.nsp;
-    if (!sp_ok) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
-    const int spi = sp_ok ? sp_in : 0;
-    double nx = me.x, ny = me.y, nz = me.z;
-    if (pos_ok(g, me.x, me.y, me.z)) {
-        double wx0 = 0.0, wy0 = 0.0, wz0 = 0.0;
-        if (vw) {
-            wx0 = Dd.dt * vw[gi];
-            wy0 = Dd.dt * vw[gi + fstride];
-            wz0 = Dd.dt * vw[gi + 2 * fstride];
-        }
-        dry_move(g, Dd, spi, idi, me.x, me.y, me.z, fp[gi], fp[gi + fstride], fp[gi + 2 * fstride],
-                 wx0, wy0, wz0, nx, ny, nz, flags);
-    } else {
-        set_flag(flags, (isfinite(me.x) && isfinite(me.y) && isfinite(me.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
-                                                                          : DISCOS_FLAG_NONFINITE);
+    double wx0 = 0.0, wy0 = 0.0, wz0 = 0.0;
+    if (vw) {
+        wx0 = Dd.dt * vw[gi];
+        wy0 = Dd.dt * vw[gi + fstride];
+        wz0 = Dd.dt * vw[gi + 2 * fstride];
     }
-    pos[gi] = nx;
-    pos[gi + pstride] = ny;
-    pos[gi + 2 * pstride] = nz;
-    q[gi] = me.w;
-    id[gi] = idi;
-    sp[gi] = sp_in;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if (pos_ok(g, me.x, me.y, me.z)) {
+        Fx = fp[gi];
+        Fy = fp[gi + fstride];
+        Fz = fp[gi + 2 * fstride];
+    }
+    update_with_force(g, Dd, gi, me, sp_in, idi, Fx, Fy, Fz, wx0, wy0, wz0, pos, pstride, q, id, sp,
+                      flags);
+}
+
+// Output of the force pass: out[o] += F (o = perm[i] if scatter), or with U.pos set, the
+// dry step's update of ion i from its complete force out[i] + F (nothing reads the
+// forces after a dry step), written to the caller's arrays in cell-list order.
+struct FusedUpdate {
+    DryDev Dd;
+    const int* sid;
+    double* pos;
+    double* q;
+    int* id;
+    int* sp;
+};
+
+__global__ void __launch_bounds__(256)
+near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
+                 const int* __restrict__ ssp, const int* __restrict__ bin_start,
+                 const int* __restrict__ list, const int* __restrict__ count,
+                 const int* __restrict__ perm, double* __restrict__ out, int64_t stride,
+                 int scatter, int* __restrict__ flags, FusedUpdate U) {
+    __shared__ double tab[NL_TAB];
+    const int nt = min(P.tablen, NL_TAB);
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
+    __syncthreads();
+    P.tab = tab;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 me = sxyzq[i];
+    if (!pos_ok(g, me.x, me.y, me.z)) {
+        if (U.pos)
+            update_with_force(g, U.Dd, i, me, ssp[i], U.sid[i], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, U.pos, n,
+                              U.q, U.id, U.sp, flags);
+        return;
+    }
+    int spi = 0;
+    if (P.lj_on) {
+        spi = ssp[i];
+        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+    }
+    double Fx, Fy, Fz;
+    list_force(i, n, me, spi, sxyzq, ssp, bin_start, list, count[i], g, P, Fx, Fy, Fz);
+    if (U.pos) {
+        update_with_force(g, U.Dd, i, me, ssp[i], U.sid[i], out[i] + Fx, out[i + stride] + Fy,
+                          out[i + 2 * stride] + Fz, 0.0, 0.0, 0.0, U.pos, n, U.q, U.id, U.sp, flags);
+        return;
+    }
+    const int o = scatter ? perm[i] : i;
+    out[o] += Fx;
+    out[o + stride] += Fy;
+    out[o + 2 * stride] += Fz;
+}
+
+__global__ void __launch_bounds__(256)
+near_eval_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep, NearDev P,
+                       int n, const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
+                       const int* __restrict__ bin_start, const int* __restrict__ list,
+                       const int* __restrict__ count, double* __restrict__ out,
+                       int* __restrict__ flags) {
+    __shared__ double tab[NL_TAB];
+    const int nt = min(P.tablen, NL_TAB);
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
+    __syncthreads();
+    P.tab = tab;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RepDev& R = reps[ion_rep[i]];
+    const GridDev g = R.g;
+    P.s_lo = R.s_lo;
+    P.s_hi = R.s_hi;
+    const double4 me = sxyzq[i];
+    if (!pos_ok(g, me.x, me.y, me.z)) return;
+    int spi = 0;
+    if (P.lj_on) {
+        spi = ssp[i];
+        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+    }
+    double Fx, Fy, Fz;
+    list_force(i, n, me, spi, sxyzq, ssp, bin_start + R.bin_off, list, count[i], g, P, Fx, Fy, Fz);
+    out[i] += Fx;
+    out[i + n] += Fy;
+    out[i + 2 * (int64_t)n] += Fz;
+}
+
+static DryDev dry_of(const discos_params* p, uint64_t step) {
+    DryDev Dd;
+    Dd.nsp = p->nspecies;
+    Dd.kT = p->kT;
+    Dd.eta = p->eta;
+    Dd.dt = p->dt;
+    Dd.radius = p->radius;
+    Dd.coef = p->mob_coef;
+    Dd.seed = p->seed;
+    Dd.step = step;
+    return Dd;
+}
+
+int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
+                      int scatter_to_caller, hipStream_t s, int mark, const DryStepOut* upd) {
+    if (n <= 0) return DISCOS_OK;
+    const NearDev P = near_of(c, p);
+    const int T = 256;
+    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->sxyzf, c->bin_start,
+                                                   c->nlist, c->ncount);
+    if (mark >= 0) stage_mark(c, mark, s);
+    FusedUpdate U{};
+    if (upd) {
+        U.Dd = dry_of(p, upd->step);
+        U.sid = c->sid;
+        U.pos = upd->pos;
+        U.q = upd->q;
+        U.id = upd->id;
+        U.sp = upd->sp;
+    }
+    near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
+                                                   c->nlist, c->ncount, c->perm, out, out_stride,
+                                                   scatter_to_caller, c->flags, U);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
@@ -645,15 +706,7 @@ int batch_set_step(Batch* b, uint64_t v, hipStream_t s) {
 int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
                   double* pos, double* q, int* id, int* sp, hipStream_t s) {
     if (n <= 0) return DISCOS_OK;
-    DryDev Dd;
-    Dd.nsp = p->nspecies;
-    Dd.kT = p->kT;
-    Dd.eta = p->eta;
-    Dd.dt = p->dt;
-    Dd.radius = p->radius;
-    Dd.coef = p->mob_coef;
-    Dd.seed = p->seed;
-    Dd.step = step;
+    const DryDev Dd = dry_of(p, step);
     dry_update_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, Dd, n, c->sxyzq, c->sid, c->ssp, c->fp,
                                                       c->n_max, vwet, pos, n, q, id, sp, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
