@@ -47,7 +47,7 @@ ALU_PEAK = {"near_list": FP32_PEAK_TFLOPS, "near_eval": FP64_PEAK_TFLOPS}
 STAGE_KERNEL = {"spread": "spread_charge_kernel", "fft_x": "fft_x_r2c_kernel",
                 "z_solve": "zsolve_kernel", "ifft_x": "fft_x_c2r_kernel",
                 "interp": "interp_es_kernel", "near_list": "near_list_kernel",
-                "near_eval": "near_eval_kernel", "update": "dry_update_kernel"}
+                "near_eval": "near_eval_kernel"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_dry_step_256x256x128_n1048576.md")
 
 # The resolved-hydrodynamics channel: wet midpoint step with the random finite
@@ -102,10 +102,11 @@ def stage_work(stage, N, C, H, pairs, tests):
     if stage == "near_list":
         return "alu", LIST_FLOPS_PER_TEST * tests
     if stage == "near_eval":
+        # the pair forces (the fused dry update is not counted)
         return "alu", NEAR_FLOPS_PER_PAIR * pairs
-    if stage == "update":
-        return "hbm", 104.0 * N
-    return None, None  # multi-kernel or hydrodynamic stages (zero in a dry step)
+    # "update": in a dry step the near-field force pass applies the update itself (the
+    # stage is empty); the hydrodynamic stages are empty too
+    return None, None
 
 
 def cpu_baseline(w, p, pos, q, ids, species, n_sample=262144):
@@ -476,7 +477,7 @@ def main():
     for k, v in stages.items():
         b, wk = stage_work(k, N, C, H, pairs, tests)
         if b is None:
-            continue  # hydrodynamic stages: empty in a dry step
+            continue  # empty in a dry step: the update (fused) and the hydrodynamic stages
         e = {"ms": round(v, 5)}
         if b is not None:
             e["bound"] = b

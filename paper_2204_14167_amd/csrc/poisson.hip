@@ -598,7 +598,7 @@ static int ilog2(int n) {
 int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t s) {
     const int nx = c->gd.nx;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 2048 / nx);
+    const int ppb = std::max(1, 1024 / nx);
     fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
         in, spec, nx, ilog2(nx), npairs, ppb, c->tw_x);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
@@ -607,7 +607,7 @@ int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t
 int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_t s) {
     const int nx = c->gd.nx;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 2048 / nx);
+    const int ppb = std::max(1, 1024 / nx);
     fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
         spec, out, nx, ilog2(nx), npairs, ppb, c->tw_x);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
@@ -615,7 +615,7 @@ int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_
 
 int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
     const int ny = c->gd.ny, nxh = c->gd.nxh;
-    const int mc = std::max(1, std::min(16, 2048 / ny));
+    const int mc = std::max(1, std::min(16, 1024 / ny));
     dim3 gy((nxh + mc - 1) / mc, nlev);
     fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * ny * sizeof(double2), s>>>(spec, nxh, ny, ilog2(ny), mc,
                                                                            c->tw_y, inv);
@@ -628,12 +628,12 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 2048 / nx);
+    const int ppb = std::max(1, 1024 / nx);
     const size_t ldsx = (size_t)ppb * nx * sizeof(double2);
     fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(rhs, c->spec, nx, ilog2(nx),
                                                                         npairs, ppb, c->tw_x);
     if (mark_base >= 0) stage_mark(c, mark_base, s);
-    const int mc = std::max(1, std::min(16, 2048 / ny));
+    const int mc = std::max(1, std::min(16, 1024 / ny));
     const size_t ldsy = (size_t)mc * ny * sizeof(double2);
     dim3 gy((nxh + mc - 1) / mc, nz);
     fft_y_kernel<<<gy, FFT_THREADS, ldsy, s>>>(c->spec, nxh, ny, ilog2(ny), mc, c->tw_y, 0);
