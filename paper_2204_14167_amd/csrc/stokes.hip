@@ -286,9 +286,10 @@ __global__ void stress_kernel(GridDev g, uint64_t seed, uint64_t step, double* _
     }
 }
 
-// f += amp div_h Z on the faces (wall faces of w untouched).
+// f_out = f_in + amp div_h Z on the faces (the wall faces of w carry f_in unchanged).
 __global__ void stress_div_kernel(GridDev g, double amp, const double* __restrict__ zd,
-                                  const double* __restrict__ ze, double* __restrict__ f) {
+                                  const double* __restrict__ ze, const double* __restrict__ fin,
+                                  double* __restrict__ f) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     const int64_t nlev = (int64_t)g.nx * g.ny * (g.nz + 1);
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -309,17 +310,19 @@ __global__ void stress_div_kernel(GridDev g, double amp, const double* __restric
         // x-face (i, j+1/2, k+1/2)
         const double fx = (Zxx[C(k, j, i)] - Zxx[C(k, j, im)]) + (Zxy[C(k, jp, i)] - Zxy[C(k, j, i)]) +
                           (Zxz[C(k + 1, j, i)] - Zxz[C(k, j, i)]);
-        f[C(k, j, i)] += amp * ih * fx;
+        f[C(k, j, i)] = fin[C(k, j, i)] + amp * ih * fx;
         // y-face (i+1/2, j, k+1/2)
         const double fy = (Zxy[C(k, j, ip)] - Zxy[C(k, j, i)]) + (Zyy[C(k, j, i)] - Zyy[C(k, jm, i)]) +
                           (Zyz[C(k + 1, j, i)] - Zyz[C(k, j, i)]);
-        f[ncell + C(k, j, i)] += amp * ih * fy;
+        f[ncell + C(k, j, i)] = fin[ncell + C(k, j, i)] + amp * ih * fy;
     }
     if (k >= 1 && k < g.nz) {
         // z-face (i+1/2, j+1/2, k)
         const double fz = (Zxz[C(k, j, ip)] - Zxz[C(k, j, i)]) + (Zyz[C(k, jp, i)] - Zyz[C(k, j, i)]) +
                           (Zzz[C(k, j, i)] - Zzz[C(k - 1, j, i)]);
-        f[2 * ncell + C(k, j, i)] += amp * ih * fz;
+        f[2 * ncell + C(k, j, i)] = fin[2 * ncell + C(k, j, i)] + amp * ih * fz;
+    } else {
+        f[2 * ncell + C(k, j, i)] = fin[2 * ncell + C(k, j, i)];
     }
 }
 
@@ -1299,11 +1302,10 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
     const double* frhs = f;
     if (noise) {
         // f + amp div Z, built in the velocity buffer (the solve reads it once)
-        hipMemcpyAsync(vel, f, (2 * ncell + nlev) * sizeof(double), hipMemcpyDeviceToDevice, s);
         const double amp = sqrt(2.0 * p->kT * p->eta / (c->grid.h * c->grid.h * c->grid.h * p->dt));
         const int T = 256;
         stress_kernel<<<(int)((nlev + T - 1) / T), T, 0, s>>>(g, p->seed, step, c->hz_diag, c->hz_edge);
-        stress_div_kernel<<<(int)((nlev + T - 1) / T), T, 0, s>>>(g, amp, c->hz_diag, c->hz_edge, vel);
+        stress_div_kernel<<<(int)((nlev + T - 1) / T), T, 0, s>>>(g, amp, c->hz_diag, c->hz_edge, f, vel);
         frhs = vel;
     }
     const size_t nsp = (size_t)g.nxh * ny;
