@@ -569,7 +569,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
             rd.seed = p->seed;
             rd.step = step;
         }
-        rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr, 1);
+        rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr, 1, ni);
         discos::stage_mark(c, 11, s);
         if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 12, s);

@@ -182,13 +182,15 @@ struct RfdDev {
     const int* sid;
     double scale, half;
     uint64_t seed, step;
+    const double* w;   // the ions' normals W, [3][wstride] in cell-list order (set by the spread)
+    int64_t wstride;
 };
 
 // S^hy of the sorted forces c->fp onto the three face arrays of out (+ the thermal
-// forcing when rfd is given).
+// forcing when rfd is given; n: the ions of the cell list, whose normals it draws).
 // species != 0: each ion's kernel from c->hy_tab by its species c->ssp.
 int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd = nullptr,
-                        int species = 0);
+                        int species = 0, int n = 0);
 // Factorisation of the Stokes mode systems of the context's grid (once, at creation).
 int stokes_factor(Ctx* c, hipStream_t s);
 // Stokes solve with no-slip walls (f: three face arrays; vel likewise; pres nullable).

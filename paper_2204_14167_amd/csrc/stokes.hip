@@ -205,10 +205,7 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
         };
         dep(a4.x, a4.y, a4.z, fw[i] * inv_h3);
         if (rfd.scale != 0.0) {
-            double w0, w1, w2, unused;
-            const uint32_t idi = (uint32_t)rfd.sid[i];
-            normal_pair(rfd.seed, rfd.step, DISCOS_TAG_RFD, 0u, idi, w0, w1);
-            normal_pair(rfd.seed, rfd.step, DISCOS_TAG_RFD, 1u, idi, w2, unused);
+            const double w0 = rfd.w[i], w1 = rfd.w[i + rfd.wstride], w2 = rfd.w[i + 2 * rfd.wstride];
             const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
             const double v = rfd.scale * wc * inv_h3;
             const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
@@ -224,6 +221,21 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
         if (COMP == 2 && (gk == 0 || gk == g.nz)) v = 0.0;
         out[((size_t)gk * g.ny + (y0 + ly)) * g.nx + (x0 + lx)] = v;
     }
+}
+
+// The random finite difference's normals W of every ion (keyed by its stable id),
+// drawn once for the three component spreads.
+__global__ void rfd_normals_kernel(int n, const int* __restrict__ sid, uint64_t seed, uint64_t step,
+                                   double* __restrict__ w, int64_t stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double w0, w1, w2, unused;
+    const uint32_t idi = (uint32_t)sid[i];
+    normal_pair(seed, step, DISCOS_TAG_RFD, 0u, idi, w0, w1);
+    normal_pair(seed, step, DISCOS_TAG_RFD, 1u, idi, w2, unused);
+    w[i] = w0;
+    w[i + stride] = w1;
+    w[i + 2 * stride] = w2;
 }
 
 template <int T, int KM>
@@ -243,9 +255,17 @@ static void spread_faces(Ctx* c, const RfdDev& rfd, const int* ssp, double* out,
                                                               out + 2 * ncell);
 }
 
-int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in, int species) {
+int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in, int species, int n) {
     RfdDev rfd{};
-    if (rfd_in) rfd = *rfd_in;
+    if (rfd_in) {
+        rfd = *rfd_in;
+        // the normals go to c->hvi, which the wet step fills only after the solve
+        if (n > 0)
+            rfd_normals_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, rfd.sid, rfd.seed, rfd.step, c->hvi,
+                                                              c->n_max);
+        rfd.w = c->hvi;
+        rfd.wstride = c->n_max;
+    }
     const int km = species ? c->hy_km : 0;
     if (km == 0) spread_faces<SH_TX, 0>(c, rfd, nullptr, out, s);
     else if (km <= 2) spread_faces<16, 2>(c, rfd, c->ssp, out, s);
