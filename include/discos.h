@@ -214,7 +214,8 @@ int discos_interpolate(discos_ctx* ctx, int op, int64_t n, const double* pos,
 int discos_set_hydro_kernel(discos_ctx* ctx, int32_t nspecies, const double* kernel);
 
 /* S^hy F (as DISCOS_SPREAD_FORCE) with each ion's kernel chosen by its species (DEVICE
- * [n], values in [0, nspecies of p]); out: the three face arrays back to back. */
+ * [n]; a species without a kernel set, negative ones included, uses the Peskin kernel);
+ * out: the three face arrays back to back. */
 int discos_spread_force_species(discos_ctx* ctx, int64_t n, const double* pos, const double* F,
                                 const int32_t* species, const discos_params* p, double* out,
                                 void* stream);

@@ -276,7 +276,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         hb += 2 * carve_bytes(2 * ncell + nlev, sizeof(double));            // hvel, hfor
         hb += carve_bytes(3 * nm, sizeof(double));                          // hvi
         hb += carve_bytes(nm, sizeof(double4));                             // hmid
-        hb += carve_bytes(4 * DISCOS_HY_MAXSP, sizeof(double));              // kernel table
+        hb += carve_bytes(4 * (DISCOS_HY_MAXSP + 1), sizeof(double));        // kernel table
         void* hp = nullptr;
         if (hipMalloc(&hp, hb) != hipSuccess) {
             hipFree(c->pool);
@@ -293,11 +293,11 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hfor = carve<double>(hc, 2 * ncell + nlev);
         c->hvi = carve<double>(hc, 3 * nm);
         c->hmid = carve<double4>(hc, nm);
-        c->hy_tab = carve<double>(hc, 4 * DISCOS_HY_MAXSP);
+        c->hy_tab = carve<double>(hc, 4 * (DISCOS_HY_MAXSP + 1));
         c->gd.tsg[0] = c->gd.tsg[1] = -1.0;  // no-slip until a call says otherwise
         // every species on the 4-point Peskin kernel (rows of zeros: w = 0); the Stokes
         // mode factorisation of this grid
-        if (hipMemset(c->hy_tab, 0, 4 * DISCOS_HY_MAXSP * sizeof(double)) != hipSuccess ||
+        if (hipMemset(c->hy_tab, 0, 4 * (DISCOS_HY_MAXSP + 1) * sizeof(double)) != hipSuccess ||
             discos::stokes_factor(c, nullptr) != DISCOS_OK || hipDeviceSynchronize() != hipSuccess) {
             hipFree(hp);
             hipFree(c->pool);
@@ -428,7 +428,7 @@ int discos_set_hydro_kernel(discos_ctx* c, int32_t nspecies, const double* kerne
     if (nspecies < 0 || nspecies > DISCOS_HY_MAXSP)
         return fail(c, DISCOS_E_ARG, "nspecies must lie in [0, DISCOS_HY_MAXSP]");
     if (!kernel) nspecies = 0;
-    double tab[4 * DISCOS_HY_MAXSP] = {};
+    double tab[4 * (DISCOS_HY_MAXSP + 1)] = {};  // the last row stays Peskin (w = 0)
     int km = 0;
     bool any_esc = false;
     for (int sp = 0; sp < nspecies; ++sp) {

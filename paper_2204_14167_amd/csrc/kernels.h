@@ -48,8 +48,9 @@ struct Ctx {
     double4* hmid;    // [n_max] midpoint positions (x, y, z, q) in cell-list order
     double* part;     // [2][PART_MAX] partial sums of the deterministic reductions
     double* bcg;      // [2][ny][nx] wall-field adjoints gathered from the ghost layers
-    // hydrodynamic kernel per species: [DISCOS_HY_MAXSP][4] rows (w, beta, 1 / alpha,
-    // 1 / integral), w = 0 for the 4-point Peskin kernel (every row past the set ones);
+    // hydrodynamic kernel per species: [DISCOS_HY_MAXSP + 1][4] rows (w, beta, 1 / alpha,
+    // 1 / integral), w = 0 for the 4-point Peskin kernel (every row past the set ones,
+    // and the extra last row that species out of range read);
     // hy_km: half-width of the node window of the widest set kernel (0: all Peskin)
     double* hy_tab;
     int hy_km;

@@ -68,9 +68,10 @@ __device__ __forceinline__ void deposit_face(const GridDev& g, double* acc, int 
 
 // ---- hydrodynamic kernels per species (App. B, eq eskernel) ----------------------
 // Row of the kernel table for species sp: (w, beta, 1 / alpha, 1 / integral); species
-// outside the table use the last row, which is the 4-point Peskin kernel (w = 0).
+// outside [0, DISCOS_HY_MAXSP) use the extra last row, always the 4-point Peskin kernel
+// (w = 0), as do the species past the ones set.
 __device__ __forceinline__ const double* hy_row(const double* __restrict__ tab, int sp) {
-    return tab + 4 * ((sp >= 0 && sp < DISCOS_HY_MAXSP) ? sp : DISCOS_HY_MAXSP - 1);
+    return tab + 4 * ((sp >= 0 && sp < DISCOS_HY_MAXSP) ? sp : DISCOS_HY_MAXSP);
 }
 
 // phi(zeta), zeta in cells: the 4-point Peskin kernel of eq peskin1d for w = 0, else

@@ -19,6 +19,9 @@ KERNELS = {
     "narrow": [(4, 8.0), (0, 0.0), (3, 5.0), (2, 1.0)],
     # the widest kernel, odd and even widths, beta = 0 (the box kernel), Peskin
     "wide": [(8, 12.0), (5, 4.0), (0, 0.0), (6, 0.0)],
+    # the ends of the accepted range: beta = 100 (a sharply peaked kernel, the host
+    # quadrature's hardest integrand), the narrowest width, a nearly flat kernel
+    "extreme": [(2, 100.0), (8, 100.0), (3, 0.5), (7, 60.0)],
 }
 
 
@@ -68,7 +71,7 @@ def _flat(*a):
 
 
 CASES = [("paper", (32, 32, 16, 600)), ("narrow", (32, 16, 12, 500)), ("wide", (16, 32, 12, 500)),
-         ("wide", (8, 16, 12, 300)), ("paper", (64, 64, 32, 4096))]
+         ("wide", (8, 16, 12, 300)), ("paper", (64, 64, 32, 4096)), ("extreme", (32, 16, 12, 500))]
 
 
 @pytest.mark.parametrize("kset,shape", CASES)
@@ -190,6 +193,24 @@ def test_wet_step_rfd_paper_kernels():
 
 def test_wet_step_rfd_widest_kernel_at_tile_edges():
     _wet([(8, 9.0), (4, 8.0)], rfd=True, edge=True, step=3)
+
+
+def test_full_table_and_out_of_range_species():
+    """All DISCOS_HY_MAXSP species set: species outside [0, 8) still take the Peskin
+    kernel, not the last species' one."""
+    nx, ny, nz, n = 16, 16, 12, 400
+    table = [(7, 7.0), (4, 8.0), (5, 3.0), (3, 2.0), (6, 9.0), (2, 1.0), (8, 20.0), (7, 1.5)]
+    pos, _ = _ions(nx, ny, nz, n, 8, seed=23)
+    sp = np.random.default_rng(24).choice(np.array([-3, -1, 8, 11, 0, 3, 6, 7], dtype=np.int32), n)
+    F = np.random.default_rng(25).normal(size=(3, n))
+    grid = es.Grid(nx, ny, nz)
+    per_ion = np.array([table[k] if 0 <= k < 8 else (0, 0.0) for k in sp], dtype=np.float64)
+    ref = _flat(*stokes.spread_force_kernels(grid, pos, F, per_ion))
+    ctx = _ctx(nx, ny, nz, n)
+    ctx.set_hydro_kernel(table)
+    out = host(ctx.spread_species(dev(pos), dev(F), dev(sp), ctx.params(_params())))
+    ctx.check()
+    assert rel_l2(out, ref) < TOL
 
 
 def test_hydro_kernel_rejections():
