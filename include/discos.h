@@ -208,7 +208,9 @@ int discos_interpolate(discos_ctx* ctx, int op, int64_t n, const double* pos,
  * to discos_spread_force_species, discos_interpolate_vel_species and the hydrodynamic
  * stages of discos_step (S^hy, the random finite difference, J^hy); the plain
  * DISCOS_SPREAD_FORCE and DISCOS_INTERP_VEL keep the Peskin kernel.  Needs
- * DISCOS_CREATE_HYDRO and nz > w for every w > 0.  Errors: DISCOS_E_ARG, DISCOS_E_SHAPE.
+ * DISCOS_CREATE_HYDRO and nz > w for every w > 0.  A set-up call: it synchronises the
+ * device before replacing the table that calls in flight may read.
+ * Errors: DISCOS_E_ARG, DISCOS_E_SHAPE, DISCOS_E_HIP.
  */
 #define DISCOS_HY_MAXSP 8
 int discos_set_hydro_kernel(discos_ctx* ctx, int32_t nspecies, const double* kernel);
