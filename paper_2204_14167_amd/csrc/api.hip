@@ -275,7 +275,6 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         hb += carve_bytes(2 * nlev, sizeof(double));                        // stress xz yz
         hb += 2 * carve_bytes(2 * ncell + nlev, sizeof(double));            // hvel, hfor
         hb += carve_bytes(3 * nm, sizeof(double));                          // hvi
-        hb += carve_bytes(nm, sizeof(double4));                             // hmid
         hb += carve_bytes(4 * (DISCOS_HY_MAXSP + 1), sizeof(double));        // kernel table
         void* hp = nullptr;
         if (hipMalloc(&hp, hb) != hipSuccess) {
@@ -292,7 +291,6 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hvel = carve<double>(hc, 2 * ncell + nlev);
         c->hfor = carve<double>(hc, 2 * ncell + nlev);
         c->hvi = carve<double>(hc, 3 * nm);
-        c->hmid = carve<double4>(hc, nm);
         c->hy_tab = carve<double>(hc, 4 * (DISCOS_HY_MAXSP + 1));
         c->gd.tsg[0] = c->gd.tsg[1] = -1.0;  // no-slip until a call says otherwise
         // every species on the 4-point Peskin kernel (rows of zeros: w = 0); the Stokes

@@ -45,7 +45,6 @@ struct Ctx {
     double* hvel;     // face velocity scratch for the wet step (3 face arrays)
     double* hfor;     // face force scratch (3 face arrays)
     double* hvi;      // [3][n_max] interpolated ion velocities
-    double4* hmid;    // [n_max] midpoint positions (x, y, z, q) in cell-list order
     double* part;     // [2][PART_MAX] partial sums of the deterministic reductions
     double* bcg;      // [2][ny][nx] wall-field adjoints gathered from the ghost layers
     // hydrodynamic kernel per species: [DISCOS_HY_MAXSP + 1][4] rows (w, beta, 1 / alpha,
@@ -201,7 +200,7 @@ int solve_stokes(Ctx* c, const double* f, const discos_params* p, uint64_t step,
 int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
                      hipStream_t s, int species = 0);
 
-// Predictor and corrector velocities of the wet step: c->hmid = x*, c->hvi = J(x*) v.
+// The wet step's midpoint velocities c->hvi = J(x*) v, x* = x + dt/2 J(x) v.
 int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s, int species = 0);
 
 // Update of the sorted ions from their complete forces c->fp (dry terms of eq step2)

@@ -1148,37 +1148,14 @@ __device__ __forceinline__ double face_val(const double* __restrict__ a, const G
     return s * a[((size_t)k * g.ny + j) * g.nx + i];
 }
 
-// V = J^hy v at the positions xs.  With mid != nullptr the kernel is the predictor of
-// eq step1: mid[i] = (x + half_dt V wrapped in x, y and reflected in z, q); otherwise
-// V goes to out[o] (o = perm[i] if scatter) with the given component stride.  KM = 0:
-// the 4-point Peskin kernel; KM = 2 or 4: ion i's kernel from the table by its species
-// ssp[i], over a window of 2 KM nodes per axis.
+// J^hy v at one position a4 (cell-list ion with kernel row kr when KM != 0): res[3].
+// KM = 0: the 4-point Peskin kernel; KM = 2 or 4: the kernel of row kr over a window of
+// 2 KM nodes per axis.
 template <int KM>
-__global__ void __launch_bounds__(256) interp_hy_kernel(GridDev g, int n, const double4* __restrict__ xs,
-                                 const int* __restrict__ perm, const double* __restrict__ vel,
-                                 double* __restrict__ out, int64_t stride, int scatter,
-                                 double4* __restrict__ mid, double half_dt,
-                                 int* __restrict__ flags, const int* __restrict__ ssp,
-                                 const double* __restrict__ hy_tab) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 a4 = xs[i];
-    if (!pos_ok(g, a4.x, a4.y, a4.z)) {
-        set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
-                                                                          : DISCOS_FLAG_NONFINITE);
-        if (mid) {
-            mid[i] = a4;
-        } else {
-            const int o = scatter ? perm[i] : i;
-            out[o] = out[o + stride] = out[o + 2 * stride] = 0.0;
-        }
-        return;
-    }
+__device__ __forceinline__ void jhy_at(const GridDev& g, const double* __restrict__ vel, double4 a4,
+                                       const double* kr, double res[3]) {
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
-    double res[3];
     if constexpr (KM != 0) {
-        const double* row = hy_row(hy_tab, ssp[i]);
-        const double kr[4] = {row[0], row[1], row[2], row[3]};
         for (int comp = 0; comp < 3; ++comp) {
             const double* a = vel + comp * ncell;
             double wx[2 * KM], wy[2 * KM];
@@ -1245,52 +1222,87 @@ __global__ void __launch_bounds__(256) interp_hy_kernel(GridDev g, int n, const 
         res[comp] = acc;
     }
     }
-    if (mid) {
-        double mx = a4.x + half_dt * res[0], my = a4.y + half_dt * res[1], mz = a4.z + half_dt * res[2];
-        if (!(isfinite(mx) && isfinite(my) && isfinite(mz))) {
-            set_flag(flags, DISCOS_FLAG_NONFINITE);
-            mid[i] = a4;
-            return;
-        }
-        mid[i] = make_double4(wrap_coord(mx, g.Lx), wrap_coord(my, g.Ly), reflect_walls(mz, g.Lz), a4.w);
+}
+
+// V = J^hy v for the ions xs of the cell list.  midpoint = 0: V at x to out[o]
+// (o = perm[i] if scatter) with the given component stride.  midpoint = 1: the two
+// stages of eq step1 for the same ion, x* = x + half_dt J(x) v (wrapped in x, y,
+// reflected in z) and then J(x*) v to out.  Ion i's kernel: the Peskin kernel (KM = 0) or
+// its species' row of the kernel table.
+template <int KM>
+__global__ void __launch_bounds__(256) interp_hy_kernel(GridDev g, int n, const double4* __restrict__ xs,
+                                 const int* __restrict__ perm, const double* __restrict__ vel,
+                                 double* __restrict__ out, int64_t stride, int scatter,
+                                 int midpoint, double half_dt, int* __restrict__ flags,
+                                 const int* __restrict__ ssp, const double* __restrict__ hy_tab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = scatter ? perm[i] : i;
+    auto outside = [&](double4 a) {
+        set_flag(flags, (isfinite(a.x) && isfinite(a.y) && isfinite(a.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                       : DISCOS_FLAG_NONFINITE);
+        out[o] = out[o + stride] = out[o + 2 * stride] = 0.0;
+    };
+    const double4 a4 = xs[i];
+    if (!pos_ok(g, a4.x, a4.y, a4.z)) {
+        outside(a4);
         return;
     }
-    const int o = scatter ? perm[i] : i;
+    double kr[4] = {0.0, 0.0, 0.0, 0.0};
+    if (KM != 0) {
+        const double* row = hy_row(hy_tab, ssp[i]);
+        kr[0] = row[0]; kr[1] = row[1]; kr[2] = row[2]; kr[3] = row[3];
+    }
+    double res[3];
+    jhy_at<KM>(g, vel, a4, kr, res);
+    if (midpoint) {
+        const double mx = a4.x + half_dt * res[0], my = a4.y + half_dt * res[1],
+                     mz = a4.z + half_dt * res[2];
+        double4 m4 = a4;
+        if (!(isfinite(mx) && isfinite(my) && isfinite(mz)))
+            set_flag(flags, DISCOS_FLAG_NONFINITE);
+        else
+            m4 = make_double4(wrap_coord(mx, g.Lx), wrap_coord(my, g.Ly), reflect_walls(mz, g.Lz), a4.w);
+        if (!pos_ok(g, m4.x, m4.y, m4.z)) {
+            outside(m4);
+            return;
+        }
+        jhy_at<KM>(g, vel, m4, kr, res);
+    }
     out[o] = res[0];
     out[o + stride] = res[1];
     out[o + 2 * stride] = res[2];
 }
 
 template <int KM>
-static void interp_hy_launch(Ctx* c, int n, const double4* xs, const double* vel, double* out,
-                             int64_t stride, int scatter, double4* mid, double half_dt, hipStream_t s) {
-    interp_hy_kernel<KM><<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, xs, c->perm, vel, out, stride,
-                                                        scatter, mid, half_dt, c->flags, c->ssp,
+static void interp_hy_launch(Ctx* c, int n, const double* vel, double* out, int64_t stride,
+                             int scatter, int midpoint, double half_dt, hipStream_t s) {
+    interp_hy_kernel<KM><<<(n + 255) / 256, 256, 0, s>>>(c->gd, n, c->sxyzq, c->perm, vel, out, stride,
+                                                        scatter, midpoint, half_dt, c->flags, c->ssp,
                                                         c->hy_tab);
 }
 
-static void interp_hy_any(Ctx* c, int species, int n, const double4* xs, const double* vel,
-                          double* out, int64_t stride, int scatter, double4* mid, double half_dt,
-                          hipStream_t s) {
+static void interp_hy_any(Ctx* c, int species, int n, const double* vel, double* out, int64_t stride,
+                          int scatter, int midpoint, double half_dt, hipStream_t s) {
     const int km = species ? c->hy_km : 0;
-    if (km == 0) interp_hy_launch<0>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
-    else if (km <= 2) interp_hy_launch<2>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
-    else interp_hy_launch<4>(c, n, xs, vel, out, stride, scatter, mid, half_dt, s);
+    if (km == 0) interp_hy_launch<0>(c, n, vel, out, stride, scatter, midpoint, half_dt, s);
+    else if (km <= 2) interp_hy_launch<2>(c, n, vel, out, stride, scatter, midpoint, half_dt, s);
+    else interp_hy_launch<4>(c, n, vel, out, stride, scatter, midpoint, half_dt, s);
 }
 
 int interp_hy_sorted(Ctx* c, int n, const double* vel, double* out, int64_t stride, int scatter,
                      hipStream_t s, int species) {
     if (n <= 0) return DISCOS_OK;
-    interp_hy_any(c, species, n, c->sxyzq, vel, out, stride, scatter, nullptr, 0.0, s);
+    interp_hy_any(c, species, n, vel, out, stride, scatter, 0, 0.0, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
-// Stage 4 velocities of the wet step for the ions of the cell list: the predictor
-// x* = x + dt/2 J(x) v into c->hmid, then J(x*) v into c->hvi ([3][n_max], sorted).
+// Stage 4 velocities of the wet step for the ions of the cell list: J(x*) v with the
+// predictor x* = x + dt/2 J(x) v, into c->hvi ([3][n_max], sorted); one thread per ion
+// takes both gathers.
 int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s, int species) {
     if (n <= 0) return DISCOS_OK;
-    interp_hy_any(c, species, n, c->sxyzq, vel, nullptr, 0, 0, c->hmid, 0.5 * dt, s);
-    interp_hy_any(c, species, n, c->hmid, vel, c->hvi, c->n_max, 0, nullptr, 0.0, s);
+    interp_hy_any(c, species, n, vel, c->hvi, c->n_max, 0, 1, 0.5 * dt, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
