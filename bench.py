@@ -230,12 +230,12 @@ def wet_stage_bytes(stage, N, C3):
     """Algorithmic bytes of the hydrodynamic stages of one wet step (N ions, C3 face
     values of the three velocity components): S^hy reads positions (32 B), forces
     (24 B) and ids (4 B, the random finite difference) and writes every face once; the
-    midpoint J^hy reads positions, writes x* (32 B), reads x* and writes V (24 B), and
-    reads the faces once per pass."""
+    midpoint J^hy (both gathers by one thread per ion) reads positions (32 B), writes the
+    velocity (24 B) and reads the faces once per gather."""
     if stage == "spread_hy":
         return 60.0 * N + 8.0 * C3
     if stage == "interp_hy":
-        return 120.0 * N + 16.0 * C3
+        return 56.0 * N + 16.0 * C3
     return None
 
 
