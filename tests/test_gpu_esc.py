@@ -228,3 +228,49 @@ def test_hydro_kernel_rejections():
     with pytest.raises(discos.DiscosError, match="HYDRO"):
         dry.set_hydro_kernel([(4, 8.0)])
     dry.close()
+
+
+def test_species_calls_and_steps_without_ions():
+    """n = 0: the species spread returns zero faces, the interpolation and the dry and
+    wet steps (with ESC kernels) launch nothing and leave no error."""
+    from paper_2204_14167_amd import discos
+    w = workloads.WORKLOADS["dirichlet_32x32x32_n256"]
+    p = workloads.make_params(w)
+    p["rfd_delta"] = 1e-4
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, 8, hydro=True)
+    ctx.set_hydro_kernel(KERNELS["paper"])
+    dp = ctx.params(p)
+    empty = dev(np.zeros((3, 0)))
+    e_sp = dev(np.zeros(0, dtype=np.int32))
+    out = host(ctx.spread_species(empty, empty, e_sp, dp))
+    assert out.shape == (ctx.face_size,) and np.all(out == 0.0)
+    v = dev(np.zeros(ctx.face_size))
+    assert host(ctx.interpolate_vel_species(empty, v, e_sp, dp)).shape == (3, 0)
+    args = (empty, dev(np.zeros(0)), dev(np.zeros(0, dtype=np.int32)), e_sp)
+    ctx.step(*args, dp, 0)
+    ctx.step(*args, dp, 1, mode=discos.STEP_WET | discos.STEP_RFD)
+    ctx.check()
+
+
+def test_wet_step_esc_two_slip_walls_rfd():
+    """Every addition at once: the paper's ESC pair, two slip walls, the random finite
+    difference, one wet step against the oracle's."""
+    from paper_2204_14167_amd import discos
+    w = workloads.WORKLOADS["dirichlet_32x32x32_n256"]
+    p = workloads.make_params(w)
+    p["hydro_kernel"] = np.asarray(KERNELS["paper"], dtype=np.float64)
+    p["slip"] = (True, True)
+    delta = 1e-4 * w.h
+    p["rfd_delta"] = delta
+    pos, q, ids, species = workloads.make_ions(w)
+    grid = es.Grid(w.nx, w.ny, w.nz, w.h)
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, hydro=True)
+    ctx.set_hydro_kernel(KERNELS["paper"])
+    args = (dev(pos), dev(q), dev(ids), dev(species))
+    ref, _, _ = dynamics.wet_step(grid, pos, q, species, ids, p, 7, rfd_delta=delta, near="brute")
+    ctx.step(*args, ctx.params(p), 7, mode=discos.STEP_WET | discos.STEP_RFD)
+    ctx.check()
+    got = by_id(host(args[0]), host(args[2]), ids)
+    r = np.linalg.norm(min_image(got - ref, grid.L)) / np.linalg.norm(min_image(ref - pos, grid.L))
+    log(f"esc + two slip walls + rfd rel={r:.3e}")
+    assert r < TOL
