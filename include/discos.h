@@ -286,12 +286,17 @@ int discos_energy_flux(discos_ctx* ctx, int64_t n, const double* pos, const doub
  * dbc_hi, [ny][nx]: phi_b or sigma of each column) and the applied field (de, [3]).
  * Every output is a DEVICE array, may be NULL (not computed), and is overwritten.
  * phi must be the checkpoint written by discos_energy_flux for the same pos, q and p.
- * Cost: one transposed interpolation, one Poisson solve, one gradient gather.
+ * Cost: one transposed interpolation, one Poisson solve, one gradient gather, and the
+ * cell list of the ions unless flags has DISCOS_ADJ_REUSE_CELLS: the caller then states
+ * that pos and q are unchanged since the discos_energy_flux call that wrote phi, and
+ * the cell list that call built is used again, if no call on the context has rebuilt
+ * it since and n is the same (else it is rebuilt).
  */
+#define DISCOS_ADJ_REUSE_CELLS 1u
 int discos_energy_flux_backward(discos_ctx* ctx, int64_t n, const double* pos, const double* q,
                                 const discos_params* p, const double* phi, const double* g,
                                 double* dpos, double* dq, double* dbc_lo, double* dbc_hi,
-                                double* de, void* stream);
+                                double* de, uint32_t flags, void* stream);
 
 /*
  * Batches of independent channels (a project addition; each channel is exactly the

@@ -45,7 +45,9 @@ class EnergyFlux(torch.autograd.Function):
         gU = torch.zeros((), dtype=torch.float64, device="cuda") if gU is None else gU
         gQ = torch.zeros((), dtype=torch.float64, device="cuda") if gQ is None else gQ
         g = torch.stack([gU.reshape(()), gQ.reshape(())]).to(torch.float64).contiguous()
-        res = fctx.dctx.energy_flux_backward(pos, q, fctx.prm, phi, g, want=want)
+        # the saved tensors are the forward's (autograd rejects in-place changes to them),
+        # so the forward's cell list may serve, unless another call rebuilt it
+        res = fctx.dctx.energy_flux_backward(pos, q, fctx.prm, phi, g, want=want, reuse_cells=True)
         de = res["e_ext"]
         if de is not None:
             de = de.to(fctx.e_device)

@@ -305,6 +305,9 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         c->hydro = 1;
     }
     c->zg_key = -1;
+    c->cl_gen = 0;
+    c->ef_gen = ~(uint64_t)0;  // no forward list yet
+    c->ef_n = -1;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;
     c->last_stream = nullptr;
@@ -597,6 +600,8 @@ int discos_energy_flux(discos_ctx* c, int64_t n, const double* pos, const double
     if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
     const int ni = (int)n;
     rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
+    c->ef_gen = c->cl_gen;
+    c->ef_n = ni;
     if (!rc) rc = discos::spread_charge_sorted(c, p, 1, c->rho, s);
     if (!rc) rc = discos::solve_poisson(c, c->rho, p, phi, s);
     if (!rc && ni > 0)
@@ -608,7 +613,7 @@ int discos_energy_flux(discos_ctx* c, int64_t n, const double* pos, const double
 int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, const double* q,
                                 const discos_params* p, const double* phi, const double* g,
                                 double* dpos, double* dq, double* dbc_lo, double* dbc_hi,
-                                double* de, void* stream) {
+                                double* de, uint32_t flags, void* stream) {
     if (!c) return DISCOS_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
@@ -618,7 +623,10 @@ int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, con
     if (rc) return rc;
     if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
     const int ni = (int)n;
-    rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
+    // the forward pass's cell list when the caller vouches for unchanged ions and no call
+    // has rebuilt it since
+    const bool reuse = (flags & DISCOS_ADJ_REUSE_CELLS) && c->ef_gen == c->cl_gen && c->ef_n == ni;
+    if (!reuse) rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
     if (!rc) rc = discos::energy_flux_backward(c, ni, p, phi, g, dpos, dq, dbc_lo, dbc_hi, de, s);
     return rc ? fail(c, rc, "energy/flux backward launch failed") : DISCOS_OK;
 }

@@ -184,6 +184,7 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
 int build_cell_list(Ctx* c, int n, const double* x, const double* y, const double* z,
                     const double* q, const int* id, const int* sp, hipStream_t s,
                     const double* w3, int64_t w3_stride) {
+    ++c->cl_gen;
     const GridDev& g = c->gd;
     const int64_t nb = c->nbins;
     const int T = 256;

@@ -59,6 +59,11 @@ struct Ctx {
     size_t pool_bytes;
     hipStream_t last_stream;
     std::string err;
+    // cell-list generations: every build advances cl_gen; discos_energy_flux records the
+    // generation and ion count of the list it built (for the backward pass to reuse)
+    uint64_t cl_gen;
+    uint64_t ef_gen;
+    int ef_n;
     // stage timing (discos_profile): one row of DISCOS_NSTAGE + 1 events per step,
     // for up to PROF_MAX steps
     int profile;

@@ -24,6 +24,7 @@ STEP_DRY, STEP_WET, STEP_RFD = 0, 1, 0x10
 CREATE_HYDRO = 1
 STOKES_NOISE = 1
 HYDRO_NOSLIP, HYDRO_SLIP = 0, 1
+ADJ_REUSE_CELLS = 1
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -105,7 +106,7 @@ def lib():
                                           ctypes.POINTER(ctypes.c_int)]
         L.discos_energy_flux.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp, vp]
         L.discos_energy_flux_backward.argtypes = [vp, i64, vp, vp, ctypes.POINTER(DiscosParams), vp, vp,
-                                                  vp, vp, vp, vp, vp, vp]
+                                                  vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
         L.discos_batch_create.argtypes = [ctypes.POINTER(DiscosReplica), i32, ctypes.c_double,
                                           ctypes.POINTER(DiscosParams), ctypes.POINTER(vp)]
         L.discos_batch_destroy.argtypes = [vp]
@@ -377,8 +378,11 @@ class Context:
                                           _ptr(phi), _ptr(out), _stream()))
         return out, phi
 
-    def energy_flux_backward(self, pos, q, params, phi, g, want=("pos", "q", "bc_lo", "bc_hi", "e_ext")):
-        """gU dU + gQ dQ (g = [gU, gQ] on the device) w.r.t. the requested inputs."""
+    def energy_flux_backward(self, pos, q, params, phi, g, want=("pos", "q", "bc_lo", "bc_hi", "e_ext"),
+                             reuse_cells=False):
+        """gU dU + gQ dQ (g = [gU, gQ] on the device) w.r.t. the requested inputs.
+        reuse_cells: pos and q are unchanged since the energy_flux call that wrote phi, so
+        its cell list may serve again (the library rebuilds it if another call did)."""
         n = pos.shape[1] if pos is not None else 0
         nx, ny, nz, _ = self.grid
         dev = dict(dtype=torch.float64, device="cuda")
@@ -391,7 +395,7 @@ class Context:
         self._rc(lib().discos_energy_flux_backward(
             self.handle, n, _ptr(pos), _ptr(q), ctypes.byref(params.struct), _ptr(phi), _ptr(g),
             _ptr(res["pos"]), _ptr(res["q"]), _ptr(res["bc_lo"]), _ptr(res["bc_hi"]), _ptr(res["e_ext"]),
-            _stream()))
+            ADJ_REUSE_CELLS if reuse_cells else 0, _stream()))
         return res
 
     def check(self):

@@ -91,6 +91,34 @@ def test_each_functional_alone(gU, gQ):
         assert np.all(got["e_ext"] == 0.0)
 
 
+def test_backward_reusing_the_forward_cell_list():
+    """DISCOS_ADJ_REUSE_CELLS gives the gradients of a rebuilt cell list; after another
+    call rebuilt the context's list (or with another n) the backward pass rebuilds it."""
+    grid, pos, q, p = _case((D, N))
+    n = pos.shape[1]
+    ctx = _ctx(grid, n)
+    prm = ctx.params(p)
+    dpos, dq = dev(pos), dev(q)
+    g = dev(np.array([0.7, -1.3]))
+    out, phi = ctx.energy_flux(dpos, dq, prm)
+    ref = {k: host(v) for k, v in ctx.energy_flux_backward(dpos, dq, prm, phi, g).items()}
+    # right after the forward pass
+    out, phi = ctx.energy_flux(dpos, dq, prm)
+    got = {k: host(v) for k, v in ctx.energy_flux_backward(dpos, dq, prm, phi, g, reuse_cells=True).items()}
+    for k in ref:
+        assert rel_l2(got[k], ref[k]) < 1e-12, k
+    # another call rebuilds the list in between (as many ions, elsewhere, other charges):
+    # the flag must not reuse it
+    from paper_2204_14167_amd import discos
+    other = pos.copy()
+    other[0] = np.mod(other[0] + 3.3, grid.L[0])
+    ctx.spread(discos.SPREAD_CHARGE, dev(other), dev(q[::-1].copy()), prm)
+    got = {k: host(v) for k, v in ctx.energy_flux_backward(dpos, dq, prm, phi, g, reuse_cells=True).items()}
+    for k in ref:
+        assert rel_l2(got[k], ref[k]) < 1e-12, k
+    ctx.check()
+
+
 def test_no_ions():
     grid, pos, q, p = _case((D, D))
     ref = adjoint.gradients(grid, pos[:, :0], q[:0], p, gU=1.0, gQ=1.0)
