@@ -212,11 +212,38 @@ __device__ __forceinline__ double shift_of(int code, double L) {
     return code == 1 ? -L : (code == 2 ? L : 0.0);
 }
 
+// Runs of candidate bins of one slab (one z-row of bins, or one image layer), at most
+// two per y-row: 2R + 1 <= nbx, so a row of 2R + 1 bins crosses the periodic seam at
+// most once.  Each thread keeps its slab's runs in its own column of the block's LDS
+// buffer (entry = first sorted index | shift and mode code, end index).
+#define NL_SLAB_RUNS(R) (2 * (2 * (R) + 1))
+
+// A run entry decoded: its candidate range, code bits, and the ion's x and y against
+// the candidates' periodic copy.
+struct NlRun {
+    int j, e, code;
+    float xs, ys;
+};
+
+__device__ __forceinline__ NlRun nl_run(int2 r, float xf0, float xf1, float xf2, float yf0,
+                                        float yf1, float yf2) {
+    NlRun u;
+    u.j = r.x & 0x3FFFFFF;
+    u.code = r.x & ~0x3FFFFFF;
+    u.e = r.y;
+    const int xc = (r.x >> 26) & 3, yc = (r.x >> 28) & 3;
+    u.xs = xc == 0 ? xf0 : (xc == 1 ? xf1 : xf2);
+    u.ys = yc == 0 ? yf0 : (yc == 1 ? yf1 : yf2);
+    return u;
+}
+
+template <int R>
 __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P, int i, int n,
                                               const double4* __restrict__ sxyzq,
                                               const float4* __restrict__ sxyzf,
                                               const int* __restrict__ bin_start,
-                                              int* __restrict__ list, int* __restrict__ count) {
+                                              int* __restrict__ list, int* __restrict__ count,
+                                              int2* __restrict__ buf, int bstride) {
     const double4 me = sxyzq[i];
     const double xi = me.x, yi = me.y, zi = me.z;
     if (!pos_ok(g, xi, yi, zi)) {
@@ -227,16 +254,22 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
     const double inv_Bh = 1.0 / Bh;
     const double rs2 = P.rsearch * P.rsearch;
     const double r2cut = fmax(P.psi2, P.lj_on ? rs2 * (1.0 + 1e-12) : 0.0);
-    const int R = P.R;
     int bx, by, bz;
     bin_of(g, xi, yi, zi, bx, by, bz);
-    int4* chunks = reinterpret_cast<int4*>(list);  // chunk c of ion i at [c * n + i]
     // Candidates are filtered in FP32 against the cutoff widened by a margin that bounds
     // the FP32 error of the squared distance (coordinates up to Lmax, distances up to
     // the search radius): the lists are a superset of the pairs inside the cutoff, and
     // the force pass applies the exact FP64 test.
     const double Lmax = fmax(fmax(g.Lx, g.Ly), 2.0 * g.Lz);
     const double margin = 32.0 * sqrt(r2cut) * Lmax * 0x1.0p-24;
+    // the ion's coordinates against a candidate's periodic copy, by shift code 0, 1, 2
+    float xf0 = (float)xi, xf1 = (float)(xi + g.Lx), xf2 = (float)(xi - g.Lx);
+    float yf0 = (float)yi, yf1 = (float)(yi + g.Ly), yf2 = (float)(yi - g.Ly);
+    // opaque to the optimiser: otherwise it folds the per-run choice of these six values
+    // back into an FP64 add and conversion inside the candidate loop
+    asm("" : "+v"(xf0), "+v"(xf1), "+v"(xf2), "+v"(yf0), "+v"(yf1), "+v"(yf2));
+    // chunk c of ion i at [c * n + i]; the last four hits are kept in h0..h3 (oldest first)
+    int4* const chunks = reinterpret_cast<int4*>(list) + i;
     int nh = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
     for (int mode = 0; mode < 3; ++mode) {
         int zlo, zhi;
@@ -254,90 +287,162 @@ __device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P
         }
         const double r2m = mode == 0 ? rs2 : P.psi2;
         const double cut = mode == 0 ? r2cut : P.psi2;
+        const float zsf = mode == 0 ? 1.0f : -1.0f;
+        const float zef = (float)(mode == 2 ? zi - 2.0 * g.Lz : zi);
+        const float cutf = (float)(cut * (1.0 + 1e-5) + margin);
+        const int self = mode == 0 ? i : -1;  // the ion itself is excluded by index
+        const int mcode = mode << 30;
         for (int cz = zlo; cz <= zhi; ++cz) {
             const double zb0 = cz * Bh, zb1 = fmin((cz + 1) * Bh, g.Lz);
             const double dzm = mode == 0 ? fmax(0.0, fmax(zb0 - zi, zi - zb1))
                                          : (mode == 1 ? zi + zb0 : (2.0 * g.Lz - zb1) - zi);
             const double remz = r2m - dzm * dzm;
             if (!(remz > 0.0)) continue;
+            // 1. the slab's non-empty runs
+            int nr = 0;
+#pragma unroll 1
             for (int dyb = -R; dyb <= R; ++dyb) {
                 const int cyu = by + dyb;
                 const double yb0 = cyu * Bh;
                 const double dym = fmax(0.0, fmax(yb0 - yi, yi - (yb0 + Bh)));
                 const double rem = remz - dym * dym;
                 if (!(rem > 0.0)) continue;
-                const double wx = sqrt(rem);
+                // half chord of the search sphere in x; the FP32 root (within 2^-22
+                // relative of the exact one) is widened so that the bin range can only grow
+                const double wx =
+                    (double)__builtin_amdgcn_sqrtf((float)rem) * (1.0 + 0x1.0p-18) + 0x1.0p-20 * Bh;
                 const int bxl = max(bx - R, (int)floor((xi - wx) * inv_Bh));
                 const int bxh = min(bx + R, (int)floor((xi + wx) * inv_Bh));
                 if (bxl > bxh) continue;
                 const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
-                const int ysc = cyu < 0 ? 1 : (cyu >= g.nby ? 2 : 0);
-                const double ys = yi - shift_of(ysc, g.Ly);
+                const int ycode = (cyu < 0 ? 1 : (cyu >= g.nby ? 2 : 0)) << 28;
                 const int row = (cz * g.nby + cy) * g.nbx;
-                for (int bu = bxl; bu <= bxh;) {
-                    // contiguous run of bins up to the periodic seam
-                    const int cx = bu < 0 ? bu + g.nbx : (bu >= g.nbx ? bu - g.nbx : bu);
-                    const int xsc = bu < 0 ? 1 : (bu >= g.nbx ? 2 : 0);
-                    const int run_end = bu < 0 ? min(bxh, -1) : (bu < g.nbx ? min(bxh, g.nbx - 1) : bxh);
-                    const int cx_end = cx + (run_end - bu);
-                    bu = run_end + 1;
-                    const double xs = xi - shift_of(xsc, g.Lx);
-                    const int code = (xsc << 26) | (ysc << 28) | (mode << 30);
-                    const int j0 = bin_start[row + cx], j1 = bin_start[row + cx_end + 1];
-                    const float xsf = (float)xs, ysf = (float)ys;
-                    const float zsf = mode == 0 ? 1.0f : -1.0f;
-                    const float zef = (float)(mode == 2 ? zi - 2.0 * g.Lz : zi);
-                    const float cutf = (float)(cut * (1.0 + 1e-5) + margin);
-                    for (int j = j0; j < j1; ++j) {
-                        const float4 o = sxyzf[j];
-                        const float dx = xsf - o.x;
-                        const float dy = ysf - o.y;
-                        const float dz = zef - zsf * o.z;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        // the ion itself is excluded by index: a zero FP32 distance may be
-                        // a distinct (coincident in FP32) pair
-                        if (r2 < cutf && (mode != 0 || j != i)) {
-                            const int e = j | code;
-                            const int slot = nh & 3;
-                            h0 = slot == 0 ? e : h0;
-                            h1 = slot == 1 ? e : h1;
-                            h2 = slot == 2 ? e : h2;
-                            h3 = slot == 3 ? e : h3;
-                            if (slot == 3 && nh < P.cap)
-                                chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
-                            ++nh;
-                        }
-                    }
+                // first run: up to the seam (or the whole range)
+                const int e1 = bxl < 0 ? min(bxh, -1) : (bxl < g.nbx ? min(bxh, g.nbx - 1) : bxh);
+                const int cx1 = bxl < 0 ? bxl + g.nbx : (bxl >= g.nbx ? bxl - g.nbx : bxl);
+                const int xc1 = bxl < 0 ? 1 : (bxl >= g.nbx ? 2 : 0);
+                const int j0 = bin_start[row + cx1], j1 = bin_start[row + cx1 + (e1 - bxl) + 1];
+                // second run: past the seam
+                const bool two = e1 < bxh;
+                const int b2 = e1 + 1;
+                const int cx2 = b2 >= g.nbx ? b2 - g.nbx : b2;
+                const int xc2 = b2 >= g.nbx ? 2 : 0;
+                const int k0 = two ? bin_start[row + cx2] : 0;
+                const int k1 = two ? bin_start[row + cx2 + (bxh - b2) + 1] : 0;
+                if (j0 < j1) buf[(nr++) * bstride] = make_int2(j0 | (xc1 << 26) | ycode | mcode, j1);
+                if (k0 < k1) buf[(nr++) * bstride] = make_int2(k0 | (xc2 << 26) | ycode | mcode, k1);
+            }
+            // 2. their candidates in one loop: a lane's trip count is its slab total.  The
+            // next candidate (and, at a run's end, the next run from LDS) is found while
+            // the current one's coordinates are in flight.
+            const int2* rp = buf;
+            const int2* const rend = buf + nr * bstride;
+            int j = 0, je = 0, code = 0;
+            float xs = 0.0f, ys = 0.0f;
+            if (rp < rend) {
+                const NlRun u = nl_run(*rp, xf0, xf1, xf2, yf0, yf1, yf2);
+                j = u.j;
+                je = u.e;
+                code = u.code;
+                xs = u.xs;
+                ys = u.ys;
+                rp += bstride;
+            }
+            while (j < je) {
+                const float4 o = sxyzf[j];
+                int jn = j + 1, jen = je, coden = code;
+                float xsn = xs, ysn = ys;
+                if (jn >= je && rp < rend) {
+                    const NlRun u = nl_run(*rp, xf0, xf1, xf2, yf0, yf1, yf2);
+                    jn = u.j;
+                    jen = u.e;
+                    coden = u.code;
+                    xsn = u.xs;
+                    ysn = u.ys;
+                    rp += bstride;
                 }
+                const float dx = xs - o.x;
+                const float dy = ys - o.y;
+                const float dz = zef - zsf * o.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                // a zero FP32 distance may be a distinct (coincident in FP32) pair
+                if (r2 < cutf && j != self) {
+                    h0 = h1;
+                    h1 = h2;
+                    h2 = h3;
+                    h3 = j | code;
+                    ++nh;
+                    if ((nh & 3) == 0 && nh <= P.cap)
+                        chunks[(size_t)((nh >> 2) - 1) * n] = make_int4(h0, h1, h2, h3);
+                }
+                j = jn;
+                je = jen;
+                code = coden;
+                xs = xsn;
+                ys = ysn;
             }
         }
     }
-    // the incomplete last chunk
-    if ((nh & 3) && nh <= P.cap) chunks[(size_t)(nh >> 2) * n + i] = make_int4(h0, h1, h2, h3);
+    // the incomplete last chunk: its m = nh mod 4 hits are the newest m of h0..h3
+    const int m = nh & 3;
+    if (m && nh <= P.cap)
+        chunks[(size_t)(nh >> 2) * n] =
+            m == 1 ? make_int4(h3, 0, 0, 0) : (m == 2 ? make_int4(h2, h3, 0, 0) : make_int4(h1, h2, h3, 0));
     count[i] = nh;
 }
 
+template <int R>
 __global__ void __launch_bounds__(256)
 near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
                  const float4* __restrict__ sxyzf,
                  const int* __restrict__ bin_start, int* __restrict__ list,
                  int* __restrict__ count) {
+    extern __shared__ int2 nl_buf[];
     const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    near_list_one(g, P, i, n, sxyzq, sxyzf, bin_start, list, count);
+    near_list_one<R>(g, P, i, n, sxyzq, sxyzf, bin_start, list, count, nl_buf + threadIdx.x,
+                     blockDim.x);
 }
 
 // Batched: ion i (cell-list order) belongs to channel ion_rep[i]; its bins start at the
 // channel's bin offset, and its list entries are batch-wide sorted indices.
-__global__ void near_list_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
-                                       NearDev P, int n, const double4* __restrict__ sxyzq,
-                                       const float4* __restrict__ sxyzf,
-                                       const int* __restrict__ bin_start, int* __restrict__ list,
-                                       int* __restrict__ count) {
+template <int R>
+__global__ void __launch_bounds__(256)
+near_list_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                       NearDev P, int n, const double4* __restrict__ sxyzq,
+                       const float4* __restrict__ sxyzf,
+                       const int* __restrict__ bin_start, int* __restrict__ list,
+                       int* __restrict__ count) {
+    extern __shared__ int2 nl_buf[];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const RepDev& R = reps[ion_rep[i]];
-    near_list_one(R.g, P, i, n, sxyzq, sxyzf, bin_start + R.bin_off, list, count);
+    const RepDev& Rp = reps[ion_rep[i]];
+    near_list_one<R>(Rp.g, P, i, n, sxyzq, sxyzf, bin_start + Rp.bin_off, list, count,
+                     nl_buf + threadIdx.x, blockDim.x);
+}
+
+// The list pass for search radii of 1 to 3 bins (larger radii are rejected up front).
+static int launch_near_list(const NearDev& P, int n, int T, hipStream_t s, const GridDev* g,
+                            const RepDev* reps, const int* ion_rep, const double4* sxyzq,
+                            const float4* sxyzf, const int* bin_start, int* list, int* count) {
+    if (P.R < 1 || P.R > 3 || T > 256) return DISCOS_E_ARG;
+    const size_t lds = (size_t)NL_SLAB_RUNS(P.R) * T * sizeof(int2);
+    const int nb = (n + T - 1) / T;
+#define NL_LAUNCH(RR)                                                                           \
+    if (g)                                                                                      \
+        near_list_kernel<RR><<<nb, T, lds, s>>>(*g, P, n, sxyzq, sxyzf, bin_start, list, count); \
+    else                                                                                        \
+        near_list_batch_kernel<RR><<<nb, T, lds, s>>>(reps, ion_rep, P, n, sxyzq, sxyzf,        \
+                                                      bin_start, list, count);
+    if (P.R == 1) {
+        NL_LAUNCH(1)
+    } else if (P.R == 2) {
+        NL_LAUNCH(2)
+    } else {
+        NL_LAUNCH(3)
+    }
+#undef NL_LAUNCH
+    return DISCOS_OK;
 }
 
 // Pair forces of ion i from its list (or, when the list overflowed, from a direct
@@ -612,8 +717,9 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
     const int T = 256;
-    near_list_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->sxyzf, c->bin_start,
-                                                   c->nlist, c->ncount);
+    int rc = launch_near_list(P, n, T, s, &c->gd, nullptr, nullptr, c->sxyzq, c->sxyzf,
+                              c->bin_start, c->nlist, c->ncount);
+    if (rc) return rc;
     if (mark >= 0) stage_mark(c, mark, s);
     FusedUpdate U{};
     if (upd) {
@@ -670,8 +776,9 @@ int batch_near(Batch* b, hipStream_t s) {
     NearDev P = near_of_h(b->h, &b->p);
     P.cap = b->nl_cap;
     const int T = b->cfg.ion_block;
-    near_list_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
-                                                         b->sxyzf, b->bin_start, b->nlist, b->ncount);
+    int rc = launch_near_list(P, n, T, s, nullptr, b->reps_d, b->ion_rep, b->sxyzq, b->sxyzf,
+                              b->bin_start, b->nlist, b->ncount);
+    if (rc) return rc;
     near_eval_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
                                                          b->ssp, b->bin_start, b->nlist, b->ncount,
                                                          b->fp, b->flags);
