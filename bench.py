@@ -49,6 +49,7 @@ STAGE_KERNEL = {"spread": "spread_charge_kernel", "fft_x": "fft_x_r2c_kernel",
                 "interp": "interp_es_kernel", "near_list": "near_list_kernel",
                 "near_eval": "near_eval_kernel"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_dry_step_256x256x128_n1048576.md")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "sq_issue_dry_step_256x256x128_n1048576.md")
 
 # The resolved-hydrodynamics channel: wet midpoint step with the random finite
 # difference and the stochastic stress, with the 4-point Peskin kernel and with the ESC
@@ -69,21 +70,34 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated), or None if absent or taken on other sources."""
+def committed_block(path):
+    """The fenced JSON block of a committed profile summary, or None if it is absent or
+    was taken on other kernel sources."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     block = text.split("```json", 1)
     if len(block) < 2:
         return None
     data = json.loads(block[1].split("```", 1)[0])
-    if data.get("source_sha256") != kernel_source_hash():
-        return None
-    k = data.get("kernels", {}).get(kernel)
+    return data if data.get("source_sha256") == kernel_source_hash() else None
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or None if absent or taken on other sources."""
+    data = committed_block(TRAFFIC_FILE)
+    k = None if data is None else data.get("kernels", {}).get(kernel)
     return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def committed_issue(kernel):
+    """Share of the chip's VALU issue cycles `kernel` fills (SQ instruction counters over
+    its kernel-trace duration), or None if absent or taken on other sources."""
+    data = committed_block(ISSUE_FILE)
+    k = None if data is None else data.get("kernels", {}).get(kernel)
+    return None if k is None else k["valu_issue_share"]
 
 
 def stage_work(stage, N, C, H, pairs, tests):
@@ -473,7 +487,8 @@ def main():
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "precision": "fp32" if peak == FP32_PEAK_TFLOPS else "fp64",
                 "traffic": traffic, "algorithmic_flops": work, "ms_per_launch": dom_live_ms,
-                "pairs_per_ion": pairs / N, "tests_per_ion": tests / N}
+                "pairs_per_ion": pairs / N, "tests_per_ion": tests / N,
+                "valu_issue_share": committed_issue(STAGE_KERNEL[dom])}
     per_stage = {}
     for k, v in stages.items():
         b, wk = stage_work(k, N, C, H, pairs, tests)

@@ -6,8 +6,13 @@
       HBM bytes per dispatch of every kernel from a FETCH_SIZE run and a WRITE_SIZE run,
       each scaled by what the same counter reads for the 1 GiB device copy those runs
       include (bench.py --copy-calibration), with a fenced JSON block that bench.py reads
+  python -m paper_2204_14167_amd.rocprof_summary issue SQ.db KT.db --command "..." > out.md
+      instructions per wavefront (VALU, SALU, vector memory reads, LDS) from an SQ counter
+      run, and the share of VALU issue cycles each kernel fills over its kernel-trace
+      duration: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles, and the
+      chip has 1024 SIMDs (256 CUs x 4) at 2.4 GHz
 
-Both read only the rocpd SQLite tables `kernels` and `counters_collection`.
+All read only the rocpd SQLite tables `kernels` and `counters_collection`.
 """
 import argparse
 import json
@@ -16,10 +21,13 @@ import sqlite3
 import sys
 
 COPY_BYTES = 1 << 30  # the calibration copy of bench.py --copy-calibration
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
 
 
 def _short(name):
-    return re.sub(r"\(.*", "", name).replace("discos::", "")
+    """Kernel name without namespace, return type, template and call arguments."""
+    name = re.sub(r"\(.*", "", name).replace("discos::", "")
+    return re.sub(r"<.*?>", "", re.sub(r"^void ", "", name))
 
 
 def kernel_rows(db):
@@ -89,6 +97,46 @@ def cmd_traffic(args):
     print("\n```json\n" + json.dumps(data, indent=1) + "\n```")
 
 
+def cmd_issue(args):
+    cur = sqlite3.connect(args.db).cursor()
+    q = ("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+         "group by kernel_name, counter_name")
+    per = {}
+    for k, c, v, n in cur.execute(q).fetchall():
+        per.setdefault(_short(k), {})[c] = (v, n)
+    dur = {r[0]: r[2] for r in kernel_rows(args.trace_db)}  # mean ns
+    print(f"# Instruction issue per wavefront: {args.title}\n")
+    print("Commands (counters, then the kernel trace whose mean durations are used):\n")
+    for c in args.command:
+        print(f"    {c}")
+    print(f"\nVALU issue share = VALU instructions x {CYCLES_PER_VALU} cycles / ({SIMDS} SIMDs x "
+          f"{CLOCK_HZ / 1e9:.1f} GHz x mean duration).\n")
+    print("| kernel | dispatches | waves | VALU / wave | SALU / wave | VMEM rd / wave | LDS / wave "
+          "| mean us | VALU issue share |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+    data = {}
+    for k in sorted(per, key=lambda k: -per[k].get("SQ_INSTS_VALU", (0, 0))[0]):
+        d = per[k]
+        if "SQ_WAVES" not in d or "SQ_INSTS_VALU" not in d or "rocclr" in k or "at::native" in k:
+            continue
+        waves = d["SQ_WAVES"][0]
+        if waves <= 0:
+            continue
+        pw = {c: d[c][0] / waves for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+                                           "SQ_INSTS_LDS") if c in d}
+        t = dur.get(k)
+        share = (d["SQ_INSTS_VALU"][0] * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ * t * 1e-9)
+                 if t else None)
+        cell = lambda c: f"{pw[c]:.0f}" if c in pw else "-"
+        print(f"| {k} | {d['SQ_WAVES'][1]} | {waves:.0f} | {cell('SQ_INSTS_VALU')} | "
+              f"{cell('SQ_INSTS_SALU')} | {cell('SQ_INSTS_VMEM_RD')} | {cell('SQ_INSTS_LDS')} | "
+              f"{'-' if t is None else f'{t / 1e3:.2f}'} | {'-' if share is None else f'{share:.2f}'} |")
+        data[k] = {"valu_per_wave": round(pw["SQ_INSTS_VALU"], 1),
+                   "valu_issue_share": None if share is None else round(share, 3)}
+    print("\n```json\n" + json.dumps({"source_sha256": args.source_sha256, "kernels": data},
+                                      indent=1) + "\n```")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -104,6 +152,13 @@ def main(argv=None):
     b.add_argument("--title", default="")
     b.add_argument("--source-sha256", required=True)
     b.set_defaults(fn=cmd_traffic)
+    c = sub.add_parser("issue")
+    c.add_argument("db")
+    c.add_argument("trace_db")
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--source-sha256", required=True)
+    c.set_defaults(fn=cmd_issue)
     args = ap.parse_args(argv)
     args.fn(args)
 
