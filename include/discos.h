@@ -128,6 +128,9 @@ typedef struct discos_ctx discos_ctx;
  */
 #define DISCOS_CREATE_HYDRO 1u /* also allocate the Stokes / wet-step scratch */
 int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out);
+/* Waits for the device, then releases the context and its buffers.  Everything is
+ * released even when the runtime reports an error on the way; that error is returned
+ * as DISCOS_E_HIP.  DISCOS_E_ARG for a null context. */
 int discos_destroy(discos_ctx* ctx);
 
 /*
@@ -323,6 +326,8 @@ typedef struct discos_batch discos_batch;
  * [off_r, off_r + n_r) of the batch ion arrays, off_r = n_0 + ... + n_{r-1}. */
 int discos_batch_create(const discos_replica* reps, int32_t count, double h,
                         const discos_params* p, discos_batch** out);
+/* Releases the batch as discos_destroy does a context (DISCOS_E_HIP if the runtime
+ * reported an error on the way, everything released regardless). */
 int discos_batch_destroy(discos_batch* b);
 
 /* One dry step of every channel.  pos [3][N], q [N], id [N], species [N] (DEVICE,

@@ -175,7 +175,10 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     if (!c) return DISCOS_E_HIP;
     c->grid = *grid;
     c->n_max = n_max;
-    hipGetDevice(&c->device);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return DISCOS_E_HIP;
+    }
     discos::GridDev& g = c->gd;
     g.nx = grid->nx;
     g.ny = grid->ny;
@@ -252,7 +255,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         }
         if (hipMemcpy(pass == 0 ? c->tw_x : c->tw_y, tw.data(), (N / 2) * sizeof(double2),
                       hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(c->pool);
+            (void)hipFree(c->pool);
             delete c;
             return DISCOS_E_HIP;
         }
@@ -260,7 +263,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     // flags, and the bin counts (the scan that reads them clears them again)
     if (hipMemset(c->flags, 0, 64 * sizeof(int)) != hipSuccess ||
         hipMemset(c->bin_count, 0, c->nbins * sizeof(int)) != hipSuccess) {
-        hipFree(c->pool);
+        (void)hipFree(c->pool);
         delete c;
         return DISCOS_E_HIP;
     }
@@ -278,7 +281,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         hb += carve_bytes(4 * (DISCOS_HY_MAXSP + 1), sizeof(double));        // kernel table
         void* hp = nullptr;
         if (hipMalloc(&hp, hb) != hipSuccess) {
-            hipFree(c->pool);
+            (void)hipFree(c->pool);
             delete c;
             return DISCOS_E_HIP;
         }
@@ -297,8 +300,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
         // mode factorisation of this grid
         if (hipMemset(c->hy_tab, 0, 4 * (DISCOS_HY_MAXSP + 1) * sizeof(double)) != hipSuccess ||
             discos::stokes_factor(c, nullptr) != DISCOS_OK || hipDeviceSynchronize() != hipSuccess) {
-            hipFree(hp);
-            hipFree(c->pool);
+            (void)hipFree(hp);
+            (void)hipFree(c->pool);
             delete c;
             return DISCOS_E_HIP;
         }
@@ -323,15 +326,17 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
 
 int discos_destroy(discos_ctx* c) {
     if (!c) return DISCOS_E_ARG;
-    hipDeviceSynchronize();
+    // everything is released even if the device reports an error on the way
+    bool ok = hipDeviceSynchronize() == hipSuccess;
     if (c->ev) {
-        for (size_t k = 0; k < (size_t)PROF_MAX * (DISCOS_NSTAGE + 1); ++k) hipEventDestroy(c->ev[k]);
+        for (size_t k = 0; k < (size_t)PROF_MAX * (DISCOS_NSTAGE + 1); ++k)
+            ok = (hipEventDestroy(c->ev[k]) == hipSuccess) && ok;
         delete[] c->ev;
     }
-    hipFree(c->pool);
-    if (c->hydro) hipFree(c->hpool);
+    ok = (hipFree(c->pool) == hipSuccess) && ok;
+    if (c->hydro) ok = (hipFree(c->hpool) == hipSuccess) && ok;
     delete c;
-    return DISCOS_OK;
+    return ok ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 int discos_spread(discos_ctx* c, int op, int64_t n, const double* pos, const double* w,
@@ -684,7 +689,8 @@ int discos_check(discos_ctx* c) {
     int f = 0;
     if (hipMemcpy(&f, c->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DISCOS_E_HIP, "flag read failed");
-    if (f) hipMemset(c->flags, 0, sizeof(int));
+    if (f && hipMemset(c->flags, 0, sizeof(int)) != hipSuccess)
+        return fail(c, DISCOS_E_HIP, "flag reset failed");
     if (f & DISCOS_FLAG_NONFINITE) return fail(c, DISCOS_E_NONFINITE, "non-finite position");
     if (f & DISCOS_FLAG_BAD_SPECIES) return fail(c, DISCOS_E_ARG, "species index out of range");
     if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(c, DISCOS_E_NOT_NEUTRAL, "system not neutral");

@@ -43,15 +43,18 @@ int tiles_of(const discos_replica& r, int tx, int ty, int tz) {
     return (r.nx / std::min(tx, r.nx)) * (r.ny / std::min(ty, r.ny)) * ((r.nz + tz - 1) / tz);
 }
 
-void destroy(discos_batch* b) {
-    if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->ev_in) hipEventDestroy(b->ev_in);
-    if (b->ev_out) hipEventDestroy(b->ev_out);
-    if (b->own) hipStreamDestroy(b->own);
-    if (b->pool) hipFree(b->pool);
+// Releases everything; false if the runtime reported an error on the way.
+bool destroy(discos_batch* b) {
+    if (!b) return true;
+    bool ok = true;
+    if (b->exec) ok = (hipGraphExecDestroy(b->exec) == hipSuccess) && ok;
+    if (b->graph) ok = (hipGraphDestroy(b->graph) == hipSuccess) && ok;
+    if (b->ev_in) ok = (hipEventDestroy(b->ev_in) == hipSuccess) && ok;
+    if (b->ev_out) ok = (hipEventDestroy(b->ev_out) == hipSuccess) && ok;
+    if (b->own) ok = (hipStreamDestroy(b->own) == hipSuccess) && ok;
+    if (b->pool) ok = (hipFree(b->pool) == hipSuccess) && ok;
     delete b;
+    return ok;
 }
 
 int run_step(discos_batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s) {
@@ -110,9 +113,14 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->cfg = {16, 0, 16, 0, 256};
     b->next_step = ~uint64_t(0);
     int dev = 0;
-    hipGetDevice(&dev);
-    b->ncu = 256;
-    hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess) {
+        destroy(b);
+        return DISCOS_E_HIP;
+    }
+    // the compute-unit count only sizes the tuning candidates: 256 if it cannot be read
+    if (hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        b->ncu <= 0)
+        b->ncu = 256;
 
     // ions and bins in channel order
     b->ion_off.assign(count + 1, 0);
@@ -362,9 +370,8 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
 
 int discos_batch_destroy(discos_batch* b) {
     if (!b) return DISCOS_E_ARG;
-    hipDeviceSynchronize();
-    destroy(b);
-    return DISCOS_OK;
+    const bool synced = hipDeviceSynchronize() == hipSuccess;
+    return destroy(b) && synced ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int32_t* species,
@@ -385,11 +392,11 @@ int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int3
                       args[2] == b->graph_args[2] && args[3] == b->graph_args[3];
     if (!same) {
         if (b->exec) {
-            hipGraphExecDestroy(b->exec);
+            (void)hipGraphExecDestroy(b->exec);
             b->exec = nullptr;
         }
         if (b->graph) {
-            hipGraphDestroy(b->graph);
+            (void)hipGraphDestroy(b->graph);
             b->graph = nullptr;
         }
         if (hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -398,7 +405,7 @@ int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int3
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->own, &g);
         if (rc || e != hipSuccess || !g) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return fail(b, DISCOS_E_HIP, "graph capture failed");
         }
         b->graph = g;
@@ -430,19 +437,20 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(b, DISCOS_E_HIP, "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(b, DISCOS_E_HIP, "event create");
     }
     const int reps = 3;
+    bool timing_ok = true;  // a failed event call times a candidate as never best
     auto timed = [&](auto&& fn) -> float {
         fn();  // warm
-        hipEventRecord(e0, s);
+        bool ok = hipEventRecord(e0, s) == hipSuccess;
         for (int k = 0; k < reps; ++k) fn();
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
-        return ms;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        timing_ok = timing_ok && ok;
+        return ok ? ms : 1e30f;
     };
     int rc = discos::batch_cell_list(b, pos, q, const_cast<int*>(id), const_cast<int*>(species), s);
     const int blocks[3] = {0, 4 * b->ncu, 8 * b->ncu};
@@ -490,15 +498,15 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         }
     }
     b->cfg = c;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     // a captured graph holds the previous launch shapes
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     if (cfg_out) {
@@ -508,7 +516,8 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         cfg_out[3] = c.interp_blocks;
         cfg_out[4] = c.ion_block;
     }
-    if (rc || hipGetLastError() != hipSuccess) return fail(b, DISCOS_E_HIP, "tuning launch failed");
+    if (rc || !timing_ok || hipGetLastError() != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "tuning launch failed");
     return DISCOS_OK;
 }
 
@@ -519,7 +528,8 @@ int discos_batch_check(discos_batch* b) {
     int f = 0;
     if (hipMemcpy(&f, b->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(b, DISCOS_E_HIP, "flag read failed");
-    if (f) hipMemset(b->flags, 0, sizeof(int));
+    if (f && hipMemset(b->flags, 0, sizeof(int)) != hipSuccess)
+        return fail(b, DISCOS_E_HIP, "flag reset failed");
     if (f & DISCOS_FLAG_NONFINITE) return fail(b, DISCOS_E_NONFINITE, "non-finite position");
     if (f & DISCOS_FLAG_BAD_SPECIES) return fail(b, DISCOS_E_ARG, "species index out of range");
     if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(b, DISCOS_E_NOT_NEUTRAL, "channel not neutral");

@@ -236,9 +236,14 @@ class Context:
         self.n_max = int(n_max)
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().discos_destroy(self.handle)
+        """Release the context (waits for the device).  Raises DiscosError if the runtime
+        reported an error on the way; the context is released regardless."""
+        h = getattr(self, "handle", None)
+        if h:
             self.handle = None
+            rc = lib().discos_destroy(h)
+            if rc != OK:
+                raise DiscosError(rc, "device error while releasing the context")
 
     def __del__(self):
         try:
@@ -440,9 +445,13 @@ class Batch:
         self.handle = h_
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().discos_batch_destroy(self.handle)
+        """Release the batch (waits for the device); raises as Context.close does."""
+        h = getattr(self, "handle", None)
+        if h:
             self.handle = None
+            rc = lib().discos_batch_destroy(h)
+            if rc != OK:
+                raise DiscosError(rc, "device error while releasing the batch")
 
     def __del__(self):
         try:
