@@ -194,6 +194,39 @@ def test_near_field(bc, lj):
     assert rel_l2((out - F0)[:, keep], ref[:, keep]) < 1e-12
 
 
+@pytest.mark.parametrize("psi,h,lj_sigma", [
+    (1.5, 1.0, None),   # search radius 1 bin (bins of 2 cells)
+    (2.0, 1.0, None),   # 1 bin exactly
+    (4.5, 1.0, None),   # 3 bins (the LDS copy of the P3M table reaches psi = 5 h)
+    (2.4, 0.5, None),   # 3 bins on a finer grid (psi = 4.8 h)
+    (4.0, 1.0, 2.0),    # LJ range 5 h beyond psi: 3 bins, LJ pairs past the cutoff
+])
+def test_near_field_search_radii(psi, h, lj_sigma):
+    """The list pass for every search radius it is built for (1 to 3 bins), with ions on
+    and near both walls, both wall images, and periodic neighbours across the seams."""
+    nx, ny, nz, n = 32, 32, 20, 2000
+    bc = (D, N)
+    log(f"near_field radii psi={psi} h={h} lj_sigma={lj_sigma}")
+    pos, q = _wall_ions(nx, ny, nz, n, seed=13, h=h)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    species = np.where(q > 0, 0, 1).astype(np.int32)
+    p = _params(bc, nx, ny)
+    p["psi"] = psi
+    if lj_sigma is not None:
+        p.update(lj_on=True, lj_sigma=np.full((2, 2), lj_sigma), lj_xi=np.full((2, 2), 0.3),
+                 lj_cut_factor=2.5)
+    grid = es.Grid(nx, ny, nz, h)
+    ref = es.near_field(grid, pos, q, EPS, psi, p["p3m_table"], p["p3m_dr"], bc)
+    ref[2] += shortrange.wall_force(pos[2], grid.L[2], p["wall_sigma"], p["wall_xi"], p["wall_cut"])
+    if lj_sigma is not None:
+        ref += shortrange.lj_pair_forces(grid.L, pos, species, p["lj_sigma"], p["lj_xi"], 2.5)
+    keep = np.all(np.isfinite(ref), axis=0)
+    ctx = _ctx(nx, ny, nz, n, h=h)
+    out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p), species=dev(species)))
+    ctx.check()
+    assert rel_l2(out[:, keep], ref[:, keep]) < 1e-12
+
+
 def _step_case(name, steps_checked=1, sample=None, seed_shift=0):
     w = workloads.WORKLOADS[name]
     p = workloads.make_params(w)
