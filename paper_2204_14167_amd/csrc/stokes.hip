@@ -156,6 +156,108 @@ __device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, in
     }
 }
 
+// Window weights of one axis at s (cells): the 4-point Peskin kernel (KM = 0) or the
+// table kernel kr over 2 KM nodes; nodes outside the tile (lxs >= tn) get 0 for KM > 0.
+template <int KM>
+__device__ __forceinline__ void face_axis(double s, int i0, const double* kr, const int* lxs, int tn,
+                                          double* wt) {
+    if constexpr (KM == 0) {
+        int unused;
+        peskin4(s, unused, wt);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 2 * KM; ++a)
+            wt[a] = lxs[a] < tn ? hy_weight(s - (double)(i0 + a), kr[0], kr[1], kr[2], kr[3]) : 0.0;
+    }
+}
+
+// The force deposit v0 phi(x - node) and the random finite difference
+// v [phi(x + d - node) - phi(x - d - node)] of one ion in one pass, one atomic per node:
+// possible when the three kernel centres' windows start at the same node on every axis
+// (the shift d is far below a cell, so nearly always).  Returns false, depositing
+// nothing, otherwise.  Folds as deposit_face.
+template <int COMP, int KM>
+__device__ __forceinline__ bool deposit_face_rfd(const GridDev& g, double* acc, int x0, int y0,
+                                                 int z0, int tx, int ty, int tz, double px,
+                                                 double py, double pz, double hx, double hy,
+                                                 double hz, double v0, double v, const double* kr) {
+    constexpr int NW = KM == 0 ? 4 : 2 * KM;
+    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
+    const double sx = px * g.inv_h - ox, sy = py * g.inv_h - oy, sz = pz * g.inv_h - oz;
+    const double sxp = (px + hx) * g.inv_h - ox, syp = (py + hy) * g.inv_h - oy,
+                 szp = (pz + hz) * g.inv_h - oz;
+    const double sxm = (px - hx) * g.inv_h - ox, sym = (py - hy) * g.inv_h - oy,
+                 szm = (pz - hz) * g.inv_h - oz;
+    const double fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    if (floor(sxp) != fx || floor(sxm) != fx || floor(syp) != fy || floor(sym) != fy ||
+        floor(szp) != fz || floor(szm) != fz)
+        return false;
+    const int off = KM == 0 ? -1 : 1 - KM;  // first node relative to floor(s)
+    const int ix0 = (int)fx + off, iy0 = (int)fy + off, iz0 = (int)fz + off;
+    int lxs[NW], lys[NW];
+#pragma unroll
+    for (int a = 0; a < NW; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+#pragma unroll
+    for (int b = 0; b < NW; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+    double wx0[NW], wxp[NW], wxm[NW], wy0[NW], wyp[NW], wym[NW];
+    face_axis<KM>(sx, ix0, kr, lxs, tx, wx0);
+    face_axis<KM>(sxp, ix0, kr, lxs, tx, wxp);
+    face_axis<KM>(sxm, ix0, kr, lxs, tx, wxm);
+    face_axis<KM>(sy, iy0, kr, lys, ty, wy0);
+    face_axis<KM>(syp, iy0, kr, lys, ty, wyp);
+    face_axis<KM>(sym, iy0, kr, lys, ty, wym);
+    double wz0[KM == 0 ? 4 : 1], wzp[KM == 0 ? 4 : 1], wzm[KM == 0 ? 4 : 1];
+    if constexpr (KM == 0) {
+        int unused;
+        peskin4(sz, unused, wz0);
+        peskin4(szp, unused, wzp);
+        peskin4(szm, unused, wzm);
+    }
+    for (int c = 0; c < NW; ++c) {
+        int kz = iz0 + c;
+        double sgn = 1.0;
+        if (COMP == 2) {
+            if (kz < 0) { kz = -kz; sgn = -1.0; }
+            else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
+            if (kz == 0 || kz == g.nz) continue;
+        } else {
+            if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
+            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
+        }
+        const int lz = kz - z0;
+        if (lz < 0 || lz >= tz) continue;
+        double z0c, zpc, zmc;
+        if constexpr (KM == 0) {
+            z0c = wz0[c];
+            zpc = wzp[c];
+            zmc = wzm[c];
+        } else {
+            const double nz = (double)(iz0 + c);
+            z0c = hy_weight(sz - nz, kr[0], kr[1], kr[2], kr[3]);
+            zpc = hy_weight(szp - nz, kr[0], kr[1], kr[2], kr[3]);
+            zmc = hy_weight(szm - nz, kr[0], kr[1], kr[2], kr[3]);
+            if (z0c == 0.0 && zpc == 0.0 && zmc == 0.0) continue;
+        }
+        z0c *= sgn * v0;
+        zpc *= sgn * v;
+        zmc *= sgn * v;
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            if (lys[b] >= ty) continue;
+            const double y0c = z0c * wy0[b], ypc = zpc * wyp[b], ymc = zmc * wym[b];
+            if (KM != 0 && y0c == 0.0 && ypc == 0.0 && ymc == 0.0) continue;
+#pragma unroll
+            for (int a = 0; a < NW; ++a) {
+                if (lxs[a] >= tx) continue;
+                if (KM != 0 && wx0[a] == 0.0 && wxp[a] == 0.0 && wxm[a] == 0.0) continue;
+                atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]],
+                          y0c * wx0[a] + (ypc * wxp[a] - ymc * wxm[a]));
+            }
+        }
+    }
+    return true;
+}
+
 // S^hy F on one face grid; with rfd.scale != 0 every ion also deposits the random
 // finite difference (kT / delta) [phi(x + delta/2 W) - phi(x - delta/2 W)] W_COMP of
 // the thermal forcing.  The shifts are below half a cell: along an axis whose nodes
@@ -204,15 +306,21 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
             if constexpr (KM == 0) deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v);
             else deposit_face_k<COMP, KM>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v, kr);
         };
-        dep(a4.x, a4.y, a4.z, fw[i] * inv_h3);
-        if (rfd.scale != 0.0) {
-            const double w0 = rfd.w[i], w1 = rfd.w[i + rfd.wstride], w2 = rfd.w[i + 2 * rfd.wstride];
-            const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
-            const double v = rfd.scale * wc * inv_h3;
-            const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
-            dep(a4.x + hx, a4.y + hy, a4.z + hz, v);
-            dep(a4.x - hx, a4.y - hy, a4.z - hz, -v);
+        const double v0 = fw[i] * inv_h3;
+        if (rfd.scale == 0.0) {
+            dep(a4.x, a4.y, a4.z, v0);
+            continue;
         }
+        const double w0 = rfd.w[i], w1 = rfd.w[i + rfd.wstride], w2 = rfd.w[i + 2 * rfd.wstride];
+        const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
+        const double v = rfd.scale * wc * inv_h3;
+        const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
+        if (deposit_face_rfd<COMP, KM>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, hx, hy,
+                                       hz, v0, v, kr))
+            continue;
+        dep(a4.x, a4.y, a4.z, v0);
+        dep(a4.x + hx, a4.y + hy, a4.z + hz, v);
+        dep(a4.x - hx, a4.y - hy, a4.z - hz, -v);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
