@@ -84,19 +84,29 @@ def committed_block(path):
     return data if data.get("source_sha256") == kernel_source_hash() else None
 
 
+def kernel_entry(data, kernel):
+    """The entry of `kernel` in a profile's JSON block: by exact name, else the one
+    instantiation of that template (name<...>)."""
+    if data is None:
+        return None
+    ks = data.get("kernels", {})
+    if kernel in ks:
+        return ks[kernel]
+    hits = [v for k, v in ks.items() if k.split("<", 1)[0] == kernel]
+    return hits[0] if len(hits) == 1 else None
+
+
 def committed_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE +
     WRITE_SIZE, copy-calibrated), or None if absent or taken on other sources."""
-    data = committed_block(TRAFFIC_FILE)
-    k = None if data is None else data.get("kernels", {}).get(kernel)
+    k = kernel_entry(committed_block(TRAFFIC_FILE), kernel)
     return None if k is None else float(k["hbm_bytes_per_launch"])
 
 
 def committed_issue(kernel):
     """Share of the chip's VALU issue cycles `kernel` fills (SQ instruction counters over
     its kernel-trace duration), or None if absent or taken on other sources."""
-    data = committed_block(ISSUE_FILE)
-    k = None if data is None else data.get("kernels", {}).get(kernel)
+    k = kernel_entry(committed_block(ISSUE_FILE), kernel)
     return None if k is None else k["valu_issue_share"]
 
 

@@ -25,9 +25,10 @@ SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
 
 
 def _short(name):
-    """Kernel name without namespace, return type, template and call arguments."""
+    """Kernel name without namespace, return type and call arguments (template arguments
+    kept, so that instantiations stay apart)."""
     name = re.sub(r"\(.*", "", name).replace("discos::", "")
-    return re.sub(r"<.*?>", "", re.sub(r"^void ", "", name))
+    return re.sub(r"^void ", "", name)
 
 
 def kernel_rows(db):

@@ -1,5 +1,5 @@
 """Host logic of the profile summaries on a synthetic rocpd database: kernel names lose
-namespace, return type and template arguments; the issue share is VALU instructions x
+namespace, return type and call arguments; the issue share is VALU instructions x
 4 cycles over 1024 SIMDs x 2.4 GHz x the mean kernel-trace duration; the copy
 calibration scales the traffic counters."""
 import json
@@ -22,7 +22,7 @@ def _db(path, kernels, counters):
 
 
 def test_short_names():
-    assert rs._short("void discos::near_list_kernel<2>(discos::GridDev, int)") == "near_list_kernel"
+    assert rs._short("void discos::near_list_kernel<2>(discos::GridDev, int)") == "near_list_kernel<2>"
     assert rs._short("discos::spread_charge_kernel(discos::GridDev)") == "spread_charge_kernel"
 
 
@@ -35,7 +35,7 @@ def test_issue_share(tmp_path, capsys):
     rs.main(["issue", sq, kt, "--command", "a", "--command", "b", "--source-sha256", "x"])
     out = capsys.readouterr().out
     data = json.loads(out.split("```json", 1)[1].split("```", 1)[0])
-    k = data["kernels"]["near_list_kernel"]
+    k = data["kernels"]["near_list_kernel<2>"]
     assert k["valu_per_wave"] == 8000.0
     assert k["valu_issue_share"] == pytest.approx(round(valu * 4 / (1024 * 2.4e9 * 250e-6), 3))
     assert data["source_sha256"] == "x"
