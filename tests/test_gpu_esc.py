@@ -183,6 +183,32 @@ def _wet(table, rfd, name="dirichlet_32x32x32_n256", edge=False, step=0):
     assert r < TOL
 
 
+def test_wet_step_rfd_paper_kernels_eo_128cube():
+    """The full-size channel (128^3, 262,144 ions, charged walls) with the paper's pair and
+    the random finite difference: one GPU step against the oracle's step at 1,500 sampled
+    ions, stored by tests/golden/make_esc_wet_eo128.py (the oracle takes minutes here)."""
+    from paper_2204_14167_amd import discos
+    from tests.golden import make_esc_wet_eo128 as gold
+    w, p, (pos, q, ids, species), targets, delta = gold.case()
+    data = np.loadtxt(gold.OUT)
+    want = data[:, 0].astype(np.int64)
+    ref = data[:, 1:].T
+    assert np.array_equal(want, ids[targets])
+    grid = es.Grid(w.nx, w.ny, w.nz, w.h)
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, hydro=True)
+    ctx.set_hydro_kernel(gold.KERNELS)
+    dp = ctx.params(p)
+    args = (dev(pos), dev(q), dev(ids), dev(species))
+    log("esc wet eo128: GPU")
+    ctx.step(*args, dp, gold.STEP, mode=discos.STEP_WET | discos.STEP_RFD)
+    ctx.check()
+    got = by_id(host(args[0]), host(args[2]), want)
+    old = pos[:, targets]
+    r = np.linalg.norm(min_image(got - ref, grid.L)) / np.linalg.norm(min_image(ref - old, grid.L))
+    log(f"esc wet eo128 rel={r:.3e}")
+    assert r < TOL
+
+
 def test_wet_step_paper_kernels():
     _wet(KERNELS["paper"], rfd=False)
 
