@@ -227,7 +227,7 @@ def test_near_field_search_radii(psi, h, lj_sigma):
     assert rel_l2(out[:, keep], ref[:, keep]) < 1e-12
 
 
-def _step_case(name, steps_checked=1, sample=None, seed_shift=0):
+def _step_case(name, steps_checked=1, sample=None, seed_shift=0, near="brute"):
     w = workloads.WORKLOADS[name]
     p = workloads.make_params(w)
     pos, q, ids, species = workloads.make_ions(w)
@@ -243,7 +243,7 @@ def _step_case(name, steps_checked=1, sample=None, seed_shift=0):
         cur_pos, cur_q, cur_ids, cur_sp = cur_pos[:, order], cur_q[order], cur_ids[order], cur_sp[order]
         targets = None if sample is None else np.sort(rng.choice(w.n, sample, replace=False))
         ref, _, _ = dynamics.dry_step(grid, cur_pos, cur_q, cur_sp, cur_ids, p, s + seed_shift,
-                                      targets=targets)
+                                      targets=targets, near=near)
         ctx.step(dpos, dq, dids, dsp, dp, s + seed_shift)
         ctx.check()
         got_all, got_ids = host(dpos), host(dids)
@@ -270,6 +270,13 @@ def test_step_dielectric_32cube():
 
 def test_step_dielectric_128x128x64():
     _step_case("dielectric_128x128x64_n65536", steps_checked=2, sample=400)
+
+
+def test_step_headline_1m_sampled():
+    """The timed workload itself: 1,048,576 ions on 256x256x128 with dielectric walls and
+    E_x = 0.1, one step in the library's launch configuration, against the oracle at
+    1,500 sampled ions (the oracle's near field from its pair search; about 16 s)."""
+    _step_case("dielectric_256x256x128_n1048576", steps_checked=1, sample=1500, near="pairs")
 
 
 def test_near_field_dense_cluster():
