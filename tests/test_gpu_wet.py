@@ -16,7 +16,8 @@ def _ctx(w):
     return discos.Context(w.nx, w.ny, w.nz, w.h, w.n, hydro=True)
 
 
-def _wet_case(name, steps_checked=1, sample=None, rfd=False, pure_wet=False, seed_shift=0):
+def _wet_case(name, steps_checked=1, sample=None, rfd=False, pure_wet=False, seed_shift=0,
+              slip=None):
     from paper_2204_14167_amd import discos
     w = workloads.WORKLOADS[name]
     p = workloads.make_params(w)
@@ -24,6 +25,8 @@ def _wet_case(name, steps_checked=1, sample=None, rfd=False, pure_wet=False, see
         p["radius"] = np.array([np.inf, np.inf])
     delta = 1e-4 * w.h if rfd else 0.0
     p["rfd_delta"] = delta
+    if slip is not None:
+        p["slip"] = slip
     pos, q, ids, species = workloads.make_ions(w)
     grid = es.Grid(w.nx, w.ny, w.nz, w.h)
     ctx = _ctx(w)
@@ -74,6 +77,13 @@ def test_wet_step_rfd_dielectric_32cube():
 
 def test_wet_step_electro_osmosis_128cube():
     _wet_case("eo_stokes_128x128x128_n262144", steps_checked=1, sample=1500)
+
+
+def test_wet_step_rfd_two_slip_walls_128cube():
+    """The timed slip-wall variant: 262,144 ions on 128^3 between two slip walls, with the
+    random finite difference, at 1,500 sampled ions."""
+    _wet_case("eo_stokes_128x128x128_n262144", steps_checked=1, sample=1500, rfd=True,
+              slip=(True, True), seed_shift=7)
 
 
 def test_wet_step_rejections():
