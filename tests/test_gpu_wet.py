@@ -79,6 +79,12 @@ def test_wet_step_electro_osmosis_128cube():
     _wet_case("eo_stokes_128x128x128_n262144", steps_checked=1, sample=1500)
 
 
+def test_wet_step_rfd_electro_osmosis_128cube():
+    """The timed no-slip variant with the random finite difference, 1,500 sampled ions."""
+    _wet_case("eo_stokes_128x128x128_n262144", steps_checked=1, sample=1500, rfd=True,
+              seed_shift=3)
+
+
 def test_wet_step_rfd_two_slip_walls_128cube():
     """The timed slip-wall variant: 262,144 ions on 128^3 between two slip walls, with the
     random finite difference, at 1,500 sampled ions."""
