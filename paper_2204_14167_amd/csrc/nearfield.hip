@@ -458,8 +458,11 @@ __device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
     if (cnt <= P.cap) {
         const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
         const int4* chunks = reinterpret_cast<const int4*>(list);
+        // the next chunk's entries load while this chunk's pairs are evaluated
+        int4 chn = cnt > 0 ? chunks[i] : make_int4(0, 0, 0, 0);
         for (int k4 = 0; k4 < cnt; k4 += 4) {
-            const int4 ch = chunks[(size_t)(k4 >> 2) * n + i];
+            const int4 ch = chn;
+            if (k4 + 4 < cnt) chn = chunks[(size_t)((k4 >> 2) + 1) * n + i];
             const int m4 = min(4, cnt - k4);
             // the four gathers are issued together (unused slots read the ion itself)
             double4 ob[4];
