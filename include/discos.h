@@ -243,6 +243,23 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
                       void* stream);
 
 /*
+ * The table g(rho) that the near-field correction subtracts (F^P of eq LC, Sec. II.B.1):
+ * the mean radial field between two unit charges through the grid operators, in units
+ * of 1 / (4 pi eps h^2), measured as the paper describes.  A unit charge at src[p] is
+ * spread with the 4-point Peskin kernel (eq peskin1d) onto a triply periodic n^3 box of
+ * unit cells; -eps lap_h phi = rho (7-point Laplacian, eps = 1 / (4 pi), zero mean) is
+ * solved by FFT; E = -grad_h phi on the faces is interpolated at src[p] + rho_k u; the
+ * field rho_k / (3 eps n^3) of the neutralising background is removed and the radial
+ * component averaged over the nplace placements.  rho_k = k drho, k < nrho; u is
+ * dir[p][.][k] normalised.  src [nplace][3] in [0, n), dir [nplace][3][nrho], g [nrho]:
+ * host arrays owned by the caller; g[0] = 0.  Host computation (threads, no GPU work,
+ * no context).  n a power of two in [8, 256].  Errors: DISCOS_E_ARG.  The result is the
+ * p3m_table of discos_params (p3m_dr = drho) for the Peskin kernel.
+ */
+int discos_p3m_table(int n, int nplace, int nrho, double drho, const double* src,
+                     const double* dir, double* g);
+
+/*
  * One time step (Sec. II.D).  mode DISCOS_STEP_DRY: stages 1-2 (spread, Poisson,
  * interpolation, P3M near-field, wall and applied forces) and the dry update of
  * eq ions3 / eq step2 with the wall-modified diffusion tensor D Gamma(z) of

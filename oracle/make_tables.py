@@ -25,17 +25,19 @@ import os
 import numpy as np
 from scipy.optimize import least_squares
 
+from paper_2204_14167_amd import workloads
+
 from . import electrostatics as es
 from . import mobility
 
 OUT_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_2204_14167_amd", "data")
 
-RHO_MAX = 6.0
-DRHO = 1.0 / 64.0
-N_BOX = 64
-PLACEMENTS = 400
-SEED = 20414167
+RHO_MAX = workloads.P3M_RHO_MAX
+DRHO = workloads.P3M_DRHO
+N_BOX = workloads.P3M_BOX
+PLACEMENTS = workloads.P3M_PLACEMENTS
+SEED = workloads.P3M_SEED
 
 
 def p3m_table():
@@ -45,12 +47,13 @@ def p3m_table():
     V = float(np.prod(L))
     rho = np.arange(0, int(round(RHO_MAX / DRHO)) + 1) * DRHO
     acc = np.zeros_like(rho)
-    rng = np.random.default_rng(SEED)
-    for _ in range(PLACEMENTS):
-        src = rng.uniform(0.0, L[0], size=(3, 1))
+    # the seeded placements (charge position, directions) are inputs
+    srcs, dirs = workloads.p3m_placements()
+    for k in range(PLACEMENTS):
+        src = srcs[k][:, None]
         dens = es.spread_periodic(grid, src, np.array([1.0]))
         phi = es.periodic_poisson(grid, eps, dens)
-        u = rng.normal(size=(3, len(rho)))
+        u = dirs[k].copy()
         u /= np.linalg.norm(u, axis=0)
         tgt = np.mod(src + rho[None, :] * u, L[:, None])
         E = es.periodic_grid_field(grid, tgt, phi)

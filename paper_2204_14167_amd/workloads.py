@@ -73,6 +73,26 @@ def physical_params():
                 lj_on=False, radius=np.array([1.0, 1.0]))
 
 
+# Placements that define the grid pair-force table of the P3M correction: a unit charge
+# at a uniform position of a periodic box of P3M_BOX^3 unit cells, and normally
+# distributed directions (normalised by the table builders) for the separations
+# 0, P3M_DRHO, ..., P3M_RHO_MAX cells, P3M_PLACEMENTS times, drawn in that order from one
+# seeded stream.
+P3M_BOX, P3M_DRHO, P3M_RHO_MAX, P3M_PLACEMENTS, P3M_SEED = 64, 1.0 / 64.0, 6.0, 400, 20414167
+
+
+def p3m_placements():
+    """(src [P, 3] charge positions, dirs [P, 3, nrho] unnormalised directions)."""
+    nrho = int(round(P3M_RHO_MAX / P3M_DRHO)) + 1
+    rng = np.random.default_rng(P3M_SEED)
+    src = np.empty((P3M_PLACEMENTS, 3))
+    dirs = np.empty((P3M_PLACEMENTS, 3, nrho))
+    for k in range(P3M_PLACEMENTS):
+        src[k] = rng.uniform(0.0, float(P3M_BOX), size=(3, 1))[:, 0]
+        dirs[k] = rng.normal(size=(3, nrho))
+    return src, dirs
+
+
 def load_p3m_table():
     """(g, dr): tabulated free-space grid pair force of the 4-point Peskin kernel,
     g(i dr) for rho = r / h, written by the oracle's table tool."""
