@@ -431,8 +431,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the slit-channel step is measured on a single "
-              "MI355X (multi-GPU sharding is a design, not part of this build).", file=sys.stderr)
+        print("bench.py measures one GPU only: the slit-channel step runs on a single MI355X "
+              "and is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch
