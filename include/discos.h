@@ -45,7 +45,7 @@ extern "C" {
 #define DISCOS_E_OUT_OF_DOMAIN (-4) /* sticky: an ion had z outside [0, Lz] or |x|, |y| huge */
 #define DISCOS_E_NOT_NEUTRAL (-5)  /* sticky: both walls Neumann and the system is charged */
 #define DISCOS_E_NONFINITE (-6)    /* sticky: a non-finite position or force */
-#define DISCOS_E_CAPACITY (-7)     /* n larger than the context's n_max */
+#define DISCOS_E_CAPACITY (-7)     /* n larger than the context's n_max; host memory exhausted */
 
 /* ---- wall boundary conditions for the potential (Sec. II.B.1) --------------- */
 #define DISCOS_BC_DIRICHLET 0 /* fixed potential phi_b (eq esbc1) */
@@ -253,7 +253,8 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
  * component averaged over the nplace placements.  rho_k = k drho, k < nrho; u is
  * dir[p][.][k] normalised.  src [nplace][3] in [0, n), dir [nplace][3][nrho], g [nrho]:
  * host arrays owned by the caller; g[0] = 0.  Host computation (threads, no GPU work,
- * no context).  n a power of two in [8, 256].  Errors: DISCOS_E_ARG.  The result is the
+ * no context; threads hold at most about 1 GiB of boxes).  n a power of two in
+ * [8, 256].  Errors: DISCOS_E_ARG, DISCOS_E_CAPACITY (host memory).  The result is the
  * p3m_table of discos_params (p3m_dr = drho) for the Peskin kernel.
  */
 int discos_p3m_table(int n, int nplace, int nrho, double drho, const double* src,

@@ -6,6 +6,8 @@
 // face differences E = -grad_h phi are interpolated back at distance rho along a given
 // direction, the neutralising background's field rho / (3 eps V) is removed, and the
 // radial component is averaged over the placements.  Host code, run once per table.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <thread>
@@ -137,39 +139,62 @@ extern "C" int discos_p3m_table(int n, int nplace, int nrho, double drho, const 
     if (n < 8 || n > 256 || (n & (n - 1)) || nplace < 1 || nrho < 1 || !(drho > 0.0) ||
         !std::isfinite(drho) || !src || !dir || !g)
         return DISCOS_E_ARG;
-    const size_t n2 = (size_t)n * n, n3 = n2 * n;
-    std::vector<cplx> tw(n / 2);
-    for (int k = 0; k < n / 2; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * k / n);
-    // 1 / lambda of the 7-point Laplacian per mode (h = 1); the mean mode is dropped
-    std::vector<double> inv_k2(n3);
-    std::vector<double> s2(n);
-    for (int k = 0; k < n; ++k) {
-        const double s = std::sin(M_PI * k / n);
-        s2[k] = 4.0 * s * s;
-    }
-    for (int z = 0; z < n; ++z)
-        for (int y = 0; y < n; ++y)
-            for (int x = 0; x < n; ++x) {
-                const double l = s2[z] + s2[y] + s2[x];
-                inv_k2[(size_t)z * n2 + (size_t)y * n + x] = l > 0.0 ? 1.0 / l : 0.0;
+    // no exception may leave this function: allocation failures become an error code
+    try {
+        const size_t n2 = (size_t)n * n, n3 = n2 * n;
+        std::vector<cplx> tw(n / 2);
+        for (int k = 0; k < n / 2; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * k / n);
+        // 1 / lambda of the 7-point Laplacian per mode (h = 1); the mean mode is dropped
+        std::vector<double> inv_k2(n3);
+        std::vector<double> s2(n);
+        for (int k = 0; k < n; ++k) {
+            const double s = std::sin(M_PI * k / n);
+            s2[k] = 4.0 * s * s;
+        }
+        for (int z = 0; z < n; ++z)
+            for (int y = 0; y < n; ++y)
+                for (int x = 0; x < n; ++x) {
+                    const double l = s2[z] + s2[y] + s2[x];
+                    inv_k2[(size_t)z * n2 + (size_t)y * n + x] = l > 0.0 ? 1.0 / l : 0.0;
+                }
+        std::vector<double> per((size_t)nplace * nrho);
+        // at most 16 threads, and at most about 1 GiB of boxes (24 bytes per cell each)
+        const unsigned hw = std::thread::hardware_concurrency();
+        size_t nt = std::min<size_t>(16, hw ? hw : 1);
+        nt = std::max<size_t>(1, std::min(nt, ((size_t)1 << 30) / (24 * n3)));
+        const int nthreads = (int)nt;
+        std::atomic<bool> failed{false};
+        auto work = [&](int t) {
+            try {
+                for (int p = t; p < nplace; p += nthreads)
+                    one_placement(n, nrho, drho, src + 3 * (size_t)p, dir + 3 * (size_t)p * nrho,
+                                  tw, inv_k2, &per[(size_t)p * nrho]);
+            } catch (...) {
+                failed = true;
             }
-    std::vector<double> per((size_t)nplace * nrho);
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int nthreads = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nthreads; ++t)
-        pool.emplace_back([&, t] {
-            for (int p = t; p < nplace; p += nthreads)
-                one_placement(n, nrho, drho, src + 3 * (size_t)p, dir + 3 * (size_t)p * nrho, tw,
-                              inv_k2, &per[(size_t)p * nrho]);
-        });
-    for (auto& th : pool) th.join();
-    // average in placement order, independent of the thread count
-    for (int k = 0; k < nrho; ++k) {
-        double acc = 0.0;
-        for (int p = 0; p < nplace; ++p) acc += per[(size_t)p * nrho + k];
-        g[k] = acc / nplace;
+        };
+        std::vector<std::thread> pool;
+        int started = 1;  // share 0 is the calling thread's
+        try {
+            for (int t = 1; t < nthreads; ++t) {
+                pool.emplace_back(work, t);
+                ++started;
+            }
+        } catch (...) {
+        }
+        work(0);
+        for (int t = started; t < nthreads; ++t) work(t);  // shares whose thread did not start
+        for (auto& th : pool) th.join();
+        if (failed) return DISCOS_E_CAPACITY;
+        // average in placement order, independent of the thread count
+        for (int k = 0; k < nrho; ++k) {
+            double acc = 0.0;
+            for (int p = 0; p < nplace; ++p) acc += per[(size_t)p * nrho + k];
+            g[k] = acc / nplace;
+        }
+        g[0] = 0.0;
+    } catch (...) {
+        return DISCOS_E_CAPACITY;
     }
-    g[0] = 0.0;
     return DISCOS_OK;
 }
