@@ -36,3 +36,14 @@ def test_library_table_rejects_bad_arguments():
         discos.p3m_table(16, 0.0, src, dirs)
     with pytest.raises(ValueError):
         discos.p3m_table(16, 0.25, src, np.ones((3, 3, 5)))
+
+
+def test_oracle_tool_reproduces_the_committed_table():
+    """The committed table is exactly what the oracle's tool writes from the seeded
+    placements (bitwise)."""
+    from oracle import make_tables
+    rho, g = make_tables.p3m_table()
+    ref, dr = workloads.load_p3m_table()
+    assert dr == make_tables.DRHO
+    assert np.array_equal(rho, np.arange(len(ref)) * dr)
+    assert np.array_equal(g, ref)
