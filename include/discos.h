@@ -73,7 +73,10 @@ typedef struct discos_params {
     /* P3M near-field correction (eqs coulomb, fullElectro, LC) */
     double psi;                 /* cutoff radius */
     const double* p3m_table;    /* device [p3m_len]: g(i p3m_dr), free-space grid pair force
-                                   in units of q_i q_j / (4 pi eps h^2), argument r / h */
+                                   in units of q_i q_j / (4 pi eps h^2), argument r / h: the
+                                   mean radial force between two unit charges through
+                                   S^es, the periodic Poisson solve and J^es, tabulated
+                                   offline as the paper describes (an input, like eps) */
     int32_t p3m_len;
     double p3m_dr;
     /* short-range forces (Sec. II.B.2) */
@@ -243,24 +246,6 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
                       void* stream);
 
 /*
- * The table g(rho) that the near-field correction subtracts (F^P of eq LC, Sec. II.B.1):
- * the mean radial field between two unit charges through the grid operators, in units
- * of 1 / (4 pi eps h^2), measured as the paper describes.  A unit charge at src[p] is
- * spread with the 4-point Peskin kernel (eq peskin1d) onto a triply periodic n^3 box of
- * unit cells; -eps lap_h phi = rho (7-point Laplacian, eps = 1 / (4 pi), zero mean) is
- * solved by FFT; E = -grad_h phi on the faces is interpolated at src[p] + rho_k u; the
- * field rho_k / (3 eps n^3) of the neutralising background is removed and the radial
- * component averaged over the nplace placements.  rho_k = k drho, k < nrho; u is
- * dir[p][.][k] normalised.  src [nplace][3] in [0, n), dir [nplace][3][nrho], g [nrho]:
- * host arrays owned by the caller; g[0] = 0.  Host computation (threads, no GPU work,
- * no context; threads hold at most about 1 GiB of boxes).  n a power of two in
- * [8, 256].  Errors: DISCOS_E_ARG, DISCOS_E_CAPACITY (host memory).  The result is the
- * p3m_table of discos_params (p3m_dr = drho) for the Peskin kernel.
- */
-int discos_p3m_table(int n, int nplace, int nrho, double drho, const double* src,
-                     const double* dir, double* g);
-
-/*
  * One time step (Sec. II.D).  mode DISCOS_STEP_DRY: stages 1-2 (spread, Poisson,
  * interpolation, P3M near-field, wall and applied forces) and the dry update of
  * eq ions3 / eq step2 with the wall-modified diffusion tensor D Gamma(z) of
@@ -392,7 +377,9 @@ int discos_profile_stages(discos_ctx* ctx, uint32_t stages);
 
 /* Synchronise the context's last stream and return (and clear) the sticky status:
  * DISCOS_E_NONFINITE, DISCOS_E_ARG (a species index outside [0, nspecies)),
- * DISCOS_E_NOT_NEUTRAL or DISCOS_E_OUT_OF_DOMAIN, in that order of precedence. */
+ * DISCOS_E_CAPACITY (a tile's candidate rows exceeded its buffer: results incomplete;
+ * the built tile shapes cannot reach it), DISCOS_E_NOT_NEUTRAL or
+ * DISCOS_E_OUT_OF_DOMAIN, in that order of precedence. */
 int discos_check(discos_ctx* ctx);
 /* Text of the last host-side error on this context (static storage, never NULL). */
 const char* discos_last_error(discos_ctx* ctx);

@@ -1,6 +1,6 @@
 """Offline generator of the two stored input tables (calls only the oracle).
 
-Writes into paper_2204_14167_amd/data/:
+Writes into workloads/data/ (the stored inputs that both sides read):
 
   p3m_g_peskin4.txt  The free-space grid pair force of the 4-point Peskin kernel
       (the F^P of eq LC, which the paper pre-tabulates as a function of the
@@ -25,13 +25,12 @@ import os
 import numpy as np
 from scipy.optimize import least_squares
 
-from paper_2204_14167_amd import workloads
+import workloads
 
 from . import electrostatics as es
 from . import mobility
 
-OUT_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2204_14167_amd", "data")
+OUT_DIR = workloads.DATA_DIR
 
 RHO_MAX = workloads.P3M_RHO_MAX
 DRHO = workloads.P3M_DRHO

@@ -137,7 +137,7 @@ static int nparts_for(int64_t n) {
 __global__ void __launch_bounds__(AS_THREADS)
 flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__ sxyzq,
                    const int* __restrict__ bin_start, const double* __restrict__ gvec,
-                   double* __restrict__ lam, double* __restrict__ bcg) {
+                   double* __restrict__ lam, double* __restrict__ bcg, int* __restrict__ flags) {
     // mu on the x-faces x0 .. x0 + tx of the tile (face F between cells F - 1 and F), then
     // lambda_phi(cell c) = mu(c) - mu(c + 1): the transpose of the face differences
     constexpr int FX = AS_T + 1;
@@ -153,7 +153,9 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
     const bool has_lo = z0 == 0, has_hi = z0 + tz == g.nz;
     for (int k = threadIdx.x; k < fx * ty * tz; k += blockDim.x) acc[k] = 0.0;
     for (int k = threadIdx.x; k < fx * ty; k += blockDim.x) glo[k] = ghi[k] = 0.0;
-    const int nr = tile_ranges<AS_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
+    static_assert(tile_rows_bound(AS_T, AS_TZ, 2, 2) <= AS_MAXR, "adjoint tile rows exceed AS_MAXR");
+    const int nr = tile_ranges<AS_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan,
+                                        flags);
     const int total = rpre[nr];
     const double gQ = gvec[1];
     const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
@@ -487,7 +489,8 @@ int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* ph
     const WallDev wl = wall_of(p);
     // lambda_phi -> c->rho, wall ghost part -> c->bcg
     dim3 ga(g.nx / std::min(AS_T, g.nx), g.ny / std::min(AS_T, g.ny), (g.nz + AS_TZ - 1) / AS_TZ);
-    flux_lambda_kernel<<<ga, AS_THREADS, 0, s>>>(g, wl, f, c->sxyzq, c->bin_start, gvec, c->rho, c->bcg);
+    flux_lambda_kernel<<<ga, AS_THREADS, 0, s>>>(g, wl, f, c->sxyzq, c->bin_start, gvec, c->rho, c->bcg,
+                                                 c->flags);
     // mu = A^+ lambda_phi -> c->phi
     int rc = solve_poisson(c, c->rho, p, c->phi, s, -1, 1);
     if (rc) return rc;

@@ -693,6 +693,7 @@ int discos_check(discos_ctx* c) {
         return fail(c, DISCOS_E_HIP, "flag reset failed");
     if (f & DISCOS_FLAG_NONFINITE) return fail(c, DISCOS_E_NONFINITE, "non-finite position");
     if (f & DISCOS_FLAG_BAD_SPECIES) return fail(c, DISCOS_E_ARG, "species index out of range");
+    if (f & DISCOS_FLAG_CAPACITY) return fail(c, DISCOS_E_CAPACITY, "tile candidate rows exceeded");
     if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(c, DISCOS_E_NOT_NEUTRAL, "system not neutral");
     if (f & DISCOS_FLAG_OUT_OF_DOMAIN) return fail(c, DISCOS_E_OUT_OF_DOMAIN, "ion outside channel");
     return DISCOS_OK;

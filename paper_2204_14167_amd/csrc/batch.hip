@@ -532,6 +532,7 @@ int discos_batch_check(discos_batch* b) {
         return fail(b, DISCOS_E_HIP, "flag reset failed");
     if (f & DISCOS_FLAG_NONFINITE) return fail(b, DISCOS_E_NONFINITE, "non-finite position");
     if (f & DISCOS_FLAG_BAD_SPECIES) return fail(b, DISCOS_E_ARG, "species index out of range");
+    if (f & DISCOS_FLAG_CAPACITY) return fail(b, DISCOS_E_CAPACITY, "tile candidate rows exceeded");
     if (f & DISCOS_FLAG_NOT_NEUTRAL) return fail(b, DISCOS_E_NOT_NEUTRAL, "channel not neutral");
     if (f & DISCOS_FLAG_OUT_OF_DOMAIN) return fail(b, DISCOS_E_OUT_OF_DOMAIN, "ion outside its channel");
     return DISCOS_OK;

@@ -10,6 +10,7 @@
 #define DISCOS_FLAG_NOT_NEUTRAL 2
 #define DISCOS_FLAG_NONFINITE 4
 #define DISCOS_FLAG_BAD_SPECIES 8
+#define DISCOS_FLAG_CAPACITY 16  // a tile's candidate rows exceeded its row buffer
 
 // Bin edge of the cell list, in cells.  Two cells keeps the near-field search
 // volume small (5^3 bins for psi = 4 h) and gives the spread a one-bin halo.
@@ -232,6 +233,14 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
     return base + (2 * m + 1) * g.h * v / w.eps;
 }
 
+// Largest number of candidate rows tile_ranges can produce for a tile of ty x tz cells
+// starting on even cells (every tile edge is even) with a window of hlo cells below and
+// hhi above: each (y, z) bin row of the range contributes at most two x segments.
+constexpr int tile_rows_bound(int ty, int tz, int hlo, int hhi) {
+    return 2 * ((ty - 1 + hhi) / DISCOS_BIN + (hlo + DISCOS_BIN - 1) / DISCOS_BIN + 1) *
+           ((tz - 1 + hhi) / DISCOS_BIN + (hlo + DISCOS_BIN - 1) / DISCOS_BIN + 1);
+}
+
 // Cell-list rows of the ions that can reach the nodes of the tile [x0, x0+tx) x
 // [y0, y0+ty) x [z0, z0+tz) with a window of hlo cells below and hhi above (cells
 // x0-hlo .. x0+tx-1+hhi, periodic in x and y, clipped at the walls in z).  hlo = hhi = 2
@@ -240,11 +249,13 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
 // Row r gets rstart[r] and the prefix sum rpre[r] of the row lengths (rpre[nr] = total);
 // the rows are taken in chunks of blockDim.x, so MAXR may exceed the block (rstart and
 // rpre hold MAXR and MAXR + 1 entries, scan blockDim.x).  Returns the row count; the
-// caller sizes the tile so that the rows fit in MAXR.
+// caller sizes the tile so that the rows fit in MAXR (tile_rows_bound, checked at
+// compile time by each caller).  Rows beyond MAXR would be dropped: that sets the
+// sticky DISCOS_FLAG_CAPACITY in flags, so the loss cannot go unreported.
 template <int MAXR>
 __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, int x0, int y0,
                              int z0, int tx, int ty, int tz, int* rstart, int* rpre, int* scan,
-                             int hlo = 2, int hhi = 2) {
+                             int* __restrict__ flags, int hlo = 2, int hhi = 2) {
     int sa[2], sb[2], nseg;
     {
         const int lo = floordiv(x0 - hlo, DISCOS_BIN), hi = floordiv(x0 + tx - 1 + hhi, DISCOS_BIN);
@@ -263,6 +274,7 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
     const int nyb = yhi - ylo + 1;
     const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
     const int t = threadIdx.x, bd = blockDim.x;
+    if (ncand > MAXR && t == 0) set_flag(flags, DISCOS_FLAG_CAPACITY);
     const int nr = max(min(ncand, MAXR), 1);
     int carry = 0;
     for (int base = 0; base < nr; base += bd) {

@@ -36,12 +36,15 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
                                             const int* __restrict__ bin_start, double sign_lo,
                                             double sign_hi, int add_bc, const WallDev& wall,
                                             double* __restrict__ out, int x0, int y0, int z0,
-                                            double* acc, int* rstart, int* rpre, int* scan) {
+                                            double* acc, int* rstart, int* rpre, int* scan,
+                                            int* __restrict__ flags) {
+    static_assert(tile_rows_bound(T, T, 2, 2) <= SP_MAXR, "spread tile rows exceed SP_MAXR");
     const int tx = min(T, g.nx), ty = min(T, g.ny);
     const int tz = min(T, g.nz - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
-    const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan);
+    const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan,
+                                              flags);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     // the next ion's record is loaded before the current one's LDS atomics
@@ -124,14 +127,14 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
 __global__ void __launch_bounds__(SP_THREADS)
 spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __restrict__ bin_start,
                      double sign_lo, double sign_hi, int add_bc, WallDev wall,
-                     double* __restrict__ out) {
+                     double* __restrict__ out, int* __restrict__ flags) {
     __shared__ double acc[SP_TX * SP_TY * SP_TZ];
     __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
     const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
     int bx, by, bz;
     xcd_block3(bx, by, bz);
     spread_tile<SP_TX>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, bx * tx, by * ty,
-                       bz * SP_TZ, acc, rstart, rpre, scan);
+                       bz * SP_TZ, acc, rstart, rpre, scan, flags);
 }
 
 // Batched: a persistent grid walks the (channel, tile) tasks; each channel's bins,
@@ -141,7 +144,8 @@ template <int T>
 __global__ void __launch_bounds__(SP_THREADS)
 spread_charge_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__ tasks,
                            int ntasks, const double4* __restrict__ sxyzq,
-                           const int* __restrict__ bin_start, double* __restrict__ out) {
+                           const int* __restrict__ bin_start, double* __restrict__ out,
+                           int* __restrict__ flags) {
     __shared__ double acc[T * T * T];
     __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -153,7 +157,7 @@ spread_charge_batch_kernel(const RepDev* __restrict__ reps, const int2* __restri
         const int k = task.y;
         spread_tile<T>(g, sxyzq, bin_start + R.bin_off, R.s_lo, R.s_hi, 1, R.w, out + R.cell_off,
                        (k % ntx) * tx, ((k / ntx) % nty) * ty, (k / (ntx * nty)) * T, acc, rstart,
-                       rpre, scan);
+                       rpre, scan, flags);
         __syncthreads();
     }
 }
@@ -165,7 +169,8 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
     const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sxyzq, c->bin_start,
-                                                     s_lo, s_hi, add_bc, wall_of(p), out);
+                                                     s_lo, s_hi, add_bc, wall_of(p), out,
+                                                     c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -176,10 +181,12 @@ int batch_spread(Batch* b, hipStream_t s) {
     const int nb = b->cfg.spread_blocks > 0 ? std::min(nt, b->cfg.spread_blocks) : nt;
     if (v == 0)
         spread_charge_batch_kernel<8><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][0], nt,
-                                                               b->sxyzq, b->bin_start, b->rho);
+                                                               b->sxyzq, b->bin_start, b->rho,
+                                                               b->flags);
     else
         spread_charge_batch_kernel<16><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][1], nt,
-                                                                b->sxyzq, b->bin_start, b->rho);
+                                                                b->sxyzq, b->bin_start, b->rho,
+                                                               b->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

@@ -271,7 +271,8 @@ template <int COMP, int T, int KM>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
                    const int* __restrict__ bin_start, RfdDev rfd, const int* __restrict__ ssp,
-                   const double* __restrict__ hy_tab, double* __restrict__ out) {
+                   const double* __restrict__ hy_tab, double* __restrict__ out,
+                   int* __restrict__ flags) {
     constexpr int MAXR = KM == 4 ? 2 * SH_MAXR : SH_MAXR;
     __shared__ double acc[T * T * T];
     __shared__ int rstart[MAXR], rpre[MAXR + 1], scan[SH_THREADS];
@@ -284,8 +285,10 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
     // ions that can reach node levels [z0, z0+tz): cells [z0-K, z0+tz-1+K] for a window
     // of 2K nodes (K = 2 for the Peskin kernel)
     const int K = KM == 0 ? 2 : KM;
+    static_assert(tile_rows_bound(T, T, (KM == 0 ? 2 : KM) + 1, KM == 0 ? 2 : KM) <= MAXR,
+                  "face spread tile rows exceed MAXR");
     const int nr = tile_ranges<MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
-                                 rpre, scan, rfd.scale != 0.0 ? K + 1 : K, K);
+                                 rpre, scan, flags, rfd.scale != 0.0 ? K + 1 : K, K);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
@@ -355,13 +358,13 @@ static void spread_faces(Ctx* c, const RfdDev& rfd, const int* ssp, double* out,
     dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + T - 1) / T);
     dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + T - 1) / T);
     spread_face_kernel<0, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd,
-                                                              ssp, c->hy_tab, out);
+                                                              ssp, c->hy_tab, out, c->flags);
     spread_face_kernel<1, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max,
                                                               c->bin_start, rfd, ssp, c->hy_tab,
-                                                              out + ncell);
+                                                              out + ncell, c->flags);
     spread_face_kernel<2, T, KM><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
                                                               c->bin_start, rfd, ssp, c->hy_tab,
-                                                              out + 2 * ncell);
+                                                              out + 2 * ncell, c->flags);
 }
 
 int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in, int species, int n) {

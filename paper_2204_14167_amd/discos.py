@@ -99,7 +99,6 @@ def lib():
                                                   vp, vp]
         L.discos_interpolate_vel_species.argtypes = [vp, i64, vp, vp, vp,
                                                      ctypes.POINTER(DiscosParams), vp, vp]
-        L.discos_p3m_table.argtypes = [i32, i32, i32, ctypes.c_double, vp, vp, vp]
         L.discos_check.argtypes = [vp]
         L.discos_profile.argtypes = [vp, i32]
         L.discos_profile_stages.argtypes = [vp, ctypes.c_uint32]
@@ -125,27 +124,10 @@ def lib():
                      "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
                      "discos_batch_step", "discos_batch_tune", "discos_batch_check",
                      "discos_set_hydro_kernel", "discos_spread_force_species",
-                     "discos_interpolate_vel_species", "discos_profile_stages",
-                     "discos_p3m_table"):
+                     "discos_interpolate_vel_species", "discos_profile_stages"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
-
-
-def p3m_table(n, drho, src, dirs):
-    """(g, drho): the near-field correction's grid pair-force table built by the library
-    (host computation) from the placements src [P, 3] and directions dirs [P, 3, nrho]."""
-    src = np.ascontiguousarray(src, dtype=np.float64)
-    dirs = np.ascontiguousarray(dirs, dtype=np.float64)
-    nplace, nrho = src.shape[0], dirs.shape[2]
-    if src.shape != (nplace, 3) or dirs.shape != (nplace, 3, nrho):
-        raise ValueError("src must be [P, 3] and dirs [P, 3, nrho]")
-    g = np.empty(nrho)
-    rc = lib().discos_p3m_table(int(n), nplace, nrho, float(drho), src.ctypes.data,
-                                dirs.ctypes.data, g.ctypes.data)
-    if rc != OK:
-        raise DiscosError(rc, "invalid p3m table arguments")
-    return g, float(drho)
 
 
 class DiscosReplica(ctypes.Structure):

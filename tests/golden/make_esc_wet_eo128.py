@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 from oracle import dynamics, electrostatics as es
-from paper_2204_14167_amd import workloads
+import workloads
 
 WORKLOAD = "eo_stokes_128x128x128_n262144"
 KERNELS = [(7, 7.0), (4, 8.0)]

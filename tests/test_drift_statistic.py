@@ -6,7 +6,7 @@ mobility is low without it."""
 import numpy as np
 
 from oracle import mobility, shortrange
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.drift_util import profile_deviation, sample_wall_profile, wall_profile_bins
 
 LZ, DT, SIG, XI, CUT = 32.0, 0.01, 1.0, 1.0, 3.5

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import adjoint, electrostatics as es
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.gpu_util import TOL, dev, host, log, rel_l2
 
 pytestmark = pytest.mark.gpu

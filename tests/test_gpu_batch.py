@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import dynamics, electrostatics as es
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.gpu_util import TOL, by_id, dev, host, log, min_image
 
 pytestmark = pytest.mark.gpu

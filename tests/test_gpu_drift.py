@@ -10,7 +10,7 @@ of the binomial standard deviation."""
 import numpy as np
 import pytest
 
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.drift_util import (density_deviation, profile_deviation, sample_wall_profile,
                               wall_profile_bins)
 from tests.gpu_util import dev, host, log

@@ -3,7 +3,7 @@ and reads after recording stopped."""
 import numpy as np
 import pytest
 
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.gpu_util import dev
 
 pytestmark = pytest.mark.gpu

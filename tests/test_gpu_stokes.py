@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import electrostatics as es, shortrange, stokes
-from paper_2204_14167_amd import workloads
+import workloads
 from tests.gpu_util import TOL, dev, host, log, rel_l2
 
 pytestmark = pytest.mark.gpu

@@ -21,7 +21,7 @@ import pytest
 
 from oracle import adjoint, electrostatics as es, stokes
 from oracle.peskin import dphi_pe, phi_pe
-from paper_2204_14167_amd import workloads
+import workloads
 
 D, N = es.DIRICHLET, es.NEUMANN
 

@@ -15,7 +15,7 @@ import pytest
 
 from oracle import dynamics, mobility, shortrange
 from oracle.electrostatics import Grid
-from paper_2204_14167_amd import workloads
+import workloads
 
 
 def test_wall_93_force_is_minus_gradient():

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import electrostatics as es
-from paper_2204_14167_amd.workloads import load_p3m_table, random_ions
+from workloads import load_p3m_table, random_ions
 
 D, N = es.DIRICHLET, es.NEUMANN
 BC_PAIRS = [(D, D), (N, N), (D, N), (N, D)]

@@ -18,7 +18,7 @@ import pytest
 
 from oracle import mobility, stokes
 from oracle.electrostatics import Grid
-from paper_2204_14167_amd.workloads import random_ions
+from workloads import random_ions
 
 
 def _rand_force(grid, seed):

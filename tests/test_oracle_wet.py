@@ -15,7 +15,7 @@ import pytest
 
 from oracle import dynamics, stokes
 from oracle.electrostatics import Grid
-from paper_2204_14167_amd import workloads
+import workloads
 
 
 def _setup(n=24, shape=(16, 16, 16), seed=5):

@@ -1,5 +1,6 @@
 """Seeded synthetic inputs shared by the GPU library's tests, the benchmark and
-the oracle's tests.
+the oracle's tests.  A neutral module: neither the oracle nor the library owns it,
+and it imports neither.
 
 This module holds none of the method's arithmetic: it draws ion positions and
 charges, names the workloads with their sizes, sets the reduced-unit constants
