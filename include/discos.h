@@ -156,6 +156,30 @@ int discos_spread(discos_ctx* ctx, int op, int64_t n, const double* pos, const d
                   const discos_params* p, double* out, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): S^es charge spreading as
+ * discos_spread(DISCOS_SPREAD_CHARGE[ | DISCOS_SPREAD_ADD_BC]) without a context.
+ * rho = S^es q (eq kernel2, images folded per Sec. II.B.1; with DISCOS_SPREAD_ADD_BC in
+ * flags, the wall terms as for discos_spread).  pos [3][n], q [n] and rho [nz][ny][nx]
+ * are DEVICE arrays owned by the caller; rho is overwritten.  p supplies eps, bc_type
+ * and bc_value only.  status: DEVICE int32 [1] or NULL; receives DISCOS_OK or the
+ * sticky device condition of this call (DISCOS_E_NONFINITE, DISCOS_E_CAPACITY,
+ * DISCOS_E_OUT_OF_DOMAIN).
+ * Allocates nothing: its cell list lives in one fixed device array of about 6.5 MiB
+ * per GPU, held until the process ends, which limits a call to
+ * n <= DISCOS_NOALLOC_MAX_IONS and (nx/2)(ny/2)ceil(nz/2) <= DISCOS_NOALLOC_MAX_BINS
+ * (for example 65,536 ions on 128 x 128 x 64 cells); larger calls return
+ * DISCOS_E_CAPACITY before anything is enqueued.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (two streams, two threads) race.  Runs on the
+ * current device.  Errors: DISCOS_E_ARG, DISCOS_E_SHAPE, DISCOS_E_CAPACITY, DISCOS_E_HIP.
+ */
+#define DISCOS_NOALLOC_MAX_IONS 65536
+#define DISCOS_NOALLOC_MAX_BINS 262144
+int discos_spread_charge_noalloc(const discos_grid* grid, int64_t n, const double* pos,
+                                 const double* q, const discos_params* p, uint32_t flags,
+                                 double* rho, int32_t* status, void* stream);
+
+/*
  * Solve -eps lap_h phi = rhs (eq poisson) with the walls' homogeneous ghost rules
  * (phi_{-1} = -phi_0 Dirichlet, +phi_0 Neumann); inhomogeneous wall values enter
  * through rhs (DISCOS_SPREAD_ADD_BC).  In-plane FFTs, then one tridiagonal solve in z

@@ -99,6 +99,9 @@ def lib():
                                                   vp, vp]
         L.discos_interpolate_vel_species.argtypes = [vp, i64, vp, vp, vp,
                                                      ctypes.POINTER(DiscosParams), vp, vp]
+        L.discos_spread_charge_noalloc.argtypes = [ctypes.POINTER(DiscosGrid), i64, vp, vp,
+                                                   ctypes.POINTER(DiscosParams), ctypes.c_uint32,
+                                                   vp, vp, vp]
         L.discos_check.argtypes = [vp]
         L.discos_profile.argtypes = [vp, i32]
         L.discos_profile_stages.argtypes = [vp, ctypes.c_uint32]
@@ -124,7 +127,8 @@ def lib():
                      "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
                      "discos_batch_step", "discos_batch_tune", "discos_batch_check",
                      "discos_set_hydro_kernel", "discos_spread_force_species",
-                     "discos_interpolate_vel_species", "discos_profile_stages"):
+                     "discos_interpolate_vel_species", "discos_profile_stages",
+                     "discos_spread_charge_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -219,6 +223,26 @@ class Params:
         s.hydro_bc[0] = HYDRO_SLIP if sl[0] else HYDRO_NOSLIP
         s.hydro_bc[1] = HYDRO_SLIP if sl[1] else HYDRO_NOSLIP
         self.struct = s
+
+
+NOALLOC_MAX_IONS, NOALLOC_MAX_BINS = 65536, 262144
+
+
+def spread_charge_noalloc(grid, pos, q, params, add_bc=False, out=None, status=None):
+    """rho = S^es q through discos_spread_charge_noalloc (no context, no allocation in the
+    library).  grid = (nx, ny, nz, h); params from Params(p, grid); out [nz, ny, nx] and
+    status (int32 [1], receives the call's device condition) are optional device tensors."""
+    nx, ny, nz, h = grid
+    g = DiscosGrid(int(nx), int(ny), int(nz), float(h))
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float64, device=pos.device)
+    rc = lib().discos_spread_charge_noalloc(ctypes.byref(g), pos.shape[1], _ptr(pos), _ptr(q),
+                                            ctypes.byref(params.struct),
+                                            SPREAD_ADD_BC if add_bc else 0, _ptr(out),
+                                            _ptr(status), _stream())
+    if rc != OK:
+        raise DiscosError(rc, "discos_spread_charge_noalloc failed")
+    return out
 
 
 class Context:
