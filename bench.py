@@ -38,16 +38,15 @@ FP32_PEAK_TFLOPS = 157.3  # vector FP32 (no matrix cores)
 # Algorithmic work per launch of each stage (bytes that the stage must move, or
 # flops for the compute-bound near-field), for N ions, C cells and H = (nx/2+1) ny nz
 # half-spectrum cells.
-NEAR_FLOPS_PER_PAIR = 40.0   # FP64 pair force of the P3M correction, wall images included
-LIST_FLOPS_PER_TEST = 9.0    # one FP32 candidate distance test: 3 sub, 3 mul, 2 add, 1 cmp
+NEAR_FLOPS_PER_PAIR = 50.0   # FP64 pair work of the P3M correction (pairs within psi, wall
+                             # images included), as the survey prices it
 # peak of the arithmetic each compute-bound stage runs in
-ALU_PEAK = {"near_list": FP32_PEAK_TFLOPS, "near_eval": FP64_PEAK_TFLOPS}
+ALU_PEAK = {"near_field": FP64_PEAK_TFLOPS}
 
 # Stages that are one kernel launch each, with the kernel's name in rocprofv3 output.
 STAGE_KERNEL = {"spread": "spread_charge_kernel", "fft_x": "fft_x_r2c_kernel",
                 "z_solve": "zsolve_kernel", "ifft_x": "fft_x_c2r_kernel",
-                "interp": "interp_es_kernel", "near_list": "near_list_kernel",
-                "near_eval": "near_eval_kernel"}
+                "interp": "interp_es_kernel", "near_field": "near_field_kernel"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_dry_step_256x256x128_n1048576.md")
 ISSUE_FILE = os.path.join(ROOT, "profiles", "sq_issue_dry_step_256x256x128_n1048576.md")
 
@@ -129,10 +128,8 @@ def stage_work(stage, N, C, H, pairs, tests):
         return "hbm", 16.0 * H + 8.0 * C
     if stage == "interp":
         return "hbm", 56.0 * N + 8.0 * C
-    if stage == "near_list":
-        return "alu", LIST_FLOPS_PER_TEST * tests
-    if stage == "near_eval":
-        # the pair forces (the fused dry update is not counted)
+    if stage == "near_field":
+        # the pair forces (the candidate tests and the fused dry update are not counted)
         return "alu", NEAR_FLOPS_PER_PAIR * pairs
     # "update": in a dry step the near-field force pass applies the update itself (the
     # stage is empty); the hydrodynamic stages are empty too

@@ -384,12 +384,13 @@ const char* discos_batch_last_error(discos_batch* b);
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
  * the mean elapsed milliseconds per recorded step of each stage (host array of at
  * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
- * inverse y-FFT, inverse x-FFT, interpolation, near-field neighbour lists, near-field
- * forces, S^hy, Stokes solve, the two J^hy passes with the predictor, update; the
- * hydrodynamic stages read 0 in dry steps) and sets *count (0 when no step was
+ * inverse y-FFT, inverse x-FFT, interpolation, near field (candidates, pair forces,
+ * wall force, and in a dry step the update), S^hy, Stokes solve, the two J^hy passes
+ * with the predictor, the update of a wet step; the hydrodynamic stages and the last
+ * read 0 in dry steps) and sets *count (0 when no step was
  * recorded).  Each recorded event costs the stream a few microseconds.
  */
-#define DISCOS_NSTAGE 14
+#define DISCOS_NSTAGE 13
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
 

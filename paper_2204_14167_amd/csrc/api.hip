@@ -201,10 +201,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     const int64_t nspec = c->nmode * g.nz;
     size_t bytes = 0;
     bytes += carve_bytes(nm, sizeof(double4));         // sxyzq
-    bytes += carve_bytes(nm, sizeof(float4));          // sxyzf
     bytes += carve_bytes(3 * nm, sizeof(double));      // fp
-    bytes += carve_bytes(64 * nm, sizeof(int));        // nlist
-    bytes += carve_bytes(nm, sizeof(int));             // ncount
     bytes += 5 * carve_bytes(nm, sizeof(int));         // sid ssp perm ion_bin ion_rank
     bytes += carve_bytes(c->nbins, sizeof(int));
     bytes += carve_bytes(c->nbins + 1, sizeof(int));
@@ -217,6 +214,13 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     bytes += carve_bytes(64, sizeof(int));
     bytes += carve_bytes(2 * PART_MAX, sizeof(double));                 // reduction partials
     bytes += carve_bytes(2 * (size_t)g.nx * g.ny, sizeof(double));     // wall adjoints
+    // the near field's padded cell list, sized for search radii up to 3 bins
+    const int64_t nl_bins = discos::near_list_bins(g, 3);
+    const int64_t nl_cap = discos::near_list_entries(g, n_max);
+    bytes += carve_bytes(nl_bins, sizeof(int)) + carve_bytes(nl_bins + 1, sizeof(int));
+    bytes += carve_bytes(nl_bins / 1024 + 2, sizeof(int));
+    bytes += carve_bytes(nl_cap, sizeof(double4)) + carve_bytes(nl_cap, sizeof(float4));
+    bytes += carve_bytes(nl_cap, sizeof(int));
     if (hipMalloc(&c->pool, bytes) != hipSuccess) {
         delete c;
         return DISCOS_E_HIP;
@@ -224,10 +228,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->pool_bytes = bytes;
     char* cur = static_cast<char*>(c->pool);
     c->sxyzq = carve<double4>(cur, nm);
-    c->sxyzf = carve<float4>(cur, nm);
     c->fp = carve<double>(cur, 3 * nm);
-    c->nlist = carve<int>(cur, 64 * nm);
-    c->ncount = carve<int>(cur, nm);
     c->sid = carve<int>(cur, nm);
     c->ssp = carve<int>(cur, nm);
     c->perm = carve<int>(cur, nm);
@@ -245,6 +246,14 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->flags = carve<int>(cur, 64);
     c->part = carve<double>(cur, 2 * PART_MAX);
     c->bcg = carve<double>(cur, 2 * (size_t)g.nx * g.ny);
+    c->nl.count = carve<int>(cur, nl_bins);
+    c->nl.start = carve<int>(cur, nl_bins + 1);
+    c->nl.tmp = carve<int>(cur, nl_bins / 1024 + 2);
+    c->nl.xyzq = carve<double4>(cur, nl_cap);
+    c->nl.xyzf = carve<float4>(cur, nl_cap);
+    c->nl.sp = carve<int>(cur, nl_cap);
+    c->nl.cap = nl_cap;
+    c->nl.bins_cap = nl_bins;
     // twiddles exp(-2 pi i k / N)
     std::vector<double2> tw(std::max(g.nx, g.ny) / 2);
     for (int pass = 0; pass < 2; ++pass) {
@@ -564,7 +573,6 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9,
                                                       wet ? nullptr : &dry_out);
     else discos::stage_mark(c, 9, s);
-    discos::stage_mark(c, 10, s);
     const double* vwet = nullptr;
     if (wet && !rc && ni > 0) {
         discos::RfdDev rd{};
@@ -576,19 +584,19 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
             rd.step = step;
         }
         rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr, 1, ni);
-        discos::stage_mark(c, 11, s);
+        discos::stage_mark(c, 10, s);
         if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
-        discos::stage_mark(c, 12, s);
+        discos::stage_mark(c, 11, s);
         if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s, 1);
-        discos::stage_mark(c, 13, s);
+        discos::stage_mark(c, 12, s);
         vwet = c->hvi;
     } else {
+        discos::stage_mark(c, 10, s);
         discos::stage_mark(c, 11, s);
         discos::stage_mark(c, 12, s);
-        discos::stage_mark(c, 13, s);
     }
     if (!rc && wet) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
-    discos::stage_mark(c, 14, s);
+    discos::stage_mark(c, 13, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
 }

@@ -132,6 +132,16 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         bin_off[r + 1] = bin_off[r] + nb;
     }
     b->nbins_tot = bin_off[count];
+    // the near field's padded bins and copies, per channel (search radius Rb bins)
+    std::vector<int> pbin_off(count + 1, 0);
+    int64_t nl_cap = 0;
+    for (int r = 0; r < count; ++r) {
+        const discos_replica& c = reps[r];
+        const int64_t nbz = (c.nz + DISCOS_BIN - 1) / DISCOS_BIN;
+        pbin_off[r + 1] = pbin_off[r] + (int)((c.nx / DISCOS_BIN + 2 * Rb) * (int64_t)(c.ny / DISCOS_BIN + 2 * Rb) *
+                                              (nbz + 2 * Rb + (c.nz & 1)));
+        nl_cap += std::max<int64_t>(c.n, 1) * 4 * (nbz < 7 ? 3 : 2);
+    }
     // cells and spectra by (nx, ny) class
     std::map<std::pair<int, int>, std::vector<int>> cls;
     for (int r = 0; r < count; ++r) cls[{reps[r].nx, reps[r].ny}].push_back(r);
@@ -252,16 +262,15 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     std::vector<std::pair<int, int>> tw_at;
     for (auto& k : b->classes) tw_at.push_back({tw_of(k.nx), tw_of(k.ny)});
 
-    // neighbour lists sized for the densest channel
-    double rho_max = 0.0;
-    for (int r = 0; r < count; ++r)
-        rho_max = std::max(rho_max, (double)reps[r].n / ((double)reps[r].nx * reps[r].ny * reps[r].nz * h * h * h));
-    b->nl_cap = discos::near_list_capacity(h, p, rho_max);
     // one allocation
     const size_t n = (size_t)std::max<int64_t>(n_tot, 1);
     const size_t nblk = (size_t)(b->nbins_tot + 1023) / 1024 + 1;
     size_t bytes = 0;
-    bytes += carve_bytes(n, sizeof(double4)) + carve_bytes(n, sizeof(float4));
+    bytes += carve_bytes(n, sizeof(double4));
+    bytes += carve_bytes(pbin_off[count], sizeof(int)) + carve_bytes(pbin_off[count] + 1, sizeof(int));
+    bytes += carve_bytes(pbin_off[count] / 1024 + 2, sizeof(int)) + carve_bytes(count + 1, sizeof(int));
+    bytes += carve_bytes(nl_cap, sizeof(double4)) + carve_bytes(nl_cap, sizeof(float4));
+    bytes += carve_bytes(nl_cap, sizeof(int));
     bytes += 6 * carve_bytes(n, sizeof(int));  // sid ssp perm ion_bin ion_rank ion_rep
     bytes += carve_bytes(b->nbins_tot, sizeof(int)) + carve_bytes(b->nbins_tot + 1, sizeof(int));
     bytes += carve_bytes(nblk, sizeof(int));
@@ -271,7 +280,6 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     bytes += carve_bytes(std::max<int64_t>(zg_len, 1), sizeof(double));
     for (int v = 0; v < 3; ++v) bytes += carve_bytes(std::max<size_t>(zt[v].size(), 1), sizeof(int2));
     bytes += carve_bytes(3 * n, sizeof(double));
-    bytes += carve_bytes((size_t)b->nl_cap * n, sizeof(int)) + carve_bytes(n, sizeof(int));
     bytes += carve_bytes(64, sizeof(int)) + carve_bytes(1, sizeof(uint64_t));
     bytes += carve_bytes(count + 1, sizeof(int)) + carve_bytes(count, sizeof(int));
     bytes += carve_bytes(count, sizeof(discos::RepDev));
@@ -285,7 +293,15 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     }
     char* cur = static_cast<char*>(b->pool);
     b->sxyzq = carve<double4>(cur, n);
-    b->sxyzf = carve<float4>(cur, n);
+    b->nl.count = carve<int>(cur, pbin_off[count]);
+    b->nl.start = carve<int>(cur, pbin_off[count] + 1);
+    b->nl.tmp = carve<int>(cur, pbin_off[count] / 1024 + 2);
+    b->nl.xyzq = carve<double4>(cur, nl_cap);
+    b->nl.xyzf = carve<float4>(cur, nl_cap);
+    b->nl.sp = carve<int>(cur, nl_cap);
+    b->nl.cap = nl_cap;
+    b->nl.bins_cap = pbin_off[count];
+    b->pbin_off = carve<int>(cur, count + 1);
     b->sid = carve<int>(cur, n);
     b->ssp = carve<int>(cur, n);
     b->perm = carve<int>(cur, n);
@@ -305,8 +321,6 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         b->ztasks_n[v] = (int)zt[v].size();
     }
     b->fp = carve<double>(cur, 3 * n);
-    b->nlist = carve<int>(cur, (size_t)b->nl_cap * n);
-    b->ncount = carve<int>(cur, n);
     b->flags = carve<int>(cur, 64);
     b->step_d = carve<uint64_t>(cur, 1);
     b->mode_off = carve<int>(cur, count + 1);
@@ -341,6 +355,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     bool ok = hipMemcpy(b->ion_rep, ion_rep.data(), n * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->walls, walls.data(), walls.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->reps_d, b->reps_h.data(), count * sizeof(discos::RepDev), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->pbin_off, pbin_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->mode_off, mode_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->mode_rep, mode_rep.data(), count * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(tw_d, tw_all.data(), tw_all.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;

@@ -95,10 +95,10 @@ __global__ void scan_reduce_kernel(const int* __restrict__ count, int64_t nb,
 }
 
 // Also clears the counts it has read, so that the next binning starts from zero
-// without a fill (contexts and batches clear them once at creation).
+// without a fill (contexts and batches clear them once at creation).  start[nb] receives
+// the total.
 __global__ void scan_final_kernel(int* __restrict__ count, int64_t nb,
-                                  const int* __restrict__ block_sum, int* __restrict__ start,
-                                  int n_total) {
+                                  const int* __restrict__ block_sum, int* __restrict__ start) {
     __shared__ int sh[SCAN_BLOCK];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     // this block's offset: the sums of the blocks before it
@@ -121,7 +121,13 @@ __global__ void scan_final_kernel(int* __restrict__ count, int64_t nb,
         if (i < nb) start[i] = ex;
         ex += v[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) start[nb] = n_total;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) start[nb] = ex;
+}
+
+void scan_counts(int* count, int64_t nb, int* tmp, int* start, hipStream_t s) {
+    const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
+    scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(count, nb, tmp);
+    scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(count, nb, tmp, start);
 }
 
 // Sorted copies of the ion arrays; perm[sorted] = original index.
@@ -133,8 +139,8 @@ __global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
                                          const double* __restrict__ y, const double* __restrict__ z,
                                          const double* __restrict__ q, const int* __restrict__ id,
                                          const int* __restrict__ sp, double4* __restrict__ sxyzq,
-                                         float4* __restrict__ sxyzf, int* __restrict__ sid,
-                                         int* __restrict__ ssp, int* __restrict__ perm) {
+                                         int* __restrict__ sid, int* __restrict__ ssp,
+                                         int* __restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const GridDev& g = reps[ion_rep[i]].g;
@@ -145,7 +151,6 @@ __global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
         yi = reduce_periodic(yi, g.Ly);
     }
     sxyzq[d] = make_double4(xi, yi, z[i], q[i]);
-    sxyzf[d] = make_float4((float)xi, (float)yi, (float)z[i], 0.0f);
     sid[d] = id[i];
     ssp[d] = sp[i];
     perm[d] = i;
@@ -156,7 +161,7 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
                                    const double* __restrict__ x, const double* __restrict__ y,
                                    const double* __restrict__ z, const double* __restrict__ q,
                                    const int* __restrict__ id, const int* __restrict__ sp,
-                                   GridDev g, double4* __restrict__ sxyzq, float4* __restrict__ sxyzf,
+                                   GridDev g, double4* __restrict__ sxyzq,
                                    int* __restrict__ sid, int* __restrict__ ssp,
                                    int* __restrict__ perm, const double* __restrict__ w3,
                                    int64_t w3_stride, double* __restrict__ sw3,
@@ -170,7 +175,6 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
         yi = reduce_periodic(yi, g.Ly);
     }
     sxyzq[d] = make_double4(xi, yi, z[i], q ? q[i] : 0.0);
-    sxyzf[d] = make_float4((float)xi, (float)yi, (float)z[i], 0.0f);
     if (id) sid[d] = id[i];
     if (sp) ssp[d] = sp[i];
     if (w3) {
@@ -191,12 +195,10 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
     if (n > 0)
         bin_count_kernel<<<(n + T - 1) / T, T, 0, s>>>(g, n, x, y, z, c->bin_count, c->ion_bin,
                                                        c->ion_rank, c->flags);
-    const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
-    scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp);
-    scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(c->bin_count, nb, c->scan_tmp, c->bin_start, n);
+    scan_counts(c->bin_count, nb, c->scan_tmp, c->bin_start, s);
     if (n > 0)
         bin_scatter_kernel<<<(n + T - 1) / T, T, 0, s>>>(n, c->ion_bin, c->ion_rank, c->bin_start,
-                                                         x, y, z, q, id, sp, g, c->sxyzq, c->sxyzf,
+                                                         x, y, z, q, id, sp, g, c->sxyzq,
                                                          c->sid, c->ssp, c->perm, w3, w3_stride,
                                                          c->fp, c->n_max);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
@@ -210,13 +212,11 @@ int batch_cell_list(Batch* b, const double* pos, const double* q, const int* id,
     bin_count_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, pos, pos + n,
                                                          pos + 2 * (int64_t)n, b->bin_count,
                                                          b->ion_bin, b->ion_rank, b->flags);
-    const int nblk = (int)((nb + SCAN_TILE - 1) / SCAN_TILE);
-    scan_reduce_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp);
-    scan_final_kernel<<<nblk, SCAN_BLOCK, 0, s>>>(b->bin_count, nb, b->scan_tmp, b->bin_start, n);
+    scan_counts(b->bin_count, nb, b->scan_tmp, b->bin_start, s);
     bin_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, n, b->ion_bin,
                                                            b->ion_rank, b->bin_start, pos, pos + n,
                                                            pos + 2 * (int64_t)n, q, id, sp, b->sxyzq,
-                                                           b->sxyzf, b->sid, b->ssp, b->perm);
+                                                           b->sid, b->ssp, b->perm);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

@@ -10,6 +10,20 @@
 
 namespace discos {
 
+// The near-field pass's own copy of the cell list, padded so that every search row is
+// one contiguous run: R ghost bins on each x and y side hold the periodic copies (x and y
+// shifted by a period), and R ghost slabs beyond each wall hold the mirror images of the
+// first R slabs (z mirrored, charge times the wall's image sign, species -1).
+struct NearList {
+    int* count;      // [bins_cap] entries per padded bin
+    int* start;      // [bins_cap + 1] exclusive starts (start[nb] = total)
+    int* tmp;        // scan block sums
+    double4* xyzq;   // [cap] x, y, z, q of every copy
+    float4* xyzf;    // [cap] the same in FP32 (the candidate filter)
+    int* sp;         // [cap] species of the copy, -1 for wall images
+    int64_t cap, bins_cap;
+};
+
 struct Ctx {
     discos_grid grid;
     GridDev gd;
@@ -22,7 +36,6 @@ struct Ctx {
     // sorted ion copies (cell-list order): (x, y, z, q) with x, y reduced into
     // [0, L], plus ids, species and the permutation back to caller order
     double4* sxyzq;
-    float4* sxyzf;   // the same positions in FP32: candidate filter of the neighbour lists
     int *sid, *ssp, *perm;
     int *ion_bin, *ion_rank;
     int *bin_count, *bin_start, *scan_tmp;
@@ -32,9 +45,8 @@ struct Ctx {
     double* cprime;  // z-solve pivots [nz][nmode] (or Thomas scratch when nz > 128)
     int zg_key;      // wall types the pivots in cprime were computed for (-1: none)
     double* fp;      // [3][n_max] per-ion forces in cell-list order
-    int* nlist;      // near-field neighbour lists, [64][n_max] (entry-major)
-    int* ncount;     // [n_max] list lengths
     double2 *tw_x, *tw_y;
+    NearList nl;     // the near-field pass's padded copy of the cell list
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
     int hydro;
     double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
@@ -112,15 +124,15 @@ struct Batch {
     double* zg;                    // pivots of every shape, [nz][nmode] each
     bool z_legacy = false;         // some channel has nz > 128 (per-mode Thomas, scratch cprime)
     bool z_singular = false;       // both walls Neumann
-    int nl_cap = 64;               // neighbour-list entries per ion (densest channel)
     std::vector<BatchClass> classes;
     double* walls;                 // per-channel wall fields [2][ny][nx], back to back
     double4* sxyzq;
-    float4* sxyzf;
     int *sid, *ssp, *perm, *ion_bin, *ion_rank, *bin_count, *bin_start, *scan_tmp;
+    NearList nl;                   // padded copy of the near field (every channel's bins)
+    int* pbin_off;                 // [R + 1] first padded bin of each channel (device)
     double *rho, *phi, *cprime, *fp;
     double2* spec;
-    int *nlist, *ncount, *flags;
+    int* flags;
     uint64_t* step_d;
     void* pool;
     BatchCfg cfg;
@@ -150,6 +162,12 @@ int build_cell_list(Ctx* c, int n, const double* x, const double* y, const doubl
                     const double* q, const int* id, const int* sp, hipStream_t s,
                     const double* w3 = nullptr, int64_t w3_stride = 0);
 void fill_f64(double* a, int64_t n, double v, hipStream_t s);
+// Exclusive scan of count[0, nb) into start[0, nb] (start[nb] = total), clearing count.
+void scan_counts(int* count, int64_t nb, int* tmp, int* start, hipStream_t s);
+// Padded near-field list sizes for a grid: entries for n ions and padded bins, for search
+// radii up to 3 bins.
+int64_t near_list_entries(const GridDev& g, int64_t n);
+int64_t near_list_bins(const GridDev& g, int R);
 
 // S^es over the cell list: rho = S q (sorted copies sx..sq) with fold signs; optional
 // wall terms of the discrete Poisson problem.
@@ -234,6 +252,5 @@ int batch_near(Batch* b, hipStream_t s);
 int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s);
 int batch_set_step(Batch* b, uint64_t v, hipStream_t s);
 int near_radius_bins_h(double h, const discos_params* p);
-int near_list_capacity(double h, const discos_params* p, double rho_max);
 
 }  // namespace discos

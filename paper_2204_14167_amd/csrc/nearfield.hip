@@ -1,14 +1,12 @@
 // Particle-particle part of the step: the P3M near-field correction with wall images
 // (eqs coulomb, fullElectro, LC and the image rule of Sec. II.B.1), the 9-3 wall
 // force and the optional ion-ion LJ force (Sec. II.B.2), and the dry update
-// (eq ions3, eq step2 with the tensor of eq diff1).  One thread per ion in cell-list
+// (eq ions3, eq step2 with the tensor of eq diff1).  One lane per ion in cell-list
 // order; neighbours come from the (2R+1)^2 rows of 2R+1 contiguous bins around the
-// ion's bin, so consecutive threads read overlapping, cache-resident neighbour lists.
+// ion's bin, so consecutive lanes read overlapping, cache-resident candidates.
 #include "kernels.h"
 
 namespace discos {
-
-#define NL_CAP_DEFAULT 64  // list entries per ion of a single context
 
 struct NearDev {
     double psi, psi2, psi2g, inv4pieps, h, inv_h2, inv_hdr;
@@ -24,7 +22,6 @@ struct NearDev {
     const double* ljx;
     double ljf;
     int nsp;
-    int cap;  // list entries per ion (a multiple of 4); longer lists take the cache-read path
 };
 
 static NearDev near_of_h(double h, const discos_params* p) {
@@ -53,7 +50,6 @@ static NearDev near_of_h(double h, const discos_params* p) {
     d.ljx = p->lj_xi;
     d.ljf = p->lj_cut_factor;
     d.nsp = p->nspecies;
-    d.cap = NL_CAP_DEFAULT;
     return d;
 }
 
@@ -61,16 +57,6 @@ static NearDev near_of(const Ctx* c, const discos_params* p) { return near_of_h(
 
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
 
-// List capacity for ion densities up to rho_max (ions per unit volume): the mean number
-// of candidates inside the search sphere (wall images replace the part of the sphere
-// beyond a wall, so the sphere bounds them), 25 % more for the FP32 margin and bin
-// shapes, plus six standard deviations; at least the single-context capacity.
-int near_list_capacity(double h, const discos_params* p, double rho_max) {
-    const double r = near_of_h(h, p).rsearch;
-    const double mean = 1.25 * (4.0 / 3.0) * M_PI * r * r * r * rho_max;
-    const int cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
-    return std::max(NL_CAP_DEFAULT, (cap + 3) & ~3);
-}
 int near_radius_bins_h(double h, const discos_params* p) { return near_of_h(h, p).R; }
 
 // 1/sqrt(r2) to full FP64 accuracy: hardware estimate plus two Newton steps.
@@ -96,15 +82,6 @@ __device__ __forceinline__ void es_pair_r2(double dx, double dy, double dz, doub
     fx += mag * dx;
     fy += mag * dy;
     fz += mag * dz;
-}
-
-// F^C - F^P for one pair (or ion-image pair) at separation d, charge product qq.
-// A pair at zero separation has no direction and contributes nothing.
-__device__ __forceinline__ void es_pair(double dx, double dy, double dz, double qq,
-                                        const NearDev& P, double& fx, double& fy, double& fz) {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < P.psi2) || !(r2 > 0.0)) return;
-    es_pair_r2(dx, dy, dz, r2, qq, P, fx, fy, fz);
 }
 
 __device__ __forceinline__ void lj_pair(double dx, double dy, double dz, int si, int sj,
@@ -134,368 +111,6 @@ __device__ __forceinline__ double du93(double y, const NearDev& P) {
     const double sy = P.wsig / y;
     const double sy3 = sy * sy * sy;
     return c93 * P.wxi * (-9.0 * sy3 * sy3 * sy3 + 3.0 * sy3) / y;
-}
-
-// ---- global-memory path (one thread per ion, candidates read through the caches) ----
-// Used only for blocks whose neighbourhood does not fit the LDS stage (very dense
-// clusters); the staged path below is the normal one.
-__device__ void near_force_global(int i, double4 me, int spi, const double4* __restrict__ sxyzq,
-                                  const int* __restrict__ ssp, const int* __restrict__ bin_start,
-                                  const GridDev& g, const NearDev& P, double& Fx, double& Fy,
-                                  double& Fz) {
-    const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
-    int bx, by, bz;
-    bin_of(g, xi, yi, zi, bx, by, bz);
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int mode = 0; mode < 3; ++mode) {
-        int zlo, zhi;
-        double sgn = 1.0;
-        if (mode == 0) {
-            zlo = max(bz - P.R, 0);
-            zhi = min(bz + P.R, g.nbz - 1);
-        } else if (mode == 1) {
-            if (!(zi < P.psi)) continue;
-            zlo = 0;
-            zhi = min(g.nbz - 1, (int)floor(P.psi * g.inv_h) / DISCOS_BIN);
-            sgn = P.s_lo;
-        } else {
-            if (!(zi > g.Lz - P.psi)) continue;
-            zlo = max(0, (int)floor((g.Lz - P.psi) * g.inv_h) / DISCOS_BIN);
-            zhi = g.nbz - 1;
-            sgn = P.s_hi;
-        }
-        for (int cz = zlo; cz <= zhi; ++cz)
-            for (int dyb = -P.R; dyb <= P.R; ++dyb) {
-                const int cyu = by + dyb;
-                const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
-                const double ys = yi - (cyu < 0 ? -g.Ly : (cyu >= g.nby ? g.Ly : 0.0));
-                const int row = (cz * g.nby + cy) * g.nbx;
-                for (int dxb = -P.R; dxb <= P.R; ++dxb) {
-                    const int cxu = bx + dxb;
-                    const int cx = cxu < 0 ? cxu + g.nbx : (cxu >= g.nbx ? cxu - g.nbx : cxu);
-                    const double xs = xi - (cxu < 0 ? -g.Lx : (cxu >= g.nbx ? g.Lx : 0.0));
-                    const int j0 = bin_start[row + cx], j1 = bin_start[row + cx + 1];
-                    for (int j = j0; j < j1; ++j) {
-                        const double4 o = sxyzq[j];
-                        const double dx = xs - o.x, dy = ys - o.y;
-                        if (mode == 0) {
-                            if (j == i) continue;
-                            const double dz = zi - o.z;
-                            es_pair(dx, dy, dz, qi * o.w, P, fx, fy, fz);
-                            if (P.lj_on) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
-                        } else {
-                            const double zimg = mode == 1 ? -o.z : 2.0 * g.Lz - o.z;
-                            es_pair(dx, dy, zi - zimg, qi * (sgn * o.w), P, fx, fy, fz);
-                        }
-                    }
-                }
-            }
-    }
-    Fx = fx;
-    Fy = fy;
-    Fz = fz;
-}
-
-// ---- neighbour list + force pass -------------------------------------------------
-// Pass 1 (one thread per ion of the cell list): visit the rows of bins around the ion
-// (a row is skipped when its slab is farther than the search radius and cut to the
-// x-bins that can reach the sphere; periodic copies and wall images carry a shift /
-// mode code), test each candidate's distance, and append the hits to the ion's list.
-// Pass 2 (one thread per ion) evaluates the pair forces of its list.  The
-// distance test, whose trip count differs between lanes, is thereby separated from the
-// pair arithmetic, which then runs only on pairs inside the cutoff.  Lists are written
-// and read in chunks of four entries; chunk c of ion i sits at [c * n + i], so the
-// chunk reads of a wavefront are contiguous.
-#define NL_TAB 320
-
-__device__ __forceinline__ double shift_of(int code, double L) {
-    return code == 1 ? -L : (code == 2 ? L : 0.0);
-}
-
-// Runs of candidate bins of one slab (one z-row of bins, or one image layer), at most
-// two per y-row: 2R + 1 <= nbx, so a row of 2R + 1 bins crosses the periodic seam at
-// most once.  Each thread keeps its slab's runs in its own column of the block's LDS
-// buffer (entry = first sorted index | shift and mode code, end index).
-#define NL_SLAB_RUNS(R) (2 * (2 * (R) + 1))
-
-// A run entry decoded: its candidate range, code bits, and the ion's x and y against
-// the candidates' periodic copy.
-struct NlRun {
-    int j, e, code;
-    float xs, ys;
-};
-
-__device__ __forceinline__ NlRun nl_run(int2 r, float xf0, float xf1, float xf2, float yf0,
-                                        float yf1, float yf2) {
-    NlRun u;
-    u.j = r.x & 0x3FFFFFF;
-    u.code = r.x & ~0x3FFFFFF;
-    u.e = r.y;
-    const int xc = (r.x >> 26) & 3, yc = (r.x >> 28) & 3;
-    u.xs = xc == 0 ? xf0 : (xc == 1 ? xf1 : xf2);
-    u.ys = yc == 0 ? yf0 : (yc == 1 ? yf1 : yf2);
-    return u;
-}
-
-template <int R>
-__device__ __forceinline__ void near_list_one(const GridDev& g, const NearDev& P, int i, int n,
-                                              const double4* __restrict__ sxyzq,
-                                              const float4* __restrict__ sxyzf,
-                                              const int* __restrict__ bin_start,
-                                              int* __restrict__ list, int* __restrict__ count,
-                                              int2* __restrict__ buf, int bstride) {
-    const double4 me = sxyzq[i];
-    const double xi = me.x, yi = me.y, zi = me.z;
-    if (!pos_ok(g, xi, yi, zi)) {
-        count[i] = 0;
-        return;
-    }
-    const double Bh = DISCOS_BIN * g.h;
-    const double inv_Bh = 1.0 / Bh;
-    const double rs2 = P.rsearch * P.rsearch;
-    const double r2cut = fmax(P.psi2, P.lj_on ? rs2 * (1.0 + 1e-12) : 0.0);
-    int bx, by, bz;
-    bin_of(g, xi, yi, zi, bx, by, bz);
-    // Candidates are filtered in FP32 against the cutoff widened by a margin that bounds
-    // the FP32 error of the squared distance (coordinates up to Lmax, distances up to
-    // the search radius): the lists are a superset of the pairs inside the cutoff, and
-    // the force pass applies the exact FP64 test.
-    const double Lmax = fmax(fmax(g.Lx, g.Ly), 2.0 * g.Lz);
-    const double margin = 32.0 * sqrt(r2cut) * Lmax * 0x1.0p-24;
-    // the ion's coordinates against a candidate's periodic copy, by shift code 0, 1, 2
-    float xf0 = (float)xi, xf1 = (float)(xi + g.Lx), xf2 = (float)(xi - g.Lx);
-    float yf0 = (float)yi, yf1 = (float)(yi + g.Ly), yf2 = (float)(yi - g.Ly);
-    // opaque to the optimiser: otherwise it folds the per-run choice of these six values
-    // back into an FP64 add and conversion inside the candidate loop
-    asm("" : "+v"(xf0), "+v"(xf1), "+v"(xf2), "+v"(yf0), "+v"(yf1), "+v"(yf2));
-    // chunk c of ion i at [c * n + i]; the last four hits are kept in h0..h3 (oldest first)
-    int4* const chunks = reinterpret_cast<int4*>(list) + i;
-    int nh = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
-    for (int mode = 0; mode < 3; ++mode) {
-        int zlo, zhi;
-        if (mode == 0) {
-            zlo = max(bz - R, 0);
-            zhi = min(bz + R, g.nbz - 1);
-        } else if (mode == 1) {
-            if (!(zi < P.psi)) continue;
-            zlo = 0;
-            zhi = min(g.nbz - 1, (int)floor(P.psi * g.inv_h) / DISCOS_BIN);
-        } else {
-            if (!(zi > g.Lz - P.psi)) continue;
-            zlo = max(0, (int)floor((g.Lz - P.psi) * g.inv_h) / DISCOS_BIN);
-            zhi = g.nbz - 1;
-        }
-        const double r2m = mode == 0 ? rs2 : P.psi2;
-        const double cut = mode == 0 ? r2cut : P.psi2;
-        const float zsf = mode == 0 ? 1.0f : -1.0f;
-        const float zef = (float)(mode == 2 ? zi - 2.0 * g.Lz : zi);
-        const float cutf = (float)(cut * (1.0 + 1e-5) + margin);
-        const int self = mode == 0 ? i : -1;  // the ion itself is excluded by index
-        const int mcode = mode << 30;
-        for (int cz = zlo; cz <= zhi; ++cz) {
-            const double zb0 = cz * Bh, zb1 = fmin((cz + 1) * Bh, g.Lz);
-            const double dzm = mode == 0 ? fmax(0.0, fmax(zb0 - zi, zi - zb1))
-                                         : (mode == 1 ? zi + zb0 : (2.0 * g.Lz - zb1) - zi);
-            const double remz = r2m - dzm * dzm;
-            if (!(remz > 0.0)) continue;
-            // 1. the slab's non-empty runs
-            int nr = 0;
-#pragma unroll 1
-            for (int dyb = -R; dyb <= R; ++dyb) {
-                const int cyu = by + dyb;
-                const double yb0 = cyu * Bh;
-                const double dym = fmax(0.0, fmax(yb0 - yi, yi - (yb0 + Bh)));
-                const double rem = remz - dym * dym;
-                if (!(rem > 0.0)) continue;
-                // half chord of the search sphere in x; the FP32 root (within 2^-22
-                // relative of the exact one) is widened so that the bin range can only grow
-                const double wx =
-                    (double)__builtin_amdgcn_sqrtf((float)rem) * (1.0 + 0x1.0p-18) + 0x1.0p-20 * Bh;
-                const int bxl = max(bx - R, (int)floor((xi - wx) * inv_Bh));
-                const int bxh = min(bx + R, (int)floor((xi + wx) * inv_Bh));
-                if (bxl > bxh) continue;
-                const int cy = cyu < 0 ? cyu + g.nby : (cyu >= g.nby ? cyu - g.nby : cyu);
-                const int ycode = (cyu < 0 ? 1 : (cyu >= g.nby ? 2 : 0)) << 28;
-                const int row = (cz * g.nby + cy) * g.nbx;
-                // first run: up to the seam (or the whole range)
-                const int e1 = bxl < 0 ? min(bxh, -1) : (bxl < g.nbx ? min(bxh, g.nbx - 1) : bxh);
-                const int cx1 = bxl < 0 ? bxl + g.nbx : (bxl >= g.nbx ? bxl - g.nbx : bxl);
-                const int xc1 = bxl < 0 ? 1 : (bxl >= g.nbx ? 2 : 0);
-                const int j0 = bin_start[row + cx1], j1 = bin_start[row + cx1 + (e1 - bxl) + 1];
-                // second run: past the seam
-                const bool two = e1 < bxh;
-                const int b2 = e1 + 1;
-                const int cx2 = b2 >= g.nbx ? b2 - g.nbx : b2;
-                const int xc2 = b2 >= g.nbx ? 2 : 0;
-                const int k0 = two ? bin_start[row + cx2] : 0;
-                const int k1 = two ? bin_start[row + cx2 + (bxh - b2) + 1] : 0;
-                if (j0 < j1) buf[(nr++) * bstride] = make_int2(j0 | (xc1 << 26) | ycode | mcode, j1);
-                if (k0 < k1) buf[(nr++) * bstride] = make_int2(k0 | (xc2 << 26) | ycode | mcode, k1);
-            }
-            // 2. their candidates in one loop: a lane's trip count is its slab total.  The
-            // next candidate (and, at a run's end, the next run from LDS) is found while
-            // the current one's coordinates are in flight.
-            const int2* rp = buf;
-            const int2* const rend = buf + nr * bstride;
-            int j = 0, je = 0, code = 0;
-            float xs = 0.0f, ys = 0.0f;
-            if (rp < rend) {
-                const NlRun u = nl_run(*rp, xf0, xf1, xf2, yf0, yf1, yf2);
-                j = u.j;
-                je = u.e;
-                code = u.code;
-                xs = u.xs;
-                ys = u.ys;
-                rp += bstride;
-            }
-            while (j < je) {
-                const float4 o = sxyzf[j];
-                int jn = j + 1, jen = je, coden = code;
-                float xsn = xs, ysn = ys;
-                if (jn >= je && rp < rend) {
-                    const NlRun u = nl_run(*rp, xf0, xf1, xf2, yf0, yf1, yf2);
-                    jn = u.j;
-                    jen = u.e;
-                    coden = u.code;
-                    xsn = u.xs;
-                    ysn = u.ys;
-                    rp += bstride;
-                }
-                const float dx = xs - o.x;
-                const float dy = ys - o.y;
-                const float dz = zef - zsf * o.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                // a zero FP32 distance may be a distinct (coincident in FP32) pair
-                if (r2 < cutf && j != self) {
-                    h0 = h1;
-                    h1 = h2;
-                    h2 = h3;
-                    h3 = j | code;
-                    ++nh;
-                    if ((nh & 3) == 0 && nh <= P.cap)
-                        chunks[(size_t)((nh >> 2) - 1) * n] = make_int4(h0, h1, h2, h3);
-                }
-                j = jn;
-                je = jen;
-                code = coden;
-                xs = xsn;
-                ys = ysn;
-            }
-        }
-    }
-    // the incomplete last chunk: its m = nh mod 4 hits are the newest m of h0..h3
-    const int m = nh & 3;
-    if (m && nh <= P.cap)
-        chunks[(size_t)(nh >> 2) * n] =
-            m == 1 ? make_int4(h3, 0, 0, 0) : (m == 2 ? make_int4(h2, h3, 0, 0) : make_int4(h1, h2, h3, 0));
-    count[i] = nh;
-}
-
-template <int R>
-__global__ void __launch_bounds__(256)
-near_list_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
-                 const float4* __restrict__ sxyzf,
-                 const int* __restrict__ bin_start, int* __restrict__ list,
-                 int* __restrict__ count) {
-    extern __shared__ int2 nl_buf[];
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    near_list_one<R>(g, P, i, n, sxyzq, sxyzf, bin_start, list, count, nl_buf + threadIdx.x,
-                     blockDim.x);
-}
-
-// Batched: ion i (cell-list order) belongs to channel ion_rep[i]; its bins start at the
-// channel's bin offset, and its list entries are batch-wide sorted indices.
-template <int R>
-__global__ void __launch_bounds__(256)
-near_list_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
-                       NearDev P, int n, const double4* __restrict__ sxyzq,
-                       const float4* __restrict__ sxyzf,
-                       const int* __restrict__ bin_start, int* __restrict__ list,
-                       int* __restrict__ count) {
-    extern __shared__ int2 nl_buf[];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const RepDev& Rp = reps[ion_rep[i]];
-    near_list_one<R>(Rp.g, P, i, n, sxyzq, sxyzf, bin_start + Rp.bin_off, list, count,
-                     nl_buf + threadIdx.x, blockDim.x);
-}
-
-// The list pass for search radii of 1 to 3 bins (larger radii are rejected up front).
-static int launch_near_list(const NearDev& P, int n, int T, hipStream_t s, const GridDev* g,
-                            const RepDev* reps, const int* ion_rep, const double4* sxyzq,
-                            const float4* sxyzf, const int* bin_start, int* list, int* count) {
-    if (P.R < 1 || P.R > 3 || T > 256) return DISCOS_E_ARG;
-    const size_t lds = (size_t)NL_SLAB_RUNS(P.R) * T * sizeof(int2);
-    const int nb = (n + T - 1) / T;
-#define NL_LAUNCH(RR)                                                                           \
-    if (g)                                                                                      \
-        near_list_kernel<RR><<<nb, T, lds, s>>>(*g, P, n, sxyzq, sxyzf, bin_start, list, count); \
-    else                                                                                        \
-        near_list_batch_kernel<RR><<<nb, T, lds, s>>>(reps, ion_rep, P, n, sxyzq, sxyzf,        \
-                                                      bin_start, list, count);
-    if (P.R == 1) {
-        NL_LAUNCH(1)
-    } else if (P.R == 2) {
-        NL_LAUNCH(2)
-    } else {
-        NL_LAUNCH(3)
-    }
-#undef NL_LAUNCH
-    return DISCOS_OK;
-}
-
-// Pair forces of ion i from its list (or, when the list overflowed, from a direct
-// walk of the cell list), plus the 9-3 wall force.
-__device__ __forceinline__ void list_force(int i, int n, double4 me, int spi,
-                                           const double4* __restrict__ sxyzq,
-                                           const int* __restrict__ ssp,
-                                           const int* __restrict__ bin_start,
-                                           const int* __restrict__ list, int cnt, const GridDev& g,
-                                           const NearDev& P, double& Fx, double& Fy, double& Fz) {
-    const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (cnt <= P.cap) {
-        const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
-        const int4* chunks = reinterpret_cast<const int4*>(list);
-        // the next chunk's entries load while this chunk's pairs are evaluated
-        int4 chn = cnt > 0 ? chunks[i] : make_int4(0, 0, 0, 0);
-        for (int k4 = 0; k4 < cnt; k4 += 4) {
-            const int4 ch = chn;
-            if (k4 + 4 < cnt) chn = chunks[(size_t)((k4 >> 2) + 1) * n + i];
-            const int m4 = min(4, cnt - k4);
-            // the four gathers are issued together (unused slots read the ion itself)
-            double4 ob[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = u == 0 ? ch.x : (u == 1 ? ch.y : (u == 2 ? ch.z : ch.w));
-                ob[u] = sxyzq[u < m4 ? (e & 0x3FFFFFF) : i];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u >= m4) break;
-                const int e = u == 0 ? ch.x : (u == 1 ? ch.y : (u == 2 ? ch.z : ch.w));
-                const int j = e & 0x3FFFFFF;
-                const int mode = (e >> 30) & 3;
-                const double4 o = ob[u];
-                const double dx = (xi - shift_of((e >> 26) & 3, g.Lx)) - o.x;
-                const double dy = (yi - shift_of((e >> 28) & 3, g.Ly)) - o.y;
-                const double dz = mode == 0 ? zi - o.z : (mode == 1 ? zi + o.z : zi - (2.0 * g.Lz - o.z));
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double sg = mode == 0 ? 1.0 : (mode == 1 ? P.s_lo : P.s_hi);
-                // the list is a superset (FP32 filter): the exact FP64 tests decide, and a
-                // pair at zero separation has no direction and contributes nothing
-                if (r2 < P.psi2 && r2 > 0.0) es_pair_r2(dx, dy, dz, r2, qi * (sg * o.w), P, fx, fy, fz);
-                if (P.lj_on && mode == 0 && r2 < r2lj && r2 > 0.0) lj_pair(dx, dy, dz, spi, ssp[j], P, fx, fy, fz);
-            }
-        }
-    } else {
-        near_force_global(i, me, spi, sxyzq, ssp, bin_start, g, P, fx, fy, fz);
-    }
-    if (P.wall_on) fz += -du93(zi, P) + du93(g.Lz - zi, P);
-    Fx = fx;
-    Fy = fy;
-    Fz = fz;
 }
 
 // ---- dry update --------------------------------------------------------------
@@ -633,22 +248,428 @@ struct FusedUpdate {
     int* sp;
 };
 
-__global__ void __launch_bounds__(256)
-near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
-                 const int* __restrict__ ssp, const int* __restrict__ bin_start,
-                 const int* __restrict__ list, const int* __restrict__ count,
-                 const int* __restrict__ perm, double* __restrict__ out, int64_t stride,
-                 int scatter, int* __restrict__ flags, FusedUpdate U) {
-    __shared__ double tab[NL_TAB];
-    const int nt = min(P.tablen, NL_TAB);
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
-    __syncthreads();
-    P.tab = tab;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+// ---- the near-field pass's padded cell list ----------------------------------------
+// A copy of the cell list in which every search row of the pass is one contiguous run
+// and every candidate already sits where the pair sees it.  Padded bins (px, py, pz),
+// px in [0, nbx + 2R) (likewise y) and pz in [0, nbz + 2R + (nz odd)), x fastest:
+//   - px - R and py - R are the real bins, periodic: the R bins on either side hold the
+//     copies of the bins across the periodic seam, with x (y) shifted by the period;
+//   - pz - R in [0, nbz) are the real slabs; the R slabs beyond each wall hold the
+//     mirror images of the R slabs next to it (Sec. II.B.1): z -> -z below the lower
+//     wall and z -> 2 Lz - z above the upper one, charge times the wall's image sign,
+//     species -1 (the images carry no short-range force).
+// Each real bin's ions keep their order in every copy, so the copy of the ion of rank k
+// of a real bin is entry k of the padded bin.  Only first images are needed: a second
+// reflection lies at least Lz >= 4 h away, beyond every cutoff the pass accepts.
+
+// With nz odd the last real slab is one cell thick, so the image slabs above the upper
+// wall sit one cell off the two-cell bin grid: a window of R slabs around an ion then
+// spans only 2R - 1 cells above the wall, and the upper side gets one image slab more
+// (and the pass searches one slab further up).
+__host__ __device__ __forceinline__ int pad_top(const GridDev& g, int R) { return R + (g.nz & 1); }
+
+// Real bin (channel-local) whose ions padded bin P holds, or -1 (a mirrored slab that
+// does not exist in a channel thinner than the image layers).
+__device__ __forceinline__ int pad_source(const GridDev& g, int R, int P) {
+    const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
+    const int px = P % PX, py = (P / PX) % PY, pz = P / (PX * PY);
+    const int bx = wrapi(px - R, g.nbx), by = wrapi(py - R, g.nby);
+    int t = pz - R;
+    if (t < 0)
+        t = -t - 1;
+    else if (t >= g.nbz)
+        t = 2 * g.nbz - 1 - t;
+    if (t < 0 || t >= g.nbz) return -1;
+    return (t * g.nby + by) * g.nbx + bx;
+}
+
+int64_t near_list_bins(const GridDev& g, int R) {
+    return (int64_t)(g.nbx + 2 * R) * (g.nby + 2 * R) * (g.nbz + R + pad_top(g, R));
+}
+
+// Copies per ion: at most two in x and two in y (2R + 1 <= nbx, nby, so no bin is within
+// R of both seams), and in z the ion itself plus one image per wall within the image
+// layers (both walls only when nbz < 2R + 1); sized for R up to 3.
+int64_t near_list_entries(const GridDev& g, int64_t n) {
+    return std::max<int64_t>(n, 1) * 4 * (g.nbz < 7 ? 3 : 2);
+}
+
+__global__ void pad_count_kernel(GridDev g, int R, int64_t nb, const int* __restrict__ bin_start,
+                                 int* __restrict__ count) {
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < nb;
+         P += (int64_t)gridDim.x * blockDim.x) {
+        const int s = pad_source(g, R, (int)P);
+        count[P] = s < 0 ? 0 : bin_start[s + 1] - bin_start[s];
+    }
+}
+
+// Batched: padded bin P belongs to the channel r with pbin_off[r] <= P < pbin_off[r + 1].
+__global__ void pad_count_batch_kernel(const RepDev* __restrict__ reps, int nrep, int R,
+                                       const int* __restrict__ pbin_off, const int* __restrict__ bin_start,
+                                       int* __restrict__ count) {
+    const int64_t nb = pbin_off[nrep];
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < nb;
+         P += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nrep - 1;
+        while (lo < hi) {  // last channel with pbin_off[r] <= P
+            const int mid = (lo + hi + 1) >> 1;
+            if (pbin_off[mid] <= P)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const RepDev& Rp = reps[lo];
+        const int s = pad_source(Rp.g, R, (int)(P - pbin_off[lo]));
+        count[P] = s < 0 ? 0 : bin_start[Rp.bin_off + s + 1] - bin_start[Rp.bin_off + s];
+    }
+}
+
+struct NlOut {
+    double4* xyzq;
+    float4* xyzf;
+    int* sp;
+    int64_t cap;
+    int* flags;
+};
+
+// Every copy of sorted ion i (channel-local real bin b, rank k in it).  pstart: the
+// channel's padded starts.  An ion outside the channel (flagged by the binning) still
+// fills its slots, with coordinates that no distance test accepts.
+__device__ __forceinline__ void pad_scatter_one(const GridDev& g, int R, int b, int k, double4 a,
+                                                int spi, double s_lo, double s_hi,
+                                                const int* __restrict__ pstart, const NlOut& o) {
+    const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
+    const int bx = b % g.nbx, by = (b / g.nbx) % g.nby, bz = b / (g.nbx * g.nby);
+    const bool ok = pos_ok(g, a.x, a.y, a.z);
+    int pxs[2], pys[2], pzs[3], nzk = 1;
+    double sxs[2], sys[2];
+    int zkind[3];
+    pxs[0] = bx + R;
+    sxs[0] = 0.0;
+    int ncx = 1;
+    if (bx < R) { pxs[1] = bx + R + g.nbx; sxs[1] = g.Lx; ncx = 2; }
+    else if (bx >= g.nbx - R) { pxs[1] = bx + R - g.nbx; sxs[1] = -g.Lx; ncx = 2; }
+    pys[0] = by + R;
+    sys[0] = 0.0;
+    int ncy = 1;
+    if (by < R) { pys[1] = by + R + g.nby; sys[1] = g.Ly; ncy = 2; }
+    else if (by >= g.nby - R) { pys[1] = by + R - g.nby; sys[1] = -g.Ly; ncy = 2; }
+    pzs[0] = bz + R;
+    zkind[0] = 0;
+    if (bz < R) { pzs[nzk] = R - 1 - bz; zkind[nzk++] = 1; }
+    if (bz >= g.nbz - pad_top(g, R)) { pzs[nzk] = R + 2 * g.nbz - 1 - bz; zkind[nzk++] = 2; }
+    const double bad = __builtin_nan("");
+    for (int cz = 0; cz < nzk; ++cz) {
+        const double zc = zkind[cz] == 0 ? a.z : (zkind[cz] == 1 ? -a.z : 2.0 * g.Lz - a.z);
+        const double qc = zkind[cz] == 0 ? a.w : (zkind[cz] == 1 ? s_lo : s_hi) * a.w;
+        const int spc = zkind[cz] == 0 ? spi : -1;
+        for (int cy = 0; cy < ncy; ++cy)
+            for (int cx = 0; cx < ncx; ++cx) {
+                const int P = (pzs[cz] * PY + pys[cy]) * PX + pxs[cx];
+                const int64_t d = (int64_t)pstart[P] + k;
+                if (d >= o.cap) {
+                    set_flag(o.flags, DISCOS_FLAG_CAPACITY);
+                    continue;
+                }
+                const double xc = ok ? a.x + sxs[cx] : bad, yc = a.y + sys[cy];
+                o.xyzq[d] = make_double4(xc, yc, zc, qc);
+                o.xyzf[d] = make_float4((float)xc, (float)yc, (float)zc, 0.0f);
+                o.sp[d] = spc;
+            }
+    }
+}
+
+__global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double s_hi,
+                                   const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
+                                   const int* __restrict__ perm, const int* __restrict__ ion_bin,
+                                   const int* __restrict__ bin_start,
+                                   const int* __restrict__ pstart, NlOut o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int b = ion_bin[perm[i]];
+    pad_scatter_one(g, R, b, i - bin_start[b], sxyzq[i], ssp ? ssp[i] : 0, s_lo, s_hi, pstart, o);
+}
+
+__global__ void pad_scatter_batch_kernel(const RepDev* __restrict__ reps,
+                                         const int* __restrict__ ion_rep, int R, int n,
+                                         const double4* __restrict__ sxyzq,
+                                         const int* __restrict__ ssp, const int* __restrict__ perm,
+                                         const int* __restrict__ ion_bin,
+                                         const int* __restrict__ bin_start,
+                                         const int* __restrict__ pbin_off,
+                                         const int* __restrict__ pstart, NlOut o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = ion_rep[i];
+    const RepDev& Rp = reps[r];
+    const int b = ion_bin[perm[i]];  // batch-wide bin
+    pad_scatter_one(Rp.g, R, b - Rp.bin_off, i - bin_start[b], sxyzq[i], ssp[i], Rp.s_lo, Rp.s_hi,
+                    pstart + pbin_off[r], o);
+}
+
+// ---- the near-field pass ----------------------------------------------------------
+// One lane per ion, consecutive ions of the cell list in consecutive lanes.  Each lane
+// visits the 2R + 1 padded slabs around its ion (real slabs and, next to a wall, its
+// image slabs):
+//   1. the slab's 2R + 1 rows are cut to the search sphere (the slab and the row at
+//      their nearest distance; in x the bins the sphere's chord reaches), and each
+//      row's run of candidates goes to the lane's column of an LDS buffer;
+//   2. one loop tests the slab's candidates in FP32 against the cutoff widened by a
+//      bound of the FP32 error of the squared distance (coordinates below
+//      2 Lmax, Lmax = max(Lx, Ly, 2 Lz), distances below the search radius: the margin
+//      32 r_cut Lmax 2^-24), so the hits are a superset of the pairs, and appends every
+//      hit (its padded index) to the lane's column of an LDS hit buffer;
+//   3. as soon as one lane's buffer is full, every lane of the wavefront evaluates the
+//      pairs in its own buffer (the exact FP64 cutoff, the P3M pair force, LJ) and
+//      empties it; after the last slab the remaining buffers are evaluated.
+// No neighbour list goes to memory, and the buffer size bounds nothing: denser systems
+// only flush more often.  The slab and candidate loops have wavefront-uniform trip
+// counts (a lane whose runs are exhausted idles), so a flush has every lane active.
+
+#ifndef NF_THREADS
+#define NF_THREADS 128  // two wavefronts per workgroup (they share the table)
+#endif
+#ifndef NF_HITS
+#define NF_HITS 16      // hit buffer entries per lane (a multiple of NF_GROUP)
+#endif
+#ifndef NF_GROUP
+#define NF_GROUP 1      // buffered pairs whose gathers are issued ahead together
+#endif
+#define NL_TAB 320
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+template <int R>
+struct NfShared {
+    int2 runs[2 * R + 2][NF_THREADS];  // a slab's runs, and one slot read past the last
+    int hits[NF_HITS][NF_THREADS];
+    double tab[NL_TAB];
+};
+
+// The padded list as the pass reads it.
+struct NlView {
+    const int* start;
+    const double4* xyzq;
+    const float4* xyzf;
+    const int* sp;
+};
+
+// Pair forces of the m entries buffered in this lane's column (entry k at
+// col[k * NF_THREADS]) on the ion at (xi, yi, zi) with charge qi, species spi.  The four
+// gathers of a group of entries are issued together (a group's unused slots read the
+// first entry's copy again).
+__device__ __forceinline__ void nf_pairs(const int* col, int m, double xi, double yi, double zi,
+                                         double qi, int spi, const NearDev& P, const NlView& L,
+                                         double& fx, double& fy, double& fz) {
+    const double r2lj = P.rsearch * P.rsearch * (1.0 + 1e-12);
+    if (m <= 0) return;
+    // group k + NF_GROUP's entries and gathers are in flight while group k is evaluated
+    int e[NF_GROUP];
+    double4 ob[NF_GROUP];
+#pragma unroll
+    for (int u = 0; u < NF_GROUP; ++u) e[u] = col[u * NF_THREADS];
+#pragma unroll
+    for (int u = 0; u < NF_GROUP; ++u) ob[u] = L.xyzq[u < m ? e[u] : e[0]];
+    for (int k = 0; k < m; k += NF_GROUP) {
+        const int m4 = min(NF_GROUP, m - k);
+        const int kn = k + NF_GROUP < m ? k + NF_GROUP : k;
+        int en[NF_GROUP];
+        double4 obn[NF_GROUP];
+#pragma unroll
+        for (int u = 0; u < NF_GROUP; ++u) en[u] = col[(kn + u) * NF_THREADS];
+#pragma unroll
+        for (int u = 0; u < NF_GROUP; ++u) obn[u] = L.xyzq[kn + u < m ? en[u] : en[0]];
+#pragma unroll
+        for (int u = 0; u < NF_GROUP; ++u) {
+            if (u >= m4) break;
+            const double dx = xi - ob[u].x, dy = yi - ob[u].y, dz = zi - ob[u].z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            // the buffer is a superset (FP32 filter): the exact FP64 tests decide, and a
+            // pair at zero separation has no direction and contributes nothing
+            if (r2 < P.psi2 && r2 > 0.0) es_pair_r2(dx, dy, dz, r2, qi * ob[u].w, P, fx, fy, fz);
+            if (P.lj_on && r2 < r2lj && r2 > 0.0) lj_pair(dx, dy, dz, spi, L.sp[e[u]], P, fx, fy, fz);
+        }
+#pragma unroll
+        for (int u = 0; u < NF_GROUP; ++u) {
+            e[u] = en[u];
+            ob[u] = obn[u];
+        }
+    }
+}
+
+// Extent in z of padded slab t - R (t = pz - R, channel-local): a real slab, or the
+// mirror image of one beyond a wall; empty (lo > hi) if that slab does not exist.
+__device__ __forceinline__ void slab_extent(const GridDev& g, int t, double& lo, double& hi) {
+    const double Bh = DISCOS_BIN * g.h;
+    if (t >= 0 && t < g.nbz) {
+        lo = t * Bh;
+        hi = fmin((t + 1) * Bh, g.Lz);
+    } else {
+        const int s = t < 0 ? -t - 1 : 2 * g.nbz - 1 - t;
+        if (s < 0 || s >= g.nbz) {
+            lo = 1.0;
+            hi = 0.0;
+            return;
+        }
+        const double a = s * Bh, b = fmin((s + 1) * Bh, g.Lz);
+        lo = t < 0 ? -b : 2.0 * g.Lz - b;
+        hi = t < 0 ? -a : 2.0 * g.Lz - a;
+    }
+}
+
+// Near-field, wall (and LJ) force of ion i of the cell list (x, y reduced into [0, L];
+// real bin (bx, by, bz); self: its own real entry in the padded list) into (fx, fy, fz).
+template <int R>
+__device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int bx, int by, int bz,
+                                       int self, double4 me, int spi, const NlView& L,
+                                       const int* __restrict__ pstart, NfShared<R>& sh,
+                                       double& fx, double& fy, double& fz) {
+    const int lane = threadIdx.x;
+    const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
+    const double Bh = DISCOS_BIN * g.h;
+    const double inv_Bh = 1.0 / Bh;
+    const double rs2 = P.rsearch * P.rsearch;
+    const double r2cut = fmax(P.psi2, P.lj_on ? rs2 * (1.0 + 1e-12) : 0.0);
+    const double Lmax = fmax(fmax(g.Lx, g.Ly), 2.0 * g.Lz);
+    const double margin = 32.0 * sqrt(r2cut) * Lmax * 0x1.0p-24;
+    const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
+    const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
+    int2* const rcol = &sh.runs[0][lane];
+    int* const hcol = &sh.hits[0][lane];
+    int cnt = 0;
+    const int dz_hi = R + (g.nz & 1);  // one slab more with the offset upper image layers
+#pragma unroll 1
+    for (int dzb = -R; dzb <= dz_hi; ++dzb) {
+        const int t = bz + dzb;
+        const bool image = t < 0 || t >= g.nbz;
+        double zb0, zb1;
+        slab_extent(g, t, zb0, zb1);
+        const double dzm = fmax(0.0, fmax(zb0 - zi, zi - zb1));
+        // images carry only the electrostatic correction: their search radius is psi
+        const double remz = (zb0 <= zb1) ? (image ? P.psi2 : rs2) - dzm * dzm : -1.0;
+        const float cutf = (float)((image ? P.psi2 : r2cut) * (1.0 + 1e-5) + margin);
+        // 1. the slab's runs, one per row: every row's bounds are computed and loaded
+        // together (a row cut away loads a valid index and is dropped), then the
+        // non-empty runs go to LDS
+        int nr = 0;
+        if (remz > 0.0) {
+            const int slab = (t + R) * PY;
+            int a0[2 * R + 1], a1[2 * R + 1];
+            bool keep[2 * R + 1];
+#pragma unroll
+            for (int r = 0; r < 2 * R + 1; ++r) {
+                const int dyb = r - R;
+                const double yb0 = (by + dyb) * Bh;
+                const double dym = fmax(0.0, fmax(yb0 - yi, yi - (yb0 + Bh)));
+                const double rem = remz - dym * dym;
+                // half chord of the search sphere in x; the FP32 root (within 2^-22
+                // relative of the exact one) is widened so that the bin range can only grow
+                const double wx = (double)__builtin_amdgcn_sqrtf((float)fmax(rem, 0.0)) *
+                                      (1.0 + 0x1.0p-18) + 0x1.0p-20 * Bh;
+                const int bxl = max(bx - R, (int)floor((xi - wx) * inv_Bh));
+                const int bxh = min(bx + R, (int)floor((xi + wx) * inv_Bh));
+                keep[r] = rem > 0.0 && bxl <= bxh;
+                const int row = (slab + by + dyb + R) * PX + R;
+                a0[r] = keep[r] ? row + bxl : row;
+                a1[r] = keep[r] ? row + bxh + 1 : row;
+            }
+            int j0[2 * R + 1], j1[2 * R + 1];
+#pragma unroll
+            for (int r = 0; r < 2 * R + 1; ++r) {
+                j0[r] = pstart[a0[r]];
+                j1[r] = pstart[a1[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < 2 * R + 1; ++r)
+                if (keep[r] && j0[r] < j1[r]) rcol[(nr++) * NF_THREADS] = make_int2(j0[r], j1[r]);
+        }
+        // 2. their candidates in one loop without branches: each iteration first steps
+        // to the next candidate (the next run's bounds were read from LDS ahead of time)
+        // and issues its load, then tests the current one, whose coordinates arrived
+        // meanwhile, and writes it to the hit buffer's next slot (kept only on a hit).
+        int j = 0, je = 0, k = 0;
+        if (nr > 0) {
+            const int2 u = rcol[0];
+            j = u.x;
+            je = u.y;
+            k = 1;
+        }
+        int2 un = rcol[k * NF_THREADS];  // the run after the current one (if k < nr)
+        float4 o = L.xyzf[j < je ? j : 0];
+        for (;;) {
+            const bool act = j < je;
+            if (!wave_any(act)) break;
+            const bool sw = j + 1 >= je && k < nr;
+            const int jn = act ? (sw ? un.x : j + 1) : je;
+            const int jen = sw ? un.y : je;
+            k += sw ? 1 : 0;
+            const float4 on = L.xyzf[jn < jen ? jn : 0];
+            if (sw) un = rcol[k * NF_THREADS];
+            const float dx = xf - o.x, dy = yf - o.y, dz = zf - o.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            // a zero FP32 distance may be a distinct (coincident in FP32) pair
+            const bool hit = act && r2 < cutf && j != self;
+            hcol[cnt * NF_THREADS] = j;
+            cnt += hit ? 1 : 0;
+            j = jn;
+            je = jen;
+            o = on;
+            // 3. a full buffer anywhere: every lane evaluates and empties its own
+            if (wave_any(cnt == NF_HITS)) {
+                nf_pairs(hcol, cnt, xi, yi, zi, qi, spi, P, L, fx, fy, fz);
+                cnt = 0;
+            }
+        }
+    }
+    nf_pairs(hcol, cnt, xi, yi, zi, qi, spi, P, L, fx, fy, fz);
+    if (P.wall_on) fz += -du93(zi, P) + du93(g.Lz - zi, P);
+}
+
+// The cell-list bin of a sorted ion (x, y already reduced into [0, L]): the bin the
+// binning gave it, for ions inside the channel.
+__device__ __forceinline__ void sorted_bin(const GridDev& g, double x, double y, double z, int& bx,
+                                           int& by, int& bz) {
+    bx = min(max((int)floor(x * g.inv_h), 0), g.nx - 1) / DISCOS_BIN;
+    by = min(max((int)floor(y * g.inv_h), 0), g.ny - 1) / DISCOS_BIN;
+    bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) / DISCOS_BIN;
+}
+
+// The pass over every ion of a context (BATCH = false: out[o] += F with o = perm[i] if
+// scatter, else i; or with U.pos set, the dry step's update from the complete force
+// out[i] + F) or of a batch (BATCH = true: ion i belongs to channel ion_rep[i], whose
+// grid, bins and padded bins it uses; out[i] += F).
+#ifndef NF_MINW
+#define NF_MINW 5  // waves per SIMD the register allocation is held to
+#endif
+template <int R, bool BATCH>
+__global__ void __launch_bounds__(NF_THREADS, NF_MINW)
+near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                  const int* __restrict__ pbin_off, NearDev P, int n,
+                  const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
+                  const int* __restrict__ bin_start0, NlView L, const int* __restrict__ perm,
+                  double* __restrict__ out, int64_t stride, int scatter, int* __restrict__ flags,
+                  FusedUpdate U) {
+    __shared__ NfShared<R> sh;
+    const int nt = min(P.tablen, NL_TAB);
+    for (int k = threadIdx.x; k < nt; k += NF_THREADS) sh.tab[k] = P.tab[k];
+    __syncthreads();
+    P.tab = sh.tab;
+    const int i = (BATCH ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * NF_THREADS +
+                  (int)threadIdx.x;
+    if (i >= n) return;
+    GridDev g = g0;
+    const int* bin_start = bin_start0;
+    const int* pstart = L.start;
+    if (BATCH) {
+        const int r = ion_rep[i];
+        const RepDev& Rp = reps[r];
+        g = Rp.g;
+        bin_start += Rp.bin_off;
+        pstart += pbin_off[r];
+    }
     const double4 me = sxyzq[i];
     if (!pos_ok(g, me.x, me.y, me.z)) {
-        if (U.pos)
+        if (!BATCH && U.pos)
             update_with_force(g, U.Dd, i, me, ssp[i], U.sid[i], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, U.pos, n,
                               U.q, U.id, U.sp, flags);
         return;
@@ -658,8 +679,19 @@ near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
         spi = ssp[i];
         if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
     }
-    double Fx, Fy, Fz;
-    list_force(i, n, me, spi, sxyzq, ssp, bin_start, list, count[i], g, P, Fx, Fy, Fz);
+    int bx, by, bz;
+    sorted_bin(g, me.x, me.y, me.z, bx, by, bz);
+    const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
+    const int self = pstart[((bz + R) * PY + by + R) * PX + bx + R] +
+                     (i - bin_start[(bz * g.nby + by) * g.nbx + bx]);
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    nf_ion<R>(g, P, bx, by, bz, self, me, spi, L, pstart, sh, Fx, Fy, Fz);
+    if (BATCH) {
+        out[i] += Fx;
+        out[i + stride] += Fy;
+        out[i + 2 * stride] += Fz;
+        return;
+    }
     if (U.pos) {
         update_with_force(g, U.Dd, i, me, ssp[i], U.sid[i], out[i] + Fx, out[i + stride] + Fy,
                           out[i + 2 * stride] + Fz, 0.0, 0.0, 0.0, U.pos, n, U.q, U.id, U.sp, flags);
@@ -671,35 +703,47 @@ near_eval_kernel(GridDev g, NearDev P, int n, const double4* __restrict__ sxyzq,
     out[o + 2 * stride] += Fz;
 }
 
-__global__ void __launch_bounds__(256)
-near_eval_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep, NearDev P,
-                       int n, const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
-                       const int* __restrict__ bin_start, const int* __restrict__ list,
-                       const int* __restrict__ count, double* __restrict__ out,
-                       int* __restrict__ flags) {
-    __shared__ double tab[NL_TAB];
-    const int nt = min(P.tablen, NL_TAB);
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) tab[k] = P.tab[k];
-    __syncthreads();
-    P.tab = tab;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const RepDev& R = reps[ion_rep[i]];
-    const GridDev g = R.g;
-    P.s_lo = R.s_lo;
-    P.s_hi = R.s_hi;
-    const double4 me = sxyzq[i];
-    if (!pos_ok(g, me.x, me.y, me.z)) return;
-    int spi = 0;
-    if (P.lj_on) {
-        spi = ssp[i];
-        if (spi < 0 || spi >= max(P.nsp, 1)) set_flag(flags, DISCOS_FLAG_BAD_SPECIES);
+// The pass for search radii of 1 to 3 bins (larger radii are rejected up front).
+static int launch_near(const NearDev& P, int n, hipStream_t s, const GridDev& g,
+                       const RepDev* reps, const int* ion_rep, const int* pbin_off,
+                       const double4* sxyzq, const int* ssp, const int* bin_start, const NlView& L,
+                       const int* perm, double* out, int64_t stride, int scatter, int* flags,
+                       const FusedUpdate& U) {
+    if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
+    const int nb = (n + NF_THREADS - 1) / NF_THREADS;
+#define NF_LAUNCH(RR)                                                                         \
+    if (reps)                                                                                 \
+        near_field_kernel<RR, true><<<nb, NF_THREADS, 0, s>>>(g, reps, ion_rep, pbin_off, P, n, \
+                                                              sxyzq, ssp, bin_start, L, perm,  \
+                                                              out, stride, scatter, flags, U); \
+    else                                                                                      \
+        near_field_kernel<RR, false><<<nb, NF_THREADS, 0, s>>>(g, reps, ion_rep, pbin_off, P, n, \
+                                                               sxyzq, ssp, bin_start, L, perm, \
+                                                               out, stride, scatter, flags, U);
+    if (P.R == 1) {
+        NF_LAUNCH(1)
+    } else if (P.R == 2) {
+        NF_LAUNCH(2)
+    } else {
+        NF_LAUNCH(3)
     }
-    double Fx, Fy, Fz;
-    list_force(i, n, me, spi, sxyzq, ssp, bin_start + R.bin_off, list, count[i], g, P, Fx, Fy, Fz);
-    out[i] += Fx;
-    out[i + n] += Fy;
-    out[i + 2 * (int64_t)n] += Fz;
+#undef NF_LAUNCH
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
+// The padded list of a context's cell list for search radius R.
+static int build_near_list(Ctx* c, int n, int R, double s_lo, double s_hi, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int64_t nb = near_list_bins(g, R);
+    if (nb > c->nl.bins_cap) return DISCOS_E_ARG;
+    pad_count_kernel<<<(int)std::min<int64_t>((nb + 255) / 256, 4096), 256, 0, s>>>(
+        g, R, nb, c->bin_start, c->nl.count);
+    scan_counts(c->nl.count, nb, c->nl.tmp, c->nl.start, s);
+    const NlOut o{const_cast<double4*>(c->nl.xyzq), const_cast<float4*>(c->nl.xyzf), c->nl.sp,
+                  c->nl.cap, c->flags};
+    pad_scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(g, R, n, s_lo, s_hi, c->sxyzq, c->ssp, c->perm,
+                                                       c->ion_bin, c->bin_start, c->nl.start, o);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 static DryDev dry_of(const discos_params* p, uint64_t step) {
@@ -719,11 +763,9 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
                       int scatter_to_caller, hipStream_t s, int mark, const DryStepOut* upd) {
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
-    const int T = 256;
-    int rc = launch_near_list(P, n, T, s, &c->gd, nullptr, nullptr, c->sxyzq, c->sxyzf,
-                              c->bin_start, c->nlist, c->ncount);
+    if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
+    int rc = build_near_list(c, n, P.R, P.s_lo, P.s_hi, s);
     if (rc) return rc;
-    if (mark >= 0) stage_mark(c, mark, s);
     FusedUpdate U{};
     if (upd) {
         U.Dd = dry_of(p, upd->step);
@@ -733,10 +775,11 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
         U.id = upd->id;
         U.sp = upd->sp;
     }
-    near_eval_kernel<<<(n + T - 1) / T, T, 0, s>>>(c->gd, P, n, c->sxyzq, c->ssp, c->bin_start,
-                                                   c->nlist, c->ncount, c->perm, out, out_stride,
-                                                   scatter_to_caller, c->flags, U);
-    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+    const NlView L{c->nl.start, c->nl.xyzq, c->nl.xyzf, c->nl.sp};
+    rc = launch_near(P, n, s, c->gd, nullptr, nullptr, nullptr, c->sxyzq, c->ssp, c->bin_start, L,
+                     c->perm, out, out_stride, scatter_to_caller, c->flags, U);
+    if (mark >= 0) stage_mark(c, mark, s);
+    return rc;
 }
 
 __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
@@ -776,16 +819,21 @@ __global__ void step_set_kernel(uint64_t* step, uint64_t v) { *step = v; }
 int batch_near(Batch* b, hipStream_t s) {
     const int n = (int)b->n_tot;
     if (n == 0) return DISCOS_OK;
-    NearDev P = near_of_h(b->h, &b->p);
-    P.cap = b->nl_cap;
+    const NearDev P = near_of_h(b->h, &b->p);
+    if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
+    const int nrep = (int)b->reps.size();
+    pad_count_batch_kernel<<<(int)std::min<int64_t>((b->nl.bins_cap + 255) / 256, 4096), 256, 0, s>>>(
+        b->reps_d, nrep, P.R, b->pbin_off, b->bin_start, b->nl.count);
+    scan_counts(b->nl.count, b->nl.bins_cap, b->nl.tmp, b->nl.start, s);
+    const NlOut o{b->nl.xyzq, b->nl.xyzf, b->nl.sp, b->nl.cap, b->flags};
     const int T = b->cfg.ion_block;
-    int rc = launch_near_list(P, n, T, s, nullptr, b->reps_d, b->ion_rep, b->sxyzq, b->sxyzf,
-                              b->bin_start, b->nlist, b->ncount);
-    if (rc) return rc;
-    near_eval_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P, n, b->sxyzq,
-                                                         b->ssp, b->bin_start, b->nlist, b->ncount,
-                                                         b->fp, b->flags);
-    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+    pad_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P.R, n, b->sxyzq,
+                                                         b->ssp, b->perm, b->ion_bin, b->bin_start,
+                                                         b->pbin_off, b->nl.start, o);
+    const NlView L{b->nl.start, b->nl.xyzq, b->nl.xyzf, b->nl.sp};
+    GridDev g{};
+    return launch_near(P, n, s, g, b->reps_d, b->ion_rep, b->pbin_off, b->sxyzq, b->ssp, b->bin_start,
+                       L, nullptr, b->fp, n, 0, b->flags, FusedUpdate{});
 }
 
 int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s) {

@@ -20,8 +20,7 @@ constexpr int64_t NA_SCAN = NA_BINS / 1024 + 2;
 
 // Layout of the scratch array (each part 256-byte aligned).
 constexpr size_t OFF_SXYZQ = 0;
-constexpr size_t OFF_SXYZF = OFF_SXYZQ + al256(NA_IONS * sizeof(double4));
-constexpr size_t OFF_PERM = OFF_SXYZF + al256(NA_IONS * sizeof(float4));
+constexpr size_t OFF_PERM = OFF_SXYZQ + al256(NA_IONS * sizeof(double4));
 constexpr size_t OFF_BIN = OFF_PERM + al256(NA_IONS * sizeof(int));
 constexpr size_t OFF_RANK = OFF_BIN + al256(NA_IONS * sizeof(int));
 constexpr size_t OFF_COUNT = OFF_RANK + al256(NA_IONS * sizeof(int));
@@ -116,7 +115,6 @@ extern "C" int discos_spread_charge_noalloc(const discos_grid* grid, int64_t n, 
     c.ncell = (int64_t)g.nx * g.ny * g.nz;
     c.nbins = nbins;
     c.sxyzq = reinterpret_cast<double4*>(base + OFF_SXYZQ);
-    c.sxyzf = reinterpret_cast<float4*>(base + OFF_SXYZF);
     c.perm = reinterpret_cast<int*>(base + OFF_PERM);
     c.ion_bin = reinterpret_cast<int*>(base + OFF_BIN);
     c.ion_rank = reinterpret_cast<int*>(base + OFF_RANK);

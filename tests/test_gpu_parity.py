@@ -194,6 +194,31 @@ def test_near_field(bc, lj):
     assert rel_l2((out - F0)[:, keep], ref[:, keep]) < 1e-12
 
 
+@pytest.mark.parametrize("bc", [(D, N), (N, D)])
+@pytest.mark.parametrize("nz", [4, 5, 9, 21])
+def test_near_field_channel_heights(bc, nz):
+    """Odd heights (the last bin layer is one cell thick, so the images beyond the upper
+    wall sit one cell off the bin grid) and channels so thin that an ion's search reaches
+    the images of both walls; LJ on, ions on and next to both walls."""
+    nx, ny, n = 32, 16, 900
+    log(f"near_field heights nz={nz} bc={bc}")
+    pos, q = _wall_ions(nx, ny, nz, n, seed=40 + nz)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    species = np.where(q > 0, 0, 1).astype(np.int32)
+    p = _params(bc, nx, ny)
+    p.update(lj_on=True, lj_sigma=np.array([[1.0, 0.8], [0.8, 1.2]]),
+             lj_xi=np.array([[1.0, 2.0], [2.0, 0.5]]), lj_cut_factor=2.5)
+    grid = es.Grid(nx, ny, nz)
+    ref = es.near_field(grid, pos, q, EPS, p["psi"], p["p3m_table"], p["p3m_dr"], bc)
+    ref[2] += shortrange.wall_force(pos[2], grid.L[2], p["wall_sigma"], p["wall_xi"], p["wall_cut"])
+    ref += shortrange.lj_pair_forces(grid.L, pos, species, p["lj_sigma"], p["lj_xi"], 2.5)
+    keep = np.all(np.isfinite(ref), axis=0)
+    ctx = _ctx(nx, ny, nz, n)
+    out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p), species=dev(species)))
+    ctx.check()
+    assert rel_l2(out[:, keep], ref[:, keep]) < 1e-12
+
+
 @pytest.mark.parametrize("psi,h,lj_sigma", [
     (1.5, 1.0, None),   # search radius 1 bin (bins of 2 cells)
     (2.0, 1.0, None),   # 1 bin exactly

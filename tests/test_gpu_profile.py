@@ -23,12 +23,12 @@ def test_profile_all_and_selected_stages():
         ctx.step(*args, dp, k)
     st = ctx.profile_read()
     assert all(st[s] > 0.0 for s in dry)
-    ctx.profile_stages(["near_list", "update"])
+    ctx.profile_stages(["near_field", "update"])
     for k in range(3):
         ctx.step(*args, dp, 3 + k)
     st = ctx.profile_read()
-    assert st["near_list"] > 0.0 and st["update"] > 0.0
-    assert all(st[s] == 0.0 for s in ctx.STAGES if s not in ("near_list", "update"))
+    assert st["near_field"] > 0.0 and st["update"] > 0.0
+    assert all(st[s] == 0.0 for s in ctx.STAGES if s not in ("near_field", "update"))
     ctx.profile_stages([])
     ctx.step(*args, dp, 6)
     assert all(v == 0.0 for v in ctx.profile_read().values())
