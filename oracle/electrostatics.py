@@ -17,6 +17,13 @@ by both implementations):
     -eps dphi/dz(0+) = sigma_lo and +eps dphi/dz(Lz-) = sigma_hi, the only sign
     for which an all-Neumann system is solvable exactly when it is neutral
     (Sec. II.B.1, closing remark on electro-neutrality).
+  * a wall's type is one type for the whole wall, or a map [ny, nx] giving the
+    type of each wall column (i, j) (a metal strip on a dielectric wall,
+    Sec. IV.B; the closing remark of Sec. II.B.1 lets the wall data vary along
+    the wall).  Every rule below then applies column by column: the image sign of
+    a folded kernel node is that of its column, the wall term and the ghost
+    values of a column follow its type, and the image of a charge takes the type
+    of the wall column directly below (above) it.
 """
 import numpy as np
 
@@ -41,8 +48,44 @@ class Grid:
 
 def image_sign(bc):
     """Sign of the image charge (Sec. II.B.1): opposite at a fixed-potential
-    wall, like-signed at a dielectric (Neumann) wall."""
-    return -1.0 if bc == DIRICHLET else 1.0
+    wall, like-signed at a dielectric (Neumann) wall; per column for a type map."""
+    a = np.asarray(bc)
+    if a.ndim == 0:
+        return -1.0 if int(a) == DIRICHLET else 1.0
+    return np.where(a == DIRICHLET, -1.0, 1.0)
+
+
+def type_field(grid, bc):
+    """[ny, nx] types of a wall's columns (one type broadcast, or the map itself)."""
+    a = np.asarray(bc)
+    if a.ndim == 0:
+        return np.full((grid.ny, grid.nx), int(a))
+    if a.shape != (grid.ny, grid.nx):
+        raise ValueError("a wall type map must be [ny, nx]")
+    return a.astype(np.int64)
+
+
+def uniform_type(bc):
+    """The wall's single type, or None when its columns differ."""
+    a = np.unique(np.asarray(bc))
+    return int(a[0]) if len(a) == 1 else None
+
+
+def ion_columns(grid, pos):
+    """Wall column (i, j) of each ion: the cell column containing (x, y)."""
+    L = grid.L
+    ci = np.minimum(np.floor(np.mod(pos[0], L[0]) / grid.h).astype(np.int64), grid.nx - 1)
+    cj = np.minimum(np.floor(np.mod(pos[1], L[1]) / grid.h).astype(np.int64), grid.ny - 1)
+    return ci, cj
+
+
+def source_image_signs(grid, pos, bc):
+    """Image sign of each ion's image at one wall: the type of its wall column."""
+    s = image_sign(bc)
+    if np.ndim(s) == 0:
+        return np.full(pos.shape[1], s)
+    ci, cj = ion_columns(grid, pos)
+    return s[cj, ci]
 
 
 def _check_positions(grid, pos):
@@ -72,19 +115,21 @@ def spread_scalar(grid, pos, w, signs):
     ix, wx = node_weights(pos[0], h, 0.5, nx)
     iy, wy = node_weights(pos[1], h, 0.5, ny)
     iz, wz = node_weights(pos[2], h, 0.5)
-    s = np.ones_like(wz)
     lo = iz < 0
     hi = iz >= nz
     iz = np.where(lo, -1 - iz, np.where(hi, 2 * nz - 1 - iz, iz))
-    s[lo] = signs[0]
-    s[hi] = signs[1]
+    s_lo = np.broadcast_to(np.asarray(signs[0], dtype=np.float64), (ny, nx))
+    s_hi = np.broadcast_to(np.asarray(signs[1], dtype=np.float64), (ny, nx))
     out = np.zeros((nz, ny, nx))
     w = np.asarray(w, dtype=np.float64)
     for c in range(5):
         for b in range(5):
             for a in range(5):
+                # the folded node's sign is that of its own wall column
+                col = (iy[:, b], ix[:, a])
+                s = np.where(lo[:, c], s_lo[col], np.where(hi[:, c], s_hi[col], 1.0))
                 np.add.at(out, (iz[:, c], iy[:, b], ix[:, a]),
-                          w * s[:, c] * wx[:, a] * wy[:, b] * wz[:, c] / h ** 3)
+                          w * s * wx[:, a] * wy[:, b] * wz[:, c] / h ** 3)
     return out
 
 
@@ -106,10 +151,8 @@ def bc_rhs(grid, eps, bc_types, bc_values):
     b = np.zeros((grid.nz, grid.ny, grid.nx))
     for wall, layer in ((0, 0), (1, grid.nz - 1)):
         v = _bc_field(grid, bc_values[wall])
-        if bc_types[wall] == DIRICHLET:
-            b[layer] += 2.0 * eps * v / h ** 2
-        else:
-            b[layer] += v / h
+        t = type_field(grid, bc_types[wall])
+        b[layer] += np.where(t == DIRICHLET, 2.0 * eps * v / h ** 2, v / h)
     return b
 
 
@@ -152,6 +195,10 @@ def solve_poisson(grid, eps, bc_types, rhs, project=False):
     applies the pseudo-inverse to any rhs (the component along the null space is
     dropped): the adjoint of the minimum-norm solve, used by the gradient sweeps.
     """
+    u_lo, u_hi = uniform_type(bc_types[0]), uniform_type(bc_types[1])
+    if u_lo is None or u_hi is None:
+        return _solve_poisson_mixed(grid, eps, bc_types, rhs)
+    bc_types = (u_lo, u_hi)
     nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
     R = np.fft.fft2(rhs, axes=(1, 2)) * (h * h / eps)
     m = np.arange(nx)
@@ -180,6 +227,46 @@ def solve_poisson(grid, eps, bc_types, rhs, project=False):
     return np.real(np.fft.ifft2(X, axes=(1, 2)))
 
 
+def poisson_matrix(grid, eps, bc_types):
+    """-eps lap_h with the homogeneous ghost rule of each wall column as a sparse
+    matrix on the cells, index (k ny + j) nx + i: 7-point stencil, periodic in x
+    and y; the ghost below cell (i, j, 0) is s phi(i, j, 0) with s = -1 for a
+    Dirichlet column and +1 for a Neumann one (likewise above layer nz - 1)."""
+    from scipy import sparse
+    nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
+    c = eps / h ** 2
+    idx = np.arange(nz * ny * nx).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+
+    def add(r, q, v):
+        rows.append(r.ravel())
+        cols.append(q.ravel())
+        vals.append(np.broadcast_to(v, r.shape).ravel())
+
+    diag = np.full((nz, ny, nx), 6.0 * c)
+    diag[0] -= c * image_sign(type_field(grid, bc_types[0]))
+    diag[-1] -= c * image_sign(type_field(grid, bc_types[1]))
+    add(idx, idx, diag)
+    add(idx, np.roll(idx, 1, axis=2), -c)
+    add(idx, np.roll(idx, -1, axis=2), -c)
+    add(idx, np.roll(idx, 1, axis=1), -c)
+    add(idx, np.roll(idx, -1, axis=1), -c)
+    add(idx[1:], idx[:-1], -c)
+    add(idx[:-1], idx[1:], -c)
+    n = nz * ny * nx
+    return sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(n, n))
+
+
+def _solve_poisson_mixed(grid, eps, bc_types, rhs):
+    """Exact solve of the mixed-wall problem: a wall whose columns differ couples the
+    in-plane Fourier modes, so the matrix of poisson_matrix is factored directly
+    (sparse LU).  Such a wall has a Dirichlet column, so the system is nonsingular."""
+    from scipy.sparse.linalg import spsolve
+    A = poisson_matrix(grid, eps, bc_types).tocsc()
+    return spsolve(A, rhs.ravel()).reshape(rhs.shape)
+
+
 def ghost_extend(grid, eps, bc_types, bc_values, phi, depth=3):
     """phi with `depth` ghost layers below and above, filled from the wall BC.
 
@@ -197,12 +284,10 @@ def ghost_extend(grid, eps, bc_types, bc_values, phi, depth=3):
     for m in range(depth):
         for wall in (0, 1):
             v = _bc_field(grid, bc_values[wall])
+            t = type_field(grid, bc_types[wall])
             src = phi[m] if wall == 0 else phi[nz - 1 - m]
             dst = depth - 1 - m if wall == 0 else depth + nz + m
-            if bc_types[wall] == DIRICHLET:
-                out[dst] = 2.0 * v - src
-            else:
-                out[dst] = src + (2 * m + 1) * h * v / eps
+            out[dst] = np.where(t == DIRICHLET, 2.0 * v - src, src + (2 * m + 1) * h * v / eps)
     return out
 
 
@@ -305,7 +390,7 @@ def near_field(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
     h = grid.h
     n = pos.shape[1]
     targets = np.arange(n) if targets is None else np.asarray(targets)
-    s = (image_sign(bc_types[0]), image_sign(bc_types[1]))
+    s = (source_image_signs(grid, pos, bc_types[0]), source_image_signs(grid, pos, bc_types[1]))
     out = np.zeros((3, len(targets)))
     src_sets = [
         (pos, q, False),
@@ -360,13 +445,13 @@ def _near_field_targets(grid, pos, q, eps, psi, table, dr, bc_types, targets):
     pts[:, 1] = np.mod(pts[:, 1], L[1])
     box = [L[0], L[1], 4.0 * L[2] + 8.0 * psi]
     off = 2.0 * psi  # keep every point set inside the tree box in z
-    s = (image_sign(bc_types[0]), image_sign(bc_types[1]))
-    sets = [(pts, np.arange(pos.shape[1]), 1.0)]
+    s = (source_image_signs(grid, pos, bc_types[0]), source_image_signs(grid, pos, bc_types[1]))
+    sets = [(pts, np.arange(pos.shape[1]), np.ones(pos.shape[1]))]
     for wall in (0, 1):
         idx = np.nonzero(pos[2] < psi if wall == 0 else pos[2] > L[2] - psi)[0]
         img = pts[idx].copy()
         img[:, 2] = -img[:, 2] if wall == 0 else 2.0 * L[2] - img[:, 2]
-        sets.append((img, idx, s[wall]))
+        sets.append((img, idx, s[wall][idx]))
     for src, ids, sign in sets:
         if len(ids) == 0:
             continue
@@ -380,7 +465,7 @@ def _near_field_targets(grid, pos, q, eps, psi, table, dr, bc_types, targets):
             continue
         b = np.concatenate([np.asarray(x, dtype=np.int64) for x in lists])
         d = pos[:, t[a]] - np.stack([pos[0, ids[b]], pos[1, ids[b]], src[b, 2]])
-        ok, f = _pair_force(grid, eps, psi, table, dr, q[t[a]], sign * q[ids[b]], d)
+        ok, f = _pair_force(grid, eps, psi, table, dr, q[t[a]], sign[b] * q[ids[b]], d)
         for k in range(3):
             np.add.at(out[k], a[ok], f[k])
     return out
@@ -416,7 +501,7 @@ def near_field_pairs(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
         for k in range(3):
             np.add.at(out[k], i, mag * d[k])
             np.add.at(out[k], j, -mag * d[k])
-    s = (image_sign(bc_types[0]), image_sign(bc_types[1]))
+    s = (source_image_signs(grid, pos, bc_types[0]), source_image_signs(grid, pos, bc_types[1]))
     for wall, near in ((0, pos[2] < psi), (1, pos[2] > L[2] - psi)):
         idx = np.nonzero(near)[0]
         if len(idx) == 0:
@@ -441,7 +526,7 @@ def near_field_pairs(grid, pos, q, eps, psi, table, dr, bc_types, targets=None):
         ok = (r < psi) & (r > 0.0)
         a, b, d, r = a[ok], b[ok], d[:, ok], r[ok]
         g = table_lookup(table, dr, r / h)
-        mag = (q[a] * (s[wall] * q[b])) / (4.0 * np.pi * eps) * (1.0 / r ** 2 - g / h ** 2) / r
+        mag = (q[a] * (s[wall][b] * q[b])) / (4.0 * np.pi * eps) * (1.0 / r ** 2 - g / h ** 2) / r
         for k in range(3):
             np.add.at(out[k], a, mag * d[k])
     return out
