@@ -46,6 +46,8 @@ extern "C" {
 #define DISCOS_E_NOT_NEUTRAL (-5)  /* sticky: both walls Neumann and the system is charged */
 #define DISCOS_E_NONFINITE (-6)    /* sticky: a non-finite position or force */
 #define DISCOS_E_CAPACITY (-7)     /* n larger than the context's n_max; host memory exhausted */
+#define DISCOS_E_NOT_CONVERGED (-8) /* the iterative Poisson solve of mixed walls did not reach
+                                       its tolerance in 1000 iterations */
 
 /* ---- wall boundary conditions for the potential (Sec. II.B.1) --------------- */
 #define DISCOS_BC_DIRICHLET 0 /* fixed potential phi_b (eq esbc1) */
@@ -105,6 +107,22 @@ typedef struct discos_params {
                                    tangential images); with two slip walls the in-plane
                                    mean of the tangential force is solved with its z-mean
                                    removed and zero z-mean flow */
+    /* walls of mixed type (Sec. IV.B: a metal strip on a dielectric wall; Sec. II.B.1,
+       closing remark: the wall data may vary along the wall) */
+    const int32_t* bc_type_map[2]; /* device [ny][nx] per wall, or NULL: the type
+                                   (DISCOS_BC_*) of each wall column (i, j), replacing
+                                   bc_type[w] for that wall.  Column by column: the image
+                                   sign of folded kernel nodes, the wall term, the ghost
+                                   values, and the image of a charge (the type of the column
+                                   below / above the charge).  A wall whose columns differ
+                                   couples the Fourier modes: the Poisson solve is then
+                                   conjugate gradients preconditioned by the per-mode solve
+                                   of a uniform wall pair (Dirichlet for a wall with any
+                                   Dirichlet column), iterated to a residual below 1e-13 of
+                                   the right-hand side; the calls that read a map copy it to
+                                   the host (checking every entry) and synchronise the stream
+                                   to test convergence.  discos_energy_flux(_backward) and
+                                   batches take uniform walls only. */
 } discos_params;
 
 #define DISCOS_HYDRO_NOSLIP 0

@@ -21,6 +21,8 @@ WallDev wall_of(const discos_params* p) {
     w.value[0] = p->bc_value[0];
     w.value[1] = p->bc_value[1];
     w.eps = p->eps;
+    w.map[0] = p->bc_type_map[0];
+    w.map[1] = p->bc_type_map[1];
     return w;
 }
 
@@ -75,6 +77,37 @@ int check_near_params(discos_ctx* c, const discos_params* p, const int32_t* spec
     if (2 * R + 1 > c->gd.nbx || 2 * R + 1 > c->gd.nby)
         return fail(c, DISCOS_E_SHAPE,
                     "cutoff too large for the periodic box (need nx/2, ny/2 >= 2 ceil(psi/2h) + 1)");
+    return DISCOS_OK;
+}
+
+// The wall type maps of p, read on the host (the stream is synchronised first): every
+// entry must be a DISCOS_BC_* type.  q receives p with bc_type[w] replaced by the type of
+// a uniform map, or for a wall whose columns differ by the preconditioner's reference
+// type (Dirichlet); c->wm_mixed records whether a wall's columns differ.
+int read_wall_maps(discos_ctx* c, const discos_params* p, hipStream_t s, discos_params& q) {
+    q = *p;
+    c->wm_mixed = 0;
+    c->wm_ref[0] = p->bc_type[0];
+    c->wm_ref[1] = p->bc_type[1];
+    if (!p->bc_type_map[0] && !p->bc_type_map[1]) return DISCOS_OK;
+    const size_t ncol = (size_t)c->gd.nx * c->gd.ny;
+    std::vector<int32_t> m(ncol);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(c, DISCOS_E_HIP, "stream failed");
+    for (int w = 0; w < 2; ++w) {
+        if (!p->bc_type_map[w]) continue;
+        if (hipMemcpy(m.data(), p->bc_type_map[w], ncol * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return fail(c, DISCOS_E_HIP, "reading a wall type map failed");
+        size_t nd = 0, nn = 0;
+        for (size_t k = 0; k < ncol; ++k) {
+            nd += m[k] == DISCOS_BC_DIRICHLET;
+            nn += m[k] == DISCOS_BC_NEUMANN;
+        }
+        if (nd + nn != ncol) return fail(c, DISCOS_E_ARG, "bc_type_map entries must be DISCOS_BC_*");
+        q.bc_type[w] = nd > 0 ? DISCOS_BC_DIRICHLET : DISCOS_BC_NEUMANN;
+        c->wm_ref[w] = q.bc_type[w];
+        if (nd > 0 && nn > 0) c->wm_mixed = 1;
+    }
     return DISCOS_OK;
 }
 
@@ -214,6 +247,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     bytes += carve_bytes(64, sizeof(int));
     bytes += carve_bytes(2 * PART_MAX, sizeof(double));                 // reduction partials
     bytes += carve_bytes(2 * (size_t)g.nx * g.ny, sizeof(double));     // wall adjoints
+    bytes += carve_bytes(3 * (size_t)c->ncell, sizeof(double)) + carve_bytes(8, sizeof(double));  // CG
     // the near field's padded cell list, sized for search radii up to 3 bins
     const int64_t nl_bins = discos::near_list_bins(g, 3);
     const int64_t nl_cap = discos::near_list_entries(g, n_max);
@@ -246,6 +280,10 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->flags = carve<int>(cur, 64);
     c->part = carve<double>(cur, 2 * PART_MAX);
     c->bcg = carve<double>(cur, 2 * (size_t)g.nx * g.ny);
+    c->pcg = carve<double>(cur, 3 * (size_t)c->ncell);
+    c->pcg_s = carve<double>(cur, 8);
+    c->wm_mixed = 0;
+    c->wm_ref[0] = c->wm_ref[1] = DISCOS_BC_DIRICHLET;
     c->nl.count = carve<int>(cur, nl_bins);
     c->nl.start = carve<int>(cur, nl_bins + 1);
     c->nl.tmp = carve<int>(cur, nl_bins / 1024 + 2);
@@ -386,7 +424,11 @@ int discos_solve_poisson(discos_ctx* c, const double* rhs, const discos_params* 
     if (!rhs || !phi) return fail(c, DISCOS_E_ARG, "null array");
     int rc = check_es_params(c, p);
     if (rc) return rc;
-    rc = discos::solve_poisson(c, rhs, p, phi, s);
+    discos_params pm;
+    rc = read_wall_maps(c, p, s, pm);
+    if (rc) return rc;
+    rc = discos::solve_poisson(c, rhs, &pm, phi, s);
+    if (rc == DISCOS_E_NOT_CONVERGED) return fail(c, rc, "mixed-wall Poisson solve did not converge");
     return rc ? fail(c, rc, "poisson launch failed") : DISCOS_OK;
 }
 
@@ -556,6 +598,10 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
         rc = set_hydro_walls(c, p);
         if (rc) return rc;
     }
+    discos_params pm;
+    rc = read_wall_maps(c, p, s, pm);
+    if (rc) return rc;
+    p = &pm;
     const int ni = (int)n;
     double* pos = ions->pos;
     discos::stage_mark(c, 0, s);
@@ -608,6 +654,8 @@ int discos_energy_flux(discos_ctx* c, int64_t n, const double* pos, const double
     c->last_stream = s;
     if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
     if (!phi || !out || (n > 0 && (!pos || !q))) return fail(c, DISCOS_E_ARG, "null array");
+    if (p && (p->bc_type_map[0] || p->bc_type_map[1]))
+        return fail(c, DISCOS_E_ARG, "the energy / flux adjoint takes uniform walls");
     int rc = check_es_params(c, p);
     if (rc) return rc;
     if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
@@ -632,6 +680,8 @@ int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, con
     c->last_stream = s;
     if (n < 0 || n > c->n_max) return fail(c, DISCOS_E_CAPACITY, "n exceeds n_max");
     if (!phi || !g || (n > 0 && (!pos || !q))) return fail(c, DISCOS_E_ARG, "null array");
+    if (p && (p->bc_type_map[0] || p->bc_type_map[1]))
+        return fail(c, DISCOS_E_ARG, "the energy / flux adjoint takes uniform walls");
     int rc = check_es_params(c, p);
     if (rc) return rc;
     if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");

@@ -89,6 +89,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     // the entries the cutoff can reach are copied to LDS by the force pass (320 at most)
     if (p->psi / h / p->p3m_dr + 2.0 > 320.0) return DISCOS_E_ARG;
     if (p->lj_on && (!p->lj_sigma || !p->lj_xi || !finite_pos(p->lj_range))) return DISCOS_E_ARG;
+    if (p->bc_type_map[0] || p->bc_type_map[1]) return DISCOS_E_ARG;  // channels have uniform walls
     const int Rb = discos::near_radius_bins_h(h, p);
     if (Rb > 3) return DISCOS_E_ARG;
     int64_t n_tot = 0;

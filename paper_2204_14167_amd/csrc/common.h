@@ -32,7 +32,15 @@ struct WallDev {
     int type[2];              // DISCOS_BC_*
     const double* value[2];   // [ny][nx] or null (= 0)
     double eps;
+    const int* map[2] = {nullptr, nullptr};  // per-column types [ny][nx] (null: type[w])
 };
+
+// Type of wall column (i, j) (nx columns per row).
+__device__ __forceinline__ int wall_type_at(const WallDev& w, int wall, int i, int j, int nx) {
+    return w.map[wall] ? w.map[wall][(size_t)j * nx + i] : w.type[wall];
+}
+
+#define DISCOS_FLAG_NOT_CONVERGED 32
 
 // One channel of a batch as the kernels see it: its grid and walls, and where its data
 // sit in the batch arrays (cells and spectra grouped by size class, ions and bins in
@@ -229,7 +237,7 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
     const int src = min(max(k < 0 ? m : g.nz - 1 - m, 0), g.nz - 1);
     const double base = phi[((size_t)src * g.ny + j) * g.nx + i];
     const double v = w.value[wall] ? w.value[wall][(size_t)j * g.nx + i] : 0.0;
-    if (w.type[wall] == DISCOS_BC_DIRICHLET) return 2.0 * v - base;
+    if (wall_type_at(w, wall, i, j, g.nx) == DISCOS_BC_DIRICHLET) return 2.0 * v - base;
     return base + (2 * m + 1) * g.h * v / w.eps;
 }
 

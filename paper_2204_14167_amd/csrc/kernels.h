@@ -47,6 +47,12 @@ struct Ctx {
     double* fp;      // [3][n_max] per-ion forces in cell-list order
     double2 *tw_x, *tw_y;
     NearList nl;     // the near-field pass's padded copy of the cell list
+    // conjugate gradients of walls of mixed type: r, p and z / A p, [3][ncell], and the
+    // iteration's scalars; wm_*: the wall maps of the current call (read on the host)
+    double* pcg;
+    double* pcg_s;
+    int wm_mixed;
+    int wm_ref[2];
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
     int hydro;
     double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
@@ -177,6 +183,11 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
 // for any rhs in the all-Neumann case (the adjoint solve), without the neutrality flag.
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
                   int mark_base = -1, int project = 0);
+
+// Poisson solve with walls of mixed type (conjugate gradients preconditioned by the
+// uniform pair ref); returns DISCOS_E_NOT_CONVERGED if the tolerance was not reached.
+int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const int ref[2],
+                        double* phi, hipStream_t s);
 
 // E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi
 // (DISCOS_INTERP_PHI) for the ions of the cell list; out[perm[i]] if scatter, else out[i].

@@ -15,6 +15,7 @@ struct NearDev {
     int tablen;
     int R;  // search radius in bins
     double s_lo, s_hi;
+    const int* map[2];  // per-column wall types (image sign of each source's column)
     int wall_on;
     double wsig, wxi, wcut;
     int lj_on;
@@ -41,6 +42,8 @@ static NearDev near_of_h(double h, const discos_params* p) {
     d.R = (int)std::ceil(range / (DISCOS_BIN * h));
     d.s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    d.map[0] = p->bc_type_map[0];
+    d.map[1] = p->bc_type_map[1];
     d.wall_on = p->wall_on;
     d.wsig = p->wall_sigma;
     d.wxi = p->wall_xi;
@@ -337,10 +340,18 @@ struct NlOut {
 // fills its slots, with coordinates that no distance test accepts.
 __device__ __forceinline__ void pad_scatter_one(const GridDev& g, int R, int b, int k, double4 a,
                                                 int spi, double s_lo, double s_hi,
+                                                const int* const* map,
                                                 const int* __restrict__ pstart, const NlOut& o) {
     const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
     const int bx = b % g.nbx, by = (b / g.nbx) % g.nby, bz = b / (g.nbx * g.nby);
     const bool ok = pos_ok(g, a.x, a.y, a.z);
+    if (ok && (map[0] || map[1])) {
+        // a wall of mixed type: the image takes the type of the column below (above) the ion
+        const int ci = min(max((int)floor(a.x * g.inv_h), 0), g.nx - 1);
+        const int cj = min(max((int)floor(a.y * g.inv_h), 0), g.ny - 1);
+        if (map[0]) s_lo = map[0][(size_t)cj * g.nx + ci] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+        if (map[1]) s_hi = map[1][(size_t)cj * g.nx + ci] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
+    }
     int pxs[2], pys[2], pzs[3], nzk = 1;
     double sxs[2], sys[2];
     int zkind[3];
@@ -380,6 +391,7 @@ __device__ __forceinline__ void pad_scatter_one(const GridDev& g, int R, int b, 
 }
 
 __global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double s_hi,
+                                   const int* map_lo, const int* map_hi,
                                    const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
                                    const int* __restrict__ perm, const int* __restrict__ ion_bin,
                                    const int* __restrict__ bin_start,
@@ -387,7 +399,8 @@ __global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int b = ion_bin[perm[i]];
-    pad_scatter_one(g, R, b, i - bin_start[b], sxyzq[i], ssp ? ssp[i] : 0, s_lo, s_hi, pstart, o);
+    const int* map[2] = {map_lo, map_hi};
+    pad_scatter_one(g, R, b, i - bin_start[b], sxyzq[i], ssp ? ssp[i] : 0, s_lo, s_hi, map, pstart, o);
 }
 
 __global__ void pad_scatter_batch_kernel(const RepDev* __restrict__ reps,
@@ -403,8 +416,9 @@ __global__ void pad_scatter_batch_kernel(const RepDev* __restrict__ reps,
     const int r = ion_rep[i];
     const RepDev& Rp = reps[r];
     const int b = ion_bin[perm[i]];  // batch-wide bin
+    const int* const map[2] = {nullptr, nullptr};  // channels of a batch have uniform walls
     pad_scatter_one(Rp.g, R, b - Rp.bin_off, i - bin_start[b], sxyzq[i], ssp[i], Rp.s_lo, Rp.s_hi,
-                    pstart + pbin_off[r], o);
+                    map, pstart + pbin_off[r], o);
 }
 
 // ---- the near-field pass ----------------------------------------------------------
@@ -732,16 +746,17 @@ static int launch_near(const NearDev& P, int n, hipStream_t s, const GridDev& g,
 }
 
 // The padded list of a context's cell list for search radius R.
-static int build_near_list(Ctx* c, int n, int R, double s_lo, double s_hi, hipStream_t s) {
+static int build_near_list(Ctx* c, int n, int R, double s_lo, double s_hi, const int* const* map,
+                           hipStream_t s) {
     const GridDev& g = c->gd;
     const int64_t nb = near_list_bins(g, R);
     if (nb > c->nl.bins_cap) return DISCOS_E_ARG;
     pad_count_kernel<<<(int)std::min<int64_t>((nb + 255) / 256, 4096), 256, 0, s>>>(
         g, R, nb, c->bin_start, c->nl.count);
     scan_counts(c->nl.count, nb, c->nl.tmp, c->nl.start, s);
-    const NlOut o{const_cast<double4*>(c->nl.xyzq), const_cast<float4*>(c->nl.xyzf), c->nl.sp,
-                  c->nl.cap, c->flags};
-    pad_scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(g, R, n, s_lo, s_hi, c->sxyzq, c->ssp, c->perm,
+    const NlOut o{c->nl.xyzq, c->nl.xyzf, c->nl.sp, c->nl.cap, c->flags};
+    pad_scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(g, R, n, s_lo, s_hi, map[0], map[1], c->sxyzq,
+                                                       c->ssp, c->perm,
                                                        c->ion_bin, c->bin_start, c->nl.start, o);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
@@ -764,7 +779,7 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
-    int rc = build_near_list(c, n, P.R, P.s_lo, P.s_hi, s);
+    int rc = build_near_list(c, n, P.R, P.s_lo, P.s_hi, P.map, s);
     if (rc) return rc;
     FusedUpdate U{};
     if (upd) {

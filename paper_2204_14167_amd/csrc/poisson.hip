@@ -624,6 +624,13 @@ int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
 
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
                   int mark_base, int project) {
+    if (c->wm_mixed && (p->bc_type_map[0] || p->bc_type_map[1])) {
+        // walls of mixed type: the iterative solve (timed whole as the first stage)
+        const int rc = solve_poisson_mixed(c, rhs, p, c->wm_ref, phi, s);
+        if (mark_base >= 0)
+            for (int k = 0; k < 5; ++k) stage_mark(c, mark_base + k, s);
+        return rc;
+    }
     const GridDev& g = c->gd;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;

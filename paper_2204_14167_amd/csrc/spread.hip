@@ -78,16 +78,19 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
         for (int c = 0; c < 4; ++c) {
             int kz = iz0 + c;
             double sgn = 1.0;
+            const int* fmap = nullptr;  // folded onto a wall of mixed type: sign per column
             if (kz < 0) {
                 kz = -1 - kz;
                 sgn = sign_lo;
+                fmap = wall.map[0];
             } else if (kz >= g.nz) {
                 kz = 2 * g.nz - 1 - kz;
                 sgn = sign_hi;
+                fmap = wall.map[1];
             }
             const int lz = kz - z0;
             if (lz < 0 || lz >= tz) continue;
-            const double wzc = scale * sgn * wz[c];
+            const double wzc = scale * (fmap ? 1.0 : sgn) * wz[c];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (lys[b] >= ty) continue;
@@ -95,7 +98,11 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (lxs[a] >= tx) continue;
-                    atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
+                    double v = wyz * wx[a];
+                    if (fmap && fmap[(size_t)((iy0 + b) & (g.ny - 1)) * g.nx + ((ix0 + a) & (g.nx - 1))] ==
+                                    DISCOS_BC_DIRICHLET)
+                        v = -v;
+                    atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], v);
                 }
             }
         }
@@ -111,8 +118,9 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
                 for (int w = 0; w < 2; ++w) {
                     if (gk != (w == 0 ? 0 : g.nz - 1)) continue;
                     const double bv = wall.value[w] ? wall.value[w][(size_t)gj * g.nx + gi] : 0.0;
-                    v += (wall.type[w] == DISCOS_BC_DIRICHLET) ? 2.0 * wall.eps * bv * g.inv_h * g.inv_h
-                                                               : bv * g.inv_h;
+                    v += (wall_type_at(wall, w, gi, gj, g.nx) == DISCOS_BC_DIRICHLET)
+                             ? 2.0 * wall.eps * bv * g.inv_h * g.inv_h
+                             : bv * g.inv_h;
                 }
             }
             out[((size_t)gk * g.ny + gj) * g.nx + gi] = v;

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdiscos.so")
 OK = 0
 E_ARG, E_SHAPE, E_HIP, E_OUT_OF_DOMAIN, E_NOT_NEUTRAL, E_NONFINITE, E_CAPACITY = (
     -1, -2, -3, -4, -5, -6, -7)
+E_NOT_CONVERGED = -8
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 SPREAD_CHARGE, SPREAD_FORCE, SPREAD_ADD_BC = 0, 1, 0x100
 INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
@@ -62,6 +63,7 @@ class DiscosParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("rfd_delta", ctypes.c_double),
         ("hydro_bc", ctypes.c_int32 * 2),
+        ("bc_type_map", ctypes.c_void_p * 2),
     ]
 
 
@@ -167,7 +169,18 @@ class Params:
         self._keep = []
         s = DiscosParams()
         s.eps = p["eps"]
-        s.bc_type[0], s.bc_type[1] = int(p["bc_types"][0]), int(p["bc_types"][1])
+        for w in (0, 1):
+            t = p["bc_types"][w]
+            if np.ndim(t) == 0:
+                s.bc_type[w] = int(t)
+                s.bc_type_map[w] = None
+            else:
+                # a wall of mixed type: the type of every column (the library reads it)
+                m = torch.as_tensor(np.array(np.broadcast_to(t, (ny, nx)), dtype=np.int32, copy=True),
+                                    device=device)
+                self._keep.append(m)
+                s.bc_type_map[w] = m.data_ptr()
+                s.bc_type[w] = BC_DIRICHLET if bool(np.any(np.asarray(t) == BC_DIRICHLET)) else BC_NEUMANN
         for w in (0, 1):
             v = p["bc_values"][w] if p.get("bc_values") is not None else None
             if v is None:

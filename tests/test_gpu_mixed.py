@@ -1,0 +1,183 @@
+"""GPU parity with walls of mixed type (a metal strip on a dielectric wall, Sec. IV.B;
+per-column wall data, Sec. II.B.1): the HIP library through its C ABI against the
+oracle's column-by-column rules and its sparse direct solve.
+
+Bars: the spread 1e-13 (same arithmetic up to summation order); the Poisson solve,
+fields, forces and displacements 1e-10 relative L2 (the conjugate-gradient solve stops at
+a residual of 1e-13 of the right-hand side)."""
+import numpy as np
+import pytest
+
+from oracle import dynamics, electrostatics as es, shortrange
+import workloads
+from tests.gpu_util import TOL, by_id, dev, host, log, min_image, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+D, N = es.DIRICHLET, es.NEUMANN
+EPS = 1.0 / (4.0 * np.pi * 4.46)
+
+
+def _strip(nx, ny, inside=D, outside=N, lo=None, hi=None):
+    lo = nx // 3 if lo is None else lo
+    hi = 2 * nx // 3 if hi is None else hi
+    t = np.full((ny, nx), outside, dtype=np.int32)
+    t[:, lo:hi] = inside
+    return t
+
+
+def _random_map(nx, ny, seed):
+    t = np.random.default_rng(seed).integers(0, 2, size=(ny, nx)).astype(np.int32)
+    t[0, 0] = D
+    return t
+
+
+def _wall_ions(nx, ny, nz, n, seed):
+    pos, q = workloads.random_ions(nx, ny, nz, n, seed, charge="normal")
+    rng = np.random.default_rng(seed + 7)
+    k = n // 3
+    pos[2, :k // 2] = rng.uniform(0.0, 2.5, k // 2)
+    pos[2, k // 2:k] = nz - rng.uniform(0.0, 2.5, k - k // 2)
+    pos[2, 0], pos[2, 1] = 0.0, float(nz)
+    return pos, q
+
+
+def _params(types, nx, ny, values=None):
+    p = workloads.physical_params()
+    p["eps"] = EPS
+    p["bc_types"] = types
+    p["bc_values"] = values if values is not None else (None, None)
+    p["e_ext"] = np.zeros(3)
+    p["p3m_table"], p["p3m_dr"] = workloads.load_p3m_table()
+    return p
+
+
+# sizes at which the oracle's sparse direct solve takes a second or two
+SHAPES = [(32, 16, 16, 1200), (16, 32, 12, 800), (16, 16, 9, 400)]
+
+
+def _cases(nx, ny):
+    return [("strip/dielectric", (_strip(nx, ny), N)),
+            ("dielectric/strip", (N, _strip(nx, ny, inside=N, outside=D))),
+            ("random/random", (_random_map(nx, ny, 1), _random_map(nx, ny, 2))),
+            ("random/grounded", (_random_map(nx, ny, 3), D))]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mixed_spread(shape):
+    from paper_2204_14167_amd import discos
+    nx, ny, nz, n = shape
+    pos, q = _wall_ions(nx, ny, nz, n, seed=nx + nz)
+    rng = np.random.default_rng(4)
+    values = (rng.normal(size=(ny, nx)), rng.normal(size=(ny, nx)))
+    grid = es.Grid(nx, ny, nz)
+    ctx = discos.Context(nx, ny, nz, 1.0, n)
+    for name, types in _cases(nx, ny):
+        log(f"mixed spread {shape} {name}")
+        p = _params(types, nx, ny, values)
+        dp = ctx.params(p)
+        ref = es.spread_charge(grid, pos, q, types)
+        out = host(ctx.spread(discos.SPREAD_CHARGE, dev(pos), dev(q), dp))
+        assert rel_l2(out, ref) < 1e-13
+        ref_bc = ref + es.bc_rhs(grid, EPS, types, values)
+        out_bc = host(ctx.spread(discos.SPREAD_CHARGE | discos.SPREAD_ADD_BC, dev(pos), dev(q), dp))
+        assert rel_l2(out_bc, ref_bc) < 1e-13
+    ctx.check()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mixed_poisson(shape):
+    from paper_2204_14167_amd import discos
+    nx, ny, nz, n = shape
+    grid = es.Grid(nx, ny, nz)
+    ctx = discos.Context(nx, ny, nz, 1.0, n)
+    rng = np.random.default_rng(nx * ny + nz)
+    for name, types in _cases(nx, ny):
+        rhs = rng.normal(size=(nz, ny, nx))
+        ref = es.solve_poisson(grid, EPS, types, rhs)
+        got = host(ctx.solve_poisson(dev(rhs), ctx.params(_params(types, nx, ny))))
+        err = rel_l2(got, ref)
+        log(f"mixed poisson {shape} {name}: rel {err:.2e}")
+        assert err < TOL
+    ctx.check()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mixed_interpolation_and_near_field(shape):
+    from paper_2204_14167_amd import discos
+    nx, ny, nz, n = shape
+    pos, q = _wall_ions(nx, ny, nz, n, seed=3 * nx + nz)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    rng = np.random.default_rng(9)
+    values = (rng.normal(size=(ny, nx)), rng.normal(size=(ny, nx)))
+    grid = es.Grid(nx, ny, nz)
+    ctx = discos.Context(nx, ny, nz, 1.0, n)
+    for name, types in _cases(nx, ny):
+        log(f"mixed interpolation / near field {shape} {name}")
+        p = _params(types, nx, ny, values)
+        dp = ctx.params(p)
+        phi = rng.normal(size=(nz, ny, nx))
+        ext = es.ghost_extend(grid, EPS, types, values, phi)
+        ref = es.interp_field(grid, pos, *es.face_fields(grid, ext))
+        got = host(ctx.interpolate(discos.INTERP_E, dev(pos), dev(phi), dp))
+        assert rel_l2(got, ref) < 1e-13
+        ref_phi = es.interp_scalar(grid, pos, ext)
+        got_phi = host(ctx.interpolate(discos.INTERP_PHI, dev(pos), dev(phi), dp))
+        assert rel_l2(got_phi, ref_phi) < 1e-13
+        refn = es.near_field(grid, pos, q, EPS, p["psi"], p["p3m_table"], p["p3m_dr"], types)
+        refn[2] += shortrange.wall_force(pos[2], grid.L[2], p["wall_sigma"], p["wall_xi"], p["wall_cut"])
+        keep = np.all(np.isfinite(refn), axis=0)
+        outn = host(ctx.near_field(dev(pos), dev(q), dp))
+        assert rel_l2(outn[:, keep], refn[:, keep]) < 1e-12
+    ctx.check()
+
+
+def test_iceo_channel_dry_steps():
+    """An induced-charge electro-osmosis channel (Sec. IV.B in shape): a dielectric lower
+    wall carrying a metal strip held at 1 kT/e across the middle third, a dielectric upper
+    wall, an applied tangential field; two teacher-forced dry steps of every ion against
+    the oracle."""
+    from paper_2204_14167_amd import discos
+    nx, ny, nz, n = 64, 16, 16, 2048
+    t_lo = _strip(nx, ny)
+    v_lo = np.where(t_lo == D, 1.0, 0.0)
+    w = workloads.Workload("iceo_64x16x16_n2048", nx, ny, nz, n, (N, N), (0.0, 0.0),
+                           e_ext=(0.1, 0.0, 0.0), seed=workloads.MASTER_SEED + 11)
+    p = workloads.make_params(w)
+    p["bc_types"] = (t_lo, N)
+    p["bc_values"] = (v_lo, np.zeros((ny, nx)))
+    pos, q, ids, species = workloads.make_ions(w)
+    grid = es.Grid(nx, ny, nz)
+    ctx = discos.Context(nx, ny, nz, 1.0, n)
+    dp = ctx.params(p)
+    dpos, dq, dids, dsp = dev(pos), dev(q), dev(ids), dev(species)
+    for s in range(2):
+        cur_pos, cur_ids = host(dpos), host(dids)
+        order = np.argsort(cur_ids)
+        cur_pos, cur_q, cur_sp = cur_pos[:, order], host(dq)[order], host(dsp)[order]
+        ref, _, _ = dynamics.dry_step(grid, cur_pos, cur_q, cur_sp, cur_ids[order], p, s)
+        ctx.step(dpos, dq, dids, dsp, dp, s)
+        ctx.check()
+        got = by_id(host(dpos), host(dids), cur_ids[order])
+        err = min_image(got - ref, grid.L)
+        disp = min_image(ref - cur_pos, grid.L)
+        r = np.linalg.norm(err) / np.linalg.norm(disp)
+        log(f"iceo dry step {s}: rel {r:.3e}")
+        assert r < TOL
+
+
+def test_mixed_rejections():
+    import torch
+    from paper_2204_14167_amd import discos
+    nx, ny, nz = 16, 16, 8
+    ctx = discos.Context(nx, ny, nz, 1.0, 10)
+    bad = _strip(nx, ny)
+    bad[3, 3] = 7
+    with pytest.raises(discos.DiscosError) as e:
+        ctx.solve_poisson(dev(np.zeros((nz, ny, nx))), ctx.params(_params((bad, N), nx, ny)))
+    assert e.value.code == discos.E_ARG
+    pos, q = _wall_ions(nx, ny, nz, 10, seed=1)
+    with pytest.raises(discos.DiscosError) as e:
+        ctx.energy_flux(dev(pos), dev(q), ctx.params(_params((_strip(nx, ny), N), nx, ny)))
+    assert e.value.code == discos.E_ARG
+    torch.cuda.synchronize()
