@@ -8,12 +8,14 @@ J^es interpolation, P3M near-field + wall force + dry update.  The same workload
 times the energy / electro-osmotic-flux pass and its hand-written adjoint
 (discos_energy_flux, discos_energy_flux_backward) for the adjoint/forward ratio.
 
-The same run times the 512-channel batch and, on the resolved-hydrodynamics channel
-(262,144 ions, 128^3, charged walls), the wet midpoint step with the Peskin kernel and
-with the ESC pair per species.
+The same run times the 512-channel batch, 100 steps of the 65,536-ion dielectric channel
+(128 x 128 x 64, E_x = 0.1) and, on the resolved-hydrodynamics channel (262,144 ions,
+128^3, charged walls), the wet midpoint step with the Peskin kernel and with the ESC pair
+per species.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--adjoint-steps A] [--batch-steps B] [--wet-steps S] [--copy-calibration]
+                [--adjoint-steps A] [--batch-steps B] [--wet-steps S] [--c2-steps S2]
+                [--copy-calibration]
 Prints one JSON line.
 """
 import argparse
@@ -35,11 +37,12 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3  # vector FP32 (no matrix cores)
 
-# Algorithmic work per launch of each stage (bytes that the stage must move, or
-# flops for the compute-bound near-field), for N ions, C cells and H = (nx/2+1) ny nz
-# half-spectrum cells.
+# Algorithmic work per launch of each stage (bytes that the stage must move, or FP64
+# flops for the near-field pass), for N ions, C cells and H = (nx/2+1) ny nz
+# half-spectrum cells, as the survey prices them.
 NEAR_FLOPS_PER_PAIR = 50.0   # FP64 pair work of the P3M correction (pairs within psi, wall
-                             # images included), as the survey prices it
+                             # images included)
+NEAR_BYTES_PER_ION = 84.0    # the near field's minimum HBM bytes: 36 B read + 48 B written
 # peak of the arithmetic each compute-bound stage runs in
 ALU_PEAK = {"near_field": FP64_PEAK_TFLOPS}
 
@@ -115,25 +118,30 @@ def committed_issue(kernel):
     return None if k is None else k["valu_issue_share"]
 
 
-def stage_work(stage, N, C, H, pairs, tests):
+def stage_work(stage, N, C, H, pairs):
+    """(bound, algorithmic work, algorithmic HBM bytes) of one launch of a stage."""
     if stage == "cell_list":
-        return "hbm", 84.0 * N
+        return "hbm", 84.0 * N, 84.0 * N
     if stage == "spread":
-        return "hbm", 32.0 * N + 8.0 * C
+        return "hbm", 32.0 * N + 8.0 * C, 32.0 * N + 8.0 * C
     if stage == "fft_x":
-        return "hbm", 8.0 * C + 16.0 * H
+        return "hbm", 8.0 * C + 16.0 * H, 8.0 * C + 16.0 * H
     if stage in ("fft_y", "ifft_y", "z_solve"):
-        return "hbm", 32.0 * H
+        return "hbm", 32.0 * H, 32.0 * H
     if stage == "ifft_x":
-        return "hbm", 16.0 * H + 8.0 * C
+        return "hbm", 16.0 * H + 8.0 * C, 16.0 * H + 8.0 * C
     if stage == "interp":
-        return "hbm", 56.0 * N + 8.0 * C
+        return "hbm", 56.0 * N + 8.0 * C, 56.0 * N + 8.0 * C
+    if stage == "near_list":
+        # the padded copy of the sorted ions for the near-field pass: the sorted ion, its
+        # bin and permutation entry read (40 B), at least one 52-byte copy written
+        return "hbm", 92.0 * N, 92.0 * N
     if stage == "near_field":
         # the pair forces (the candidate tests and the fused dry update are not counted)
-        return "alu", NEAR_FLOPS_PER_PAIR * pairs
-    # "update": in a dry step the near-field force pass applies the update itself (the
-    # stage is empty); the hydrodynamic stages are empty too
-    return None, None
+        return "alu", NEAR_FLOPS_PER_PAIR * pairs, NEAR_BYTES_PER_ION * N
+    # "update": in a dry step the near-field pass applies the update itself (the stage is
+    # empty); the hydrodynamic stages are empty too
+    return None, None, None
 
 
 def cpu_baseline(w, p, pos, q, ids, species, n_sample=262144):
@@ -176,56 +184,34 @@ def count_pairs(pos, L, psi, sample=4096):
     return float(np.mean(cnt))
 
 
-def count_tests(pos, grid, psi, sample=4096, binw=2):
-    """Mean number of candidate distance tests per ion of the neighbour-list build: the
-    ions of every bin row segment the search visits (bins of binw cells, rows trimmed to
-    the search sphere, wall-image passes for ions within psi of a wall)."""
-    nx, ny, nz, h = grid
-    Bh = binw * h
-    nbx, nby, nbz = nx // binw, ny // binw, (nz + binw - 1) // binw
-    b = np.minimum((pos / Bh).astype(np.int64), np.array([[nbx - 1], [nby - 1], [nbz - 1]]))
-    counts = np.zeros((nbz, nby, nbx), dtype=np.int64)
-    np.add.at(counts, (b[2], b[1], b[0]), 1)
-    R = int(np.ceil(psi / Bh))
-    rng = np.random.default_rng(2)
-    idx = rng.choice(pos.shape[1], sample, replace=False)
-    Lz = nz * h
-    total = 0
-    for i in idx:
-        xi, yi, zi = pos[:, i]
-        bx, by, bz = b[:, i]
-        for mode in range(3):
-            if mode == 0:
-                zl, zh = max(bz - R, 0), min(bz + R, nbz - 1)
-            elif mode == 1:
-                if not zi < psi:
-                    continue
-                zl, zh = 0, min(nbz - 1, int(np.floor(psi / h)) // binw)
-            else:
-                if not zi > Lz - psi:
-                    continue
-                zl, zh = max(0, int(np.floor((Lz - psi) / h)) // binw), nbz - 1
-            for cz in range(zl, zh + 1):
-                zb0, zb1 = cz * Bh, min((cz + 1) * Bh, Lz)
-                dzm = (max(0.0, zb0 - zi, zi - zb1) if mode == 0 else
-                       (zi + zb0 if mode == 1 else (2 * Lz - zb1) - zi))
-                remz = psi * psi - dzm * dzm
-                if remz <= 0:
-                    continue
-                for dyb in range(-R, R + 1):
-                    yb0 = (by + dyb) * Bh
-                    dym = max(0.0, yb0 - yi, yi - (yb0 + Bh))
-                    rem = remz - dym * dym
-                    if rem <= 0:
-                        continue
-                    wx = np.sqrt(rem)
-                    lo = max(bx - R, int(np.floor((xi - wx) / Bh)))
-                    hi = min(bx + R, int(np.floor((xi + wx) / Bh)))
-                    if lo > hi:
-                        continue
-                    cols = np.arange(lo, hi + 1) % nbx
-                    total += int(counts[cz, (by + dyb) % nby, cols].sum())
-    return total / sample
+def c2_timing(steps, warmup=3):
+    """The 65,536-ion dielectric channel (128 x 128 x 64, E_x = 0.1) run for `steps` dry
+    steps (its configuration runs 100) after `warmup` untimed ones; inputs in HBM."""
+    import torch
+    from paper_2204_14167_amd import discos
+    import workloads
+    w = workloads.WORKLOADS["dielectric_128x128x64_n65536"]
+    p = workloads.make_params(w)
+    pos, q, ids, species = workloads.make_ions(w)
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n)
+    dp = ctx.params(gpu_params(p))
+    a = [torch.from_numpy(x.copy()).cuda() for x in (pos, q, ids, species)]
+    for s in range(warmup):
+        ctx.step(*a, dp, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ctx.step(*a, dp, warmup + s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    status = "ok"
+    try:
+        ctx.check()
+    except discos.DiscosError as e:
+        status = str(e)
+    return {"workload": "dielectric_128x128x64_n65536", "n_ions": w.n, "grid": [w.nx, w.ny, w.nz],
+            "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "ion_timesteps_per_s": w.n * steps / el, "device_status": status}
 
 
 def adjoint_timing(ctx, dp, dpos, dq, steps):
@@ -414,6 +400,8 @@ def main():
                          "of the batch free of the many small single-channel launches)")
     ap.add_argument("--wet-steps", type=int, default=10,
                     help="wet steps of the 262,144-ion hydrodynamic channel per kernel (0: skip)")
+    ap.add_argument("--c2-steps", type=int, default=100,
+                    help="timed steps of the 65,536-ion dielectric channel (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -474,6 +462,7 @@ def main():
     adj = adjoint_timing(ctx, dp, dpos, dq, args.adjoint_steps) if args.adjoint_steps > 0 else None
     batched = batch_timing(args.batch_steps, one_by_one=not args.no_one_by_one) if args.batch_steps > 0 else None
     wet = wet_timing(args.wet_steps) if args.wet_steps > 0 else None
+    c2 = c2_timing(args.c2_steps) if args.c2_steps > 0 else None
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -487,33 +476,37 @@ def main():
     final = dpos.cpu().numpy()
     L = np.array([w.nx, w.ny, w.nz]) * w.h
     pairs = count_pairs(final, L, p["psi"]) * N
-    tests = count_tests(final, (w.nx, w.ny, w.nz, w.h), p["psi"]) * N
-    bound, work = stage_work(dom, N, C, H, pairs, tests)
+    bound, work, abytes = stage_work(dom, N, C, H, pairs)
     t_dom = dom_live_ms * 1e-3
     traffic = committed_traffic(STAGE_KERNEL[dom])
     if bound == "hbm":
         achieved = work / t_dom / 1e9
         roof = {"bound": "hbm", "kernel": STAGE_KERNEL[dom], "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic, "algorithmic_bytes": work, "ms_per_launch": dom_live_ms}
+                "traffic": traffic, "algorithmic_bytes": abytes, "ms_per_launch": dom_live_ms}
     else:
         achieved = work / t_dom / 1e12
         peak = ALU_PEAK[dom]
         roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom], "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "precision": "fp32" if peak == FP32_PEAK_TFLOPS else "fp64",
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "precision": "fp64",
                 "traffic": traffic, "algorithmic_flops": work, "ms_per_launch": dom_live_ms,
-                "pairs_per_ion": pairs / N, "tests_per_ion": tests / N,
+                "pairs_per_ion": pairs / N, "flops_per_pair": NEAR_FLOPS_PER_PAIR,
+                "algorithmic_bytes": abytes,
+                "hbm_GBs_algorithmic": abytes / t_dom / 1e9,
+                "hbm_frac_algorithmic": abytes / t_dom / 1e9 / HBM_PEAK_GBS,
                 "valu_issue_share": committed_issue(STAGE_KERNEL[dom])}
+    roof["traffic_over_algorithmic"] = None if traffic is None else traffic / abytes
     per_stage = {}
     for k, v in stages.items():
-        b, wk = stage_work(k, N, C, H, pairs, tests)
+        b, wk, ab = stage_work(k, N, C, H, pairs)
         if b is None:
             continue  # empty in a dry step: the update (fused) and the hydrodynamic stages
-        e = {"ms": round(v, 5)}
-        if b is not None:
-            e["bound"] = b
-            e["GB/s" if b == "hbm" else "TFLOP/s"] = round(wk / (v * 1e-3) / (1e9 if b == "hbm" else 1e12), 2)
+        e = {"ms": round(v, 5), "bound": b}
+        if b == "hbm":
+            e["GB/s"] = round(wk / (v * 1e-3) / 1e9, 2)
+        else:
+            e["TFLOP/s"] = round(wk / (v * 1e-3) / 1e12, 2)
+        e["hbm_frac"] = round(ab / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         per_stage[k] = e
 
     cpu = None
@@ -545,6 +538,7 @@ def main():
         "adjoint": adj,
         "batched": batched,
         "wet": wet,
+        "dielectric_128x128x64": c2,
         "cpu_baseline": cpu,
         "device_status": "; ".join(status) if status else "ok",
     }

@@ -119,10 +119,12 @@ typedef struct discos_params {
                                    conjugate gradients preconditioned by the per-mode solve
                                    of a uniform wall pair (Dirichlet for a wall with any
                                    Dirichlet column), iterated to a residual below 1e-13 of
-                                   the right-hand side; the calls that read a map copy it to
-                                   the host (checking every entry) and synchronise the stream
-                                   to test convergence.  discos_energy_flux(_backward) and
-                                   batches take uniform walls only. */
+                                   the right-hand side.  discos_solve_poisson and discos_step
+                                   copy the maps to the host (checking every entry) and
+                                   synchronise the stream, also to test convergence every few
+                                   iterations; the other calls read the maps on the device.
+                                   discos_energy_flux(_backward) and batches take uniform
+                                   walls only (DISCOS_E_ARG). */
 } discos_params;
 
 #define DISCOS_HYDRO_NOSLIP 0
@@ -402,13 +404,14 @@ const char* discos_batch_last_error(discos_batch* b);
  * discos_profile(ctx, 0) stops recording.  discos_profile_read synchronises and writes
  * the mean elapsed milliseconds per recorded step of each stage (host array of at
  * least DISCOS_NSTAGE doubles, order: cell list, spread, x-FFT, y-FFT, z-solve,
- * inverse y-FFT, inverse x-FFT, interpolation, near field (candidates, pair forces,
- * wall force, and in a dry step the update), S^hy, Stokes solve, the two J^hy passes
- * with the predictor, the update of a wet step; the hydrodynamic stages and the last
- * read 0 in dry steps) and sets *count (0 when no step was
+ * inverse y-FFT, inverse x-FFT, interpolation, the near field's padded cell list, the
+ * near-field pass (candidates, pair forces, wall force, and in a dry step the update),
+ * S^hy, Stokes solve, the two J^hy passes with the predictor, the update of a wet step;
+ * the hydrodynamic stages and the last read 0 in dry steps; with walls of mixed type the
+ * whole iterative Poisson solve is timed as the x-FFT stage) and sets *count (0 when no step was
  * recorded).  Each recorded event costs the stream a few microseconds.
  */
-#define DISCOS_NSTAGE 13
+#define DISCOS_NSTAGE 14
 int discos_profile(discos_ctx* ctx, int enable);
 int discos_profile_read(discos_ctx* ctx, double* ms, int* count);
 

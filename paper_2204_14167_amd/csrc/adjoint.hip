@@ -292,16 +292,10 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
             rstart[t] = st;
             len = bin_start[row + nbxt] - st;
         }
-        scan[t] = len;
-        __syncthreads();
-        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-            const int a = (t >= off) ? scan[t - off] : 0;
-            __syncthreads();
-            scan[t] += a;
-            __syncthreads();
-        }
-        if (t < nrows) rpre[t] = scan[t] - len;
-        if (t == nrows - 1) rpre[nrows] = scan[t];
+        int tot;
+        const int inc = block_inclusive_scan(len, scan, tot);
+        if (t < nrows) rpre[t] = inc - len;
+        if (t == nrows - 1) rpre[nrows] = inc;
     }
     __syncthreads();
     if (rpre[nrows] == 0) return;  // the same for the whole workgroup

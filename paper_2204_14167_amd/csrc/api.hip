@@ -618,7 +618,10 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     discos::DryStepOut dry_out{step, pos, ions->q, ions->id, ions->species};
     if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9,
                                                       wet ? nullptr : &dry_out);
-    else discos::stage_mark(c, 9, s);
+    else {
+        discos::stage_mark(c, 9, s);
+        discos::stage_mark(c, 10, s);
+    }
     const double* vwet = nullptr;
     if (wet && !rc && ni > 0) {
         discos::RfdDev rd{};
@@ -630,19 +633,19 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
             rd.step = step;
         }
         rc = discos::spread_force_sorted(c, c->hfor, s, rfd ? &rd : nullptr, 1, ni);
-        discos::stage_mark(c, 10, s);
-        if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 11, s);
-        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s, 1);
+        if (!rc) rc = discos::solve_stokes(c, c->hfor, p, step, 1, c->hvel, nullptr, s);
         discos::stage_mark(c, 12, s);
+        if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s, 1);
+        discos::stage_mark(c, 13, s);
         vwet = c->hvi;
     } else {
-        discos::stage_mark(c, 10, s);
         discos::stage_mark(c, 11, s);
         discos::stage_mark(c, 12, s);
+        discos::stage_mark(c, 13, s);
     }
     if (!rc && wet) rc = discos::update_sorted(c, ni, p, step, vwet, pos, ions->q, ions->id, ions->species, s);
-    discos::stage_mark(c, 13, s);
+    discos::stage_mark(c, 14, s);
     if (c->profile && c->prof_steps < PROF_MAX) ++c->prof_steps;
     return rc ? fail(c, rc, "step launch failed") : DISCOS_OK;
 }

@@ -241,6 +241,30 @@ __device__ __forceinline__ double phi_at(const double* __restrict__ phi, const G
     return base + (2 * m + 1) * g.h * v / w.eps;
 }
 
+// Inclusive prefix sum of v over the workgroup (blockDim.x a multiple of 64): shuffles
+// within each wavefront, then the wavefront totals through wsum (blockDim.x / 64 ints of
+// LDS) after one barrier.  total receives the workgroup's sum.  Before wsum is written
+// again the caller needs a barrier.
+__device__ __forceinline__ int block_inclusive_scan(int v, int* wsum, int& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        const int s = wsum[k];
+        pre += k < wv ? s : 0;
+        tot += s;
+    }
+    total = tot;
+    return x + pre;
+}
+
 // Largest number of candidate rows tile_ranges can produce for a tile of ty x tz cells
 // starting on even cells (every tile edge is even) with a window of hlo cells below and
 // hhi above: each (y, z) bin row of the range contributes at most two x segments.
@@ -297,17 +321,11 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
             rstart[r] = st;
             len = bin_start[row + sb[sgi] + 1] - st;
         }
-        scan[t] = len;
-        __syncthreads();
-        for (int off = 1; off < bd; off <<= 1) {
-            const int a = (t >= off) ? scan[t - off] : 0;
-            __syncthreads();
-            scan[t] += a;
-            __syncthreads();
-        }
-        if (r < nr) rpre[r] = carry + scan[t] - len;
-        carry += scan[bd - 1];
-        __syncthreads();  // scan is rewritten by the next chunk
+        int tot;
+        const int inc = block_inclusive_scan(len, scan, tot);
+        if (r < nr) rpre[r] = carry + inc - len;
+        carry += tot;
+        __syncthreads();  // scan (the wavefront totals) is rewritten by the next chunk
     }
     if (t == 0) {
         rpre[nr] = (ncand > 0) ? carry : 0;

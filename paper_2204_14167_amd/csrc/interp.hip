@@ -121,45 +121,40 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
             rstart[t] = st;
             len = bin_start[row + nbxt] - st;
         }
-        scan[t] = len;
-        __syncthreads();
-        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-            const int a = (t >= off) ? scan[t - off] : 0;
-            __syncthreads();
-            scan[t] += a;
-            __syncthreads();
-        }
-        if (t < nrows) rpre[t] = scan[t] - len;
-        if (t == nrows - 1) rpre[nrows] = scan[t];
+        int tot;
+        const int inc = block_inclusive_scan(len, scan, tot);
+        if (t < nrows) rpre[t] = inc - len;
+        if (t == nrows - 1) rpre[nrows] = inc;
     }
     __syncthreads();
     const int total = rpre[nrows];
     if (total == 0) return;  // the same for the whole workgroup
     const bool direct = total <= IT_DIRECT;
     if (!direct) {
-        // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled;
-        // IT_UNROLL loads per thread are issued before the first LDS store
-        const int ne = LX * LY * lzn;
+        // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled:
+        // each thread takes whole z columns of the window (no index divisions per element),
+        // with IT_UNROLL loads in flight before the LDS stores
+        constexpr int PLANE = LX * LY;
         const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
-        for (int e0 = threadIdx.x; e0 < ne; e0 += IT_UNROLL * IT_THREADS) {
-            double v[IT_UNROLL];
+        const size_t pstride = (size_t)g.nx * g.ny;
+        for (int pp = threadIdx.x; pp < PLANE; pp += IT_THREADS) {
+            const int lx = pp % LX, ly = pp / LX;
+            const bool in_xy = lx < lxn && ly < lyn;
+            const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+            if (inner) {
+                const double* src = phi + (size_t)(z0 - 2) * pstride + (size_t)j * g.nx + i;
+                for (int lz0 = 0; lz0 < lzn; lz0 += IT_UNROLL) {
+                    double v[IT_UNROLL];
 #pragma unroll
-            for (int u = 0; u < IT_UNROLL; ++u) {
-                const int e = e0 + u * IT_THREADS;
-                const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
-                const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
-                v[u] = 0.0;
-                if (e < ne && lx < lxn && ly < lyn) {
-                    if (inner)
-                        v[u] = phi[((size_t)(z0 - 2 + lz) * g.ny + j) * g.nx + i];
-                    else
-                        v[u] = phi_at(phi, g, w, i, j, z0 - 2 + lz);
+                    for (int u = 0; u < IT_UNROLL; ++u)
+                        v[u] = (lz0 + u < lzn && in_xy) ? src[(size_t)(lz0 + u) * pstride] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < IT_UNROLL; ++u)
+                        if (lz0 + u < lzn) tile[(lz0 + u) * PLANE + pp] = v[u];
                 }
-            }
-#pragma unroll
-            for (int u = 0; u < IT_UNROLL; ++u) {
-                const int e = e0 + u * IT_THREADS;
-                if (e < ne) tile[e] = v[u];
+            } else {
+                for (int lz = 0; lz < lzn; ++lz)
+                    tile[lz * PLANE + pp] = in_xy ? phi_at(phi, g, w, i, j, z0 - 2 + lz) : 0.0;
             }
         }
         __syncthreads();

@@ -781,6 +781,7 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
     int rc = build_near_list(c, n, P.R, P.s_lo, P.s_hi, P.map, s);
     if (rc) return rc;
+    if (mark >= 0) stage_mark(c, mark, s);
     FusedUpdate U{};
     if (upd) {
         U.Dd = dry_of(p, upd->step);
@@ -793,7 +794,7 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     const NlView L{c->nl.start, c->nl.xyzq, c->nl.xyzf, c->nl.sp};
     rc = launch_near(P, n, s, c->gd, nullptr, nullptr, nullptr, c->sxyzq, c->ssp, c->bin_start, L,
                      c->perm, out, out_stride, scatter_to_caller, c->flags, U);
-    if (mark >= 0) stage_mark(c, mark, s);
+    if (mark >= 0) stage_mark(c, mark + 1, s);
     return rc;
 }
 

@@ -388,7 +388,7 @@ class Context:
                                    int(step), mode, _stream()))
 
     STAGES = ("cell_list", "spread", "fft_x", "fft_y", "z_solve", "ifft_y", "ifft_x",
-              "interp", "near_field", "spread_hy", "stokes", "interp_hy", "update")
+              "interp", "near_list", "near_field", "spread_hy", "stokes", "interp_hy", "update")
 
     def profile(self, enable=True):
         self._rc(lib().discos_profile(self.handle, int(enable)))

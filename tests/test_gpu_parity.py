@@ -297,6 +297,44 @@ def test_step_dielectric_128x128x64():
     _step_case("dielectric_128x128x64_n65536", steps_checked=2, sample=400)
 
 
+def test_step_dielectric_128x128x64_100_steps():
+    """The 65,536-ion dielectric channel with E_x = 0.1 run for its 100 steps on the GPU.
+    Every 10th step is checked teacher-forced: the oracle takes the GPU's state before the
+    step and computes the step for 400 sampled ions (near field by the oracle's k-d tree
+    route, pinned against its brute-force sum), which must agree to 1e-10."""
+    w = workloads.WORKLOADS["dielectric_128x128x64_n65536"]
+    assert w.steps == 100
+    p = workloads.make_params(w)
+    pos, q, ids, species = workloads.make_ions(w)
+    grid = es.Grid(w.nx, w.ny, w.nz, w.h)
+    ctx = _ctx(w.nx, w.ny, w.nz, w.n, w.h)
+    dp = ctx.params(p)
+    dpos, dq, dids, dsp = dev(pos), dev(q), dev(ids), dev(species)
+    rng = np.random.default_rng(29)
+    for s in range(w.steps):
+        if s % 10 == 0:
+            cur_pos, cur_q, cur_ids, cur_sp = host(dpos), host(dq), host(dids), host(dsp)
+            order = np.argsort(cur_ids)
+            cur_pos, cur_q, cur_ids, cur_sp = cur_pos[:, order], cur_q[order], cur_ids[order], cur_sp[order]
+            targets = np.sort(rng.choice(w.n, 400, replace=False))
+            ref, _, _ = dynamics.dry_step(grid, cur_pos, cur_q, cur_sp, cur_ids, p, s, targets=targets,
+                                          near="pairs")
+        ctx.step(dpos, dq, dids, dsp, dp, s)
+        if s % 10 == 0:
+            ctx.check()
+            got = by_id(host(dpos), host(dids), cur_ids[targets])
+            err = min_image(got - ref, grid.L)
+            disp = min_image(ref - cur_pos[:, targets], grid.L)
+            r = np.linalg.norm(err) / np.linalg.norm(disp)
+            log(f"c2 step {s}: rel {r:.3e}")
+            assert r < TOL
+    ctx.check()
+    got_pos, got_ids = host(dpos), host(dids)
+    assert np.all(np.isfinite(got_pos))
+    assert np.array_equal(np.sort(got_ids), np.arange(w.n))
+    assert np.all((got_pos[2] >= 0.0) & (got_pos[2] <= grid.L[2]))
+
+
 def test_step_headline_1m_sampled():
     """The timed workload itself: 1,048,576 ions on 256x256x128 with dielectric walls and
     E_x = 0.1, one step in the library's launch configuration, against the oracle at
