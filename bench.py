@@ -19,7 +19,6 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints one JSON line.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -66,21 +65,11 @@ def gpu_params(p):
     return dict(p)
 
 
-def kernel_source_hash():
-    """sha256 over the HIP sources and headers: the traffic figures of a committed
-    counter profile apply only while this is unchanged."""
-    h = hashlib.sha256()
-    base = os.path.join(ROOT, "paper_2204_14167_amd", "csrc")
-    for name in sorted(os.listdir(base)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(base, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()
-
-
-def committed_block(path):
-    """The fenced JSON block of a committed profile summary, or None if it is absent or
-    was taken on other kernel sources."""
+def committed_block(path, kernel):
+    """The entry of `kernel` in the fenced JSON block of a committed profile summary (by
+    exact name, else the one instantiation of that template), or None if the summary is
+    absent or was taken on other sources of that kernel."""
+    from paper_2204_14167_amd import rocprof_summary as rs
     try:
         text = open(path).read()
     except OSError:
@@ -89,32 +78,28 @@ def committed_block(path):
     if len(block) < 2:
         return None
     data = json.loads(block[1].split("```", 1)[0])
-    return data if data.get("source_sha256") == kernel_source_hash() else None
-
-
-def kernel_entry(data, kernel):
-    """The entry of `kernel` in a profile's JSON block: by exact name, else the one
-    instantiation of that template (name<...>)."""
-    if data is None:
-        return None
     ks = data.get("kernels", {})
     if kernel in ks:
-        return ks[kernel]
-    hits = [v for k, v in ks.items() if k.split("<", 1)[0] == kernel]
-    return hits[0] if len(hits) == 1 else None
+        name = kernel
+    else:
+        hits = [k for k in ks if k.split("<", 1)[0] == kernel]
+        if len(hits) != 1:
+            return None
+        name = hits[0]
+    return ks[name] if rs.sources_unchanged(data, name) else None
 
 
 def committed_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE +
     WRITE_SIZE, copy-calibrated), or None if absent or taken on other sources."""
-    k = kernel_entry(committed_block(TRAFFIC_FILE), kernel)
+    k = committed_block(TRAFFIC_FILE, kernel)
     return None if k is None else float(k["hbm_bytes_per_launch"])
 
 
 def committed_issue(kernel):
     """Share of the chip's VALU issue cycles `kernel` fills (SQ instruction counters over
     its kernel-trace duration), or None if absent or taken on other sources."""
-    k = kernel_entry(committed_block(ISSUE_FILE), kernel)
+    k = committed_block(ISSUE_FILE, kernel)
     return None if k is None else k["valu_issue_share"]
 
 

@@ -12,13 +12,19 @@
       duration: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles, and the
       chip has 1024 SIMDs (256 CUs x 4) at 2.4 GHz
 
-All read only the rocpd SQLite tables `kernels` and `counters_collection`.
+All read only the rocpd SQLite tables `kernels` and `counters_collection`.  The JSON
+blocks of the traffic and issue summaries carry the sha256 of every HIP source file and
+header at the time of the run, so that a reader can tell which kernels have changed since.
 """
 import argparse
+import hashlib
 import json
+import os
 import re
 import sqlite3
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 COPY_BYTES = 1 << 30  # the calibration copy of bench.py --copy-calibration
 SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
@@ -29,6 +35,42 @@ def _short(name):
     kept, so that instantiations stay apart)."""
     name = re.sub(r"\(.*", "", name).replace("discos::", "")
     return re.sub(r"^void ", "", name)
+
+
+def source_hashes(base=CSRC):
+    """{file name: sha256} of the HIP sources and headers."""
+    out = {}
+    for name in sorted(os.listdir(base)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(base, name), "rb") as f:
+                out[name] = hashlib.sha256(f.read()).hexdigest()
+    return out
+
+
+def kernel_files(kernel, base=CSRC):
+    """The source files a kernel's timing and traffic depend on: the file that defines it
+    (a __global__ function of that name) and every header."""
+    stem = re.escape(kernel.split("<", 1)[0])
+    pat = re.compile(r"__global__[^;{]*?\b" + stem + r"\s*\(")
+    files = []
+    for name in sorted(os.listdir(base)):
+        if name.endswith(".h"):
+            files.append(name)
+        elif name.endswith(".hip"):
+            with open(os.path.join(base, name)) as f:
+                if pat.search(f.read()):
+                    files.append(name)
+    return files
+
+
+def sources_unchanged(data, kernel, base=CSRC):
+    """True if the profile block `data` was taken on the present sources of `kernel`."""
+    then = data.get("source_sha256")
+    if not isinstance(then, dict):
+        return False
+    now = source_hashes(base)
+    files = kernel_files(kernel, base)
+    return any(f.endswith(".hip") for f in files) and all(then.get(f) == now[f] for f in files)
 
 
 def kernel_rows(db):
@@ -93,7 +135,7 @@ def cmd_traffic(args):
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"]):
         print(f"| {k} | {v['dispatches']} | {v['fetch_kib_raw']} | {v['write_kib_raw']} | "
               f"{v['hbm_bytes_per_launch'] / 1e6:.1f} |")
-    data = {"source_sha256": args.source_sha256, "fetch_factor": ff, "write_factor": fw,
+    data = {"source_sha256": source_hashes(), "fetch_factor": ff, "write_factor": fw,
             "kernels": {k: {"hbm_bytes_per_launch": v["hbm_bytes_per_launch"]} for k, v in kern.items()}}
     print("\n```json\n" + json.dumps(data, indent=1) + "\n```")
 
@@ -134,7 +176,7 @@ def cmd_issue(args):
               f"{'-' if t is None else f'{t / 1e3:.2f}'} | {'-' if share is None else f'{share:.2f}'} |")
         data[k] = {"valu_per_wave": round(pw["SQ_INSTS_VALU"], 1),
                    "valu_issue_share": None if share is None else round(share, 3)}
-    print("\n```json\n" + json.dumps({"source_sha256": args.source_sha256, "kernels": data},
+    print("\n```json\n" + json.dumps({"source_sha256": source_hashes(), "kernels": data},
                                       indent=1) + "\n```")
 
 
@@ -151,14 +193,12 @@ def main(argv=None):
     b.add_argument("write_db")
     b.add_argument("--command", action="append", required=True)
     b.add_argument("--title", default="")
-    b.add_argument("--source-sha256", required=True)
     b.set_defaults(fn=cmd_traffic)
     c = sub.add_parser("issue")
     c.add_argument("db")
     c.add_argument("trace_db")
     c.add_argument("--command", action="append", required=True)
     c.add_argument("--title", default="")
-    c.add_argument("--source-sha256", required=True)
     c.set_defaults(fn=cmd_issue)
     args = ap.parse_args(argv)
     args.fn(args)
