@@ -648,6 +648,34 @@ __device__ __forceinline__ void sorted_bin(const GridDev& g, double x, double y,
     bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) / DISCOS_BIN;
 }
 
+// Order of the pass's blocks within each XCD.  Block L covers ions [L NF_THREADS, ...) of
+// the cell list, whose bins run z-slab by z-slab, so the blocks form about T = nbz rows
+// (slabs) of W = ceil(nb / T) blocks, each row running through the slab's y rows.  The
+// order enumerates 8 column bands of that matrix (y bands of the channel) one after the
+// other, and each band slab by slab; xcd_block then hands XCD x the x-th eighth of this
+// order, about one band.  The blocks an XCD has in flight (a few hundred) then span many
+// slabs of one band rather than a few whole slabs, so the candidate slabs the pass reads
+// stay in that XCD's L2 while the band sweeps through them.  A bijection on [0, nb).
+__host__ __device__ inline int band_block(int p, int nb, int T) {
+    const int W = (nb + T - 1) / T;
+    T = (nb + W - 1) / W;  // rows actually used: the last one holds 1 to W blocks
+    if (T < 2 || W < DISCOS_NXCD) return p;
+    const int Wb = (W + DISCOS_NXCD - 1) / DISCOS_NXCD;  // band width in blocks
+    const int last = nb - (T - 1) * W;                   // blocks in the last slab, 1..W
+    for (int b = 0; b < DISCOS_NXCD; ++b) {
+        const int c0 = b * Wb;
+        const int wb = max(0, min(Wb, W - c0));
+        const int tail = max(0, min(wb, last - c0));  // the band's blocks in the last slab
+        const int cnt = (T - 1) * wb + tail;
+        if (p < cnt) {
+            if (p < (T - 1) * wb) return (p / wb) * W + c0 + p % wb;
+            return (T - 1) * W + c0 + (p - (T - 1) * wb);
+        }
+        p -= cnt;
+    }
+    return p;  // not reached: the bands' counts sum to nb
+}
+
 // The pass over every ion of a context (BATCH = false: out[o] += F with o = perm[i] if
 // scatter, else i; or with U.pos set, the dry step's update from the complete force
 // out[i] + F) or of a batch (BATCH = true: ion i belongs to channel ion_rep[i], whose
@@ -668,7 +696,9 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
     for (int k = threadIdx.x; k < nt; k += NF_THREADS) sh.tab[k] = P.tab[k];
     __syncthreads();
     P.tab = sh.tab;
-    const int i = (BATCH ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * NF_THREADS +
+    const int i = (BATCH ? (int)blockIdx.x
+                         : band_block(xcd_block(blockIdx.x, gridDim.x), gridDim.x, g0.nbz)) *
+                      NF_THREADS +
                   (int)threadIdx.x;
     if (i >= n) return;
     GridDev g = g0;

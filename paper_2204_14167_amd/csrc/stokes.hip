@@ -104,152 +104,56 @@ __device__ __forceinline__ int hy_axis(double s, const double* kr, double* wt) {
     return i0;
 }
 
-// deposit_face for a kernel from the table (kr: its row) over a window of 2 KM nodes per
-// axis; folds as deposit_face (one fold suffices: nz >= KM).  Weights are evaluated only
-// for the nodes inside the tile.
-template <int COMP, int KM>
-__device__ __forceinline__ void deposit_face_k(const GridDev& g, double* acc, int x0, int y0, int z0,
-                                               int tx, int ty, int tz, double px, double py,
-                                               double pz, double val, const double* kr) {
-    const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
-    const double sx = px * g.inv_h - ox, sy = py * g.inv_h - oy, sz = pz * g.inv_h - oz;
-    const int ix0 = (int)floor(sx) + 1 - KM, iy0 = (int)floor(sy) + 1 - KM;
-    const int iz0 = (int)floor(sz) + 1 - KM;
-    double wx[2 * KM], wy[2 * KM];
-    int lxs[2 * KM], lys[2 * KM];
-#pragma unroll
-    for (int a = 0; a < 2 * KM; ++a) {
-        lxs[a] = (ix0 + a - x0) & (g.nx - 1);
-        wx[a] = lxs[a] < tx ? hy_weight(sx - (double)(ix0 + a), kr[0], kr[1], kr[2], kr[3]) : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < 2 * KM; ++b) {
-        lys[b] = (iy0 + b - y0) & (g.ny - 1);
-        wy[b] = lys[b] < ty ? hy_weight(sy - (double)(iy0 + b), kr[0], kr[1], kr[2], kr[3]) : 0.0;
-    }
-    for (int c = 0; c < 2 * KM; ++c) {
-        int kz = iz0 + c;
-        double sgn = 1.0;
-        if (COMP == 2) {
-            if (kz < 0) { kz = -kz; sgn = -1.0; }
-            else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
-            if (kz == 0 || kz == g.nz) continue;
-        } else {
-            if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
-            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
-        }
-        const int lz = kz - z0;
-        if (lz < 0 || lz >= tz) continue;
-        const double wzc0 = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
-        if (wzc0 == 0.0) continue;
-        const double wzc = val * sgn * wzc0;
-#pragma unroll
-        for (int b = 0; b < 2 * KM; ++b) {
-            if (wy[b] == 0.0) continue;
-            const double wyz = wzc * wy[b];
-#pragma unroll
-            for (int a = 0; a < 2 * KM; ++a) {
-                if (wx[a] == 0.0) continue;
-                atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], wyz * wx[a]);
-            }
-        }
-    }
-}
-
-// Window weights of one axis at s (cells): the 4-point Peskin kernel (KM = 0) or the
-// table kernel kr over 2 KM nodes; nodes outside the tile (lxs >= tn) get 0 for KM > 0.
-template <int KM>
-__device__ __forceinline__ void face_axis(double s, int i0, const double* kr, const int* lxs, int tn,
-                                          double* wt) {
-    if constexpr (KM == 0) {
-        int unused;
-        peskin4(s, unused, wt);
-    } else {
-#pragma unroll
-        for (int a = 0; a < 2 * KM; ++a)
-            wt[a] = lxs[a] < tn ? hy_weight(s - (double)(i0 + a), kr[0], kr[1], kr[2], kr[3]) : 0.0;
-    }
-}
-
 // The force deposit v0 phi(x - node) and the random finite difference
 // v [phi(x + d - node) - phi(x - d - node)] of one ion in one pass, one atomic per node:
 // possible when the three kernel centres' windows start at the same node on every axis
 // (the shift d is far below a cell, so nearly always).  Returns false, depositing
 // nothing, otherwise.  Folds as deposit_face.
-template <int COMP, int KM>
+template <int COMP>
 __device__ __forceinline__ bool deposit_face_rfd(const GridDev& g, double* acc, int x0, int y0,
                                                  int z0, int tx, int ty, int tz, double px,
                                                  double py, double pz, double hx, double hy,
-                                                 double hz, double v0, double v, const double* kr) {
-    constexpr int NW = KM == 0 ? 4 : 2 * KM;
+                                                 double hz, double v0, double v) {
     const double ox = COMP == 0 ? 0.0 : 0.5, oy = COMP == 1 ? 0.0 : 0.5, oz = COMP == 2 ? 0.0 : 0.5;
-    const double sx = px * g.inv_h - ox, sy = py * g.inv_h - oy, sz = pz * g.inv_h - oz;
-    const double sxp = (px + hx) * g.inv_h - ox, syp = (py + hy) * g.inv_h - oy,
-                 szp = (pz + hz) * g.inv_h - oz;
-    const double sxm = (px - hx) * g.inv_h - ox, sym = (py - hy) * g.inv_h - oy,
-                 szm = (pz - hz) * g.inv_h - oz;
-    const double fx = floor(sx), fy = floor(sy), fz = floor(sz);
-    if (floor(sxp) != fx || floor(sxm) != fx || floor(syp) != fy || floor(sym) != fy ||
-        floor(szp) != fz || floor(szm) != fz)
-        return false;
-    const int off = KM == 0 ? -1 : 1 - KM;  // first node relative to floor(s)
-    const int ix0 = (int)fx + off, iy0 = (int)fy + off, iz0 = (int)fz + off;
-    int lxs[NW], lys[NW];
+    int ix0, iy0, iz0, jx, jy, jz, kx, ky, kz;
+    double wx0[4], wxp[4], wxm[4], wy0[4], wyp[4], wym[4], wz0[4], wzp[4], wzm[4];
+    peskin4(px * g.inv_h - ox, ix0, wx0);
+    peskin4((px + hx) * g.inv_h - ox, jx, wxp);
+    peskin4((px - hx) * g.inv_h - ox, kx, wxm);
+    peskin4(py * g.inv_h - oy, iy0, wy0);
+    peskin4((py + hy) * g.inv_h - oy, jy, wyp);
+    peskin4((py - hy) * g.inv_h - oy, ky, wym);
+    peskin4(pz * g.inv_h - oz, iz0, wz0);
+    peskin4((pz + hz) * g.inv_h - oz, jz, wzp);
+    peskin4((pz - hz) * g.inv_h - oz, kz, wzm);
+    if (jx != ix0 || kx != ix0 || jy != iy0 || ky != iy0 || jz != iz0 || kz != iz0) return false;
+    int lxs[4], lys[4];
 #pragma unroll
-    for (int a = 0; a < NW; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
+    for (int a = 0; a < 4; ++a) lxs[a] = (ix0 + a - x0) & (g.nx - 1);
 #pragma unroll
-    for (int b = 0; b < NW; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
-    double wx0[NW], wxp[NW], wxm[NW], wy0[NW], wyp[NW], wym[NW];
-    face_axis<KM>(sx, ix0, kr, lxs, tx, wx0);
-    face_axis<KM>(sxp, ix0, kr, lxs, tx, wxp);
-    face_axis<KM>(sxm, ix0, kr, lxs, tx, wxm);
-    face_axis<KM>(sy, iy0, kr, lys, ty, wy0);
-    face_axis<KM>(syp, iy0, kr, lys, ty, wyp);
-    face_axis<KM>(sym, iy0, kr, lys, ty, wym);
-    double wz0[KM == 0 ? 4 : 1], wzp[KM == 0 ? 4 : 1], wzm[KM == 0 ? 4 : 1];
-    if constexpr (KM == 0) {
-        int unused;
-        peskin4(sz, unused, wz0);
-        peskin4(szp, unused, wzp);
-        peskin4(szm, unused, wzm);
-    }
-    for (int c = 0; c < NW; ++c) {
-        int kz = iz0 + c;
+    for (int b = 0; b < 4; ++b) lys[b] = (iy0 + b - y0) & (g.ny - 1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int kk = iz0 + c;
         double sgn = 1.0;
         if (COMP == 2) {
-            if (kz < 0) { kz = -kz; sgn = -1.0; }
-            else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
-            if (kz == 0 || kz == g.nz) continue;
+            if (kk < 0) { kk = -kk; sgn = -1.0; }
+            else if (kk > g.nz) { kk = 2 * g.nz - kk; sgn = -1.0; }
+            if (kk == 0 || kk == g.nz) continue;
         } else {
-            if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
-            else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
+            if (kk < 0) { kk = -1 - kk; sgn = g.tsg[0]; }
+            else if (kk >= g.nz) { kk = 2 * g.nz - 1 - kk; sgn = g.tsg[1]; }
         }
-        const int lz = kz - z0;
+        const int lz = kk - z0;
         if (lz < 0 || lz >= tz) continue;
-        double z0c, zpc, zmc;
-        if constexpr (KM == 0) {
-            z0c = wz0[c];
-            zpc = wzp[c];
-            zmc = wzm[c];
-        } else {
-            const double nz = (double)(iz0 + c);
-            z0c = hy_weight(sz - nz, kr[0], kr[1], kr[2], kr[3]);
-            zpc = hy_weight(szp - nz, kr[0], kr[1], kr[2], kr[3]);
-            zmc = hy_weight(szm - nz, kr[0], kr[1], kr[2], kr[3]);
-            if (z0c == 0.0 && zpc == 0.0 && zmc == 0.0) continue;
-        }
-        z0c *= sgn * v0;
-        zpc *= sgn * v;
-        zmc *= sgn * v;
+        const double z0c = sgn * v0 * wz0[c], zpc = sgn * v * wzp[c], zmc = sgn * v * wzm[c];
 #pragma unroll
-        for (int b = 0; b < NW; ++b) {
+        for (int b = 0; b < 4; ++b) {
             if (lys[b] >= ty) continue;
             const double y0c = z0c * wy0[b], ypc = zpc * wyp[b], ymc = zmc * wym[b];
-            if (KM != 0 && y0c == 0.0 && ypc == 0.0 && ymc == 0.0) continue;
 #pragma unroll
-            for (int a = 0; a < NW; ++a) {
+            for (int a = 0; a < 4; ++a) {
                 if (lxs[a] >= tx) continue;
-                if (KM != 0 && wx0[a] == 0.0 && wxp[a] == 0.0 && wxm[a] == 0.0) continue;
                 atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]],
                           y0c * wx0[a] + (ypc * wxp[a] - ymc * wxm[a]));
             }
@@ -258,37 +162,30 @@ __device__ __forceinline__ bool deposit_face_rfd(const GridDev& g, double* acc, 
     return true;
 }
 
-// S^hy F on one face grid; with rfd.scale != 0 every ion also deposits the random
-// finite difference (kT / delta) [phi(x + delta/2 W) - phi(x - delta/2 W)] W_COMP of
-// the thermal forcing.  The shifts are below half a cell: along an axis whose nodes
-// sit on faces, a kernel shifted up from the cell below the tile's two-cell window
-// reaches the tile's first node, so the candidate rows then reach three cells down.
-// KM = 0: the 4-point Peskin kernel for every ion; KM = 2 or 4: each ion's kernel from
-// the table by its species, over a window of 2 KM nodes.  16^3 tiles: the halo of the
-// 8-node window (K + 1 = 5 cells below, 4 above) needs up to 13 x 13 bin rows of two
-// x segments, 338 candidate rows, within MAXR = 512.
-template <int COMP, int T, int KM>
+// S^hy F on one face grid with the 4-point Peskin kernel; with rfd.scale != 0 every ion
+// also deposits the random finite difference (kT / delta) [phi(x + delta/2 W) -
+// phi(x - delta/2 W)] W_COMP of the thermal forcing.  The shifts are below half a cell:
+// along an axis whose nodes sit on faces, a kernel shifted up from the cell below the
+// tile's two-cell window reaches the tile's first node, so the candidate rows then reach
+// three cells down.
+template <int COMP, int T>
 __global__ void __launch_bounds__(SH_THREADS)
 spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
-                   const int* __restrict__ bin_start, RfdDev rfd, const int* __restrict__ ssp,
-                   const double* __restrict__ hy_tab, double* __restrict__ out,
+                   const int* __restrict__ bin_start, RfdDev rfd, double* __restrict__ out,
                    int* __restrict__ flags) {
-    constexpr int MAXR = KM == 4 ? 2 * SH_MAXR : SH_MAXR;
     __shared__ double acc[T * T * T];
-    __shared__ int rstart[MAXR], rpre[MAXR + 1], scan[SH_THREADS];
+    __shared__ int rstart[SH_MAXR], rpre[SH_MAXR + 1], scan[SH_THREADS];
     const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
     const int tx = min(T, g.nx), ty = min(T, g.ny);
     const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * T;
     const int tz = min(T, nzn - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
-    // ions that can reach node levels [z0, z0+tz): cells [z0-K, z0+tz-1+K] for a window
-    // of 2K nodes (K = 2 for the Peskin kernel)
-    const int K = KM == 0 ? 2 : KM;
-    static_assert(tile_rows_bound(T, T, (KM == 0 ? 2 : KM) + 1, KM == 0 ? 2 : KM) <= MAXR,
-                  "face spread tile rows exceed MAXR");
-    const int nr = tile_ranges<MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1), rstart,
-                                 rpre, scan, flags, rfd.scale != 0.0 ? K + 1 : K, K);
+    // ions that can reach node levels [z0, z0+tz): cells [z0-2, z0+tz+1] (one more below
+    // with the shifts)
+    static_assert(tile_rows_bound(T, T, 3, 2) <= SH_MAXR, "face spread tile rows exceed SH_MAXR");
+    const int nr = tile_ranges<SH_MAXR>(g, bin_start, x0, y0, z0, tx, ty, min(tz, g.nz - z0 + 1),
+                                        rstart, rpre, scan, flags, rfd.scale != 0.0 ? 3 : 2, 2);
     const int total = rpre[nr];
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
@@ -300,30 +197,20 @@ spread_face_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* _
         const int i = rstart[r] + (f - rpre[r]);
         const double4 a4 = sxyzq[i];
         if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
-        double kr[4];
-        if (KM != 0) {
-            const double* row = hy_row(hy_tab, ssp[i]);
-            kr[0] = row[0]; kr[1] = row[1]; kr[2] = row[2]; kr[3] = row[3];
-        }
-        auto dep = [&](double px, double py, double pz, double v) {
-            if constexpr (KM == 0) deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v);
-            else deposit_face_k<COMP, KM>(g, acc, x0, y0, z0, tx, ty, tz, px, py, pz, v, kr);
-        };
         const double v0 = fw[i] * inv_h3;
         if (rfd.scale == 0.0) {
-            dep(a4.x, a4.y, a4.z, v0);
+            deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, v0);
             continue;
         }
         const double w0 = rfd.w[i], w1 = rfd.w[i + rfd.wstride], w2 = rfd.w[i + 2 * rfd.wstride];
         const double wc = COMP == 0 ? w0 : (COMP == 1 ? w1 : w2);
         const double v = rfd.scale * wc * inv_h3;
         const double hx = rfd.half * w0, hy = rfd.half * w1, hz = rfd.half * w2;
-        if (deposit_face_rfd<COMP, KM>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, hx, hy,
-                                       hz, v0, v, kr))
+        if (deposit_face_rfd<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, hx, hy, hz, v0, v))
             continue;
-        dep(a4.x, a4.y, a4.z, v0);
-        dep(a4.x + hx, a4.y + hy, a4.z + hz, v);
-        dep(a4.x - hx, a4.y - hy, a4.z - hz, -v);
+        deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x, a4.y, a4.z, v0);
+        deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x + hx, a4.y + hy, a4.z + hz, v);
+        deposit_face<COMP>(g, acc, x0, y0, z0, tx, ty, tz, a4.x - hx, a4.y - hy, a4.z - hz, -v);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
@@ -350,21 +237,242 @@ __global__ void rfd_normals_kernel(int n, const int* __restrict__ sid, uint64_t 
     w[i + 2 * stride] = w2;
 }
 
-template <int T, int KM>
-static void spread_faces(Ctx* c, const RfdDev& rfd, const int* ssp, double* out, hipStream_t s) {
+// ---- table kernels: each ion visited once ----------------------------------------------
+// A table kernel's window of 2 KM nodes per axis reaches over several tiles, so a spread
+// that lets every tile gather the ions of its halo evaluates an ion's weights once per
+// tile it reaches (about 3.4 tiles per component for 8-node windows on 16^3 tiles), and
+// every node test is repeated with them.  Here a tile takes only the ions of its own
+// cells and deposits their whole windows into an LDS region of the tile's nodes plus
+// own_h(KM) = KM + 1 nodes on every side, which holds the window of any ion of the tile
+// and of its two random-finite-difference shifts and, after the one fold at a wall, every
+// image level.  (A shift is delta/2 |W| with delta <= 0.1 h and |W| <= 8.6 for normals
+// drawn from 53-bit uniforms, so below half a cell: a window's first node moves by at
+// most one.)  The
+// region is then added to the grid (zeroed beforehand) with global atomics, consecutive
+// lanes on consecutive x nodes.  Each ion's weights are evaluated once per axis.
+#define OWN_T 16
+#define OWN_THREADS 512
+#define OWN_MAXR 128  // bin rows of a 16^3 tile: 8 x 8, bounded as if each had two x segments
+constexpr int own_h(int KM) { return KM + 1; }
+constexpr int own_e(int KM) { return OWN_T + 2 * own_h(KM); }
+
+// Weights of one axis at the nodes i0 .. i0 + 2 KM - 1 (i0 = floor(s) + 1 - KM).
+template <int KM>
+__device__ __forceinline__ void own_axis(double s, int i0, const double* kr, double* wt) {
+#pragma unroll
+    for (int a = 0; a < 2 * KM; ++a) wt[a] = hy_weight(s - (double)(i0 + a), kr[0], kr[1], kr[2], kr[3]);
+}
+
+// Local level of node level kz after the one fold at a wall, and the fold's sign;
+// false for a wall face of the z component (it carries nothing).
+template <int COMP>
+__device__ __forceinline__ bool own_level(const GridDev& g, int kz, int oz, int& lz, double& sgn) {
+    sgn = 1.0;
+    if (COMP == 2) {
+        if (kz < 0) { kz = -kz; sgn = -1.0; }
+        else if (kz > g.nz) { kz = 2 * g.nz - kz; sgn = -1.0; }
+        if (kz == 0 || kz == g.nz) return false;
+    } else {
+        if (kz < 0) { kz = -1 - kz; sgn = g.tsg[0]; }
+        else if (kz >= g.nz) { kz = 2 * g.nz - 1 - kz; sgn = g.tsg[1]; }
+    }
+    lz = kz - oz;
+    return true;
+}
+
+// v phi(x - node) of one kernel centre into the region (origin ox, oy, oz; rows of ex,
+// planes of exy doubles).
+template <int COMP, int KM>
+__device__ __forceinline__ void own_deposit1(const GridDev& g, double* acc, int ox, int oy, int oz,
+                                             int ex, int exy, double px, double py, double pz,
+                                             double v, const double* kr) {
+    constexpr int NW = 2 * KM;
+    const double sx = px * g.inv_h - (COMP == 0 ? 0.0 : 0.5);
+    const double sy = py * g.inv_h - (COMP == 1 ? 0.0 : 0.5);
+    const double sz = pz * g.inv_h - (COMP == 2 ? 0.0 : 0.5);
+    const int ix0 = (int)floor(sx) + 1 - KM, iy0 = (int)floor(sy) + 1 - KM, iz0 = (int)floor(sz) + 1 - KM;
+    double wx[NW], wy[NW];
+    own_axis<KM>(sx, ix0, kr, wx);
+    own_axis<KM>(sy, iy0, kr, wy);
+    const int lx = ix0 - ox, ly = iy0 - oy;
+    for (int c = 0; c < NW; ++c) {
+        int lz;
+        double sgn;
+        if (!own_level<COMP>(g, iz0 + c, oz, lz, sgn)) continue;
+        const double wz = hy_weight(sz - (double)(iz0 + c), kr[0], kr[1], kr[2], kr[3]);
+        if (wz == 0.0) continue;
+        const double wzc = v * sgn * wz;
+        double* plane = acc + lz * exy + ly * ex + lx;
+        // every node of the level, zero weights included: a branch per node costs more
+        // than the atomic it would save
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            const double wyz = wzc * wy[b];
+#pragma unroll
+            for (int a = 0; a < NW; ++a) atomicAdd(&plane[b * ex + a], wyz * wx[a]);
+        }
+    }
+}
+
+// The force v0 phi(x - node) and the random finite difference v [phi(x + d - node) -
+// phi(x - d - node)] of one ion in one pass (one atomic per node) when the three
+// windows start at the same node on every axis; false (nothing deposited) otherwise.
+template <int COMP, int KM>
+__device__ __forceinline__ bool own_deposit_rfd(const GridDev& g, double* acc, int ox, int oy, int oz,
+                                                int ex, int exy, double px, double py, double pz,
+                                                double hx, double hy, double hz, double v0, double v,
+                                                const double* kr) {
+    constexpr int NW = 2 * KM;
+    const double ofx = COMP == 0 ? 0.0 : 0.5, ofy = COMP == 1 ? 0.0 : 0.5, ofz = COMP == 2 ? 0.0 : 0.5;
+    const double sx = px * g.inv_h - ofx, sy = py * g.inv_h - ofy, sz = pz * g.inv_h - ofz;
+    const double sxp = (px + hx) * g.inv_h - ofx, syp = (py + hy) * g.inv_h - ofy,
+                 szp = (pz + hz) * g.inv_h - ofz;
+    const double sxm = (px - hx) * g.inv_h - ofx, sym = (py - hy) * g.inv_h - ofy,
+                 szm = (pz - hz) * g.inv_h - ofz;
+    const double fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    if (floor(sxp) != fx || floor(sxm) != fx || floor(syp) != fy || floor(sym) != fy ||
+        floor(szp) != fz || floor(szm) != fz)
+        return false;
+    const int ix0 = (int)fx + 1 - KM, iy0 = (int)fy + 1 - KM, iz0 = (int)fz + 1 - KM;
+    double wx0[NW], wxp[NW], wxm[NW], wy0[NW], wyp[NW], wym[NW];
+    own_axis<KM>(sx, ix0, kr, wx0);
+    own_axis<KM>(sxp, ix0, kr, wxp);
+    own_axis<KM>(sxm, ix0, kr, wxm);
+    own_axis<KM>(sy, iy0, kr, wy0);
+    own_axis<KM>(syp, iy0, kr, wyp);
+    own_axis<KM>(sym, iy0, kr, wym);
+    const int lx = ix0 - ox, ly = iy0 - oy;
+    for (int c = 0; c < NW; ++c) {
+        int lz;
+        double sgn;
+        if (!own_level<COMP>(g, iz0 + c, oz, lz, sgn)) continue;
+        const double nz = (double)(iz0 + c);
+        double z0c = hy_weight(sz - nz, kr[0], kr[1], kr[2], kr[3]);
+        double zpc = hy_weight(szp - nz, kr[0], kr[1], kr[2], kr[3]);
+        double zmc = hy_weight(szm - nz, kr[0], kr[1], kr[2], kr[3]);
+        if (z0c == 0.0 && zpc == 0.0 && zmc == 0.0) continue;
+        z0c *= sgn * v0;
+        zpc *= sgn * v;
+        zmc *= sgn * v;
+        double* plane = acc + lz * exy + ly * ex + lx;
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            const double y0c = z0c * wy0[b], ypc = zpc * wyp[b], ymc = zmc * wym[b];
+#pragma unroll
+            for (int a = 0; a < NW; ++a)
+                atomicAdd(&plane[b * ex + a], y0c * wx0[a] + (ypc * wxp[a] - ymc * wxm[a]));
+        }
+    }
+    return true;
+}
+
+// One ion's deposits: the force, and with rfd its random finite difference (merged when
+// the three windows coincide, else three deposits).
+template <int COMP, int KM>
+__device__ __forceinline__ void own_ion(const GridDev& g, double* acc, int ox, int oy, int oz, int ex,
+                                        int exy, double4 a4, bool rfd, double hx, double hy, double hz,
+                                        double v0, double v, const double* kr) {
+    if (!rfd) {
+        own_deposit1<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4.x, a4.y, a4.z, v0, kr);
+        return;
+    }
+    if (own_deposit_rfd<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4.x, a4.y, a4.z, hx, hy, hz, v0, v, kr))
+        return;
+    own_deposit1<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4.x, a4.y, a4.z, v0, kr);
+    own_deposit1<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4.x + hx, a4.y + hy, a4.z + hz, v, kr);
+    own_deposit1<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4.x - hx, a4.y - hy, a4.z - hz, -v, kr);
+}
+
+// S^hy F (+ the random finite difference) of the table kernels on one face grid: tile
+// (bx, by, bz) of OWN_T^3 cells takes the ions of its cells and adds its region to out,
+// which the caller has zeroed.
+template <int COMP, int KM>
+__global__ void __launch_bounds__(OWN_THREADS)
+spread_face_own_kernel(GridDev g, const double4* __restrict__ sxyzq, const double* __restrict__ fw,
+                       const int* __restrict__ bin_start, RfdDev rfd, const int* __restrict__ ssp,
+                       const double* __restrict__ hy_tab, double* __restrict__ out,
+                       int* __restrict__ flags) {
+    constexpr int H = own_h(KM), E = own_e(KM);
+    __shared__ double acc[E * E * E];
+    __shared__ int rstart[OWN_MAXR], rpre[OWN_MAXR + 1], scan[OWN_THREADS];
+    static_assert(tile_rows_bound(OWN_T, OWN_T, 0, 0) <= OWN_MAXR, "own-tile rows exceed OWN_MAXR");
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);
+    const int tx = min(OWN_T, g.nx), ty = min(OWN_T, g.ny);
+    const int x0 = bx * tx, y0 = by * ty, z0 = bz * OWN_T;
+    const int tz = min(OWN_T, g.nz - z0);  // cells
+    const int ex = tx + 2 * H, ey = ty + 2 * H, ez = tz + 2 * H;
+    const int exy = ex * ey, ne = exy * ez;
+    const int ox = x0 - H, oy = y0 - H, oz = z0 - H;
+    for (int k = threadIdx.x; k < ne; k += OWN_THREADS) acc[k] = 0.0;
+    const int nr = tile_ranges<OWN_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan,
+                                         flags, 0, 0);
+    const int total = rpre[nr];
+    const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
+    for (int f = threadIdx.x; f < total; f += OWN_THREADS) {
+        int r = 0, hi = nr - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (rpre[mid] <= f) r = mid; else hi = mid - 1;
+        }
+        const int i = rstart[r] + (f - rpre[r]);
+        const double4 a4 = sxyzq[i];
+        if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
+        const double* row = hy_row(hy_tab, ssp[i]);
+        const double kr[4] = {row[0], row[1], row[2], row[3]};
+        const double v0 = fw[i] * inv_h3;
+        double v = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
+        if (rfd.scale != 0.0) {
+            const double w0 = rfd.w[i], w1 = rfd.w[i + rfd.wstride], w2 = rfd.w[i + 2 * rfd.wstride];
+            v = rfd.scale * (COMP == 0 ? w0 : (COMP == 1 ? w1 : w2)) * inv_h3;
+            hx = rfd.half * w0;
+            hy = rfd.half * w1;
+            hz = rfd.half * w2;
+        }
+        own_ion<COMP, KM>(g, acc, ox, oy, oz, ex, exy, a4, rfd.scale != 0.0, hx, hy, hz, v0, v, kr);
+    }
+    __syncthreads();
+    const int nzn = COMP == 2 ? g.nz + 1 : g.nz;  // node levels
+    for (int k = threadIdx.x; k < ne; k += OWN_THREADS) {
+        const double v = acc[k];
+        if (v == 0.0) continue;
+        const int lx = k % ex, ly = (k / ex) % ey, gz = oz + k / exy;
+        if (gz < 0 || gz >= nzn) continue;  // never reached by a deposit (folded first)
+        const int gx = wrapi(ox + lx, g.nx), gy = wrapi(oy + ly, g.ny);
+        atomicAdd(&out[((size_t)gz * g.ny + gy) * g.nx + gx], v);
+    }
+}
+
+template <int KM>
+static void spread_faces_own(Ctx* c, const RfdDev& rfd, const int* ssp, double* out, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    fill_f64(out, 3 * (int64_t)ncell + (int64_t)g.nx * g.ny, 0.0, s);
+    const int tx = std::min(OWN_T, g.nx), ty = std::min(OWN_T, g.ny);
+    dim3 grid(g.nx / tx, g.ny / ty, (g.nz + OWN_T - 1) / OWN_T);
+    spread_face_own_kernel<0, KM><<<grid, OWN_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd,
+                                                              ssp, c->hy_tab, out, c->flags);
+    spread_face_own_kernel<1, KM><<<grid, OWN_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max,
+                                                              c->bin_start, rfd, ssp, c->hy_tab,
+                                                              out + ncell, c->flags);
+    spread_face_own_kernel<2, KM><<<grid, OWN_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
+                                                              c->bin_start, rfd, ssp, c->hy_tab,
+                                                              out + 2 * ncell, c->flags);
+}
+
+template <int T>
+static void spread_faces(Ctx* c, const RfdDev& rfd, double* out, hipStream_t s) {
     const GridDev& g = c->gd;
     const int tx = std::min(T, g.nx), ty = std::min(T, g.ny);
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     dim3 grid_c(g.nx / tx, g.ny / ty, (g.nz + T - 1) / T);
     dim3 grid_f(g.nx / tx, g.ny / ty, (g.nz + 1 + T - 1) / T);
-    spread_face_kernel<0, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd,
-                                                              ssp, c->hy_tab, out, c->flags);
-    spread_face_kernel<1, T, KM><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max,
-                                                              c->bin_start, rfd, ssp, c->hy_tab,
-                                                              out + ncell, c->flags);
-    spread_face_kernel<2, T, KM><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
-                                                              c->bin_start, rfd, ssp, c->hy_tab,
-                                                              out + 2 * ncell, c->flags);
+    spread_face_kernel<0, T><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp, c->bin_start, rfd, out,
+                                                          c->flags);
+    spread_face_kernel<1, T><<<grid_c, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + c->n_max, c->bin_start,
+                                                          rfd, out + ncell, c->flags);
+    spread_face_kernel<2, T><<<grid_f, SH_THREADS, 0, s>>>(g, c->sxyzq, c->fp + 2 * c->n_max,
+                                                          c->bin_start, rfd, out + 2 * ncell, c->flags);
 }
 
 int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in, int species, int n) {
@@ -379,9 +487,9 @@ int spread_force_sorted(Ctx* c, double* out, hipStream_t s, const RfdDev* rfd_in
         rfd.wstride = c->n_max;
     }
     const int km = species ? c->hy_km : 0;
-    if (km == 0) spread_faces<SH_TX, 0>(c, rfd, nullptr, out, s);
-    else if (km <= 2) spread_faces<16, 2>(c, rfd, c->ssp, out, s);
-    else spread_faces<16, 4>(c, rfd, c->ssp, out, s);
+    if (km == 0) spread_faces<SH_TX>(c, rfd, out, s);
+    else if (km <= 2) spread_faces_own<2>(c, rfd, c->ssp, out, s);
+    else spread_faces_own<4>(c, rfd, c->ssp, out, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
