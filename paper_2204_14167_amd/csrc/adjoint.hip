@@ -252,12 +252,15 @@ flux_lambda_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restrict__
 
 // ---- per-ion gradients: gather of rbar (homogeneous folds) on the centre window and of
 // the x-face differences of phi_ext (wall ghosts) on the face window ------------------
+// 16^3 tiles: the two staged arrays with their halos fill most of the LDS, so one
+// workgroup runs per CU; 12 wavefronts of it take the tile's ions (about 512 at the
+// densities of the workloads) and the staging
 #define GT_TX 16
 #define GT_TY 16
-#define GT_TZ 6
+#define GT_TZ 16
 #define GT_H 5
-#define GT_THREADS 256
-#define GT_MAXR 64
+#define GT_THREADS 768
+#define GT_MAXR 64  // bin rows of a tile: 8 z slabs x 8 y rows
 #define GT_UNROLL 4  // staging elements in flight per thread
 
 __global__ void __launch_bounds__(GT_THREADS)
@@ -271,7 +274,9 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     __shared__ double tph[LZ * LY * LX];
     __shared__ int rstart[GT_MAXR], rpre[GT_MAXR + 1], scan[GT_THREADS];
     const int tx = min(GT_TX, g.nx), ty = min(GT_TY, g.ny);
-    const int x0 = blockIdx.x * tx, y0 = blockIdx.y * ty, z0 = blockIdx.z * GT_TZ;
+    int bx, by, bz;
+    xcd_block3(bx, by, bz);  // neighbouring tiles, whose halos overlap, on one XCD
+    const int x0 = bx * tx, y0 = by * ty, z0 = bz * GT_TZ;
     const int tz = min(GT_TZ, g.nz - z0);
     const int lxn = tx + GT_H, lyn = ty + GT_H, lzn = tz + GT_H;
     const double dV = g.h * g.h * g.h;
@@ -281,6 +286,8 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
     const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
+    static_assert((GT_TZ / DISCOS_BIN) * (GT_TY / DISCOS_BIN) <= GT_MAXR && GT_MAXR <= GT_THREADS,
+                  "gradient tile rows exceed GT_MAXR");
     const int nrows = (bz1 - bz0 + 1) * nbyt;
     {
         int len = 0;
