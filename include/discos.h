@@ -182,10 +182,11 @@ int discos_spread(discos_ctx* ctx, int op, int64_t n, const double* pos, const d
  * rho = S^es q (eq kernel2, images folded per Sec. II.B.1; with DISCOS_SPREAD_ADD_BC in
  * flags, the wall terms as for discos_spread).  pos [3][n], q [n] and rho [nz][ny][nx]
  * are DEVICE arrays owned by the caller; rho is overwritten.  p supplies eps, bc_type
- * and bc_value only.  status: DEVICE int32 [1] or NULL; receives DISCOS_OK or the
+ * and bc_value only; bc_type_map must be NULL (walls of one type each), else
+ * DISCOS_E_ARG.  status: DEVICE int32 [1] or NULL; receives DISCOS_OK or the
  * sticky device condition of this call (DISCOS_E_NONFINITE, DISCOS_E_CAPACITY,
  * DISCOS_E_OUT_OF_DOMAIN).
- * Allocates nothing: its cell list lives in one fixed device array of about 6.5 MiB
+ * Allocates nothing: its cell list lives in one fixed device array of about 4.8 MiB
  * per GPU, held until the process ends, which limits a call to
  * n <= DISCOS_NOALLOC_MAX_IONS and (nx/2)(ny/2)ceil(nz/2) <= DISCOS_NOALLOC_MAX_BINS
  * (for example 65,536 ions on 128 x 128 x 64 cells); larger calls return
@@ -340,7 +341,8 @@ int discos_energy_flux(discos_ctx* ctx, int64_t n, const double* pos, const doub
  * cell list of the ions unless flags has DISCOS_ADJ_REUSE_CELLS: the caller then states
  * that pos and q are unchanged since the discos_energy_flux call that wrote phi, and
  * the cell list that call built is used again, if no call on the context has rebuilt
- * it since and n is the same (else it is rebuilt).
+ * it since and n is the same (else it is rebuilt); de then also takes the sum of
+ * w(z_i) q_i that the forward pass accumulated, when p->eta is the same.
  */
 #define DISCOS_ADJ_REUSE_CELLS 1u
 int discos_energy_flux_backward(discos_ctx* ctx, int64_t n, const double* pos, const double* q,

@@ -90,19 +90,26 @@ dot_partials_kernel(const double* __restrict__ a, const double* __restrict__ b, 
     block_sum_store(acc, part + blockIdx.x);
 }
 
-// sum_i w(z_i) v_i with v the sorted x forces (fx) or, with fx null, the charges.
+// sum_i w(z_i) v_i with v the sorted x forces (fx) or, with fx null, the charges; with
+// part_q also sum_i w(z_i) q_i (the gradient of Q in E_ext, kept for the backward pass).
 __global__ void __launch_bounds__(RD_THREADS)
 flux_partials_kernel(GridDev g, FluxDev f, const double4* __restrict__ sxyzq,
-                     const double* __restrict__ fx, int n, double* __restrict__ part) {
-    double acc = 0.0;
+                     const double* __restrict__ fx, int n, double* __restrict__ part,
+                     double* __restrict__ part_q) {
+    double acc = 0.0, accq = 0.0;
     for (int i = blockIdx.x * RD_THREADS + threadIdx.x; i < n; i += gridDim.x * RD_THREADS) {
         const double4 a4 = sxyzq[i];
         if (!pos_ok(g, a4.x, a4.y, a4.z)) continue;
         double w, dw;
         flux_weight(g, f, a4.z, w, dw);
         acc += w * (fx ? fx[i] : a4.w);
+        accq += w * a4.w;
     }
     block_sum_store(acc, part + blockIdx.x);
+    if (part_q) {
+        __syncthreads();  // the block sum's LDS is reused
+        block_sum_store(accq, part_q + blockIdx.x);
+    }
 }
 
 // out[0] = scale (* mul[0] if given) * sum(part); with zero_tail also out[1] = out[2] = 0.
@@ -130,8 +137,8 @@ static int nparts_for(int64_t n) {
 
 // ---- transposed E_x gather: lambda_i = gQ w_i q_i onto the cell grid --------------
 #define AS_T 16   // tile edge in x and y
-#define AS_TZ 8   // tile edge in z
-#define AS_THREADS 256
+#define AS_TZ 16  // tile edge in z
+#define AS_THREADS 512
 #define AS_MAXR 256
 
 __global__ void __launch_bounds__(AS_THREADS)
@@ -476,14 +483,16 @@ int energy_flux(Ctx* c, int n, const discos_params* p, const double* phi, double
     dot_partials_kernel<<<pu, RD_THREADS, 0, s>>>(c->rho, phi, c->ncell, c->part);
     finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part, pu, 0.5 * dV, nullptr, 0, out);
     const int pq = nparts_for(n);
-    flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(c->gd, flux_of(c, p), c->sxyzq, c->fp, n,
-                                                   c->part + PART_MAX);
+    const FluxDev f = flux_of(c, p);
+    flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(c->gd, f, c->sxyzq, c->fp, n, c->part + PART_MAX,
+                                                   c->part + 2 * PART_MAX);
     finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part + PART_MAX, pq, 1.0, nullptr, 0, out + 1);
+    c->ef_wq = f.inv2etanz;  // the partials of sum w q held for this flux weight
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* phi, const double* gvec,
-                         double* dpos, double* dq, double* dlo, double* dhi, double* de,
+                         double* dpos, double* dq, double* dlo, double* dhi, double* de, bool reuse,
                          hipStream_t s) {
     const GridDev& g = c->gd;
     const FluxDev f = flux_of(c, p);
@@ -505,9 +514,12 @@ int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* ph
         flux_bc_kernel<<<(int)((ncol + 255) / 256), 256, 0, s>>>(g, wl, phi, c->phi, gvec, c->bcg, dlo, dhi);
     }
     if (de) {
+        // sum w q: from the forward pass when it ran on these cells with this weight
         const int pq = nparts_for(n);
-        flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(g, f, c->sxyzq, nullptr, n, c->part + PART_MAX);
-        finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part + PART_MAX, pq, 1.0, gvec + 1, 1, de);
+        if (!(reuse && c->ef_wq == f.inv2etanz))
+            flux_partials_kernel<<<pq, RD_THREADS, 0, s>>>(g, f, c->sxyzq, nullptr, n,
+                                                           c->part + 2 * PART_MAX, nullptr);
+        finish_kernel<<<1, RD_THREADS, 0, s>>>(c->part + 2 * PART_MAX, pq, 1.0, gvec + 1, 1, de);
     }
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }

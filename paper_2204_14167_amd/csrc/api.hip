@@ -245,7 +245,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     bytes += carve_bytes(g.nx / 2, sizeof(double2));
     bytes += carve_bytes(g.ny / 2, sizeof(double2));
     bytes += carve_bytes(64, sizeof(int));
-    bytes += carve_bytes(2 * PART_MAX, sizeof(double));                 // reduction partials
+    bytes += carve_bytes(3 * PART_MAX, sizeof(double));                 // reduction partials
     bytes += carve_bytes(2 * (size_t)g.nx * g.ny, sizeof(double));     // wall adjoints
     bytes += carve_bytes(3 * (size_t)c->ncell, sizeof(double)) + carve_bytes(8, sizeof(double));  // CG
     // the near field's padded cell list, sized for search radii up to 3 bins
@@ -278,7 +278,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->tw_x = carve<double2>(cur, g.nx / 2);
     c->tw_y = carve<double2>(cur, g.ny / 2);
     c->flags = carve<int>(cur, 64);
-    c->part = carve<double>(cur, 2 * PART_MAX);
+    c->part = carve<double>(cur, 3 * PART_MAX);
     c->bcg = carve<double>(cur, 2 * (size_t)g.nx * g.ny);
     c->pcg = carve<double>(cur, 3 * (size_t)c->ncell);
     c->pcg_s = carve<double>(cur, 8);
@@ -358,6 +358,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->cl_gen = 0;
     c->ef_gen = ~(uint64_t)0;  // no forward list yet
     c->ef_n = -1;
+    c->ef_wq = 0.0;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;
     c->last_stream = nullptr;
@@ -663,6 +664,7 @@ int discos_energy_flux(discos_ctx* c, int64_t n, const double* pos, const double
     if (rc) return rc;
     if (!finite_pos(p->eta)) return fail(c, DISCOS_E_ARG, "eta must be positive (flux weight)");
     const int ni = (int)n;
+    c->ef_wq = 0.0;  // set again by a complete forward pass
     rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
     c->ef_gen = c->cl_gen;
     c->ef_n = ni;
@@ -693,7 +695,7 @@ int discos_energy_flux_backward(discos_ctx* c, int64_t n, const double* pos, con
     // has rebuilt it since
     const bool reuse = (flags & DISCOS_ADJ_REUSE_CELLS) && c->ef_gen == c->cl_gen && c->ef_n == ni;
     if (!reuse) rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, q, nullptr, nullptr, s);
-    if (!rc) rc = discos::energy_flux_backward(c, ni, p, phi, g, dpos, dq, dbc_lo, dbc_hi, de, s);
+    if (!rc) rc = discos::energy_flux_backward(c, ni, p, phi, g, dpos, dq, dbc_lo, dbc_hi, de, reuse, s);
     return rc ? fail(c, rc, "energy/flux backward launch failed") : DISCOS_OK;
 }
 

@@ -63,7 +63,8 @@ struct Ctx {
     double* hvel;     // face velocity scratch for the wet step (3 face arrays)
     double* hfor;     // face force scratch (3 face arrays)
     double* hvi;      // [3][n_max] interpolated ion velocities
-    double* part;     // [2][PART_MAX] partial sums of the deterministic reductions
+    double* part;     // [3][PART_MAX] partial sums of the deterministic reductions (the third:
+                      // sum w(z) q of the last energy / flux forward pass)
     double* bcg;      // [2][ny][nx] wall-field adjoints gathered from the ghost layers
     // hydrodynamic kernel per species: [DISCOS_HY_MAXSP + 1][4] rows (w, beta, 1 / alpha,
     // 1 / integral), w = 0 for the 4-point Peskin kernel (every row past the set ones,
@@ -82,6 +83,7 @@ struct Ctx {
     uint64_t cl_gen;
     uint64_t ef_gen;
     int ef_n;
+    double ef_wq;  // flux weight (1 / (2 eta nz)) the held sum w q was taken with; 0: none
     // stage timing (discos_profile): one row of DISCOS_NSTAGE + 1 events per step,
     // for up to PROF_MAX steps
     int profile;
@@ -249,7 +251,7 @@ int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const do
 int energy_flux(Ctx* c, int n, const discos_params* p, const double* phi, double* out, hipStream_t s);
 // Reverse sweep of energy_flux over the current cell list (outputs nullable).
 int energy_flux_backward(Ctx* c, int n, const discos_params* p, const double* phi, const double* gvec,
-                         double* dpos, double* dq, double* dlo, double* dhi, double* de,
+                         double* dpos, double* dq, double* dlo, double* dhi, double* de, bool reuse,
                          hipStream_t s);
 
 // Batched stages (one launch each over all channels of the batch).

@@ -86,7 +86,8 @@ extern "C" int discos_spread_charge_noalloc(const discos_grid* grid, int64_t n, 
         return DISCOS_E_SHAPE;
     if (!(std::isfinite(p->eps) && p->eps > 0.0)) return DISCOS_E_ARG;
     for (int w = 0; w < 2; ++w)
-        if (p->bc_type[w] != DISCOS_BC_DIRICHLET && p->bc_type[w] != DISCOS_BC_NEUMANN)
+        if ((p->bc_type[w] != DISCOS_BC_DIRICHLET && p->bc_type[w] != DISCOS_BC_NEUMANN) ||
+            p->bc_type_map[w] != nullptr)  // walls of one type each only
             return DISCOS_E_ARG;
     discos::Ctx c{};
     discos::GridDev& g = c.gd;

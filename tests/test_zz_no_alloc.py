@@ -78,6 +78,13 @@ def test_noalloc_spread_flags_and_refusals():
     with pytest.raises(discos.DiscosError) as e:
         discos.spread_charge_noalloc((nx, ny, nz, 1.0), dev(np.zeros((3, big))), dev(np.zeros(big)), p)
     assert e.value.code == discos.E_CAPACITY
+    # walls whose type varies per column are not taken
+    pm = _params((0, 0), nx, ny, seed=1)
+    pm["bc_types"] = (np.zeros((ny, nx), dtype=np.int32), 0)
+    with pytest.raises(discos.DiscosError) as e:
+        discos.spread_charge_noalloc((nx, ny, nz, 1.0), dev(pos), dev(q),
+                                     discos.Params(pm, (nx, ny, nz, 1.0)))
+    assert e.value.code == discos.E_ARG
     p2 = discos.Params(_params((0, 0), 1024, 1024, seed=1), (1024, 1024, 8, 1.0))
     with pytest.raises(discos.DiscosError) as e:
         discos.spread_charge_noalloc((1024, 1024, 8, 1.0), dev(pos), dev(q), p2)
