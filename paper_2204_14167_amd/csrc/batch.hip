@@ -288,6 +288,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         for (int v = 0; v < 2; ++v) bytes += carve_bytes(std::max<size_t>(tk[kind][v].size(), 1), sizeof(int2));
     bytes += carve_bytes(std::max<int64_t>(wall, 1), sizeof(double));
     bytes += carve_bytes(tw_all.size(), sizeof(double2));
+    bytes += carve_bytes(b->classes.size(), sizeof(discos::FftClassDev));
     if (hipMalloc(&b->pool, bytes) != hipSuccess) {
         destroy(b);
         return DISCOS_E_HIP;
@@ -302,6 +303,9 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->nl.sp = carve<int>(cur, nl_cap);
     b->nl.cap = nl_cap;
     b->nl.bins_cap = pbin_off[count];
+    int pmax = 1;
+    for (int r = 0; r < count; ++r) pmax = std::max(pmax, pbin_off[r + 1] - pbin_off[r]);
+    b->pbin_xblocks = std::min((pmax + 255) / 256, 64);
     b->pbin_off = carve<int>(cur, count + 1);
     b->sid = carve<int>(cur, n);
     b->ssp = carve<int>(cur, n);
@@ -338,6 +342,34 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         b->classes[c].tw_x = tw_d + tw_at[c].first;
         b->classes[c].tw_y = tw_d + tw_at[c].second;
     }
+    // the batched FFT passes' class table (block ranges and LDS as the per-grid passes)
+    b->fcls = carve<discos::FftClassDev>(cur, b->classes.size());
+    std::vector<discos::FftClassDev> fcls;
+    b->fft_xblocks = b->fft_yblocks = 0;
+    b->fft_xlds = b->fft_ylds = 0;
+    for (const discos::BatchClass& k : b->classes) {
+        discos::FftClassDev f{};
+        f.tw_x = k.tw_x;
+        f.tw_y = k.tw_y;
+        f.cell_off = k.cell_off;
+        f.spec_off = k.spec_off;
+        f.nx = k.nx;
+        f.ny = k.ny;
+        f.nxh = k.nx / 2 + 1;
+        f.logx = __builtin_ctz((unsigned)k.nx);
+        f.logy = __builtin_ctz((unsigned)k.ny);
+        f.npairs = k.rows / 2;
+        f.ppb = std::max(1, 2048 / k.nx);
+        f.xb0 = b->fft_xblocks;
+        f.ltpb = __builtin_ctz((unsigned)std::max(1, 1024 / k.ny));
+        f.ncol = f.nxh * k.levels;
+        f.yb0 = b->fft_yblocks;
+        b->fft_xblocks += (f.npairs + f.ppb - 1) / f.ppb;
+        b->fft_yblocks += (f.ncol + (1 << f.ltpb) - 1) >> f.ltpb;
+        b->fft_xlds = std::max(b->fft_xlds, (size_t)f.ppb * k.nx * sizeof(double2));
+        b->fft_ylds = std::max(b->fft_ylds, ((size_t)k.ny << f.ltpb) * sizeof(double2));
+        fcls.push_back(f);
+    }
     // host tables -> device
     std::vector<int> ion_rep(n, 0);
     std::vector<double> walls(std::max<int64_t>(wall, 1), 0.0);
@@ -360,6 +392,8 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     ok = ok && hipMemcpy(b->mode_off, mode_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->mode_rep, mode_rep.data(), count * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(tw_d, tw_all.data(), tw_all.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->fcls, fcls.data(), fcls.size() * sizeof(discos::FftClassDev),
+                         hipMemcpyHostToDevice) == hipSuccess;
     for (int kind = 0; kind < 2; ++kind)
         for (int v = 0; v < 2; ++v)
             if (!tk[kind][v].empty())

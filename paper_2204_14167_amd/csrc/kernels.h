@@ -103,6 +103,18 @@ struct BatchClass {   // channels of one (nx, ny): their grids and spectra are c
     double2 *tw_x, *tw_y;
 };
 
+// One (nx, ny) class as the batched FFT passes read it: its first x-pass block (xb0,
+// blocks of ppb row pairs) and first y-pass block (yb0, blocks of 2^ltpb of its ncol
+// spectrum columns).
+struct FftClassDev {
+    const double2* tw_x;
+    const double2* tw_y;
+    int64_t cell_off, spec_off;
+    int nx, ny, nxh, logx, logy;
+    int npairs, ppb, xb0;
+    int ltpb, ncol, yb0;
+};
+
 struct BatchCfg {   // launch choices (the autotuner's output)
     int spread_t;       // spread tile edge: 8 or 16
     int spread_blocks;  // persistent blocks of the spread (0: one per task)
@@ -133,11 +145,15 @@ struct Batch {
     bool z_legacy = false;         // some channel has nz > 128 (per-mode Thomas, scratch cprime)
     bool z_singular = false;       // both walls Neumann
     std::vector<BatchClass> classes;
+    FftClassDev* fcls;            // [classes] for the batched FFT passes
+    int fft_xblocks, fft_yblocks; // blocks of the x passes and of the y pass
+    size_t fft_xlds, fft_ylds;    // their dynamic LDS
     double* walls;                 // per-channel wall fields [2][ny][nx], back to back
     double4* sxyzq;
     int *sid, *ssp, *perm, *ion_bin, *ion_rank, *bin_count, *bin_start, *scan_tmp;
     NearList nl;                   // padded copy of the near field (every channel's bins)
-    int* pbin_off;                 // [R + 1] first padded bin of each channel (device)
+    int* pbin_off;
+    int pbin_xblocks;  // x blocks of the per-channel padded-bin grid (the largest channel's)                 // [R + 1] first padded bin of each channel (device)
     double *rho, *phi, *cprime, *fp;
     double2* spec;
     int* flags;

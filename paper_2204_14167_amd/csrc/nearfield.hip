@@ -306,24 +306,18 @@ __global__ void pad_count_kernel(GridDev g, int R, int64_t nb, const int* __rest
     }
 }
 
-// Batched: padded bin P belongs to the channel r with pbin_off[r] <= P < pbin_off[r + 1].
+// Batched: channels r = blockIdx.y, + gridDim.y, ..., whose padded bins are
+// [pbin_off[r], pbin_off[r + 1]).
 __global__ void pad_count_batch_kernel(const RepDev* __restrict__ reps, int nrep, int R,
                                        const int* __restrict__ pbin_off, const int* __restrict__ bin_start,
                                        int* __restrict__ count) {
-    const int64_t nb = pbin_off[nrep];
-    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < nb;
-         P += (int64_t)gridDim.x * blockDim.x) {
-        int lo = 0, hi = nrep - 1;
-        while (lo < hi) {  // last channel with pbin_off[r] <= P
-            const int mid = (lo + hi + 1) >> 1;
-            if (pbin_off[mid] <= P)
-                lo = mid;
-            else
-                hi = mid - 1;
+    for (int r = blockIdx.y; r < nrep; r += gridDim.y) {
+        const RepDev& Rp = reps[r];
+        const int p0 = pbin_off[r], nb = pbin_off[r + 1] - p0;
+        for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < nb; P += gridDim.x * blockDim.x) {
+            const int s = pad_source(Rp.g, R, P);
+            count[p0 + P] = s < 0 ? 0 : bin_start[Rp.bin_off + s + 1] - bin_start[Rp.bin_off + s];
         }
-        const RepDev& Rp = reps[lo];
-        const int s = pad_source(Rp.g, R, (int)(P - pbin_off[lo]));
-        count[P] = s < 0 ? 0 : bin_start[Rp.bin_off + s + 1] - bin_start[Rp.bin_off + s];
     }
 }
 
@@ -868,7 +862,7 @@ int batch_near(Batch* b, hipStream_t s) {
     const NearDev P = near_of_h(b->h, &b->p);
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
     const int nrep = (int)b->reps.size();
-    pad_count_batch_kernel<<<(int)std::min<int64_t>((b->nl.bins_cap + 255) / 256, 4096), 256, 0, s>>>(
+    pad_count_batch_kernel<<<dim3(b->pbin_xblocks, std::min(nrep, 65535)), 256, 0, s>>>(
         b->reps_d, nrep, P.R, b->pbin_off, b->bin_start, b->nl.count);
     scan_counts(b->nl.count, b->nl.bins_cap, b->nl.tmp, b->nl.start, s);
     const NlOut o{b->nl.xyzq, b->nl.xyzf, b->nl.sp, b->nl.cap, b->flags};

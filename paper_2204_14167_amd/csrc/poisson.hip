@@ -100,12 +100,11 @@ __device__ void lds_fft(double2* a, int N, int logN, int lines, const double2* _
 
 // Real rows (nrows of length nx, rows r and r+1 packed as one complex line) ->
 // half spectra [nrows][nx/2 + 1].
-__global__ void __launch_bounds__(FFT_THREADS)
-fft_x_r2c_kernel(const double* __restrict__ in, double2* __restrict__ spec, int nx, int logN,
-                 int npairs, int ppb, const double2* __restrict__ tw) {
-    extern __shared__ double2 lds[];
+__device__ __forceinline__ void fft_x_r2c_block(const double* __restrict__ in, double2* __restrict__ spec,
+                                                int nx, int logN, int npairs, int ppb,
+                                                const double2* __restrict__ tw, int blk, double2* lds) {
     const int nxh = nx / 2 + 1;
-    const int p0 = blockIdx.x * ppb;
+    const int p0 = blk * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e >> logN, n = e & (nx - 1);
         const int pr = p0 + p;
@@ -144,13 +143,19 @@ fft_x_r2c_kernel(const double* __restrict__ in, double2* __restrict__ spec, int 
     }
 }
 
-// Half spectra -> real rows (inverse, unnormalised).
 __global__ void __launch_bounds__(FFT_THREADS)
-fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int nx, int logN,
+fft_x_r2c_kernel(const double* __restrict__ in, double2* __restrict__ spec, int nx, int logN,
                  int npairs, int ppb, const double2* __restrict__ tw) {
     extern __shared__ double2 lds[];
+    fft_x_r2c_block(in, spec, nx, logN, npairs, ppb, tw, blockIdx.x, lds);
+}
+
+// Half spectra -> real rows (inverse, unnormalised).
+__device__ __forceinline__ void fft_x_c2r_block(const double2* __restrict__ spec, double* __restrict__ out,
+                                                int nx, int logN, int npairs, int ppb,
+                                                const double2* __restrict__ tw, int blk, double2* lds) {
     const int nxh = nx / 2 + 1;
-    const int p0 = blockIdx.x * ppb;
+    const int p0 = blk * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e >> logN, n = e & (nx - 1);
         const int pr = p0 + p;
@@ -185,32 +190,97 @@ fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int
     }
 }
 
-// Complex FFT along y of spec[k][j][m] for a block of MC consecutive m at one k.
-// Spectrum rows (nx/2 + 1 entries) do not start on cache-line boundaries, so the
-// blocks of neighbouring m share lines; the XCD renumbering runs all blocks of a level
-// on one XCD, where the second read of a shared line hits its L2.
 __global__ void __launch_bounds__(FFT_THREADS)
-fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int mc,
-             const double2* __restrict__ tw, int inv) {
+fft_x_c2r_kernel(const double2* __restrict__ spec, double* __restrict__ out, int nx, int logN,
+                 int npairs, int ppb, const double2* __restrict__ tw) {
     extern __shared__ double2 lds[];
-    int bx, by, bz;
-    xcd_block3(bx, by, bz);
-    const int m0 = bx * mc;
-    const size_t kbase = (size_t)by * ny * nxh;
-    const int lmc = __builtin_ctz(mc);
-    for (int e = threadIdx.x; e < mc * ny; e += blockDim.x) {
-        const int c = e & (mc - 1), j = e >> lmc;
-        const int m = m0 + c;
-        lds[c * ny + bitrev(j, logN)] =
-            (m < nxh) ? spec[kbase + (size_t)j * nxh + m] : make_double2(0.0, 0.0);
+    fft_x_c2r_block(spec, out, nx, logN, npairs, ppb, tw, blockIdx.x, lds);
+}
+
+// Complex FFTs along y of spec[k][j][m]: the columns (k, m) of nlev levels, numbered
+// t = k nxh + m, are taken tpb at a time (tpb = 2^ltpb) by one block, so that no block
+// holds padding columns and small grids put several levels in one block.  For a fixed j
+// the block's columns are consecutive m (a level's boundary aside), so its loads and
+// stores run along spectrum rows.
+__device__ __forceinline__ void fft_y_block(double2* __restrict__ spec, int nxh, int ny, int logN,
+                                            int ltpb, int ncol, const double2* __restrict__ tw,
+                                            int inv, int blk, double2* lds) {
+    const int tpb = 1 << ltpb;
+    const int t0 = blk * tpb;
+    // t -> (k, m) with k = t / nxh through a float reciprocal when t < 2^22 (t exact as a
+    // float, the quotient off by at most one and corrected), else an integer division
+    const float inv_nxh = 1.0f / (float)nxh;
+    const bool fdiv = ncol < (1 << 22);
+    auto at = [&](int t, int j) {
+        int k = fdiv ? (int)((float)t * inv_nxh) : t / nxh;
+        int m = t - k * nxh;
+        if (m < 0) {
+            --k;
+            m += nxh;
+        } else if (m >= nxh) {
+            ++k;
+            m -= nxh;
+        }
+        return ((size_t)k * ny + j) * nxh + m;
+    };
+    for (int e = threadIdx.x; e < tpb * ny; e += blockDim.x) {
+        const int c = e & (tpb - 1), j = e >> ltpb;
+        const int t = t0 + c;
+        lds[c * ny + bitrev(j, logN)] = t < ncol ? spec[at(t, j)] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    lds_fft(lds, ny, logN, mc, tw, inv);
-    for (int e = threadIdx.x; e < mc * ny; e += blockDim.x) {
-        const int c = e & (mc - 1), j = e >> lmc;
-        const int m = m0 + c;
-        if (m < nxh) spec[kbase + (size_t)j * nxh + m] = lds[c * ny + j];
+    lds_fft(lds, ny, logN, tpb, tw, inv);
+    for (int e = threadIdx.x; e < tpb * ny; e += blockDim.x) {
+        const int c = e & (tpb - 1), j = e >> ltpb;
+        const int t = t0 + c;
+        if (t < ncol) spec[at(t, j)] = lds[c * ny + j];
     }
+}
+
+__global__ void __launch_bounds__(FFT_THREADS)
+fft_y_kernel(double2* __restrict__ spec, int nxh, int ny, int logN, int ltpb, int ncol,
+             const double2* __restrict__ tw, int inv) {
+    extern __shared__ double2 lds[];
+    // consecutive blocks (neighbouring columns, which share cache lines) on one XCD
+    fft_y_block(spec, nxh, ny, logN, ltpb, ncol, tw, inv, xcd_block(blockIdx.x, gridDim.x), lds);
+}
+
+// The same passes over every (nx, ny) class of a batch in one launch: block b belongs
+// to the last class whose first block (xb0 for the x passes, yb0 for the y pass) is at
+// most b.
+__device__ __forceinline__ int fft_class_of(const FftClassDev* __restrict__ cls, int ncls, int b, bool y) {
+    int k = 0;
+    while (k + 1 < ncls && (y ? cls[k + 1].yb0 : cls[k + 1].xb0) <= b) ++k;
+    return k;
+}
+
+__global__ void __launch_bounds__(FFT_THREADS)
+fft_x_r2c_cls_kernel(const FftClassDev* __restrict__ cls, int ncls, const double* __restrict__ in,
+                     double2* __restrict__ spec) {
+    extern __shared__ double2 lds[];
+    const int k = fft_class_of(cls, ncls, blockIdx.x, false);
+    const FftClassDev& c = cls[k];
+    fft_x_r2c_block(in + c.cell_off, spec + c.spec_off, c.nx, c.logx, c.npairs, c.ppb, c.tw_x,
+                    blockIdx.x - c.xb0, lds);
+}
+
+__global__ void __launch_bounds__(FFT_THREADS)
+fft_x_c2r_cls_kernel(const FftClassDev* __restrict__ cls, int ncls, const double2* __restrict__ spec,
+                     double* __restrict__ out) {
+    extern __shared__ double2 lds[];
+    const int k = fft_class_of(cls, ncls, blockIdx.x, false);
+    const FftClassDev& c = cls[k];
+    fft_x_c2r_block(spec + c.spec_off, out + c.cell_off, c.nx, c.logx, c.npairs, c.ppb, c.tw_x,
+                    blockIdx.x - c.xb0, lds);
+}
+
+__global__ void __launch_bounds__(FFT_THREADS)
+fft_y_cls_kernel(const FftClassDev* __restrict__ cls, int ncls, double2* __restrict__ spec, int inv) {
+    extern __shared__ double2 lds[];
+    const int b = xcd_block(blockIdx.x, gridDim.x);  // a class's levels on neighbouring XCDs
+    const int k = fft_class_of(cls, ncls, b, true);
+    const FftClassDev& c = cls[k];
+    fft_y_block(spec + c.spec_off, c.nxh, c.ny, c.logy, c.ltpb, c.ncol, c.tw_y, inv, b - c.yb0, lds);
 }
 
 // Tridiagonal solve along z for every in-plane mode (one thread per mode).
@@ -613,12 +683,17 @@ int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
-int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
+// The y pass over nlev levels: 1024 elements (1024 / ny columns) per block.
+static void fft_y_launch(const Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
     const int ny = c->gd.ny, nxh = c->gd.nxh;
-    const int mc = std::max(1, std::min(16, 1024 / ny));
-    dim3 gy((nxh + mc - 1) / mc, nlev);
-    fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * ny * sizeof(double2), s>>>(spec, nxh, ny, ilog2(ny), mc,
-                                                                           c->tw_y, inv);
+    const int ltpb = ilog2(std::max(1, 1024 / ny));
+    const int ncol = nlev * nxh;
+    fft_y_kernel<<<(ncol + (1 << ltpb) - 1) >> ltpb, FFT_THREADS, ((size_t)ny << ltpb) * sizeof(double2),
+                   s>>>(spec, nxh, ny, ilog2(ny), ltpb, ncol, c->tw_y, inv);
+}
+
+int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
+    fft_y_launch(c, spec, nlev, inv, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -640,10 +715,7 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(rhs, c->spec, nx, ilog2(nx),
                                                                         npairs, ppb, c->tw_x);
     if (mark_base >= 0) stage_mark(c, mark_base, s);
-    const int mc = std::max(1, std::min(16, 1024 / ny));
-    const size_t ldsy = (size_t)mc * ny * sizeof(double2);
-    dim3 gy((nxh + mc - 1) / mc, nz);
-    fft_y_kernel<<<gy, FFT_THREADS, ldsy, s>>>(c->spec, nxh, ny, ilog2(ny), mc, c->tw_y, 0);
+    fft_y_launch(c, c->spec, nz, 0, s);
     if (mark_base >= 0) stage_mark(c, mark_base + 1, s);
     const double scale = (c->grid.h * c->grid.h / p->eps) / ((double)nx * ny);
     const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
@@ -675,7 +747,7 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
                                                       singular, c->flags);
     }
     if (mark_base >= 0) stage_mark(c, mark_base + 2, s);
-    fft_y_kernel<<<gy, FFT_THREADS, ldsy, s>>>(c->spec, nxh, ny, ilog2(ny), mc, c->tw_y, 1);
+    fft_y_launch(c, c->spec, nz, 1, s);
     if (mark_base >= 0) stage_mark(c, mark_base + 3, s);
     fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(c->spec, phi, nx, ilog2(nx),
                                                                         npairs, ppb, c->tw_x);
@@ -696,21 +768,14 @@ int batch_pivots(Batch* b, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
-// Poisson for every channel: x- and y-FFTs per size class (a class's grids and spectra
-// are contiguous, so its rows and levels form single ranges); z-solves with pivots per
-// segment length (one launch each), the Thomas sweep for channels with nz > 128.
+// Poisson for every channel: each FFT pass one launch over every (nx, ny) class (a
+// class's grids and spectra are contiguous, so its rows and levels form single ranges);
+// z-solves with pivots per segment length (one launch each), the Thomas sweep for
+// channels with nz > 128.
 int batch_poisson(Batch* b, hipStream_t s) {
-    for (const BatchClass& k : b->classes) {
-        const int nxh = k.nx / 2 + 1;
-        const int ppb = std::max(1, 2048 / k.nx);
-        const int npairs = k.rows / 2;
-        fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * k.nx * sizeof(double2), s>>>(
-            b->rho + k.cell_off, b->spec + k.spec_off, k.nx, ilog2(k.nx), npairs, ppb, k.tw_x);
-        const int mc = std::max(1, std::min(16, 2048 / k.ny));
-        dim3 gy((nxh + mc - 1) / mc, k.levels);
-        fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * k.ny * sizeof(double2), s>>>(
-            b->spec + k.spec_off, nxh, k.ny, ilog2(k.ny), mc, k.tw_y, 0);
-    }
+    const int ncls = (int)b->classes.size();
+    fft_x_r2c_cls_kernel<<<b->fft_xblocks, FFT_THREADS, b->fft_xlds, s>>>(b->fcls, ncls, b->rho, b->spec);
+    fft_y_cls_kernel<<<b->fft_yblocks, FFT_THREADS, b->fft_ylds, s>>>(b->fcls, ncls, b->spec, 0);
     if (b->ztasks_n[0] > 0)
         zsolve_seg_batch_kernel<8><<<(b->ztasks_n[0] + 3) / 4, 256, 0, s>>>(b->reps_d, b->ztasks[0],
                                                                           b->ztasks_n[0], b->spec, b->zg);
@@ -724,17 +789,8 @@ int batch_poisson(Batch* b, hipStream_t s) {
     if (b->z_legacy)
         zsolve_batch_kernel<<<(int)((b->nmode_tot + 63) / 64), 64, 0, s>>>(
             b->reps_d, b->mode_off, b->mode_rep, b->R, b->nmode_tot, b->spec, b->cprime, b->flags);
-    for (const BatchClass& k : b->classes) {
-        const int nxh = k.nx / 2 + 1;
-        const int mc = std::max(1, std::min(16, 2048 / k.ny));
-        dim3 gy((nxh + mc - 1) / mc, k.levels);
-        fft_y_kernel<<<gy, FFT_THREADS, (size_t)mc * k.ny * sizeof(double2), s>>>(
-            b->spec + k.spec_off, nxh, k.ny, ilog2(k.ny), mc, k.tw_y, 1);
-        const int ppb = std::max(1, 2048 / k.nx);
-        const int npairs = k.rows / 2;
-        fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * k.nx * sizeof(double2), s>>>(
-            b->spec + k.spec_off, b->phi + k.cell_off, k.nx, ilog2(k.nx), npairs, ppb, k.tw_x);
-    }
+    fft_y_cls_kernel<<<b->fft_yblocks, FFT_THREADS, b->fft_ylds, s>>>(b->fcls, ncls, b->spec, 1);
+    fft_x_c2r_cls_kernel<<<b->fft_xblocks, FFT_THREADS, b->fft_xlds, s>>>(b->fcls, ncls, b->spec, b->phi);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
