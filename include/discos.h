@@ -389,10 +389,14 @@ int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int3
                       uint64_t step, uint32_t flags, void* stream);
 
 /* Autotuner: times the spread tile (8^3 or 16^3) with its persistent block count, the
- * interpolation tile (8x8x8 or 16x16x8) with its block count, and the workgroup size of
- * the per-ion stages on the current ions, without advancing them, and keeps the fastest
- * of each.  cfg (host [5], nullable) receives spread tile, spread blocks (0 = one per
- * task), interpolation tile, interpolation blocks, per-ion workgroup size. */
+ * interpolation tile (8x8x8 or 16x16x8) with its block count, the channel densities below
+ * which the interpolation reads each ion's window directly instead of staging tiles and
+ * the spread adds each ion's window with global atomics (0, 8, 24, 64 ions per 2048
+ * cells, or every channel), and the workgroup size of the per-ion stages on the current
+ * ions, without advancing them, and keeps the fastest of each.  cfg (host [7], nullable)
+ * receives spread tile, spread blocks (0 = one per task), interpolation tile,
+ * interpolation blocks, per-ion workgroup size, and the two densities (interpolation,
+ * spread; 2^30: every channel). */
 int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const int32_t* id,
                       const int32_t* species, int32_t* cfg, void* stream);
 

@@ -71,6 +71,23 @@ int run_step(discos_batch* b, double* pos, double* q, int* id, int* sp, hipStrea
 
 extern "C" {
 
+// Flag the channels with fewer than thresh ions per 2048 cells for the one-thread-per-ion
+// interpolation (stage 0) or spread (stage 1); synchronous copy: at creation and while
+// tuning.
+static bool set_direct(discos_batch* b, int stage, int thresh) {
+    std::vector<int> f(b->ions_per_tile.size(), 0);
+    int nf = 0;
+    for (size_t r = 0; r < f.size(); ++r)
+        if (b->ions_per_tile[r] < thresh) {
+            f[r] = 1;
+            ++nf;
+        }
+    (stage == 0 ? b->n_direct : b->n_sdirect) = nf;
+    (stage == 0 ? b->cfg.interp_direct : b->cfg.spread_direct) = thresh;
+    return hipMemcpy(stage == 0 ? b->idirect : b->sdirect, f.data(), f.size() * sizeof(int),
+                     hipMemcpyHostToDevice) == hipSuccess;
+}
+
 int discos_batch_create(const discos_replica* reps, int32_t count, double h, const discos_params* p,
                         discos_batch** out) {
     if (!out) return DISCOS_E_ARG;
@@ -111,7 +128,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->p = *p;
     b->reps.assign(reps, reps + count);
     b->n_tot = n_tot;
-    b->cfg = {16, 0, 16, 0, 256};
+    b->cfg = {16, 0, 16, 0, 256, 1 << 30, 24};
     b->next_step = ~uint64_t(0);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -289,6 +306,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     bytes += carve_bytes(std::max<int64_t>(wall, 1), sizeof(double));
     bytes += carve_bytes(tw_all.size(), sizeof(double2));
     bytes += carve_bytes(b->classes.size(), sizeof(discos::FftClassDev));
+    bytes += 2 * carve_bytes(count, sizeof(int));  // idirect, sdirect
     if (hipMalloc(&b->pool, bytes) != hipSuccess) {
         destroy(b);
         return DISCOS_E_HIP;
@@ -342,6 +360,10 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         b->classes[c].tw_x = tw_d + tw_at[c].first;
         b->classes[c].tw_y = tw_d + tw_at[c].second;
     }
+    b->idirect = carve<int>(cur, count);
+    b->sdirect = carve<int>(cur, count);
+    for (int r = 0; r < count; ++r)
+        b->ions_per_tile.push_back(2048.0 * reps[r].n / ((double)reps[r].nx * reps[r].ny * reps[r].nz));
     // the batched FFT passes' class table (block ranges and LDS as the per-grid passes)
     b->fcls = carve<discos::FftClassDev>(cur, b->classes.size());
     std::vector<discos::FftClassDev> fcls;
@@ -394,6 +416,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     ok = ok && hipMemcpy(tw_d, tw_all.data(), tw_all.size() * sizeof(double2), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->fcls, fcls.data(), fcls.size() * sizeof(discos::FftClassDev),
                          hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && set_direct(b, 0, b->cfg.interp_direct) && set_direct(b, 1, b->cfg.spread_direct);
     for (int kind = 0; kind < 2; ++kind)
         for (int v = 0; v < 2; ++v)
             if (!tk[kind][v].empty())
@@ -520,6 +543,20 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         }
     b->cfg.spread_t = c.spread_t;
     b->cfg.spread_blocks = c.spread_blocks;
+    // spread: the density below which channels add their ions with global atomics
+    best = 1e30f;
+    for (int th : {0, 8, 24, 64, 1 << 30}) {
+        if (!set_direct(b, 1, th)) {
+            timing_ok = false;
+            break;
+        }
+        const float ms = timed([&] { discos::batch_spread(b, s); });
+        if (ms < best) {
+            best = ms;
+            c.spread_direct = th;
+        }
+    }
+    if (!set_direct(b, 1, c.spread_direct)) timing_ok = false;
     if (!rc) rc = discos::batch_spread(b, s);
     if (!rc) rc = discos::batch_poisson(b, s);
     // interpolation: tile shape x persistent blocks
@@ -537,6 +574,20 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         }
     b->cfg.interp_t = c.interp_t;
     b->cfg.interp_blocks = c.interp_blocks;
+    // interpolation: the density below which channels skip the staged tiles
+    best = 1e30f;
+    for (int th : {0, 8, 24, 64, 1 << 30}) {
+        if (!set_direct(b, 0, th)) {
+            timing_ok = false;
+            break;
+        }
+        const float ms = timed([&] { discos::batch_interp(b, s); });
+        if (ms < best) {
+            best = ms;
+            c.interp_direct = th;
+        }
+    }
+    if (!set_direct(b, 0, c.interp_direct)) timing_ok = false;
     // per-ion stages: workgroup size (the near-field pair of kernels)
     best = 1e30f;
     for (int wg : {64, 128, 256}) {
@@ -565,6 +616,8 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         cfg_out[2] = c.interp_t;
         cfg_out[3] = c.interp_blocks;
         cfg_out[4] = c.ion_block;
+        cfg_out[5] = c.interp_direct;
+        cfg_out[6] = c.spread_direct;
     }
     if (rc || !timing_ok || hipGetLastError() != hipSuccess)
         return fail(b, DISCOS_E_HIP, "tuning launch failed");

@@ -93,6 +93,32 @@ __device__ __forceinline__ void window_sums(const F& fetch, const double wcx[5],
 // find the tile's ions in the cell list; if there are any, stage phi with its halo and
 // ghost layers in LDS (tile holds (TX+5)(TY+5)(TZ+5) doubles) or, for a few ions, read
 // it directly, and interpolate every ion of the tile's cells.
+// The window sums of an ion in cell (cx, cy, cz) read straight from phi (no staged
+// tile): ghost rules only where the window reaches past a wall.
+__device__ __forceinline__ void direct_sums(const GridDev& g, const WallDev& w,
+                                            const double* __restrict__ phi, int cx, int cy, int cz,
+                                            const double wcx[5], const double dwx[5],
+                                            const double wcy[5], const double dwy[5],
+                                            const double wcz[5], const double dwz[5], double& Ex,
+                                            double& Ey, double& Ez, double& P) {
+    const int nx1 = g.nx - 1, ny1 = g.ny - 1;
+    if (cz >= 2 && cz + 2 < g.nz) {
+        // window cells cx-2 .. cx+2 (likewise y, z), all inside the channel
+        window_sums<1>(
+            [&](int kx, int ky, int kz) {
+                return phi[((size_t)(cz - 2 + kz) * g.ny + ((cy - 2 + ky) & ny1)) * g.nx +
+                           ((cx - 2 + kx) & nx1)];
+            },
+            wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+    } else {
+        window_sums<1>(
+            [&](int kx, int ky, int kz) {
+                return phi_at(phi, g, w, (cx - 2 + kx) & nx1, (cy - 2 + ky) & ny1, cz - 2 + kz);
+            },
+            wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+    }
+}
+
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, int op,
                                             const double4* __restrict__ sxyzq,
@@ -199,22 +225,8 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
             const double* base = &tile[(lz0 * LY + ly0) * LX + lx0];
             window_sums<5>([&](int kx, int ky, int kz) { return base[(kz * LY + ky) * LX + kx]; },
                         wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
-        } else if (cz >= 2 && cz + 2 < g.nz) {
-            // window cells cx-2 .. cx+2 (likewise y, z), all inside the channel
-            const int nx1 = g.nx - 1, ny1 = g.ny - 1;
-            window_sums<1>(
-                [&](int kx, int ky, int kz) {
-                    return phi[((size_t)(cz - 2 + kz) * g.ny + ((cy - 2 + ky) & ny1)) * g.nx +
-                               ((cx - 2 + kx) & nx1)];
-                },
-                wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
         } else {
-            const int nx1 = g.nx - 1, ny1 = g.ny - 1;
-            window_sums<1>(
-                [&](int kx, int ky, int kz) {
-                    return phi_at(phi, g, w, (cx - 2 + kx) & nx1, (cy - 2 + ky) & ny1, cz - 2 + kz);
-                },
-                wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+            direct_sums(g, w, phi, cx, cy, cz, wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
         }
         if (op == DISCOS_INTERP_PHI) {
             out[o] = P;
@@ -258,11 +270,13 @@ interp_es_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__
                        int ntasks, const double4* __restrict__ sxyzq,
                        const int* __restrict__ bin_start, const int* __restrict__ perm,
                        const double* __restrict__ phi, double ex0, double ex1, double ex2,
-                       double* __restrict__ out, int64_t stride, int* __restrict__ flags) {
+                       double* __restrict__ out, int64_t stride, const int* __restrict__ idirect,
+                       int* __restrict__ flags) {
     __shared__ double tile[(TZ + IT_H) * (TY + IT_H) * (TX + IT_H)];
     __shared__ int rstart[IT_MAXR], rpre[IT_MAXR + 1], scan[IT_THREADS];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const int2 task = tasks[t];
+        if (idirect[task.x]) continue;  // interpolated one thread per ion
         const RepDev& R = reps[task.x];
         const GridDev g = R.g;
         const int tx = min(TX, g.nx), ty = min(TY, g.ny);
@@ -274,6 +288,38 @@ interp_es_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__
                                 tile, rstart, rpre, scan);
         __syncthreads();
     }
+}
+
+// Batched, the channels flagged in idirect (few ions per tile, where staging a tile
+// would serve a handful of ions): one thread per ion, its window read from phi.
+__global__ void __launch_bounds__(256)
+interp_es_direct_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                              const int* __restrict__ idirect, int n, const double4* __restrict__ sxyzq,
+                              const double* __restrict__ phi, double ex0, double ex1, double ex2,
+                              double* __restrict__ out, int64_t stride, int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = ion_rep[i];
+    if (!idirect[r]) return;
+    const RepDev& R = reps[r];
+    const GridDev& g = R.g;
+    const double4 a4 = sxyzq[i];
+    if (!pos_ok(g, a4.x, a4.y, a4.z)) {
+        set_flag(flags, (isfinite(a4.x) && isfinite(a4.y) && isfinite(a4.z)) ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                                                          : DISCOS_FLAG_NONFINITE);
+        out[i] = out[i + stride] = out[i + 2 * stride] = 0.0;
+        return;
+    }
+    double wcx[5], dwx[5], wcy[5], dwy[5], wcz[5], dwz[5];
+    const int cx = window_weights(a4.x * g.inv_h, wcx, dwx);
+    const int cy = window_weights(a4.y * g.inv_h, wcy, dwy);
+    const int cz = window_weights(a4.z * g.inv_h, wcz, dwz);
+    double Ex, Ey, Ez, P;
+    direct_sums(g, R.w, phi + R.cell_off, cx, cy, cz, wcx, dwx, wcy, dwy, wcz, dwz, Ex, Ey, Ez, P);
+    const double qi = a4.w;
+    out[i] = qi * (-g.inv_h * Ex + ex0);
+    out[i + stride] = qi * (-g.inv_h * Ey + ex1);
+    out[i + 2 * stride] = qi * (-g.inv_h * Ez + ex2);
 }
 
 int interp_es_sorted(Ctx* c, int op, int n, const double* phi, const discos_params* p,
@@ -294,14 +340,20 @@ int batch_interp(Batch* b, hipStream_t s) {
     if (nt == 0) return DISCOS_OK;
     const int nb = b->cfg.interp_blocks > 0 ? std::min(nt, b->cfg.interp_blocks) : nt;
     const double* e = b->p.e_ext;
-    if (v == 0)
+    if (b->n_direct == (int)b->reps.size()) {
+        // every channel one thread per ion: no tiles
+    } else if (v == 0)
         interp_es_batch_kernel<8, 8, 8><<<nb, IT_THREADS, 0, s>>>(
             b->reps_d, b->tasks[1][0], nt, b->sxyzq, b->bin_start, b->perm, b->phi, e[0], e[1], e[2],
-            b->fp, b->n_tot, b->flags);
+            b->fp, b->n_tot, b->idirect, b->flags);
     else
         interp_es_batch_kernel<IT_TX, IT_TY, IT_TZ><<<nb, IT_THREADS, 0, s>>>(
             b->reps_d, b->tasks[1][1], nt, b->sxyzq, b->bin_start, b->perm, b->phi, e[0], e[1], e[2],
-            b->fp, b->n_tot, b->flags);
+            b->fp, b->n_tot, b->idirect, b->flags);
+    if (b->n_direct > 0)
+        interp_es_direct_batch_kernel<<<(int)((b->n_tot + 255) / 256), 256, 0, s>>>(
+            b->reps_d, b->ion_rep, b->idirect, (int)b->n_tot, b->sxyzq, b->phi, e[0], e[1], e[2], b->fp,
+            b->n_tot, b->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

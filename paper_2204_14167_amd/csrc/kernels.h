@@ -121,6 +121,9 @@ struct BatchCfg {   // launch choices (the autotuner's output)
     int interp_t;       // interpolation tile: 16 -> 16x16x8, 8 -> 8x8x8
     int interp_blocks;  // persistent blocks of the interpolation (0: one per task)
     int ion_block;      // workgroup size of the per-ion kernels
+    int interp_direct;  // channels with fewer ions per 2048 cells are interpolated one
+                        // thread per ion instead of by staged tiles
+    int spread_direct;  // likewise spread one thread per ion with global atomics
 };
 
 struct Batch {
@@ -145,6 +148,11 @@ struct Batch {
     bool z_legacy = false;         // some channel has nz > 128 (per-mode Thomas, scratch cprime)
     bool z_singular = false;       // both walls Neumann
     std::vector<BatchClass> classes;
+    int* idirect;                 // [channels] 1: interpolated one thread per ion
+    int n_direct;                 // channels so flagged
+    int* sdirect;                 // [channels] 1: spread one thread per ion
+    int n_sdirect;
+    std::vector<double> ions_per_tile;  // per channel: ions per 2048 cells
     FftClassDev* fcls;            // [classes] for the batched FFT passes
     int fft_xblocks, fft_yblocks; // blocks of the x passes and of the y pass
     size_t fft_xlds, fft_ylds;    // their dynamic LDS

@@ -37,15 +37,19 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
                                             double sign_hi, int add_bc, const WallDev& wall,
                                             double* __restrict__ out, int x0, int y0, int z0,
                                             double* acc, int* rstart, int* rpre, int* scan,
-                                            int* __restrict__ flags) {
+                                            int* __restrict__ flags, bool gather = true) {
     static_assert(tile_rows_bound(T, T, 2, 2) <= SP_MAXR, "spread tile rows exceed SP_MAXR");
     const int tx = min(T, g.nx), ty = min(T, g.ny);
     const int tz = min(T, g.nz - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
-    const int nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan,
-                                              flags);
-    const int total = rpre[nr];
+    int nr = 1, total = 0;
+    if (gather) {  // else the tile stores its wall terms only (ions added by the caller)
+        nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan, flags);
+        total = rpre[nr];
+    } else {
+        __syncthreads();  // acc cleared
+    }
     const double inv_h3 = g.inv_h * g.inv_h * g.inv_h;
     // the next ion's record is loaded before the current one's LDS atomics
     double4 nxt = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -153,7 +157,7 @@ __global__ void __launch_bounds__(SP_THREADS)
 spread_charge_batch_kernel(const RepDev* __restrict__ reps, const int2* __restrict__ tasks,
                            int ntasks, const double4* __restrict__ sxyzq,
                            const int* __restrict__ bin_start, double* __restrict__ out,
-                           int* __restrict__ flags) {
+                           const int* __restrict__ sdirect, int* __restrict__ flags) {
     __shared__ double acc[T * T * T];
     __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -165,8 +169,51 @@ spread_charge_batch_kernel(const RepDev* __restrict__ reps, const int2* __restri
         const int k = task.y;
         spread_tile<T>(g, sxyzq, bin_start + R.bin_off, R.s_lo, R.s_hi, 1, R.w, out + R.cell_off,
                        (k % ntx) * tx, ((k / ntx) % nty) * ty, (k / (ntx * nty)) * T, acc, rstart,
-                       rpre, scan, flags);
+                       rpre, scan, flags, !sdirect[task.x]);
         __syncthreads();
+    }
+}
+
+// Batched, the channels flagged in sdirect (few ions per tile): after the tile pass has
+// stored their wall terms, one thread per ion adds its 4^3 window with global atomics.
+__global__ void __launch_bounds__(256)
+spread_charge_direct_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
+                                  const int* __restrict__ sdirect, int n,
+                                  const double4* __restrict__ sxyzq, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = ion_rep[i];
+    if (!sdirect[r]) return;
+    const RepDev& R = reps[r];
+    const GridDev& g = R.g;
+    const double4 a4 = sxyzq[i];
+    if (!pos_ok(g, a4.x, a4.y, a4.z)) return;  // flagged by the interpolation
+    int ix0, iy0, iz0;
+    double wx[4], wy[4], wz[4];
+    peskin4(a4.x * g.inv_h - 0.5, ix0, wx);
+    peskin4(a4.y * g.inv_h - 0.5, iy0, wy);
+    peskin4(a4.z * g.inv_h - 0.5, iz0, wz);
+    const double scale = a4.w * g.inv_h * g.inv_h * g.inv_h;
+    double* o = out + R.cell_off;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int kz = iz0 + c;
+        double sgn = 1.0;
+        if (kz < 0) {
+            kz = -1 - kz;
+            sgn = R.s_lo;
+        } else if (kz >= g.nz) {
+            kz = 2 * g.nz - 1 - kz;
+            sgn = R.s_hi;
+        }
+        const double wzc = scale * sgn * wz[c];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const double wyz = wzc * wy[b];
+            double* row = o + ((size_t)kz * g.ny + ((iy0 + b) & (g.ny - 1))) * g.nx;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) atomicAdd(&row[(ix0 + a) & (g.nx - 1)], wyz * wx[a]);
+        }
     }
 }
 
@@ -190,11 +237,14 @@ int batch_spread(Batch* b, hipStream_t s) {
     if (v == 0)
         spread_charge_batch_kernel<8><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][0], nt,
                                                                b->sxyzq, b->bin_start, b->rho,
-                                                               b->flags);
+                                                               b->sdirect, b->flags);
     else
         spread_charge_batch_kernel<16><<<nb, SP_THREADS, 0, s>>>(b->reps_d, b->tasks[0][1], nt,
                                                                 b->sxyzq, b->bin_start, b->rho,
-                                                               b->flags);
+                                                                b->sdirect, b->flags);
+    if (b->n_sdirect > 0)
+        spread_charge_direct_batch_kernel<<<(int)((b->n_tot + 255) / 256), 256, 0, s>>>(
+            b->reps_d, b->ion_rep, b->sdirect, (int)b->n_tot, b->sxyzq, b->rho);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 

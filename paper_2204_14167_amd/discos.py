@@ -505,11 +505,12 @@ class Batch:
                                          int(step), BATCH_GRAPH if graph else 0, _stream()))
 
     def tune(self, pos, q, ids, species):
-        cfg = (ctypes.c_int32 * 5)()
+        cfg = (ctypes.c_int32 * 7)()
         self._rc(lib().discos_batch_tune(self.handle, _ptr(pos), _ptr(q), _ptr(ids), _ptr(species),
                                          cfg, _stream()))
         return dict(spread_tile=cfg[0], spread_blocks=cfg[1], interp_tile=cfg[2],
-                    interp_blocks=cfg[3], ion_block=cfg[4])
+                    interp_blocks=cfg[3], ion_block=cfg[4], interp_direct=cfg[5],
+                    spread_direct=cfg[6])
 
     def check(self):
         self._rc(lib().discos_batch_check(self.handle))

@@ -132,6 +132,8 @@ def test_tuning_keeps_results():
     log(f"tuned: {cfg}")
     assert cfg["spread_tile"] in (8, 16) and cfg["interp_tile"] in (8, 16)
     assert cfg["ion_block"] in (64, 128, 256)
+    assert cfg["interp_direct"] in (0, 8, 24, 64, 1 << 30)
+    assert cfg["spread_direct"] in (0, 8, 24, 64, 1 << 30)
     # tuning does not move the ions
     assert np.array_equal(host(arrays[0]), before[0])
     b.step(*arrays, step=1, graph=True)
