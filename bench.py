@@ -331,12 +331,18 @@ def batch_timing(steps, seq_steps=3, one_by_one=True):
     b.step(*arr, step=0, graph=True)
     b.step(*arr, step=1)
     torch.cuda.synchronize()
+    # GPU time per step (events) and the host's time to issue a step (the graph replaces
+    # the step's launches by one graph launch; the GPU runs the same kernels either way)
     ev[0].record()
+    h0 = time.perf_counter()
     for k in range(steps):
         b.step(*arr, step=2 + k, graph=True)
+    h1 = time.perf_counter()
     ev[1].record()
+    h2 = time.perf_counter()
     for k in range(steps):
         b.step(*arr, step=2 + steps + k)
+    h3 = time.perf_counter()
     ev[2].record()
     torch.cuda.synchronize()
     b.check()
@@ -346,6 +352,8 @@ def batch_timing(steps, seq_steps=3, one_by_one=True):
     out = {"channels": len(reps), "ions": int(n),
            "cells": int(sum(r["nx"] * r["ny"] * r["nz"] for r in reps)),
            "graph_ms_per_step": t_graph, "eager_ms_per_step": t_eager,
+           "host_us_per_step_graph": 1e6 * (h1 - h0) / steps,
+           "host_us_per_step_eager": 1e6 * (h3 - h2) / steps,
            "ion_timesteps_per_s_graph": n / (t_graph * 1e-3), "tuned": cfg}
     if not one_by_one:
         return out

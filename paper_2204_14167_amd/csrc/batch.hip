@@ -49,8 +49,6 @@ bool destroy(discos_batch* b) {
     bool ok = true;
     if (b->exec) ok = (hipGraphExecDestroy(b->exec) == hipSuccess) && ok;
     if (b->graph) ok = (hipGraphDestroy(b->graph) == hipSuccess) && ok;
-    if (b->ev_in) ok = (hipEventDestroy(b->ev_in) == hipSuccess) && ok;
-    if (b->ev_out) ok = (hipEventDestroy(b->ev_out) == hipSuccess) && ok;
     if (b->own) ok = (hipStreamDestroy(b->own) == hipSuccess) && ok;
     if (b->pool) ok = (hipFree(b->pool) == hipSuccess) && ok;
     delete b;
@@ -431,8 +429,6 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     // bin counts start at zero; the scan that reads them clears them again
     ok = ok && hipMemset(b->bin_count, 0, b->nbins_tot * sizeof(int)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         destroy(b);
         return DISCOS_E_HIP;
@@ -489,15 +485,12 @@ int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int3
         for (int k = 0; k < 4; ++k) b->graph_args[k] = args[k];
         b->next_step = ~uint64_t(0);
     }
-    // order the replay after the caller's stream, and the caller's stream after it
-    if (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(b->own, b->ev_in, 0) != hipSuccess)
-        return fail(b, DISCOS_E_HIP, "stream ordering failed");
-    if (step != b->next_step && discos::batch_set_step(b, step, b->own))
+    // the graph was captured on the batch's own stream; it replays on the caller's, in
+    // order with the caller's other work and without cross-stream events
+    if (step != b->next_step && discos::batch_set_step(b, step, s))
         return fail(b, DISCOS_E_HIP, "step counter update failed");
-    if (hipGraphLaunch(b->exec, b->own) != hipSuccess) return fail(b, DISCOS_E_HIP, "graph launch failed");
+    if (hipGraphLaunch(b->exec, s) != hipSuccess) return fail(b, DISCOS_E_HIP, "graph launch failed");
     b->next_step = step + 1;
-    if (hipEventRecord(b->ev_out, b->own) != hipSuccess || hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess)
-        return fail(b, DISCOS_E_HIP, "stream ordering failed");
     return DISCOS_OK;
 }
 

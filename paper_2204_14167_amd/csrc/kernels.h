@@ -169,8 +169,7 @@ struct Batch {
     void* pool;
     BatchCfg cfg;
     int ncu;
-    hipStream_t own;               // stream of the captured graph
-    hipEvent_t ev_in, ev_out;
+    hipStream_t own;               // stream the graph is captured on (it replays on the caller's)
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void* graph_args[4];
