@@ -15,6 +15,7 @@ per species.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                 [--adjoint-steps A] [--batch-steps B] [--wet-steps S] [--c2-steps S2]
+                [--mixed-steps S3]
                 [--copy-calibration]
 Prints one JSON line.
 """
@@ -230,6 +231,54 @@ def c2_timing(steps, warmup=3):
             "ion_timesteps_per_s": w.n * steps / el, "device_status": status}
 
 
+def mixed_timing(steps, warmup=2):
+    """Walls of mixed type at the size of the 65,536-ion channel: 128 x 128 x 64, the lower
+    wall dielectric with a metal strip at 1 kT/e over the middle third of x (the ICEO
+    geometry of Sec. IV.B), the upper wall dielectric, E_x = 0.1.  Dry steps (the Poisson
+    solve by preconditioned conjugate gradients) and, from steps with stage events, the
+    Poisson solve's time."""
+    import torch
+    from paper_2204_14167_amd import discos
+    import workloads
+    w0 = workloads.WORKLOADS["dielectric_128x128x64_n65536"]
+    w = workloads.Workload("iceo_128x128x64_n65536", w0.nx, w0.ny, w0.nz, w0.n, (1, 1), (0.0, 0.0),
+                           e_ext=(0.1, 0.0, 0.0), seed=w0.seed)
+    p = workloads.make_params(w)
+    strip = np.ones((w.ny, w.nx), dtype=np.int32)  # Neumann (dielectric) columns
+    strip[:, w.nx // 3:2 * w.nx // 3] = 0           # Dirichlet (metal) columns
+    p["bc_types"] = (strip, 1)
+    p["bc_values"] = (np.where(strip == 0, 1.0, 0.0), np.zeros((w.ny, w.nx)))
+    pos, q, ids, species = workloads.make_ions(w)
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n)
+    dp = ctx.params(gpu_params(p))
+    a = [torch.from_numpy(x.copy()).cuda() for x in (pos, q, ids, species)]
+    for s in range(warmup):
+        ctx.step(*a, dp, s)
+    ctx.profile(True)
+    for s in range(steps):
+        ctx.step(*a, dp, warmup + s)
+    st = ctx.profile_read()
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ctx.step(*a, dp, warmup + steps + s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    status = "ok"
+    try:
+        ctx.check()
+    except discos.DiscosError as e:
+        status = str(e)
+    poisson = sum(st.get(k, 0.0) for k in ("fft_x", "fft_y", "z_solve", "ifft_y", "ifft_x"))
+    return {"workload": w.name, "n_ions": w.n, "grid": [w.nx, w.ny, w.nz],
+            "walls": "lower: dielectric with a metal strip at 1 kT/e over the middle third of x; "
+                     "upper: dielectric",
+            "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "ion_timesteps_per_s": w.n * steps / el, "poisson_ms": poisson,
+            "device_status": status}
+
+
 def adjoint_timing(ctx, dp, dpos, dq, steps):
     """Mean times of the energy / flux forward pass and of its backward pass (all
     gradients: positions, charges, both wall fields, applied field) on the same
@@ -426,6 +475,8 @@ def main():
                     help="wet steps of the 262,144-ion hydrodynamic channel per kernel (0: skip)")
     ap.add_argument("--c2-steps", type=int, default=100,
                     help="timed steps of the 65,536-ion dielectric channel (0: skip)")
+    ap.add_argument("--mixed-steps", type=int, default=10,
+                    help="dry steps of the 65,536-ion channel with a metal strip on one wall (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -487,6 +538,7 @@ def main():
     batched = batch_timing(args.batch_steps, one_by_one=not args.no_one_by_one) if args.batch_steps > 0 else None
     wet = wet_timing(args.wet_steps) if args.wet_steps > 0 else None
     c2 = c2_timing(args.c2_steps) if args.c2_steps > 0 else None
+    mixed = mixed_timing(args.mixed_steps) if args.mixed_steps > 0 else None
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -563,6 +615,7 @@ def main():
         "batched": batched,
         "wet": wet,
         "dielectric_128x128x64": c2,
+        "mixed_walls": mixed,
         "cpu_baseline": cpu,
         "device_status": "; ".join(status) if status else "ok",
     }

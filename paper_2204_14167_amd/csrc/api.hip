@@ -359,6 +359,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->ef_gen = ~(uint64_t)0;  // no forward list yet
     c->ef_n = -1;
     c->ef_wq = 0.0;
+    c->phi_warm = 0;
+    c->mx_iters = 0;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;
     c->last_stream = nullptr;

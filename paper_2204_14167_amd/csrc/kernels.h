@@ -52,6 +52,8 @@ struct Ctx {
     double* pcg;
     double* pcg_s;
     int wm_mixed;
+    int phi_warm;  // phi holds a solved potential (the mixed-wall iteration may start there)
+    int mx_iters;  // iterations of the last mixed-wall solve
     int wm_ref[2];
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
     int hydro;

@@ -13,6 +13,7 @@
 //
 // Reductions use a fixed grid and a fixed order (deterministic), and the scalars of the
 // iteration stay on the device; the host reads the residual every few iterations.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -172,10 +173,13 @@ int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const
     auto finish = [&](int slot, int roll) {
         mx_finish_kernel<<<1, MX_THREADS, 0, s>>>(part, nb, S, slot, roll);
     };
-    // r = b (b may share storage with phi), x = M b, r = b - A x, z = M r, p = z
+    // r = b (b may share storage with phi), x = M b, r = b - A x, z = M r, p = z.  In a
+    // step, phi holds the previous step's potential (c->phi_warm): x starts from it, which
+    // changes only the iteration count (the result is the solve to the same residual)
+    const bool warm = phi == c->phi && rhs != phi && c->phi_warm;
     mx_copy_kernel<<<nb, MX_THREADS, 0, s>>>(n, rhs, r, part);
     finish(S_BB, 0);
-    int rc = solve_poisson(c, r, &pu, phi, s);
+    int rc = warm ? DISCOS_OK : solve_poisson(c, r, &pu, phi, s);
     if (rc) return rc;
     mx_residual_kernel<<<nb, MX_THREADS, 0, s>>>(g, w, cst, n, phi, r, part);
     finish(S_RR, 0);
@@ -184,19 +188,25 @@ int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const
     mx_dot_kernel<<<nb, MX_THREADS, 0, s>>>(n, r, zq, part);
     finish(S_RZN, 0);
     mx_direction_kernel<<<nb, MX_THREADS, 0, s>>>(n, S, 1, zq, pd);
+    // the host reads the residual every MX_CHECK iterations, from a few iterations short
+    // of the last solve's count on (each read waits for the stream)
+    const int first_check = std::max(MX_CHECK, (c->mx_iters - 2 * MX_CHECK) / MX_CHECK * MX_CHECK);
     for (int it = 1; it <= MX_MAX_ITER; ++it) {
         mx_apply_kernel<<<nb, MX_THREADS, 0, s>>>(g, w, cst, n, pd, zq, part);
         finish(S_PQ, 1);
         mx_step_kernel<<<nb, MX_THREADS, 0, s>>>(n, S, pd, zq, phi, r, part);
         finish(S_RR, 0);
         if (hipGetLastError() != hipSuccess) return DISCOS_E_HIP;
-        if (it % MX_CHECK == 0 || it == MX_MAX_ITER) {
+        if ((it >= first_check && it % MX_CHECK == 0) || it == MX_MAX_ITER) {
             double h[2];
             if (hipMemcpyAsync(h, S, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return DISCOS_E_HIP;
             if (!(std::isfinite(h[S_RR]) && std::isfinite(h[S_BB]))) return DISCOS_E_NONFINITE;
-            if (h[S_RR] <= MX_TOL * MX_TOL * h[S_BB]) return DISCOS_OK;
+            if (h[S_RR] <= MX_TOL * MX_TOL * h[S_BB]) {
+                c->mx_iters = it;
+                return DISCOS_OK;
+            }
             if (it == MX_MAX_ITER) return DISCOS_E_NOT_CONVERGED;
         }
         rc = solve_poisson(c, r, &pu, zq, s);

@@ -704,8 +704,10 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
         const int rc = solve_poisson_mixed(c, rhs, p, c->wm_ref, phi, s);
         if (mark_base >= 0)
             for (int k = 0; k < 5; ++k) stage_mark(c, mark_base + k, s);
+        if (phi == c->phi) c->phi_warm = rc == DISCOS_OK;
         return rc;
     }
+    if (phi == c->phi) c->phi_warm = 1;  // a finite potential from here on (launch order)
     const GridDev& g = c->gd;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;

@@ -166,6 +166,37 @@ def test_iceo_channel_dry_steps():
         assert r < TOL
 
 
+def test_iceo_channel_wet_step():
+    """The ICEO-shaped channel of the dry test, one wet midpoint step with the random
+    finite difference: the electrostatic forces with the strip enter the Stokes solve;
+    every ion against the oracle's wet step."""
+    from paper_2204_14167_amd import discos
+    nx, ny, nz, n = 64, 16, 16, 2048
+    t_lo = _strip(nx, ny)
+    w = workloads.Workload("iceo_64x16x16_n2048", nx, ny, nz, n, (N, N), (0.0, 0.0),
+                           e_ext=(0.1, 0.0, 0.0), seed=workloads.MASTER_SEED + 11)
+    p = workloads.make_params(w)
+    p["bc_types"] = (t_lo, N)
+    p["bc_values"] = (np.where(t_lo == D, 1.0, 0.0), np.zeros((ny, nx)))
+    p["rfd_delta"] = 1e-4
+    pos, q, ids, species = workloads.make_ions(w)
+    grid = es.Grid(nx, ny, nz)
+    ctx = discos.Context(nx, ny, nz, 1.0, n, hydro=True)
+    dp = ctx.params(p)
+    dpos, dq, dids, dsp = dev(pos), dev(q), dev(ids), dev(species)
+    log("iceo wet step: oracle")
+    ref, _, _ = dynamics.wet_step(grid, pos, q, species, ids, p, 0, rfd_delta=1e-4, near="pairs")
+    log("iceo wet step: GPU")
+    ctx.step(dpos, dq, dids, dsp, dp, 0, mode=discos.STEP_WET | discos.STEP_RFD)
+    ctx.check()
+    got = by_id(host(dpos), host(dids), ids)
+    err = min_image(got - ref, grid.L)
+    disp = min_image(ref - pos, grid.L)
+    r = np.linalg.norm(err) / np.linalg.norm(disp)
+    log(f"iceo wet step: rel {r:.3e}")
+    assert r < TOL
+
+
 def test_mixed_rejections():
     import torch
     from paper_2204_14167_amd import discos
