@@ -115,14 +115,16 @@ typedef struct discos_params {
                                    sign of folded kernel nodes, the wall term, the ghost
                                    values, and the image of a charge (the type of the column
                                    below / above the charge).  A wall whose columns differ
-                                   couples the Fourier modes: the Poisson solve is then
-                                   conjugate gradients preconditioned by the per-mode solve
-                                   of a uniform wall pair (Dirichlet for a wall with any
-                                   Dirichlet column), iterated to a residual below 1e-13 of
-                                   the right-hand side.  discos_solve_poisson and discos_step
-                                   copy the maps to the host (checking every entry) and
-                                   synchronise the stream, also to test convergence every few
-                                   iterations; the other calls read the maps on the device.
+                                   couples the Fourier modes: the Poisson solve is then two
+                                   per-mode solves of a uniform wall pair (Dirichlet for a
+                                   wall with any Dirichlet column) and, between them, a
+                                   capacitance system on the wall layers (Woodbury identity)
+                                   iterated by preconditioned conjugate gradients to a
+                                   residual below 1e-14 of its right-hand side.
+                                   discos_solve_poisson and discos_step copy the maps to the
+                                   host (checking every entry) and synchronise the stream,
+                                   also to test convergence every few iterations; the other
+                                   calls read the maps on the device.
                                    discos_energy_flux(_backward) and batches take uniform
                                    walls only (DISCOS_E_ARG). */
 } discos_params;

@@ -247,7 +247,9 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     bytes += carve_bytes(64, sizeof(int));
     bytes += carve_bytes(3 * PART_MAX, sizeof(double));                 // reduction partials
     bytes += carve_bytes(2 * (size_t)g.nx * g.ny, sizeof(double));     // wall adjoints
-    bytes += carve_bytes(3 * (size_t)c->ncell, sizeof(double)) + carve_bytes(8, sizeof(double));  // CG
+    const size_t ncap = 6 * (size_t)g.nxh * g.ny + 12 * (size_t)g.nx * g.ny;
+    bytes += carve_bytes(2 * (size_t)c->ncell, sizeof(double)) + carve_bytes(ncap, sizeof(double)) +
+             carve_bytes(8, sizeof(double));  // walls of mixed type
     // the near field's padded cell list, sized for search radii up to 3 bins
     const int64_t nl_bins = discos::near_list_bins(g, 3);
     const int64_t nl_cap = discos::near_list_entries(g, n_max);
@@ -280,7 +282,9 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->flags = carve<int>(cur, 64);
     c->part = carve<double>(cur, 3 * PART_MAX);
     c->bcg = carve<double>(cur, 2 * (size_t)g.nx * g.ny);
-    c->pcg = carve<double>(cur, 3 * (size_t)c->ncell);
+    c->pcg = carve<double>(cur, 2 * (size_t)c->ncell);
+    c->cap = carve<double>(cur, ncap);
+    c->cap_key = -1;
     c->pcg_s = carve<double>(cur, 8);
     c->wm_mixed = 0;
     c->wm_ref[0] = c->wm_ref[1] = DISCOS_BC_DIRICHLET;
@@ -359,7 +363,6 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->ef_gen = ~(uint64_t)0;  // no forward list yet
     c->ef_n = -1;
     c->ef_wq = 0.0;
-    c->phi_warm = 0;
     c->mx_iters = 0;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;

@@ -47,12 +47,17 @@ struct Ctx {
     double* fp;      // [3][n_max] per-ion forces in cell-list order
     double2 *tw_x, *tw_y;
     NearList nl;     // the near-field pass's padded copy of the cell list
-    // conjugate gradients of walls of mixed type: r, p and z / A p, [3][ncell], and the
+    // walls of mixed type (a capacitance solve on the wall layers): pcg, [2][ncell], the
+    // right-hand side and solution of the second uniform-wall solve; cap, the per-mode
+    // wall Green's function and preconditioner ([3][ny][nx/2+1] each, for the reference
+    // pair cap_key) and six vectors on the two wall planes ([2][ny][nx] each); pcg_s, the
     // iteration's scalars; wm_*: the wall maps of the current call (read on the host)
     double* pcg;
+    double* cap;
+    int cap_key;     // reference pair and walls with unknowns the tables hold (-1: none)
+    double cap_eps;  // and the permittivity they were scaled with
     double* pcg_s;
     int wm_mixed;
-    int phi_warm;  // phi holds a solved potential (the mixed-wall iteration may start there)
     int mx_iters;  // iterations of the last mixed-wall solve
     int wm_ref[2];
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
@@ -211,10 +216,13 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
 int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi, hipStream_t s,
                   int mark_base = -1, int project = 0);
 
-// Poisson solve with walls of mixed type (conjugate gradients preconditioned by the
-// uniform pair ref); returns DISCOS_E_NOT_CONVERGED if the tolerance was not reached.
+// Poisson solve with walls of mixed type (the uniform pair ref, corrected on the wall
+// layers by a capacitance system); returns DISCOS_E_NOT_CONVERGED if the tolerance was
+// not reached.
 int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const int ref[2],
                         double* phi, hipStream_t s);
+// out = F^-1 [C_k F in] on a pair of (x, y) planes with per-mode 2 x 2 maps coef.
+int plane_pair_filter(Ctx* c, const double* in, double* out, const double* coef, hipStream_t s);
 
 // E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi
 // (DISCOS_INTERP_PHI) for the ions of the cell list; out[perm[i]] if scatter, else out[i].

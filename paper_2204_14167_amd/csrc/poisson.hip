@@ -692,6 +692,38 @@ static void fft_y_launch(const Ctx* c, double2* spec, int nlev, int inv, hipStre
                    s>>>(spec, nxh, ny, ilog2(ny), ltpb, ncol, c->tw_y, inv);
 }
 
+// out = F^-1 [C_k F in] on a pair of (x, y) planes (in, out: [2][ny][nx]; spectra in
+// c->spec): per in-plane mode k the 2 x 2 symmetric map C_k = [[c0, c1], [c1, c2]]
+// (coef: [3][ny][nx/2 + 1]) couples the two planes' coefficients; out includes the
+// 1 / (nx ny) of the inverse transforms.
+__global__ void plane_pair_mode_kernel(int nmode, double2* __restrict__ spec,
+                                       const double* __restrict__ coef, double norm) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nmode) return;
+    const double c0 = coef[t] * norm, c1 = coef[nmode + t] * norm, c2 = coef[2 * nmode + t] * norm;
+    const double2 a = spec[t], b = spec[nmode + t];
+    spec[t] = make_double2(c0 * a.x + c1 * b.x, c0 * a.y + c1 * b.y);
+    spec[nmode + t] = make_double2(c1 * a.x + c2 * b.x, c1 * a.y + c2 * b.y);
+}
+
+int plane_pair_filter(Ctx* c, const double* in, double* out, const double* coef, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const int nx = g.nx, ny = g.ny, nxh = g.nxh;
+    const int npairs = ny;  // 2 ny rows
+    const int ppb = std::max(1, 1024 / nx);
+    const size_t ldsx = (size_t)ppb * nx * sizeof(double2);
+    fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(in, c->spec, nx, ilog2(nx),
+                                                                        npairs, ppb, c->tw_x);
+    fft_y_launch(c, c->spec, 2, 0, s);
+    const int nmode = nxh * ny;
+    plane_pair_mode_kernel<<<(nmode + 255) / 256, 256, 0, s>>>(nmode, c->spec, coef,
+                                                                1.0 / ((double)nx * ny));
+    fft_y_launch(c, c->spec, 2, 1, s);
+    fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(c->spec, out, nx, ilog2(nx),
+                                                                        npairs, ppb, c->tw_x);
+    return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
+}
+
 int fft_cols(Ctx* c, double2* spec, int nlev, int inv, hipStream_t s) {
     fft_y_launch(c, spec, nlev, inv, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
@@ -704,10 +736,8 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
         const int rc = solve_poisson_mixed(c, rhs, p, c->wm_ref, phi, s);
         if (mark_base >= 0)
             for (int k = 0; k < 5; ++k) stage_mark(c, mark_base + k, s);
-        if (phi == c->phi) c->phi_warm = rc == DISCOS_OK;
         return rc;
     }
-    if (phi == c->phi) c->phi_warm = 1;  // a finite potential from here on (launch order)
     const GridDev& g = c->gd;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;
