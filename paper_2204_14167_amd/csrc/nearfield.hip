@@ -435,7 +435,7 @@ __global__ void pad_scatter_batch_kernel(const RepDev* __restrict__ reps,
 // counts (a lane whose runs are exhausted idles), so a flush has every lane active.
 
 #ifndef NF_THREADS
-#define NF_THREADS 128  // two wavefronts per workgroup (they share the table)
+#define NF_THREADS 256  // four wavefronts per workgroup (they share the table)
 #endif
 #ifndef NF_HITS
 #define NF_HITS 16      // hit buffer entries per lane (a multiple of NF_GROUP)
@@ -526,10 +526,12 @@ __device__ __forceinline__ void slab_extent(const GridDev& g, int t, double& lo,
 }
 
 // Near-field, wall (and LJ) force of ion i of the cell list (x, y reduced into [0, L];
-// real bin (bx, by, bz); self: its own real entry in the padded list) into (fx, fy, fz).
+// real bin (bx, by, bz)) into (fx, fy, fz).  The ion's own entry among the candidates
+// is a copy of its coordinates, so it passes the FP32 filter and is dropped by the
+// exact test (zero separation), like any pair at zero separation.
 template <int R>
 __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int bx, int by, int bz,
-                                       int self, double4 me, int spi, const NlView& L,
+                                       double4 me, int spi, const NlView& L,
                                        const int* __restrict__ pstart, NfShared<R>& sh,
                                        double& fx, double& fy, double& fz) {
     const int lane = threadIdx.x;
@@ -616,7 +618,7 @@ __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int b
             const float dx = xf - o.x, dy = yf - o.y, dz = zf - o.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             // a zero FP32 distance may be a distinct (coincident in FP32) pair
-            const bool hit = act && r2 < cutf && j != self;
+            const bool hit = act && r2 < cutf;
             hcol[cnt * NF_THREADS] = j;
             cnt += hit ? 1 : 0;
             j = jn;
@@ -682,7 +684,7 @@ __global__ void __launch_bounds__(NF_THREADS, NF_MINW)
 near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
                   const int* __restrict__ pbin_off, NearDev P, int n,
                   const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
-                  const int* __restrict__ bin_start0, NlView L, const int* __restrict__ perm,
+                  NlView L, const int* __restrict__ perm,
                   double* __restrict__ out, int64_t stride, int scatter, int* __restrict__ flags,
                   FusedUpdate U) {
     __shared__ NfShared<R> sh;
@@ -696,13 +698,10 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
                   (int)threadIdx.x;
     if (i >= n) return;
     GridDev g = g0;
-    const int* bin_start = bin_start0;
     const int* pstart = L.start;
     if (BATCH) {
         const int r = ion_rep[i];
-        const RepDev& Rp = reps[r];
-        g = Rp.g;
-        bin_start += Rp.bin_off;
+        g = reps[r].g;
         pstart += pbin_off[r];
     }
     const double4 me = sxyzq[i];
@@ -719,11 +718,8 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
     }
     int bx, by, bz;
     sorted_bin(g, me.x, me.y, me.z, bx, by, bz);
-    const int PX = g.nbx + 2 * R, PY = g.nby + 2 * R;
-    const int self = pstart[((bz + R) * PY + by + R) * PX + bx + R] +
-                     (i - bin_start[(bz * g.nby + by) * g.nbx + bx]);
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    nf_ion<R>(g, P, bx, by, bz, self, me, spi, L, pstart, sh, Fx, Fy, Fz);
+    nf_ion<R>(g, P, bx, by, bz, me, spi, L, pstart, sh, Fx, Fy, Fz);
     if (BATCH) {
         out[i] += Fx;
         out[i + stride] += Fy;
@@ -744,7 +740,7 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
 // The pass for search radii of 1 to 3 bins (larger radii are rejected up front).
 static int launch_near(const NearDev& P, int n, hipStream_t s, const GridDev& g,
                        const RepDev* reps, const int* ion_rep, const int* pbin_off,
-                       const double4* sxyzq, const int* ssp, const int* bin_start, const NlView& L,
+                       const double4* sxyzq, const int* ssp, const NlView& L,
                        const int* perm, double* out, int64_t stride, int scatter, int* flags,
                        const FusedUpdate& U) {
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
@@ -752,11 +748,11 @@ static int launch_near(const NearDev& P, int n, hipStream_t s, const GridDev& g,
 #define NF_LAUNCH(RR)                                                                         \
     if (reps)                                                                                 \
         near_field_kernel<RR, true><<<nb, NF_THREADS, 0, s>>>(g, reps, ion_rep, pbin_off, P, n, \
-                                                              sxyzq, ssp, bin_start, L, perm,  \
+                                                              sxyzq, ssp, L, perm,  \
                                                               out, stride, scatter, flags, U); \
     else                                                                                      \
         near_field_kernel<RR, false><<<nb, NF_THREADS, 0, s>>>(g, reps, ion_rep, pbin_off, P, n, \
-                                                               sxyzq, ssp, bin_start, L, perm, \
+                                                               sxyzq, ssp, L, perm, \
                                                                out, stride, scatter, flags, U);
     if (P.R == 1) {
         NF_LAUNCH(1)
@@ -816,7 +812,7 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
         U.sp = upd->sp;
     }
     const NlView L{c->nl.start, c->nl.xyzq, c->nl.xyzf, c->nl.sp};
-    rc = launch_near(P, n, s, c->gd, nullptr, nullptr, nullptr, c->sxyzq, c->ssp, c->bin_start, L,
+    rc = launch_near(P, n, s, c->gd, nullptr, nullptr, nullptr, c->sxyzq, c->ssp, L,
                      c->perm, out, out_stride, scatter_to_caller, c->flags, U);
     if (mark >= 0) stage_mark(c, mark + 1, s);
     return rc;
@@ -872,8 +868,8 @@ int batch_near(Batch* b, hipStream_t s) {
                                                          b->pbin_off, b->nl.start, o);
     const NlView L{b->nl.start, b->nl.xyzq, b->nl.xyzf, b->nl.sp};
     GridDev g{};
-    return launch_near(P, n, s, g, b->reps_d, b->ion_rep, b->pbin_off, b->sxyzq, b->ssp, b->bin_start,
-                       L, nullptr, b->fp, n, 0, b->flags, FusedUpdate{});
+    return launch_near(P, n, s, g, b->reps_d, b->ion_rep, b->pbin_off, b->sxyzq, b->ssp, L,
+                       nullptr, b->fp, n, 0, b->flags, FusedUpdate{});
 }
 
 int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s) {

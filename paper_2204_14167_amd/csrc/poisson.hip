@@ -663,23 +663,40 @@ static int ilog2(int n) {
     return l;
 }
 
+// Launch shape of the x passes over npairs row pairs: 512 elements (512 / nx pairs) per
+// block, four per thread.  (The y pass takes 1024 per block: its blocks read spectrum
+// rows column-wise, and wider blocks read longer runs of each row.)
+#define FFT_X_POINTS 512
+struct XLaunch {
+    int ppb, threads, blocks;
+    size_t lds;
+};
+static XLaunch x_launch(int nx, int npairs) {
+    XLaunch L;
+    L.ppb = std::max(1, FFT_X_POINTS / nx);
+    L.threads = std::min(FFT_THREADS, std::max(64, L.ppb * nx / 4));
+    L.blocks = (npairs + L.ppb - 1) / L.ppb;
+    L.lds = (size_t)L.ppb * nx * sizeof(double2);
+    return L;
+}
+
 // Real FFT along x of nrows rows (nrows even) into half spectra, and its inverse;
 // complex FFT along y of nlev levels of half spectra.
 int fft_rows_r2c(Ctx* c, const double* in, double2* spec, int nrows, hipStream_t s) {
     const int nx = c->gd.nx;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 1024 / nx);
-    fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
-        in, spec, nx, ilog2(nx), npairs, ppb, c->tw_x);
+    const XLaunch X = x_launch(nx, npairs);
+    fft_x_r2c_kernel<<<X.blocks, X.threads, X.lds, s>>>(in, spec, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
 int fft_rows_c2r(Ctx* c, const double2* spec, double* out, int nrows, hipStream_t s) {
     const int nx = c->gd.nx;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 1024 / nx);
-    fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, (size_t)ppb * nx * sizeof(double2), s>>>(
-        spec, out, nx, ilog2(nx), npairs, ppb, c->tw_x);
+    const XLaunch X = x_launch(nx, npairs);
+    fft_x_c2r_kernel<<<X.blocks, X.threads, X.lds, s>>>(spec, out, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -710,17 +727,16 @@ int plane_pair_filter(Ctx* c, const double* in, double* out, const double* coef,
     const GridDev& g = c->gd;
     const int nx = g.nx, ny = g.ny, nxh = g.nxh;
     const int npairs = ny;  // 2 ny rows
-    const int ppb = std::max(1, 1024 / nx);
-    const size_t ldsx = (size_t)ppb * nx * sizeof(double2);
-    fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(in, c->spec, nx, ilog2(nx),
-                                                                        npairs, ppb, c->tw_x);
+    const XLaunch X = x_launch(nx, npairs);
+    fft_x_r2c_kernel<<<X.blocks, X.threads, X.lds, s>>>(in, c->spec, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     fft_y_launch(c, c->spec, 2, 0, s);
     const int nmode = nxh * ny;
     plane_pair_mode_kernel<<<(nmode + 255) / 256, 256, 0, s>>>(nmode, c->spec, coef,
                                                                 1.0 / ((double)nx * ny));
     fft_y_launch(c, c->spec, 2, 1, s);
-    fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(c->spec, out, nx, ilog2(nx),
-                                                                        npairs, ppb, c->tw_x);
+    fft_x_c2r_kernel<<<X.blocks, X.threads, X.lds, s>>>(c->spec, out, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
@@ -742,10 +758,9 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxh = g.nxh;
     const int nrows = ny * nz;
     const int npairs = nrows / 2;
-    const int ppb = std::max(1, 1024 / nx);
-    const size_t ldsx = (size_t)ppb * nx * sizeof(double2);
-    fft_x_r2c_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(rhs, c->spec, nx, ilog2(nx),
-                                                                        npairs, ppb, c->tw_x);
+    const XLaunch X = x_launch(nx, npairs);
+    fft_x_r2c_kernel<<<X.blocks, X.threads, X.lds, s>>>(rhs, c->spec, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     if (mark_base >= 0) stage_mark(c, mark_base, s);
     fft_y_launch(c, c->spec, nz, 0, s);
     if (mark_base >= 0) stage_mark(c, mark_base + 1, s);
@@ -781,8 +796,8 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
     if (mark_base >= 0) stage_mark(c, mark_base + 2, s);
     fft_y_launch(c, c->spec, nz, 1, s);
     if (mark_base >= 0) stage_mark(c, mark_base + 3, s);
-    fft_x_c2r_kernel<<<(npairs + ppb - 1) / ppb, FFT_THREADS, ldsx, s>>>(c->spec, phi, nx, ilog2(nx),
-                                                                        npairs, ppb, c->tw_x);
+    fft_x_c2r_kernel<<<X.blocks, X.threads, X.lds, s>>>(c->spec, phi, nx, ilog2(nx), npairs, X.ppb,
+                                                        c->tw_x);
     if (mark_base >= 0) stage_mark(c, mark_base + 4, s);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
