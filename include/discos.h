@@ -152,6 +152,15 @@ typedef struct discos_ctx discos_ctx;
  * Errors: DISCOS_E_ARG, DISCOS_E_SHAPE, DISCOS_E_HIP.
  */
 #define DISCOS_CREATE_HYDRO 1u /* also allocate the Stokes / wet-step scratch */
+/* Walls of mixed type (discos_params.bc_type_map) are solved through a capacitance
+ * system on the wall layers.  By default, when it has at most DISCOS_MIXED_DENSE_MAX
+ * unknowns, the system's inverse is formed once per set of maps (a dense Cholesky
+ * factorisation; the one exception to "later calls allocate nothing": up to
+ * 8 DISCOS_MIXED_DENSE_MAX^2 bytes, allocated when a map set is first solved) and each
+ * solve applies it; otherwise, and always with this flag, it is solved by conjugate
+ * gradients with no allocation. */
+#define DISCOS_CREATE_MIXED_ITERATIVE 2u
+#define DISCOS_MIXED_DENSE_MAX 16384
 int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out);
 /* Waits for the device, then releases the context and its buffers.  Everything is
  * released even when the runtime reports an error on the way; that error is returned

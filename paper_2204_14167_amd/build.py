@@ -49,7 +49,8 @@ def build(verbose=True, jobs=None):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     tmp = LIB + ".tmp"
-    _run([hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", *objs, "-o", tmp], verbose)
+    _run([hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", *objs, "-lrocsolver", "-lrocblas",
+          "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

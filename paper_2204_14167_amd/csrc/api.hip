@@ -107,7 +107,17 @@ int read_wall_maps(discos_ctx* c, const discos_params* p, hipStream_t s, discos_
         q.bc_type[w] = nd > 0 ? DISCOS_BC_DIRICHLET : DISCOS_BC_NEUMANN;
         c->wm_ref[w] = q.bc_type[w];
         if (nd > 0 && nn > 0) c->wm_mixed = 1;
+        // the direct solve of walls of mixed type depends on the maps' contents
+        if (c->wm_host[w] != m) {
+            c->wm_host[w] = m;
+            ++c->wm_gen;
+        }
     }
+    for (int w = 0; w < 2; ++w)
+        if (!p->bc_type_map[w] && !c->wm_host[w].empty()) {
+            c->wm_host[w].clear();
+            ++c->wm_gen;
+        }
     return DISCOS_OK;
 }
 
@@ -364,6 +374,8 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->ef_n = -1;
     c->ef_wq = 0.0;
     c->mx_iters = 0;
+    c->mx_iterative = (flags & DISCOS_CREATE_MIXED_ITERATIVE) ? 1 : 0;
+    c->cap_nd = -1;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;
     c->last_stream = nullptr;
@@ -388,6 +400,7 @@ int discos_destroy(discos_ctx* c) {
     }
     ok = (hipFree(c->pool) == hipSuccess) && ok;
     if (c->hydro) ok = (hipFree(c->hpool) == hipSuccess) && ok;
+    ok = discos::release_dense_capacitance(c) && ok;
     delete c;
     return ok ? DISCOS_OK : DISCOS_E_HIP;
 }

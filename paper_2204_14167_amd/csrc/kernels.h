@@ -60,6 +60,21 @@ struct Ctx {
     int wm_mixed;
     int mx_iters;  // iterations of the last mixed-wall solve
     int wm_ref[2];
+    // walls of mixed type solved directly: the inverse of -S on the cap_nd unknowns
+    // (column-major, symmetric), their wall-plane indices and two packed vectors,
+    // allocated for cap_alloc unknowns when a map set is first solved this way
+    int mx_iterative;  // DISCOS_CREATE_MIXED_ITERATIVE: conjugate gradients only
+    double* cap_inv;
+    int* cap_idx;
+    double* cap_vec;
+    int64_t cap_alloc;
+    int cap_nd;         // unknowns of the held inverse (-1: none, 0: solve iteratively)
+    int cap_dkey;       // table key, generation of the maps' contents and permittivity
+    uint64_t cap_dgen;  // the held inverse belongs to
+    double cap_deps;
+    uint64_t wm_gen;    // advances whenever the wall maps' contents change
+    std::vector<int32_t> wm_host[2];
+    void* rb;           // rocBLAS handle of the factorisation (created on first use)
     // hydrodynamics (allocated with DISCOS_CREATE_HYDRO)
     int hydro;
     double2* hspec;   // spectra of u, v, w, p: nz, nz, nz+1, nz levels of [ny][nx/2+1]
@@ -223,6 +238,9 @@ int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const
                         double* phi, hipStream_t s);
 // out = F^-1 [C_k F in] on a pair of (x, y) planes with per-mode 2 x 2 maps coef.
 int plane_pair_filter(Ctx* c, const double* in, double* out, const double* coef, hipStream_t s);
+
+// Frees the dense capacitance inverse and its rocBLAS handle (false on a runtime error).
+bool release_dense_capacitance(Ctx* c);
 
 // E^P (op DISCOS_INTERP_E), q (E^P + E_ext) (DISCOS_INTERP_FORCE) or J phi
 // (DISCOS_INTERP_PHI) for the ions of the cell list; out[perm[i]] if scatter, else out[i].

@@ -22,6 +22,9 @@
 //
 // Reductions use a fixed grid and a fixed order (deterministic), and the scalars of the
 // iteration stay on the device; the host reads the residual every few iterations.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -244,46 +247,214 @@ __global__ void cap_sub_kernel(int64_t n, const double* __restrict__ v, double* 
         phi[e] -= v[e];
 }
 
-int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const int ref[2],
-                        double* phi, hipStream_t s) {
-    const GridDev& g = c->gd;
-    const WallDev w = wall_of(p);
-    const int64_t n = c->ncell, ncol = (int64_t)g.nx * g.ny, n2 = 2 * ncol;
-    const int nmode = g.nxh * g.ny;
-    const double cst = p->eps / (c->grid.h * c->grid.h);
-    const int nb = (int)std::min<int64_t>((n2 + MX_THREADS - 1) / MX_THREADS, PART_MAX);
-    const int nbv = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    double* G = c->cap;
-    double* P = c->cap + 3 * (size_t)nmode;
-    double* y = c->cap + 6 * (size_t)nmode;
-    double* r = y + n2;
-    double* pd = r + n2;
-    double* z = pd + n2;
-    double* q = z + n2;
-    double* t = q + n2;
-    double* S = c->pcg_s;
-    double* part = c->part;
-    const CapRef cr{{ref[0], ref[1]}};
-    // the uniform pair of reference types, no maps
-    discos_params pu = *p;
-    pu.bc_type[0] = ref[0];
-    pu.bc_type[1] = ref[1];
-    pu.bc_type_map[0] = pu.bc_type_map[1] = nullptr;
-    const int use_lo = p->bc_type_map[0] != nullptr, use_hi = p->bc_type_map[1] != nullptr;
-    const int key = ref[0] + 2 * ref[1] + 4 * use_lo + 8 * use_hi;
-    if (c->cap_key != key || c->cap_eps != p->eps) {
-        cap_table_kernel<<<(nmode + 255) / 256, 256, 0, s>>>(
-            g, 1.0 / cst, ref[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0,
-            ref[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0, use_lo, use_hi, G, P);
-        c->cap_key = key;
-        c->cap_eps = p->eps;
+// ---- the direct solve --------------------------------------------------------------
+// The capacitance system lives on the wall cells only, and its operator
+// -S = (1 / 2c) I - U^T M^-1 U is fixed by the maps, the wall types and eps.  Its entries
+// follow from the wall Green's functions: (U^T M^-1 U)_ij = g_ab(x_i - x_j) for unknown i
+// on wall plane b and unknown j on wall plane a, with g_ab(d) the response on plane b to
+// a unit source at the origin of plane a (the uniform-wall operator is invariant under
+// in-plane periodic shifts), read off two filter passes of unit sources.  -S is factorised
+// once per set of maps (Cholesky) and inverted; a solve is then one product with the
+// inverse, about 8 n^2 bytes read, in place of 10 to 25 preconditioned iterations of two
+// filter passes each.
+
+// out = the unit vector at e (n entries).
+__global__ void cap_unit_kernel(int64_t n, int64_t e, double* __restrict__ out) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = k == e ? 1.0 : 0.0;
+}
+
+// A[i + j nd] = (1 / 2c) [i = j] - g_{a b}(x_i - x_j), a the plane of unknown j, b that of
+// unknown i (t0, t1: the responses [2][ny][nx] to unit sources at the origin of plane 0, 1).
+__global__ void cap_dense_assemble_kernel(GridDev g, int nd, const int* __restrict__ idx,
+                                          const double* __restrict__ t0,
+                                          const double* __restrict__ t1, double hc,
+                                          double* __restrict__ A) {
+    const int64_t ncol = (int64_t)g.nx * g.ny, total = (int64_t)nd * nd;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / nd), i = (int)(e - (int64_t)j * nd);
+        const int ei = idx[i], ej = idx[j];
+        const int bi = ei >= ncol ? 1 : 0, aj = ej >= ncol ? 1 : 0;
+        const int ci = ei - bi * (int)ncol, cj = ej - aj * (int)ncol;
+        const int dx = ((ci % g.nx) - (cj % g.nx)) & (g.nx - 1);
+        const int dy = ((ci / g.nx) - (cj / g.nx)) & (g.ny - 1);
+        const double* t = aj ? t1 : t0;
+        A[e] = (i == j ? hc : 0.0) - t[bi * ncol + (int64_t)dy * g.nx + dx];
     }
+}
+
+// The upper triangle from the lower one.
+__global__ void cap_symmetrize_kernel(int nd, double* __restrict__ A) {
+    const int64_t total = (int64_t)nd * nd;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / nd), i = (int)(e - (int64_t)j * nd);
+        if (i < j) A[e] = A[j + (int64_t)i * nd];
+    }
+}
+
+// rv = -U^T u on the unknowns (u's wall layers).
+__global__ void cap_dense_pack_kernel(GridDev g, int nd, const int* __restrict__ idx,
+                                      const double* __restrict__ u, double* __restrict__ rv) {
+    const int64_t ncol = (int64_t)g.nx * g.ny;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
+        const int e = idx[i];
+        const int wall = e >= ncol ? 1 : 0;
+        rv[i] = -u[(wall ? (int64_t)(g.nz - 1) * ncol : 0) + (e - wall * ncol)];
+    }
+}
+
+// yv = A rv with A symmetric: output i is column i's product with rv, one wavefront per
+// output (its lanes along the column, coalesced), summed in a fixed order.
+__global__ void __launch_bounds__(256) cap_dense_gemv_kernel(int nd, const double* __restrict__ A,
+                                                             const double* __restrict__ rv,
+                                                             double* __restrict__ yv) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nd) return;
+    const double* col = A + (size_t)i * nd;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = lane;
+    for (; j + 192 < nd; j += 256) {
+        a0 += col[j] * rv[j];
+        a1 += col[j + 64] * rv[j + 64];
+        a2 += col[j + 128] * rv[j + 128];
+        a3 += col[j + 192] * rv[j + 192];
+    }
+    for (; j < nd; j += 64) a0 += col[j] * rv[j];
+    double acc = (a0 + a1) + (a2 + a3);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) yv[i] = acc;
+}
+
+// y[idx[i]] = yv[i] (y cleared before).
+__global__ void cap_dense_scatter_kernel(int nd, const int* __restrict__ idx,
+                                         const double* __restrict__ yv, double* __restrict__ y) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x)
+        y[idx[i]] = yv[i];
+}
+
+bool release_dense_capacitance(Ctx* c) {
+    bool ok = true;
+    if (c->cap_inv) ok = hipFree(c->cap_inv) == hipSuccess && ok;
+    if (c->cap_idx) ok = hipFree(c->cap_idx) == hipSuccess && ok;
+    if (c->cap_vec) ok = hipFree(c->cap_vec) == hipSuccess && ok;
+    c->cap_inv = nullptr;
+    c->cap_idx = nullptr;
+    c->cap_vec = nullptr;
+    c->cap_alloc = 0;
+    c->cap_nd = -1;
+    if (c->rb) {
+        ok = rocblas_destroy_handle(static_cast<rocblas_handle>(c->rb)) == rocblas_status_success && ok;
+        c->rb = nullptr;
+    }
+    return ok;
+}
+
+// The inverse of -S for the present maps (cap_nd unknowns), formed when the maps, wall
+// types or eps changed and there are at most DISCOS_MIXED_DENSE_MAX unknowns.  cap_nd = 0
+// (the iterative solve) otherwise, with DISCOS_CREATE_MIXED_ITERATIVE, or when memory
+// or the factorisation fails.  tmp: 3 wall-plane pairs of scratch.
+static int prepare_dense(Ctx* c, const int ref[2], int key, double eps, double hc,
+                         const double* G, double* tmp, hipStream_t s) {
+    if (c->cap_nd >= 0 && c->cap_dkey == key && c->cap_dgen == c->wm_gen && c->cap_deps == eps)
+        return DISCOS_OK;
+    c->cap_nd = 0;
+    c->cap_dkey = key;
+    c->cap_dgen = c->wm_gen;
+    c->cap_deps = eps;
+    if (c->mx_iterative) return DISCOS_OK;
+    const GridDev& g = c->gd;
+    const int64_t ncol = (int64_t)g.nx * g.ny, n2 = 2 * ncol;
+    std::vector<int> idx;
+    for (int w = 0; w < 2; ++w) {
+        const std::vector<int32_t>& m = c->wm_host[w];
+        if ((int64_t)m.size() != ncol) continue;
+        for (int64_t col = 0; col < ncol; ++col)
+            if (m[col] != ref[w]) idx.push_back((int)(w * ncol + col));
+    }
+    const int nd = (int)idx.size();
+    if (nd == 0 || nd > DISCOS_MIXED_DENSE_MAX) return DISCOS_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return DISCOS_E_HIP;
+    if (nd > c->cap_alloc) {
+        rocblas_handle keep = static_cast<rocblas_handle>(c->rb);
+        c->rb = nullptr;
+        if (!release_dense_capacitance(c)) return DISCOS_E_HIP;
+        c->rb = keep;
+        c->cap_nd = 0;
+        if (hipMalloc(&c->cap_inv, (size_t)nd * nd * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->cap_idx, (size_t)(nd + 1) * sizeof(int)) != hipSuccess ||
+            hipMalloc(&c->cap_vec, (size_t)2 * nd * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();  // out of memory: the iterative solve needs none of it
+            keep = static_cast<rocblas_handle>(c->rb);
+            c->rb = nullptr;
+            release_dense_capacitance(c);
+            c->rb = keep;
+            c->cap_nd = 0;
+            return DISCOS_OK;
+        }
+        c->cap_alloc = nd;
+    }
+    if (!c->rb) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return DISCOS_OK;
+        c->rb = h;
+    }
+    rocblas_handle h = static_cast<rocblas_handle>(c->rb);
+    if (hipMemcpy(c->cap_idx, idx.data(), (size_t)nd * sizeof(int), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return DISCOS_E_HIP;
+    // the Green's functions: responses to unit sources at the origins of the two planes
+    double* src = tmp;
+    double* t0 = tmp + n2;
+    double* t1 = tmp + 2 * n2;
+    const int nbu = (int)std::min<int64_t>((n2 + 255) / 256, 4096);
+    cap_unit_kernel<<<nbu, 256, 0, s>>>(n2, 0, src);
+    int rc = plane_pair_filter(c, src, t0, G, s);
+    if (rc) return rc;
+    cap_unit_kernel<<<nbu, 256, 0, s>>>(n2, ncol, src);
+    rc = plane_pair_filter(c, src, t1, G, s);
+    if (rc) return rc;
+    const int64_t total = (int64_t)nd * nd;
+    const int nba = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    cap_dense_assemble_kernel<<<nba, 256, 0, s>>>(g, nd, c->cap_idx, t0, t1, hc, c->cap_inv);
+    if (hipGetLastError() != hipSuccess) return DISCOS_E_HIP;
+    // -S = L L^T, then its inverse from the factor (lower triangle), then the upper half
+    rocblas_int* info = reinterpret_cast<rocblas_int*>(c->cap_idx + nd);
+    if (rocblas_set_stream(h, s) != rocblas_status_success ||
+        rocsolver_dpotrf(h, rocblas_fill_lower, nd, c->cap_inv, nd, info) != rocblas_status_success)
+        return DISCOS_E_HIP;
+    rocblas_int ih = 0;
+    if (hipMemcpyAsync(&ih, info, sizeof(ih), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DISCOS_E_HIP;
+    if (ih != 0) return DISCOS_OK;  // not positive definite in floating point: iterate
+    if (rocsolver_dpotri(h, rocblas_fill_lower, nd, c->cap_inv, nd, info) != rocblas_status_success)
+        return DISCOS_E_HIP;
+    if (hipMemcpyAsync(&ih, info, sizeof(ih), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DISCOS_E_HIP;
+    if (ih != 0) return DISCOS_OK;
+    cap_symmetrize_kernel<<<nba, 256, 0, s>>>(nd, c->cap_inv);
+    if (hipGetLastError() != hipSuccess) return DISCOS_E_HIP;
+    c->cap_nd = nd;
+    return DISCOS_OK;
+}
+
+// The capacitance system by preconditioned conjugate gradients: r = -U^T u, y = 0, then
+// iterate to the tolerance.
+static int solve_capacitance_cg(Ctx* c, const GridDev& g, const WallDev& w, const CapRef& cr,
+                                const double* G, const double* P, int nb, double* S,
+                                double* part, const double* phi, double* y, double* r, double* pd,
+                                double* z, double* q, double* t, hipStream_t s) {
+    const int64_t n2 = 2 * (int64_t)g.nx * g.ny;
+    const double cst = c->cap_eps / (c->grid.h * c->grid.h);
     auto finish = [&](int slot, int roll) {
         mx_finish_kernel<<<1, MX_THREADS, 0, s>>>(part, nb, S, slot, roll);
     };
-    // u = M^-1 b into phi (b may share storage with phi); r = -U^T u, y = 0
-    int rc = solve_poisson(c, rhs, &pu, phi, s);
-    if (rc) return rc;
+    int rc = DISCOS_OK;
     cap_rhs_kernel<<<nb, MX_THREADS, 0, s>>>(g, w, cr, phi, r, y, part);
     finish(S_BB, 0);
     // z = P r (restricted), p = z
@@ -324,6 +495,62 @@ int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const
         mx_direction_kernel<<<nb, MX_THREADS, 0, s>>>(n2, S, 0, z, pd);
     }
     if (!done) return DISCOS_E_NOT_CONVERGED;
+    return DISCOS_OK;
+}
+
+int solve_poisson_mixed(Ctx* c, const double* rhs, const discos_params* p, const int ref[2],
+                        double* phi, hipStream_t s) {
+    const GridDev& g = c->gd;
+    const WallDev w = wall_of(p);
+    const int64_t n = c->ncell, ncol = (int64_t)g.nx * g.ny, n2 = 2 * ncol;
+    const int nmode = g.nxh * g.ny;
+    const double cst = p->eps / (c->grid.h * c->grid.h);
+    const int nb = (int)std::min<int64_t>((n2 + MX_THREADS - 1) / MX_THREADS, PART_MAX);
+    const int nbv = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    double* G = c->cap;
+    double* P = c->cap + 3 * (size_t)nmode;
+    double* y = c->cap + 6 * (size_t)nmode;
+    double* r = y + n2;
+    double* pd = r + n2;
+    double* z = pd + n2;
+    double* q = z + n2;
+    double* t = q + n2;
+    double* S = c->pcg_s;
+    double* part = c->part;
+    const CapRef cr{{ref[0], ref[1]}};
+    // the uniform pair of reference types, no maps
+    discos_params pu = *p;
+    pu.bc_type[0] = ref[0];
+    pu.bc_type[1] = ref[1];
+    pu.bc_type_map[0] = pu.bc_type_map[1] = nullptr;
+    const int use_lo = p->bc_type_map[0] != nullptr, use_hi = p->bc_type_map[1] != nullptr;
+    const int key = ref[0] + 2 * ref[1] + 4 * use_lo + 8 * use_hi;
+    if (c->cap_key != key || c->cap_eps != p->eps) {
+        cap_table_kernel<<<(nmode + 255) / 256, 256, 0, s>>>(
+            g, 1.0 / cst, ref[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0,
+            ref[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0, use_lo, use_hi, G, P);
+        c->cap_key = key;
+        c->cap_eps = p->eps;
+    }
+    int rc = prepare_dense(c, ref, key, p->eps, 0.5 / cst, G, r, s);
+    if (rc) return rc;
+    // u = M^-1 b into phi (b may share storage with phi)
+    rc = solve_poisson(c, rhs, &pu, phi, s);
+    if (rc) return rc;
+    if (c->cap_nd > 0) {
+        // y = (-S)^-1 (-U^T u) by the held inverse
+        const int nd = c->cap_nd;
+        double* rv = c->cap_vec;
+        double* yv = rv + nd;
+        const int nbd = (nd + 255) / 256;
+        cap_dense_pack_kernel<<<nbd, 256, 0, s>>>(g, nd, c->cap_idx, phi, rv);
+        cap_dense_gemv_kernel<<<(nd + 3) / 4, 256, 0, s>>>(nd, c->cap_inv, rv, yv);
+        fill_f64(y, n2, 0.0, s);
+        cap_dense_scatter_kernel<<<nbd, 256, 0, s>>>(nd, c->cap_idx, yv, y);
+    } else {
+        rc = solve_capacitance_cg(c, g, w, cr, G, P, nb, S, part, phi, y, r, pd, z, q, t, s);
+        if (rc) return rc;
+    }
     // phi = u - M^-1 U y
     double* f = c->pcg;
     double* v = c->pcg + n;
