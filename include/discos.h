@@ -399,17 +399,28 @@ int discos_batch_destroy(discos_batch* b);
 int discos_batch_step(discos_batch* b, double* pos, double* q, int32_t* id, int32_t* species,
                       uint64_t step, uint32_t flags, void* stream);
 
-/* Autotuner: times the spread tile (8^3 or 16^3) with its persistent block count, the
- * interpolation tile (8x8x8 or 16x16x8) with its block count, the channel densities below
- * which the interpolation reads each ion's window directly instead of staging tiles and
- * the spread adds each ion's window with global atomics (0, 8, 24, 64 ions per 2048
- * cells, or every channel), and the workgroup size of the per-ion stages on the current
- * ions, without advancing them, and keeps the fastest of each.  cfg (host [7], nullable)
- * receives spread tile, spread blocks (0 = one per task), interpolation tile,
- * interpolation blocks, per-ion workgroup size, and the two densities (interpolation,
- * spread; 2^30: every channel). */
+/* Autotuner: for each cell-list bin edge (2 cells, and 4 cells when every channel is at
+ * least 2 (2R + 1) cells wide for the near-field search radius R of 4-cell bins), times
+ * the spread tile (8^3 or 16^3) with its persistent block count, the interpolation tile
+ * (8x8x8 or 16x16x8) with its block count, the channel densities below which the
+ * interpolation reads each ion's window directly instead of staging tiles and the spread
+ * adds each ion's window with global atomics (0, 8, 24, 64 ions per 2048 cells, or every
+ * channel), and the workgroup size of the per-ion stages on the current ions, without
+ * advancing them, and keeps the fastest of each; then keeps the bin edge whose cell list,
+ * spread, interpolation and near field take the least time together.  cfg (host [10],
+ * nullable) receives spread tile, spread blocks (0 = one per task), interpolation tile,
+ * interpolation blocks, per-ion workgroup size, the two densities (interpolation, spread;
+ * 2^30: every channel), the bin edge in cells, and the microseconds those four stages
+ * took together with bins of 2 and of 4 cells (0: not tried).  Results do not depend on
+ * the choices (the bins only order the work). */
 int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const int32_t* id,
                       const int32_t* species, int32_t* cfg, void* stream);
+
+/* Sets the cell-list bin edge of the batch to `bin` cells (2, the default, or 4), as the
+ * autotuner would; DISCOS_E_ARG for another value, DISCOS_E_SHAPE if some channel is
+ * narrower than 2 (2R + 1) bins of that edge.  Synchronises the device; a captured graph
+ * is captured again at the next graph step. */
+int discos_batch_set_bin(discos_batch* b, int32_t bin);
 
 /* Sticky device flags of the batch (as discos_check) and the last host error. */
 int discos_batch_check(discos_batch* b);

@@ -291,8 +291,8 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     const double udv = gU * dV;
     const double s_lo = wl.type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = wl.type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
-    const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
+    const int nbxt = tx >> g.lb, nbyt = ty >> g.lb;
+    const int bz0 = z0 >> g.lb, bz1 = (z0 + tz - 1) >> g.lb;
     static_assert((GT_TZ / DISCOS_BIN) * (GT_TY / DISCOS_BIN) <= GT_MAXR && GT_MAXR <= GT_THREADS,
                   "gradient tile rows exceed GT_MAXR");
     const int nrows = (bz1 - bz0 + 1) * nbyt;
@@ -300,8 +300,8 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
         int len = 0;
         const int t = threadIdx.x;
         if (t < nrows) {
-            const int bz = bz0 + t / nbyt, by = y0 / DISCOS_BIN + t % nbyt;
-            const int row = (bz * g.nby + by) * g.nbx + x0 / DISCOS_BIN;
+            const int bz = bz0 + t / nbyt, by = (y0 >> g.lb) + t % nbyt;
+            const int row = (bz * g.nby + by) * g.nbx + (x0 >> g.lb);
             const int st = bin_start[row];
             rstart[t] = st;
             len = bin_start[row + nbxt] - st;

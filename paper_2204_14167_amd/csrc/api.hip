@@ -232,6 +232,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     g.Lx = grid->nx * grid->h;
     g.Ly = grid->ny * grid->h;
     g.Lz = grid->nz * grid->h;
+    g.lb = DISCOS_LB;
     g.nbx = grid->nx / DISCOS_BIN;
     g.nby = grid->ny / DISCOS_BIN;
     g.nbz = (grid->nz + DISCOS_BIN - 1) / DISCOS_BIN;

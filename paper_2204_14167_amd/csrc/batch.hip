@@ -86,6 +86,92 @@ static bool set_direct(discos_batch* b, int stage, int thresh) {
                      hipMemcpyHostToDevice) == hipSuccess;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Grid of channel c with the cell-list bin edge 2^lb cells (the bin fields only).
+discos::GridDev bin_grid(const discos_replica& c, double h, int lb) {
+    discos::GridDev g{};
+    g.nx = c.nx;
+    g.ny = c.ny;
+    g.nz = c.nz;
+    g.h = h;
+    g.lb = lb;
+    g.nbx = c.nx >> lb;
+    g.nby = c.ny >> lb;
+    g.nbz = (c.nz + (1 << lb) - 1) >> lb;
+    return g;
+}
+
+// Bins and padded bins of every channel for the bin edge 2^lb (host side only).
+discos::BinLayout bin_layout(const std::vector<discos_replica>& reps, double h,
+                             const discos_params* p, int lb) {
+    discos::BinLayout L;
+    const int count = (int)reps.size();
+    L.R = discos::near_radius_bins_h(h, p, lb);
+    L.ok = L.R >= 1 && L.R <= 3;
+    L.bin_off.assign(count + 1, 0);
+    L.pbin_off.assign(count + 1, 0);
+    int pmax = 1;
+    for (int r = 0; r < count; ++r) {
+        const discos_replica& c = reps[r];
+        const discos::GridDev g = bin_grid(c, h, lb);
+        // the search window of 2R + 1 bins may not wrap onto itself in x or y
+        if (2 * L.R + 1 > g.nbx || 2 * L.R + 1 > g.nby) L.ok = false;
+        L.bin_off[r + 1] = L.bin_off[r] + g.nbx * g.nby * g.nbz;
+        const int64_t pb = discos::near_list_bins(g, std::max(L.R, 1));
+        L.pbin_off[r + 1] = L.pbin_off[r] + (int)pb;
+        pmax = std::max(pmax, (int)pb);
+        L.nl_entries += discos::near_list_entries(g, c.n);
+    }
+    L.nbins = L.bin_off[count];
+    L.pbins = L.pbin_off[count];
+    L.pbin_xblocks = std::min((pmax + 255) / 256, 64);
+    return L;
+}
+
+// Switches the batch to the bin edge 2^lb (a layout whose bins fit the allocation):
+// channel grids and first bins on the device, bin counts cleared, a captured graph
+// dropped (its launch shapes change).  Synchronous.
+bool apply_layout(discos_batch* b, int lb) {
+    const discos::BinLayout& L = b->lay[lb];
+    const int count = (int)b->reps.size();
+    for (int r = 0; r < count; ++r) {
+        discos::RepDev& d = b->reps_h[r];
+        const discos::GridDev g = bin_grid(b->reps[r], b->h, lb);
+        d.g.lb = lb;
+        d.g.nbx = g.nbx;
+        d.g.nby = g.nby;
+        d.g.nbz = g.nbz;
+        d.bin_off = L.bin_off[r];
+    }
+    b->cfg.lb = lb;
+    b->nbins_tot = L.nbins;
+    b->pbins_tot = L.pbins;
+    b->pbin_xblocks = L.pbin_xblocks;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    bool ok = hipDeviceSynchronize() == hipSuccess;
+    ok = ok && hipMemcpy(b->reps_d, b->reps_h.data(), count * sizeof(discos::RepDev),
+                         hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->pbin_off, L.pbin_off.data(), (count + 1) * sizeof(int),
+                         hipMemcpyHostToDevice) == hipSuccess;
+    // bin counts start at zero; the scan that reads them clears them again
+    ok = ok && hipMemset(b->bin_count, 0, b->lay[1].nbins * sizeof(int)) == hipSuccess;
+    return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
 int discos_batch_create(const discos_replica* reps, int32_t count, double h, const discos_params* p,
                         discos_batch** out) {
     if (!out) return DISCOS_E_ARG;
@@ -105,7 +191,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     if (p->psi / h / p->p3m_dr + 2.0 > 320.0) return DISCOS_E_ARG;
     if (p->lj_on && (!p->lj_sigma || !p->lj_xi || !finite_pos(p->lj_range))) return DISCOS_E_ARG;
     if (p->bc_type_map[0] || p->bc_type_map[1]) return DISCOS_E_ARG;  // channels have uniform walls
-    const int Rb = discos::near_radius_bins_h(h, p);
+    const int Rb = discos::near_radius_bins_h(h, p, DISCOS_LB);
     if (Rb > 3) return DISCOS_E_ARG;
     int64_t n_tot = 0;
     for (int r = 0; r < count; ++r) {
@@ -126,7 +212,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->p = *p;
     b->reps.assign(reps, reps + count);
     b->n_tot = n_tot;
-    b->cfg = {16, 0, 16, 0, 256, 1 << 30, 24};
+    b->cfg = {16, 0, 16, 0, 256, 1 << 30, 24, DISCOS_LB};
     b->next_step = ~uint64_t(0);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -138,26 +224,19 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
         b->ncu <= 0)
         b->ncu = 256;
 
-    // ions and bins in channel order
+    // ions and bins in channel order; the bins and the near field's padded bins and copies
+    // for both bin edges (2 cells: DISCOS_BIN, the default; 4 cells where every channel is
+    // wide enough), buffers sized for the larger of the two
     b->ion_off.assign(count + 1, 0);
-    std::vector<int> bin_off(count + 1, 0);
-    for (int r = 0; r < count; ++r) {
-        const discos_replica& c = reps[r];
-        b->ion_off[r + 1] = b->ion_off[r] + c.n;
-        const int nb = (c.nx / DISCOS_BIN) * (c.ny / DISCOS_BIN) * ((c.nz + DISCOS_BIN - 1) / DISCOS_BIN);
-        bin_off[r + 1] = bin_off[r] + nb;
-    }
-    b->nbins_tot = bin_off[count];
-    // the near field's padded bins and copies, per channel (search radius Rb bins)
-    std::vector<int> pbin_off(count + 1, 0);
-    int64_t nl_cap = 0;
-    for (int r = 0; r < count; ++r) {
-        const discos_replica& c = reps[r];
-        const int64_t nbz = (c.nz + DISCOS_BIN - 1) / DISCOS_BIN;
-        pbin_off[r + 1] = pbin_off[r] + (int)((c.nx / DISCOS_BIN + 2 * Rb) * (int64_t)(c.ny / DISCOS_BIN + 2 * Rb) *
-                                              (nbz + 2 * Rb + (c.nz & 1)));
-        nl_cap += std::max<int64_t>(c.n, 1) * 4 * (nbz < 7 ? 3 : 2);
-    }
+    for (int r = 0; r < count; ++r) b->ion_off[r + 1] = b->ion_off[r] + reps[r].n;
+    for (int lb = 1; lb <= 2; ++lb) b->lay[lb] = bin_layout(b->reps, h, p, lb);
+    const std::vector<int>& bin_off = b->lay[DISCOS_LB].bin_off;
+    const std::vector<int>& pbin_off = b->lay[DISCOS_LB].pbin_off;
+    b->nbins_tot = b->lay[DISCOS_LB].nbins;
+    b->pbins_tot = b->lay[DISCOS_LB].pbins;
+    const int64_t nbins_cap = std::max(b->lay[1].nbins, b->lay[2].nbins);
+    const int64_t pbins_cap = std::max(b->lay[1].pbins, b->lay[2].ok ? b->lay[2].pbins : 0);
+    const int64_t nl_cap = std::max(b->lay[1].nl_entries, b->lay[2].ok ? b->lay[2].nl_entries : 0);
     // cells and spectra by (nx, ny) class
     std::map<std::pair<int, int>, std::vector<int>> cls;
     for (int r = 0; r < count; ++r) cls[{reps[r].nx, reps[r].ny}].push_back(r);
@@ -186,9 +265,10 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
             g.Lx = c.nx * h;
             g.Ly = c.ny * h;
             g.Lz = c.nz * h;
-            g.nbx = c.nx / DISCOS_BIN;
-            g.nby = c.ny / DISCOS_BIN;
-            g.nbz = (c.nz + DISCOS_BIN - 1) / DISCOS_BIN;
+            g.lb = DISCOS_LB;
+            g.nbx = c.nx >> DISCOS_LB;
+            g.nby = c.ny >> DISCOS_LB;
+            g.nbz = (c.nz + DISCOS_BIN - 1) >> DISCOS_LB;
             d.cell_off = cell;
             d.spec_off = spec;
             d.bin_off = bin_off[r];
@@ -280,15 +360,15 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
 
     // one allocation
     const size_t n = (size_t)std::max<int64_t>(n_tot, 1);
-    const size_t nblk = (size_t)(b->nbins_tot + 1023) / 1024 + 1;
+    const size_t nblk = (size_t)(nbins_cap + 1023) / 1024 + 1;
     size_t bytes = 0;
     bytes += carve_bytes(n, sizeof(double4));
-    bytes += carve_bytes(pbin_off[count], sizeof(int)) + carve_bytes(pbin_off[count] + 1, sizeof(int));
-    bytes += carve_bytes(pbin_off[count] / 1024 + 2, sizeof(int)) + carve_bytes(count + 1, sizeof(int));
+    bytes += carve_bytes(pbins_cap, sizeof(int)) + carve_bytes(pbins_cap + 1, sizeof(int));
+    bytes += carve_bytes(pbins_cap / 1024 + 2, sizeof(int)) + carve_bytes(count + 1, sizeof(int));
     bytes += carve_bytes(nl_cap, sizeof(double4)) + carve_bytes(nl_cap, sizeof(float4));
     bytes += carve_bytes(nl_cap, sizeof(int));
     bytes += 6 * carve_bytes(n, sizeof(int));  // sid ssp perm ion_bin ion_rank ion_rep
-    bytes += carve_bytes(b->nbins_tot, sizeof(int)) + carve_bytes(b->nbins_tot + 1, sizeof(int));
+    bytes += carve_bytes(nbins_cap, sizeof(int)) + carve_bytes(nbins_cap + 1, sizeof(int));
     bytes += carve_bytes(nblk, sizeof(int));
     bytes += 2 * carve_bytes(b->ncell_tot, sizeof(double));
     const int64_t ncp = b->z_legacy ? b->nspec_tot : 1;
@@ -311,17 +391,15 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     }
     char* cur = static_cast<char*>(b->pool);
     b->sxyzq = carve<double4>(cur, n);
-    b->nl.count = carve<int>(cur, pbin_off[count]);
-    b->nl.start = carve<int>(cur, pbin_off[count] + 1);
-    b->nl.tmp = carve<int>(cur, pbin_off[count] / 1024 + 2);
+    b->nl.count = carve<int>(cur, pbins_cap);
+    b->nl.start = carve<int>(cur, pbins_cap + 1);
+    b->nl.tmp = carve<int>(cur, pbins_cap / 1024 + 2);
     b->nl.xyzq = carve<double4>(cur, nl_cap);
     b->nl.xyzf = carve<float4>(cur, nl_cap);
     b->nl.sp = carve<int>(cur, nl_cap);
     b->nl.cap = nl_cap;
-    b->nl.bins_cap = pbin_off[count];
-    int pmax = 1;
-    for (int r = 0; r < count; ++r) pmax = std::max(pmax, pbin_off[r + 1] - pbin_off[r]);
-    b->pbin_xblocks = std::min((pmax + 255) / 256, 64);
+    b->nl.bins_cap = pbins_cap;
+    b->pbin_xblocks = b->lay[DISCOS_LB].pbin_xblocks;
     b->pbin_off = carve<int>(cur, count + 1);
     b->sid = carve<int>(cur, n);
     b->ssp = carve<int>(cur, n);
@@ -329,8 +407,8 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     b->ion_bin = carve<int>(cur, n);
     b->ion_rank = carve<int>(cur, n);
     b->ion_rep = carve<int>(cur, n);
-    b->bin_count = carve<int>(cur, b->nbins_tot);
-    b->bin_start = carve<int>(cur, b->nbins_tot + 1);
+    b->bin_count = carve<int>(cur, nbins_cap);
+    b->bin_start = carve<int>(cur, nbins_cap + 1);
     b->scan_tmp = carve<int>(cur, nblk);
     b->rho = carve<double>(cur, b->ncell_tot);
     b->phi = carve<double>(cur, b->ncell_tot);
@@ -427,7 +505,7 @@ int discos_batch_create(const discos_replica* reps, int32_t count, double h, con
     ok = ok && discos::batch_pivots(b, 0) == DISCOS_OK && hipStreamSynchronize(0) == hipSuccess;
     ok = ok && hipMemset(b->flags, 0, 64 * sizeof(int)) == hipSuccess;
     // bin counts start at zero; the scan that reads them clears them again
-    ok = ok && hipMemset(b->bin_count, 0, b->nbins_tot * sizeof(int)) == hipSuccess;
+    ok = ok && hipMemset(b->bin_count, 0, nbins_cap * sizeof(int)) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         destroy(b);
@@ -518,79 +596,111 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         timing_ok = timing_ok && ok;
         return ok ? ms : 1e30f;
     };
-    int rc = discos::batch_cell_list(b, pos, q, const_cast<int*>(id), const_cast<int*>(species), s);
-    const int blocks[3] = {0, 4 * b->ncu, 8 * b->ncu};
-    // spread: tile edge x persistent blocks
-    float best = 1e30f;
-    discos::BatchCfg c = b->cfg;
-    for (int t : {8, 16})
-        for (int nb : blocks) {
-            b->cfg.spread_t = t;
-            b->cfg.spread_blocks = nb;
+    // every stage's choices for one bin edge; returns the summed best times of the stages
+    // the bin edge affects (cell list, spread, interpolation, near field)
+    auto tune_stages = [&](discos::BatchCfg& c, int& rc) -> float {
+        const float t_cells = timed([&] {
+            discos::batch_cell_list(b, pos, q, const_cast<int*>(id), const_cast<int*>(species), s);
+        });
+        rc = discos::batch_cell_list(b, pos, q, const_cast<int*>(id), const_cast<int*>(species), s);
+        const int blocks[3] = {0, 4 * b->ncu, 8 * b->ncu};
+        // spread: tile edge x persistent blocks
+        float best = 1e30f;
+        c = b->cfg;
+        for (int t : {8, 16})
+            for (int nb : blocks) {
+                b->cfg.spread_t = t;
+                b->cfg.spread_blocks = nb;
+                const float ms = timed([&] { discos::batch_spread(b, s); });
+                if (ms < best) {
+                    best = ms;
+                    c.spread_t = t;
+                    c.spread_blocks = nb;
+                }
+            }
+        b->cfg.spread_t = c.spread_t;
+        b->cfg.spread_blocks = c.spread_blocks;
+        // spread: the density below which channels add their ions with global atomics
+        best = 1e30f;
+        for (int th : {0, 8, 24, 64, 1 << 30}) {
+            if (!set_direct(b, 1, th)) {
+                timing_ok = false;
+                break;
+            }
             const float ms = timed([&] { discos::batch_spread(b, s); });
             if (ms < best) {
                 best = ms;
-                c.spread_t = t;
-                c.spread_blocks = nb;
+                c.spread_direct = th;
             }
         }
-    b->cfg.spread_t = c.spread_t;
-    b->cfg.spread_blocks = c.spread_blocks;
-    // spread: the density below which channels add their ions with global atomics
-    best = 1e30f;
-    for (int th : {0, 8, 24, 64, 1 << 30}) {
-        if (!set_direct(b, 1, th)) {
-            timing_ok = false;
-            break;
-        }
-        const float ms = timed([&] { discos::batch_spread(b, s); });
-        if (ms < best) {
-            best = ms;
-            c.spread_direct = th;
-        }
-    }
-    if (!set_direct(b, 1, c.spread_direct)) timing_ok = false;
-    if (!rc) rc = discos::batch_spread(b, s);
-    if (!rc) rc = discos::batch_poisson(b, s);
-    // interpolation: tile shape x persistent blocks
-    best = 1e30f;
-    for (int t : {8, 16})
-        for (int nb : blocks) {
-            b->cfg.interp_t = t;
-            b->cfg.interp_blocks = nb;
+        const float t_spread = best;
+        if (!set_direct(b, 1, c.spread_direct)) timing_ok = false;
+        if (!rc) rc = discos::batch_spread(b, s);
+        if (!rc) rc = discos::batch_poisson(b, s);
+        // interpolation: tile shape x persistent blocks
+        best = 1e30f;
+        for (int t : {8, 16})
+            for (int nb : blocks) {
+                b->cfg.interp_t = t;
+                b->cfg.interp_blocks = nb;
+                const float ms = timed([&] { discos::batch_interp(b, s); });
+                if (ms < best) {
+                    best = ms;
+                    c.interp_t = t;
+                    c.interp_blocks = nb;
+                }
+            }
+        b->cfg.interp_t = c.interp_t;
+        b->cfg.interp_blocks = c.interp_blocks;
+        // interpolation: the density below which channels skip the staged tiles
+        best = 1e30f;
+        for (int th : {0, 8, 24, 64, 1 << 30}) {
+            if (!set_direct(b, 0, th)) {
+                timing_ok = false;
+                break;
+            }
             const float ms = timed([&] { discos::batch_interp(b, s); });
             if (ms < best) {
                 best = ms;
-                c.interp_t = t;
-                c.interp_blocks = nb;
+                c.interp_direct = th;
             }
         }
-    b->cfg.interp_t = c.interp_t;
-    b->cfg.interp_blocks = c.interp_blocks;
-    // interpolation: the density below which channels skip the staged tiles
-    best = 1e30f;
-    for (int th : {0, 8, 24, 64, 1 << 30}) {
-        if (!set_direct(b, 0, th)) {
+        const float t_interp = best;
+        if (!set_direct(b, 0, c.interp_direct)) timing_ok = false;
+        // per-ion stages: workgroup size (the padded list and the near-field pass)
+        best = 1e30f;
+        for (int wg : {64, 128, 256}) {
+            b->cfg.ion_block = wg;
+            const float ms = timed([&] { discos::batch_near(b, s); });
+            if (ms < best) {
+                best = ms;
+                c.ion_block = wg;
+            }
+        }
+        b->cfg = c;
+        return t_cells + t_spread + t_interp + best;
+    };
+    // the bin edge: 2 cells, and 4 cells where every channel is wide enough for it
+    int rc = 0;
+    discos::BatchCfg c = b->cfg;
+    float best_total = 1e30f;
+    float totals[3] = {0.0f, 0.0f, 0.0f};
+    for (int lb = 1; lb <= 2 && !rc; ++lb) {
+        if (!b->lay[lb].ok) continue;
+        if (!apply_layout(b, lb)) {
             timing_ok = false;
             break;
         }
-        const float ms = timed([&] { discos::batch_interp(b, s); });
-        if (ms < best) {
-            best = ms;
-            c.interp_direct = th;
+        discos::BatchCfg cl;
+        const float total = tune_stages(cl, rc);
+        totals[lb] = total;
+        if (total < best_total) {
+            best_total = total;
+            c = cl;
         }
     }
-    if (!set_direct(b, 0, c.interp_direct)) timing_ok = false;
-    // per-ion stages: workgroup size (the near-field pair of kernels)
-    best = 1e30f;
-    for (int wg : {64, 128, 256}) {
-        b->cfg.ion_block = wg;
-        const float ms = timed([&] { discos::batch_near(b, s); });
-        if (ms < best) {
-            best = ms;
-            c.ion_block = wg;
-        }
-    }
+    if (!apply_layout(b, c.lb)) timing_ok = false;
+    if (!set_direct(b, 0, c.interp_direct) || !set_direct(b, 1, c.spread_direct)) timing_ok = false;
     b->cfg = c;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -611,9 +721,22 @@ int discos_batch_tune(discos_batch* b, const double* pos, const double* q, const
         cfg_out[4] = c.ion_block;
         cfg_out[5] = c.interp_direct;
         cfg_out[6] = c.spread_direct;
+        cfg_out[7] = 1 << c.lb;
+        // microseconds of one pass of the bin-dependent stages, per bin edge (0: not tried)
+        cfg_out[8] = (int32_t)(1e3f * totals[1] / reps + 0.5f);
+        cfg_out[9] = (int32_t)(1e3f * totals[2] / reps + 0.5f);
     }
     if (rc || !timing_ok || hipGetLastError() != hipSuccess)
         return fail(b, DISCOS_E_HIP, "tuning launch failed");
+    return DISCOS_OK;
+}
+
+int discos_batch_set_bin(discos_batch* b, int32_t bin) {
+    if (!b) return DISCOS_E_ARG;
+    if (bin != 2 && bin != 4) return fail(b, DISCOS_E_ARG, "bin edge must be 2 or 4 cells");
+    const int lb = bin == 2 ? 1 : 2;
+    if (!b->lay[lb].ok) return fail(b, DISCOS_E_SHAPE, "a channel is too narrow for this bin edge");
+    if (!apply_layout(b, lb)) return fail(b, DISCOS_E_HIP, "bin layout update failed");
     return DISCOS_OK;
 }
 

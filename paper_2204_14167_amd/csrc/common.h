@@ -12,9 +12,12 @@
 #define DISCOS_FLAG_BAD_SPECIES 8
 #define DISCOS_FLAG_CAPACITY 16  // a tile's candidate rows exceeded its row buffer
 
-// Bin edge of the cell list, in cells.  Two cells keeps the near-field search
-// volume small (5^3 bins for psi = 4 h) and gives the spread a one-bin halo.
+// Bin edge of the cell list, in cells: DISCOS_BIN for a single channel (two cells keep the
+// near-field search volume small, 5^3 bins for psi = 4 h, and give the spread a one-bin
+// halo).  A batch may use 2 or 4 (GridDev::lb); DISCOS_BIN is the smallest edge, which
+// the compile-time row bounds of the tile gathers assume.
 #define DISCOS_BIN 2
+#define DISCOS_LB 1  // log2(DISCOS_BIN)
 
 namespace discos {
 
@@ -22,6 +25,7 @@ struct GridDev {
     int nx, ny, nz, nxh;
     double h, inv_h, Lx, Ly, Lz;
     int nbx, nby, nbz;  // cell-list bins per dimension
+    int lb = DISCOS_LB;  // log2 of the bin edge in cells (1: 2 cells, 2: 4 cells)
     // image sign of the tangential velocity components at the lower / upper wall:
     // -1 no-slip, +1 slip (set per hydrodynamic call)
     double tsg[2] = {-1.0, -1.0};
@@ -186,7 +190,10 @@ __device__ __forceinline__ void normal_pair(uint64_t seed, uint64_t step, uint32
 #define DISCOS_TAG_STRESS_EDGE 3u
 #define DISCOS_TAG_RFD 4u
 
-// Cell-list bin of a position (bins of DISCOS_BIN cells; z clamped into the channel).
+// Bin edge of a grid's cell list, in length units.
+__host__ __device__ __forceinline__ double bin_edge(const GridDev& g) { return (double)(1 << g.lb) * g.h; }
+
+// Cell-list bin of a position (bins of 2^lb cells; z clamped into the channel).
 __device__ __forceinline__ int bin_of(const GridDev& g, double x, double y, double z, int& bx,
                                       int& by, int& bz) {
     int cx = (int)floor(reduce_periodic(x, g.Lx) * g.inv_h);
@@ -195,9 +202,9 @@ __device__ __forceinline__ int bin_of(const GridDev& g, double x, double y, doub
     cx = min(max(cx, 0), g.nx - 1);
     cy = min(max(cy, 0), g.ny - 1);
     cz = min(max(cz, 0), g.nz - 1);
-    bx = cx / DISCOS_BIN;
-    by = cy / DISCOS_BIN;
-    bz = cz / DISCOS_BIN;
+    bx = cx >> g.lb;
+    by = cy >> g.lb;
+    bz = cz >> g.lb;
     return (bz * g.nby + by) * g.nbx + bx;
 }
 
@@ -267,7 +274,8 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int* wsum, int& total
 
 // Largest number of candidate rows tile_ranges can produce for a tile of ty x tz cells
 // starting on even cells (every tile edge is even) with a window of hlo cells below and
-// hhi above: each (y, z) bin row of the range contributes at most two x segments.
+// hhi above: each (y, z) bin row of the range contributes at most two x segments.  Bins
+// of DISCOS_BIN cells give the most rows; larger bins give fewer.
 constexpr int tile_rows_bound(int ty, int tz, int hlo, int hhi) {
     return 2 * ((ty - 1 + hhi) / DISCOS_BIN + (hlo + DISCOS_BIN - 1) / DISCOS_BIN + 1) *
            ((tz - 1 + hhi) / DISCOS_BIN + (hlo + DISCOS_BIN - 1) / DISCOS_BIN + 1);
@@ -290,7 +298,8 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
                              int* __restrict__ flags, int hlo = 2, int hhi = 2) {
     int sa[2], sb[2], nseg;
     {
-        const int lo = floordiv(x0 - hlo, DISCOS_BIN), hi = floordiv(x0 + tx - 1 + hhi, DISCOS_BIN);
+        // arithmetic shifts: floor division by the bin edge, negative cells included
+        const int lo = (x0 - hlo) >> g.lb, hi = (x0 + tx - 1 + hhi) >> g.lb;
         if (hi - lo + 1 >= g.nbx) {
             nseg = 1; sa[0] = 0; sb[0] = g.nbx - 1;
         } else {
@@ -299,10 +308,10 @@ __device__ int tile_ranges(const GridDev& g, const int* __restrict__ bin_start, 
             else { nseg = 2; sa[0] = a; sb[0] = g.nbx - 1; sa[1] = 0; sb[1] = b; }
         }
     }
-    int ylo = floordiv(y0 - hlo, DISCOS_BIN), yhi = floordiv(y0 + ty - 1 + hhi, DISCOS_BIN);
+    int ylo = (y0 - hlo) >> g.lb, yhi = (y0 + ty - 1 + hhi) >> g.lb;
     if (yhi - ylo + 1 >= g.nby) { ylo = 0; yhi = g.nby - 1; }
     const int czlo = max(z0 - hlo, 0), czhi = min(z0 + tz - 1 + hhi, g.nz - 1);
-    const int bzlo = czlo / DISCOS_BIN, bzhi = czhi / DISCOS_BIN;
+    const int bzlo = czlo >> g.lb, bzhi = czhi >> g.lb;
     const int nyb = yhi - ylo + 1;
     const int ncand = max(bzhi - bzlo + 1, 0) * nyb * nseg;
     const int t = threadIdx.x, bd = blockDim.x;

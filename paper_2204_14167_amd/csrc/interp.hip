@@ -132,17 +132,17 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
     const int tx = min(TX, g.nx), ty = min(TY, g.ny);
     const int tz = min(TZ, g.nz - z0);
     const int lxn = tx + IT_H, lyn = ty + IT_H, lzn = tz + IT_H;
-    // ions of the tile: rows (bz, by) of tx / DISCOS_BIN contiguous bins
-    const int nbxt = tx / DISCOS_BIN, nbyt = ty / DISCOS_BIN;
-    const int bz0 = z0 / DISCOS_BIN, bz1 = (z0 + tz - 1) / DISCOS_BIN;
+    // ions of the tile: rows (bz, by) of tx / 2^lb contiguous bins (tile edges fall on bin edges)
+    const int nbxt = tx >> g.lb, nbyt = ty >> g.lb;
+    const int bz0 = z0 >> g.lb, bz1 = (z0 + tz - 1) >> g.lb;
     const int nrows = (bz1 - bz0 + 1) * nbyt;
     {
         // thread t < nrows owns row t; a workgroup scan of the row lengths gives rpre
         int len = 0;
         const int t = threadIdx.x;
         if (t < nrows) {
-            const int bz = bz0 + t / nbyt, by = y0 / DISCOS_BIN + t % nbyt;
-            const int row = (bz * g.nby + by) * g.nbx + x0 / DISCOS_BIN;
+            const int bz = bz0 + t / nbyt, by = (y0 >> g.lb) + t % nbyt;
+            const int row = (bz * g.nby + by) * g.nbx + (x0 >> g.lb);
             const int st = bin_start[row];
             rstart[t] = st;
             len = bin_start[row + nbxt] - st;

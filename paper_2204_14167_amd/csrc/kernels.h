@@ -146,6 +146,16 @@ struct BatchCfg {   // launch choices (the autotuner's output)
     int interp_direct;  // channels with fewer ions per 2048 cells are interpolated one
                         // thread per ion instead of by staged tiles
     int spread_direct;  // likewise spread one thread per ion with global atomics
+    int lb;             // log2 of the cell-list bin edge in cells (1: 2 cells, 2: 4 cells)
+};
+
+// The cell list's bins and the near field's padded bins of a batch for one bin edge.
+struct BinLayout {
+    bool ok = false;            // every channel is wide enough for the search window
+    int R = 0;                  // near-field search radius in bins
+    int64_t nbins = 0, pbins = 0, nl_entries = 0;
+    int pbin_xblocks = 1;       // x blocks of the padded-bin count (the largest channel's)
+    std::vector<int> bin_off, pbin_off;  // [channels + 1]
 };
 
 struct Batch {
@@ -182,8 +192,10 @@ struct Batch {
     double4* sxyzq;
     int *sid, *ssp, *perm, *ion_bin, *ion_rank, *bin_count, *bin_start, *scan_tmp;
     NearList nl;                   // padded copy of the near field (every channel's bins)
-    int* pbin_off;
-    int pbin_xblocks;  // x blocks of the per-channel padded-bin grid (the largest channel's)                 // [R + 1] first padded bin of each channel (device)
+    int* pbin_off;                 // [R + 1] first padded bin of each channel (device)
+    int pbin_xblocks;  // x blocks of the per-channel padded-bin grid (the largest channel's)
+    int64_t pbins_tot;             // padded bins of the current bin edge
+    BinLayout lay[3];              // by log2 of the bin edge (entries 1 and 2)
     double *rho, *phi, *cprime, *fp;
     double2* spec;
     int* flags;
@@ -315,6 +327,6 @@ int batch_interp(Batch* b, hipStream_t s);
 int batch_near(Batch* b, hipStream_t s);
 int batch_update(Batch* b, double* pos, double* q, int* id, int* sp, hipStream_t s);
 int batch_set_step(Batch* b, uint64_t v, hipStream_t s);
-int near_radius_bins_h(double h, const discos_params* p);
+int near_radius_bins_h(double h, const discos_params* p, int lb);
 
 }  // namespace discos

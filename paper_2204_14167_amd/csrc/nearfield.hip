@@ -25,7 +25,7 @@ struct NearDev {
     int nsp;
 };
 
-static NearDev near_of_h(double h, const discos_params* p) {
+static NearDev near_of_h(double h, const discos_params* p, int lb) {
     NearDev d;
     d.psi = p->psi;
     d.psi2 = p->psi * p->psi;
@@ -39,7 +39,7 @@ static NearDev near_of_h(double h, const discos_params* p) {
     double range = p->psi;
     if (p->lj_on) range = std::max(range, p->lj_range);
     d.rsearch = range;
-    d.R = (int)std::ceil(range / (DISCOS_BIN * h));
+    d.R = (int)std::ceil(range / ((double)(1 << lb) * h));
     d.s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     d.map[0] = p->bc_type_map[0];
@@ -56,11 +56,11 @@ static NearDev near_of_h(double h, const discos_params* p) {
     return d;
 }
 
-static NearDev near_of(const Ctx* c, const discos_params* p) { return near_of_h(c->grid.h, p); }
+static NearDev near_of(const Ctx* c, const discos_params* p) { return near_of_h(c->grid.h, p, c->gd.lb); }
 
 int near_radius_bins(const Ctx* c, const discos_params* p) { return near_of(c, p).R; }
 
-int near_radius_bins_h(double h, const discos_params* p) { return near_of_h(h, p).R; }
+int near_radius_bins_h(double h, const discos_params* p, int lb) { return near_of_h(h, p, lb).R; }
 
 // 1/sqrt(r2) to full FP64 accuracy: hardware estimate plus two Newton steps.
 __device__ __forceinline__ double inv_sqrt(double r2) {
@@ -265,11 +265,17 @@ struct FusedUpdate {
 // of a real bin is entry k of the padded bin.  Only first images are needed: a second
 // reflection lies at least Lz >= 4 h away, beyond every cutoff the pass accepts.
 
-// With nz odd the last real slab is one cell thick, so the image slabs above the upper
-// wall sit one cell off the two-cell bin grid: a window of R slabs around an ion then
-// spans only 2R - 1 cells above the wall, and the upper side gets one image slab more
-// (and the pass searches one slab further up).
-__host__ __device__ __forceinline__ int pad_top(const GridDev& g, int R) { return R + (g.nz & 1); }
+// When nz is not a multiple of the bin edge B, the last real slab is th < B cells thick,
+// and so is its mirror image above the upper wall: the image slabs there sit 2 (B - th)
+// cells below where a slab grid continued through the wall would put them, and a window
+// of R slabs above an ion reaches that much less far.  The upper side then gets
+// ceil(2 (B - th) / B) image slabs more (one with two-cell bins and nz odd), and the
+// pass searches as many slabs further up.
+__host__ __device__ __forceinline__ int pad_top(const GridDev& g, int R) {
+    if (g.lb == 1) return R + (g.nz & 1);
+    const int B = 1 << g.lb, th = g.nz - ((g.nbz - 1) << g.lb);
+    return R + (th >= B ? 0 : (2 * (B - th) + B - 1) / B);
+}
 
 // Real bin (channel-local) whose ions padded bin P holds, or -1 (a mirrored slab that
 // does not exist in a channel thinner than the image layers).
@@ -292,9 +298,9 @@ int64_t near_list_bins(const GridDev& g, int R) {
 
 // Copies per ion: at most two in x and two in y (2R + 1 <= nbx, nby, so no bin is within
 // R of both seams), and in z the ion itself plus one image per wall within the image
-// layers (both walls only when nbz < 2R + 1); sized for R up to 3.
+// layers (both walls only when nbz < R + pad_top); sized for R up to 3.
 int64_t near_list_entries(const GridDev& g, int64_t n) {
-    return std::max<int64_t>(n, 1) * 4 * (g.nbz < 7 ? 3 : 2);
+    return std::max<int64_t>(n, 1) * 4 * (g.nbz < 3 + pad_top(g, 3) ? 3 : 2);
 }
 
 __global__ void pad_count_kernel(GridDev g, int R, int64_t nb, const int* __restrict__ bin_start,
@@ -508,7 +514,7 @@ __device__ __forceinline__ void nf_pairs(const int* col, int m, double xi, doubl
 // Extent in z of padded slab t - R (t = pz - R, channel-local): a real slab, or the
 // mirror image of one beyond a wall; empty (lo > hi) if that slab does not exist.
 __device__ __forceinline__ void slab_extent(const GridDev& g, int t, double& lo, double& hi) {
-    const double Bh = DISCOS_BIN * g.h;
+    const double Bh = bin_edge(g);
     if (t >= 0 && t < g.nbz) {
         lo = t * Bh;
         hi = fmin((t + 1) * Bh, g.Lz);
@@ -536,7 +542,7 @@ __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int b
                                        double& fx, double& fy, double& fz) {
     const int lane = threadIdx.x;
     const double xi = me.x, yi = me.y, zi = me.z, qi = me.w;
-    const double Bh = DISCOS_BIN * g.h;
+    const double Bh = bin_edge(g);
     const double inv_Bh = 1.0 / Bh;
     const double rs2 = P.rsearch * P.rsearch;
     const double r2cut = fmax(P.psi2, P.lj_on ? rs2 * (1.0 + 1e-12) : 0.0);
@@ -547,7 +553,7 @@ __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int b
     int2* const rcol = &sh.runs[0][lane];
     int* const hcol = &sh.hits[0][lane];
     int cnt = 0;
-    const int dz_hi = R + (g.nz & 1);  // one slab more with the offset upper image layers
+    const int dz_hi = pad_top(g, R);  // more slabs up with offset upper image layers
 #pragma unroll 1
     for (int dzb = -R; dzb <= dz_hi; ++dzb) {
         const int t = bz + dzb;
@@ -639,9 +645,9 @@ __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int b
 // binning gave it, for ions inside the channel.
 __device__ __forceinline__ void sorted_bin(const GridDev& g, double x, double y, double z, int& bx,
                                            int& by, int& bz) {
-    bx = min(max((int)floor(x * g.inv_h), 0), g.nx - 1) / DISCOS_BIN;
-    by = min(max((int)floor(y * g.inv_h), 0), g.ny - 1) / DISCOS_BIN;
-    bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) / DISCOS_BIN;
+    bx = min(max((int)floor(x * g.inv_h), 0), g.nx - 1) >> g.lb;
+    by = min(max((int)floor(y * g.inv_h), 0), g.ny - 1) >> g.lb;
+    bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) >> g.lb;
 }
 
 // Order of the pass's blocks within each XCD.  Block L covers ions [L NF_THREADS, ...) of
@@ -698,6 +704,7 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
                   (int)threadIdx.x;
     if (i >= n) return;
     GridDev g = g0;
+    if (!BATCH) g.lb = DISCOS_LB;  // a single channel's bins: a compile-time edge
     const int* pstart = L.start;
     if (BATCH) {
         const int r = ion_rep[i];
@@ -855,12 +862,12 @@ __global__ void step_set_kernel(uint64_t* step, uint64_t v) { *step = v; }
 int batch_near(Batch* b, hipStream_t s) {
     const int n = (int)b->n_tot;
     if (n == 0) return DISCOS_OK;
-    const NearDev P = near_of_h(b->h, &b->p);
+    const NearDev P = near_of_h(b->h, &b->p, b->cfg.lb);
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
     const int nrep = (int)b->reps.size();
     pad_count_batch_kernel<<<dim3(b->pbin_xblocks, std::min(nrep, 65535)), 256, 0, s>>>(
         b->reps_d, nrep, P.R, b->pbin_off, b->bin_start, b->nl.count);
-    scan_counts(b->nl.count, b->nl.bins_cap, b->nl.tmp, b->nl.start, s);
+    scan_counts(b->nl.count, b->pbins_tot, b->nl.tmp, b->nl.start, s);
     const NlOut o{b->nl.xyzq, b->nl.xyzf, b->nl.sp, b->nl.cap, b->flags};
     const int T = b->cfg.ion_block;
     pad_scatter_batch_kernel<<<(n + T - 1) / T, T, 0, s>>>(b->reps_d, b->ion_rep, P.R, n, b->sxyzq,

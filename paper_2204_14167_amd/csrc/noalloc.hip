@@ -100,6 +100,7 @@ extern "C" int discos_spread_charge_noalloc(const discos_grid* grid, int64_t n, 
     g.Lx = grid->nx * grid->h;
     g.Ly = grid->ny * grid->h;
     g.Lz = grid->nz * grid->h;
+    g.lb = DISCOS_LB;
     g.nbx = grid->nx / DISCOS_BIN;
     g.nby = grid->ny / DISCOS_BIN;
     g.nbz = (grid->nz + DISCOS_BIN - 1) / DISCOS_BIN;

@@ -119,6 +119,7 @@ def lib():
         L.discos_batch_destroy.argtypes = [vp]
         L.discos_batch_step.argtypes = [vp, vp, vp, vp, vp, u64, ctypes.c_uint32, vp]
         L.discos_batch_tune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+        L.discos_batch_set_bin.argtypes = [vp, i32]
         L.discos_batch_check.argtypes = [vp]
         L.discos_batch_last_error.argtypes = [vp]
         L.discos_batch_last_error.restype = ctypes.c_char_p
@@ -129,7 +130,7 @@ def lib():
                      "discos_interpolate", "discos_near_field", "discos_step", "discos_check",
                      "discos_profile", "discos_profile_read", "discos_energy_flux",
                      "discos_energy_flux_backward", "discos_batch_create", "discos_batch_destroy",
-                     "discos_batch_step", "discos_batch_tune", "discos_batch_check",
+                     "discos_batch_step", "discos_batch_tune", "discos_batch_set_bin", "discos_batch_check",
                      "discos_set_hydro_kernel", "discos_spread_force_species",
                      "discos_interpolate_vel_species", "discos_profile_stages",
                      "discos_spread_charge_noalloc"):
@@ -509,12 +510,16 @@ class Batch:
                                          int(step), BATCH_GRAPH if graph else 0, _stream()))
 
     def tune(self, pos, q, ids, species):
-        cfg = (ctypes.c_int32 * 7)()
+        cfg = (ctypes.c_int32 * 10)()
         self._rc(lib().discos_batch_tune(self.handle, _ptr(pos), _ptr(q), _ptr(ids), _ptr(species),
                                          cfg, _stream()))
         return dict(spread_tile=cfg[0], spread_blocks=cfg[1], interp_tile=cfg[2],
                     interp_blocks=cfg[3], ion_block=cfg[4], interp_direct=cfg[5],
-                    spread_direct=cfg[6])
+                    spread_direct=cfg[6], bin=cfg[7], bin_us={2: cfg[8], 4: cfg[9]})
+
+    def set_bin(self, bin_cells):
+        """Cell-list bin edge in cells (2 or 4), as the autotuner chooses it."""
+        self._rc(lib().discos_batch_set_bin(self.handle, int(bin_cells)))
 
     def check(self):
         self._rc(lib().discos_batch_check(self.handle))

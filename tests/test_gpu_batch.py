@@ -134,6 +134,7 @@ def test_tuning_keeps_results():
     assert cfg["ion_block"] in (64, 128, 256)
     assert cfg["interp_direct"] in (0, 8, 24, 64, 1 << 30)
     assert cfg["spread_direct"] in (0, 8, 24, 64, 1 << 30)
+    assert cfg["bin"] in (2, 4)
     # tuning does not move the ions
     assert np.array_equal(host(arrays[0]), before[0])
     b.step(*arrays, step=1, graph=True)
@@ -243,3 +244,30 @@ def test_batch_z_solve_paths(walls):
         e = np.linalg.norm(min_image(a - c, L)) / np.linalg.norm(min_image(c - pos[:, lo:hi], L))
         log(f"  vs single context rel {e:.3e}")
         assert e < 1e-12
+
+
+@pytest.mark.parametrize("walls", [((workloads.DIRICHLET, workloads.DIRICHLET), (1.0, 0.0)),
+                                   ((workloads.NEUMANN, workloads.NEUMANN), (0.0, 0.0))])
+def test_batch_bin_edges(walls):
+    """Cell-list bins of 4 cells (near-field search radius 1 bin for psi = 4 h) and of 2
+    cells give the oracle's step on every channel.  The heights leave the last slab 1, 2, 3
+    or 4 cells thick, so the image slabs above the upper wall sit off the slab grid by 6,
+    4, 2 or 0 cells (two, one or no extra image slabs); widths of 16 cells give 4 bins of
+    4 cells, the narrowest that a 3-bin search window allows."""
+    from paper_2204_14167_amd import discos
+    shapes = [(16, 16, 13, 160), (16, 32, 14, 200), (32, 16, 15, 240), (16, 16, 16, 180),
+              (32, 32, 33, 600), (16, 16, 6, 80), (64, 16, 22, 400)]
+    b, reps, pos, q, ids, sp = _custom_batch(shapes, walls[0], walls[1], seed=808)
+    for bin_cells in (4, 2):
+        b.set_bin(bin_cells)
+        arrays = (dev(pos), dev(q), dev(ids), dev(sp))
+        before = _host_all(arrays)
+        b.step(*arrays, step=5)
+        b.check()
+        after = _host_all(arrays)
+        for r in range(len(reps)):
+            err = _oracle_check(reps, b, before, after, r, 5, p=_custom_params(reps[r]))
+            log(f"bin {bin_cells}, {walls[0]} channel {shapes[r]} vs oracle rel {err:.3e}")
+            assert err < TOL
+    with pytest.raises(discos.DiscosError, match="2 or 4"):
+        b.set_bin(3)
