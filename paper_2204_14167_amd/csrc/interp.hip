@@ -119,7 +119,7 @@ __device__ __forceinline__ void direct_sums(const GridDev& g, const WallDev& w,
     }
 }
 
-template <int TX, int TY, int TZ>
+template <int TX, int TY, int TZ, bool EARLY = false>
 __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, int op,
                                             const double4* __restrict__ sxyzq,
                                             const int* __restrict__ bin_start,
@@ -136,6 +136,28 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
     const int nbxt = tx >> g.lb, nbyt = ty >> g.lb;
     const int bz0 = z0 >> g.lb, bz1 = (z0 + tz - 1) >> g.lb;
     const int nrows = (bz1 - bz0 + 1) * nbyt;
+    constexpr int PLANE = LX * LY;
+    const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
+    const size_t pstride = (size_t)g.nx * g.ny;
+    // EARLY (a single channel, where nearly every tile holds ions): an inner tile's phi
+    // window is loaded into registers before the row scan, so that its loads and the
+    // bin-start loads are in flight together; the values go to LDS after the scan (an
+    // empty tile has then read its window for nothing)
+    constexpr int NCOL = (PLANE + IT_THREADS - 1) / IT_THREADS, LZW = TZ + IT_H;
+    double early[EARLY ? NCOL : 1][EARLY ? LZW : 1];
+    if (EARLY && inner) {
+#pragma unroll
+        for (int k = 0; k < NCOL; ++k) {
+            const int pp = threadIdx.x + k * IT_THREADS;
+            const int lx = pp % LX, ly = pp / LX;
+            const bool in = pp < PLANE && lx < lxn && ly < lyn;
+            const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+            const double* src = phi + (size_t)(z0 - 2) * pstride + (size_t)j * g.nx + i;
+#pragma unroll
+            for (int u = 0; u < LZW; ++u)
+                early[k][u] = (in && u < lzn) ? src[(size_t)u * pstride] : 0.0;
+        }
+    }
     {
         // thread t < nrows owns row t; a workgroup scan of the row lengths gives rpre
         int len = 0;
@@ -156,13 +178,21 @@ __device__ __forceinline__ void interp_tile(const GridDev& g, const WallDev& w, 
     const int total = rpre[nrows];
     if (total == 0) return;  // the same for the whole workgroup
     const bool direct = total <= IT_DIRECT;
-    if (!direct) {
+    if (EARLY && inner) {
+#pragma unroll
+        for (int k = 0; k < NCOL; ++k) {
+            const int pp = threadIdx.x + k * IT_THREADS;
+            if (pp < PLANE) {
+#pragma unroll
+                for (int u = 0; u < LZW; ++u)
+                    if (u < lzn) tile[u * PLANE + pp] = early[k][u];
+            }
+        }
+        __syncthreads();
+    } else if (!direct) {
         // phi on cells [x0-2, x0+tx+3) x [y0-2, y0+ty+3) x [z0-2, z0+tz+3), ghosts filled:
         // each thread takes whole z columns of the window (no index divisions per element),
         // with IT_UNROLL loads in flight before the LDS stores
-        constexpr int PLANE = LX * LY;
-        const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
-        const size_t pstride = (size_t)g.nx * g.ny;
         for (int pp = threadIdx.x; pp < PLANE; pp += IT_THREADS) {
             const int lx = pp % LX, ly = pp / LX;
             const bool in_xy = lx < lxn && ly < lyn;
@@ -257,9 +287,9 @@ interp_es_kernel(GridDev g, WallDev w, int op, const double4* __restrict__ sxyzq
     const int tx = min(IT_TX, g.nx), ty = min(IT_TY, g.ny);
     int bx, by, bz;
     xcd_block3(bx, by, bz);
-    interp_tile<IT_TX, IT_TY, IT_TZ>(g, w, op, sxyzq, bin_start, perm, phi, ex0, ex1, ex2, out, stride,
-                                     scatter, flags, bx * tx, by * ty, bz * IT_TZ, tile, rstart, rpre,
-                                     scan);
+    interp_tile<IT_TX, IT_TY, IT_TZ, true>(g, w, op, sxyzq, bin_start, perm, phi, ex0, ex1, ex2,
+                                           out, stride, scatter, flags, bx * tx, by * ty, bz * IT_TZ,
+                                           tile, rstart, rpre, scan);
 }
 
 // Batched: forces q (E^P + E_ext) of every channel's ions, in cell-list order; the

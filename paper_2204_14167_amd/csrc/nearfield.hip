@@ -390,6 +390,15 @@ __device__ __forceinline__ void pad_scatter_one(const GridDev& g, int R, int b, 
     }
 }
 
+// The cell-list bin of a sorted ion (x, y already reduced into [0, L]): the bin the
+// binning gave it, for ions inside the channel.
+__device__ __forceinline__ void sorted_bin(const GridDev& g, double x, double y, double z, int& bx,
+                                           int& by, int& bz) {
+    bx = min(max((int)floor(x * g.inv_h), 0), g.nx - 1) >> g.lb;
+    by = min(max((int)floor(y * g.inv_h), 0), g.ny - 1) >> g.lb;
+    bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) >> g.lb;
+}
+
 __global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double s_hi,
                                    const int* map_lo, const int* map_hi,
                                    const double4* __restrict__ sxyzq, const int* __restrict__ ssp,
@@ -398,9 +407,22 @@ __global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double 
                                    const int* __restrict__ pstart, NlOut o) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int b = ion_bin[perm[i]];
+    g.lb = DISCOS_LB;  // a single channel's bins: a compile-time edge
+    // the bin of an ion inside the channel follows from its sorted position (no dependent
+    // loads through perm and ion_bin): the binning computed it from the same reduced
+    // coordinates.  Others, and any slot outside that bin's range, take the bin the
+    // binning recorded.
+    const double4 a = sxyzq[i];
+    int b = -1;
+    if (pos_ok(g, a.x, a.y, a.z)) {
+        int bx, by, bz;
+        sorted_bin(g, a.x, a.y, a.z, bx, by, bz);
+        b = (bz * g.nby + by) * g.nbx + bx;
+        if (i < bin_start[b] || i >= bin_start[b + 1]) b = -1;
+    }
+    if (b < 0) b = ion_bin[perm[i]];
     const int* map[2] = {map_lo, map_hi};
-    pad_scatter_one(g, R, b, i - bin_start[b], sxyzq[i], ssp ? ssp[i] : 0, s_lo, s_hi, map, pstart, o);
+    pad_scatter_one(g, R, b, i - bin_start[b], a, ssp ? ssp[i] : 0, s_lo, s_hi, map, pstart, o);
 }
 
 __global__ void pad_scatter_batch_kernel(const RepDev* __restrict__ reps,
@@ -641,14 +663,6 @@ __device__ __forceinline__ void nf_ion(const GridDev& g, const NearDev& P, int b
     if (P.wall_on) fz += -du93(zi, P) + du93(g.Lz - zi, P);
 }
 
-// The cell-list bin of a sorted ion (x, y already reduced into [0, L]): the bin the
-// binning gave it, for ions inside the channel.
-__device__ __forceinline__ void sorted_bin(const GridDev& g, double x, double y, double z, int& bx,
-                                           int& by, int& bz) {
-    bx = min(max((int)floor(x * g.inv_h), 0), g.nx - 1) >> g.lb;
-    by = min(max((int)floor(y * g.inv_h), 0), g.ny - 1) >> g.lb;
-    bz = min(max((int)floor(z * g.inv_h), 0), g.nz - 1) >> g.lb;
-}
 
 // Order of the pass's blocks within each XCD.  Block L covers ions [L NF_THREADS, ...) of
 // the cell list, whose bins run z-slab by z-slab, so the blocks form about T = nbz rows

@@ -10,9 +10,13 @@
 
 namespace discos {
 
+// A single channel's tiles: 16 x 16 x 32 cells (64 KB of LDS) with 512 threads; the tiles
+// of a batch: 8^3 or 16^3 with 256 threads.
 #define SP_TX 16
 #define SP_TY 16
-#define SP_TZ 16
+#define SP_TZ 32
+#define SP_THREADS_ONE 512
+#define SP_MAXR_ONE 512
 #define SP_THREADS 256
 #define SP_MAXR 256
 
@@ -29,23 +33,25 @@ __device__ __forceinline__ int find_range(const int* rpre, int nr, int f) {
     return lo;
 }
 
-// One tile [x0, x0 + T) x [y0, y0 + T) x [z0, z0 + T) (clipped to the grid): gather the
-// ions of the tile and its halo, accumulate in LDS, store once.  acc holds T^3 doubles.
-template <int T>
+// One tile [x0, x0 + T) x [y0, y0 + T) x [z0, z0 + TZ) (clipped to the grid): gather the
+// ions of the tile and its halo, accumulate in LDS, store once.  acc holds T^2 TZ doubles.
+// MIXED: a wall may have a per-column type map, whose fold sign is then looked up per
+// node; with uniform walls (MIXED = false) the fold sign is one factor per layer.
+template <int T, bool MIXED = false, int TZ = T, int MAXR = SP_MAXR>
 __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __restrict__ sxyzq,
                                             const int* __restrict__ bin_start, double sign_lo,
                                             double sign_hi, int add_bc, const WallDev& wall,
                                             double* __restrict__ out, int x0, int y0, int z0,
                                             double* acc, int* rstart, int* rpre, int* scan,
                                             int* __restrict__ flags, bool gather = true) {
-    static_assert(tile_rows_bound(T, T, 2, 2) <= SP_MAXR, "spread tile rows exceed SP_MAXR");
+    static_assert(tile_rows_bound(T, TZ, 2, 2) <= MAXR, "spread tile rows exceed MAXR");
     const int tx = min(T, g.nx), ty = min(T, g.ny);
-    const int tz = min(T, g.nz - z0);
+    const int tz = min(TZ, g.nz - z0);
     const int ncell = tx * ty * tz;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) acc[k] = 0.0;
     int nr = 1, total = 0;
     if (gather) {  // else the tile stores its wall terms only (ions added by the caller)
-        nr = tile_ranges<SP_MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan, flags);
+        nr = tile_ranges<MAXR>(g, bin_start, x0, y0, z0, tx, ty, tz, rstart, rpre, scan, flags);
         total = rpre[nr];
     } else {
         __syncthreads();  // acc cleared
@@ -86,11 +92,11 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
             if (kz < 0) {
                 kz = -1 - kz;
                 sgn = sign_lo;
-                fmap = wall.map[0];
+                if (MIXED) fmap = wall.map[0];
             } else if (kz >= g.nz) {
                 kz = 2 * g.nz - 1 - kz;
                 sgn = sign_hi;
-                fmap = wall.map[1];
+                if (MIXED) fmap = wall.map[1];
             }
             const int lz = kz - z0;
             if (lz < 0 || lz >= tz) continue;
@@ -103,8 +109,9 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
                 for (int a = 0; a < 4; ++a) {
                     if (lxs[a] >= tx) continue;
                     double v = wyz * wx[a];
-                    if (fmap && fmap[(size_t)((iy0 + b) & (g.ny - 1)) * g.nx + ((ix0 + a) & (g.nx - 1))] ==
-                                    DISCOS_BC_DIRICHLET)
+                    if (MIXED && fmap &&
+                        fmap[(size_t)((iy0 + b) & (g.ny - 1)) * g.nx + ((ix0 + a) & (g.nx - 1))] ==
+                            DISCOS_BC_DIRICHLET)
                         v = -v;
                     atomicAdd(&acc[(lz * ty + lys[b]) * tx + lxs[a]], v);
                 }
@@ -136,17 +143,18 @@ __device__ __forceinline__ void spread_tile(const GridDev& g, const double4* __r
         store(tx, ty);
 }
 
-__global__ void __launch_bounds__(SP_THREADS)
+template <bool MIXED>
+__global__ void __launch_bounds__(SP_THREADS_ONE)
 spread_charge_kernel(GridDev g, const double4* __restrict__ sxyzq, const int* __restrict__ bin_start,
                      double sign_lo, double sign_hi, int add_bc, WallDev wall,
                      double* __restrict__ out, int* __restrict__ flags) {
     __shared__ double acc[SP_TX * SP_TY * SP_TZ];
-    __shared__ int rstart[SP_MAXR], rpre[SP_MAXR + 1], scan[SP_THREADS];
+    __shared__ int rstart[SP_MAXR_ONE], rpre[SP_MAXR_ONE + 1], scan[SP_THREADS_ONE];
     const int tx = min(SP_TX, g.nx), ty = min(SP_TY, g.ny);
     int bx, by, bz;
     xcd_block3(bx, by, bz);
-    spread_tile<SP_TX>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, bx * tx, by * ty,
-                       bz * SP_TZ, acc, rstart, rpre, scan, flags);
+    spread_tile<SP_TX, MIXED, SP_TZ, SP_MAXR_ONE>(g, sxyzq, bin_start, sign_lo, sign_hi, add_bc, wall, out, bx * tx,
+                              by * ty, bz * SP_TZ, acc, rstart, rpre, scan, flags);
 }
 
 // Batched: a persistent grid walks the (channel, tile) tasks; each channel's bins,
@@ -223,9 +231,13 @@ int spread_charge_sorted(Ctx* c, const discos_params* p, int add_bc, double* out
     dim3 grid(g.nx / tx, g.ny / ty, (g.nz + SP_TZ - 1) / SP_TZ);
     const double s_lo = p->bc_type[0] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
     const double s_hi = p->bc_type[1] == DISCOS_BC_DIRICHLET ? -1.0 : 1.0;
-    spread_charge_kernel<<<grid, SP_THREADS, 0, s>>>(g, c->sxyzq, c->bin_start,
-                                                     s_lo, s_hi, add_bc, wall_of(p), out,
-                                                     c->flags);
+    const WallDev w = wall_of(p);
+    if (w.map[0] || w.map[1])
+        spread_charge_kernel<true><<<grid, SP_THREADS_ONE, 0, s>>>(g, c->sxyzq, c->bin_start, s_lo, s_hi,
+                                                               add_bc, w, out, c->flags);
+    else
+        spread_charge_kernel<false><<<grid, SP_THREADS_ONE, 0, s>>>(g, c->sxyzq, c->bin_start, s_lo, s_hi,
+                                                                add_bc, w, out, c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
