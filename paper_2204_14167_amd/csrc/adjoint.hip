@@ -296,6 +296,29 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     static_assert((GT_TZ / DISCOS_BIN) * (GT_TY / DISCOS_BIN) <= GT_MAXR && GT_MAXR <= GT_THREADS,
                   "gradient tile rows exceed GT_MAXR");
     const int nrows = (bz1 - bz0 + 1) * nbyt;
+    const int ne = LX * LY * lzn;
+    const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
+    // an inner tile's window (every element of this thread) is loaded before the row scan,
+    // so that its loads and the bin-start loads are in flight together
+    constexpr int NPT = (LX * LY * LZ + GT_THREADS - 1) / GT_THREADS;
+    double er[NPT], ep[NPT];
+    if (inner) {
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int e = threadIdx.x + u * GT_THREADS;
+            const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+            const int i = (x0 - 2 + lx) & (g.nx - 1), j = (y0 - 2 + ly) & (g.ny - 1);
+            const int il = (i - 1) & (g.nx - 1);
+            er[u] = 0.0;
+            ep[u] = 0.0;
+            if (e < ne && lx < lxn && ly < lyn) {
+                const size_t row = ((size_t)(z0 - 2 + lz) * g.ny + j) * g.nx;
+                const double pv = phi[row + i];
+                er[u] = udv * pv + mu[row + i];
+                ep[u] = pv - phi[row + il];
+            }
+        }
+    }
     {
         int len = 0;
         const int t = threadIdx.x;
@@ -315,9 +338,17 @@ flux_energy_grad_kernel(GridDev g, WallDev wl, FluxDev f, const double4* __restr
     if (rpre[nrows] == 0) return;  // the same for the whole workgroup
     // rbar (homogeneous folds) and phi (wall ghosts) on the tile and its halo; GT_UNROLL
     // elements per thread are loaded before the first LDS store
-    const int ne = LX * LY * lzn;
-    const bool inner = z0 >= 2 && z0 + tz + 3 <= g.nz;  // no ghost layer in the window
-    for (int e0 = threadIdx.x; e0 < ne; e0 += GT_UNROLL * GT_THREADS) {
+    if (inner) {
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int e = threadIdx.x + u * GT_THREADS;
+            if (e < ne) {
+                trb[e] = er[u];
+                tph[e] = ep[u];
+            }
+        }
+    }
+    for (int e0 = threadIdx.x; !inner && e0 < ne; e0 += GT_UNROLL * GT_THREADS) {
         double vr[GT_UNROLL], vp[GT_UNROLL];
 #pragma unroll
         for (int u = 0; u < GT_UNROLL; ++u) {
