@@ -17,25 +17,49 @@ __global__ void fill_f64_kernel(double* __restrict__ a, int64_t n, double v) {
         a[i] = v;
 }
 
-// Bin of ion i (bins of its channel start at bin_off) and its rank inside the bin
-// (arrival order of the atomic).
-__device__ __forceinline__ void bin_count_one(const GridDev& g, int bin_off, int i,
+// Bin of ion i (bins of its channel start at bin_off) and its rank inside the bin.
+// Ions of consecutive lanes that share a bin (the ions of a step arrive in the previous
+// step's cell order, so most neighbours in a bin are adjacent) take their ranks from one
+// atomic of the first lane of their run: rank = the run's base + the lane's place in it.
+// The ranks of a bin are distinct and cover 0 .. count - 1 whatever the arrival order.
+// Every lane of the wavefront calls this (active = false for lanes past the last ion).
+__device__ __forceinline__ void bin_count_one(const GridDev& g, int bin_off, int i, bool active,
                                               const double* __restrict__ x,
                                               const double* __restrict__ y,
                                               const double* __restrict__ z,
                                               int* __restrict__ count, int* __restrict__ ion_bin,
                                               int* __restrict__ ion_rank, int* __restrict__ flags) {
-    const double xi = x[i], yi = y[i], zi = z[i];
-    if (!pos_ok(g, xi, yi, zi))
-        set_flag(flags, (isfinite(xi) && isfinite(yi) && isfinite(zi)) ? DISCOS_FLAG_OUT_OF_DOMAIN
-                                                                      : DISCOS_FLAG_NONFINITE);
-    int bx, by, bz;
-    const int b = (isfinite(xi) && isfinite(yi) && isfinite(zi) && fabs(xi) < 1e12 * g.h &&
-                   fabs(yi) < 1e12 * g.h)
-                      ? bin_of(g, xi, yi, zi, bx, by, bz)
-                      : 0;
-    ion_bin[i] = bin_off + b;
-    ion_rank[i] = atomicAdd(&count[bin_off + b], 1);
+    int b = -1;
+    if (active) {
+        const double xi = x[i], yi = y[i], zi = z[i];
+        if (!pos_ok(g, xi, yi, zi))
+            set_flag(flags, (isfinite(xi) && isfinite(yi) && isfinite(zi))
+                                ? DISCOS_FLAG_OUT_OF_DOMAIN
+                                : DISCOS_FLAG_NONFINITE);
+        int bx, by, bz;
+        b = bin_off + ((isfinite(xi) && isfinite(yi) && isfinite(zi) && fabs(xi) < 1e12 * g.h &&
+                        fabs(yi) < 1e12 * g.h)
+                           ? bin_of(g, xi, yi, zi, bx, by, bz)
+                           : 0);
+    }
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(b, 1, 64);
+    const bool head = active && (lane == 0 || prev != b);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long live = __ballot(active);
+    // first lane of this lane's run, and the run's length (up to the next head or the last
+    // active lane)
+    const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    const int h = active ? 63 - __clzll(upto) : 0;
+    const unsigned long long above = heads & ~((2ull << h) - 1) & (h == 63 ? 0ull : ~0ull);
+    const int end = above ? __ffsll(above) - 1 : 64 - __clzll(live);
+    int base = 0;
+    if (head) base = atomicAdd(&count[b], end - h);
+    base = __shfl(base, h, 64);
+    if (active) {
+        ion_bin[i] = b;
+        ion_rank[i] = base + (lane - h);
+    }
 }
 
 __global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
@@ -43,8 +67,7 @@ __global__ void bin_count_kernel(GridDev g, int n, const double* __restrict__ x,
                                  int* __restrict__ count, int* __restrict__ ion_bin,
                                  int* __restrict__ ion_rank, int* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bin_count_one(g, 0, i, x, y, z, count, ion_bin, ion_rank, flags);
+    bin_count_one(g, 0, i, i < n, x, y, z, count, ion_bin, ion_rank, flags);
 }
 
 __global__ void bin_count_batch_kernel(const RepDev* __restrict__ reps, const int* __restrict__ ion_rep,
@@ -53,9 +76,9 @@ __global__ void bin_count_batch_kernel(const RepDev* __restrict__ reps, const in
                                        int* __restrict__ count, int* __restrict__ ion_bin,
                                        int* __restrict__ ion_rank, int* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const RepDev& R = reps[ion_rep[i]];
-    bin_count_one(R.g, R.bin_off, i, x, y, z, count, ion_bin, ion_rank, flags);
+    const bool active = i < n;
+    const int r = active ? ion_rep[i] : 0;
+    bin_count_one(reps[r].g, reps[r].bin_off, i, active, x, y, z, count, ion_bin, ion_rank, flags);
 }
 
 // Exclusive scan of `count` (nb entries) into `start` (nb + 1 entries) in two launches:
@@ -145,6 +168,7 @@ __global__ void bin_scatter_batch_kernel(const RepDev* __restrict__ reps,
     if (i >= n) return;
     const GridDev& g = reps[ion_rep[i]].g;
     const int d = start[ion_bin[i]] + ion_rank[i];
+    if (d < 0 || d >= n) return;  // ranks are a permutation of each bin's slots
     double xi = x[i], yi = y[i];
     if (isfinite(xi) && isfinite(yi)) {
         xi = reduce_periodic(xi, g.Lx);
@@ -169,6 +193,7 @@ __global__ void bin_scatter_kernel(int n, const int* __restrict__ ion_bin,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int d = start[ion_bin[i]] + ion_rank[i];
+    if (d < 0 || d >= n) return;  // ranks are a permutation of each bin's slots
     double xi = x[i], yi = y[i];
     if (isfinite(xi) && isfinite(yi)) {
         xi = reduce_periodic(xi, g.Lx);

@@ -421,6 +421,10 @@ __global__ void pad_scatter_kernel(GridDev g, int R, int n, double s_lo, double 
         if (i < bin_start[b] || i >= bin_start[b + 1]) b = -1;
     }
     if (b < 0) b = ion_bin[perm[i]];
+    if (i < bin_start[b] || i >= bin_start[b + 1]) {  // an inconsistent cell list
+        set_flag(o.flags, DISCOS_FLAG_CAPACITY);
+        return;
+    }
     const int* map[2] = {map_lo, map_hi};
     pad_scatter_one(g, R, b, i - bin_start[b], a, ssp ? ssp[i] : 0, s_lo, s_hi, map, pstart, o);
 }
