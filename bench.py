@@ -609,7 +609,13 @@ def main():
         "stages": per_stage,
         "stages_note": (f"per-stage times from {PROFILED_STEPS} untimed steps with an event at every "
                         "stage boundary; the timed steps record only the dominant stage's two "
-                        "events (its live launch time in roofline)"),
+                        "events (its live launch time in roofline).  The near field (near_list, "
+                        "near_field) runs on a second stream beside spread .. interp, so the "
+                        "stages overlap and do not add up to ms_per_step; join_wait is the time "
+                        "the grid stages ran past the near-field pass, update the dry update "
+                        "from both forces"),
+        "dry_tail": {"join_wait_ms": round(stages.get("interp_hy", 0.0), 5),
+                     "update_ms": round(stages.get("update", 0.0), 5)},
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "adjoint": adj,
         "batched": batched,

@@ -309,6 +309,10 @@ int discos_near_field(discos_ctx* ctx, int64_t n, const double* pos, const doubl
  * W ~ N(0,1) from Philox4x32-10 with counter (id, step, 1, pair) and key `seed`;
  * ions crossing a wall are reflected and x, y are wrapped into [0, L).
  * The ion arrays are PERMUTED in place into cell order (ids follow their ions).
+ * In a dry step the near-field pass runs on a stream the context owns, forked from
+ * `stream` after the cell list and joined back before the update (events only, so the
+ * step can be captured into a graph from `stream`); nothing is left running when the
+ * step's work on `stream` is done.
  */
 #define DISCOS_STEP_DRY 0
 /* DISCOS_STEP_WET: the forces as in the dry step, then stage 3 (S^hy F, fluctuating
@@ -435,9 +439,12 @@ const char* discos_batch_last_error(discos_batch* b);
  * inverse y-FFT, inverse x-FFT, interpolation, the near field's padded cell list, the
  * near-field pass (candidates, pair forces, wall force, and in a dry step the update),
  * S^hy, Stokes solve, the two J^hy passes with the predictor, the update of a wet step;
- * the hydrodynamic stages and the last read 0 in dry steps; with walls of mixed type the
- * whole iterative Poisson solve is timed as the x-FFT stage) and sets *count (0 when no step was
- * recorded).  Each recorded event costs the stream a few microseconds.
+ * with walls of mixed type the whole iterative Poisson solve is timed as the x-FFT stage)
+ * and sets *count (0 when no step was recorded).  In a dry step the padded list and the
+ * pass run on the context's second stream beside the spread .. interpolation stages (the
+ * stages overlap), S^hy and the Stokes solve read 0, the J^hy stage reads the time the
+ * grid stages ran past the end of the pass, and the last stage the dry update.  Each
+ * recorded event costs the stream a few microseconds.
  */
 #define DISCOS_NSTAGE 14
 int discos_profile(discos_ctx* ctx, int enable);

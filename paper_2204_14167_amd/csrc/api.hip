@@ -246,6 +246,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     size_t bytes = 0;
     bytes += carve_bytes(nm, sizeof(double4));         // sxyzq
     bytes += carve_bytes(3 * nm, sizeof(double));      // fp
+    bytes += carve_bytes(3 * nm, sizeof(double));      // fnear
     bytes += 5 * carve_bytes(nm, sizeof(int));         // sid ssp perm ion_bin ion_rank
     bytes += carve_bytes(c->nbins, sizeof(int));
     bytes += carve_bytes(c->nbins + 1, sizeof(int));
@@ -276,6 +277,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     char* cur = static_cast<char*>(c->pool);
     c->sxyzq = carve<double4>(cur, nm);
     c->fp = carve<double>(cur, 3 * nm);
+    c->fnear = carve<double>(cur, 3 * nm);
     c->sid = carve<int>(cur, nm);
     c->ssp = carve<int>(cur, nm);
     c->perm = carve<int>(cur, nm);
@@ -386,6 +388,14 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->prof_marks = 0;
     c->prof_steps = 0;
     c->ev = nullptr;
+    // the dry step's near field runs on a stream of its own beside the grid stages (default
+    // priority; fork and join by events, so the step is also capturable into a graph)
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)discos_destroy(c);
+        return DISCOS_E_HIP;
+    }
     *out = c;
     return DISCOS_OK;
 }
@@ -399,6 +409,13 @@ int discos_destroy(discos_ctx* c) {
             ok = (hipEventDestroy(c->ev[k]) == hipSuccess) && ok;
         delete[] c->ev;
     }
+    if (c->ev_side) {
+        for (size_t k = 0; k < PROF_MAX; ++k) ok = (hipEventDestroy(c->ev_side[k]) == hipSuccess) && ok;
+        delete[] c->ev_side;
+    }
+    if (c->ev_fork) ok = (hipEventDestroy(c->ev_fork) == hipSuccess) && ok;
+    if (c->ev_join) ok = (hipEventDestroy(c->ev_join) == hipSuccess) && ok;
+    if (c->side) ok = (hipStreamDestroy(c->side) == hipSuccess) && ok;
     ok = (hipFree(c->pool) == hipSuccess) && ok;
     if (c->hydro) ok = (hipFree(c->hpool) == hipSuccess) && ok;
     ok = discos::release_dense_capacitance(c) && ok;
@@ -628,6 +645,24 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     rc = discos::build_cell_list(c, ni, pos, pos + n, pos + 2 * n, ions->q, ions->id,
                                  ions->species, s);
     discos::stage_mark(c, 1, s);
+    // a dry step: the near field (which needs only the cell list) runs on the side stream
+    // while this stream spreads, solves and interpolates; the update then adds the two
+    // forces.  Stage marks: the padded list opens on the side stream, which also closes it
+    // and the pass (and the two hydrodynamic stages after it, empty); this stream closes
+    // the interpolation, then the join (stage 12: the time the grid stages ran past the
+    // pass) and the update (stage 13).
+    const bool beside = !wet && ni > 0 && !rc;
+    if (beside) {
+        if (hipEventRecord(c->ev_fork, s) != hipSuccess ||
+            hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess)
+            rc = DISCOS_E_HIP;
+        discos::stage_open_side(c, 8, c->side);
+        if (!rc) rc = discos::near_field_sorted(c, ni, p, c->fnear, c->n_max, 0, c->side, 9,
+                                                nullptr, true);
+        discos::stage_mark(c, 11, c->side);
+        discos::stage_mark(c, 12, c->side);
+        if (!rc && hipEventRecord(c->ev_join, c->side) != hipSuccess) rc = DISCOS_E_HIP;
+    }
     if (!rc) rc = discos::spread_charge_sorted(c, p, 1, c->rho, s);
     discos::stage_mark(c, 2, s);
     if (!rc) rc = discos::solve_poisson(c, c->rho, p, c->phi, s, 3);
@@ -636,7 +671,12 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     // complete the forces in place: fp (grid + applied field) += near field + wall (+ LJ);
     // in a dry step the same pass applies the update from the complete forces
     discos::DryStepOut dry_out{step, pos, ions->q, ions->id, ions->species};
-    if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9,
+    if (beside) {
+        if (!rc && hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess) rc = DISCOS_E_HIP;
+        discos::stage_mark(c, 13, s);
+        if (!rc) rc = discos::update_sorted(c, ni, p, step, nullptr, pos, ions->q, ions->id,
+                                            ions->species, s, c->fnear);
+    } else if (!rc && ni > 0) rc = discos::near_field_sorted(c, ni, p, c->fp, c->n_max, 0, s, 9,
                                                       wet ? nullptr : &dry_out);
     else {
         discos::stage_mark(c, 9, s);
@@ -659,7 +699,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
         if (!rc) rc = discos::midpoint_velocity(c, ni, c->hvel, p->dt, s, 1);
         discos::stage_mark(c, 13, s);
         vwet = c->hvi;
-    } else {
+    } else if (!beside) {
         discos::stage_mark(c, 11, s);
         discos::stage_mark(c, 12, s);
         discos::stage_mark(c, 13, s);
@@ -732,7 +772,12 @@ int discos_profile_stages(discos_ctx* c, uint32_t stages) {
         if (!c->ev) return fail(c, DISCOS_E_HIP, "event table");
         for (size_t k = 0; k < ne; ++k)
             if (hipEventCreate(&c->ev[k]) != hipSuccess) return fail(c, DISCOS_E_HIP, "event create");
+        c->ev_side = new (std::nothrow) hipEvent_t[PROF_MAX];
+        if (!c->ev_side) return fail(c, DISCOS_E_HIP, "event table");
+        for (size_t k = 0; k < PROF_MAX; ++k)
+            if (hipEventCreate(&c->ev_side[k]) != hipSuccess) return fail(c, DISCOS_E_HIP, "event create");
     }
+    c->prof_side.assign(PROF_MAX, 0);
     c->profile = enable ? 1 : 0;
     c->prof_stages = stages;
     c->prof_marks = stages | (stages << 1);
@@ -756,8 +801,10 @@ int discos_profile_read(discos_ctx* c, double* ms, int* count) {
         for (int k = 0; k < DISCOS_NSTAGE; ++k) {
             if (!((c->prof_stages >> k) & 1u)) continue;
             float t = 0.0f;
-            if (hipEventElapsedTime(&t, c->ev[(size_t)st * row + k], c->ev[(size_t)st * row + k + 1]) !=
-                hipSuccess)
+            // a stage that ran on the side stream opened there
+            const hipEvent_t open = (k == 8 && c->prof_side[st]) ? c->ev_side[st]
+                                                                  : c->ev[(size_t)st * row + k];
+            if (hipEventElapsedTime(&t, open, c->ev[(size_t)st * row + k + 1]) != hipSuccess)
                 return fail(c, DISCOS_E_HIP, "event elapsed");
             ms[k] += t / ns;
         }

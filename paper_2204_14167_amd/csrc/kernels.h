@@ -45,6 +45,9 @@ struct Ctx {
     double* cprime;  // z-solve pivots [nz][nmode] (or Thomas scratch when nz > 128)
     int zg_key;      // wall types the pivots in cprime were computed for (-1: none)
     double* fp;      // [3][n_max] per-ion forces in cell-list order
+    double* fnear;   // [3][n_max] near-field forces of a dry step computed beside the grid stages
+    hipStream_t side = nullptr;                      // the near field's stream in a dry step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // the cell list is built / the pass is done
     double2 *tw_x, *tw_y;
     NearList nl;     // the near-field pass's padded copy of the cell list
     // walls of mixed type (a capacitance solve on the wall layers): pcg, [2][ncell], the
@@ -113,6 +116,10 @@ struct Ctx {
     uint32_t prof_marks;   // events recorded: both bounds of every timed stage
     int prof_steps;
     hipEvent_t* ev;
+    // a dry step whose near field ran on the side stream: the event that opened its
+    // padded-list stage there (one per profiled step), and which steps did
+    hipEvent_t* ev_side = nullptr;
+    std::vector<char> prof_side;
 };
 
 #define PROF_MAX 512
@@ -220,6 +227,15 @@ inline void stage_mark(Ctx* c, int k, hipStream_t s) {
         (void)hipEventRecord(c->ev[(size_t)c->prof_steps * (DISCOS_NSTAGE + 1) + k], s);
 }
 
+// Record the opening of stage k (the padded list) on the side stream s of the current
+// profiled step, whose closing and the earlier stages' events are recorded elsewhere.
+inline void stage_open_side(Ctx* c, int k, hipStream_t s) {
+    if (c->profile && c->prof_steps < PROF_MAX && ((c->prof_marks >> k) & 1u)) {
+        (void)hipEventRecord(c->ev_side[c->prof_steps], s);
+        c->prof_side[c->prof_steps] = 1;
+    }
+}
+
 WallDev wall_of(const discos_params* p);
 
 // Cell list from positions (and optional companions) in caller order.
@@ -274,7 +290,7 @@ struct DryStepOut {
 // done in the same pass (out is not written).
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
                       int scatter_to_caller, hipStream_t s, int mark = -1,
-                      const DryStepOut* upd = nullptr);
+                      const DryStepOut* upd = nullptr, bool store = false);
 
 // Random finite difference of the thermal forcing (scale = kT / delta, half = delta / 2;
 // scale 0: off); sid holds the ions' stable ids in cell-list order.
@@ -307,7 +323,8 @@ int midpoint_velocity(Ctx* c, int n, const double* vel, double dt, hipStream_t s
 // plus dt * vwet (nullable, [3][n_max] sorted), written to the caller's arrays in
 // cell-list order.
 int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
-                  double* pos, double* q, int* id, int* sp, hipStream_t s);
+                  double* pos, double* q, int* id, int* sp, hipStream_t s,
+                  const double* fp2 = nullptr);
 
 // U = (1/2) dV <c->rho, phi> and Q = sum w(z) F_x over the sorted forces c->fp into
 // out[0], out[1] (device).

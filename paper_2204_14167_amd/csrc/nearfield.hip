@@ -215,7 +215,8 @@ __device__ __forceinline__ void update_with_force(const GridDev& g, const DryDev
 __device__ __forceinline__ void update_one(const GridDev& g, const DryDev& Dd, int gi,
                                            const double4* __restrict__ sxyzq,
                                            const int* __restrict__ sid, const int* __restrict__ ssp,
-                                           const double* __restrict__ fp, int64_t fstride,
+                                           const double* __restrict__ fp,
+                                           const double* __restrict__ fp2, int64_t fstride,
                                            const double* __restrict__ vw, double* __restrict__ pos,
                                            int64_t pstride, double* __restrict__ q,
                                            int* __restrict__ id, int* __restrict__ sp,
@@ -234,6 +235,11 @@ __device__ __forceinline__ void update_one(const GridDev& g, const DryDev& Dd, i
         Fx = fp[gi];
         Fy = fp[gi + fstride];
         Fz = fp[gi + 2 * fstride];
+        if (fp2) {  // the grid force plus the near-field force computed apart
+            Fx += fp2[gi];
+            Fy += fp2[gi + fstride];
+            Fz += fp2[gi + 2 * fstride];
+        }
     }
     update_with_force(g, Dd, gi, me, sp_in, idi, Fx, Fy, Fz, wx0, wy0, wz0, pos, pstride, q, id, sp,
                       flags);
@@ -249,6 +255,7 @@ struct FusedUpdate {
     double* q;
     int* id;
     int* sp;
+    int store;  // without an update: out[o] = F instead of out[o] += F
 };
 
 // ---- the near-field pass's padded cell list ----------------------------------------
@@ -757,6 +764,12 @@ near_field_kernel(GridDev g0, const RepDev* __restrict__ reps, const int* __rest
         return;
     }
     const int o = scatter ? perm[i] : i;
+    if (U.store) {
+        out[o] = Fx;
+        out[o + stride] = Fy;
+        out[o + 2 * stride] = Fz;
+        return;
+    }
     out[o] += Fx;
     out[o + stride] += Fy;
     out[o + 2 * stride] += Fz;
@@ -820,7 +833,8 @@ static DryDev dry_of(const discos_params* p, uint64_t step) {
 }
 
 int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_t out_stride,
-                      int scatter_to_caller, hipStream_t s, int mark, const DryStepOut* upd) {
+                      int scatter_to_caller, hipStream_t s, int mark, const DryStepOut* upd,
+                      bool store) {
     if (n <= 0) return DISCOS_OK;
     const NearDev P = near_of(c, p);
     if (P.R < 1 || P.R > 3) return DISCOS_E_ARG;
@@ -828,6 +842,7 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
     if (rc) return rc;
     if (mark >= 0) stage_mark(c, mark, s);
     FusedUpdate U{};
+    U.store = store ? 1 : 0;
     if (upd) {
         U.Dd = dry_of(p, upd->step);
         U.sid = c->sid;
@@ -845,14 +860,15 @@ int near_field_sorted(Ctx* c, int n, const discos_params* p, double* out, int64_
 
 __global__ void dry_update_kernel(GridDev g, DryDev Dd, int n, const double4* __restrict__ sxyzq,
                                   const int* __restrict__ sid, const int* __restrict__ ssp,
-                                  const double* __restrict__ fp, int64_t fstride,
+                                  const double* __restrict__ fp, const double* __restrict__ fp2,
+                                  int64_t fstride,
                                   const double* __restrict__ vw,
                                   double* __restrict__ pos, int64_t pstride, double* __restrict__ q,
                                   int* __restrict__ id, int* __restrict__ sp,
                                   int* __restrict__ flags) {
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n) return;
-    update_one(g, Dd, gi, sxyzq, sid, ssp, fp, fstride, vw, pos, pstride, q, id, sp, flags);
+    update_one(g, Dd, gi, sxyzq, sid, ssp, fp, fp2, fstride, vw, pos, pstride, q, id, sp, flags);
 }
 
 // Batched: each ion's channel supplies its grid, noise key and mobility fit; the step
@@ -871,7 +887,7 @@ __global__ void dry_update_batch_kernel(const RepDev* __restrict__ reps,
     Dd.seed = R.seed;
     Dd.coef = R.coef;
     Dd.step = *step;
-    update_one(R.g, Dd, gi, sxyzq, sid, ssp, fp, n, nullptr, pos, n, q, id, sp, flags);
+    update_one(R.g, Dd, gi, sxyzq, sid, ssp, fp, nullptr, n, nullptr, pos, n, q, id, sp, flags);
 }
 
 __global__ void step_advance_kernel(uint64_t* step) { *step += 1; }
@@ -923,11 +939,12 @@ int batch_set_step(Batch* b, uint64_t v, hipStream_t s) {
 }
 
 int update_sorted(Ctx* c, int n, const discos_params* p, uint64_t step, const double* vwet,
-                  double* pos, double* q, int* id, int* sp, hipStream_t s) {
+                  double* pos, double* q, int* id, int* sp, hipStream_t s, const double* fp2) {
     if (n <= 0) return DISCOS_OK;
     const DryDev Dd = dry_of(p, step);
     dry_update_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->gd, Dd, n, c->sxyzq, c->sid, c->ssp, c->fp,
-                                                      c->n_max, vwet, pos, n, q, id, sp, c->flags);
+                                                      fp2, c->n_max, vwet, pos, n, q, id, sp,
+                                                      c->flags);
     return hipGetLastError() == hipSuccess ? DISCOS_OK : DISCOS_E_HIP;
 }
 
