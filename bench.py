@@ -479,6 +479,10 @@ def main():
                     help="dry steps of the 65,536-ion channel with a metal strip on one wall (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--serial", action="store_true",
+                    help="the 1M-ion context runs every stage in order on one stream (each "
+                         "kernel alone, for per-kernel profiles); the default overlaps the "
+                         "dry step's near field with the grid stages")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -494,7 +498,7 @@ def main():
     p = workloads.make_params(w)
     pos, q, ids, species = workloads.make_ions(w)
     torch.cuda.set_device(0)
-    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n)
+    ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, serial=args.serial)
     dp = ctx.params(gpu_params(p))
     dpos = torch.from_numpy(pos.copy()).cuda()
     dq = torch.from_numpy(q.copy()).cuda()
@@ -604,16 +608,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n_ions": N, "grid": [w.nx, w.ny, w.nz],
                    "walls": "dielectric (Neumann limit, sigma = 0)", "e_ext": list(w.e_ext),
-                   "psi": p["psi"], "mode": "dry step"},
+                   "psi": p["psi"], "mode": "dry step",
+                   "streams": "one (serial)" if args.serial else "two (near field beside the grid stages)"},
         "roofline": roof,
         "stages": per_stage,
         "stages_note": (f"per-stage times from {PROFILED_STEPS} untimed steps with an event at every "
                         "stage boundary; the timed steps record only the dominant stage's two "
-                        "events (its live launch time in roofline).  The near field (near_list, "
-                        "near_field) runs on a second stream beside spread .. interp, so the "
-                        "stages overlap and do not add up to ms_per_step; join_wait is the time "
-                        "the grid stages ran past the near-field pass, update the dry update "
-                        "from both forces"),
+                        "events (its live launch time in roofline).  " +
+                        ("Every stage ran alone (--serial)." if args.serial else
+                         "The near field (near_list, near_field) runs on a second stream beside "
+                         "spread .. interp, so the stages overlap and do not add up to "
+                         "ms_per_step; join_wait is the time the grid stages ran past the "
+                         "near-field pass, update the dry update from both forces")),
         "dry_tail": {"join_wait_ms": round(stages.get("interp_hy", 0.0), 5),
                      "update_ms": round(stages.get("update", 0.0), 5)},
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],

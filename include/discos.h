@@ -161,6 +161,11 @@ typedef struct discos_ctx discos_ctx;
  * gradients with no allocation. */
 #define DISCOS_CREATE_MIXED_ITERATIVE 2u
 #define DISCOS_MIXED_DENSE_MAX 16384
+/* A dry step runs its near field on a second stream of the context beside the spread,
+ * Poisson solve and interpolation (discos_step).  With this flag every stage runs in
+ * order on the caller's stream instead (each kernel then has the chip to itself, as a
+ * profile of the kernels one by one needs); results are the same. */
+#define DISCOS_CREATE_SERIAL 4u
 int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos_ctx** out);
 /* Waits for the device, then releases the context and its buffers.  Everything is
  * released even when the runtime reports an error on the way; that error is returned

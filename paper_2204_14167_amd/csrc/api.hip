@@ -378,6 +378,7 @@ int discos_create(const discos_grid* grid, int64_t n_max, uint32_t flags, discos
     c->ef_wq = 0.0;
     c->mx_iters = 0;
     c->mx_iterative = (flags & DISCOS_CREATE_MIXED_ITERATIVE) ? 1 : 0;
+    c->serial = (flags & DISCOS_CREATE_SERIAL) ? 1 : 0;
     c->cap_nd = -1;
     c->hy_km = 0;
     if (!c->hydro) c->hy_tab = nullptr;
@@ -651,7 +652,7 @@ int discos_step(discos_ctx* c, discos_ions* ions, const discos_params* p, uint64
     // and the pass (and the two hydrodynamic stages after it, empty); this stream closes
     // the interpolation, then the join (stage 12: the time the grid stages ran past the
     // pass) and the update (stage 13).
-    const bool beside = !wet && ni > 0 && !rc;
+    const bool beside = !wet && !c->serial && ni > 0 && !rc;
     if (beside) {
         if (hipEventRecord(c->ev_fork, s) != hipSuccess ||
             hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess)

@@ -47,6 +47,7 @@ struct Ctx {
     double* fp;      // [3][n_max] per-ion forces in cell-list order
     double* fnear;   // [3][n_max] near-field forces of a dry step computed beside the grid stages
     hipStream_t side = nullptr;                      // the near field's stream in a dry step
+    int serial = 0;                                  // DISCOS_CREATE_SERIAL: no side stream work
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // the cell list is built / the pass is done
     double2 *tw_x, *tw_y;
     NearList nl;     // the near-field pass's padded copy of the cell list

@@ -24,6 +24,7 @@ INTERP_E, INTERP_FORCE, INTERP_PHI, INTERP_VEL = 0, 1, 2, 3
 STEP_DRY, STEP_WET, STEP_RFD = 0, 1, 0x10
 CREATE_HYDRO = 1
 CREATE_MIXED_ITERATIVE = 2
+CREATE_SERIAL = 4
 MIXED_DENSE_MAX = 16384
 STOKES_NOISE = 1
 HYDRO_NOSLIP, HYDRO_SLIP = 0, 1
@@ -264,13 +265,16 @@ def spread_charge_noalloc(grid, pos, q, params, add_bc=False, out=None, status=N
 class Context:
     """One grid and up to n_max ions; owns the library context."""
 
-    def __init__(self, nx, ny, nz, h=1.0, n_max=0, hydro=False, mixed_iterative=False):
+    def __init__(self, nx, ny, nz, h=1.0, n_max=0, hydro=False, mixed_iterative=False,
+                 serial=False):
         """mixed_iterative: walls of mixed type by conjugate gradients only (no dense
-        inverse of their capacitance system)."""
+        inverse of their capacitance system).  serial: every stage of a step in order on
+        the caller's stream (no second stream for the dry step's near field)."""
         self.grid = (int(nx), int(ny), int(nz), float(h))
         g = DiscosGrid(int(nx), int(ny), int(nz), float(h))
         h_ = ctypes.c_void_p()
-        flags = (CREATE_HYDRO if hydro else 0) | (CREATE_MIXED_ITERATIVE if mixed_iterative else 0)
+        flags = ((CREATE_HYDRO if hydro else 0) | (CREATE_MIXED_ITERATIVE if mixed_iterative else 0)
+                 | (CREATE_SERIAL if serial else 0))
         rc = lib().discos_create(ctypes.byref(g), int(n_max), flags, ctypes.byref(h_))
         if rc != OK:
             raise DiscosError(rc, "discos_create failed")

@@ -396,3 +396,28 @@ def test_near_field_cutoff_and_coincidence_edges(bc):
     out = host(ctx.near_field(dev(pos), dev(q), ctx.params(p)))
     assert np.all(np.isfinite(out))
     assert rel_l2(out, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["dielectric_32x32x32_n4096", "dielectric_128x128x64_n65536"])
+def test_step_serial_equals_two_streams(name):
+    """A context created with DISCOS_CREATE_SERIAL (every stage in order on the caller's
+    stream, the update inside the near-field pass) and one whose dry step runs the near
+    field on its second stream give the same steps: per ion the same forces summed in
+    the same order, so equal to rounding of the in-bin order of the cell list."""
+    from paper_2204_14167_amd import discos
+    w = workloads.WORKLOADS[name]
+    p = workloads.make_params(w)
+    pos, q, ids, species = workloads.make_ions(w)
+    out = []
+    for serial in (True, False):
+        ctx = discos.Context(w.nx, w.ny, w.nz, w.h, w.n, serial=serial)
+        dp = ctx.params(p)
+        arrays = (dev(pos), dev(q), dev(ids), dev(species))
+        for s in range(3):
+            ctx.step(*arrays, dp, s)
+        ctx.check()
+        out.append(by_id(host(arrays[0]), host(arrays[2]), np.arange(w.n)))
+    L = np.array([w.nx, w.ny, w.nz], float) * w.h
+    rel = np.linalg.norm(min_image(out[0] - out[1], L)) / np.linalg.norm(min_image(out[0] - pos, L))
+    log(f"{name}: serial vs two streams over 3 steps, rel {rel:.3e}")
+    assert rel < 1e-12
