@@ -459,11 +459,13 @@ __global__ void __launch_bounds__(64) zpivot_kernel(double* __restrict__ zg, int
 // maps over the four lanes gives each segment's carry, and a second pass applies it.
 // Lane l of a wavefront: mode 16 w + (l & 15), segment l >> 4, so one load instruction
 // reads 16 consecutive modes at four levels.
-template <int L>
+template <int L, int S = 4>
 __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, const double* __restrict__ zg,
                                                 int nmode, int nz, double scale, int skip0, int t0) {
+    static_assert(S == 4 || S == 8 || S == 16, "segments per mode");
+    constexpr int ML = 64 / S;  // modes per wavefront
     const int lane = threadIdx.x & 63;
-    const int ml = lane & 15, seg = lane >> 4;
+    const int ml = lane % ML, seg = lane / ML;
     const int t = t0 + ml;
     const bool valid = t < nmode && !(skip0 && t == 0);
     const int tt = min(t, nmode - 1);
@@ -488,15 +490,21 @@ __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, cons
             d[u] = dl;
         }
     }
-    // carry into this segment: maps of the segments below, in order
-    double2 din = make_double2(0.0, 0.0);
+    // carry into this segment: the affine maps x -> A x + dl of the segments below,
+    // composed by an inclusive scan over the segments (log2 S rounds), then shifted by one
+    double Ac = A, cx = dl.x, cy = dl.y;
 #pragma unroll
-    for (int sp = 0; sp < 3; ++sp) {
-        const int src = ml + 16 * sp;
-        const double As = __shfl(A, src, 64);
-        const double bx = __shfl(dl.x, src, 64), by = __shfl(dl.y, src, 64);
-        if (seg > sp) din = make_double2(As * din.x + bx, As * din.y + by);
+    for (int o = 1; o < S; o <<= 1) {
+        const double Ap = __shfl_up(Ac, ML * o, 64);
+        const double px = __shfl_up(cx, ML * o, 64), py = __shfl_up(cy, ML * o, 64);
+        if (seg >= o) {
+            cx = Ac * px + cx;
+            cy = Ac * py + cy;
+            Ac *= Ap;
+        }
     }
+    const double cinx = __shfl_up(cx, ML, 64), ciny = __shfl_up(cy, ML, 64);
+    const double2 din = seg > 0 ? make_double2(cinx, ciny) : make_double2(0.0, 0.0);
     double p = 1.0;
 #pragma unroll
     for (int u = 0; u < L; ++u) {
@@ -516,14 +524,20 @@ __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, cons
             d[u] = xl;
         }
     }
-    double2 xin = make_double2(0.0, 0.0);
+    // the segments above, composed from the top down the same way
+    double Bc = B, ex = xl.x, ey = xl.y;
 #pragma unroll
-    for (int sp = 3; sp >= 1; --sp) {
-        const int src = ml + 16 * sp;
-        const double Bs = __shfl(B, src, 64);
-        const double bx = __shfl(xl.x, src, 64), by = __shfl(xl.y, src, 64);
-        if (seg < sp) xin = make_double2(Bs * xin.x + bx, Bs * xin.y + by);
+    for (int o = 1; o < S; o <<= 1) {
+        const double Bn = __shfl_down(Bc, ML * o, 64);
+        const double nx = __shfl_down(ex, ML * o, 64), ny = __shfl_down(ey, ML * o, 64);
+        if (seg + o < S) {
+            ex = Bc * nx + ex;
+            ey = Bc * ny + ey;
+            Bc *= Bn;
+        }
     }
+    const double xinx = __shfl_down(ex, ML, 64), xiny = __shfl_down(ey, ML, 64);
+    const double2 xin = seg + 1 < S ? make_double2(xinx, xiny) : make_double2(0.0, 0.0);
     double q = 1.0;
 #pragma unroll
     for (int u = L - 1; u >= 0; --u) {
@@ -541,9 +555,10 @@ __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, cons
 __device__ __forceinline__ void zsolve_mode0_wave(double2* __restrict__ spec, int nmode, int nz,
                                                   double scale, int singular, int* __restrict__ flags);
 
-// Wavefront w of block b solves modes 16 (4 b + w) .. + 15.  With singular != 0 mode 0
-// is skipped there and solved by the first wavefront of one extra last block.
-template <int L>
+// Wavefront w of block b solves modes M (4 b + w) .. + M - 1, M = 64 / S, each mode in S
+// segments of L levels.  With singular != 0 mode 0 is skipped there and solved by the
+// first wavefront of one extra last block.
+template <int L, int S>
 __global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ spec,
                                                         const double* __restrict__ zg, int nmode,
                                                         int nz, double scale, int singular,
@@ -552,8 +567,8 @@ __global__ void __launch_bounds__(256) zsolve_seg_kernel(double2* __restrict__ s
         if (threadIdx.x < 64) zsolve_mode0_wave(spec, nmode, nz, scale, singular, flags);
         return;
     }
-    zsolve_seg_wave<L>(spec, zg, nmode, nz, scale, singular != 0,
-                       (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16);
+    zsolve_seg_wave<L, S>(spec, zg, nmode, nz, scale, singular != 0,
+                          (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / S));
 }
 
 // Batched: task (channel, first mode) per wavefront, for channels whose nz fits L
@@ -779,15 +794,18 @@ int solve_poisson(Ctx* c, const double* rhs, const discos_params* p, double* phi
             zpivot_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->cprime, nx, ny, nz, s_lo, s_hi, singular != 0);
             c->zg_key = key;
         }
-        const int L = (nz + 3) / 4;
+        // segments of 8 levels, 4, 8 or 16 per mode: few registers per wavefront (about 80),
+        // so that the solve's wavefronts find room beside other work on the device
+        const int S = nz <= 32 ? 4 : nz <= 64 ? 8 : 16;
+        const int per_block = 4 * (64 / S);
         // one extra block carries the singular kappa = 0 mode
-        const int nb = (nmode + 63) / 64 + (singular ? 1 : 0);
-        if (L <= 8)
-            zsolve_seg_kernel<8><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
-        else if (L <= 16)
-            zsolve_seg_kernel<16><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
+        const int nb = (nmode + per_block - 1) / per_block + (singular ? 1 : 0);
+        if (S == 4)
+            zsolve_seg_kernel<8, 4><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
+        else if (S == 8)
+            zsolve_seg_kernel<8, 8><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
         else
-            zsolve_seg_kernel<32><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
+            zsolve_seg_kernel<8, 16><<<nb, 256, 0, s>>>(c->spec, c->cprime, nmode, nz, scale, singular, c->flags);
     } else {
         c->zg_key = -1;
         zsolve_kernel<<<(nmode + 63) / 64, 64, 0, s>>>(c->spec, c->cprime, nx, ny, nz, scale, s_lo, s_hi,
