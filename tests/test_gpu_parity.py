@@ -86,7 +86,8 @@ def test_spread_empty_and_capacity():
 
 @pytest.mark.parametrize("bc", BC_PAIRS)
 @pytest.mark.parametrize("shape", [(32, 32, 32), (8, 16, 5), (64, 8, 12), (256, 16, 4), (16, 128, 9),
-                                   (16, 16, 61), (32, 16, 100), (8, 8, 127), (16, 8, 130)])
+                                   (16, 16, 61), (32, 16, 100), (8, 8, 127), (16, 8, 130),
+                                   (16, 8, 64), (8, 16, 128), (8, 8, 33), (8, 8, 65)])
 def test_poisson(bc, shape):
     nx, ny, nz = shape
     log(f"poisson bc={bc} shape={shape}")
