@@ -453,12 +453,12 @@ __global__ void __launch_bounds__(64) zpivot_kernel(double* __restrict__ zg, int
 }
 
 // Solve along z with the pivots g: forward d_k = g_k (r_k + d_{k-1}), back
-// x_k = d_k + g_k x_{k+1} (x_nz = 0) -- two first-order linear recurrences.  Four lanes
+// x_k = d_k + g_k x_{k+1} (x_nz = 0) -- two first-order linear recurrences.  S lanes
 // share a mode, each holding one segment of L levels in registers: a segment's local
 // recurrence gives an affine map (product of its g, local end value), a scan of those
-// maps over the four lanes gives each segment's carry, and a second pass applies it.
-// Lane l of a wavefront: mode 16 w + (l & 15), segment l >> 4, so one load instruction
-// reads 16 consecutive modes at four levels.
+// maps over the S lanes gives each segment's carry, and a second pass applies it.
+// Lane l of a wavefront: mode M w + (l mod M), segment l / M with M = 64 / S, so one load
+// instruction reads M consecutive modes at S levels.
 template <int L, int S = 4>
 __device__ __forceinline__ void zsolve_seg_wave(double2* __restrict__ spec, const double* __restrict__ zg,
                                                 int nmode, int nz, double scale, int skip0, int t0) {
